@@ -1,0 +1,164 @@
+"""Benchmark of the SwiftWRF render path on one MI355X.
+
+Workload: N = 100,000 synthetic 2D Gaussians, 90 x 360 spectra (1 deg/px),
+deformation MLP 89 -> 4 x 256 -> 7. A step renders one batch of B transmitter
+positions end to end (PE -> MLP -> deform/preprocess -> scan -> keys -> radix
+sort -> tile ranges -> blend) with the inputs resident in HBM. The headline
+value is the batched throughput (spectra/s); the plain one-query-per-launch
+FP32 path is timed beside it on the same GPU, and the oracle on the host CPU.
+
+Prints one JSON line (see the repository's design notes for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spectra/s at N=100k, 90x360 (batched vs plain); p50/p99 query latency us"
+FLOP_PER_PAIR = 2 * (26 * 256 + 3 * 256 * 256 + 256 * 7)  # MLP per (query, Gaussian) pair
+PEAK = {"bf16": 2500.0, "fp32": 157.3}  # dense TFLOP/s (MFMA bf16; fp32 vector incl. packed)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--batch", type=int, default=64)
+    p.add_argument("--n", type=int, default=100_000)
+    p.add_argument("--height", type=int, default=90)
+    p.add_argument("--width", type=int, default=360)
+    p.add_argument("--mlp", choices=("bf16", "fp32"), default="bf16")
+    p.add_argument("--plain-queries", type=int, default=16)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--quick", action="store_true", help="timed steps only (for profiler runs)")
+    return p.parse_args()
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def cpu_baseline(g, Ws, bs, H, W, txs, budget_s):
+    """The FP64 oracle timed on the host: whole spectra (MLP + brute-force
+    compositing over all Gaussians in depth order) until the budget is used."""
+    from oracle import model as M
+    s = M.Scene.from_arrays(g, H, W)
+    mlp = M.MLP([w.astype(np.float64) for w in Ws], [b.astype(np.float64) for b in bs])
+    pix = M.full_grid(H, W)
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        M.render_query(s, mlp, txs[done % len(txs)].astype(np.float64), pix=pix, margins=None)
+        done += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = min(threads, os.cpu_count() or threads)
+    return {"value": done / dt, "unit": "spectra/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} full {H}x{W} spectra at N={len(g['mean_x'])} (FP64 MLP + brute-force compositing), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+
+    H, W, N, Bq = a.height, a.width, a.n, a.batch
+    g = synth.gaussians(N, H, W, seed=1003)
+    Ws, bs = synth.mlp_weights(seed=3003)
+    nbat = a.warmup + a.steps
+    txs = synth.tx_positions(nbat * Bq, seed=2003)
+    ctx = B.Context(0)
+    sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
+    tx_dev = torch.from_numpy(txs).cuda().view(nbat, Bq, 3)
+    out = torch.empty((Bq, H, W), device="cuda", dtype=torch.float32)
+    flags = B.MLP_BF16 if a.mlp == "bf16" else B.MLP_FP32
+
+    for i in range(a.warmup):
+        ctx.render(sid, tx_dev[i], flags=flags, out=out)
+    torch.cuda.synchronize()
+    ctx.stage_timing(True)
+    ctx.stage_times()  # reset
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(a.steps):
+        ctx.render(sid, tx_dev[a.warmup + i], flags=flags, out=out)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.stage_timing(False)
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(a.steps)]
+    gpu_ms = sum(step_ms)
+    elapsed = max(wall, gpu_ms / 1e3)
+    value = a.steps * Bq / elapsed
+    ms_per_step = 1e3 * elapsed / a.steps
+
+    mlp_ms, mlp_n = stages["mlp_preprocess"]
+    avg_mlp_ms = mlp_ms / max(mlp_n, 1)
+    flops = float(FLOP_PER_PAIR) * N * Bq
+    achieved = flops / (avg_mlp_ms * 1e-3) / 1e12
+    peak = PEAK[a.mlp]
+    roofline = {"kernel": f"mlp_{a.mlp}_deform_preprocess", "bound": "mfma" if a.mlp == "bf16" else "alu",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "avg_launch_ms": avg_mlp_ms, "flop_per_launch": flops}
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "spectra/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": a.mlp, "data": "synthetic",
+        "config": {"workload": f"batched deformable render, N={N} Gaussians, {H}x{W} spectra, batch {Bq} TX "
+                               f"positions, {a.mlp.upper()} MLP 89-4x256-7",
+                   "n_gaussians": N, "height": H, "width": W, "batch": Bq, "mlp": a.mlp},
+        "latency_us": {"batched_p50": 1e3 * pct(step_ms, 50), "batched_p99": 1e3 * pct(step_ms, 99),
+                       "note": "closed-loop: every query of a batch completes with its batch"},
+        "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+        "roofline": roofline,
+    }
+    if not a.quick:
+        # plain one-query-per-launch FP32 path
+        q = a.plain_queries
+        txp = torch.from_numpy(synth.tx_positions(q + 2, seed=2103)).cuda()
+        o1 = torch.empty((1, H, W), device="cuda", dtype=torch.float32)
+        for i in range(2):
+            ctx.render(sid, txp[i:i + 1], flags=B.MLP_FP32, out=o1)
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for i in range(q):
+            s0 = time.perf_counter()
+            ctx.render(sid, txp[2 + i:3 + i], flags=B.MLP_FP32, out=o1)
+            torch.cuda.synchronize()
+            lat.append(1e6 * (time.perf_counter() - s0))
+        pw = time.perf_counter() - t0
+        plain = q / pw
+        rec["plain"] = {"value": plain, "unit": "spectra/s", "dtype": "fp32", "batch": 1,
+                        "p50_us": pct(lat, 50), "p99_us": pct(lat, 99)}
+        rec["batched_over_plain"] = value / plain
+        if not a.no_cpu_baseline:
+            rec["cpu_baseline"] = cpu_baseline(g, Ws, bs, H, W, txs[:8], a.cpu_seconds)
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * swiftwrf.h -- C ABI of libswiftwrf.so: the SwiftWRF spectrum render path on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The library renders the spatial spectrum seen by a fixed receiver from N
+ * anisotropic 2D Gaussians after a deformation MLP has shifted them for a
+ * transmitter position: the mapping F: R^3 -> spectrum, s -> F(s), of the
+ * problem statement (paper Sec. 3.3, "Problem Definition"). Per query:
+ *
+ *   gamma(mu_hat), gamma(s_hat)      positional encoding, Sec. 4.2 eq. (posenc)
+ *   dG = F_theta(gamma(mu), gamma(s)) deformation MLP, Sec. 4.2
+ *   G^s = G^0 + dG                    GOP reference frame + residuals, Sec. 4.2
+ *   K = delta exp(-d^T Sigma^-1 d / 2) kernel weight, Sec. 4.1
+ *   front-to-back alpha compositing   blending rule reviewed in Sec. 3.2, over
+ *                                     16x16 tiles (Sec. 4.1 tile partitioning)
+ *
+ * Conventions used by every entry point:
+ *  - Spectrum layout: B x H x W float32, row-major; row = elevation, column =
+ *    azimuth (the matrix of Sec. 3.1). Pixel (row y, column x) samples the
+ *    continuous point (x, y) in pixel units. Gaussian means are in pixel units.
+ *  - Per-Gaussian parameters (SoA, float32, length n): mean_x, mean_y (pixels),
+ *    log_scale_x, log_scale_y (natural log of the standard deviations along the
+ *    principal axes, pixels), rotation (radians; principal axis 1 points along
+ *    (cos r, sin r)), opacity_logit (opacity = sigmoid(logit)), amplitude (the
+ *    real signal response), depth (blending order; ties go to the lower id).
+ *  - Blending per pixel, in ascending (depth, id) order: q = d^T Sigma^-1 d;
+ *    skip if q > 9; alpha = min(0.99, opacity exp(-q/2)); skip if
+ *    alpha < 1/255; T' = T (1 - alpha); stop (without adding) if T' < 1e-4;
+ *    else C += amp alpha T and T = T'. No background term.
+ *  - Deformation MLP input: [gamma(mu_hat) (2(2*6+1) = 26) | gamma(s_hat)
+ *    (3(2*10+1) = 63)], mu_hat = (mean_x / W, mean_y / H) of the canonical mean,
+ *    s_hat = (tx - room_lo) / (room_hi - room_lo). gamma(v) = [v, sin(2^k pi v)
+ *    for k < L, cos(2^k pi v) for k < L], each block over all components in
+ *    order. Hidden layers Linear + ReLU, output Linear with 7 residuals in the
+ *    order (d_mean_x, d_mean_y, d_log_scale_x, d_log_scale_y, d_rotation,
+ *    d_opacity_logit, d_amplitude). Deformed opacity = sigmoid(logit + d).
+ *  - Device pointers are HIP device addresses (e.g. torch CUDA tensors on
+ *    ROCm). "stream" is a hipStream_t passed as void*; NULL = default stream.
+ *  - Ownership: the caller owns every buffer it passes. The context owns the
+ *    scenes it uploaded (deep copies) and all scratch memory.
+ *  - Errors: every entry point returns a swf_status. On an argument error
+ *    (SWF_E_INVALID) nothing is enqueued. No C++ exception crosses the ABI.
+ *  - Threading: a context may be used by one host thread at a time, except the
+ *    serving entry points (swf_serve_*), which are thread-safe.
+ */
+#ifndef SWIFTWRF_H
+#define SWIFTWRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t swf_status;
+enum {
+    SWF_OK = 0,
+    SWF_E_INVALID = -1,   /* bad argument; nothing enqueued                     */
+    SWF_E_OOM = -2,       /* device or host allocation failed                   */
+    SWF_E_DEVICE = -3,    /* a HIP runtime call failed                          */
+    SWF_E_NOT_FOUND = -4, /* unknown scene id or ticket                         */
+    SWF_E_OVERFLOW = -5,  /* a capacity was exceeded (key buffer, scratch)     */
+    SWF_E_STATE = -6,     /* call not valid in the current state               */
+    SWF_E_PENDING = -7,   /* serving: result not ready yet                      */
+};
+
+/* Render flags (bitwise or). */
+enum {
+    SWF_MLP_FP32 = 0,        /* deformation MLP in FP32 (FMA, FP32 accumulate)   */
+    SWF_MLP_BF16 = 1 << 0,   /* deformation MLP on BF16 MFMA, FP32 accumulate    */
+    SWF_NO_DEFORM = 1 << 1,  /* static render of the canonical Gaussians         */
+    SWF_KEEP_AUX = 1 << 2,   /* write the per-pixel blend state `aux` (training) */
+    SWF_FULL_SORT = 1 << 3,  /* sort full 64-bit (tile << 32 | depth) keys
+                                instead of eliding the depth digits (same
+                                result; used to check the elision)               */
+    SWF_TILE8 = 1 << 4,      /* 8x8 tiles instead of 16x16 (same result)         */
+    SWF_PAPER_DEFORM = 1 << 5/* zero the covariance residuals (outputs 2..4), as
+                                the paper does not deform the covariance         */
+};
+
+typedef struct swf_ctx swf_ctx;
+
+typedef struct {
+    int32_t device;          /* HIP device ordinal                                */
+    int32_t reserved[7];
+} swf_config;
+
+typedef struct {
+    int32_t n;               /* number of Gaussians, >= 0                          */
+    const float *mean_x, *mean_y, *log_scale_x, *log_scale_y;
+    const float *rotation, *opacity_logit, *amplitude, *depth;
+} swf_gaussians;
+
+#define SWF_MAX_LAYERS 8
+typedef struct {
+    int32_t mean_bands;      /* L of gamma(mu_hat); 6                             */
+    int32_t tx_bands;        /* L of gamma(s_hat); 10                             */
+    int32_t hidden;          /* hidden width; 256 (multiple of 32, <= 256)        */
+    int32_t n_hidden;        /* number of hidden layers; 1..SWF_MAX_LAYERS-1      */
+    const float *weight[SWF_MAX_LAYERS]; /* W_l row-major [out][in], l = 0..n_hidden */
+    const float *bias[SWF_MAX_LAYERS];   /* b_l [out]                                */
+    float room_lo[3], room_hi[3];        /* TX normalisation box (metres)            */
+} swf_mlp;
+
+/* Per-pixel blend state kept for the backward pass (SWF_KEEP_AUX): for each of
+ * the B*H*W pixels, T_final (float32) then, in a second plane, the number of
+ * tile-list entries consumed up to and including the last added Gaussian
+ * (uint32). Size: 8 * B * H * W bytes. */
+
+/* Gradient buffers (device, float32, caller-owned, overwritten). Any may be
+ * NULL to skip it. Base-parameter gradients are summed over the batch. */
+typedef struct {
+    float *mean_x, *mean_y, *log_scale_x, *log_scale_y, *rotation, *opacity_logit, *amplitude;
+    float *weight[SWF_MAX_LAYERS];
+    float *bias[SWF_MAX_LAYERS];
+} swf_grads;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on cfg->device (cfg may be NULL: device 0). */
+swf_status swf_create(swf_ctx **out, const swf_config *cfg);
+/* Destroy a context and everything it owns. Waits for its work to finish. */
+swf_status swf_destroy(swf_ctx *ctx);
+/* Static string for a status code. */
+const char *swf_status_string(swf_status s);
+/* Last error message of this context (static storage owned by the context). */
+const char *swf_last_error(swf_ctx *ctx);
+
+/* ---- scenes (paper Sec. 4.2: canonical reference frame G^0 plus F_theta) ---
+ * Upload n Gaussians (and optionally the deformation MLP) for an H x W grid.
+ * The context copies everything (host or device source, src_is_device). The
+ * Gaussians are reordered by (depth, id) on upload; ids seen through the debug
+ * entry points are the caller's original indices. mlp may be NULL for a static
+ * scene. H and W must lie in [1, 4096]. Synchronous. */
+swf_status swf_scene_upload(swf_ctx *ctx, const swf_gaussians *g, const swf_mlp *mlp, int32_t height,
+                            int32_t width, int32_t src_is_device, int32_t *scene_id);
+swf_status swf_scene_release(swf_ctx *ctx, int32_t scene_id);
+/* Device bytes held by a scene (its Gaussians, presort data and weights). */
+swf_status swf_scene_bytes(swf_ctx *ctx, int32_t scene_id, uint64_t *bytes);
+
+/* ---- render (Sec. 4.3: PE -> MLP -> deform -> tile rasterization) ----------
+ * tx: device float32 [batch][3] transmitter positions (ignored with
+ * SWF_NO_DEFORM, may be NULL then). out: device float32 [batch][H][W].
+ * aux: device buffer of 8*batch*H*W bytes when SWF_KEEP_AUX, else NULL.
+ * Enqueued on `stream`; the call returns after enqueueing, except that it waits
+ * once on the stream for the total key count (a 8-byte device-to-host read)
+ * to size the key buffers. */
+swf_status swf_render(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags, float *out,
+                      void *aux, void *stream);
+
+/* ---- backward (hand-written; transmittance replayed back to front) --------
+ * Gradient of sum(grad_out * out) with respect to the scene's base parameters
+ * and MLP weights, for the same (scene, tx, batch, flags) as the swf_render
+ * call that produced `aux` (flags must include SWF_KEEP_AUX there). Every
+ * discrete decision is held at its forward outcome; where the 0.99 alpha clamp
+ * is active the derivative through opacity and q is zero. Depth gets no
+ * gradient. Recomputes the forward intermediates it needs. */
+swf_status swf_render_backward(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags,
+                               const float *grad_out, const void *aux, const swf_grads *grads, void *stream);
+
+/* L1 loss (paper Sec. 4.4, the l1 term): loss = mean |pred - target| over n
+ * values, written to *loss (device float32); grad (device, may be NULL)
+ * receives sign(pred - target) / n with sign(0) = 0. */
+swf_status swf_l1_loss(swf_ctx *ctx, const float *pred, const float *target, int64_t n, float *loss, float *grad,
+                       void *stream);
+
+/* ---- stage timing ----------------------------------------------------------
+ * When enabled, swf_render records a HIP event pair around each stage on the
+ * render stream. swf_stage_times waits for them and returns, per stage, the
+ * summed milliseconds and the number of launches since the last reset:
+ * stage 0 tx features, 1 MLP+deform+preprocess, 2 scan, 3 emit keys,
+ * 4 radix sort, 5 tile ranges, 6 blend. n_stages is in/out (capacity/used). */
+enum { SWF_STAGE_TX = 0, SWF_STAGE_MLP, SWF_STAGE_SCAN, SWF_STAGE_EMIT, SWF_STAGE_SORT, SWF_STAGE_RANGES,
+       SWF_STAGE_BLEND, SWF_N_STAGES };
+swf_status swf_stage_timing(swf_ctx *ctx, int32_t enable);
+swf_status swf_stage_times(swf_ctx *ctx, double *ms, int64_t *launches, int32_t *n_stages);
+
+/* ---- debug / step-level entry points --------------------------------------
+ * swf_debug_deform: the 7 MLP residuals of every (query, Gaussian) pair, device
+ * float32 [batch][n][7], Gaussians in the caller's original order.
+ * swf_debug_keys: after a swf_render of the same scene, batch and flags on the
+ * same context, copies to HOST buffers: counts [batch*n] and offsets
+ * [batch*n] (uint32, pairs in (query, depth-sorted Gaussian) order), the sorted
+ * keys [n_keys] as uint64 (global tile << 32 | depth bits), the sorted values
+ * [n_keys] as (query << 32 | original Gaussian id), and the tile ranges
+ * [batch*tiles][2] (uint32 start, end). Pass NULL for any output to skip it;
+ * *n_keys returns the key count. Sizes must hold what is copied. */
+swf_status swf_debug_deform(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags,
+                            float *delta, void *stream);
+swf_status swf_debug_keys(swf_ctx *ctx, uint32_t *counts, uint32_t *offsets, uint64_t *keys, uint64_t *values,
+                          uint32_t *ranges, uint64_t *n_keys, uint64_t capacity);
+
+/* Stable LSD radix sort of n (key, value) pairs in place, device memory, on
+ * the key bits [begin_bit, end_bit). key_bytes is 4 (uint32 keys) or 8 (uint64
+ * keys). 8-bit digits, wave-ballot ranking. Enqueued on stream. */
+swf_status swf_radix_sort(swf_ctx *ctx, void *keys, uint32_t *values, int64_t n, int32_t key_bytes,
+                          int32_t begin_bit, int32_t end_bit, void *stream);
+/* Exclusive prefix sum of n uint32 counts (device) into offsets (device,
+ * uint32); the 64-bit total goes to *total (device uint64). */
+swf_status swf_exclusive_scan(swf_ctx *ctx, const uint32_t *counts, uint32_t *offsets, uint64_t *total, int64_t n,
+                              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWIFTWRF_H */

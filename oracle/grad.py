@@ -120,7 +120,7 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
     for b in range(B):
         delta = M.deltas(scene, mlp, txs[b], room) if mlp is not None else None
         g = M.deform(scene, delta)
-        rg = M.gaussians_for_raster(g)
+        rg = M.gaussians_for_raster(g, scene.depth)
         res = M.composite(rg, order, pix[0], pix[1], margins=None)
         t = np.asarray(targets[b], np.float64).ravel()
         loss += np.abs(res.C - t).sum() / count

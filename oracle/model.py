@@ -273,11 +273,15 @@ class RenderResult:
     overflow: np.ndarray
 
 
-def gaussians_for_raster(g: dict):
-    """Per-Gaussian arrays the compositor needs, from deformed parameters."""
+def gaussians_for_raster(g: dict, depth=None):
+    """Per-Gaussian arrays the compositor needs, from deformed parameters.
+    A Gaussian takes part if its parameters are finite, det Sigma > 0 and its
+    depth (when given) is not NaN."""
     sxx, sxy, syy = covariance(g["lsx"], g["lsy"], g["rot"])
     ixx, ixy, iyy, det, live = inverse2(sxx, sxy, syy)
     fin = np.isfinite(g["mx"]) & np.isfinite(g["my"]) & np.isfinite(g["opacity"]) & np.isfinite(g["amp"])
+    if depth is not None:
+        fin &= ~np.isnan(np.asarray(depth, np.float64))
     live = live & fin
     z = lambda a: np.ascontiguousarray(np.where(live, a, 0.0), np.float64)
     return dict(mx=z(g["mx"]), my=z(g["my"]), ixx=z(ixx), ixy=z(ixy), iyy=z(iyy), op=z(g["opacity"]),
@@ -320,7 +324,7 @@ def render_query(scene: Scene, mlp: MLP | None, tx, room=DEFAULT_ROOM, pix=None,
     if delta is None:
         delta = deltas(scene, mlp, tx, room, bf16=bf16) if mlp is not None else None
     g = deform(scene, delta)
-    rg = gaussians_for_raster(g)
+    rg = gaussians_for_raster(g, scene.depth)
     order = depth_order(scene.depth)
     if pix is None:
         pix = full_grid(scene.H, scene.W)

@@ -1,0 +1,259 @@
+"""Python binding of libswiftwrf.so (ctypes): argument marshalling only.
+
+Every step of the render path runs in the HIP library; PyTorch provides device
+memory and the current stream. Loading fails loudly when the library has not
+been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswiftwrf.so")
+
+# render flags (include/swiftwrf.h)
+MLP_FP32 = 0
+MLP_BF16 = 1 << 0
+NO_DEFORM = 1 << 1
+KEEP_AUX = 1 << 2
+FULL_SORT = 1 << 3
+TILE8 = 1 << 4
+PAPER_DEFORM = 1 << 5
+
+STAGES = ("tx_features", "mlp_preprocess", "scan", "emit_keys", "radix_sort", "tile_ranges", "blend")
+MAX_LAYERS = 8
+PARAMS = ("mean_x", "mean_y", "log_scale_x", "log_scale_y", "rotation", "opacity_logit", "amplitude", "depth")
+
+_fp = ctypes.POINTER(ctypes.c_float)
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class _Gaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32)] + [(k, ctypes.c_void_p) for k in PARAMS]
+
+
+class _Mlp(ctypes.Structure):
+    _fields_ = [("mean_bands", ctypes.c_int32), ("tx_bands", ctypes.c_int32), ("hidden", ctypes.c_int32),
+                ("n_hidden", ctypes.c_int32), ("weight", ctypes.c_void_p * MAX_LAYERS),
+                ("bias", ctypes.c_void_p * MAX_LAYERS), ("room_lo", ctypes.c_float * 3),
+                ("room_hi", ctypes.c_float * 3)]
+
+
+class _Grads(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in PARAMS[:7]] + [("weight", ctypes.c_void_p * MAX_LAYERS),
+                                                             ("bias", ctypes.c_void_p * MAX_LAYERS)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded native library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the render path has no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        sig = {
+            "swf_create": [P, P],
+            "swf_destroy": [P],
+            "swf_last_error": [P],
+            "swf_status_string": [I32],
+            "swf_scene_upload": [P, P, P, I32, I32, I32, P],
+            "swf_scene_release": [P, I32],
+            "swf_scene_bytes": [P, I32, P],
+            "swf_render": [P, I32, P, I32, I32, P, P, P],
+            "swf_render_backward": [P, I32, P, I32, I32, P, P, P, P],
+            "swf_l1_loss": [P, P, P, I64, P, P, P],
+            "swf_stage_timing": [P, I32],
+            "swf_stage_times": [P, P, P, P],
+            "swf_debug_deform": [P, I32, P, I32, I32, P, P],
+            "swf_debug_keys": [P, P, P, P, P, P, P, ctypes.c_uint64],
+            "swf_radix_sort": [P, P, P, I64, I32, I32, I32, P],
+            "swf_exclusive_scan": [P, P, P, P, I64, P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int32
+        L.swf_last_error.restype = ctypes.c_char_p
+        L.swf_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+class SwfError(RuntimeError):
+    pass
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One libswiftwrf context on one GPU."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self._L = lib()
+        h = ctypes.c_void_p()
+        cfg = _Config(device=device)
+        self._check(self._L.swf_create(ctypes.byref(h), ctypes.byref(cfg)), ctx=False)
+        self._h = h
+        self._keep = {}
+
+    def _check(self, st, ctx=True):
+        if st != 0:
+            msg = self._L.swf_status_string(st).decode()
+            if ctx and getattr(self, "_h", None):
+                msg += ": " + self._L.swf_last_error(self._h).decode()
+            raise SwfError(f"libswiftwrf status {st} ({msg})")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.swf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- scenes -------------------------------------------------------------
+    def upload_scene(self, gaussians: dict, H: int, W: int, mlp=None, room=((0, 0, 0), (6, 6, 3))) -> int:
+        """Upload FP32 Gaussians (numpy arrays, host) and optional MLP weights
+        (Ws, bs) lists of FP32 arrays with W_l of shape (out, in)."""
+        cols = {k: np.ascontiguousarray(gaussians[k], dtype=np.float32) for k in PARAMS}
+        n = len(cols["mean_x"])
+        g = _Gaussians(n=n, **{k: cols[k].ctypes.data for k in PARAMS})
+        m = None
+        keep = [cols]
+        if mlp is not None:
+            Ws, bs = mlp
+            Ws = [np.ascontiguousarray(w, dtype=np.float32) for w in Ws]
+            bs = [np.ascontiguousarray(b, dtype=np.float32) for b in bs]
+            keep += [Ws, bs]
+            m = _Mlp(mean_bands=6, tx_bands=10, hidden=Ws[0].shape[0], n_hidden=len(Ws) - 1)
+            for l in range(len(Ws)):
+                m.weight[l] = Ws[l].ctypes.data
+                m.bias[l] = bs[l].ctypes.data
+            for k in range(3):
+                m.room_lo[k] = room[0][k]
+                m.room_hi[k] = room[1][k]
+        sid = ctypes.c_int32()
+        self._check(self._L.swf_scene_upload(self._h, ctypes.byref(g), ctypes.byref(m) if m is not None else None,
+                                             H, W, 0, ctypes.byref(sid)))
+        self._keep[sid.value] = (H, W, n, mlp is not None)
+        return sid.value
+
+    def release_scene(self, sid: int):
+        self._check(self._L.swf_scene_release(self._h, sid))
+        self._keep.pop(sid, None)
+
+    def scene_bytes(self, sid: int) -> int:
+        v = ctypes.c_uint64()
+        self._check(self._L.swf_scene_bytes(self._h, sid, ctypes.byref(v)))
+        return v.value
+
+    def scene_shape(self, sid: int):
+        return self._keep[sid]
+
+    # ---- render ---------------------------------------------------------------
+    def render(self, sid: int, tx=None, flags: int = 0, batch: int | None = None, out=None, aux=None):
+        torch = self.torch
+        H, W, n, _ = self._keep[sid]
+        if tx is not None:
+            assert tx.is_cuda and tx.dtype == torch.float32 and tx.is_contiguous() and tx.shape[-1] == 3
+            batch = tx.shape[0]
+        batch = batch or 1
+        if out is None:
+            out = torch.empty((batch, H, W), device=self.device, dtype=torch.float32)
+        if (flags & KEEP_AUX) and aux is None:
+            aux = torch.empty((2, batch, H, W), device=self.device, dtype=torch.float32)
+        self._check(self._L.swf_render(self._h, sid, _ptr(tx), batch, flags, _ptr(out), _ptr(aux), _stream()))
+        return (out, aux) if (flags & KEEP_AUX) else out
+
+    def render_backward(self, sid: int, tx, flags: int, grad_out, aux, grads: dict):
+        gr = _Grads()
+        for k in PARAMS[:7]:
+            setattr(gr, k, grads[k].data_ptr() if grads.get(k) is not None else None)
+        for l, w in enumerate(grads.get("weight", []) or []):
+            gr.weight[l] = w.data_ptr() if w is not None else None
+        for l, b in enumerate(grads.get("bias", []) or []):
+            gr.bias[l] = b.data_ptr() if b is not None else None
+        batch = tx.shape[0] if tx is not None else grad_out.shape[0]
+        self._check(self._L.swf_render_backward(self._h, sid, _ptr(tx), batch, flags, _ptr(grad_out), _ptr(aux),
+                                                ctypes.byref(gr), _stream()))
+
+    def l1_loss(self, pred, target, want_grad=True):
+        torch = self.torch
+        loss = torch.empty((), device=self.device, dtype=torch.float32)
+        grad = torch.empty_like(pred) if want_grad else None
+        self._check(self._L.swf_l1_loss(self._h, _ptr(pred), _ptr(target), pred.numel(), _ptr(loss), _ptr(grad),
+                                        _stream()))
+        return loss, grad
+
+    # ---- timing ---------------------------------------------------------------
+    def stage_timing(self, enable: bool):
+        self._check(self._L.swf_stage_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int64 * len(STAGES))()
+        n = ctypes.c_int32(len(STAGES))
+        self._check(self._L.swf_stage_times(self._h, ms, cnt, ctypes.byref(n)))
+        return {STAGES[i]: (ms[i], cnt[i]) for i in range(n.value)}
+
+    # ---- debug / step-level ------------------------------------------------------
+    def debug_deform(self, sid: int, tx, flags: int = 0):
+        torch = self.torch
+        H, W, n, _ = self._keep[sid]
+        d = torch.empty((tx.shape[0], n, 7), device=self.device, dtype=torch.float32)
+        self._check(self._L.swf_debug_deform(self._h, sid, _ptr(tx), tx.shape[0], flags, _ptr(d), _stream()))
+        return d
+
+    def debug_keys(self, batch: int, n: int, tiles: int, capacity: int | None = None):
+        self.torch.cuda.synchronize()
+        nk = ctypes.c_uint64()
+        self._check(self._L.swf_debug_keys(self._h, None, None, None, None, None, ctypes.byref(nk), 0))
+        nkeys = nk.value
+        counts = np.zeros(batch * n, np.uint32)
+        offsets = np.zeros(batch * n, np.uint32)
+        keys = np.zeros(max(nkeys, 1), np.uint64)
+        vals = np.zeros(max(nkeys, 1), np.uint64)
+        ranges = np.zeros((batch * tiles, 2), np.uint32)
+        P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._check(self._L.swf_debug_keys(self._h, P(counts), P(offsets), P(keys), P(vals), P(ranges),
+                                           ctypes.byref(nk), nkeys))
+        return dict(counts=counts, offsets=offsets, keys=keys[:nkeys], values=vals[:nkeys], ranges=ranges)
+
+    def radix_sort(self, keys, values, begin_bit=0, end_bit=None):
+        kb = keys.element_size()
+        end_bit = 8 * kb if end_bit is None else end_bit
+        self._check(self._L.swf_radix_sort(self._h, _ptr(keys), _ptr(values), keys.numel(), kb, begin_bit, end_bit,
+                                           _stream()))
+
+    def exclusive_scan(self, counts):
+        torch = self.torch
+        off = torch.empty_like(counts)
+        tot = torch.zeros(1, device=self.device, dtype=torch.int64)
+        self._check(self._L.swf_exclusive_scan(self._h, _ptr(counts), _ptr(off), _ptr(tot), counts.numel(), _stream()))
+        return off, tot

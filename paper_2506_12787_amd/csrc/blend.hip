@@ -1,0 +1,108 @@
+// Per-tile front-to-back blending (Sec. 3.2 blending rule applied to the 2D
+// Gaussian kernel of Sec. 4.1, one workgroup per (query, tile)).
+//
+// Each workgroup owns one TILE x TILE pixel tile, one pixel per thread. It walks
+// the tile's depth-ordered list in batches of TILE*TILE records: every thread
+// stages one record into LDS (mean re-expressed relative to the enclosing
+// 64-pixel block, in full precision from the hi + lo pair), then every thread composites its
+// pixel over the batch. A block-wide vote ends the walk once every pixel has
+// reached the transmittance floor.
+#include "kernels.h"
+#include "swf_device.h"
+
+namespace swf {
+
+namespace {
+
+template <int TILE>
+__global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* __restrict__ ranges,
+                                                                    const uint32_t* __restrict__ vals,
+                                                                    const float4* __restrict__ geo,
+                                                                    const float4* __restrict__ wm,
+                                                                    const float2* __restrict__ oa, int H, int W,
+                                                                    int TW, int tiles, float* __restrict__ out,
+                                                                    float* __restrict__ aux_T,
+                                                                    uint32_t* __restrict__ aux_last) {
+    constexpr int kN = TILE * TILE;
+    __shared__ float2 s_pos[kN];
+    __shared__ float4 s_wm[kN];
+    __shared__ float2 s_oa[kN];
+
+    const int gtile = blockIdx.x;
+    const int b = gtile / tiles;
+    const int t = gtile - b * tiles;
+    const int tx = t % TW, ty = t / TW;
+    const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+    const int px = tx * TILE + lx, py = ty * TILE + ly;
+    const bool inside = px < W && py < H;
+    // Offsets are taken relative to the enclosing 64-pixel block, the same for
+    // every tile size <= 64, so the arithmetic does not depend on the tiling.
+    const int bx0 = (tx * TILE) & ~63, by0 = (ty * TILE) & ~63;
+    const float x0 = (float)bx0, y0 = (float)by0;
+    const float fx = (float)(px - bx0), fy = (float)(py - by0);
+
+    const uint2 rg = ranges[gtile];
+    float T = 1.0f, C = 0.0f;
+    uint32_t last = 0;
+    bool done = !inside;
+
+    for (uint32_t start = rg.x; start < rg.y; start += kN) {
+        if (__syncthreads_count(done) == kN) break;
+        const uint32_t i = start + threadIdx.x;
+        if (i < rg.y) {
+            const uint32_t v = vals[i];
+            const float4 g = geo[v];
+            s_pos[threadIdx.x] = make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
+            s_wm[threadIdx.x] = wm[v];
+            s_oa[threadIdx.x] = oa[v];
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)kN, rg.y - start);
+        if (!done) {
+            for (int j = 0; j < cnt; ++j) {
+                const float2 p = s_pos[j];
+                const float4 m = s_wm[j];
+                const float dx = fx - p.x, dy = fy - p.y;
+                const float u = fmaf(m.x, dx, m.y * dy);
+                const float w = fmaf(m.z, dx, m.w * dy);
+                const float q = fmaf(u, u, w * w);
+                if (q > kQMax) continue;
+                const float2 o = s_oa[j];
+                const float a = fminf(kAlphaMax, o.x * __builtin_amdgcn_exp2f(q * kNegHalfLog2e));
+                if (a < kAlphaMin) continue;
+                const float Tn = T * (1.0f - a);
+                if (Tn < kTMin) {
+                    done = true;
+                    break;
+                }
+                C = fmaf(o.y * a, T, C);
+                T = Tn;
+                last = start + (uint32_t)j + 1u - rg.x;
+            }
+        }
+    }
+    if (inside) {
+        const size_t pix = (size_t)b * H * W + (size_t)py * W + px;
+        out[pix] = C;
+        if (aux_T) {
+            aux_T[pix] = T;
+            aux_last[pix] = last;
+        }
+    }
+}
+
+}  // namespace
+
+void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
+                          float* out, float* aux_T, uint32_t* aux_last, hipStream_t st) {
+    const unsigned blocks = (unsigned)(B * g.tiles);
+    if (!blocks) return;
+    if (g.tile == 8)
+        blend_forward_kernel<8><<<blocks, 64, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles, out,
+                                                       aux_T, aux_last);
+    else
+        blend_forward_kernel<16><<<blocks, 256, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles,
+                                                         out, aux_T, aux_last);
+}
+
+}  // namespace swf

@@ -1,0 +1,78 @@
+// Host-side launch interface between the runtime (runtime.cpp) and the HIP
+// kernel translation units of libswiftwrf.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swf {
+
+// Device-resident scene. Gaussians are stored in ascending (depth, id) order
+// ("sorted position" p); perm[p] is the caller's original index. Positions
+// p >= n_live (NaN depth) never render.
+struct DevScene {
+    int n = 0, n_live = 0, H = 0, W = 0;
+    float *mx = nullptr, *my = nullptr, *lsx = nullptr, *lsy = nullptr;
+    float *rot = nullptr, *logit = nullptr, *amp = nullptr;
+    uint32_t *dbits = nullptr;  // order-preserving depth bits
+    uint32_t *perm = nullptr;   // sorted position -> original id
+    uint32_t *inv_perm = nullptr;  // original id -> sorted position
+    // deformation MLP (hidden width 256)
+    bool has_mlp = false;
+    int hidden = 0, n_hidden = 0, in_dim = 0;
+    float *w[8] = {}, *b[8] = {};   // FP32 master, row-major [out][in]
+    float *w1m_t = nullptr;         // [26][hidden]   layer-1 mean part, in-major
+    float *wh_t[8] = {};            // [hidden][hidden] hidden->hidden, in-major
+    float *wo_t = nullptr;          // [hidden][7]
+    uint16_t *bf_stream = nullptr;  // BF16 weights in MFMA fragment order (16 KiB chunks)
+    uint16_t *bf_mfeat = nullptr;   // [n][32] BF16 gamma(mu_hat), zero padded
+    float room_lo[3] = {0, 0, 0}, room_hi[3] = {6, 6, 3};
+    uint64_t bytes = 0;
+};
+
+struct Records {
+    float4 *geo = nullptr;
+    float4 *wm = nullptr;
+    float2 *oa = nullptr;
+    uint2 *rect = nullptr;
+    uint32_t *count = nullptr;
+};
+
+struct Grid {
+    int H, W, tile, TW, TH, tiles;  // tiles per query
+};
+
+// pe_mlp.hip
+void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hipStream_t st);
+void launch_mlp_fp32(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
+                     float* delta_out, hipStream_t st);
+void launch_preprocess_static(const DevScene& s, int B, const Grid& g, const Records& r, hipStream_t st);
+void launch_permute_delta(const float* delta_sorted, const uint32_t* perm, int B, int n, float* delta_out,
+                          hipStream_t st);
+
+// mlp_bf16.hip
+bool bf16_available();
+void compute_mean_features_bf16(DevScene& s, hipStream_t st);
+void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
+                     float* delta_out, hipStream_t st);
+
+// sort.hip
+int scan_grid(int64_t n);
+size_t scan_scratch_bytes(int64_t n);
+void launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t* total, int64_t n, void* scratch,
+                           hipStream_t st);
+void launch_emit_keys(const Records& r, const uint32_t* offsets, const uint32_t* dbits, int B, int N,
+                      const Grid& g, uint64_t capacity, bool full_keys, void* keys, uint32_t* vals,
+                      uint32_t* status, hipStream_t st);
+size_t radix_scratch_bytes(int64_t n);
+// Sorts (keys, vals) on bits [begin_bit, end_bit); returns 1 if the result
+// ended in the alternate buffers (kalt, valt), 0 if in (keys, vals).
+int launch_radix_sort(void* keys, uint32_t* vals, void* kalt, uint32_t* valt, int64_t n, int key_bytes,
+                      int begin_bit, int end_bit, void* scratch, hipStream_t st);
+void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gtiles, uint2* ranges,
+                        hipStream_t st);
+
+// blend.hip
+void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
+                          float* out, float* aux_T, uint32_t* aux_last, hipStream_t st);
+
+}  // namespace swf

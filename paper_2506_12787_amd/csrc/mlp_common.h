@@ -1,0 +1,85 @@
+// Arguments and the fused epilogue shared by the FP32 and BF16 deformation-MLP
+// kernels: residuals -> deformed Gaussian (Sec. 4.2, G^s = G^0 + dG) -> record.
+#pragma once
+#include "kernels.h"
+#include "swf_device.h"
+
+namespace swf {
+
+__device__ __forceinline__ void write_record(const Records& r, size_t row, const PairOut& o) {
+    r.geo[row] = o.geo;
+    r.wm[row] = o.wm;
+    r.oa[row] = o.oa;
+    r.rect[row] = make_uint2(o.rect_x, o.rect_y);
+    r.count[row] = o.count;
+}
+
+struct MlpArgs {
+    int N, B, H, W, TW, TH, n_live, n_mid;
+    float inv_tile;
+    int paper_mask;
+    const float *mx, *my, *lsx, *lsy, *rot, *logit, *amp;
+    const float* qs;
+    const float* w1m_t;
+    const float* wh_t[7];
+    const float* bh[7];
+    const float* wo_t;
+    const float* bo;
+    Records rec;
+    float* delta_out;
+};
+
+
+// Epilogue shared by both MLP kernels: residuals -> deformed Gaussian -> record.
+__device__ __forceinline__ void deform_epilogue(const MlpArgs& a, size_t row, int p, const float* d) {
+    float dv[kOut];
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) dv[k] = d[k];
+    if (a.paper_mask) dv[2] = dv[3] = dv[4] = 0.0f;
+    if (a.delta_out) {
+#pragma unroll
+        for (int k = 0; k < kOut; ++k) a.delta_out[row * kOut + k] = dv[k];
+    }
+    PairOut o;
+    if (p < a.n_live) {
+        o = preprocess_pair(a.mx[p], a.my[p], dv[0], dv[1], a.lsx[p] + dv[2], a.lsy[p] + dv[3], a.rot[p] + dv[4],
+                            a.logit[p] + dv[5], a.amp[p] + dv[6], a.W, a.H, a.TW, a.TH, a.inv_tile);
+    } else {
+        o.geo = make_float4(0, 0, 0, 0);
+        o.wm = make_float4(0, 0, 0, 0);
+        o.oa = make_float2(0, 0);
+        o.rect_x = o.rect_y = 0;
+        o.count = 0;
+    }
+    write_record(a.rec, row, o);
+}
+
+inline MlpArgs make_args(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
+                  float* delta_out) {
+    MlpArgs a{};
+    a.N = s.n;
+    a.B = B;
+    a.H = g.H;
+    a.W = g.W;
+    a.TW = g.TW;
+    a.TH = g.TH;
+    a.n_live = s.n_live;
+    a.inv_tile = 1.0f / (float)g.tile;
+    a.paper_mask = paper_mask ? 1 : 0;
+    a.mx = s.mx; a.my = s.my; a.lsx = s.lsx; a.lsy = s.lsy; a.rot = s.rot; a.logit = s.logit; a.amp = s.amp;
+    a.qs = qs;
+    a.w1m_t = s.w1m_t;
+    a.n_mid = s.has_mlp ? s.n_hidden - 1 : 0;
+    for (int l = 0; l < a.n_mid && l < 7; ++l) {
+        a.wh_t[l] = s.wh_t[l];
+        a.bh[l] = s.b[l + 1];
+    }
+    a.wo_t = s.wo_t;
+    a.bo = s.has_mlp ? s.b[s.n_hidden] : nullptr;
+    a.rec = r;
+    a.delta_out = delta_out;
+    return a;
+}
+
+
+}  // namespace swf

@@ -1,0 +1,672 @@
+// Host runtime of libswiftwrf: context, scene registry, workspace, the render
+// pipeline and the C ABI declared in include/swiftwrf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/swiftwrf.h"
+#include "kernels.h"
+#include "runtime.h"
+
+using namespace swf;
+
+namespace swf {
+
+const char* status_name(swf_status s) {
+    switch (s) {
+        case SWF_OK: return "ok";
+        case SWF_E_INVALID: return "invalid argument";
+        case SWF_E_OOM: return "out of memory";
+        case SWF_E_DEVICE: return "HIP runtime error";
+        case SWF_E_NOT_FOUND: return "not found";
+        case SWF_E_OVERFLOW: return "capacity exceeded";
+        case SWF_E_STATE: return "invalid state";
+        case SWF_E_PENDING: return "pending";
+        default: return "unknown status";
+    }
+}
+
+swf_status Ctx::fail(swf_status s, const std::string& msg) {
+    err = msg;
+    return s;
+}
+
+swf_status Ctx::hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return SWF_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? SWF_E_OOM : SWF_E_DEVICE;
+}
+
+swf_status Buf::reserve(Ctx* c, size_t n, hipStream_t st) {
+    if (n <= cap) return SWF_OK;
+    if (ptr) {
+        if (st) hipStreamSynchronize(st);
+        hipDeviceSynchronize();
+        hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+    }
+    size_t want = n + n / 4 + 256;
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        return c->hip(e, "hipMalloc(workspace)");
+    }
+    cap = want;
+    return SWF_OK;
+}
+
+void Buf::release() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+}
+
+static int bits_for(uint64_t m) {
+    int b = 0;
+    while (b < 64 && (1ull << b) < m) ++b;
+    return b;
+}
+
+Grid make_grid(int H, int W, int tile) {
+    Grid g;
+    g.H = H;
+    g.W = W;
+    g.tile = tile;
+    g.TW = (W + tile - 1) / tile;
+    g.TH = (H + tile - 1) / tile;
+    g.tiles = g.TW * g.TH;
+    return g;
+}
+
+void Ctx::stage_begin(int stage, hipStream_t st) {
+    if (!timing) return;
+    TimedStage t;
+    t.stage = stage;
+    if (!event_pool.empty()) {
+        t.a = event_pool.back();
+        event_pool.pop_back();
+    } else {
+        hipEventCreate(&t.a);
+    }
+    if (!event_pool.empty()) {
+        t.b = event_pool.back();
+        event_pool.pop_back();
+    } else {
+        hipEventCreate(&t.b);
+    }
+    hipEventRecord(t.a, st);
+    pending.push_back(t);
+}
+
+void Ctx::stage_end(hipStream_t st) {
+    if (!timing || pending.empty()) return;
+    hipEventRecord(pending.back().b, st);
+    if (pending.size() > 8192) resolve_timing();
+}
+
+void Ctx::resolve_timing() {
+    for (auto& t : pending) {
+        hipEventSynchronize(t.b);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            stage_ms[t.stage] += ms;
+            stage_n[t.stage] += 1;
+        }
+        event_pool.push_back(t.a);
+        event_pool.push_back(t.b);
+    }
+    pending.clear();
+}
+
+Scene* Ctx::scene(int id) {
+    auto it = scenes.find(id);
+    return it == scenes.end() ? nullptr : it->second;
+}
+
+static void free_scene(Scene* s) {
+    DevScene& d = s->d;
+    for (void* p : s->allocs) hipFree(p);
+    s->allocs.clear();
+    (void)d;
+    delete s;
+}
+
+// Allocate and copy a host array to the device, tracked by the scene.
+template <typename T>
+static swf_status upload(Ctx* c, Scene* s, T** dst, const T* src, size_t n) {
+    *dst = nullptr;
+    const size_t bytes = std::max<size_t>(n * sizeof(T), 16);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return c->hip(e, "hipMalloc(scene)");
+    s->allocs.push_back(p);
+    s->d.bytes += bytes;
+    if (n) {
+        e = hipMemcpy(p, src, n * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return c->hip(e, "hipMemcpy(scene)");
+    }
+    *dst = reinterpret_cast<T*>(p);
+    return SWF_OK;
+}
+
+static swf_status fetch(Ctx* c, std::vector<float>& dst, const float* src, size_t n, bool dev) {
+    dst.resize(n);
+    if (!n) return SWF_OK;
+    if (!src) return c->fail(SWF_E_INVALID, "null parameter array");
+    if (dev) return c->hip(hipMemcpy(dst.data(), src, n * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy(D2H)");
+    std::memcpy(dst.data(), src, n * sizeof(float));
+    return SWF_OK;
+}
+
+static uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+swf_status Ctx::upload_scene(const swf_gaussians* g, const swf_mlp* mlp, int H, int W, bool dev, int* id) {
+    if (!g || !id || g->n < 0) return fail(SWF_E_INVALID, "null gaussians/id or n < 0");
+    if (H < 1 || H > 4096 || W < 1 || W > 4096) return fail(SWF_E_INVALID, "H and W must lie in [1, 4096]");
+    if ((int64_t)g->n * 1 > (int64_t)INT32_MAX) return fail(SWF_E_INVALID, "n too large");
+    const size_t n = (size_t)g->n;
+    std::vector<float> col[8];
+    const float* src[8] = {g->mean_x, g->mean_y, g->log_scale_x, g->log_scale_y,
+                           g->rotation, g->opacity_logit, g->amplitude, g->depth};
+    for (int k = 0; k < 8; ++k) {
+        swf_status st = fetch(this, col[k], src[k], n, dev);
+        if (st) return st;
+    }
+    if (mlp) {
+        if (mlp->mean_bands != kMeanBands || mlp->tx_bands != kTxBands)
+            return fail(SWF_E_INVALID, "positional encoding bands must be 6 (mean) and 10 (tx)");
+        if (mlp->hidden != 256) return fail(SWF_E_INVALID, "hidden width must be 256");
+        if (mlp->n_hidden < 1 || mlp->n_hidden > SWF_MAX_LAYERS - 1)
+            return fail(SWF_E_INVALID, "n_hidden must lie in [1, 7]");
+        for (int l = 0; l <= mlp->n_hidden; ++l)
+            if (!mlp->weight[l] || !mlp->bias[l]) return fail(SWF_E_INVALID, "null MLP weight or bias");
+        for (int k = 0; k < 3; ++k)
+            if (!(mlp->room_hi[k] > mlp->room_lo[k])) return fail(SWF_E_INVALID, "room_hi must exceed room_lo");
+    }
+    // (depth, id) order; NaN depths last (never rendered)
+    std::vector<uint32_t> perm(n);
+    for (size_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+    const std::vector<float>& dep = col[7];
+    std::stable_sort(perm.begin(), perm.end(), [&](uint32_t a, uint32_t b) {
+        const bool na = std::isnan(dep[a]), nb = std::isnan(dep[b]);
+        if (na != nb) return !na;
+        if (na) return false;
+        return dep[a] < dep[b];
+    });
+    size_t n_live = 0;
+    for (size_t i = 0; i < n; ++i) n_live += !std::isnan(dep[i]);
+    std::vector<float> sorted[7];
+    for (int k = 0; k < 7; ++k) {
+        sorted[k].resize(n);
+        for (size_t p = 0; p < n; ++p) sorted[k][p] = col[k][perm[p]];
+    }
+    std::vector<uint32_t> dbits(n), inv(n);
+    for (size_t p = 0; p < n; ++p) {
+        dbits[p] = depth_key_bits(dep[perm[p]]);
+        inv[perm[p]] = (uint32_t)p;
+    }
+
+    Scene* s = new (std::nothrow) Scene();
+    if (!s) return fail(SWF_E_OOM, "host allocation");
+    DevScene& d = s->d;
+    d.n = (int)n;
+    d.n_live = (int)n_live;
+    d.H = H;
+    d.W = W;
+    swf_status st = SWF_OK;
+    float** dst[7] = {&d.mx, &d.my, &d.lsx, &d.lsy, &d.rot, &d.logit, &d.amp};
+    for (int k = 0; k < 7 && !st; ++k) st = upload(this, s, dst[k], sorted[k].data(), n);
+    if (!st) st = upload(this, s, &d.dbits, dbits.data(), n);
+    if (!st) st = upload(this, s, &d.perm, perm.data(), n);
+    if (!st) st = upload(this, s, &d.inv_perm, inv.data(), n);
+    s->host_dbits = dbits;
+    s->host_perm = perm;
+    if (!st && mlp) {
+        d.has_mlp = true;
+        d.hidden = mlp->hidden;
+        d.n_hidden = mlp->n_hidden;
+        d.in_dim = kMeanFeat + kTxFeat;
+        for (int k = 0; k < 3; ++k) {
+            d.room_lo[k] = mlp->room_lo[k];
+            d.room_hi[k] = mlp->room_hi[k];
+        }
+        const int Hd = d.hidden;
+        std::vector<int> rows(d.n_hidden + 1), cols(d.n_hidden + 1);
+        for (int l = 0; l <= d.n_hidden; ++l) {
+            rows[l] = l == d.n_hidden ? kOut : Hd;
+            cols[l] = l == 0 ? d.in_dim : Hd;
+        }
+        std::vector<std::vector<float>> Wh(d.n_hidden + 1), Bh(d.n_hidden + 1);
+        for (int l = 0; l <= d.n_hidden && !st; ++l) {
+            st = fetch(this, Wh[l], mlp->weight[l], (size_t)rows[l] * cols[l], dev);
+            if (!st) st = fetch(this, Bh[l], mlp->bias[l], (size_t)rows[l], dev);
+            if (!st) st = upload(this, s, &d.w[l], Wh[l].data(), Wh[l].size());
+            if (!st) st = upload(this, s, &d.b[l], Bh[l].data(), Bh[l].size());
+        }
+        if (!st) {
+            std::vector<float> t((size_t)kMeanFeat * Hd);
+            for (int k = 0; k < kMeanFeat; ++k)
+                for (int j = 0; j < Hd; ++j) t[(size_t)k * Hd + j] = Wh[0][(size_t)j * d.in_dim + k];
+            st = upload(this, s, &d.w1m_t, t.data(), t.size());
+        }
+        for (int l = 1; l < d.n_hidden && !st; ++l) {
+            std::vector<float> t((size_t)Hd * Hd);
+            for (int k = 0; k < Hd; ++k)
+                for (int j = 0; j < Hd; ++j) t[(size_t)k * Hd + j] = Wh[l][(size_t)j * Hd + k];
+            st = upload(this, s, &d.wh_t[l - 1], t.data(), t.size());
+        }
+        if (!st) {
+            std::vector<float> t((size_t)Hd * kOut);
+            for (int k = 0; k < Hd; ++k)
+                for (int o = 0; o < kOut; ++o) t[(size_t)k * kOut + o] = Wh[d.n_hidden][(size_t)o * Hd + k];
+            st = upload(this, s, &d.wo_t, t.data(), t.size());
+        }
+        // BF16 weight stream for the MFMA kernel: per tile of pairs the kernel
+        // consumes chunks of 16 fragments; fragment (t, c) of a layer holds, for
+        // lane l = 16 g + r and element j, W[16 t + r][k(c, g, j)]. Layer 1 (mean
+        // part, K = 26 padded to 32): k = 8 g + j. Later layers: k = 32 c + f(g, j)
+        // with f(g, j) = j < 4 ? 4 g + j : 16 + 4 g + j - 4, matching the register
+        // layout of the previous layer's output tiles. The output layer (7 rows
+        // padded to 16) fills one chunk with its 8 k-chunk fragments.
+        if (!st) {
+            const int n_chunks = 2 + 8 * (d.n_hidden - 1);
+            std::vector<uint16_t> t((size_t)n_chunks * 8192, 0);
+            auto fk = [](int c, int g, int j) { return 32 * c + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4)); };
+            for (int tt = 0; tt < 16; ++tt)
+                for (int l = 0; l < 64; ++l)
+                    for (int j = 0; j < 8; ++j) {
+                        const int row = 16 * tt + (l & 15), k = 8 * (l >> 4) + j;
+                        const float w = k < kMeanFeat ? Wh[0][(size_t)row * d.in_dim + k] : 0.f;
+                        t[(size_t)tt * 512 + l * 8 + j] = f32_to_bf16_rne(w);
+                    }
+            for (int L = 1; L < d.n_hidden; ++L)
+                for (int c = 0; c < 8; ++c) {
+                    const size_t ch = (size_t)(1 + 8 * (L - 1) + c) * 8192;
+                    for (int tt = 0; tt < 16; ++tt)
+                        for (int l = 0; l < 64; ++l)
+                            for (int j = 0; j < 8; ++j) {
+                                const int row = 16 * tt + (l & 15), k = fk(c, l >> 4, j);
+                                t[ch + (size_t)tt * 512 + l * 8 + j] = f32_to_bf16_rne(Wh[L][(size_t)row * Hd + k]);
+                            }
+                }
+            {
+                const size_t ch = (size_t)(n_chunks - 1) * 8192;
+                for (int c = 0; c < 8; ++c)
+                    for (int l = 0; l < 64; ++l)
+                        for (int j = 0; j < 8; ++j) {
+                            const int o = l & 15, k = fk(c, l >> 4, j);
+                            const float w = o < kOut ? Wh[d.n_hidden][(size_t)o * Hd + k] : 0.f;
+                            t[ch + (size_t)c * 512 + l * 8 + j] = f32_to_bf16_rne(w);
+                        }
+            }
+            st = upload(this, s, &d.bf_stream, t.data(), t.size());
+        }
+        if (!st) {
+            std::vector<uint16_t> z((size_t)n * 32, 0);
+            st = upload(this, s, &d.bf_mfeat, z.data(), z.size());
+            if (!st) {
+                compute_mean_features_bf16(d, nullptr);
+                st = hip(hipDeviceSynchronize(), "mean features");
+            }
+        }
+    }
+    if (st) {
+        free_scene(s);
+        return st;
+    }
+    const int sid = next_scene++;
+    scenes[sid] = s;
+    *id = sid;
+    return SWF_OK;
+}
+
+swf_status Ctx::release_scene(int id) {
+    auto it = scenes.find(id);
+    if (it == scenes.end()) return fail(SWF_E_NOT_FOUND, "unknown scene id");
+    hipDeviceSynchronize();
+    free_scene(it->second);
+    scenes.erase(it);
+    return SWF_OK;
+}
+
+// Enqueue preprocess (+ MLP) for B queries into the workspace records.
+swf_status Ctx::enqueue_preprocess(Scene* sc, const float* tx, int B, int flags, const Grid& g, float* delta_sorted,
+                                   hipStream_t st) {
+    const DevScene& d = sc->d;
+    const bool deform = !(flags & SWF_NO_DEFORM);
+    if (deform && (flags & SWF_MLP_BF16) && !bf16_available())
+        return fail(SWF_E_STATE, "BF16 MLP kernel is not available in this build");
+    const size_t pairs = (size_t)B * d.n;
+    swf_status s = SWF_OK;
+    if ((s = ws_geo.reserve(this, pairs * sizeof(float4), st))) return s;
+    if ((s = ws_wm.reserve(this, pairs * sizeof(float4), st))) return s;
+    if ((s = ws_oa.reserve(this, pairs * sizeof(float2), st))) return s;
+    if ((s = ws_rect.reserve(this, pairs * sizeof(uint2), st))) return s;
+    if ((s = ws_count.reserve(this, pairs * sizeof(uint32_t), st))) return s;
+    rec.geo = (float4*)ws_geo.ptr;
+    rec.wm = (float4*)ws_wm.ptr;
+    rec.oa = (float2*)ws_oa.ptr;
+    rec.rect = (uint2*)ws_rect.ptr;
+    rec.count = (uint32_t*)ws_count.ptr;
+    if (deform) {
+        if (!d.has_mlp) return fail(SWF_E_INVALID, "scene has no deformation MLP (use SWF_NO_DEFORM)");
+        if (!tx) return fail(SWF_E_INVALID, "tx is NULL");
+        if ((s = ws_qs.reserve(this, (size_t)B * d.hidden * sizeof(float), st))) return s;
+        stage_begin(SWF_STAGE_TX, st);
+        launch_tx_features(d, tx, B, (float*)ws_qs.ptr, st);
+        stage_end(st);
+        stage_begin(SWF_STAGE_MLP, st);
+        if (flags & SWF_MLP_BF16)
+            launch_mlp_bf16(d, (const float*)ws_qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, rec, delta_sorted, st);
+        else
+            launch_mlp_fp32(d, (const float*)ws_qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, rec, delta_sorted, st);
+        stage_end(st);
+    } else {
+        stage_begin(SWF_STAGE_MLP, st);
+        launch_preprocess_static(d, B, g, rec, st);
+        stage_end(st);
+    }
+    return hip(hipGetLastError(), "preprocess launch");
+}
+
+swf_status Ctx::render(int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st) {
+    Scene* sc = scene(sid);
+    if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
+    if (B < 1) return fail(SWF_E_INVALID, "batch must be >= 1");
+    if (!out) return fail(SWF_E_INVALID, "out is NULL");
+    if ((flags & SWF_KEEP_AUX) && !aux) return fail(SWF_E_INVALID, "SWF_KEEP_AUX needs aux");
+    const DevScene& d = sc->d;
+    if ((uint64_t)B * (uint64_t)d.n >= (1ull << 32)) return fail(SWF_E_INVALID, "batch * n must be < 2^32");
+    const Grid g = make_grid(d.H, d.W, (flags & SWF_TILE8) ? 8 : 16);
+    if ((uint64_t)B * g.tiles >= (1ull << 31)) return fail(SWF_E_INVALID, "batch * tiles too large");
+    hipSetDevice(device);
+    swf_status s = enqueue_preprocess(sc, tx, B, flags, g, nullptr, st);
+    if (s) return s;
+    const int64_t pairs = (int64_t)B * d.n;
+    if ((s = ws_off.reserve(this, (size_t)pairs * sizeof(uint32_t) + 16, st))) return s;
+    if ((s = ws_scan.reserve(this, scan_scratch_bytes(pairs) + 64, st))) return s;
+    stage_begin(SWF_STAGE_SCAN, st);
+    launch_exclusive_scan(rec.count, (uint32_t*)ws_off.ptr, total_dev, pairs, ws_scan.ptr, st);
+    stage_end(st);
+    if ((s = hip(hipMemcpyAsync(total_host, total_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, st), "total D2H")))
+        return s;
+    if ((s = hip(hipStreamSynchronize(st), "stream sync"))) return s;
+    const uint64_t nk = *total_host;
+    if (nk >= (1ull << 32)) return fail(SWF_E_OVERFLOW, "more than 2^32 - 1 keys; render a smaller batch");
+    const bool full = (flags & SWF_FULL_SORT) != 0;
+    const size_t kb = full ? 8 : 4;
+    if ((s = ws_keys.reserve(this, nk * kb + 16, st))) return s;
+    if ((s = ws_keys2.reserve(this, nk * kb + 16, st))) return s;
+    if ((s = ws_vals.reserve(this, nk * 4 + 16, st))) return s;
+    if ((s = ws_vals2.reserve(this, nk * 4 + 16, st))) return s;
+    if ((s = ws_hist.reserve(this, radix_scratch_bytes((int64_t)nk) + 64, st))) return s;
+    const int64_t n_gt = (int64_t)B * g.tiles;
+    if ((s = ws_ranges.reserve(this, (size_t)n_gt * sizeof(uint2), st))) return s;
+    stage_begin(SWF_STAGE_EMIT, st);
+    launch_emit_keys(rec, (const uint32_t*)ws_off.ptr, d.dbits, B, d.n, g, nk, full, ws_keys.ptr,
+                     (uint32_t*)ws_vals.ptr, status_dev, st);
+    stage_end(st);
+    const int tbits = bits_for((uint64_t)n_gt);
+    stage_begin(SWF_STAGE_SORT, st);
+    const int flip = launch_radix_sort(ws_keys.ptr, (uint32_t*)ws_vals.ptr, ws_keys2.ptr, (uint32_t*)ws_vals2.ptr,
+                                       (int64_t)nk, (int)kb, 0, full ? 32 + tbits : tbits, ws_hist.ptr, st);
+    stage_end(st);
+    void* skeys = flip ? ws_keys2.ptr : ws_keys.ptr;
+    uint32_t* svals = (uint32_t*)(flip ? ws_vals2.ptr : ws_vals.ptr);
+    stage_begin(SWF_STAGE_RANGES, st);
+    launch_tile_ranges(skeys, (int)kb, (int64_t)nk, n_gt, (uint2*)ws_ranges.ptr, st);
+    stage_end(st);
+    float* auxT = nullptr;
+    uint32_t* auxL = nullptr;
+    if (flags & SWF_KEEP_AUX) {
+        auxT = (float*)aux;
+        auxL = (uint32_t*)((char*)aux + sizeof(float) * (size_t)B * d.H * d.W);
+    }
+    stage_begin(SWF_STAGE_BLEND, st);
+    launch_blend_forward((const uint2*)ws_ranges.ptr, svals, rec, B, g, out, auxT, auxL, st);
+    stage_end(st);
+    last.valid = true;
+    last.scene = sid;
+    last.B = B;
+    last.N = d.n;
+    last.flags = flags;
+    last.grid = g;
+    last.n_keys = nk;
+    last.full = full;
+    last.keys = skeys;
+    last.vals = svals;
+    return hip(hipGetLastError(), "render launch");
+}
+
+}  // namespace swf
+
+// ============================================================================
+// C ABI
+// ============================================================================
+#define CTX_GUARD(c)                                               \
+    if (!(c)) return SWF_E_INVALID;                                \
+    std::lock_guard<std::recursive_mutex> _lock((c)->mu);          \
+    hipSetDevice((c)->device)
+
+extern "C" {
+
+const char* swf_status_string(swf_status s) { return swf::status_name(s); }
+
+swf_status swf_create(swf_ctx** out, const swf_config* cfg) {
+    if (!out) return SWF_E_INVALID;
+    *out = nullptr;
+    int dev = cfg ? cfg->device : 0;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SWF_E_DEVICE;
+    if (dev < 0 || dev >= ndev) return SWF_E_INVALID;
+    if (hipSetDevice(dev) != hipSuccess) return SWF_E_DEVICE;
+    Ctx* c = new (std::nothrow) Ctx();
+    if (!c) return SWF_E_OOM;
+    c->device = dev;
+    if (hipMalloc(&c->total_dev, 64) != hipSuccess || hipHostMalloc(&c->total_host, 64, 0) != hipSuccess) {
+        delete c;
+        return SWF_E_OOM;
+    }
+    c->status_dev = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(c->total_dev) + 16);
+    hipMemset(c->total_dev, 0, 64);
+    *out = reinterpret_cast<swf_ctx*>(c);
+    return SWF_OK;
+}
+
+swf_status swf_destroy(swf_ctx* h) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!c) return SWF_E_INVALID;
+    hipSetDevice(c->device);
+    serve_shutdown(c);
+    hipDeviceSynchronize();
+    for (auto& kv : c->scenes) {
+        for (void* p : kv.second->allocs) hipFree(p);
+        delete kv.second;
+    }
+    c->scenes.clear();
+    for (Buf* b : c->all_bufs()) b->release();
+    c->resolve_timing();
+    for (auto e : c->event_pool) hipEventDestroy(e);
+    hipFree(c->total_dev);
+    hipHostFree(c->total_host);
+    delete c;
+    return SWF_OK;
+}
+
+const char* swf_last_error(swf_ctx* h) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    return c ? c->err.c_str() : "null context";
+}
+
+swf_status swf_scene_upload(swf_ctx* h, const swf_gaussians* g, const swf_mlp* mlp, int32_t height, int32_t width,
+                            int32_t src_is_device, int32_t* scene_id) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    return c->upload_scene(g, mlp, height, width, src_is_device != 0, scene_id);
+}
+
+swf_status swf_scene_release(swf_ctx* h, int32_t scene_id) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    return c->release_scene(scene_id);
+}
+
+swf_status swf_scene_bytes(swf_ctx* h, int32_t scene_id, uint64_t* bytes) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    Scene* s = c->scene(scene_id);
+    if (!s) return c->fail(SWF_E_NOT_FOUND, "unknown scene id");
+    if (!bytes) return c->fail(SWF_E_INVALID, "bytes is NULL");
+    *bytes = s->d.bytes;
+    return SWF_OK;
+}
+
+swf_status swf_render(swf_ctx* h, int32_t scene_id, const float* tx, int32_t batch, int32_t flags, float* out,
+                      void* aux, void* stream) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    return c->render(scene_id, tx, batch, flags, out, aux, (hipStream_t)stream);
+}
+
+swf_status swf_stage_timing(swf_ctx* h, int32_t enable) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    c->resolve_timing();
+    c->timing = enable != 0;
+    return SWF_OK;
+}
+
+swf_status swf_stage_times(swf_ctx* h, double* ms, int64_t* launches, int32_t* n_stages) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    if (!n_stages) return c->fail(SWF_E_INVALID, "n_stages is NULL");
+    c->resolve_timing();
+    const int n = std::min<int>(*n_stages, SWF_N_STAGES);
+    for (int i = 0; i < n; ++i) {
+        if (ms) ms[i] = c->stage_ms[i];
+        if (launches) launches[i] = c->stage_n[i];
+        c->stage_ms[i] = 0.0;
+        c->stage_n[i] = 0;
+    }
+    *n_stages = n;
+    return SWF_OK;
+}
+
+swf_status swf_debug_deform(swf_ctx* h, int32_t scene_id, const float* tx, int32_t batch, int32_t flags, float* delta,
+                            void* stream) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    Scene* sc = c->scene(scene_id);
+    if (!sc) return c->fail(SWF_E_NOT_FOUND, "unknown scene id");
+    if (batch < 1 || !delta || !tx) return c->fail(SWF_E_INVALID, "bad batch, delta or tx");
+    if (flags & SWF_NO_DEFORM) return c->fail(SWF_E_INVALID, "deform debug needs the MLP");
+    hipStream_t st = (hipStream_t)stream;
+    const DevScene& d = sc->d;
+    const size_t cnt = (size_t)batch * d.n * kOut;
+    swf_status s = c->ws_delta.reserve(c, cnt * sizeof(float) + 16, st);
+    if (s) return s;
+    const Grid g = make_grid(d.H, d.W, (flags & SWF_TILE8) ? 8 : 16);
+    s = c->enqueue_preprocess(sc, tx, batch, flags, g, (float*)c->ws_delta.ptr, st);
+    if (s) return s;
+    launch_permute_delta((const float*)c->ws_delta.ptr, d.perm, batch, d.n, delta, st);
+    c->last.valid = false;
+    return c->hip(hipGetLastError(), "debug deform");
+}
+
+swf_status swf_debug_keys(swf_ctx* h, uint32_t* counts, uint32_t* offsets, uint64_t* keys, uint64_t* values,
+                          uint32_t* ranges, uint64_t* n_keys, uint64_t capacity) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    if (!c->last.valid) return c->fail(SWF_E_STATE, "no render to inspect");
+    Scene* sc = c->scene(c->last.scene);
+    if (!sc) return c->fail(SWF_E_STATE, "scene of the last render was released");
+    hipDeviceSynchronize();
+    const auto& L = c->last;
+    const size_t pairs = (size_t)L.B * L.N;
+    if (n_keys) *n_keys = L.n_keys;
+    swf_status s = SWF_OK;
+    if (counts && (s = c->hip(hipMemcpy(counts, c->rec.count, pairs * 4, hipMemcpyDeviceToHost), "D2H counts")))
+        return s;
+    if (offsets && (s = c->hip(hipMemcpy(offsets, c->ws_off.ptr, pairs * 4, hipMemcpyDeviceToHost), "D2H offsets")))
+        return s;
+    if ((keys || values) && L.n_keys > capacity) return c->fail(SWF_E_OVERFLOW, "capacity below key count");
+    if (keys || values) {
+        std::vector<uint32_t> v(L.n_keys);
+        if (L.n_keys && (s = c->hip(hipMemcpy(v.data(), L.vals, L.n_keys * 4, hipMemcpyDeviceToHost), "D2H vals")))
+            return s;
+        std::vector<uint64_t> k64(L.n_keys);
+        if (L.full) {
+            if (L.n_keys && (s = c->hip(hipMemcpy(k64.data(), L.keys, L.n_keys * 8, hipMemcpyDeviceToHost), "D2H keys")))
+                return s;
+        } else {
+            std::vector<uint32_t> k32(L.n_keys);
+            if (L.n_keys && (s = c->hip(hipMemcpy(k32.data(), L.keys, L.n_keys * 4, hipMemcpyDeviceToHost), "D2H keys")))
+                return s;
+            for (uint64_t i = 0; i < L.n_keys; ++i)
+                k64[i] = ((uint64_t)k32[i] << 32) | sc->host_dbits[v[i] % L.N];
+        }
+        for (uint64_t i = 0; i < L.n_keys; ++i) {
+            if (keys) keys[i] = k64[i];
+            if (values) values[i] = ((uint64_t)(v[i] / L.N) << 32) | sc->host_perm[v[i] % L.N];
+        }
+    }
+    if (ranges) {
+        const size_t m = (size_t)L.B * L.grid.tiles;
+        if ((s = c->hip(hipMemcpy(ranges, c->ws_ranges.ptr, m * 8, hipMemcpyDeviceToHost), "D2H ranges"))) return s;
+    }
+    return SWF_OK;
+}
+
+swf_status swf_radix_sort(swf_ctx* h, void* keys, uint32_t* values, int64_t n, int32_t key_bytes, int32_t begin_bit,
+                          int32_t end_bit, void* stream) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    if (n < 0 || (n > 0 && (!keys || !values))) return c->fail(SWF_E_INVALID, "bad keys/values/n");
+    if (key_bytes != 4 && key_bytes != 8) return c->fail(SWF_E_INVALID, "key_bytes must be 4 or 8");
+    if (begin_bit < 0 || end_bit > 8 * key_bytes || begin_bit > end_bit)
+        return c->fail(SWF_E_INVALID, "bad bit range");
+    if (n >= (1ll << 32)) return c->fail(SWF_E_INVALID, "n must be < 2^32");
+    hipStream_t st = (hipStream_t)stream;
+    swf_status s = SWF_OK;
+    if ((s = c->ws_sortk.reserve(c, (size_t)n * key_bytes + 16, st))) return s;
+    if ((s = c->ws_sortv.reserve(c, (size_t)n * 4 + 16, st))) return s;
+    if ((s = c->ws_hist.reserve(c, radix_scratch_bytes(n) + 64, st))) return s;
+    c->last.valid = false;
+    const int flip = launch_radix_sort(keys, values, c->ws_sortk.ptr, (uint32_t*)c->ws_sortv.ptr, n, key_bytes,
+                                       begin_bit, end_bit, c->ws_hist.ptr, st);
+    if (flip) {
+        hipMemcpyAsync(keys, c->ws_sortk.ptr, (size_t)n * key_bytes, hipMemcpyDeviceToDevice, st);
+        hipMemcpyAsync(values, c->ws_sortv.ptr, (size_t)n * 4, hipMemcpyDeviceToDevice, st);
+    }
+    return c->hip(hipGetLastError(), "radix sort");
+}
+
+swf_status swf_exclusive_scan(swf_ctx* h, const uint32_t* counts, uint32_t* offsets, uint64_t* total, int64_t n,
+                              void* stream) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    if (n < 0 || !total || (n > 0 && (!counts || !offsets))) return c->fail(SWF_E_INVALID, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    swf_status s = c->ws_scan.reserve(c, scan_scratch_bytes(n) + 64, st);
+    if (s) return s;
+    launch_exclusive_scan(counts, offsets, total, n, c->ws_scan.ptr, st);
+    return c->hip(hipGetLastError(), "scan");
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Host-side runtime state of libswiftwrf (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/swiftwrf.h"
+#include "kernels.h"
+#include "swf_device.h"
+
+namespace swf {
+
+struct Ctx;
+
+// Grow-only device buffer.
+struct Buf {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    swf_status reserve(Ctx* c, size_t bytes, hipStream_t st);
+    void release();
+};
+
+struct Scene {
+    DevScene d;
+    std::vector<void*> allocs;
+    std::vector<uint32_t> host_dbits;  // per sorted position
+    std::vector<uint32_t> host_perm;   // sorted position -> original id
+};
+
+struct TimedStage {
+    int stage;
+    hipEvent_t a, b;
+};
+
+struct LastRender {
+    bool valid = false;
+    int scene = -1, B = 0, N = 0, flags = 0;
+    Grid grid{};
+    uint64_t n_keys = 0;
+    bool full = false;
+    void* keys = nullptr;
+    uint32_t* vals = nullptr;
+};
+
+struct ServeState;
+
+struct Ctx {
+    int device = 0;
+    std::recursive_mutex mu;
+    std::string err;
+    std::map<int, Scene*> scenes;
+    int next_scene = 1;
+
+    // workspace
+    Buf ws_qs, ws_geo, ws_wm, ws_oa, ws_rect, ws_count, ws_off, ws_scan, ws_keys, ws_keys2, ws_vals, ws_vals2,
+        ws_hist, ws_ranges, ws_delta, ws_sortk, ws_sortv, ws_grad;
+    std::vector<Buf*> all_bufs() {
+        return {&ws_qs, &ws_geo, &ws_wm, &ws_oa, &ws_rect, &ws_count, &ws_off, &ws_scan, &ws_keys, &ws_keys2,
+                &ws_vals, &ws_vals2, &ws_hist, &ws_ranges, &ws_delta, &ws_sortk, &ws_sortv, &ws_grad};
+    }
+    Records rec;
+    uint64_t* total_dev = nullptr;   // device: scan total (and status word after it)
+    uint32_t* status_dev = nullptr;
+    uint64_t* total_host = nullptr;  // pinned
+    LastRender last;
+
+    // stage timing
+    bool timing = false;
+    std::vector<TimedStage> pending;
+    std::vector<hipEvent_t> event_pool;
+    double stage_ms[SWF_N_STAGES] = {};
+    int64_t stage_n[SWF_N_STAGES] = {};
+
+    ServeState* serve = nullptr;
+
+    swf_status fail(swf_status s, const std::string& msg);
+    swf_status hip(hipError_t e, const char* what);
+    Scene* scene(int id);
+    swf_status upload_scene(const swf_gaussians* g, const swf_mlp* mlp, int H, int W, bool dev, int* id);
+    swf_status release_scene(int id);
+    swf_status enqueue_preprocess(Scene* sc, const float* tx, int B, int flags, const Grid& g, float* delta_sorted,
+                                  hipStream_t st);
+    swf_status render(int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st);
+    void stage_begin(int stage, hipStream_t st);
+    void stage_end(hipStream_t st);
+    void resolve_timing();
+};
+
+Grid make_grid(int H, int W, int tile);
+const char* status_name(swf_status s);
+void serve_shutdown(Ctx* c);
+
+}  // namespace swf

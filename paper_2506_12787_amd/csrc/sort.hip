@@ -1,0 +1,385 @@
+// Device prefix scan, key emission, stable LSD radix sort and tile ranges:
+// the binning stage that turns per-pair tile rectangles into per-tile,
+// front-to-back Gaussian lists (the tile partitioning of Sec. 4.1).
+//
+// Sort: reduce-then-scan LSD radix sort with 8-bit digits and a fixed grid (no
+// inter-workgroup waits, so no forward-progress assumption). Each pass:
+// per-block digit histograms -> one-block exclusive scan over (digit, block) ->
+// scatter, where keys are ranked stably inside a 2048-key tile with wave64
+// ballots (8 ballots give each lane the mask of lanes sharing its digit).
+#include "kernels.h"
+#include "swf_device.h"
+
+namespace swf {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kItems = 8;
+constexpr int kTile = kThreads * kItems;  // keys per scatter tile
+constexpr int kMaxGrid = 1024;
+
+__device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// Inclusive scan across a wave64.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T t = __shfl_up(v, o, 64);
+        if ((int)lane_id() >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan across the 256-thread block; returns the block total in *tot.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* lds /* kWaves + 1 */, T* tot) {
+    const T inc = wave_inclusive_scan(v);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 63) lds[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int i = 0; i < kWaves; ++i) {
+            const T t = lds[i];
+            lds[i] = run;
+            run += t;
+        }
+        lds[kWaves] = run;
+    }
+    __syncthreads();
+    const T r = lds[w] + inc - v;
+    *tot = lds[kWaves];
+    __syncthreads();
+    return r;
+}
+
+// ---- exclusive scan of uint32 counts (3 kernels) ---------------------------
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                               int64_t chunk, uint64_t* __restrict__ sums) {
+    __shared__ uint64_t lds[kWaves + 1];
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = min(beg + chunk, n);
+    uint64_t s = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) s += in[i];
+    uint64_t tot;
+    block_exclusive_scan<uint64_t>(s, lds, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_top_kernel(uint64_t* __restrict__ sums, int G,
+                                                            uint64_t* __restrict__ total) {
+    __shared__ uint64_t lds[kWaves + 1];
+    uint64_t base = 0;
+    for (int c = 0; c < G; c += kThreads) {
+        const int i = c + threadIdx.x;
+        const uint64_t v = i < G ? sums[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_scan<uint64_t>(v, lds, &tot);
+        if (i < G) sums[i] = base + ex;
+        base += tot;
+    }
+    if (threadIdx.x == 0) *total = base;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                             int64_t chunk, const uint64_t* __restrict__ sums,
+                                                             uint32_t* __restrict__ out) {
+    __shared__ uint64_t lds[kWaves + 1];
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = min(beg + chunk, n);
+    uint64_t base = sums[blockIdx.x];
+    // per-thread runs of kItems consecutive elements for coalescing-friendly reads
+    for (int64_t t0 = beg; t0 < end; t0 += (int64_t)kThreads * kItems) {
+        uint32_t v[kItems];
+        uint64_t s = 0;
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int64_t i = t0 + (int64_t)threadIdx.x * kItems + j;
+            v[j] = i < end ? in[i] : 0u;
+            s += v[j];
+        }
+        uint64_t tot;
+        uint64_t ex = block_exclusive_scan<uint64_t>(s, lds, &tot) + base;
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int64_t i = t0 + (int64_t)threadIdx.x * kItems + j;
+            if (i < end) out[i] = (uint32_t)ex;
+            ex += v[j];
+        }
+        base += tot;
+    }
+}
+
+// ---- key emission -----------------------------------------------------------
+// One thread per pair: one key per tile of the pair's rectangle, row-major.
+// key = global tile (query * tiles + ty * TW + tx), or with full keys
+// (global tile << 32 | depth bits); value = pair index.
+template <bool kFull>
+__global__ __launch_bounds__(kThreads) void emit_keys_kernel(const uint2* __restrict__ rect,
+                                                             const uint32_t* __restrict__ count,
+                                                             const uint32_t* __restrict__ offsets,
+                                                             const uint32_t* __restrict__ dbits, int N, int64_t total,
+                                                             int TW, int tiles, uint64_t capacity,
+                                                             void* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                             uint32_t* __restrict__ status) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= total) return;
+    const uint32_t c = count[i];
+    if (c == 0) return;
+    const uint64_t off = offsets[i];
+    if (off + c > capacity) {
+        atomicOr(status, 1u);
+        return;
+    }
+    const uint2 r = rect[i];
+    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+    const uint32_t q = (uint32_t)(i / N);
+    const uint32_t base = q * (uint32_t)tiles;
+    const uint32_t db = kFull ? dbits[i % N] : 0u;
+    uint64_t o = off;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            const uint32_t gt = base + (uint32_t)(ty * TW + tx);
+            if (kFull)
+                reinterpret_cast<uint64_t*>(keys)[o] = ((uint64_t)gt << 32) | db;
+            else
+                reinterpret_cast<uint32_t*>(keys)[o] = gt;
+            vals[o] = (uint32_t)i;
+            ++o;
+        }
+    }
+}
+
+// ---- radix sort ---------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const K* __restrict__ keys, int64_t n, int shift,
+                                                              int64_t chunk, uint32_t* __restrict__ hist, int G) {
+    __shared__ uint32_t h[kWaves][256];
+    for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = min(beg + chunk, n);
+    for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) {
+        const uint32_t d = (uint32_t)(keys[i] >> shift) & 255u;
+        atomicAdd(&h[w][d], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += kThreads) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) s += h[k][d];
+        hist[(size_t)d * G + blockIdx.x] = s;
+    }
+}
+
+// Exclusive scan of m uint32 values in place by one block (digit-major
+// histogram, m = 256 * G <= 256 * kMaxGrid).
+__global__ __launch_bounds__(1024) void hist_scan_kernel(uint32_t* __restrict__ h, int m) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int per = (m + 1023) / 1024;
+    const int beg = min(t * per, m), end = min(beg + per, m);
+    uint32_t s = 0;
+    for (int i = beg; i < end; ++i) s += h[i];
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele over 1024 partial sums
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (int i = beg; i < end; ++i) {
+        const uint32_t v = h[i];
+        h[i] = run;
+        run += v;
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const K* __restrict__ kin,
+                                                                 const uint32_t* __restrict__ vin,
+                                                                 K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                                 int64_t n, int shift, int64_t chunk,
+                                                                 const uint32_t* __restrict__ hist, int G) {
+    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t ttot[256];
+    const int w = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < 256; d += kThreads) base[d] = hist[(size_t)d * G + blockIdx.x];
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = min(beg + chunk, n);
+    for (int64_t t0 = beg; t0 < end; t0 += kTile) {
+        for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wcnt[0][0])[i] = 0;
+        __syncthreads();
+        K k[kItems];
+        uint32_t v[kItems], dig[kItems], lr[kItems];
+        bool ok[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int64_t idx = t0 + (int64_t)(w * kItems + j) * 64 + lane_id();
+            ok[j] = idx < end;
+            k[j] = ok[j] ? kin[idx] : (K)0;
+            v[j] = ok[j] ? vin[idx] : 0u;
+            const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
+            dig[j] = d;
+            const uint64_t valid = __ballot(ok[j]);
+            uint64_t match = valid;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bal = __ballot(bit && ok[j]);
+                match &= bit ? bal : ~bal;
+            }
+            const uint32_t rank = (uint32_t)__popcll(match & lanemask_lt());
+            const uint32_t cnt = (uint32_t)__popcll(match);
+            uint32_t prev = 0;
+            if (ok[j]) prev = wcnt[w][d];
+            lr[j] = prev + rank;
+            __builtin_amdgcn_wave_barrier();
+            if (ok[j] && rank == 0) wcnt[w][d] = prev + cnt;
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < 256; d += kThreads) {
+            uint32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) {
+                const uint32_t c = wcnt[q][d];
+                wcnt[q][d] = run;
+                run += c;
+            }
+            ttot[d] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            if (ok[j]) {
+                const uint32_t pos = base[dig[j]] + wcnt[w][dig[j]] + lr[j];
+                kout[pos] = k[j];
+                vout[pos] = v[j];
+            }
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < 256; d += kThreads) base[d] += ttot[d];
+        __syncthreads();
+    }
+}
+
+// ---- tile ranges -----------------------------------------------------------
+__global__ void zero_ranges_kernel(uint2* __restrict__ r, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) r[i] = make_uint2(0u, 0u);
+}
+
+template <bool kFull>
+__global__ void tile_ranges_kernel(const void* __restrict__ keys, int64_t n, uint2* __restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    auto tile_of = [&](int64_t j) -> uint32_t {
+        return kFull ? (uint32_t)(reinterpret_cast<const uint64_t*>(keys)[j] >> 32)
+                     : reinterpret_cast<const uint32_t*>(keys)[j];
+    };
+    const uint32_t t = tile_of(i);
+    if (i == 0 || tile_of(i - 1) != t) r[t].x = (uint32_t)i;
+    if (i == n - 1 || tile_of(i + 1) != t) r[t].y = (uint32_t)(i + 1);
+}
+
+int radix_grid(int64_t n) {
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid));
+}
+
+template <typename K>
+int radix_sort_t(K* keys, uint32_t* vals, K* kalt, uint32_t* valt, int64_t n, int begin_bit, int end_bit,
+                 uint32_t* hist, hipStream_t st) {
+    if (n <= 1 || end_bit <= begin_bit) return 0;
+    const int G = radix_grid(n);
+    int64_t chunk = (n + G - 1) / G;
+    chunk = ((chunk + kTile - 1) / kTile) * kTile;
+    K* ki = keys;
+    uint32_t* vi = vals;
+    K* ko = kalt;
+    uint32_t* vo = valt;
+    int flips = 0;
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        radix_hist_kernel<K><<<G, kThreads, 0, st>>>(ki, n, shift, chunk, hist, G);
+        hist_scan_kernel<<<1, 1024, 0, st>>>(hist, 256 * G);
+        radix_scatter_kernel<K><<<G, kThreads, 0, st>>>(ki, vi, ko, vo, n, shift, chunk, hist, G);
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+        flips ^= 1;
+    }
+    return flips;
+}
+
+}  // namespace
+
+int scan_grid(int64_t n) {
+    const int64_t per = (int64_t)kThreads * kItems;
+    const int64_t g = (n + per - 1) / per;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 4096));
+}
+
+size_t scan_scratch_bytes(int64_t n) { return sizeof(uint64_t) * (size_t)(scan_grid(n) + 1); }
+
+void launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t* total, int64_t n, void* scratch,
+                           hipStream_t st) {
+    uint64_t* sums = reinterpret_cast<uint64_t*>(scratch);
+    if (n <= 0) {
+        hipMemsetAsync(total, 0, sizeof(uint64_t), st);
+        return;
+    }
+    const int G = scan_grid(n);
+    int64_t chunk = (n + G - 1) / G;
+    chunk = ((chunk + kThreads * kItems - 1) / (kThreads * kItems)) * (kThreads * kItems);
+    scan_reduce_kernel<<<G, kThreads, 0, st>>>(in, n, chunk, sums);
+    scan_top_kernel<<<1, kThreads, 0, st>>>(sums, G, total);
+    scan_down_kernel<<<G, kThreads, 0, st>>>(in, n, chunk, sums, out);
+}
+
+void launch_emit_keys(const Records& r, const uint32_t* offsets, const uint32_t* dbits, int B, int N, const Grid& g,
+                      uint64_t capacity, bool full_keys, void* keys, uint32_t* vals, uint32_t* status,
+                      hipStream_t st) {
+    const int64_t total = (int64_t)B * N;
+    if (total <= 0) return;
+    const unsigned blocks = (unsigned)((total + kThreads - 1) / kThreads);
+    if (full_keys)
+        emit_keys_kernel<true><<<blocks, kThreads, 0, st>>>(r.rect, r.count, offsets, dbits, N, total, g.TW, g.tiles,
+                                                            capacity, keys, vals, status);
+    else
+        emit_keys_kernel<false><<<blocks, kThreads, 0, st>>>(r.rect, r.count, offsets, dbits, N, total, g.TW,
+                                                             g.tiles, capacity, keys, vals, status);
+}
+
+size_t radix_scratch_bytes(int64_t n) { return sizeof(uint32_t) * 256 * (size_t)radix_grid(n); }
+
+int launch_radix_sort(void* keys, uint32_t* vals, void* kalt, uint32_t* valt, int64_t n, int key_bytes, int begin_bit,
+                      int end_bit, void* scratch, hipStream_t st) {
+    uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
+    if (key_bytes == 8)
+        return radix_sort_t<uint64_t>(reinterpret_cast<uint64_t*>(keys), vals, reinterpret_cast<uint64_t*>(kalt), valt,
+                                      n, begin_bit, end_bit, hist, st);
+    return radix_sort_t<uint32_t>(reinterpret_cast<uint32_t*>(keys), vals, reinterpret_cast<uint32_t*>(kalt), valt, n,
+                                  begin_bit, end_bit, hist, st);
+}
+
+void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gtiles, uint2* ranges, hipStream_t st) {
+    if (n_gtiles > 0) zero_ranges_kernel<<<(unsigned)((n_gtiles + 255) / 256), 256, 0, st>>>(ranges, n_gtiles);
+    if (n <= 0) return;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (key_bytes == 8)
+        tile_ranges_kernel<true><<<blocks, 256, 0, st>>>(keys, n, ranges);
+    else
+        tile_ranges_kernel<false><<<blocks, 256, 0, st>>>(keys, n, ranges);
+}
+
+}  // namespace swf

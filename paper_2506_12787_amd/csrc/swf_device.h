@@ -1,0 +1,136 @@
+// Device-side helpers shared by the HIP translation units of libswiftwrf:
+// blending constants, the per-pair record layout and the preprocess step
+// (deform -> whitening factor -> 3-sigma extent -> tile rectangle).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swf {
+
+// Blending rule constants (Sec. 3.2 blending with the 3-sigma cutoff).
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr float kQMax = 9.0f;
+constexpr float kExtentEps = 1e-3f;           // binning margin on the 3-sigma half extent (px)
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
+
+constexpr int kMeanBands = 6;
+constexpr int kTxBands = 10;
+constexpr int kMeanFeat = 2 * (2 * kMeanBands + 1);  // 26
+constexpr int kTxFeat = 3 * (2 * kTxBands + 1);      // 63
+constexpr int kOut = 7;
+
+// Per (query, Gaussian) pair record, three arrays of vectors:
+//   geo  float4 (mx_hi, my_hi, mx_lo, my_lo): deformed mean as an unevaluated
+//        sum hi + lo (exact value of mu0 + d_mu), so that tile-relative offsets
+//        keep full precision at any grid width
+//   wm   float4 (m11, m12, m21, m22): whitening factor M = S^-1 R^T with
+//        Sigma^-1 = M^T M, so q = |M d|^2 (no 2x2 inversion, no cancellation)
+//   oa   float2 (opacity, amplitude)
+// plus rect (uint2: tx0 | tx1 << 16, ty0 | ty1 << 16) and count (uint32 tiles).
+struct PairOut {
+    float4 geo;
+    float4 wm;
+    float2 oa;
+    uint32_t rect_x, rect_y;
+    uint32_t count;
+};
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v); }
+
+// Deformed Gaussian -> record. mean = (mx0 + dmx, my0 + dmy); all other
+// parameters already deformed. tile is 8 or 16 (power of two, so the division
+// of an edge coordinate by the tile size is exact).
+__device__ __forceinline__ PairOut preprocess_pair(float mx0, float my0, float dmx, float dmy, float lsx, float lsy,
+                                                   float rot, float logit, float amp, int W, int H, int TW, int TH,
+                                                   float inv_tile) {
+    PairOut r;
+    float mxh, mxl, myh, myl;
+    two_sum(mx0, dmx, mxh, mxl);
+    two_sum(my0, dmy, myh, myl);
+    float s, c;
+    sincosf(rot, &s, &c);
+    const float isx = expf(-lsx), isy = expf(-lsy);
+    const float vx = expf(2.0f * lsx), vy = expf(2.0f * lsy);
+    const float sxx = c * c * vx + s * s * vy;
+    const float syy = s * s * vx + c * c * vy;
+    const float hx = 3.0f * sqrtf(sxx) + kExtentEps;
+    const float hy = 3.0f * sqrtf(syy) + kExtentEps;
+    const float op = 1.0f / (1.0f + expf(-logit));
+    r.geo = make_float4(mxh, myh, mxl, myl);
+    r.wm = make_float4(c * isx, s * isx, -s * isy, c * isy);
+    r.oa = make_float2(op, amp);
+    const float x0 = mxh - hx, x1 = mxh + hx, y0 = myh - hy, y1 = myh + hy;
+    const bool ok = finitef(x0) && finitef(x1) && finitef(y0) && finitef(y1) && finitef(r.wm.x) &&
+                    finitef(r.wm.y) && finitef(r.wm.z) && finitef(r.wm.w) && finitef(op) && finitef(amp) &&
+                    finitef(mxl) && finitef(myl) && !(x1 < 0.0f) && !(x0 > (float)(W - 1)) && !(y1 < 0.0f) &&
+                    !(y0 > (float)(H - 1));
+    if (!ok) {
+        r.rect_x = r.rect_y = 0;
+        r.count = 0;
+        return r;
+    }
+    const int tx0 = max(0, min(TW - 1, (int)floorf(x0 * inv_tile)));
+    const int tx1 = max(0, min(TW - 1, (int)floorf(x1 * inv_tile)));
+    const int ty0 = max(0, min(TH - 1, (int)floorf(y0 * inv_tile)));
+    const int ty1 = max(0, min(TH - 1, (int)floorf(y1 * inv_tile)));
+    r.rect_x = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
+    r.rect_y = (uint32_t)ty0 | ((uint32_t)ty1 << 16);
+    r.count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    return r;
+}
+
+// Order-preserving map of an FP32 depth to uint32 (-0 like +0).
+__host__ __device__ __forceinline__ uint32_t depth_key_bits(float d) {
+    if (d == 0.0f) d = 0.0f;
+    uint32_t u;
+    __builtin_memcpy(&u, &d, 4);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// sin(pi x) and cos(pi x) of x = hi + lo (an unevaluated sum, |lo| tiny) after
+// scaling by 2^k: the scaled hi is reduced exactly modulo 2 before adding the
+// scaled lo, so the phase keeps the accuracy of the two-term input.
+__device__ __forceinline__ void sincospi_scaled(float hi, float lo, int k, float& sv, float& cv) {
+    const float sh = ldexpf(hi, k);                        // exact
+    const float red = sh - 2.0f * rintf(0.5f * sh);        // exact: sh mod 2 in [-1, 1]
+    const float t = red + ldexpf(lo, k);
+    sv = sinpif(t);
+    cv = cospif(t);
+}
+
+// (a / b) as hi + lo with lo the rounded residual: a = hi * b + r exactly.
+__device__ __forceinline__ void div_two(float a, float b, float& hi, float& lo) {
+    hi = a / b;
+    const float r = fmaf(-hi, b, a);
+    lo = r / b;
+}
+
+// gamma(mu_hat) of a canonical mean, mu_hat = (mx / W, my / H), in the
+// order [mu_hat, sin(2^k pi mu_hat) for k < 6, cos(2^k pi mu_hat) for k < 6].
+__device__ __forceinline__ void mean_features(float mx, float my, int W, int H, float* out) {
+    float hx, lx, hy, ly;
+    div_two(mx, (float)W, hx, lx);
+    div_two(my, (float)H, hy, ly);
+    out[0] = hx + lx;
+    out[1] = hy + ly;
+#pragma unroll
+    for (int k = 0; k < kMeanBands; ++k) {
+        float sx, cx, sy, cy;
+        sincospi_scaled(hx, lx, k, sx, cx);
+        sincospi_scaled(hy, ly, k, sy, cy);
+        out[2 + 2 * k] = sx;
+        out[3 + 2 * k] = sy;
+        out[2 + 2 * kMeanBands + 2 * k] = cx;
+        out[3 + 2 * kMeanBands + 2 * k] = cy;
+    }
+}
+
+}  // namespace swf

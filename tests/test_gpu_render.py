@@ -1,0 +1,192 @@
+"""GPU parity of the render path (HIP library through the C ABI) against the
+FP64 oracle: static render, deformable FP32 render, step oracles (scan, sort,
+keys, ranges) and edge cases."""
+import numpy as np
+import pytest
+
+from oracle import model as M
+from paper_2506_12787_amd import synth
+from tests import helpers as Hh
+
+pytestmark = pytest.mark.gpu
+
+H0, W0 = 90, 360
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2506_12787_amd import binding
+    assert torch.cuda.is_available(), "GPU test on a machine without a GPU"
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _tx(b, seed):
+    import torch
+    return torch.from_numpy(synth.tx_positions(b, seed=seed)).cuda()
+
+
+def _render_static(ctx, g, H, W, flags=0):
+    from paper_2506_12787_amd import binding as B
+    sid = ctx.upload_scene(g, H, W)
+    out = ctx.render(sid, None, flags=B.NO_DEFORM | flags, batch=1)
+    return sid, out[0].cpu().numpy()
+
+
+def test_static_render_matches_oracle_c0(ctx):
+    # N = 2000, 90 x 360, static FP32
+    g, s = Hh.problem(2000, H0, W0, seed=1000)
+    sid, img = _render_static(ctx, g, H0, W0)
+    res, _, _, _ = M.render_query(s, None, None)
+    rep = Hh.parity(img, res)
+    print("c0 parity", rep)
+    assert rep["worst_unflagged_rel"] <= Hh.TOL_REL
+    ctx.release_scene(sid)
+
+
+@pytest.mark.parametrize("H,W,n,seed", [(17, 33, 60, 5), (1, 1, 3, 6), (16, 16, 40, 7), (45, 130, 700, 8)])
+def test_static_ragged_grids(ctx, H, W, n, seed):
+    g, s = Hh.problem(n, H, W, seed=seed, scale_range=(0.5, 6.0))
+    sid, img = _render_static(ctx, g, H, W)
+    res, _, _, _ = M.render_query(s, None, None)
+    Hh.parity(img, res)
+    ctx.release_scene(sid)
+
+
+def test_empty_and_culled_render_exact_zero(ctx):
+    g, _ = Hh.problem(0, 20, 30, seed=1)
+    sid, img = _render_static(ctx, g, 20, 30)
+    assert np.all(img == 0.0)
+    ctx.release_scene(sid)
+    g, _ = Hh.problem(50, 20, 30, seed=2)
+    g["mean_x"][:] = -200.0
+    g["log_scale_y"][:5] = np.nan
+    g["depth"][5:10] = np.nan
+    sid, img = _render_static(ctx, g, 20, 30)
+    assert np.all(img == 0.0)
+    ctx.release_scene(sid)
+
+
+def test_tile8_and_full_sort_are_bitwise_equal(ctx):
+    from paper_2506_12787_amd import binding as B
+    g, s = Hh.problem(1500, H0, W0, seed=21)
+    sid = ctx.upload_scene(g, H0, W0)
+    a = ctx.render(sid, None, flags=B.NO_DEFORM, batch=1).cpu().numpy()
+    b = ctx.render(sid, None, flags=B.NO_DEFORM | B.TILE8, batch=1).cpu().numpy()
+    c = ctx.render(sid, None, flags=B.NO_DEFORM | B.FULL_SORT, batch=1).cpu().numpy()
+    d = ctx.render(sid, None, flags=B.NO_DEFORM, batch=1).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, c)
+    np.testing.assert_array_equal(a, d)  # deterministic
+    ctx.release_scene(sid)
+
+
+def _oracle_keys(s, H, W, tile=16):
+    gm = M.deform(s, None)
+    rg = M.gaussians_for_raster(gm, s.depth)
+    rect, flagged, alts = M.tile_rects(gm, rg, H, W, tile)
+    return rect, flagged, alts
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_keys_offsets_ranges_bit_exact(ctx, full):
+    from paper_2506_12787_amd import binding as B
+    H, W = H0, W0
+    g, s = Hh.problem(800, H, W, seed=31)
+    sid = ctx.upload_scene(g, H, W)
+    ctx.render(sid, None, flags=B.NO_DEFORM | (B.FULL_SORT if full else 0), batch=1)
+    TW, TH = -(-W // 16), -(-H // 16)
+    dk = ctx.debug_keys(1, s.n, TW * TH)
+    rect, flagged, alts = _oracle_keys(s, H, W)
+    order = M.depth_order(s.depth)
+    assert not flagged.any(), "seeded case chosen without ambiguous rectangles"
+    counts = M.rect_count(rect)[order]
+    offs, tot = M.exclusive_scan(counts)
+    np.testing.assert_array_equal(dk["counts"], counts.astype(np.uint32))
+    np.testing.assert_array_equal(dk["offsets"], offs.astype(np.uint32))
+    gt, dbits, ids, ranges = M.key_list(rect, s.depth, H, W)
+    assert len(dk["keys"]) == tot == len(gt)
+    np.testing.assert_array_equal(dk["keys"], (gt << np.uint64(32)) | dbits)
+    np.testing.assert_array_equal(dk["values"], ids.astype(np.uint64))
+    np.testing.assert_array_equal(dk["ranges"].astype(np.int64), ranges)
+    ctx.release_scene(sid)
+
+
+@pytest.mark.parametrize("n", [0, 1, 255, 256, 257, 4097, (1 << 20) + 1])
+def test_exclusive_scan_matches_sequential_sum(ctx, n):
+    import torch
+    rng = np.random.default_rng(n)
+    c = rng.integers(0, 200, n).astype(np.uint32)
+    off, tot = ctx.exclusive_scan(torch.from_numpy(c.view(np.int32)).cuda())
+    ref, rtot = M.exclusive_scan(c)
+    assert int(tot.cpu()[0]) == rtot
+    np.testing.assert_array_equal(off.cpu().numpy().view(np.uint32), ref.astype(np.uint32))
+
+
+@pytest.mark.parametrize("n,kind,bits", [
+    (0, "rand", 32), (1, "rand", 32), (255, "rand", 32), (256, "rand", 20), (257, "rand", 32),
+    (5000, "equal", 32), (5000, "reversed", 16), (100003, "rand", 13), ((1 << 20) + 1, "rand", 32),
+    (70000, "rand64", 64), (70000, "rand64", 46)])
+def test_radix_sort_matches_stable_sort(ctx, n, kind, bits):
+    import torch
+    rng = np.random.default_rng(n + bits)
+    wide = kind == "rand64"
+    dt = np.uint64 if wide else np.uint32
+    if kind == "equal":
+        k = np.full(n, 7, dt)
+    elif kind == "reversed":
+        k = np.arange(n, 0, -1).astype(dt) % dt(1 << bits)
+    else:
+        k = rng.integers(0, 1 << min(bits, 63), n, dtype=np.uint64).astype(dt)
+        if wide and bits == 64:
+            k = k ^ (rng.integers(0, 2, n, dtype=np.uint64) << np.uint64(63))
+    v = np.arange(n, dtype=np.uint32)
+    tk = torch.from_numpy(k.view(np.int64 if wide else np.int32).copy()).cuda()
+    tv = torch.from_numpy(v.view(np.int32).copy()).cuda()
+    ctx.radix_sort(tk, tv, 0, bits)
+    o = np.argsort(k & dt((1 << bits) - 1) if bits < 64 else k, kind="stable")
+    np.testing.assert_array_equal(tk.cpu().numpy().view(dt), k[o])
+    np.testing.assert_array_equal(tv.cpu().numpy().view(np.uint32), v[o])
+
+
+def _deform_problem(n, B, seed, out_scale):
+    g, s = Hh.problem(n, H0, W0, seed=seed)
+    Ws, bs = synth.mlp_weights(seed=seed + 2000, out_scale=out_scale)
+    rng = np.random.default_rng(seed)
+    bs = [b + rng.normal(0, 0.05, b.shape).astype(np.float32) for b in bs]
+    return g, s, Ws, bs
+
+
+def test_deform_residuals_fp32_match_oracle(ctx):
+    g, s, Ws, bs = _deform_problem(3000, 4, seed=41, out_scale=1.0)
+    sid = ctx.upload_scene(g, H0, W0, mlp=(Ws, bs))
+    tx = _tx(4, 2041)
+    d = ctx.debug_deform(sid, tx).cpu().numpy().astype(np.float64)
+    mlp = Hh.mlp_f64(Ws, bs)
+    txh = tx.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    for b in range(4):
+        ref = M.deltas(s, mlp, txh[b])
+        scale = np.abs(ref).max(axis=0)
+        err = np.abs(d[b] - ref).max(axis=0) / scale
+        worst = max(worst, err.max())
+    print("FP32 MLP residual normwise rel err", worst)
+    assert worst < 2e-5
+    ctx.release_scene(sid)
+
+
+@pytest.mark.parametrize("out_scale", [0.01, 1.0])
+def test_deformable_fp32_render_matches_oracle(ctx, out_scale):
+    g, s, Ws, bs = _deform_problem(2000, 3, seed=51, out_scale=out_scale)
+    sid = ctx.upload_scene(g, H0, W0, mlp=(Ws, bs))
+    tx = _tx(3, 2051)
+    out = ctx.render(sid, tx).cpu().numpy()
+    mlp = Hh.mlp_f64(Ws, bs)
+    txh = tx.cpu().numpy().astype(np.float64)
+    for b in range(3):
+        res, _, _, _ = M.render_query(s, mlp, txh[b])
+        rep = Hh.parity(out[b], res)
+        print("deform parity", out_scale, b, rep)
+    ctx.release_scene(sid)
