@@ -38,6 +38,7 @@ def parse():
     p.add_argument("--width", type=int, default=360)
     p.add_argument("--mlp", choices=("bf16", "fp32"), default="bf16")
     p.add_argument("--plain-queries", type=int, default=16)
+    p.add_argument("--pairs-per-wave", type=int, default=0, help="BF16 MLP register tile (64 or 32)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--quick", action="store_true", help="timed steps only (for profiler runs)")
@@ -84,7 +85,7 @@ def main():
     Ws, bs = synth.mlp_weights(seed=3003)
     nbat = a.warmup + a.steps
     txs = synth.tx_positions(nbat * Bq, seed=2003)
-    ctx = B.Context(0)
+    ctx = B.Context(0, mlp_pairs_per_wave=a.pairs_per_wave)
     sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
     tx_dev = torch.from_numpy(txs).cuda().view(nbat, Bq, 3)
     out = torch.empty((Bq, H, W), device="cuda", dtype=torch.float32)

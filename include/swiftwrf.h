@@ -82,8 +82,10 @@ enum {
 typedef struct swf_ctx swf_ctx;
 
 typedef struct {
-    int32_t device;          /* HIP device ordinal                                */
-    int32_t reserved[7];
+    int32_t device;             /* HIP device ordinal                             */
+    int32_t mlp_pairs_per_wave; /* BF16 MLP tuning: pairs per wave, 64 (default,
+                                   one wave per SIMD) or 32 (two waves per SIMD)  */
+    int32_t reserved[6];
 } swf_config;
 
 typedef struct {

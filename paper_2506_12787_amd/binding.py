@@ -31,7 +31,8 @@ _fp = ctypes.POINTER(ctypes.c_float)
 
 
 class _Config(ctypes.Structure):
-    _fields_ = [("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("device", ctypes.c_int32), ("mlp_pairs_per_wave", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class _Gaussians(ctypes.Structure):
@@ -108,13 +109,13 @@ def _stream():
 class Context:
     """One libswiftwrf context on one GPU."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, mlp_pairs_per_wave: int = 0):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
         self._L = lib()
         h = ctypes.c_void_p()
-        cfg = _Config(device=device)
+        cfg = _Config(device=device, mlp_pairs_per_wave=mlp_pairs_per_wave)
         self._check(self._L.swf_create(ctypes.byref(h), ctypes.byref(cfg)), ctx=False)
         self._h = h
         self._keep = {}

@@ -53,7 +53,7 @@ void launch_permute_delta(const float* delta_sorted, const uint32_t* perm, int B
 bool bf16_available();
 void compute_mean_features_bf16(DevScene& s, hipStream_t st);
 void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
-                     float* delta_out, hipStream_t st);
+                     float* delta_out, hipStream_t st, int pairs_per_wave);
 
 // sort.hip
 int scan_grid(int64_t n);

@@ -29,12 +29,17 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t cvt_pk_bf16(float a, float b) {
+    const bf16x2 v = {(__bf16)a, (__bf16)b};  // v_cvt_pk_bf16_f32, round to nearest even
+    return __builtin_bit_cast(uint32_t, v);
+}
 
 constexpr int kChunkBytes = 16384;          // 16 fragments of 1 KiB
 constexpr int kChunkU4 = kChunkBytes / 16;  // uint4 per chunk (1024)
 constexpr int kSlots = 3;
-constexpr int kPairsPerWave = 64;
-constexpr int kPairsPerBlock = 256;
 
 struct Bf16Args {
     MlpArgs m;
@@ -43,27 +48,38 @@ struct Bf16Args {
     const bf16x8* mfeat;      // [N][32] bf16 mean features (4 x bf16x8 per Gaussian)
     const float* bias_h[7];   // biases of hidden layers 1..n_hidden-1
     const float* bias_o;      // output bias
-    int n_tiles;
+    int n_tiles;              // B * tiles_per_query
+    int tiles_per_query;      // ceil(N / pairs per block): tiles never straddle two queries
 };
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ bf16x8 pack_relu(f32x4 lo, f32x4 hi, float4 blo, float4 bhi) {
-    bf16x8 r;
-    r[0] = (__bf16)fmaxf(lo[0] + blo.x, 0.f);
-    r[1] = (__bf16)fmaxf(lo[1] + blo.y, 0.f);
-    r[2] = (__bf16)fmaxf(lo[2] + blo.z, 0.f);
-    r[3] = (__bf16)fmaxf(lo[3] + blo.w, 0.f);
-    r[4] = (__bf16)fmaxf(hi[0] + bhi.x, 0.f);
-    r[5] = (__bf16)fmaxf(hi[1] + bhi.y, 0.f);
-    r[6] = (__bf16)fmaxf(hi[2] + bhi.z, 0.f);
-    r[7] = (__bf16)fmaxf(hi[3] + bhi.w, 0.f);
-    return r;
+// Two accumulator tiles (features 4g..4g+3 and 16+4g..16+4g+3 of a 32-chunk)
+// -> ReLU'd bf16 B operand. The bias is already in the accumulators. ReLU is
+// applied after rounding as a signed 16-bit max with 0 (a negative bf16 is a
+// negative int16), which equals rounding the ReLU'd float.
+__device__ __forceinline__ bf16x8 pack_relu(f32x4 lo, f32x4 hi) {
+    uint32_t w[4];
+    w[0] = cvt_pk_bf16(lo[0], lo[1]);
+    w[1] = cvt_pk_bf16(lo[2], lo[3]);
+    w[2] = cvt_pk_bf16(hi[0], hi[1]);
+    w[3] = cvt_pk_bf16(hi[2], hi[3]);
+    const short2v z = {0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        w[i] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(short2v, w[i]), z));
+    uint4 u = make_uint4(w[0], w[1], w[2], w[3]);
+    return __builtin_bit_cast(bf16x8, u);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mlp_bf16_kernel(Bf16Args a) {
+// NCB column blocks of 16 pairs per wave (64 or 32 pairs); 4 waves per block.
+template <int NCB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCB == 2 ? 2 : 1, NCB == 2 ? 2 : 1))) void
+mlp_bf16_kernel(Bf16Args a) {
+    constexpr int kPairsPerWave = 16 * NCB;
+    constexpr int kPairsPerBlock = 4 * kPairsPerWave;
     __shared__ __attribute__((aligned(16))) uint4 ring[kSlots * kChunkU4];
     __shared__ float outs[4][kPairsPerWave][8];
 
@@ -72,136 +88,136 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int lane = tid & 63;
     const int g = lane >> 4;       // lane group (k / feature sub-block)
     const int n16 = lane & 15;     // pair column inside a 16-wide block
-    const size_t total = (size_t)a.m.N * a.m.B;
     const int S = a.n_chunks;
     const int n_mid = a.m.n_mid;
 
     // tiles of this persistent workgroup
     const int my_tiles = a.n_tiles > (int)blockIdx.x ? (a.n_tiles - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
-    const int64_t q_end = (int64_t)my_tiles * S;  // chunk steps of this workgroup
     if (my_tiles == 0) return;
+    const int q_end = my_tiles * S;  // chunk steps of this workgroup
 
-    // ring prologue: chunks 0, 1 into slots 0, 1; chunk 2 into registers
+    // Ring of kSlots chunk slots. Step q computes from slot q % 3; during step q
+    // the chunk q + 2 (prefetched into registers during step q - 1) is stored
+    // into slot (q + 2) % 3 and chunk q + 3 is fetched; one barrier ends a step.
     uint4 pf[4];
-    auto fetch = [&](int64_t q) {
-        const int c = (int)(q % S);
+    int fetch_chunk = 0;  // stream chunk index of the next fetch
+    auto fetch = [&]() {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) pf[i] = a.stream[(size_t)c * kChunkU4 + tid + i * 256];
+        for (int i = 0; i < 4; ++i) pf[i] = a.stream[(size_t)fetch_chunk * kChunkU4 + tid + i * 256];
+        fetch_chunk = fetch_chunk + 1 == S ? 0 : fetch_chunk + 1;
     };
     auto store = [&](int slot) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) ring[slot * kChunkU4 + tid + i * 256] = pf[i];
     };
-    fetch(0);
+    fetch();
     store(0);
     if (q_end > 1) {
-        fetch(1);
+        fetch();
         store(1);
     }
-    if (q_end > 2) fetch(2);
+    if (q_end > 2) fetch();
     __syncthreads();
-    int64_t q = 0;  // chunk step being computed
-    // per step: store the prefetched chunk q+2, fetch chunk q+3, compute q, barrier
+    int q = 0;         // step being computed
+    int slot = 0;      // q % 3
     auto advance = [&]() {
-        if (q + 2 < q_end) store((int)((q + 2) % kSlots));
-        if (q + 3 < q_end) fetch(q + 3);
+        const int s2 = slot == 0 ? 2 : slot - 1;  // (q + 2) % 3
+        if (q + 2 < q_end) store(s2);
+        if (q + 3 < q_end) fetch();
     };
     auto frag = [&](int t) -> bf16x8 {
-        const uint4 v = ring[(int)(q % kSlots) * kChunkU4 + t * 64 + lane];
-        return __builtin_bit_cast(bf16x8, v);
+        return __builtin_bit_cast(bf16x8, ring[slot * kChunkU4 + t * 64 + lane]);
     };
-
-    f32x4 acc[16][4];
-    bf16x8 act[8][4];
-
-    for (int it = 0; it < my_tiles; ++it) {
-        const size_t tile = (size_t)blockIdx.x + (size_t)it * gridDim.x;
-        const size_t base = tile * kPairsPerBlock + (size_t)wave * kPairsPerWave;
-        // ---- layer 1 (mean part, K = 32): B = bf16 gamma(mu_hat) ----
-        bf16x8 bm[4];
-        int qb[4];
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            const size_t row = base + cb * 16 + n16;
-            if (row < total) {
-                const int p = (int)(row % a.m.N);
-                bm[cb] = a.mfeat[(size_t)p * 4 + g];
-                qb[cb] = (int)(row / a.m.N);
-            } else {
-                bm[cb] = bf16x8{};
-                qb[cb] = 0;
-            }
-        }
-        advance();
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const bf16x8 w = frag(t);
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb) acc[t][cb] = mfma(w, bm[cb], f32x4{0.f, 0.f, 0.f, 0.f});
-        }
+    auto next_step = [&]() {
         __syncthreads();
         ++q;
-        // layer-1 bias is the per-query transceiver part qs[b]
+        slot = slot == 2 ? 0 : slot + 1;
+    };
+
+    f32x4 acc[16][NCB];
+    bf16x8 act[8][NCB];
+
+    for (int it = 0; it < my_tiles; ++it) {
+        const int tile = (int)blockIdx.x + it * (int)gridDim.x;
+        const int qry = tile / a.tiles_per_query;                  // block-uniform query
+        const int p0 = (tile - qry * a.tiles_per_query) * kPairsPerBlock + wave * kPairsPerWave;
+        const size_t row0 = (size_t)qry * a.m.N;                   // first pair of the query
+        // ---- layer 1 (mean part, K = 32): B = bf16 gamma(mu_hat); C = qs[query] ----
+        bf16x8 bm[NCB];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int p = p0 + cb * 16 + n16;
+            bm[cb] = p < a.m.N ? a.mfeat[(size_t)p * 4 + g] : bf16x8{};
+        }
+        advance();
+        {
+            const float* qrow = a.m.qs + (size_t)qry * 256 + 4 * g;
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                const float* qrow = a.m.qs + (size_t)qb[cb] * 256 + 32 * c + 4 * g;
-                const float4 blo = *reinterpret_cast<const float4*>(qrow);
-                const float4 bhi = *reinterpret_cast<const float4*>(qrow + 16);
-                act[c][cb] = pack_relu(acc[2 * c][cb], acc[2 * c + 1][cb], blo, bhi);
+            for (int t = 0; t < 16; ++t) {
+                const float4 b4 = *reinterpret_cast<const float4*>(qrow + 16 * t);
+                const f32x4 c0 = {b4.x, b4.y, b4.z, b4.w};
+                const bf16x8 w = frag(t);
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[t][cb] = mfma(w, bm[cb], c0);
             }
         }
-        // ---- hidden layers ----
+        next_step();
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) act[c][cb] = pack_relu(acc[2 * c][cb], acc[2 * c + 1][cb]);
+        // ---- hidden layers: C starts at the bias ----
         for (int l = 0; l < n_mid; ++l) {
+            const float* bias = a.bias_h[l] + 4 * g;
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 advance();
 #pragma unroll
                 for (int t = 0; t < 16; ++t) {
                     const bf16x8 w = frag(t);
+                    f32x4 c0;
+                    if (c == 0) {
+                        const float4 b4 = *reinterpret_cast<const float4*>(bias + 16 * t);
+                        c0 = f32x4{b4.x, b4.y, b4.z, b4.w};
+                    }
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-                        acc[t][cb] = mfma(w, act[c][cb], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[t][cb]);
+                    for (int cb = 0; cb < NCB; ++cb) acc[t][cb] = mfma(w, act[c][cb], c == 0 ? c0 : acc[t][cb]);
                 }
-                __syncthreads();
-                ++q;
+                next_step();
             }
-            const float* bias = a.bias_h[l];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const float4 blo = *reinterpret_cast<const float4*>(bias + 32 * c + 4 * g);
-                const float4 bhi = *reinterpret_cast<const float4*>(bias + 32 * c + 16 + 4 * g);
+            for (int c = 0; c < 8; ++c)
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) act[c][cb] = pack_relu(acc[2 * c][cb], acc[2 * c + 1][cb], blo, bhi);
-            }
+                for (int cb = 0; cb < NCB; ++cb) act[c][cb] = pack_relu(acc[2 * c][cb], acc[2 * c + 1][cb]);
         }
         // ---- output layer: one 16-row tile (7 used), 8 k-chunks in one ring chunk ----
         advance();
-        f32x4 o[4];
+        f32x4 o[NCB];
+        {
+            f32x4 ob = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) o[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < 4; ++j)
+                if (4 * g + j < kOut) ob[j] = a.bias_o[4 * g + j];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) o[cb] = ob;
+        }
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const bf16x8 w = frag(c);
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) o[cb] = mfma(w, act[c][cb], o[cb]);
+            for (int cb = 0; cb < NCB; ++cb) o[cb] = mfma(w, act[c][cb], o[cb]);
         }
         // lane (g, n16) holds outputs 4g..4g+3 of pair cb*16+n16: transpose via LDS
         if (g < 2) {
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
+            for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int oi = 4 * g + j;
-                    outs[wave][cb * 16 + n16][oi] = oi < kOut ? o[cb][j] + a.bias_o[oi] : 0.f;
-                }
+                for (int j = 0; j < 4; ++j) outs[wave][cb * 16 + n16][4 * g + j] = o[cb][j];
         }
-        __syncthreads();
-        ++q;
-        {
-            const size_t row = base + lane;
-            if (row < total) deform_epilogue(a.m, row, (int)(row % a.m.N), outs[wave][lane]);
+        next_step();
+        if (lane < kPairsPerWave) {
+            const int p = p0 + lane;
+            if (p < a.m.N) deform_epilogue(a.m, row0 + p, p, outs[wave][lane]);
         }
         // `outs` is rewritten only after the next tile's first barrier
     }
@@ -217,7 +233,7 @@ __global__ void mean_features_bf16_kernel(const float* __restrict__ mx, const fl
     for (int k = 0; k < 32; ++k) out[(size_t)p * 32 + k] = (__bf16)(k < kMeanFeat ? f[k] : 0.f);
 }
 
-int n_persistent_blocks() {
+int n_compute_units() {
     static int n = 0;
     if (!n) {
         int dev = 0, cus = 0;
@@ -237,7 +253,7 @@ void compute_mean_features_bf16(DevScene& s, hipStream_t st) {
 }
 
 void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
-                     float* delta_out, hipStream_t st) {
+                     float* delta_out, hipStream_t st, int pairs_per_wave) {
     Bf16Args a{};
     a.m = make_args(s, qs, B, g, paper_mask, r, delta_out);
     a.stream = reinterpret_cast<const uint4*>(s.bf_stream);
@@ -245,11 +261,17 @@ void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, b
     a.mfeat = reinterpret_cast<const bf16x8*>(s.bf_mfeat);
     for (int l = 0; l + 1 < s.n_hidden && l < 7; ++l) a.bias_h[l] = s.b[l + 1];
     a.bias_o = s.b[s.n_hidden];
-    const size_t total = (size_t)s.n * B;
-    a.n_tiles = (int)((total + kPairsPerBlock - 1) / kPairsPerBlock);
+    const int ncb = pairs_per_wave == 32 ? 2 : 4;
+    const int per_block = 64 * ncb;
+    a.tiles_per_query = (s.n + per_block - 1) / per_block;
+    a.n_tiles = a.tiles_per_query * B;
     if (!a.n_tiles) return;
-    const int blocks = std::min(a.n_tiles, n_persistent_blocks());
-    mlp_bf16_kernel<<<blocks, 256, 0, st>>>(a);
+    const int blocks_per_cu = ncb == 2 ? 2 : 1;
+    const int blocks = std::min(a.n_tiles, n_compute_units() * blocks_per_cu);
+    if (ncb == 2)
+        mlp_bf16_kernel<2><<<blocks, 256, 0, st>>>(a);
+    else
+        mlp_bf16_kernel<4><<<blocks, 256, 0, st>>>(a);
 }
 
 }  // namespace swf

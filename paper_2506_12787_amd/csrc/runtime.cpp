@@ -373,7 +373,8 @@ swf_status Ctx::enqueue_preprocess(Scene* sc, const float* tx, int B, int flags,
         stage_end(st);
         stage_begin(SWF_STAGE_MLP, st);
         if (flags & SWF_MLP_BF16)
-            launch_mlp_bf16(d, (const float*)ws_qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, rec, delta_sorted, st);
+            launch_mlp_bf16(d, (const float*)ws_qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, rec, delta_sorted, st,
+                            mlp_pairs_per_wave);
         else
             launch_mlp_fp32(d, (const float*)ws_qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, rec, delta_sorted, st);
         stage_end(st);
@@ -479,6 +480,7 @@ swf_status swf_create(swf_ctx** out, const swf_config* cfg) {
     Ctx* c = new (std::nothrow) Ctx();
     if (!c) return SWF_E_OOM;
     c->device = dev;
+    c->mlp_pairs_per_wave = cfg ? cfg->mlp_pairs_per_wave : 0;
     if (hipMalloc(&c->total_dev, 64) != hipSuccess || hipHostMalloc(&c->total_host, 64, 0) != hipSuccess) {
         delete c;
         return SWF_E_OOM;

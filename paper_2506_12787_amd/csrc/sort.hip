@@ -4,8 +4,8 @@
 //
 // Sort: reduce-then-scan LSD radix sort with 8-bit digits and a fixed grid (no
 // inter-workgroup waits, so no forward-progress assumption). Each pass:
-// per-block digit histograms -> one-block exclusive scan over (digit, block) ->
-// scatter, where keys are ranked stably inside a 2048-key tile with wave64
+// per-block digit histograms -> per-digit exclusive scans over the blocks
+// (digit offsets folded into the scatter prologue) -> scatter, where keys are ranked stably inside a 2048-key tile with wave64
 // ballots (8 ballots give each lane the mask of lanes sharing its digit).
 #include "kernels.h"
 #include "swf_device.h"
@@ -178,30 +178,22 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const K* __restric
     }
 }
 
-// Exclusive scan of m uint32 values in place by one block (digit-major
-// histogram, m = 256 * G <= 256 * kMaxGrid).
-__global__ __launch_bounds__(1024) void hist_scan_kernel(uint32_t* __restrict__ h, int m) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int per = (m + 1023) / 1024;
-    const int beg = min(t * per, m), end = min(beg + per, m);
-    uint32_t s = 0;
-    for (int i = beg; i < end; ++i) s += h[i];
-    part[t] = s;
-    __syncthreads();
-    // Hillis-Steele over 1024 partial sums
-    for (int o = 1; o < 1024; o <<= 1) {
-        const uint32_t v = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+// Per-digit exclusive scan over the G block counts (digit-major histogram):
+// block d scans hist[d][0..G) in place and writes the digit total.
+__global__ __launch_bounds__(kThreads) void digit_scan_kernel(uint32_t* __restrict__ hist, int G,
+                                                              uint32_t* __restrict__ dtot) {
+    __shared__ uint32_t lds[kWaves + 1];
+    uint32_t* h = hist + (size_t)blockIdx.x * G;
+    uint32_t base = 0;
+    for (int c = 0; c < G; c += kThreads) {
+        const int i = c + threadIdx.x;
+        const uint32_t v = i < G ? h[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(v, lds, &tot);
+        if (i < G) h[i] = base + ex;
+        base += tot;
     }
-    uint32_t run = part[t] - s;
-    for (int i = beg; i < end; ++i) {
-        const uint32_t v = h[i];
-        h[i] = run;
-        run += v;
-    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = base;
 }
 
 template <typename K>
@@ -209,12 +201,20 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const K* __rest
                                                                  const uint32_t* __restrict__ vin,
                                                                  K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                                  int64_t n, int shift, int64_t chunk,
-                                                                 const uint32_t* __restrict__ hist, int G) {
+                                                                 const uint32_t* __restrict__ hist, int G,
+                                                                 const uint32_t* __restrict__ dtot) {
     __shared__ uint32_t wcnt[kWaves][256];
     __shared__ uint32_t base[256];
     __shared__ uint32_t ttot[256];
+    __shared__ uint32_t lds[kWaves + 1];
     const int w = threadIdx.x >> 6;
-    for (int d = threadIdx.x; d < 256; d += kThreads) base[d] = hist[(size_t)d * G + blockIdx.x];
+    {
+        // digit offsets: exclusive scan of the digit totals
+        static_assert(kThreads == 256, "one thread per digit");
+        uint32_t tot;
+        const uint32_t doff = block_exclusive_scan<uint32_t>(dtot[threadIdx.x], lds, &tot);
+        base[threadIdx.x] = doff + hist[(size_t)threadIdx.x * G + blockIdx.x];
+    }
     const int64_t beg = (int64_t)blockIdx.x * chunk;
     const int64_t end = min(beg + chunk, n);
     for (int64_t t0 = beg; t0 < end; t0 += kTile) {
@@ -303,6 +303,7 @@ int radix_sort_t(K* keys, uint32_t* vals, K* kalt, uint32_t* valt, int64_t n, in
                  uint32_t* hist, hipStream_t st) {
     if (n <= 1 || end_bit <= begin_bit) return 0;
     const int G = radix_grid(n);
+    uint32_t* dtot = hist + (size_t)256 * G;
     int64_t chunk = (n + G - 1) / G;
     chunk = ((chunk + kTile - 1) / kTile) * kTile;
     K* ki = keys;
@@ -312,8 +313,8 @@ int radix_sort_t(K* keys, uint32_t* vals, K* kalt, uint32_t* valt, int64_t n, in
     int flips = 0;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
         radix_hist_kernel<K><<<G, kThreads, 0, st>>>(ki, n, shift, chunk, hist, G);
-        hist_scan_kernel<<<1, 1024, 0, st>>>(hist, 256 * G);
-        radix_scatter_kernel<K><<<G, kThreads, 0, st>>>(ki, vi, ko, vo, n, shift, chunk, hist, G);
+        digit_scan_kernel<<<256, kThreads, 0, st>>>(hist, G, dtot);
+        radix_scatter_kernel<K><<<G, kThreads, 0, st>>>(ki, vi, ko, vo, n, shift, chunk, hist, G, dtot);
         std::swap(ki, ko);
         std::swap(vi, vo);
         flips ^= 1;
@@ -360,7 +361,7 @@ void launch_emit_keys(const Records& r, const uint32_t* offsets, const uint32_t*
                                                              g.tiles, capacity, keys, vals, status);
 }
 
-size_t radix_scratch_bytes(int64_t n) { return sizeof(uint32_t) * 256 * (size_t)radix_grid(n); }
+size_t radix_scratch_bytes(int64_t n) { return sizeof(uint32_t) * 256 * ((size_t)radix_grid(n) + 1); }
 
 int launch_radix_sort(void* keys, uint32_t* vals, void* kalt, uint32_t* valt, int64_t n, int key_bytes, int begin_bit,
                       int end_bit, void* scratch, hipStream_t st) {
