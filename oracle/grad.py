@@ -22,8 +22,9 @@ def _pixel_weights(C, target, count):
     return np.sign(C - target) / float(count)
 
 
-def raster_grad(rg: dict, order, pix, w):
-    """d(sum_p w_p C_p) / d(mx, my, ixx, ixy, iyy, opacity, amp) per Gaussian."""
+def raster_grad(rg: dict, order, pix, w, flags_out=None):
+    """d(sum_p w_p C_p) / d(mx, my, ixx, ixy, iyy, opacity, amp) per Gaussian.
+    flags_out (int8 array of n), if given, receives the near-threshold marks."""
     lib = M._raster()
     n = len(rg["mx"])
     grad = np.zeros((n, 7))
@@ -33,8 +34,10 @@ def raster_grad(rg: dict, order, pix, w):
     w = np.ascontiguousarray(w, np.float64)
     consts = np.array([M.ALPHA_MAX, M.ALPHA_MIN, M.T_MIN, M.Q_MAX], np.float64)
     P = M._ptr
+    marg = np.array(M.DEFAULT_MARGINS, np.float64)
     lib.oracle_grad(n, P(rg["mx"]), P(rg["my"]), P(rg["ixx"]), P(rg["ixy"]), P(rg["iyy"]), P(rg["op"]),
-                    P(rg["amp"]), P(rg["live"]), P(order), P(consts), len(px), P(px), P(py), P(w), P(grad))
+                    P(rg["amp"]), P(rg["live"]), P(order), P(consts), P(marg), len(px), P(px), P(py), P(w), P(grad),
+                    None if flags_out is None else P(flags_out))
     return grad
 
 
@@ -102,17 +105,21 @@ def posenc_backward(v, L, dgamma):
     return out
 
 
-def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAULT_ROOM, stop_grad_pos=False):
+def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAULT_ROOM, stop_grad_pos=False,
+                  pixel_weights=None):
     """L1 loss over a batch of queries and its FP64 gradient.
 
     Returns (loss, grads) where grads has 'base' (n, 7) for
-    (mx, my, lsx, lsy, rot, logit, amp) and, with an MLP, 'W'/'b' lists."""
+    (mx, my, lsx, lsy, rot, logit, amp) and, with an MLP, 'W'/'b' lists.
+    With pixel_weights (one array of H*W per query) the objective is instead
+    sum_b sum_p w_bp C_bp, and the returned loss is that sum."""
     B = len(txs)
     H, W = scene.H, scene.W
     count = B * H * W
     pix = M.full_grid(H, W)
     order = M.depth_order(scene.depth)
     gbase = np.zeros((scene.n, 7))
+    gflag = np.zeros(scene.n, np.int8)
     gW = [np.zeros_like(w) for w in mlp.W] if mlp is not None else None
     gb = [np.zeros_like(b) for b in mlp.b] if mlp is not None else None
     loss = 0.0
@@ -122,10 +129,16 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
         g = M.deform(scene, delta)
         rg = M.gaussians_for_raster(g, scene.depth)
         res = M.composite(rg, order, pix[0], pix[1], margins=None)
-        t = np.asarray(targets[b], np.float64).ravel()
-        loss += np.abs(res.C - t).sum() / count
-        w = _pixel_weights(res.C, t, count)
-        gr = raster_grad(rg, order, pix, w)
+        if pixel_weights is not None:
+            w = np.asarray(pixel_weights[b], np.float64).ravel()
+            loss += float((w * res.C).sum())
+        else:
+            t = np.asarray(targets[b], np.float64).ravel()
+            loss += np.abs(res.C - t).sum() / count
+            w = _pixel_weights(res.C, t, count)
+        fl = np.zeros(scene.n, np.int8)
+        gr = raster_grad(rg, order, pix, w, fl)
+        gflag |= fl
         gp = chain_to_params(g, rg, gr)
         gbase += gp
         if mlp is not None:
@@ -140,7 +153,7 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
             gbase[:, 1] += dmu_hat[:, 1] / H
     if stop_grad_pos:
         gbase[:, 0:2] = 0.0
-    return loss, dict(base=gbase, W=gW, b=gb)
+    return loss, dict(base=gbase, W=gW, b=gb, flagged=gflag.astype(bool))
 
 
 def loss_only(scene: M.Scene, mlp, txs, targets, room=M.DEFAULT_ROOM):

@@ -245,15 +245,18 @@ void oracle_render(int64_t n, const double *mx, const double *my, const double *
 
 /* Gradient of sum_p w[p] * C[p] with every decision held at its FP64 outcome.
  * grad[g*7 + c] for c = (mx, my, ixx, ixy, iyy, opacity, amp); ixy is the single
- * off-diagonal entry, so d q / d ixy = 2 dx dy. `grad` is overwritten. */
+ * off-diagonal entry, so d q / d ixy = 2 dx dy. `grad` is overwritten. With
+ * margins and gflag, gflag[g] = 1 marks Gaussians with a near-threshold decision
+ * at some weighted pixel (writes of 1 only, so concurrent marking is benign). */
 void oracle_grad(int64_t n, const double *mx, const double *my, const double *ixx, const double *ixy,
                  const double *iyy, const double *op, const double *amp, const int8_t *live,
-                 const int64_t *order, const double *consts, int64_t npix, const int32_t *pix_x,
-                 const int32_t *pix_y, const double *w, double *grad)
+                 const int64_t *order, const double *consts, const double *margins, int64_t npix,
+                 const int32_t *pix_x, const int32_t *pix_y, const double *w, double *grad, int8_t *gflag)
 {
     scene_t s;
-    fill_scene(&s, n, mx, my, ixx, ixy, iyy, op, amp, live, order, consts, NULL);
+    fill_scene(&s, n, mx, my, ixx, ixy, iyy, op, amp, live, order, consts, margins);
     memset(grad, 0, sizeof(double) * (size_t)n * 7);
+    if (gflag) memset(gflag, 0, (size_t)n);
 #pragma omp parallel
     {
         double *acc = (double *)calloc((size_t)n * 7, sizeof(double));
@@ -272,12 +275,18 @@ void oracle_grad(int64_t n, const double *mx, const double *my, const double *ix
                 if (!s.live[g]) continue;
                 const double dx = px - s.mx[g], dy = py - s.my[g];
                 const double q = s.ixx[g] * dx * dx + 2.0 * s.ixy[g] * dx * dy + s.iyy[g] * dy * dy;
+                /* a Gaussian whose cutoff or skip decision at a weighted pixel lies
+                 * within the margin of its threshold is marked: its gradient may
+                 * legitimately differ from an FP32 evaluation */
+                if (gflag && margins && near_threshold(q, s.qmax, s.mq)) gflag[g] = 1;
                 if (!(q <= s.qmax)) continue;
                 double a = s.op[g] * exp(-0.5 * q);
                 int clamped = 0;
                 if (a > s.amax) { a = s.amax; clamped = 1; }
+                if (gflag && margins && near_threshold(a, s.amin, s.ma)) gflag[g] = 1;
                 if (!(a >= s.amin)) continue;
                 const double Tn = T * (1.0 - a);
+                if (gflag && margins && near_threshold(Tn, s.tmin, s.mt)) gflag[g] = 1;
                 if (Tn < s.tmin) break;
                 cg[m] = g; ca[m] = a; cT[m] = T; cc[m] = (int8_t)clamped;
                 ++m;

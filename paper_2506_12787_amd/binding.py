@@ -193,6 +193,8 @@ class Context:
         return (out, aux) if (flags & KEEP_AUX) else out
 
     def render_backward(self, sid: int, tx, flags: int, grad_out, aux, grads: dict):
+        """Gradients of sum(grad_out * out) into the caller's device tensors in
+        `grads` (keys of PARAMS[:7], and optionally 'weight' / 'bias' lists)."""
         gr = _Grads()
         for k in PARAMS[:7]:
             setattr(gr, k, grads[k].data_ptr() if grads.get(k) is not None else None)

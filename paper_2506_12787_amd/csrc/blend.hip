@@ -60,15 +60,11 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
         const int cnt = (int)min((uint32_t)kN, rg.y - start);
         if (!done) {
             for (int j = 0; j < cnt; ++j) {
-                const float2 p = s_pos[j];
-                const float4 m = s_wm[j];
-                const float dx = fx - p.x, dy = fy - p.y;
-                const float u = fmaf(m.x, dx, m.y * dy);
-                const float w = fmaf(m.z, dx, m.w * dy);
-                const float q = fmaf(u, u, w * w);
+                float dx, dy, u, w;
+                const float q = blend_q(fx, fy, s_pos[j], s_wm[j], dx, dy, u, w);
                 if (q > kQMax) continue;
                 const float2 o = s_oa[j];
-                const float a = fminf(kAlphaMax, o.x * __builtin_amdgcn_exp2f(q * kNegHalfLog2e));
+                const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
                 if (a < kAlphaMin) continue;
                 const float Tn = T * (1.0f - a);
                 if (Tn < kTMin) {

@@ -42,9 +42,10 @@ struct Grid {
 };
 
 // pe_mlp.hip
-void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hipStream_t st);
+void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hipStream_t st,
+                        float* feat_out = nullptr);
 void launch_mlp_fp32(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
-                     float* delta_out, hipStream_t st);
+                     float* delta_out, hipStream_t st, float* const* act_out = nullptr);
 void launch_preprocess_static(const DevScene& s, int B, const Grid& g, const Records& r, hipStream_t st);
 void launch_permute_delta(const float* delta_sorted, const uint32_t* perm, int B, int n, float* delta_out,
                           hipStream_t st);
@@ -70,6 +71,22 @@ int launch_radix_sort(void* keys, uint32_t* vals, void* kalt, uint32_t* valt, in
                       int begin_bit, int end_bit, void* scratch, hipStream_t st);
 void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gtiles, uint2* ranges,
                         hipStream_t st);
+
+// backward.hip
+void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
+                           const float* grad_out, const float* aux_T, const uint32_t* aux_last, float* dpair,
+                           hipStream_t st);
+void launch_preprocess_backward(const float* dpair, const Records& r, int64_t P, bool paper_mask, float* dbase,
+                                float* dy, hipStream_t st);
+void launch_base_reduce(const float* dbase, const float* dmu_pe, const uint32_t* perm, int B, int N,
+                        float* const* out_dev, hipStream_t st);
+void launch_dgrad(const float* in, int K, const float* Wrm, const float* Hmask, int64_t P, float* out,
+                  hipStream_t st);
+int64_t wgrad_chunks(int64_t P);
+void launch_wgrad(const float* dz, int O, const float* X, int I, const float* fmean, const float* ftx, int N, int64_t P,
+                  float* part, float* dW, float* db, hipStream_t st);
+void launch_pe_backward(const float* dz0, const DevScene& s, int B, float* dmu, hipStream_t st);
+void launch_mean_features_f32(const DevScene& s, float* out, hipStream_t st);
 
 // blend.hip
 void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,

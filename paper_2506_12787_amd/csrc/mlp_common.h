@@ -25,8 +25,9 @@ struct MlpArgs {
     const float* bh[7];
     const float* wo_t;
     const float* bo;
-    Records rec;
+    Records rec;         // rec.geo == nullptr: no records (activation recompute only)
     float* delta_out;
+    float* act_out[8];   // FP32 kernel only: store hidden activations H_l [P][256] when set
 };
 
 
@@ -51,7 +52,7 @@ __device__ __forceinline__ void deform_epilogue(const MlpArgs& a, size_t row, in
         o.rect_x = o.rect_y = 0;
         o.count = 0;
     }
-    write_record(a.rec, row, o);
+    if (a.rec.geo) write_record(a.rec, row, o);
 }
 
 inline MlpArgs make_args(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,

@@ -19,7 +19,8 @@ namespace {
 __global__ __launch_bounds__(256) void tx_features_kernel(const float* __restrict__ tx, const float* __restrict__ w1,
                                                           const float* __restrict__ b1, int hidden, int in_dim,
                                                           float lox, float loy, float loz, float rx, float ry,
-                                                          float rz, float* __restrict__ qs) {
+                                                          float rz, float* __restrict__ qs,
+                                                          float* __restrict__ feat_out) {
     __shared__ float feat[kTxFeat];
     const int b = blockIdx.x;
     const int t = threadIdx.x;
@@ -43,6 +44,7 @@ __global__ __launch_bounds__(256) void tx_features_kernel(const float* __restric
         }
     }
     __syncthreads();
+    if (feat_out && t < kTxFeat) feat_out[(size_t)b * kTxFeat + t] = feat[t];
     for (int j = t; j < hidden; j += blockDim.x) {
         const float* row = w1 + (size_t)j * in_dim + kMeanFeat;
         float acc = b1[j];
@@ -114,6 +116,12 @@ __global__ __launch_bounds__(256, 2) void mlp_fp32_kernel(MlpArgs a) {
         float4* dst = reinterpret_cast<float4*>(&act[(tr * 4 + i) * kActStride + tc * 8]);
         dst[0] = make_float4(fmaxf(acc[i][0], 0.f), fmaxf(acc[i][1], 0.f), fmaxf(acc[i][2], 0.f), fmaxf(acc[i][3], 0.f));
         dst[1] = make_float4(fmaxf(acc[i][4], 0.f), fmaxf(acc[i][5], 0.f), fmaxf(acc[i][6], 0.f), fmaxf(acc[i][7], 0.f));
+        const size_t row = row0 + tr * 4 + i;
+        if (a.act_out[0] && row < total) {
+            float4* g = reinterpret_cast<float4*>(a.act_out[0] + row * kHid + tc * 8);
+            g[0] = dst[0];
+            g[1] = dst[1];
+        }
     }
 
     // hidden -> hidden layers; weights streamed through ws in kKS-row slabs
@@ -169,6 +177,12 @@ __global__ __launch_bounds__(256, 2) void mlp_fp32_kernel(MlpArgs a) {
             float4* dst = reinterpret_cast<float4*>(&act[(tr * 4 + i) * kActStride + tc * 8]);
             dst[0] = make_float4(fmaxf(acc[i][0], 0.f), fmaxf(acc[i][1], 0.f), fmaxf(acc[i][2], 0.f), fmaxf(acc[i][3], 0.f));
             dst[1] = make_float4(fmaxf(acc[i][4], 0.f), fmaxf(acc[i][5], 0.f), fmaxf(acc[i][6], 0.f), fmaxf(acc[i][7], 0.f));
+            const size_t row = row0 + tr * 4 + i;
+            if (a.act_out[l + 1] && row < total) {
+                float4* g = reinterpret_cast<float4*>(a.act_out[l + 1] + row * kHid + tc * 8);
+                g[0] = dst[0];
+                g[1] = dst[1];
+            }
         }
     }
     // output layer: 7 dot products of length 256 per row
@@ -219,15 +233,17 @@ __global__ void permute_delta_kernel(const float* __restrict__ src, const uint32
 
 }  // namespace
 
-void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hipStream_t st) {
+void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hipStream_t st, float* feat_out) {
     const float rx = s.room_hi[0] - s.room_lo[0], ry = s.room_hi[1] - s.room_lo[1], rz = s.room_hi[2] - s.room_lo[2];
     tx_features_kernel<<<B, 256, 0, st>>>(tx, s.w[0], s.b[0], s.hidden, s.in_dim, s.room_lo[0], s.room_lo[1],
-                                          s.room_lo[2], rx, ry, rz, qs);
+                                          s.room_lo[2], rx, ry, rz, qs, feat_out);
 }
 
 void launch_mlp_fp32(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
-                     float* delta_out, hipStream_t st) {
-    const MlpArgs a = make_args(s, qs, B, g, paper_mask, r, delta_out);
+                     float* delta_out, hipStream_t st, float* const* act_out) {
+    MlpArgs a = make_args(s, qs, B, g, paper_mask, r, delta_out);
+    if (act_out)
+        for (int l = 0; l < s.n_hidden && l < 8; ++l) a.act_out[l] = act_out[l];
     const size_t total = (size_t)s.n * B;
     const unsigned blocks = (unsigned)((total + kR - 1) / kR);
     if (blocks) mlp_fp32_kernel<<<blocks, 256, 0, st>>>(a);

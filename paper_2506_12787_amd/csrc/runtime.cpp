@@ -386,17 +386,17 @@ swf_status Ctx::enqueue_preprocess(Scene* sc, const float* tx, int B, int flags,
     return hip(hipGetLastError(), "preprocess launch");
 }
 
-swf_status Ctx::render(int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st) {
+// Forward up to the per-tile lists: preprocess (+ MLP), scan, keys, sort,
+// tile ranges. Records the result in `last`.
+swf_status Ctx::forward_lists(int sid, const float* tx, int B, int flags, hipStream_t st) {
     Scene* sc = scene(sid);
     if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
     if (B < 1) return fail(SWF_E_INVALID, "batch must be >= 1");
-    if (!out) return fail(SWF_E_INVALID, "out is NULL");
-    if ((flags & SWF_KEEP_AUX) && !aux) return fail(SWF_E_INVALID, "SWF_KEEP_AUX needs aux");
     const DevScene& d = sc->d;
     if ((uint64_t)B * (uint64_t)d.n >= (1ull << 32)) return fail(SWF_E_INVALID, "batch * n must be < 2^32");
     const Grid g = make_grid(d.H, d.W, (flags & SWF_TILE8) ? 8 : 16);
     if ((uint64_t)B * g.tiles >= (1ull << 31)) return fail(SWF_E_INVALID, "batch * tiles too large");
-    hipSetDevice(device);
+    last.valid = false;
     swf_status s = enqueue_preprocess(sc, tx, B, flags, g, nullptr, st);
     if (s) return s;
     const int64_t pairs = (int64_t)B * d.n;
@@ -433,15 +433,6 @@ swf_status Ctx::render(int sid, const float* tx, int B, int flags, float* out, v
     stage_begin(SWF_STAGE_RANGES, st);
     launch_tile_ranges(skeys, (int)kb, (int64_t)nk, n_gt, (uint2*)ws_ranges.ptr, st);
     stage_end(st);
-    float* auxT = nullptr;
-    uint32_t* auxL = nullptr;
-    if (flags & SWF_KEEP_AUX) {
-        auxT = (float*)aux;
-        auxL = (uint32_t*)((char*)aux + sizeof(float) * (size_t)B * d.H * d.W);
-    }
-    stage_begin(SWF_STAGE_BLEND, st);
-    launch_blend_forward((const uint2*)ws_ranges.ptr, svals, rec, B, g, out, auxT, auxL, st);
-    stage_end(st);
     last.valid = true;
     last.scene = sid;
     last.B = B;
@@ -452,6 +443,25 @@ swf_status Ctx::render(int sid, const float* tx, int B, int flags, float* out, v
     last.full = full;
     last.keys = skeys;
     last.vals = svals;
+    return hip(hipGetLastError(), "forward launch");
+}
+
+swf_status Ctx::render(int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st) {
+    if (!out) return fail(SWF_E_INVALID, "out is NULL");
+    if ((flags & SWF_KEEP_AUX) && !aux) return fail(SWF_E_INVALID, "SWF_KEEP_AUX needs aux");
+    hipSetDevice(device);
+    swf_status s = forward_lists(sid, tx, B, flags, st);
+    if (s) return s;
+    const DevScene& d = scene(sid)->d;
+    float* auxT = nullptr;
+    uint32_t* auxL = nullptr;
+    if (flags & SWF_KEEP_AUX) {
+        auxT = (float*)aux;
+        auxL = (uint32_t*)((char*)aux + sizeof(float) * (size_t)B * d.H * d.W);
+    }
+    stage_begin(SWF_STAGE_BLEND, st);
+    launch_blend_forward((const uint2*)ws_ranges.ptr, last.vals, rec, B, last.grid, out, auxT, auxL, st);
+    stage_end(st);
     return hip(hipGetLastError(), "render launch");
 }
 

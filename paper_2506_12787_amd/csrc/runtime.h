@@ -56,10 +56,12 @@ struct Ctx {
 
     // workspace
     Buf ws_qs, ws_geo, ws_wm, ws_oa, ws_rect, ws_count, ws_off, ws_scan, ws_keys, ws_keys2, ws_vals, ws_vals2,
-        ws_hist, ws_ranges, ws_delta, ws_sortk, ws_sortv, ws_grad;
+        ws_hist, ws_ranges, ws_delta, ws_sortk, ws_sortv, ws_grad, ws_dpair, ws_dbase, ws_dy, ws_act, ws_dz,
+        ws_part, ws_fmean, ws_ftx, ws_dmu, ws_ptrs;
     std::vector<Buf*> all_bufs() {
         return {&ws_qs, &ws_geo, &ws_wm, &ws_oa, &ws_rect, &ws_count, &ws_off, &ws_scan, &ws_keys, &ws_keys2,
-                &ws_vals, &ws_vals2, &ws_hist, &ws_ranges, &ws_delta, &ws_sortk, &ws_sortv, &ws_grad};
+                &ws_vals, &ws_vals2, &ws_hist, &ws_ranges, &ws_delta, &ws_sortk, &ws_sortv, &ws_grad, &ws_dpair,
+                &ws_dbase, &ws_dy, &ws_act, &ws_dz, &ws_part, &ws_fmean, &ws_ftx, &ws_dmu, &ws_ptrs};
     }
     Records rec;
     uint64_t* total_dev = nullptr;   // device: scan total (and status word after it)
@@ -84,7 +86,10 @@ struct Ctx {
     swf_status release_scene(int id);
     swf_status enqueue_preprocess(Scene* sc, const float* tx, int B, int flags, const Grid& g, float* delta_sorted,
                                   hipStream_t st);
+    swf_status forward_lists(int sid, const float* tx, int B, int flags, hipStream_t st);
     swf_status render(int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st);
+    swf_status backward(int sid, const float* tx, int B, int flags, const float* grad_out, const void* aux,
+                        const swf_grads* grads, hipStream_t st);
     void stage_begin(int stage, hipStream_t st);
     void stage_end(hipStream_t st);
     void resolve_timing();

@@ -87,6 +87,22 @@ __device__ __forceinline__ PairOut preprocess_pair(float mx0, float my0, float d
     return r;
 }
 
+// One blend evaluation of a list entry at a pixel (tile-block-relative
+// coordinates): q = |M d|^2 with d = pixel - mean. Forward and backward share
+// this code so that their cutoff / skip decisions are bitwise identical.
+__device__ __forceinline__ float blend_q(float fx, float fy, float2 p, float4 m, float& dx, float& dy, float& u,
+                                         float& w) {
+    dx = fx - p.x;
+    dy = fy - p.y;
+    u = fmaf(m.x, dx, m.y * dy);
+    w = fmaf(m.z, dx, m.w * dy);
+    return fmaf(u, u, w * w);
+}
+// opacity * exp(-q/2) before the 0.99 clamp
+__device__ __forceinline__ float blend_raw_alpha(float q, float op) {
+    return op * __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+}
+
 // Order-preserving map of an FP32 depth to uint32 (-0 like +0).
 __host__ __device__ __forceinline__ uint32_t depth_key_bits(float d) {
     if (d == 0.0f) d = 0.0f;
