@@ -138,6 +138,13 @@ const char *swf_last_error(swf_ctx *ctx);
 swf_status swf_scene_upload(swf_ctx *ctx, const swf_gaussians *g, const swf_mlp *mlp, int32_t height,
                             int32_t width, int32_t src_is_device, int32_t *scene_id);
 swf_status swf_scene_release(swf_ctx *ctx, int32_t scene_id);
+/* Replace the parameters of an uploaded scene in place (training). g (may be
+ * NULL) must have the uploaded n; its depth array is ignored: the scene keeps
+ * the (depth, id) order it was uploaded with (depth gets no gradient; upload a
+ * new scene to change depths). mlp (may be NULL) must have the uploaded shape.
+ * Sources are host or device (src_is_device). Waits for `stream`. */
+swf_status swf_scene_update(swf_ctx *ctx, int32_t scene_id, const swf_gaussians *g, const swf_mlp *mlp,
+                            int32_t src_is_device, void *stream);
 /* Device bytes held by a scene (its Gaussians, presort data and weights). */
 swf_status swf_scene_bytes(swf_ctx *ctx, int32_t scene_id, uint64_t *bytes);
 

@@ -70,6 +70,7 @@ def lib():
             "swf_status_string": [I32],
             "swf_scene_upload": [P, P, P, I32, I32, I32, P],
             "swf_scene_release": [P, I32],
+            "swf_scene_update": [P, I32, P, P, I32, P],
             "swf_scene_bytes": [P, I32, P],
             "swf_render": [P, I32, P, I32, I32, P, P, P],
             "swf_render_backward": [P, I32, P, I32, I32, P, P, P, P],
@@ -119,6 +120,7 @@ class Context:
         self._check(self._L.swf_create(ctypes.byref(h), ctypes.byref(cfg)), ctx=False)
         self._h = h
         self._keep = {}
+        self._rooms = {}
 
     def _check(self, st, ctx=True):
         if st != 0:
@@ -163,7 +165,33 @@ class Context:
         self._check(self._L.swf_scene_upload(self._h, ctypes.byref(g), ctypes.byref(m) if m is not None else None,
                                              H, W, 0, ctypes.byref(sid)))
         self._keep[sid.value] = (H, W, n, mlp is not None)
+        self._rooms[sid.value] = room
         return sid.value
+
+    def update_scene(self, sid: int, gaussians: dict | None = None, mlp=None):
+        """Replace parameters of a resident scene from CUDA tensors (float32,
+        contiguous): gaussians keyed like PARAMS[:7] (depth is kept), mlp as
+        (Ws, bs) lists. The scene keeps its (depth, id) order."""
+        g = m = None
+        keep = []
+        if gaussians is not None:
+            cols = {k: gaussians[k].contiguous() for k in PARAMS[:7]}
+            keep.append(cols)
+            n = self._keep[sid][2]
+            g = _Gaussians(n=n, **{k: cols[k].data_ptr() for k in PARAMS[:7]}, depth=None)
+        if mlp is not None:
+            Ws, bs = [w.contiguous() for w in mlp[0]], [b.contiguous() for b in mlp[1]]
+            keep += [Ws, bs]
+            m = _Mlp(mean_bands=6, tx_bands=10, hidden=Ws[0].shape[0], n_hidden=len(Ws) - 1)
+            for l in range(len(Ws)):
+                m.weight[l] = Ws[l].data_ptr()
+                m.bias[l] = bs[l].data_ptr()
+            room = self._rooms[sid]
+            for k in range(3):
+                m.room_lo[k] = room[0][k]
+                m.room_hi[k] = room[1][k]
+        self._check(self._L.swf_scene_update(self._h, sid, ctypes.byref(g) if g is not None else None,
+                                             ctypes.byref(m) if m is not None else None, 1, _stream()))
 
     def release_scene(self, sid: int):
         self._check(self._L.swf_scene_release(self._h, sid))

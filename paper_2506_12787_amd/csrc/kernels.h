@@ -47,6 +47,7 @@ void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hi
 void launch_mlp_fp32(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
                      float* delta_out, hipStream_t st, float* const* act_out = nullptr);
 void launch_preprocess_static(const DevScene& s, int B, const Grid& g, const Records& r, hipStream_t st);
+void launch_gather_params(float* const* src, const uint32_t* perm, int n, float* const* dst, hipStream_t st);
 void launch_permute_delta(const float* delta_sorted, const uint32_t* perm, int B, int n, float* delta_out,
                           hipStream_t st);
 

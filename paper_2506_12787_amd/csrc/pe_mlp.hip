@@ -231,7 +231,29 @@ __global__ void permute_delta_kernel(const float* __restrict__ src, const uint32
     for (int k = 0; k < kOut; ++k) dst[o * kOut + k] = src[i * kOut + k];
 }
 
+struct Ptr7 {
+    const float* s[7];
+    float* d[7];
+};
+
+__global__ void gather_params_kernel(Ptr7 p, const uint32_t* __restrict__ perm, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t src = perm[i];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) p.d[k][i] = p.s[k][src];
+}
+
 }  // namespace
+
+void launch_gather_params(float* const* src, const uint32_t* perm, int n, float* const* dst, hipStream_t st) {
+    Ptr7 p;
+    for (int k = 0; k < 7; ++k) {
+        p.s[k] = src[k];
+        p.d[k] = dst[k];
+    }
+    if (n > 0) gather_params_kernel<<<(n + 255) / 256, 256, 0, st>>>(p, perm, n);
+}
 
 void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hipStream_t st, float* feat_out) {
     const float rx = s.room_hi[0] - s.room_lo[0], ry = s.room_hi[1] - s.room_lo[1], rz = s.room_hi[2] - s.room_lo[2];

@@ -237,7 +237,28 @@ swf_status Ctx::upload_scene(const swf_gaussians* g, const swf_mlp* mlp, int H, 
     if (!st) st = upload(this, s, &d.inv_perm, inv.data(), n);
     s->host_dbits = dbits;
     s->host_perm = perm;
-    if (!st && mlp) {
+    if (!st && mlp) st = pack_mlp(s, mlp, dev, true);
+    if (st) {
+        free_scene(s);
+        return st;
+    }
+    const int sid = next_scene++;
+    scenes[sid] = s;
+    *id = sid;
+    return SWF_OK;
+}
+
+swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
+    DevScene& d = s->d;
+    const size_t n = (size_t)d.n;
+    swf_status st = SWF_OK;
+    // allocate (first upload) or overwrite in place (update; shapes must match)
+    auto put = [&](auto** dst, const auto* src, size_t cnt) -> swf_status {
+        if (alloc) return upload(this, s, dst, src, cnt);
+        if (!cnt) return SWF_OK;
+        return hip(hipMemcpy(*dst, src, cnt * sizeof(*src), hipMemcpyHostToDevice), "hipMemcpy(mlp)");
+    };
+    {
         d.has_mlp = true;
         d.hidden = mlp->hidden;
         d.n_hidden = mlp->n_hidden;
@@ -256,26 +277,26 @@ swf_status Ctx::upload_scene(const swf_gaussians* g, const swf_mlp* mlp, int H, 
         for (int l = 0; l <= d.n_hidden && !st; ++l) {
             st = fetch(this, Wh[l], mlp->weight[l], (size_t)rows[l] * cols[l], dev);
             if (!st) st = fetch(this, Bh[l], mlp->bias[l], (size_t)rows[l], dev);
-            if (!st) st = upload(this, s, &d.w[l], Wh[l].data(), Wh[l].size());
-            if (!st) st = upload(this, s, &d.b[l], Bh[l].data(), Bh[l].size());
+            if (!st) st = put(&d.w[l], Wh[l].data(), Wh[l].size());
+            if (!st) st = put(&d.b[l], Bh[l].data(), Bh[l].size());
         }
         if (!st) {
             std::vector<float> t((size_t)kMeanFeat * Hd);
             for (int k = 0; k < kMeanFeat; ++k)
                 for (int j = 0; j < Hd; ++j) t[(size_t)k * Hd + j] = Wh[0][(size_t)j * d.in_dim + k];
-            st = upload(this, s, &d.w1m_t, t.data(), t.size());
+            st = put(&d.w1m_t, t.data(), t.size());
         }
         for (int l = 1; l < d.n_hidden && !st; ++l) {
             std::vector<float> t((size_t)Hd * Hd);
             for (int k = 0; k < Hd; ++k)
                 for (int j = 0; j < Hd; ++j) t[(size_t)k * Hd + j] = Wh[l][(size_t)j * Hd + k];
-            st = upload(this, s, &d.wh_t[l - 1], t.data(), t.size());
+            st = put(&d.wh_t[l - 1], t.data(), t.size());
         }
         if (!st) {
             std::vector<float> t((size_t)Hd * kOut);
             for (int k = 0; k < Hd; ++k)
                 for (int o = 0; o < kOut; ++o) t[(size_t)k * kOut + o] = Wh[d.n_hidden][(size_t)o * Hd + k];
-            st = upload(this, s, &d.wo_t, t.data(), t.size());
+            st = put(&d.wo_t, t.data(), t.size());
         }
         // BF16 weight stream for the MFMA kernel: per tile of pairs the kernel
         // consumes chunks of 16 fragments; fragment (t, c) of a layer holds, for
@@ -315,24 +336,52 @@ swf_status Ctx::upload_scene(const swf_gaussians* g, const swf_mlp* mlp, int H, 
                             t[ch + (size_t)c * 512 + l * 8 + j] = f32_to_bf16_rne(w);
                         }
             }
-            st = upload(this, s, &d.bf_stream, t.data(), t.size());
+            st = put(&d.bf_stream, t.data(), t.size());
         }
         if (!st) {
             std::vector<uint16_t> z((size_t)n * 32, 0);
-            st = upload(this, s, &d.bf_mfeat, z.data(), z.size());
+            st = put(&d.bf_mfeat, z.data(), z.size());
             if (!st) {
                 compute_mean_features_bf16(d, nullptr);
                 st = hip(hipDeviceSynchronize(), "mean features");
             }
         }
     }
-    if (st) {
-        free_scene(s);
-        return st;
+    return st;
+}
+
+swf_status Ctx::update_scene(int id, const swf_gaussians* g, const swf_mlp* mlp, bool dev, hipStream_t st) {
+    Scene* s = scene(id);
+    if (!s) return fail(SWF_E_NOT_FOUND, "unknown scene id");
+    DevScene& d = s->d;
+    swf_status r = SWF_OK;
+    if (g) {
+        if (g->n != d.n) return fail(SWF_E_INVALID, "n differs from the uploaded scene");
+        const float* src[7] = {g->mean_x, g->mean_y, g->log_scale_x, g->log_scale_y, g->rotation, g->opacity_logit,
+                               g->amplitude};
+        float* dst[7] = {d.mx, d.my, d.lsx, d.lsy, d.rot, d.logit, d.amp};
+        const size_t bytes = (size_t)d.n * sizeof(float);
+        if ((r = ws_stage.reserve(this, 7 * bytes + 16, st))) return r;
+        for (int k = 0; k < 7; ++k) {
+            if (!src[k]) return fail(SWF_E_INVALID, "null parameter array");
+            float* tmp = (float*)((char*)ws_stage.ptr + k * bytes);
+            if ((r = hip(hipMemcpyAsync(tmp, src[k], bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st),
+                         "update copy")))
+                return r;
+        }
+        float* tmps[7];
+        for (int k = 0; k < 7; ++k) tmps[k] = (float*)((char*)ws_stage.ptr + k * bytes);
+        launch_gather_params(tmps, d.perm, d.n, dst, st);
+        if (d.has_mlp) compute_mean_features_bf16(d, st);
+        if ((r = hip(hipStreamSynchronize(st), "update sync"))) return r;
     }
-    const int sid = next_scene++;
-    scenes[sid] = s;
-    *id = sid;
+    if (mlp) {
+        if (!d.has_mlp) return fail(SWF_E_STATE, "scene was uploaded without an MLP");
+        if (mlp->n_hidden != d.n_hidden || mlp->hidden != d.hidden) return fail(SWF_E_INVALID, "MLP shape differs");
+        if ((r = hip(hipStreamSynchronize(st), "update sync"))) return r;
+        if ((r = pack_mlp(s, mlp, dev, false))) return r;
+    }
+    last.valid = false;
     return SWF_OK;
 }
 
@@ -531,6 +580,13 @@ swf_status swf_scene_upload(swf_ctx* h, const swf_gaussians* g, const swf_mlp* m
     Ctx* c = reinterpret_cast<Ctx*>(h);
     CTX_GUARD(c);
     return c->upload_scene(g, mlp, height, width, src_is_device != 0, scene_id);
+}
+
+swf_status swf_scene_update(swf_ctx* h, int32_t scene_id, const swf_gaussians* g, const swf_mlp* mlp,
+                            int32_t src_is_device, void* stream) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    return c->update_scene(scene_id, g, mlp, src_is_device != 0, (hipStream_t)stream);
 }
 
 swf_status swf_scene_release(swf_ctx* h, int32_t scene_id) {

@@ -57,11 +57,11 @@ struct Ctx {
     // workspace
     Buf ws_qs, ws_geo, ws_wm, ws_oa, ws_rect, ws_count, ws_off, ws_scan, ws_keys, ws_keys2, ws_vals, ws_vals2,
         ws_hist, ws_ranges, ws_delta, ws_sortk, ws_sortv, ws_grad, ws_dpair, ws_dbase, ws_dy, ws_act, ws_dz,
-        ws_part, ws_fmean, ws_ftx, ws_dmu, ws_ptrs;
+        ws_part, ws_fmean, ws_ftx, ws_dmu, ws_ptrs, ws_stage;
     std::vector<Buf*> all_bufs() {
         return {&ws_qs, &ws_geo, &ws_wm, &ws_oa, &ws_rect, &ws_count, &ws_off, &ws_scan, &ws_keys, &ws_keys2,
                 &ws_vals, &ws_vals2, &ws_hist, &ws_ranges, &ws_delta, &ws_sortk, &ws_sortv, &ws_grad, &ws_dpair,
-                &ws_dbase, &ws_dy, &ws_act, &ws_dz, &ws_part, &ws_fmean, &ws_ftx, &ws_dmu, &ws_ptrs};
+                &ws_dbase, &ws_dy, &ws_act, &ws_dz, &ws_part, &ws_fmean, &ws_ftx, &ws_dmu, &ws_ptrs, &ws_stage};
     }
     Records rec;
     uint64_t* total_dev = nullptr;   // device: scan total (and status word after it)
@@ -84,6 +84,8 @@ struct Ctx {
     Scene* scene(int id);
     swf_status upload_scene(const swf_gaussians* g, const swf_mlp* mlp, int H, int W, bool dev, int* id);
     swf_status release_scene(int id);
+    swf_status pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc);
+    swf_status update_scene(int id, const swf_gaussians* g, const swf_mlp* mlp, bool dev, hipStream_t st);
     swf_status enqueue_preprocess(Scene* sc, const float* tx, int B, int flags, const Grid& g, float* delta_sorted,
                                   hipStream_t st);
     swf_status forward_lists(int sid, const float* tx, int B, int flags, hipStream_t st);
