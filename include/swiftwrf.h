@@ -210,6 +210,60 @@ swf_status swf_radix_sort(swf_ctx *ctx, void *keys, uint32_t *values, int64_t n,
 swf_status swf_exclusive_scan(swf_ctx *ctx, const uint32_t *counts, uint32_t *offsets, uint64_t *total, int64_t n,
                               void *stream);
 
+/* ---- serving loop (continuous batching over resident scenes) --------------
+ * A scheduler thread owns n_slots execution slots (own stream + workspace);
+ * launches of different slots overlap on the device. Whenever a slot is free,
+ * the oldest waiting request's scene is served: up to max_batch of its waiting
+ * requests (FIFO) are rendered together, padded to a power-of-two bucket, by
+ * replaying the slot's captured hipGraph of the whole render (fixed key
+ * capacity = key_factor x calibrated keys per query x bucket, no host sync).
+ * A key overflow is detected from the status word and the batch is re-rendered
+ * with exact sizing (`fallback` in the stats). hbm_budget (bytes, 0 = none)
+ * bounds the sum of all slot workspaces: a batch that does not fit is shrunk,
+ * idle workspaces are released, or the requests wait; a single query that can
+ * never fit fails with SWF_E_OOM. Scenes must stay uploaded while served. */
+typedef struct {
+    int32_t max_batch;    /* largest batch per launch (default 64, <= 1024)    */
+    int32_t n_slots;      /* execution slots in flight (default 2, <= 16)      */
+    int32_t flags;        /* render flags: SWF_MLP_BF16 (default), ...          */
+    float key_factor;     /* key capacity headroom (default 1.5)               */
+    uint64_t hbm_budget;  /* workspace bytes over all slots, 0 = unlimited     */
+    int32_t use_graphs;   /* 1: replay captured graphs; 0: direct launches     */
+    int32_t reserved[5];
+} swf_serve_config;
+
+typedef struct {
+    double queue_us;      /* scheduled arrival -> launch                        */
+    double service_us;    /* launch -> result in the caller's buffer            */
+    double total_us;      /* scheduled arrival -> result in the caller's buffer */
+    int32_t batch;        /* requests in its launch                             */
+    int32_t bucket;       /* padded batch size of the launch                    */
+    int32_t fallback;     /* 1 if re-rendered after a key overflow              */
+    int32_t slot;         /* execution slot                                     */
+} swf_req_stats;
+
+/* Start the scheduler (cfg may be NULL for the defaults). */
+swf_status swf_serve_start(swf_ctx *ctx, const swf_serve_config *cfg);
+/* Queue one query: tx = 3 host floats, out_host = caller-owned host buffer of
+ * H*W floats that receives the spectrum (kept valid until the request is
+ * polled/waited). arrival_s = scheduled arrival on swf_serve_clock() (0: now).
+ * Thread-safe. SWF_E_NOT_FOUND for an unknown scene, SWF_E_INVALID for a
+ * non-finite tx. */
+swf_status swf_serve_submit(swf_ctx *ctx, int32_t scene_id, const float *tx, float *out_host, double arrival_s,
+                            uint64_t *ticket);
+/* SWF_OK (result delivered, stats filled, ticket retired), SWF_E_PENDING, or
+ * the request's error. Thread-safe. */
+swf_status swf_serve_poll(swf_ctx *ctx, uint64_t ticket, swf_req_stats *stats);
+/* As swf_serve_poll, blocking until the request is finished. */
+swf_status swf_serve_wait(swf_ctx *ctx, uint64_t ticket, swf_req_stats *stats);
+/* Finish in-flight launches and stop the scheduler. */
+swf_status swf_serve_stop(swf_ctx *ctx);
+/* counters[0..n): launches, completed requests, fallbacks, graph builds,
+ * budget shrinks, workspace bytes over all slots. */
+swf_status swf_serve_counters(swf_ctx *ctx, uint64_t *counters, int32_t n);
+/* The steady clock (seconds) that arrival times refer to. */
+double swf_serve_clock(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,21 @@ class _Grads(ctypes.Structure):
                                                              ("bias", ctypes.c_void_p * MAX_LAYERS)]
 
 
+class _ServeCfg(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("key_factor", ctypes.c_float), ("hbm_budget", ctypes.c_uint64), ("use_graphs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class _ReqStats(ctypes.Structure):
+    _fields_ = [("queue_us", ctypes.c_double), ("service_us", ctypes.c_double), ("total_us", ctypes.c_double),
+                ("batch", ctypes.c_int32), ("bucket", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("slot", ctypes.c_int32)]
+
+
+SERVE_COUNTERS = ("launches", "completed", "fallbacks", "graph_builds", "budget_shrinks", "workspace_bytes")
+PENDING = -7
+
 _lib = None
 
 
@@ -81,12 +96,20 @@ def lib():
             "swf_debug_keys": [P, P, P, P, P, P, P, ctypes.c_uint64],
             "swf_radix_sort": [P, P, P, I64, I32, I32, I32, P],
             "swf_exclusive_scan": [P, P, P, P, I64, P],
+            "swf_serve_start": [P, P],
+            "swf_serve_submit": [P, I32, P, P, ctypes.c_double, P],
+            "swf_serve_poll": [P, ctypes.c_uint64, P],
+            "swf_serve_wait": [P, ctypes.c_uint64, P],
+            "swf_serve_stop": [P],
+            "swf_serve_counters": [P, P, I32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = ctypes.c_int32
         L.swf_last_error.restype = ctypes.c_char_p
+        L.swf_serve_clock.argtypes = []
+        L.swf_serve_clock.restype = ctypes.c_double
         L.swf_status_string.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -121,6 +144,7 @@ class Context:
         self._h = h
         self._keep = {}
         self._rooms = {}
+        self._serve_out = {}
 
     def _check(self, st, ctx=True):
         if st != 0:
@@ -133,6 +157,7 @@ class Context:
         if getattr(self, "_h", None):
             self._L.swf_destroy(self._h)
             self._h = None
+            self._serve_out = {}
 
     def __del__(self):
         try:
@@ -288,3 +313,51 @@ class Context:
         tot = torch.zeros(1, device=self.device, dtype=torch.int64)
         self._check(self._L.swf_exclusive_scan(self._h, _ptr(counts), _ptr(off), _ptr(tot), counts.numel(), _stream()))
         return off, tot
+
+    # ---- serving ------------------------------------------------------------------
+    def serve_start(self, max_batch=64, n_slots=2, flags=MLP_BF16, key_factor=1.5, hbm_budget=0, use_graphs=True):
+        cfg = _ServeCfg(max_batch=max_batch, n_slots=n_slots, flags=flags, key_factor=key_factor,
+                        hbm_budget=hbm_budget, use_graphs=1 if use_graphs else 0)
+        self._check(self._L.swf_serve_start(self._h, ctypes.byref(cfg)))
+
+    def serve_submit(self, sid: int, tx, out: np.ndarray, arrival: float = 0.0) -> int:
+        """Queue one query; `out` (H x W float32, C-contiguous) receives the result."""
+        assert out.dtype == np.float32 and out.flags["C_CONTIGUOUS"]
+        t = (ctypes.c_float * 3)(*[float(v) for v in tx])
+        tk = ctypes.c_uint64()
+        st = self._L.swf_serve_submit(self._h, sid, t, out.ctypes.data_as(ctypes.c_void_p), float(arrival),
+                                      ctypes.byref(tk))
+        if st != 0:
+            raise SwfError(f"serve_submit status {st} ({self._L.swf_status_string(st).decode()})")
+        self._serve_out[tk.value] = out
+        return tk.value
+
+    def _stats(self, tk, st, rs):
+        self._serve_out.pop(tk, None)
+        if st != 0:
+            raise SwfError(f"request {tk} failed with status {st} ({self._L.swf_status_string(st).decode()})")
+        return {"queue_us": rs.queue_us, "service_us": rs.service_us, "total_us": rs.total_us, "batch": rs.batch,
+                "bucket": rs.bucket, "fallback": rs.fallback, "slot": rs.slot}
+
+    def serve_poll(self, ticket: int):
+        rs = _ReqStats()
+        st = self._L.swf_serve_poll(self._h, ticket, ctypes.byref(rs))
+        if st == PENDING:
+            return None
+        return self._stats(ticket, st, rs)
+
+    def serve_wait(self, ticket: int):
+        rs = _ReqStats()
+        st = self._L.swf_serve_wait(self._h, ticket, ctypes.byref(rs))
+        return self._stats(ticket, st, rs)
+
+    def serve_stop(self):
+        self._check(self._L.swf_serve_stop(self._h))
+
+    def serve_counters(self):
+        v = (ctypes.c_uint64 * len(SERVE_COUNTERS))()
+        self._check(self._L.swf_serve_counters(self._h, v, len(SERVE_COUNTERS)))
+        return dict(zip(SERVE_COUNTERS, list(v)))
+
+    def clock(self) -> float:
+        return self._L.swf_serve_clock()

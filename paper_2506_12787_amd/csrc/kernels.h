@@ -68,10 +68,14 @@ void launch_emit_keys(const Records& r, const uint32_t* offsets, const uint32_t*
 size_t radix_scratch_bytes(int64_t n);
 // Sorts (keys, vals) on bits [begin_bit, end_bit); returns 1 if the result
 // ended in the alternate buffers (kalt, valt), 0 if in (keys, vals).
+// n_dev (optional): key count on the device; then n is the capacity and the
+// kernels use min(*n_dev, n) (no host synchronisation, graph-capturable).
 int launch_radix_sort(void* keys, uint32_t* vals, void* kalt, uint32_t* valt, int64_t n, int key_bytes,
-                      int begin_bit, int end_bit, void* scratch, hipStream_t st);
+                      int begin_bit, int end_bit, void* scratch, hipStream_t st, const uint64_t* n_dev = nullptr);
 void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gtiles, uint2* ranges,
-                        hipStream_t st);
+                        hipStream_t st, const uint64_t* n_dev = nullptr);
+void launch_clear_u32(uint32_t* p, int n, hipStream_t st);
+void launch_effective_count(const uint64_t* total, uint64_t cap, uint64_t* n_eff, hipStream_t st);
 
 // backward.hip
 void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,

@@ -55,10 +55,10 @@ extern "C" swf_status swf_l1_loss(swf_ctx* h, const float* pred, const float* ta
     hipSetDevice(c->device);
     if (n < 1 || !pred || !target || !loss) return c->fail(SWF_E_INVALID, "bad loss arguments");
     hipStream_t st = (hipStream_t)stream;
-    swf_status s = c->ws_grad.reserve(c, kLossBlocks * sizeof(double), st);
+    swf_status s = c->ws.grad.reserve(c, kLossBlocks * sizeof(double), st);
     if (s) return s;
     const int blocks = (int)std::min<int64_t>(kLossBlocks, (n + 255) / 256);
-    l1_partial_kernel<<<blocks, 256, 0, st>>>(pred, target, n, (float)(1.0 / (double)n), grad, (double*)c->ws_grad.ptr);
-    l1_final_kernel<<<1, 256, 0, st>>>((const double*)c->ws_grad.ptr, blocks, 1.0 / (double)n, loss);
+    l1_partial_kernel<<<blocks, 256, 0, st>>>(pred, target, n, (float)(1.0 / (double)n), grad, (double*)c->ws.grad.ptr);
+    l1_final_kernel<<<1, 256, 0, st>>>((const double*)c->ws.grad.ptr, blocks, 1.0 / (double)n, loss);
     return c->hip(hipGetLastError(), "l1 loss");
 }

@@ -62,7 +62,23 @@ swf_status Buf::reserve(Ctx* c, size_t n, hipStream_t st) {
         return c->hip(e, "hipMalloc(workspace)");
     }
     cap = want;
+    ++gen;
     return SWF_OK;
+}
+
+swf_status Workspace::init(Ctx* c) {
+    if (hipMalloc(&total_dev, 64) != hipSuccess) return c->fail(SWF_E_OOM, "hipMalloc(status)");
+    if (hipHostMalloc(&total_host, 64, 0) != hipSuccess) return c->fail(SWF_E_OOM, "hipHostMalloc(status)");
+    status_dev = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(total_dev) + 16);
+    return c->hip(hipMemset(total_dev, 0, 64), "hipMemset(status)");
+}
+
+void Workspace::release() {
+    for (Buf* b : bufs()) b->release();
+    if (total_dev) hipFree(total_dev);
+    if (total_host) hipHostFree(total_host);
+    total_dev = nullptr;
+    total_host = nullptr;
 }
 
 void Buf::release() {
@@ -89,7 +105,7 @@ Grid make_grid(int H, int W, int tile) {
 }
 
 void Ctx::stage_begin(int stage, hipStream_t st) {
-    if (!timing) return;
+    if (!timing || serve_timing_disabled()) return;
     TimedStage t;
     t.stage = stage;
     if (!event_pool.empty()) {
@@ -109,7 +125,7 @@ void Ctx::stage_begin(int stage, hipStream_t st) {
 }
 
 void Ctx::stage_end(hipStream_t st) {
-    if (!timing || pending.empty()) return;
+    if (!timing || serve_timing_disabled() || pending.empty()) return;
     hipEventRecord(pending.back().b, st);
     if (pending.size() > 8192) resolve_timing();
 }
@@ -361,16 +377,16 @@ swf_status Ctx::update_scene(int id, const swf_gaussians* g, const swf_mlp* mlp,
                                g->amplitude};
         float* dst[7] = {d.mx, d.my, d.lsx, d.lsy, d.rot, d.logit, d.amp};
         const size_t bytes = (size_t)d.n * sizeof(float);
-        if ((r = ws_stage.reserve(this, 7 * bytes + 16, st))) return r;
+        if ((r = ws.stage.reserve(this, 7 * bytes + 16, st))) return r;
         for (int k = 0; k < 7; ++k) {
             if (!src[k]) return fail(SWF_E_INVALID, "null parameter array");
-            float* tmp = (float*)((char*)ws_stage.ptr + k * bytes);
+            float* tmp = (float*)((char*)ws.stage.ptr + k * bytes);
             if ((r = hip(hipMemcpyAsync(tmp, src[k], bytes, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st),
                          "update copy")))
                 return r;
         }
         float* tmps[7];
-        for (int k = 0; k < 7; ++k) tmps[k] = (float*)((char*)ws_stage.ptr + k * bytes);
+        for (int k = 0; k < 7; ++k) tmps[k] = (float*)((char*)ws.stage.ptr + k * bytes);
         launch_gather_params(tmps, d.perm, d.n, dst, st);
         if (d.has_mlp) compute_mean_features_bf16(d, st);
         if ((r = hip(hipStreamSynchronize(st), "update sync"))) return r;
@@ -381,7 +397,7 @@ swf_status Ctx::update_scene(int id, const swf_gaussians* g, const swf_mlp* mlp,
         if ((r = hip(hipStreamSynchronize(st), "update sync"))) return r;
         if ((r = pack_mlp(s, mlp, dev, false))) return r;
     }
-    last.valid = false;
+    ws.last.valid = false;
     return SWF_OK;
 }
 
@@ -395,7 +411,7 @@ swf_status Ctx::release_scene(int id) {
 }
 
 // Enqueue preprocess (+ MLP) for B queries into the workspace records.
-swf_status Ctx::enqueue_preprocess(Scene* sc, const float* tx, int B, int flags, const Grid& g, float* delta_sorted,
+swf_status Ctx::enqueue_preprocess(Workspace& w, Scene* sc, const float* tx, int B, int flags, const Grid& g, float* delta_sorted,
                                    hipStream_t st) {
     const DevScene& d = sc->d;
     const bool deform = !(flags & SWF_NO_DEFORM);
@@ -403,33 +419,33 @@ swf_status Ctx::enqueue_preprocess(Scene* sc, const float* tx, int B, int flags,
         return fail(SWF_E_STATE, "BF16 MLP kernel is not available in this build");
     const size_t pairs = (size_t)B * d.n;
     swf_status s = SWF_OK;
-    if ((s = ws_geo.reserve(this, pairs * sizeof(float4), st))) return s;
-    if ((s = ws_wm.reserve(this, pairs * sizeof(float4), st))) return s;
-    if ((s = ws_oa.reserve(this, pairs * sizeof(float2), st))) return s;
-    if ((s = ws_rect.reserve(this, pairs * sizeof(uint2), st))) return s;
-    if ((s = ws_count.reserve(this, pairs * sizeof(uint32_t), st))) return s;
-    rec.geo = (float4*)ws_geo.ptr;
-    rec.wm = (float4*)ws_wm.ptr;
-    rec.oa = (float2*)ws_oa.ptr;
-    rec.rect = (uint2*)ws_rect.ptr;
-    rec.count = (uint32_t*)ws_count.ptr;
+    if ((s = w.geo.reserve(this, pairs * sizeof(float4), st))) return s;
+    if ((s = w.wm.reserve(this, pairs * sizeof(float4), st))) return s;
+    if ((s = w.oa.reserve(this, pairs * sizeof(float2), st))) return s;
+    if ((s = w.rect.reserve(this, pairs * sizeof(uint2), st))) return s;
+    if ((s = w.count.reserve(this, pairs * sizeof(uint32_t), st))) return s;
+    w.rec.geo = (float4*)w.geo.ptr;
+    w.rec.wm = (float4*)w.wm.ptr;
+    w.rec.oa = (float2*)w.oa.ptr;
+    w.rec.rect = (uint2*)w.rect.ptr;
+    w.rec.count = (uint32_t*)w.count.ptr;
     if (deform) {
         if (!d.has_mlp) return fail(SWF_E_INVALID, "scene has no deformation MLP (use SWF_NO_DEFORM)");
         if (!tx) return fail(SWF_E_INVALID, "tx is NULL");
-        if ((s = ws_qs.reserve(this, (size_t)B * d.hidden * sizeof(float), st))) return s;
+        if ((s = w.qs.reserve(this, (size_t)B * d.hidden * sizeof(float), st))) return s;
         stage_begin(SWF_STAGE_TX, st);
-        launch_tx_features(d, tx, B, (float*)ws_qs.ptr, st);
+        launch_tx_features(d, tx, B, (float*)w.qs.ptr, st);
         stage_end(st);
         stage_begin(SWF_STAGE_MLP, st);
         if (flags & SWF_MLP_BF16)
-            launch_mlp_bf16(d, (const float*)ws_qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, rec, delta_sorted, st,
+            launch_mlp_bf16(d, (const float*)w.qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, w.rec, delta_sorted, st,
                             mlp_pairs_per_wave);
         else
-            launch_mlp_fp32(d, (const float*)ws_qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, rec, delta_sorted, st);
+            launch_mlp_fp32(d, (const float*)w.qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, w.rec, delta_sorted, st);
         stage_end(st);
     } else {
         stage_begin(SWF_STAGE_MLP, st);
-        launch_preprocess_static(d, B, g, rec, st);
+        launch_preprocess_static(d, B, g, w.rec, st);
         stage_end(st);
     }
     return hip(hipGetLastError(), "preprocess launch");
@@ -437,7 +453,8 @@ swf_status Ctx::enqueue_preprocess(Scene* sc, const float* tx, int B, int flags,
 
 // Forward up to the per-tile lists: preprocess (+ MLP), scan, keys, sort,
 // tile ranges. Records the result in `last`.
-swf_status Ctx::forward_lists(int sid, const float* tx, int B, int flags, hipStream_t st) {
+swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int flags, hipStream_t st,
+                              uint64_t key_cap) {
     Scene* sc = scene(sid);
     if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
     if (B < 1) return fail(SWF_E_INVALID, "batch must be >= 1");
@@ -445,61 +462,72 @@ swf_status Ctx::forward_lists(int sid, const float* tx, int B, int flags, hipStr
     if ((uint64_t)B * (uint64_t)d.n >= (1ull << 32)) return fail(SWF_E_INVALID, "batch * n must be < 2^32");
     const Grid g = make_grid(d.H, d.W, (flags & SWF_TILE8) ? 8 : 16);
     if ((uint64_t)B * g.tiles >= (1ull << 31)) return fail(SWF_E_INVALID, "batch * tiles too large");
-    last.valid = false;
-    swf_status s = enqueue_preprocess(sc, tx, B, flags, g, nullptr, st);
+    w.last.valid = false;
+    swf_status s = enqueue_preprocess(w, sc, tx, B, flags, g, nullptr, st);
     if (s) return s;
     const int64_t pairs = (int64_t)B * d.n;
-    if ((s = ws_off.reserve(this, (size_t)pairs * sizeof(uint32_t) + 16, st))) return s;
-    if ((s = ws_scan.reserve(this, scan_scratch_bytes(pairs) + 64, st))) return s;
+    if ((s = w.off.reserve(this, (size_t)pairs * sizeof(uint32_t) + 16, st))) return s;
+    if ((s = w.scan.reserve(this, scan_scratch_bytes(pairs) + 64, st))) return s;
     stage_begin(SWF_STAGE_SCAN, st);
-    launch_exclusive_scan(rec.count, (uint32_t*)ws_off.ptr, total_dev, pairs, ws_scan.ptr, st);
+    launch_exclusive_scan(w.rec.count, (uint32_t*)w.off.ptr, w.total_dev, pairs, w.scan.ptr, st);
     stage_end(st);
-    if ((s = hip(hipMemcpyAsync(total_host, total_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, st), "total D2H")))
-        return s;
-    if ((s = hip(hipStreamSynchronize(st), "stream sync"))) return s;
-    const uint64_t nk = *total_host;
+    uint64_t nk = key_cap;
+    const uint64_t* n_dev = nullptr;
+    if (key_cap == 0) {
+        if ((s = hip(hipMemcpyAsync(w.total_host, w.total_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, st),
+                     "total D2H")))
+            return s;
+        if ((s = hip(hipStreamSynchronize(st), "stream sync"))) return s;
+        nk = *w.total_host;
+    } else {
+        launch_clear_u32(w.status_dev, 1, st);
+        uint64_t* n_eff = w.total_dev + 1;  // the word after the scan total
+        launch_effective_count(w.total_dev, key_cap, n_eff, st);
+        n_dev = n_eff;
+    }
     if (nk >= (1ull << 32)) return fail(SWF_E_OVERFLOW, "more than 2^32 - 1 keys; render a smaller batch");
     const bool full = (flags & SWF_FULL_SORT) != 0;
     const size_t kb = full ? 8 : 4;
-    if ((s = ws_keys.reserve(this, nk * kb + 16, st))) return s;
-    if ((s = ws_keys2.reserve(this, nk * kb + 16, st))) return s;
-    if ((s = ws_vals.reserve(this, nk * 4 + 16, st))) return s;
-    if ((s = ws_vals2.reserve(this, nk * 4 + 16, st))) return s;
-    if ((s = ws_hist.reserve(this, radix_scratch_bytes((int64_t)nk) + 64, st))) return s;
+    if ((s = w.keys.reserve(this, nk * kb + 16, st))) return s;
+    if ((s = w.keys2.reserve(this, nk * kb + 16, st))) return s;
+    if ((s = w.vals.reserve(this, nk * 4 + 16, st))) return s;
+    if ((s = w.vals2.reserve(this, nk * 4 + 16, st))) return s;
+    if ((s = w.hist.reserve(this, radix_scratch_bytes((int64_t)nk) + 64, st))) return s;
     const int64_t n_gt = (int64_t)B * g.tiles;
-    if ((s = ws_ranges.reserve(this, (size_t)n_gt * sizeof(uint2), st))) return s;
+    if ((s = w.ranges.reserve(this, (size_t)n_gt * sizeof(uint2), st))) return s;
     stage_begin(SWF_STAGE_EMIT, st);
-    launch_emit_keys(rec, (const uint32_t*)ws_off.ptr, d.dbits, B, d.n, g, nk, full, ws_keys.ptr,
-                     (uint32_t*)ws_vals.ptr, status_dev, st);
+    launch_emit_keys(w.rec, (const uint32_t*)w.off.ptr, d.dbits, B, d.n, g, nk, full, w.keys.ptr,
+                     (uint32_t*)w.vals.ptr, w.status_dev, st);
     stage_end(st);
     const int tbits = bits_for((uint64_t)n_gt);
     stage_begin(SWF_STAGE_SORT, st);
-    const int flip = launch_radix_sort(ws_keys.ptr, (uint32_t*)ws_vals.ptr, ws_keys2.ptr, (uint32_t*)ws_vals2.ptr,
-                                       (int64_t)nk, (int)kb, 0, full ? 32 + tbits : tbits, ws_hist.ptr, st);
+    const int flip = launch_radix_sort(w.keys.ptr, (uint32_t*)w.vals.ptr, w.keys2.ptr, (uint32_t*)w.vals2.ptr,
+                                       (int64_t)nk, (int)kb, 0, full ? 32 + tbits : tbits, w.hist.ptr, st, n_dev);
     stage_end(st);
-    void* skeys = flip ? ws_keys2.ptr : ws_keys.ptr;
-    uint32_t* svals = (uint32_t*)(flip ? ws_vals2.ptr : ws_vals.ptr);
+    void* skeys = flip ? w.keys2.ptr : w.keys.ptr;
+    uint32_t* svals = (uint32_t*)(flip ? w.vals2.ptr : w.vals.ptr);
     stage_begin(SWF_STAGE_RANGES, st);
-    launch_tile_ranges(skeys, (int)kb, (int64_t)nk, n_gt, (uint2*)ws_ranges.ptr, st);
+    launch_tile_ranges(skeys, (int)kb, (int64_t)nk, n_gt, (uint2*)w.ranges.ptr, st, n_dev);
     stage_end(st);
-    last.valid = true;
-    last.scene = sid;
-    last.B = B;
-    last.N = d.n;
-    last.flags = flags;
-    last.grid = g;
-    last.n_keys = nk;
-    last.full = full;
-    last.keys = skeys;
-    last.vals = svals;
+    w.last.valid = true;
+    w.last.scene = sid;
+    w.last.B = B;
+    w.last.N = d.n;
+    w.last.flags = flags;
+    w.last.grid = g;
+    w.last.n_keys = nk;
+    w.last.full = full;
+    w.last.keys = skeys;
+    w.last.vals = svals;
     return hip(hipGetLastError(), "forward launch");
 }
 
-swf_status Ctx::render(int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st) {
+swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux,
+                       hipStream_t st, uint64_t key_cap) {
     if (!out) return fail(SWF_E_INVALID, "out is NULL");
     if ((flags & SWF_KEEP_AUX) && !aux) return fail(SWF_E_INVALID, "SWF_KEEP_AUX needs aux");
     hipSetDevice(device);
-    swf_status s = forward_lists(sid, tx, B, flags, st);
+    swf_status s = forward_lists(w, sid, tx, B, flags, st, key_cap);
     if (s) return s;
     const DevScene& d = scene(sid)->d;
     float* auxT = nullptr;
@@ -509,7 +537,7 @@ swf_status Ctx::render(int sid, const float* tx, int B, int flags, float* out, v
         auxL = (uint32_t*)((char*)aux + sizeof(float) * (size_t)B * d.H * d.W);
     }
     stage_begin(SWF_STAGE_BLEND, st);
-    launch_blend_forward((const uint2*)ws_ranges.ptr, last.vals, rec, B, last.grid, out, auxT, auxL, st);
+    launch_blend_forward((const uint2*)w.ranges.ptr, w.last.vals, w.rec, B, w.last.grid, out, auxT, auxL, st);
     stage_end(st);
     return hip(hipGetLastError(), "render launch");
 }
@@ -540,12 +568,11 @@ swf_status swf_create(swf_ctx** out, const swf_config* cfg) {
     if (!c) return SWF_E_OOM;
     c->device = dev;
     c->mlp_pairs_per_wave = cfg ? cfg->mlp_pairs_per_wave : 0;
-    if (hipMalloc(&c->total_dev, 64) != hipSuccess || hipHostMalloc(&c->total_host, 64, 0) != hipSuccess) {
+    if (c->ws.init(c) != SWF_OK) {
+        c->ws.release();
         delete c;
         return SWF_E_OOM;
     }
-    c->status_dev = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(c->total_dev) + 16);
-    hipMemset(c->total_dev, 0, 64);
     *out = reinterpret_cast<swf_ctx*>(c);
     return SWF_OK;
 }
@@ -561,11 +588,9 @@ swf_status swf_destroy(swf_ctx* h) {
         delete kv.second;
     }
     c->scenes.clear();
-    for (Buf* b : c->all_bufs()) b->release();
+    c->ws.release();
     c->resolve_timing();
     for (auto e : c->event_pool) hipEventDestroy(e);
-    hipFree(c->total_dev);
-    hipHostFree(c->total_host);
     delete c;
     return SWF_OK;
 }
@@ -609,7 +634,7 @@ swf_status swf_render(swf_ctx* h, int32_t scene_id, const float* tx, int32_t bat
                       void* aux, void* stream) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     CTX_GUARD(c);
-    return c->render(scene_id, tx, batch, flags, out, aux, (hipStream_t)stream);
+    return c->render(c->ws, scene_id, tx, batch, flags, out, aux, (hipStream_t)stream);
 }
 
 swf_status swf_stage_timing(swf_ctx* h, int32_t enable) {
@@ -647,13 +672,13 @@ swf_status swf_debug_deform(swf_ctx* h, int32_t scene_id, const float* tx, int32
     hipStream_t st = (hipStream_t)stream;
     const DevScene& d = sc->d;
     const size_t cnt = (size_t)batch * d.n * kOut;
-    swf_status s = c->ws_delta.reserve(c, cnt * sizeof(float) + 16, st);
+    swf_status s = c->ws.delta.reserve(c, cnt * sizeof(float) + 16, st);
     if (s) return s;
     const Grid g = make_grid(d.H, d.W, (flags & SWF_TILE8) ? 8 : 16);
-    s = c->enqueue_preprocess(sc, tx, batch, flags, g, (float*)c->ws_delta.ptr, st);
+    s = c->enqueue_preprocess(c->ws, sc, tx, batch, flags, g, (float*)c->ws.delta.ptr, st);
     if (s) return s;
-    launch_permute_delta((const float*)c->ws_delta.ptr, d.perm, batch, d.n, delta, st);
-    c->last.valid = false;
+    launch_permute_delta((const float*)c->ws.delta.ptr, d.perm, batch, d.n, delta, st);
+    c->ws.last.valid = false;
     return c->hip(hipGetLastError(), "debug deform");
 }
 
@@ -661,17 +686,17 @@ swf_status swf_debug_keys(swf_ctx* h, uint32_t* counts, uint32_t* offsets, uint6
                           uint32_t* ranges, uint64_t* n_keys, uint64_t capacity) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     CTX_GUARD(c);
-    if (!c->last.valid) return c->fail(SWF_E_STATE, "no render to inspect");
-    Scene* sc = c->scene(c->last.scene);
+    if (!c->ws.last.valid) return c->fail(SWF_E_STATE, "no render to inspect");
+    Scene* sc = c->scene(c->ws.last.scene);
     if (!sc) return c->fail(SWF_E_STATE, "scene of the last render was released");
     hipDeviceSynchronize();
-    const auto& L = c->last;
+    const auto& L = c->ws.last;
     const size_t pairs = (size_t)L.B * L.N;
     if (n_keys) *n_keys = L.n_keys;
     swf_status s = SWF_OK;
-    if (counts && (s = c->hip(hipMemcpy(counts, c->rec.count, pairs * 4, hipMemcpyDeviceToHost), "D2H counts")))
+    if (counts && (s = c->hip(hipMemcpy(counts, c->ws.rec.count, pairs * 4, hipMemcpyDeviceToHost), "D2H counts")))
         return s;
-    if (offsets && (s = c->hip(hipMemcpy(offsets, c->ws_off.ptr, pairs * 4, hipMemcpyDeviceToHost), "D2H offsets")))
+    if (offsets && (s = c->hip(hipMemcpy(offsets, c->ws.off.ptr, pairs * 4, hipMemcpyDeviceToHost), "D2H offsets")))
         return s;
     if ((keys || values) && L.n_keys > capacity) return c->fail(SWF_E_OVERFLOW, "capacity below key count");
     if (keys || values) {
@@ -696,7 +721,7 @@ swf_status swf_debug_keys(swf_ctx* h, uint32_t* counts, uint32_t* offsets, uint6
     }
     if (ranges) {
         const size_t m = (size_t)L.B * L.grid.tiles;
-        if ((s = c->hip(hipMemcpy(ranges, c->ws_ranges.ptr, m * 8, hipMemcpyDeviceToHost), "D2H ranges"))) return s;
+        if ((s = c->hip(hipMemcpy(ranges, c->ws.ranges.ptr, m * 8, hipMemcpyDeviceToHost), "D2H ranges"))) return s;
     }
     return SWF_OK;
 }
@@ -712,15 +737,15 @@ swf_status swf_radix_sort(swf_ctx* h, void* keys, uint32_t* values, int64_t n, i
     if (n >= (1ll << 32)) return c->fail(SWF_E_INVALID, "n must be < 2^32");
     hipStream_t st = (hipStream_t)stream;
     swf_status s = SWF_OK;
-    if ((s = c->ws_sortk.reserve(c, (size_t)n * key_bytes + 16, st))) return s;
-    if ((s = c->ws_sortv.reserve(c, (size_t)n * 4 + 16, st))) return s;
-    if ((s = c->ws_hist.reserve(c, radix_scratch_bytes(n) + 64, st))) return s;
-    c->last.valid = false;
-    const int flip = launch_radix_sort(keys, values, c->ws_sortk.ptr, (uint32_t*)c->ws_sortv.ptr, n, key_bytes,
-                                       begin_bit, end_bit, c->ws_hist.ptr, st);
+    if ((s = c->ws.sortk.reserve(c, (size_t)n * key_bytes + 16, st))) return s;
+    if ((s = c->ws.sortv.reserve(c, (size_t)n * 4 + 16, st))) return s;
+    if ((s = c->ws.hist.reserve(c, radix_scratch_bytes(n) + 64, st))) return s;
+    c->ws.last.valid = false;
+    const int flip = launch_radix_sort(keys, values, c->ws.sortk.ptr, (uint32_t*)c->ws.sortv.ptr, n, key_bytes,
+                                       begin_bit, end_bit, c->ws.hist.ptr, st);
     if (flip) {
-        hipMemcpyAsync(keys, c->ws_sortk.ptr, (size_t)n * key_bytes, hipMemcpyDeviceToDevice, st);
-        hipMemcpyAsync(values, c->ws_sortv.ptr, (size_t)n * 4, hipMemcpyDeviceToDevice, st);
+        hipMemcpyAsync(keys, c->ws.sortk.ptr, (size_t)n * key_bytes, hipMemcpyDeviceToDevice, st);
+        hipMemcpyAsync(values, c->ws.sortv.ptr, (size_t)n * 4, hipMemcpyDeviceToDevice, st);
     }
     return c->hip(hipGetLastError(), "radix sort");
 }
@@ -731,9 +756,9 @@ swf_status swf_exclusive_scan(swf_ctx* h, const uint32_t* counts, uint32_t* offs
     CTX_GUARD(c);
     if (n < 0 || !total || (n > 0 && (!counts || !offsets))) return c->fail(SWF_E_INVALID, "bad arguments");
     hipStream_t st = (hipStream_t)stream;
-    swf_status s = c->ws_scan.reserve(c, scan_scratch_bytes(n) + 64, st);
+    swf_status s = c->ws.scan.reserve(c, scan_scratch_bytes(n) + 64, st);
     if (s) return s;
-    launch_exclusive_scan(counts, offsets, total, n, c->ws_scan.ptr, st);
+    launch_exclusive_scan(counts, offsets, total, n, c->ws.scan.ptr, st);
     return c->hip(hipGetLastError(), "scan");
 }
 

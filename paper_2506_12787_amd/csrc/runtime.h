@@ -15,10 +15,12 @@ namespace swf {
 
 struct Ctx;
 
-// Grow-only device buffer.
+// Grow-only device buffer. `gen` counts reallocations (captured graphs that
+// hold the old address must be rebuilt).
 struct Buf {
     void* ptr = nullptr;
     size_t cap = 0;
+    uint32_t gen = 0;
     swf_status reserve(Ctx* c, size_t bytes, hipStream_t st);
     void release();
 };
@@ -45,6 +47,29 @@ struct LastRender {
     uint32_t* vals = nullptr;
 };
 
+// Scratch memory of one render stream: every pipeline stage writes here.
+struct Workspace {
+    Buf qs, geo, wm, oa, rect, count, off, scan, keys, keys2, vals, vals2, hist, ranges, delta, sortk, sortv, grad,
+        dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, ptrs, stage;
+    Records rec;
+    uint64_t* total_dev = nullptr;   // device: scan total, then the status word
+    uint32_t* status_dev = nullptr;
+    uint64_t* total_host = nullptr;  // pinned
+    LastRender last;
+    std::vector<Buf*> bufs() {
+        return {&qs, &geo, &wm, &oa, &rect, &count, &off, &scan, &keys, &keys2, &vals, &vals2, &hist, &ranges,
+                &delta, &sortk, &sortv, &grad, &dpair, &dbase, &dy, &act, &dz, &part, &fmean, &ftx, &dmu, &ptrs,
+                &stage};
+    }
+    uint64_t generation() {
+        uint64_t g = 0;
+        for (Buf* b : bufs()) g += b->gen;
+        return g;
+    }
+    swf_status init(Ctx* c);
+    void release();
+};
+
 struct ServeState;
 
 struct Ctx {
@@ -54,20 +79,7 @@ struct Ctx {
     std::map<int, Scene*> scenes;
     int next_scene = 1;
 
-    // workspace
-    Buf ws_qs, ws_geo, ws_wm, ws_oa, ws_rect, ws_count, ws_off, ws_scan, ws_keys, ws_keys2, ws_vals, ws_vals2,
-        ws_hist, ws_ranges, ws_delta, ws_sortk, ws_sortv, ws_grad, ws_dpair, ws_dbase, ws_dy, ws_act, ws_dz,
-        ws_part, ws_fmean, ws_ftx, ws_dmu, ws_ptrs, ws_stage;
-    std::vector<Buf*> all_bufs() {
-        return {&ws_qs, &ws_geo, &ws_wm, &ws_oa, &ws_rect, &ws_count, &ws_off, &ws_scan, &ws_keys, &ws_keys2,
-                &ws_vals, &ws_vals2, &ws_hist, &ws_ranges, &ws_delta, &ws_sortk, &ws_sortv, &ws_grad, &ws_dpair,
-                &ws_dbase, &ws_dy, &ws_act, &ws_dz, &ws_part, &ws_fmean, &ws_ftx, &ws_dmu, &ws_ptrs, &ws_stage};
-    }
-    Records rec;
-    uint64_t* total_dev = nullptr;   // device: scan total (and status word after it)
-    uint32_t* status_dev = nullptr;
-    uint64_t* total_host = nullptr;  // pinned
-    LastRender last;
+    Workspace ws;  // scratch of the direct (non-serving) entry points
 
     // stage timing
     bool timing = false;
@@ -86,12 +98,17 @@ struct Ctx {
     swf_status release_scene(int id);
     swf_status pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc);
     swf_status update_scene(int id, const swf_gaussians* g, const swf_mlp* mlp, bool dev, hipStream_t st);
-    swf_status enqueue_preprocess(Scene* sc, const float* tx, int B, int flags, const Grid& g, float* delta_sorted,
-                                  hipStream_t st);
-    swf_status forward_lists(int sid, const float* tx, int B, int flags, hipStream_t st);
-    swf_status render(int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st);
-    swf_status backward(int sid, const float* tx, int B, int flags, const float* grad_out, const void* aux,
-                        const swf_grads* grads, hipStream_t st);
+    swf_status enqueue_preprocess(Workspace& w, Scene* sc, const float* tx, int B, int flags, const Grid& g,
+                                  float* delta_sorted, hipStream_t st);
+    // key_cap == 0: size the key buffers from the scan total (one 8-byte
+    // device-to-host read and a stream wait). key_cap > 0: fixed capacity, no
+    // host synchronisation (graph-capturable); overflow sets the status word.
+    swf_status forward_lists(Workspace& w, int sid, const float* tx, int B, int flags, hipStream_t st,
+                             uint64_t key_cap = 0);
+    swf_status render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st,
+                      uint64_t key_cap = 0);
+    swf_status backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out,
+                        const void* aux, const swf_grads* grads, hipStream_t st);
     void stage_begin(int stage, hipStream_t st);
     void stage_end(hipStream_t st);
     void resolve_timing();
@@ -100,5 +117,6 @@ struct Ctx {
 Grid make_grid(int H, int W, int tile);
 const char* status_name(swf_status s);
 void serve_shutdown(Ctx* c);
+bool serve_timing_disabled();  // true on the serving scheduler thread
 
 }  // namespace swf

@@ -156,10 +156,23 @@ __global__ __launch_bounds__(kThreads) void emit_keys_kernel(const uint2* __rest
 }
 
 // ---- radix sort ---------------------------------------------------------------
+// Key count and per-block chunk: from the host, or (n_dev != nullptr) read on
+// the device as min(*n_dev, n) so that a captured graph needs no host sync.
+__device__ __forceinline__ void sort_extent(const uint64_t* n_dev, int64_t& n, int64_t& chunk, int G) {
+    if (n_dev) {
+        const uint64_t d = *n_dev;
+        n = (int64_t)(d < (uint64_t)n ? d : (uint64_t)n);
+        chunk = (n + G - 1) / G;
+        chunk = ((chunk + kTile - 1) / kTile) * kTile;
+    }
+}
+
 template <typename K>
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const K* __restrict__ keys, int64_t n, int shift,
-                                                              int64_t chunk, uint32_t* __restrict__ hist, int G) {
+                                                              int64_t chunk, uint32_t* __restrict__ hist, int G,
+                                                              const uint64_t* __restrict__ n_dev) {
     __shared__ uint32_t h[kWaves][256];
+    sort_extent(n_dev, n, chunk, G);
     for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0;
     __syncthreads();
     const int w = threadIdx.x >> 6;
@@ -202,7 +215,9 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const K* __rest
                                                                  K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                                  int64_t n, int shift, int64_t chunk,
                                                                  const uint32_t* __restrict__ hist, int G,
-                                                                 const uint32_t* __restrict__ dtot) {
+                                                                 const uint32_t* __restrict__ dtot,
+                                                                 const uint64_t* __restrict__ n_dev) {
+    sort_extent(n_dev, n, chunk, G);
     __shared__ uint32_t wcnt[kWaves][256];
     __shared__ uint32_t base[256];
     __shared__ uint32_t ttot[256];
@@ -281,7 +296,12 @@ __global__ void zero_ranges_kernel(uint2* __restrict__ r, int64_t m) {
 }
 
 template <bool kFull>
-__global__ void tile_ranges_kernel(const void* __restrict__ keys, int64_t n, uint2* __restrict__ r) {
+__global__ void tile_ranges_kernel(const void* __restrict__ keys, int64_t n, uint2* __restrict__ r,
+                                   const uint64_t* __restrict__ n_dev) {
+    if (n_dev) {
+        const uint64_t d = *n_dev;
+        n = (int64_t)(d < (uint64_t)n ? d : (uint64_t)n);
+    }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     auto tile_of = [&](int64_t j) -> uint32_t {
@@ -300,7 +320,7 @@ int radix_grid(int64_t n) {
 
 template <typename K>
 int radix_sort_t(K* keys, uint32_t* vals, K* kalt, uint32_t* valt, int64_t n, int begin_bit, int end_bit,
-                 uint32_t* hist, hipStream_t st) {
+                 uint32_t* hist, hipStream_t st, const uint64_t* n_dev) {
     if (n <= 1 || end_bit <= begin_bit) return 0;
     const int G = radix_grid(n);
     uint32_t* dtot = hist + (size_t)256 * G;
@@ -312,9 +332,9 @@ int radix_sort_t(K* keys, uint32_t* vals, K* kalt, uint32_t* valt, int64_t n, in
     uint32_t* vo = valt;
     int flips = 0;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        radix_hist_kernel<K><<<G, kThreads, 0, st>>>(ki, n, shift, chunk, hist, G);
+        radix_hist_kernel<K><<<G, kThreads, 0, st>>>(ki, n, shift, chunk, hist, G, n_dev);
         digit_scan_kernel<<<256, kThreads, 0, st>>>(hist, G, dtot);
-        radix_scatter_kernel<K><<<G, kThreads, 0, st>>>(ki, vi, ko, vo, n, shift, chunk, hist, G, dtot);
+        radix_scatter_kernel<K><<<G, kThreads, 0, st>>>(ki, vi, ko, vo, n, shift, chunk, hist, G, dtot, n_dev);
         std::swap(ki, ko);
         std::swap(vi, vo);
         flips ^= 1;
@@ -364,23 +384,51 @@ void launch_emit_keys(const Records& r, const uint32_t* offsets, const uint32_t*
 size_t radix_scratch_bytes(int64_t n) { return sizeof(uint32_t) * 256 * ((size_t)radix_grid(n) + 1); }
 
 int launch_radix_sort(void* keys, uint32_t* vals, void* kalt, uint32_t* valt, int64_t n, int key_bytes, int begin_bit,
-                      int end_bit, void* scratch, hipStream_t st) {
+                      int end_bit, void* scratch, hipStream_t st, const uint64_t* n_dev) {
     uint32_t* hist = reinterpret_cast<uint32_t*>(scratch);
     if (key_bytes == 8)
         return radix_sort_t<uint64_t>(reinterpret_cast<uint64_t*>(keys), vals, reinterpret_cast<uint64_t*>(kalt), valt,
-                                      n, begin_bit, end_bit, hist, st);
+                                      n, begin_bit, end_bit, hist, st, n_dev);
     return radix_sort_t<uint32_t>(reinterpret_cast<uint32_t*>(keys), vals, reinterpret_cast<uint32_t*>(kalt), valt, n,
-                                  begin_bit, end_bit, hist, st);
+                                  begin_bit, end_bit, hist, st, n_dev);
 }
 
-void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gtiles, uint2* ranges, hipStream_t st) {
+namespace {
+__global__ void clear_u32_kernel(uint32_t* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+}  // namespace
+
+namespace {
+// Key count the sort may use after a fixed-capacity emission: the scan total
+// if it fits, else 0 (the emission skipped pairs, so the key array has holes;
+// the batch renders empty and the caller re-runs it with exact sizing).
+__global__ void effective_count_kernel(const uint64_t* __restrict__ total, uint64_t cap, uint64_t* __restrict__ n_eff) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint64_t t = *total;
+        *n_eff = t <= cap ? t : 0ull;
+    }
+}
+}  // namespace
+
+void launch_effective_count(const uint64_t* total, uint64_t cap, uint64_t* n_eff, hipStream_t st) {
+    effective_count_kernel<<<1, 64, 0, st>>>(total, cap, n_eff);
+}
+
+void launch_clear_u32(uint32_t* p, int n, hipStream_t st) {
+    if (n > 0) clear_u32_kernel<<<(n + 255) / 256, 256, 0, st>>>(p, n);
+}
+
+void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gtiles, uint2* ranges, hipStream_t st,
+                        const uint64_t* n_dev) {
     if (n_gtiles > 0) zero_ranges_kernel<<<(unsigned)((n_gtiles + 255) / 256), 256, 0, st>>>(ranges, n_gtiles);
     if (n <= 0) return;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     if (key_bytes == 8)
-        tile_ranges_kernel<true><<<blocks, 256, 0, st>>>(keys, n, ranges);
+        tile_ranges_kernel<true><<<blocks, 256, 0, st>>>(keys, n, ranges, n_dev);
     else
-        tile_ranges_kernel<false><<<blocks, 256, 0, st>>>(keys, n, ranges);
+        tile_ranges_kernel<false><<<blocks, 256, 0, st>>>(keys, n, ranges, n_dev);
 }
 
 }  // namespace swf

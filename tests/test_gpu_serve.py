@@ -1,0 +1,98 @@
+"""Serving loop (continuous batching, captured graphs, admission by memory):
+each result is bitwise identical alone and in a mixed stream, under forced
+shrinking and forced key overflow; error paths."""
+import numpy as np
+import pytest
+
+from paper_2506_12787_amd import synth
+from tests import helpers as Hh
+
+pytestmark = pytest.mark.gpu
+
+SCENES = [(3000, 90, 360), (2000, 180, 720), (6000, 90, 360)]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_2506_12787_amd import binding as B
+    assert torch.cuda.is_available()
+    c = B.Context(0)
+    sids = []
+    for i, (n, H, W) in enumerate(SCENES):
+        g = synth.gaussians(n, H, W, seed=500 + i)
+        Ws, bs = synth.mlp_weights(seed=600 + i, out_scale=1.0)
+        sids.append(c.upload_scene(g, H, W, mlp=(Ws, bs)))
+    rng = np.random.default_rng(9)
+    reqs = [(int(rng.integers(0, len(SCENES))), synth.tx_positions(1, seed=700 + k)[0]) for k in range(48)]
+    alone = []
+    for si, tx in reqs:
+        t = torch.from_numpy(tx[None].copy()).cuda()
+        alone.append(c.render(sids[si], t, flags=B.MLP_BF16)[0].cpu().numpy())
+    yield c, sids, reqs, alone
+    c.close()
+
+
+def _serve_all(c, sids, reqs, **cfg):
+    c.serve_start(**cfg)
+    outs, tks = [], []
+    for si, tx in reqs:
+        n, H, W = SCENES[si]
+        o = np.zeros((H, W), np.float32)
+        tks.append(c.serve_submit(sids[si], tx, o))
+        outs.append(o)
+    stats = [c.serve_wait(t) for t in tks]
+    cnt = c.serve_counters()
+    c.serve_stop()
+    return outs, stats, cnt
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_mixed_stream_equals_alone(setup, graphs):
+    c, sids, reqs, alone = setup
+    outs, stats, cnt = _serve_all(c, sids, reqs, max_batch=8, n_slots=2, use_graphs=graphs)
+    for o, a in zip(outs, alone):
+        np.testing.assert_array_equal(o, a)
+    assert cnt["completed"] == len(reqs)
+    assert max(s["batch"] for s in stats) > 1  # requests were actually batched
+    if graphs:
+        assert cnt["graph_builds"] >= 1
+    print("counters", cnt)
+
+
+def test_memory_budget_shrinks_batches(setup):
+    c, sids, reqs, alone = setup
+    # a 16-query batch of the largest scene needs ~30 MB: 24 MB forces shrinking
+    budget = 24 << 20
+    outs, stats, cnt = _serve_all(c, sids, reqs, max_batch=16, n_slots=2, hbm_budget=budget)
+    for o, a in zip(outs, alone):
+        np.testing.assert_array_equal(o, a)
+    assert cnt["budget_shrinks"] >= 1
+    assert cnt["workspace_bytes"] <= budget
+    print("counters", cnt)
+
+
+def test_key_overflow_falls_back_to_exact_sizing(setup):
+    c, sids, reqs, alone = setup
+    outs, stats, cnt = _serve_all(c, sids, reqs[:12], max_batch=4, n_slots=2, key_factor=0.05)
+    for o, a in zip(outs, alone[:12]):
+        np.testing.assert_array_equal(o, a)
+    assert cnt["fallbacks"] >= 1 and any(s["fallback"] for s in stats)
+
+
+def test_request_errors(setup):
+    from paper_2506_12787_amd import binding as B
+    c, sids, reqs, alone = setup
+    c.serve_start(max_batch=4)
+    o = np.zeros((90, 360), np.float32)
+    with pytest.raises(B.SwfError):
+        c.serve_submit(12345, [1, 1, 1], o)
+    with pytest.raises(B.SwfError):
+        c.serve_submit(sids[0], [np.nan, 1, 1], o)
+    c.serve_stop()
+    # a budget below one query of the scene: the request fails, nothing hangs
+    c.serve_start(max_batch=4, hbm_budget=1 << 20)
+    tk = c.serve_submit(sids[2], [1, 2, 1], o)
+    with pytest.raises(B.SwfError):
+        c.serve_wait(tk)
+    c.serve_stop()
