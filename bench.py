@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--quick", action="store_true", help="timed steps only (for profiler runs)")
+    p.add_argument("--serve-requests", type=int, default=3000, help="requests per serving measurement")
+    p.add_argument("--serve-sweep", action="store_true",
+                   help="8 resident scenes, Poisson arrivals at a rate sweep (prints one JSON line per rate)")
     return p.parse_args()
 
 
@@ -71,11 +74,110 @@ def cpu_baseline(g, Ws, bs, H, W, txs, budget_s):
                       f"{dt:.1f} s"}
 
 
+class _Pool:
+    """Reusable host output buffers for serving requests (grows on demand)."""
+
+    def __init__(self, shapes, per_shape):
+        self.free = {sh: [np.zeros(sh, np.float32) for _ in range(per_shape)] for sh in set(shapes)}
+
+    def get(self, sh):
+        return self.free[sh].pop() if self.free[sh] else np.zeros(sh, np.float32)
+
+    def put(self, sh, a):
+        self.free[sh].append(a)
+
+
+def serve_run(ctx, plan, shapes, rate=None, depth=256):
+    """Serve `plan` = [(scene_id, tx)] through the serving loop. rate=None:
+    closed loop with `depth` outstanding requests (saturation); else Poisson
+    arrivals at `rate` per second, latency measured from the scheduled arrival.
+    Returns (throughput, latencies_us, stats list)."""
+    import threading
+    pool = _Pool(list(shapes.values()), min(depth, 64) + 8)
+    lock = threading.Condition()
+    inflight = []
+    lat, stats = [], []
+    done = [0]
+    n = len(plan)
+
+    def waiter():
+        while done[0] < n:
+            with lock:
+                while not inflight:
+                    lock.wait()
+                tk, sid, buf = inflight.pop(0)
+            st = ctx.serve_wait(tk)
+            lat.append(st["total_us"])
+            stats.append(st)
+            with lock:
+                pool.put(shapes[sid], buf)
+                done[0] += 1
+                lock.notify_all()
+
+    th = threading.Thread(target=waiter, daemon=True)
+    th.start()
+    t0 = ctx.clock()
+    if rate:
+        arrivals = t0 + 0.05 + np.cumsum(np.random.default_rng(11).exponential(1.0 / rate, n))
+    for i, (sid, tx) in enumerate(plan):
+        with lock:
+            while done[0] + depth <= i:
+                lock.wait()
+            buf = pool.get(shapes[sid])
+        arr = 0.0
+        if rate:
+            arr = float(arrivals[i])
+            while ctx.clock() < arr:
+                pass
+        tk = ctx.serve_submit(sid, tx, buf, arr)
+        with lock:
+            inflight.append((tk, sid, buf))
+            lock.notify_all()
+    th.join()
+    elapsed = ctx.clock() - (t0 + (0.05 if rate else 0.0))
+    return n / elapsed, lat, stats
+
+
+def serve_sweep(a):
+    """8 resident scenes (N in {5k, 20k, 100k}, 90x360 or 180x720), random scene
+    per request, Poisson arrivals at fractions of the measured saturation rate."""
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+    scenes = [(5000, 90, 360), (5000, 180, 720), (20000, 90, 360), (20000, 180, 720), (100000, 90, 360),
+              (100000, 180, 720), (20000, 90, 360), (100000, 90, 360)]
+    ctx = B.Context(0)
+    sids, shapes = [], {}
+    for i, (n, H, W) in enumerate(scenes):
+        sid = ctx.upload_scene(synth.gaussians(n, H, W, seed=1003 + 10 * i), H, W,
+                               mlp=synth.mlp_weights(seed=3003 + 10 * i))
+        sids.append(sid)
+        shapes[sid] = (H, W)
+    rng = np.random.default_rng(5003)
+    R = a.serve_requests
+    txs = synth.tx_positions(R, seed=2003)
+    plan = [(sids[int(k)], txs[j]) for j, k in enumerate(rng.integers(0, len(scenes), R))]
+    ctx.serve_start(max_batch=64, n_slots=2, flags=B.MLP_BF16)
+    serve_run(ctx, plan[:512], shapes)  # warm-up: graphs for the common buckets
+    sat, lat, _ = serve_run(ctx, plan, shapes)
+    print(json.dumps({"serve_sweep": "saturation", "rate": None, "throughput": sat,
+                      "p50_us": pct(lat, 50), "p99_us": pct(lat, 99)}), flush=True)
+    for f in (0.1, 0.25, 0.5, 0.75, 0.9, 1.1):
+        thr, lat, st = serve_run(ctx, plan, shapes, rate=f * sat, depth=1 << 30)
+        print(json.dumps({"serve_sweep": "poisson", "rate_fraction": f, "rate": f * sat, "throughput": thr,
+                          "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
+                          "mean_batch": float(np.mean([s["batch"] for s in st]))}), flush=True)
+    ctx.serve_stop()
+    ctx.close()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.serve_sweep:
+        serve_sweep(a)
+        return
     import torch
     from paper_2506_12787_amd import binding as B
     from paper_2506_12787_amd import synth
@@ -155,6 +257,26 @@ def main():
         rec["plain"] = {"value": plain, "unit": "spectra/s", "dtype": "fp32", "batch": 1,
                         "p50_us": pct(lat, 50), "p99_us": pct(lat, 99)}
         rec["batched_over_plain"] = value / plain
+        # serving loop on the same scene: captured graphs, continuous batching
+        ctx.serve_start(max_batch=Bq, n_slots=2, flags=flags)
+        R = a.serve_requests
+        stx = synth.tx_positions(R, seed=2203)
+        plan = [(sid, stx[i]) for i in range(R)]
+        shapes = {sid: (H, W)}
+        serve_run(ctx, plan[:4 * Bq], shapes)  # warm-up (graph capture)
+        sat, lat_s, st_s = serve_run(ctx, plan, shapes, depth=4 * Bq)
+        rate = 0.7 * sat
+        thr_p, lat_p, st_p = serve_run(ctx, plan, shapes, rate=rate, depth=1 << 30)
+        cnt = ctx.serve_counters()
+        ctx.serve_stop()
+        rec["serving"] = {
+            "saturation_spectra_per_s": sat, "saturation_p50_us": pct(lat_s, 50), "saturation_p99_us": pct(lat_s, 99),
+            "poisson_rate_per_s": rate, "poisson_throughput": thr_p, "poisson_p50_us": pct(lat_p, 50),
+            "poisson_p99_us": pct(lat_p, 99), "poisson_mean_batch": float(np.mean([s["batch"] for s in st_p])),
+            "requests_per_point": R, "slots": 2, "max_batch": Bq, "graphs": True, "fallbacks": cnt["fallbacks"],
+            "note": "latency from scheduled arrival to the result in the caller's host buffer"}
+        rec["latency_us"]["serving_p50"] = pct(lat_p, 50)
+        rec["latency_us"]["serving_p99"] = pct(lat_p, 99)
         if not a.no_cpu_baseline:
             rec["cpu_baseline"] = cpu_baseline(g, Ws, bs, H, W, txs[:8], a.cpu_seconds)
     ctx.close()
