@@ -12,6 +12,8 @@ Prints one JSON line (see the repository's design notes for every field).
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -25,6 +27,12 @@ sys.path.insert(0, ROOT)
 METRIC = "spectra/s at N=100k, 90x360 (batched vs plain); p50/p99 query latency us"
 FLOP_PER_PAIR = 2 * (26 * 256 + 3 * 256 * 256 + 256 * 7)  # MLP per (query, Gaussian) pair
 PEAK = {"bf16": 2500.0, "fp32": 157.3}  # dense TFLOP/s (MFMA bf16; fp32 vector incl. packed)
+# MLP kernel HBM bytes per pair that the algorithm needs: BF16 gamma(mu) (64 B) and 7 FP32 scene parameters (28 B)
+# read, one 52 B pair record written; the weight stream is per tile and L2-resident.
+MLP_ALGO_BYTES_PER_PAIR = 64 + 28 + 52
+MLP_SOURCES = ("paper_2506_12787_amd/csrc/mlp_bf16.hip", "paper_2506_12787_amd/csrc/mlp_common.h",
+               "paper_2506_12787_amd/csrc/swf_device.h")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mlp_bf16_n100k_90x360_b64_hbm_traffic.md")
 
 
 def parse():
@@ -45,7 +53,100 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=3000, help="requests per serving measurement")
     p.add_argument("--serve-sweep", action="store_true",
                    help="8 resident scenes, Poisson arrivals at a rate sweep (prints one JSON line per rate)")
+    p.add_argument("--copy-probe-mib", type=int, default=0,
+                   help="after the timed steps, run a plain FP32 copy kernel (x*1) over this many MiB three times: "
+                        "the reference kernel that scales HBM byte counters")
+    p.add_argument("--pmc-summary", nargs="+", metavar="DIR",
+                   help="summarise rocprofv3 counter CSVs (FETCH_SIZE / WRITE_SIZE runs of a --copy-probe-mib run) "
+                        "into HBM bytes per launch of the MLP kernel, then exit")
+    p.add_argument("--copy-mib", type=int, default=1024, help="copy size used by the counted run (for --pmc-summary)")
     return p.parse_args()
+
+
+def mlp_sources_hash():
+    h = hashlib.sha256()
+    for f in MLP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload_key(a):
+    ppw = a.pairs_per_wave or 64
+    return f"n{a.n}_h{a.height}_w{a.width}_b{a.batch}_{a.mlp}_ppw{ppw}"
+
+
+def read_counters(dirs):
+    """{(kernel name, counter): [value per dispatch]} from rocprofv3 counter-collection CSVs."""
+    per = {}
+    for d in dirs:
+        for root, _, files in os.walk(d):
+            for f in files:
+                if not f.endswith("counter_collection.csv"):
+                    continue
+                with open(os.path.join(root, f), newline="") as fh:
+                    for r in csv.DictReader(fh):
+                        k = (r["Kernel_Name"], r["Counter_Name"])
+                        disp = per.setdefault(k, {})
+                        disp[(f, r["Dispatch_Id"])] = disp.get((f, r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+    return {k: list(v.values()) for k, v in per.items()}
+
+
+def pmc_summary(a):
+    """HBM bytes per launch of the MLP kernel from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by what
+    the same counter reads for the plain copy kernel of known size run in the same process."""
+    c = read_counters(a.pmc_summary)
+    mean = lambda v: sum(v) / len(v)
+    names = {k for k, _ in c}
+    mlp = [n for n in names if f"mlp_{a.mlp}_kernel" in n]
+    cp = [n for n in names if "elementwise" in n]
+    if len(mlp) != 1 or not cp:
+        sys.exit(f"pmc-summary: need one mlp_{a.mlp}_kernel and a copy kernel, found {sorted(names)}")
+    mlp = mlp[0]
+    # the probe is the elementwise kernel with the largest reads
+    cp = max(cp, key=lambda n: mean(c.get((n, "FETCH_SIZE"), [0.0])))
+    copy_bytes = a.copy_mib * 2 ** 20
+    out = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        if (mlp, ctr) not in c or (cp, ctr) not in c:
+            sys.exit(f"pmc-summary: counter {ctr} missing")
+        kib_copy = mean(c[(cp, ctr)])
+        kib_mlp = mean(c[(mlp, ctr)])
+        scale = copy_bytes / (kib_copy * 1024.0)
+        out[ctr] = {"mlp_kib_per_dispatch": kib_mlp, "mlp_dispatches": len(c[(mlp, ctr)]),
+                    "copy_kib_per_dispatch": kib_copy, "copy_dispatches": len(c[(cp, ctr)]),
+                    "copy_bytes": copy_bytes, "scale": scale, "mlp_bytes": kib_mlp * 1024.0 * scale}
+    pairs = a.n * a.batch
+    traffic = out["FETCH_SIZE"]["mlp_bytes"] + out["WRITE_SIZE"]["mlp_bytes"]
+    algo = MLP_ALGO_BYTES_PER_PAIR * pairs
+    print(f"kernel: {mlp}")
+    print(f"copy kernel: {cp}")
+    for ctr, v in out.items():
+        print(f"{ctr}: mlp {v['mlp_kib_per_dispatch']:.1f} KiB/dispatch ({v['mlp_dispatches']} dispatches); copy "
+              f"{v['copy_kib_per_dispatch']:.1f} KiB/dispatch for {v['copy_bytes']} B ({v['copy_dispatches']} "
+              f"dispatches) -> scale {v['scale']:.4f} -> {v['mlp_bytes'] / 1e6:.1f} MB")
+    print(f"algorithmic bytes per launch: {algo} ({MLP_ALGO_BYTES_PER_PAIR} B x {pairs} pairs)")
+    print(f"traffic / algorithmic: {traffic / algo:.3f}")
+    print(f"workload: {workload_key(a)}")
+    print(f"sources: {mlp_sources_hash()}")
+    print(f"traffic_bytes_per_launch: {traffic:.0f}")
+
+
+def measured_traffic(a):
+    """HBM bytes per MLP launch from the committed counter summary, if it was taken on this workload and on the
+    current kernel sources; otherwise None."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            kv = dict(line.strip().split(": ", 1) for line in fh if line.count(": ") >= 1 and
+                      line.split(": ", 1)[0] in ("workload", "sources", "traffic_bytes_per_launch"))
+    except OSError:
+        return None
+    if kv.get("workload") != workload_key(a) or kv.get("sources") != mlp_sources_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def pct(a, q):
@@ -175,6 +276,9 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.pmc_summary:
+        pmc_summary(a)
+        return
     if a.serve_sweep:
         serve_sweep(a)
         return
@@ -222,7 +326,9 @@ def main():
     achieved = flops / (avg_mlp_ms * 1e-3) / 1e12
     peak = PEAK[a.mlp]
     roofline = {"kernel": f"mlp_{a.mlp}_deform_preprocess", "bound": "mfma" if a.mlp == "bf16" else "alu",
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": measured_traffic(a) if a.mlp == "bf16" else None,
+                "algorithmic_bytes_per_launch": MLP_ALGO_BYTES_PER_PAIR * N * Bq,
                 "avg_launch_ms": avg_mlp_ms, "flop_per_launch": flops}
 
     rec = {
@@ -237,6 +343,13 @@ def main():
         "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "roofline": roofline,
     }
+    if a.copy_probe_mib:
+        src = torch.ones(a.copy_probe_mib * 2 ** 18, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if not a.quick:
         # plain one-query-per-launch FP32 path
         q = a.plain_queries

@@ -322,7 +322,8 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
         // layout of the previous layer's output tiles. The output layer (7 rows
         // padded to 16) fills one chunk with its 8 k-chunk fragments.
         if (!st) {
-            const int n_chunks = 2 + 8 * (d.n_hidden - 1);
+            // steps of 32 KiB: [layer 1 | pad] [hidden chunks in pairs] [output | pad]
+            const int n_chunks = 2 + 8 * (d.n_hidden - 1) + 2;  // in 16 KiB units, padded
             std::vector<uint16_t> t((size_t)n_chunks * 8192, 0);
             auto fk = [](int c, int g, int j) { return 32 * c + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4)); };
             for (int tt = 0; tt < 16; ++tt)
@@ -334,7 +335,7 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
                     }
             for (int L = 1; L < d.n_hidden; ++L)
                 for (int c = 0; c < 8; ++c) {
-                    const size_t ch = (size_t)(1 + 8 * (L - 1) + c) * 8192;
+                    const size_t ch = (size_t)(2 + 8 * (L - 1) + c) * 8192;
                     for (int tt = 0; tt < 16; ++tt)
                         for (int l = 0; l < 64; ++l)
                             for (int j = 0; j < 8; ++j) {
@@ -343,7 +344,7 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
                             }
                 }
             {
-                const size_t ch = (size_t)(n_chunks - 1) * 8192;
+                const size_t ch = (size_t)(n_chunks - 2) * 8192;
                 for (int c = 0; c < 8; ++c)
                     for (int l = 0; l < 64; ++l)
                         for (int j = 0; j < 8; ++j) {
