@@ -31,6 +31,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short short2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t cvt_pk_bf16(float a, float b) {
     const bf16x2 v = {(__bf16)a, (__bf16)b};  // v_cvt_pk_bf16_f32, round to nearest even
@@ -76,16 +77,28 @@ __device__ __forceinline__ bf16x8 pack_relu(f32x4 lo, f32x4 hi) {
 }
 
 // NCB column blocks of 16 pairs per wave (64 or 32 pairs); 4 waves per block.
+//
+// Weight ring: kSlots LDS slots of one 32 KiB step each. The step q + 2 is
+// copied global -> LDS directly (global_load_lds, no registers) at the start of
+// step q into the slot read during step q - 1; the barrier ending step q waits
+// for it (its workgroup fence drains the vector memory counter). Fragment reads
+// run two fragments ahead, into the next slot past the end of a step.
+//
+// Hidden layers run output-tile-major: tile t (16 features) accumulates its
+// 8 k-chunks, so accumulator pairs (2c', 2c'+1) are final early and their ReLU
+// + bf16 conversion into the next layer's act[c'] is issued among the MFMAs of
+// the following tile (one column block per two fragments) instead of after
+// the layer; the last pair is converted during the next layer's first tile.
 template <int NCB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NCB == 2 ? 2 : 1, NCB == 2 ? 2 : 1))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 mlp_bf16_kernel(Bf16Args a) {
+    typedef __attribute__((address_space(3))) void* lds_ptr;
     constexpr int kPairsPerWave = 16 * NCB;
     constexpr int kPairsPerBlock = 4 * kPairsPerWave;
     __shared__ __attribute__((aligned(16))) uint4 ring[kSlots * kChunkU4];
     __shared__ float outs[4][kPairsPerWave][8];
     // Layer-1 TX term of the current and the next tile's query, hidden and
-    // output biases: C operands read from LDS, so no MFMA chain waits on a
-    // global load.
+    // output biases: C operands read from LDS.
     __shared__ __attribute__((aligned(16))) float qs_s[2][256];
     __shared__ __attribute__((aligned(16))) float bias_s[7][256];
     __shared__ __attribute__((aligned(16))) float bias_o_s[16];
@@ -101,56 +114,29 @@ mlp_bf16_kernel(Bf16Args a) {
     // tiles of this persistent workgroup
     const int my_tiles = a.n_tiles > (int)blockIdx.x ? (a.n_tiles - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
     if (my_tiles == 0) return;
-    const int q_end = my_tiles * S;  // chunk steps of this workgroup
+    const int q_end = my_tiles * S;  // ring steps of this workgroup
     for (int l = 0; l < n_mid; ++l) bias_s[l][tid] = a.bias_h[l][tid];
     if (tid < 16) bias_o_s[tid] = tid < kOut ? a.bias_o[tid] : 0.0f;
     qs_s[0][tid] = a.m.qs[(size_t)((int)blockIdx.x / a.tiles_per_query) * 256 + tid];
 
-    // Ring of kSlots chunk slots. Step q computes from slot q % 3; during step q
-    // the chunk q + 2 (prefetched into registers during step q - 1) is stored
-    // into slot (q + 2) % 3 and chunk q + 3 is fetched; one barrier ends a step.
-    // prefetched ring step: eight named registers per thread (an array here is
-    // turned into LDS or scratch by the compiler)
-    static_assert(kPF == 8, "the prefetch list below names eight registers");
-    uint4 pf0, pf1, pf2, pf3, pf4, pf5, pf6, pf7;
-    int fetch_chunk = 0;  // stream step index of the next fetch
-#define SWF_PF_EACH(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
-#define SWF_PF_LOAD(i_) pf##i_ = a.stream[(size_t)fetch_chunk * kChunkU4 + tid + (i_) * 256];
-#define SWF_RING_FETCH()                                          \
-    do {                                                          \
-        SWF_PF_EACH(SWF_PF_LOAD)                                  \
-        fetch_chunk = fetch_chunk + 1 == S ? 0 : fetch_chunk + 1; \
+    int fetch = 0;  // stream step of the next copy
+#define SWF_DMA(slot_)                                                                                     \
+    do {                                                                                                   \
+        const uint4* src_ = a.stream + (size_t)fetch * kChunkU4 + tid;                                     \
+        _Pragma("unroll") for (int i_ = 0; i_ < kPF; ++i_) __builtin_amdgcn_global_load_lds(              \
+            src_ + i_ * 256, (lds_ptr)(ring + (slot_) * kChunkU4 + i_ * 256 + wave * 64), 16, 0, 0);       \
+        fetch = fetch + 1 == S ? 0 : fetch + 1;                                                            \
     } while (0)
-#define SWF_PF_PUT(i_) ring[slot_base_ + tid + (i_) * 256] = pf##i_;
-#define SWF_RING_STORE(slot_)                    \
-    do {                                         \
-        const int slot_base_ = (slot_) * kChunkU4; \
-        SWF_PF_EACH(SWF_PF_PUT)                  \
-    } while (0)
-    SWF_RING_FETCH();
-    SWF_RING_STORE(0);
-    if (q_end > 1) {
-        SWF_RING_FETCH();
-        SWF_RING_STORE(1);
-    }
-    if (q_end > 2) SWF_RING_FETCH();
+    SWF_DMA(0);
+    if (q_end > 1) SWF_DMA(1);
     __syncthreads();
-    int q = 0;         // step being computed
-    int slot = 0;      // q % 3
-    // during step q: store the prefetched step q + 2, fetch step q + 3
-#define SWF_RING_ADVANCE()                                      \
-    do {                                                        \
-        const int s2_ = slot == 0 ? 2 : slot - 1;               \
-        if (q + 2 < q_end) SWF_RING_STORE(s2_);                 \
-        if (q + 3 < q_end) SWF_RING_FETCH();                    \
+    int q = 0;     // step being computed
+    int slot = 0;  // q % 3
+#define SWF_ADVANCE()                                         \
+    do {                                                      \
+        if (q + 2 < q_end) SWF_DMA(slot == 0 ? 2 : slot - 1); \
     } while (0)
 #define SWF_FRAG_AT(s_, t_) __builtin_bit_cast(bf16x8, ring[(s_) * kChunkU4 + (t_) * 64 + lane])
-    // Fragment pipeline: the two fragments after the one in use are already in
-    // registers, so an LDS read has two MFMA groups to land. Past the end of a
-    // step the pipeline reads the first fragments of the next slot: that slot
-    // was completed before the previous barrier and is not overwritten until two
-    // barriers later, so reading it early is safe (at the last step it holds
-    // stale data that is never used).
     bf16x8 w_a = SWF_FRAG_AT(0, 0), w_b = SWF_FRAG_AT(0, 1);
 #define SWF_TAKE(dst_, f_, nf_)                                                                          \
     do {                                                                                                 \
@@ -159,29 +145,89 @@ mlp_bf16_kernel(Bf16Args a) {
         const int nxt_ = slot == 2 ? 0 : slot + 1;                                                       \
         w_b = (f_) + 2 < (nf_) ? SWF_FRAG_AT(slot, (f_) + 2) : SWF_FRAG_AT(nxt_, (f_) + 2 - (nf_));      \
     } while (0)
-#define SWF_NEXT_STEP()                      \
-    do {                                     \
-        __syncthreads();                     \
-        ++q;                                 \
-        slot = slot == 2 ? 0 : slot + 1;     \
+#define SWF_NEXT_STEP()                  \
+    do {                                 \
+        __syncthreads();                 \
+        ++q;                             \
+        slot = slot == 2 ? 0 : slot + 1; \
+    } while (0)
+    // the empty asm pins the conversion where it is written (it would
+    // otherwise be sunk next to its first use, after the MFMAs it should overlap)
+#define SWF_PACK(dst_, cp_, cb_)                                                      \
+    do {                                                                              \
+        u32x4 u_ = __builtin_bit_cast(u32x4, pack_relu(acc[2 * (cp_)][cb_], acc[2 * (cp_) + 1][cb_])); \
+        asm volatile("" : "+v"(u_));                                                  \
+        dst_[cp_][cb_] = __builtin_bit_cast(bf16x8, u_);                              \
     } while (0)
 
     f32x4 acc[16][NCB];
-    bf16x8 act[8][NCB];
+    bf16x8 act[2][8][NCB];
+
+    // One hidden layer, act[IN_] -> act[OUT_]: 16 output tiles x 8 k-chunks, t-major,
+    // four ring steps. On entry the accumulator pair (14, 15) of the previous
+    // layer is still unconverted; it becomes act[IN_][7] during tile 0.
+#define SWF_HIDDEN(IN_, OUT_, L_)                                                                        \
+    do {                                                                                                 \
+        const float* bias_ = &bias_s[(L_)][4 * g];                                                       \
+        _Pragma("unroll") for (int t = 0; t < 16; ++t) {                                                 \
+            _Pragma("unroll") for (int c = 0; c < 8; ++c) {                                              \
+                const int f = t * 8 + c;                                                                 \
+                if ((f & 31) == 0) SWF_ADVANCE();                                                        \
+                bf16x8 w;                                                                                \
+                SWF_TAKE(w, f & 31, 32);                                                                 \
+                if (c == 0) {                                                                            \
+                    const float4 b4 = *reinterpret_cast<const float4*>(bias_ + 16 * t);                 \
+                    const f32x4 c0 = {b4.x, b4.y, b4.z, b4.w};                                           \
+                    _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) acc[t][cb] =                      \
+                        mfma(w, act[IN_][c][cb], c0);                                                    \
+                } else {                                                                                 \
+                    _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) acc[t][cb] =                      \
+                        mfma(w, act[IN_][c][cb], acc[t][cb]);                                            \
+                }                                                                                        \
+                if (t == 0 && c < NCB) SWF_PACK(act[IN_], 7, c);                                         \
+                if (t >= 2 && (t & 1) == 0 && (c & 1) == 0 && c / 2 < NCB)                               \
+                    SWF_PACK(act[OUT_], (t - 2) / 2, c / 2);                                             \
+                __builtin_amdgcn_sched_barrier(0);                                                       \
+                if ((f & 31) == 31) SWF_NEXT_STEP();                                                     \
+            }                                                                                            \
+        }                                                                                                \
+    } while (0)
+
+    // Output layer from act[IN_] (one 16-row tile, 7 used, 8 k-chunks in one
+    // ring step), transposed through LDS to one pair per lane.
+#define SWF_OUTPUT(IN_)                                                                                  \
+    do {                                                                                                 \
+        SWF_ADVANCE();                                                                                   \
+        f32x4 o[NCB];                                                                                    \
+        const float4 b4 = *reinterpret_cast<const float4*>(&bias_o_s[4 * g]);                            \
+        _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) o[cb] = f32x4{b4.x, b4.y, b4.z, b4.w};        \
+        _Pragma("unroll") for (int c = 0; c < 8; ++c) {                                                  \
+            bf16x8 w;                                                                                    \
+            SWF_TAKE(w, c, 8);                                                                           \
+            if (c < NCB) SWF_PACK(act[IN_], 7, c);                                                       \
+            _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) o[cb] = mfma(w, act[IN_][c][cb], o[cb]);  \
+            __builtin_amdgcn_sched_barrier(0);                                                           \
+        }                                                                                                \
+        if (g < 2) {                                                                                     \
+            _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb)                                           \
+                _Pragma("unroll") for (int j = 0; j < 4; ++j) outs[wave][cb * 16 + n16][4 * g + j] =     \
+                    o[cb][j];                                                                            \
+        }                                                                                                \
+    } while (0)
 
     for (int it = 0; it < my_tiles; ++it) {
         const int tile = (int)blockIdx.x + it * (int)gridDim.x;
         const int qry = tile / a.tiles_per_query;                  // block-uniform query
         const int p0 = (tile - qry * a.tiles_per_query) * kPairsPerBlock + wave * kPairsPerWave;
         const size_t row0 = (size_t)qry * a.m.N;                   // first pair of the query
-        // ---- layer 1 (mean part, K = 32): B = bf16 gamma(mu_hat); C = qs[query] ----
+        // ---- layer 1 (mean part, K = 32): B = bf16 gamma(mu_hat); C = TX term of the query ----
         bf16x8 bm[NCB];
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             const int p = p0 + cb * 16 + n16;
             bm[cb] = p < a.m.N ? a.mfeat[(size_t)p * 4 + g] : bf16x8{};
         }
-        SWF_RING_ADVANCE();
+        SWF_ADVANCE();
         {
             const float* qrow = &qs_s[it & 1][4 * g];
 #pragma unroll
@@ -192,6 +238,13 @@ mlp_bf16_kernel(Bf16Args a) {
                 SWF_TAKE(w, t, 16);
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) acc[t][cb] = mfma(w, bm[cb], c0);
+                // pairs 0..6 as 7 * NCB (pair, column block) units, NCB / 2 per
+                // fragment from t = 2 on; pair c' is final once t > 2c' + 1
+                if (t >= 2)
+#pragma unroll
+                    for (int u = (t - 2) * NCB / 2; u < (t - 1) * NCB / 2; ++u)
+                        SWF_PACK(act[0], u / NCB, u % NCB);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         SWF_NEXT_STEP();
@@ -200,57 +253,17 @@ mlp_bf16_kernel(Bf16Args a) {
         const int next_tile = tile + (int)gridDim.x;
         const float qs_next =
             it + 1 < my_tiles ? a.m.qs[(size_t)(next_tile / a.tiles_per_query) * 256 + tid] : 0.0f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) act[c][cb] = pack_relu(acc[2 * c][cb], acc[2 * c + 1][cb]);
-        // ---- hidden layers: C starts at the bias ----
-        for (int l = 0; l < n_mid; ++l) {
-            const float* bias = &bias_s[l][4 * g];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                if ((c & 1) == 0) SWF_RING_ADVANCE();
-#pragma unroll
-                for (int t = 0; t < 16; ++t) {
-                    bf16x8 w;
-                    SWF_TAKE(w, (c & 1) * 16 + t, 32);
-                    f32x4 c0;
-                    if (c == 0) {
-                        const float4 b4 = *reinterpret_cast<const float4*>(bias + 16 * t);
-                        c0 = f32x4{b4.x, b4.y, b4.z, b4.w};
-                    }
-#pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb) acc[t][cb] = mfma(w, act[c][cb], c == 0 ? c0 : acc[t][cb]);
-                }
-                if (c & 1) SWF_NEXT_STEP();
-            }
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-#pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) act[c][cb] = pack_relu(acc[2 * c][cb], acc[2 * c + 1][cb]);
+        // ---- hidden layers, two per iteration so the act buffers alternate statically ----
+        int l = 0;
+        for (; l + 1 < n_mid; l += 2) {
+            SWF_HIDDEN(0, 1, l);
+            SWF_HIDDEN(1, 0, l + 1);
         }
-        // ---- output layer: one 16-row tile (7 used), 8 k-chunks in one ring chunk ----
-        SWF_RING_ADVANCE();
-        f32x4 o[NCB];
-        {
-            const float4 b4 = *reinterpret_cast<const float4*>(&bias_o_s[4 * (g & 3)]);
-            const f32x4 ob = {b4.x, b4.y, b4.z, b4.w};  // rows >= 7 are zero and never stored
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) o[cb] = ob;
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            bf16x8 w;
-            SWF_TAKE(w, c, 8);
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) o[cb] = mfma(w, act[c][cb], o[cb]);
-        }
-        // lane (g, n16) holds outputs 4g..4g+3 of pair cb*16+n16: transpose via LDS
-        if (g < 2) {
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) outs[wave][cb * 16 + n16][4 * g + j] = o[cb][j];
+        if (l < n_mid) {
+            SWF_HIDDEN(0, 1, l);
+            SWF_OUTPUT(1);
+        } else {
+            SWF_OUTPUT(0);
         }
         qs_s[(it + 1) & 1][tid] = qs_next;
         SWF_NEXT_STEP();
@@ -260,15 +273,14 @@ mlp_bf16_kernel(Bf16Args a) {
         }
         // `outs` is rewritten only after the next tile's first barrier
     }
-#undef SWF_PF_EACH
-#undef SWF_PF_LOAD
-#undef SWF_PF_PUT
-#undef SWF_RING_FETCH
-#undef SWF_RING_STORE
-#undef SWF_RING_ADVANCE
+#undef SWF_DMA
+#undef SWF_ADVANCE
 #undef SWF_FRAG_AT
 #undef SWF_TAKE
 #undef SWF_NEXT_STEP
+#undef SWF_PACK
+#undef SWF_HIDDEN
+#undef SWF_OUTPUT
 }
 
 __global__ void mean_features_bf16_kernel(const float* __restrict__ mx, const float* __restrict__ my, int n, int W,

@@ -315,12 +315,13 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
             st = put(&d.wo_t, t.data(), t.size());
         }
         // BF16 weight stream for the MFMA kernel: per tile of pairs the kernel
-        // consumes chunks of 16 fragments; fragment (t, c) of a layer holds, for
+        // consumes the stream in order; fragment (t, c) of a layer holds, for
         // lane l = 16 g + r and element j, W[16 t + r][k(c, g, j)]. Layer 1 (mean
-        // part, K = 26 padded to 32): k = 8 g + j. Later layers: k = 32 c + f(g, j)
+        // part, K = 26 padded to 32): 16 fragments, k = 8 g + j. Hidden layers:
+        // 128 fragments in output-tile-major order (8 t + c), k = 32 c + f(g, j)
         // with f(g, j) = j < 4 ? 4 g + j : 16 + 4 g + j - 4, matching the register
         // layout of the previous layer's output tiles. The output layer (7 rows
-        // padded to 16) fills one chunk with its 8 k-chunk fragments.
+        // padded to 16): its 8 k-chunk fragments.
         if (!st) {
             // steps of 32 KiB: [layer 1 | pad] [hidden chunks in pairs] [output | pad]
             const int n_chunks = 2 + 8 * (d.n_hidden - 1) + 2;  // in 16 KiB units, padded
@@ -334,15 +335,16 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
                         t[(size_t)tt * 512 + l * 8 + j] = f32_to_bf16_rne(w);
                     }
             for (int L = 1; L < d.n_hidden; ++L)
-                for (int c = 0; c < 8; ++c) {
-                    const size_t ch = (size_t)(2 + 8 * (L - 1) + c) * 8192;
-                    for (int tt = 0; tt < 16; ++tt)
+                for (int tt = 0; tt < 16; ++tt)
+                    for (int c = 0; c < 8; ++c) {
+                        const int f = 8 * tt + c;  // output-tile-major fragment order
+                        const size_t at = (size_t)(2 + 8 * (L - 1)) * 8192 + (size_t)f * 512;
                         for (int l = 0; l < 64; ++l)
                             for (int j = 0; j < 8; ++j) {
                                 const int row = 16 * tt + (l & 15), k = fk(c, l >> 4, j);
-                                t[ch + (size_t)tt * 512 + l * 8 + j] = f32_to_bf16_rne(Wh[L][(size_t)row * Hd + k]);
+                                t[at + l * 8 + j] = f32_to_bf16_rne(Wh[L][(size_t)row * Hd + k]);
                             }
-                }
+                    }
             {
                 const size_t ch = (size_t)(n_chunks - 2) * 8192;
                 for (int c = 0; c < 8; ++c)
