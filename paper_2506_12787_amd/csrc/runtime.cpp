@@ -468,15 +468,31 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     w.last.valid = false;
     swf_status s = enqueue_preprocess(w, sc, tx, B, flags, g, nullptr, st);
     if (s) return s;
-    const int64_t pairs = (int64_t)B * d.n;
-    if ((s = w.off.reserve(this, (size_t)pairs * sizeof(uint32_t) + 16, st))) return s;
-    if ((s = w.scan.reserve(this, scan_scratch_bytes(pairs) + 64, st))) return s;
-    stage_begin(SWF_STAGE_SCAN, st);
-    launch_exclusive_scan(w.rec.count, (uint32_t*)w.off.ptr, w.total_dev, pairs, w.scan.ptr, st);
-    stage_end(st);
-    uint64_t nk = key_cap;
-    const uint64_t* n_dev = nullptr;
+    const bool full = (flags & SWF_FULL_SORT) != 0;
+    const int64_t n_gt = (int64_t)B * g.tiles;
+    if ((s = w.ranges.reserve(this, (size_t)n_gt * sizeof(uint2), st))) return s;
+    if (!full && g.tiles <= kBinMaxTiles)
+        s = lists_binned(w, d, B, g, st, key_cap);
+    else
+        s = lists_sorted(w, d, B, g, full, st, key_cap);
+    if (s) return s;
+    w.last.valid = true;
+    w.last.scene = sid;
+    w.last.B = B;
+    w.last.N = d.n;
+    w.last.flags = flags;
+    w.last.grid = g;
+    return hip(hipGetLastError(), "forward launch");
+}
+
+// Key count after an exclusive scan whose 64-bit total is in w.total_dev:
+// read back (key_cap == 0), or kept on the device as the effective count
+// (total if it fits key_cap, else 0 with the overflow bit set).
+swf_status Ctx::key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64_t& nk, const uint64_t*& n_dev) {
+    nk = key_cap;
+    n_dev = nullptr;
     if (key_cap == 0) {
+        swf_status s;
         if ((s = hip(hipMemcpyAsync(w.total_host, w.total_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, st),
                      "total D2H")))
             return s;
@@ -485,11 +501,59 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     } else {
         launch_clear_u32(w.status_dev, 1, st);
         uint64_t* n_eff = w.total_dev + 1;  // the word after the scan total
-        launch_effective_count(w.total_dev, key_cap, n_eff, st);
+        launch_effective_count(w.total_dev, key_cap, n_eff, w.status_dev, st);
         n_dev = n_eff;
     }
     if (nk >= (1ull << 32)) return fail(SWF_E_OVERFLOW, "more than 2^32 - 1 keys; render a smaller batch");
-    const bool full = (flags & SWF_FULL_SORT) != 0;
+    return SWF_OK;
+}
+
+// Lists by binning (at most 256 tiles per query): tile histograms per block of
+// pairs, their scan, stable placement, ranges. Same lists as the full sort.
+swf_status Ctx::lists_binned(Workspace& w, const DevScene& d, int B, const Grid& g, hipStream_t st,
+                             uint64_t key_cap) {
+    swf_status s;
+    const int64_t nh = (int64_t)bin_hist_entries(B, d.n);
+    if ((s = w.bins.reserve(this, (size_t)nh * sizeof(uint32_t) + 16, st))) return s;
+    if ((s = w.scan.reserve(this, scan_scratch_bytes(nh) + 64, st))) return s;
+    uint32_t* bins = (uint32_t*)w.bins.ptr;
+    stage_begin(SWF_STAGE_SCAN, st);
+    launch_bin_hist(w.rec, B, d.n, g, bins, st);
+    launch_exclusive_scan(bins, bins, w.total_dev, nh, w.scan.ptr, st);
+    stage_end(st);
+    uint64_t nk;
+    const uint64_t* n_dev;
+    if ((s = key_count(w, st, key_cap, nk, n_dev))) return s;
+    if ((s = w.vals.reserve(this, nk * 4 + 16, st))) return s;
+    stage_begin(SWF_STAGE_SORT, st);
+    launch_bin_scatter(w.rec, B, d.n, g, bins, n_dev, (uint32_t*)w.vals.ptr, st);
+    stage_end(st);
+    stage_begin(SWF_STAGE_RANGES, st);
+    launch_bin_ranges(bins, B, d.n, g, w.total_dev, n_dev, (uint2*)w.ranges.ptr, st);
+    stage_end(st);
+    w.last.n_keys = nk;
+    w.last.full = false;
+    w.last.binned = true;
+    w.last.keys = nullptr;
+    w.last.vals = (uint32_t*)w.vals.ptr;
+    return SWF_OK;
+}
+
+// Lists by key emission and LSD radix sort: on the global tile id (stable; the
+// pairs are already in depth order), or with SWF_FULL_SORT on the full 64-bit
+// (tile, depth) key.
+swf_status Ctx::lists_sorted(Workspace& w, const DevScene& d, int B, const Grid& g, bool full, hipStream_t st,
+                             uint64_t key_cap) {
+    swf_status s;
+    const int64_t pairs = (int64_t)B * d.n;
+    if ((s = w.off.reserve(this, (size_t)pairs * sizeof(uint32_t) + 16, st))) return s;
+    if ((s = w.scan.reserve(this, scan_scratch_bytes(pairs) + 64, st))) return s;
+    stage_begin(SWF_STAGE_SCAN, st);
+    launch_exclusive_scan(w.rec.count, (uint32_t*)w.off.ptr, w.total_dev, pairs, w.scan.ptr, st);
+    stage_end(st);
+    uint64_t nk;
+    const uint64_t* n_dev;
+    if ((s = key_count(w, st, key_cap, nk, n_dev))) return s;
     const size_t kb = full ? 8 : 4;
     if ((s = w.keys.reserve(this, nk * kb + 16, st))) return s;
     if ((s = w.keys2.reserve(this, nk * kb + 16, st))) return s;
@@ -497,7 +561,6 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     if ((s = w.vals2.reserve(this, nk * 4 + 16, st))) return s;
     if ((s = w.hist.reserve(this, radix_scratch_bytes((int64_t)nk) + 64, st))) return s;
     const int64_t n_gt = (int64_t)B * g.tiles;
-    if ((s = w.ranges.reserve(this, (size_t)n_gt * sizeof(uint2), st))) return s;
     stage_begin(SWF_STAGE_EMIT, st);
     launch_emit_keys(w.rec, (const uint32_t*)w.off.ptr, d.dbits, B, d.n, g, nk, full, w.keys.ptr,
                      (uint32_t*)w.vals.ptr, w.status_dev, st);
@@ -512,17 +575,12 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     stage_begin(SWF_STAGE_RANGES, st);
     launch_tile_ranges(skeys, (int)kb, (int64_t)nk, n_gt, (uint2*)w.ranges.ptr, st, n_dev);
     stage_end(st);
-    w.last.valid = true;
-    w.last.scene = sid;
-    w.last.B = B;
-    w.last.N = d.n;
-    w.last.flags = flags;
-    w.last.grid = g;
     w.last.n_keys = nk;
     w.last.full = full;
+    w.last.binned = false;
     w.last.keys = skeys;
     w.last.vals = svals;
-    return hip(hipGetLastError(), "forward launch");
+    return SWF_OK;
 }
 
 swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux,
@@ -699,15 +757,38 @@ swf_status swf_debug_keys(swf_ctx* h, uint32_t* counts, uint32_t* offsets, uint6
     swf_status s = SWF_OK;
     if (counts && (s = c->hip(hipMemcpy(counts, c->ws.rec.count, pairs * 4, hipMemcpyDeviceToHost), "D2H counts")))
         return s;
-    if (offsets && (s = c->hip(hipMemcpy(offsets, c->ws.off.ptr, pairs * 4, hipMemcpyDeviceToHost), "D2H offsets")))
-        return s;
+    if (offsets) {
+        if (L.binned) {
+            // the binning path never forms per-pair offsets: scan the counts here
+            std::vector<uint32_t> cnt(pairs);
+            if (pairs && (s = c->hip(hipMemcpy(cnt.data(), c->ws.rec.count, pairs * 4, hipMemcpyDeviceToHost),
+                                     "D2H counts")))
+                return s;
+            uint32_t run = 0;
+            for (size_t i = 0; i < pairs; ++i) {
+                offsets[i] = run;
+                run += cnt[i];
+            }
+        } else if ((s = c->hip(hipMemcpy(offsets, c->ws.off.ptr, pairs * 4, hipMemcpyDeviceToHost), "D2H offsets"))) {
+            return s;
+        }
+    }
     if ((keys || values) && L.n_keys > capacity) return c->fail(SWF_E_OVERFLOW, "capacity below key count");
     if (keys || values) {
         std::vector<uint32_t> v(L.n_keys);
         if (L.n_keys && (s = c->hip(hipMemcpy(v.data(), L.vals, L.n_keys * 4, hipMemcpyDeviceToHost), "D2H vals")))
             return s;
         std::vector<uint64_t> k64(L.n_keys);
-        if (L.full) {
+        if (L.binned) {
+            // keys of the binned lists: the tile of each list position, from the ranges
+            const size_t m = (size_t)L.B * L.grid.tiles;
+            std::vector<uint32_t> rg(2 * m);
+            if (m && (s = c->hip(hipMemcpy(rg.data(), c->ws.ranges.ptr, m * 8, hipMemcpyDeviceToHost), "D2H ranges")))
+                return s;
+            for (size_t t = 0; t < m; ++t)
+                for (uint32_t i = rg[2 * t]; i < rg[2 * t + 1] && i < L.n_keys; ++i)
+                    k64[i] = ((uint64_t)t << 32) | sc->host_dbits[v[i] % L.N];
+        } else if (L.full) {
             if (L.n_keys && (s = c->hip(hipMemcpy(k64.data(), L.keys, L.n_keys * 8, hipMemcpyDeviceToHost), "D2H keys")))
                 return s;
         } else {

@@ -43,21 +43,22 @@ struct LastRender {
     Grid grid{};
     uint64_t n_keys = 0;
     bool full = false;
+    bool binned = false;    // lists built by the binning path (no key array)
     void* keys = nullptr;
     uint32_t* vals = nullptr;
 };
 
 // Scratch memory of one render stream: every pipeline stage writes here.
 struct Workspace {
-    Buf qs, geo, wm, oa, rect, count, off, scan, keys, keys2, vals, vals2, hist, ranges, delta, sortk, sortv, grad,
-        dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, ptrs, stage;
+    Buf qs, geo, wm, oa, rect, count, off, scan, keys, keys2, vals, vals2, hist, ranges, bins, delta, sortk, sortv,
+        grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, ptrs, stage;
     Records rec;
     uint64_t* total_dev = nullptr;   // device: scan total, then the status word
     uint32_t* status_dev = nullptr;
     uint64_t* total_host = nullptr;  // pinned
     LastRender last;
     std::vector<Buf*> bufs() {
-        return {&qs, &geo, &wm, &oa, &rect, &count, &off, &scan, &keys, &keys2, &vals, &vals2, &hist, &ranges,
+        return {&qs, &geo, &wm, &oa, &rect, &count, &off, &scan, &keys, &keys2, &vals, &vals2, &hist, &ranges, &bins,
                 &delta, &sortk, &sortv, &grad, &dpair, &dbase, &dy, &act, &dz, &part, &fmean, &ftx, &dmu, &ptrs,
                 &stage};
     }
@@ -105,6 +106,10 @@ struct Ctx {
     // host synchronisation (graph-capturable); overflow sets the status word.
     swf_status forward_lists(Workspace& w, int sid, const float* tx, int B, int flags, hipStream_t st,
                              uint64_t key_cap = 0);
+    swf_status key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64_t& nk, const uint64_t*& n_dev);
+    swf_status lists_binned(Workspace& w, const DevScene& d, int B, const Grid& g, hipStream_t st, uint64_t key_cap);
+    swf_status lists_sorted(Workspace& w, const DevScene& d, int B, const Grid& g, bool full, hipStream_t st,
+                            uint64_t key_cap);
     swf_status render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st,
                       uint64_t key_cap = 0);
     swf_status backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out,

@@ -96,13 +96,14 @@ void drop_graphs(Slot* s) {
 
 // Upper bound of a slot's workspace for (scene, bucket, key capacity): records
 // (52 B) + offsets (4 B) per pair, keys and values double-buffered (16 B per
-// key), tile ranges, output and TX, per-query MLP state, scan/sort scratch;
+// key), tile ranges, output and TX, per-query MLP state, binning histogram,
+// scan/sort scratch;
 // times the 1.25 growth factor of the buffers.
 uint64_t estimate_bytes(const DevScene& d, int bucket, uint64_t key_cap) {
     const uint64_t pairs = (uint64_t)bucket * d.n;
     const uint64_t tiles = (uint64_t)bucket * ((d.W + 15) / 16) * ((d.H + 15) / 16);
     const uint64_t raw = pairs * 56 + key_cap * 16 + tiles * 8 + (uint64_t)bucket * ((uint64_t)d.H * d.W * 4 + 1024) +
-                         (uint64_t)bucket * 256 * 4 + (1u << 20);
+                         (uint64_t)bucket * 256 * 4 + bin_hist_entries(bucket, d.n) * 4 + (1u << 20);
     return raw + raw / 4 + 64 * 256;
 }
 

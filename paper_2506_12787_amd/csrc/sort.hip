@@ -289,6 +289,154 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const K* __rest
     }
 }
 
+// ---- binning: per-query stable counting sort by tile -----------------------
+// Pairs are stored in (query, depth) order and a pair covers a tile at most
+// once, so the list of a tile is the pairs covering it in pair order. With at
+// most 256 tiles per query the tile index is one 8-bit digit: one counting
+// pass per query segment gives exactly the order of the full (tile, depth)
+// sort, without materialising keys in memory.
+//   bin_hist:    block (j, q) histograms the tiles covered by pairs
+//                [j * kBinPairs, (j + 1) * kBinPairs) of query q;
+//                hist[(q * 256 + tile) * nbq + j]
+//   scan:        one exclusive scan over that (query, tile, block) order gives
+//                every block's first output position per tile
+//   bin_scatter: the same block regenerates its keys in LDS (pair order) and
+//                writes each pair index to its position, ranked stably with
+//                the wave-ballot scheme of the radix scatter
+//   bin_ranges:  tile (q, t) spans [hist(q, t, 0), hist(q, t + 1, 0))
+constexpr int kBinPairs = 1024;
+
+__global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restrict__ rect,
+                                                            const uint32_t* __restrict__ count, int N, int TW,
+                                                            int nbq, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[kWaves][256];
+    for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    const int j = blockIdx.x, q = blockIdx.y;
+    const int p_beg = j * kBinPairs, p_end = min(p_beg + kBinPairs, N);
+    const size_t row0 = (size_t)q * N;
+    for (int p = p_beg + (int)threadIdx.x; p < p_end; p += kThreads) {
+        if (count[row0 + p] == 0) continue;
+        const uint2 r = rect[row0 + p];
+        const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&h[w][ty * TW + tx], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += kThreads) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) s += h[k][d];
+        hist[((size_t)q * 256 + d) * nbq + j] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __restrict__ rect,
+                                                               const uint32_t* __restrict__ count, int N, int TW,
+                                                               int nbq, const uint32_t* __restrict__ hs,
+                                                               const uint64_t* __restrict__ n_dev,
+                                                               uint32_t* __restrict__ vals) {
+    // fixed-capacity run that overflowed: nothing is placed (block-uniform)
+    if (n_dev && *n_dev == 0) return;
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t ttot[256];
+    __shared__ uint32_t lds[kWaves + 1];
+    __shared__ uint16_t kbuf[kTile];  // tile << 8 | pair within the 256-pair batch
+    const int w = threadIdx.x >> 6;
+    const int j = blockIdx.x, q = blockIdx.y;
+    const int p_beg = j * kBinPairs, p_end = min(p_beg + kBinPairs, N);
+    const size_t row0 = (size_t)q * N;
+    base[threadIdx.x] = hs[((size_t)q * 256 + threadIdx.x) * nbq + j];
+    for (int s0 = p_beg; s0 < p_end; s0 += kThreads) {
+        const int p = s0 + (int)threadIdx.x;
+        uint32_t c = 0;
+        uint2 r = make_uint2(0u, 0u);
+        if (p < p_end) {
+            c = count[row0 + p];
+            if (c) r = rect[row0 + p];
+        }
+        uint32_t K;
+        const uint32_t o = block_exclusive_scan<uint32_t>(c, lds, &K);  // synchronises
+        const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff;
+        const uint32_t wdt = (uint32_t)(tx1 - tx0 + 1);
+        for (uint32_t c0 = 0; c0 < K; c0 += kTile) {
+            for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wcnt[0][0])[i] = 0;
+            // this thread's keys with batch positions in [c0, c0 + kTile)
+            const int64_t m0 = (int64_t)c0 > (int64_t)o ? (int64_t)c0 - (int64_t)o : 0;
+            const int64_t m1 = min((int64_t)c, (int64_t)c0 + kTile - (int64_t)o);
+            for (int64_t m = m0; m < m1; ++m) {
+                const uint32_t tile = (ty0 + (uint32_t)m / wdt) * (uint32_t)TW + tx0 + (uint32_t)m % wdt;
+                kbuf[o + m - c0] = (uint16_t)((tile << 8) | threadIdx.x);
+            }
+            __syncthreads();
+            const uint32_t n_here = min(K - c0, (uint32_t)kTile);
+            uint32_t dig[kItems], lr[kItems], pl[kItems];
+            bool ok[kItems];
+#pragma unroll
+            for (int jj = 0; jj < kItems; ++jj) {
+                const uint32_t idx = (uint32_t)(w * kItems + jj) * 64 + lane_id();
+                ok[jj] = idx < n_here;
+                const uint32_t k = ok[jj] ? kbuf[idx] : 0u;
+                const uint32_t d = k >> 8;
+                dig[jj] = d;
+                pl[jj] = k & 255u;
+                uint64_t match = __ballot(ok[jj]);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t bal = __ballot(bit && ok[jj]);
+                    match &= bit ? bal : ~bal;
+                }
+                const uint32_t rank = (uint32_t)__popcll(match & lanemask_lt());
+                const uint32_t cnt = (uint32_t)__popcll(match);
+                uint32_t prev = 0;
+                if (ok[jj]) prev = wcnt[w][d];
+                lr[jj] = prev + rank;
+                __builtin_amdgcn_wave_barrier();
+                if (ok[jj] && rank == 0) wcnt[w][d] = prev + cnt;
+                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            {
+                const int d = threadIdx.x;  // one thread per digit
+                uint32_t run = 0;
+#pragma unroll
+                for (int k = 0; k < kWaves; ++k) {
+                    const uint32_t cc = wcnt[k][d];
+                    wcnt[k][d] = run;
+                    run += cc;
+                }
+                ttot[d] = run;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int jj = 0; jj < kItems; ++jj)
+                if (ok[jj]) vals[base[dig[jj]] + wcnt[w][dig[jj]] + lr[jj]] = (uint32_t)(row0 + s0 + pl[jj]);
+            __syncthreads();
+            base[threadIdx.x] += ttot[threadIdx.x];
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void bin_ranges_kernel(const uint32_t* __restrict__ hs, int B, int T, int nbq,
+                                  const uint64_t* __restrict__ total, const uint64_t* __restrict__ n_dev,
+                                  uint2* __restrict__ ranges) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)B * T) return;
+    if (n_dev && *n_dev == 0) {
+        ranges[i] = make_uint2(0u, 0u);
+        return;
+    }
+    const int64_t q = i / T, t = i - q * T;
+    const size_t e = (size_t)q * 256 + t;
+    const uint32_t a = hs[e * nbq];
+    const uint32_t b = e + 1 < (size_t)B * 256 ? hs[(e + 1) * nbq] : (uint32_t)*total;
+    ranges[i] = a < b ? make_uint2(a, b) : make_uint2(0u, 0u);
+}
+
 // ---- tile ranges -----------------------------------------------------------
 __global__ void zero_ranges_kernel(uint2* __restrict__ r, int64_t m) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -356,7 +504,7 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t* total, i
                            hipStream_t st) {
     uint64_t* sums = reinterpret_cast<uint64_t*>(scratch);
     if (n <= 0) {
-        hipMemsetAsync(total, 0, sizeof(uint64_t), st);
+        launch_clear_u32(reinterpret_cast<uint32_t*>(total), 2, st);  // kernel, not a memset node
         return;
     }
     const int G = scan_grid(n);
@@ -404,16 +552,19 @@ namespace {
 // Key count the sort may use after a fixed-capacity emission: the scan total
 // if it fits, else 0 (the emission skipped pairs, so the key array has holes;
 // the batch renders empty and the caller re-runs it with exact sizing).
-__global__ void effective_count_kernel(const uint64_t* __restrict__ total, uint64_t cap, uint64_t* __restrict__ n_eff) {
+// An overflow also sets bit 0 of the status word.
+__global__ void effective_count_kernel(const uint64_t* __restrict__ total, uint64_t cap, uint64_t* __restrict__ n_eff,
+                                       uint32_t* __restrict__ status) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const uint64_t t = *total;
         *n_eff = t <= cap ? t : 0ull;
+        if (t > cap && status) atomicOr(status, 1u);
     }
 }
 }  // namespace
 
-void launch_effective_count(const uint64_t* total, uint64_t cap, uint64_t* n_eff, hipStream_t st) {
-    effective_count_kernel<<<1, 64, 0, st>>>(total, cap, n_eff);
+void launch_effective_count(const uint64_t* total, uint64_t cap, uint64_t* n_eff, uint32_t* status, hipStream_t st) {
+    effective_count_kernel<<<1, 64, 0, st>>>(total, cap, n_eff, status);
 }
 
 void launch_clear_u32(uint32_t* p, int n, hipStream_t st) {
@@ -429,6 +580,35 @@ void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gt
         tile_ranges_kernel<true><<<blocks, 256, 0, st>>>(keys, n, ranges, n_dev);
     else
         tile_ranges_kernel<false><<<blocks, 256, 0, st>>>(keys, n, ranges, n_dev);
+}
+
+int bin_blocks_per_query(int N) { return std::max(1, (N + kBinPairs - 1) / kBinPairs); }
+
+size_t bin_hist_entries(int B, int N) { return (size_t)B * 256 * (size_t)bin_blocks_per_query(N); }
+
+void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hist, hipStream_t st) {
+    if (B <= 0) return;
+    const int nbq = bin_blocks_per_query(N);
+    if (N <= 0) {
+        launch_clear_u32(hist, (int)bin_hist_entries(B, N), st);
+        return;
+    }
+    bin_hist_kernel<<<dim3(nbq, B), kThreads, 0, st>>>(r.rect, r.count, N, g.TW, nbq, hist);
+}
+
+void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* hist_scanned,
+                        const uint64_t* n_dev, uint32_t* vals, hipStream_t st) {
+    if (B <= 0 || N <= 0) return;
+    const int nbq = bin_blocks_per_query(N);
+    bin_scatter_kernel<<<dim3(nbq, B), kThreads, 0, st>>>(r.rect, r.count, N, g.TW, nbq, hist_scanned, n_dev, vals);
+}
+
+void launch_bin_ranges(const uint32_t* hist_scanned, int B, int N, const Grid& g, const uint64_t* total,
+                       const uint64_t* n_dev, uint2* ranges, hipStream_t st) {
+    const int64_t m = (int64_t)B * g.tiles;
+    if (m <= 0) return;
+    bin_ranges_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(hist_scanned, B, g.tiles,
+                                                                    bin_blocks_per_query(N), total, n_dev, ranges);
 }
 
 }  // namespace swf
