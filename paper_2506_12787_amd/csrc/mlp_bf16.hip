@@ -76,13 +76,29 @@ __device__ __forceinline__ bf16x8 pack_relu(f32x4 lo, f32x4 hi) {
     return __builtin_bit_cast(bf16x8, u);
 }
 
+// One lane-contiguous 1 KiB piece per wave, global -> LDS without registers:
+// lane l's 16 bytes land at lds_addr + 16 l. Written as inline assembly so the
+// compiler does not treat every later LDS read as dependent on the copy (it
+// would wait for the copy right after issuing it); completion is awaited
+// explicitly with vmem_wait_all() before the barrier that publishes the slot.
+__device__ __forceinline__ void dma_b128(const uint4* src, uint32_t lds_addr) {
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(src)
+                 : "memory", "m0");
+}
+
+// s_waitcnt vmcnt(0): every vector memory operation of this wave has completed.
+__device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // NCB column blocks of 16 pairs per wave (64 or 32 pairs); 4 waves per block.
 //
 // Weight ring: kSlots LDS slots of one 32 KiB step each. The step q + 2 is
 // copied global -> LDS directly (global_load_lds, no registers) at the start of
-// step q into the slot read during step q - 1; the barrier ending step q waits
-// for it (its workgroup fence drains the vector memory counter). Fragment reads
-// run two fragments ahead, into the next slot past the end of a step.
+// step q into the slot read during step q - 1; each wave waits for its copies
+// before the barrier ending step q, so the slot is complete from step q + 1 on.
+// Fragment reads run two fragments ahead, into the next slot past the end of a
+// step.
 //
 // Hidden layers run output-tile-major: tile t (16 features) accumulates its
 // 8 k-chunks, so accumulator pairs (2c', 2c'+1) are final early and their ReLU
@@ -120,15 +136,17 @@ mlp_bf16_kernel(Bf16Args a) {
     qs_s[0][tid] = a.m.qs[(size_t)((int)blockIdx.x / a.tiles_per_query) * 256 + tid];
 
     int fetch = 0;  // stream step of the next copy
+    const uint32_t ring_lds = (uint32_t)(uintptr_t)(lds_ptr)ring;  // LDS byte address of the ring
 #define SWF_DMA(slot_)                                                                                     \
     do {                                                                                                   \
         const uint4* src_ = a.stream + (size_t)fetch * kChunkU4 + tid;                                     \
-        _Pragma("unroll") for (int i_ = 0; i_ < kPF; ++i_) __builtin_amdgcn_global_load_lds(              \
-            src_ + i_ * 256, (lds_ptr)(ring + (slot_) * kChunkU4 + i_ * 256 + wave * 64), 16, 0, 0);       \
+        const uint32_t dst_ = ring_lds + (uint32_t)((slot_) * kChunkBytes + wave * 1024);                  \
+        _Pragma("unroll") for (int i_ = 0; i_ < kPF; ++i_) dma_b128(src_ + i_ * 256, dst_ + i_ * 4096);   \
         fetch = fetch + 1 == S ? 0 : fetch + 1;                                                            \
     } while (0)
     SWF_DMA(0);
     if (q_end > 1) SWF_DMA(1);
+    vmem_wait_all();
     __syncthreads();
     int q = 0;     // step being computed
     int slot = 0;  // q % 3
@@ -147,6 +165,7 @@ mlp_bf16_kernel(Bf16Args a) {
     } while (0)
 #define SWF_NEXT_STEP()                  \
     do {                                 \
+        vmem_wait_all();                 \
         __syncthreads();                 \
         ++q;                             \
         slot = slot == 2 ? 0 : slot + 1; \
