@@ -46,7 +46,7 @@ def parse():
     p.add_argument("--width", type=int, default=360)
     p.add_argument("--mlp", choices=("bf16", "fp32"), default="bf16")
     p.add_argument("--plain-queries", type=int, default=16)
-    p.add_argument("--pairs-per-wave", type=int, default=0, help="BF16 MLP register tile (64 or 32)")
+    p.add_argument("--pairs-per-wave", type=int, default=0, help="BF16 MLP pairs per wave (32, the default, or 64)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--quick", action="store_true", help="timed steps only (for profiler runs)")
@@ -72,7 +72,7 @@ def mlp_sources_hash():
 
 
 def workload_key(a):
-    ppw = a.pairs_per_wave or 64
+    ppw = a.pairs_per_wave or 32
     return f"n{a.n}_h{a.height}_w{a.width}_b{a.batch}_{a.mlp}_ppw{ppw}"
 
 

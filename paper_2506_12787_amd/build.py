@@ -27,9 +27,17 @@ CFLAGS = [
 ]
 
 
+# Per-file code generation options. The BF16 MLP keeps its MFMA accumulators in
+# VGPRs: the ReLU/convert of finished tiles then reads them directly instead of
+# copying each accumulator out of the AGPR file first.
+FILE_FLAGS = {
+    "mlp_bf16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = ["hipcc", *CFLAGS, "-x", "hip", "-c", src, "-o", obj]
+    cmd = ["hipcc", *CFLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

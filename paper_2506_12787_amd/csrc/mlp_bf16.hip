@@ -12,11 +12,13 @@
 // f(g, j) = j < 4 ? 4g + j : 16 + 4g + (j - 4). Activations never leave the
 // registers between layers.
 //
-// Each wave owns 64 pairs (4 column blocks of 16); a workgroup of 4 waves owns
-// 256. Weight fragments (1 KiB each: 64 lanes x 8 bf16, in lane order) are
-// streamed from a packed global buffer through a 3-slot LDS ring of 16 KiB
-// chunks with one barrier per chunk; the workgroups are persistent so the
-// weight stream never drains between tiles.
+// A workgroup owns 256 pairs: 8 waves of 32 pairs (2 column blocks of 16, two
+// waves per SIMD; the default) or 4 waves of 64 pairs (one wave per SIMD, each
+// weight fragment read from LDS feeds twice the MFMAs). Weight fragments (1 KiB
+// each: 64 lanes x 8 bf16, in lane order) are streamed from a packed global
+// buffer through a 3-slot LDS ring of 32 KiB steps with one barrier per step;
+// the workgroups are persistent so the weight stream never drains between
+// tiles.
 #include "kernels.h"
 #include "mlp_common.h"
 #include "swf_device.h"
@@ -91,7 +93,9 @@ __device__ __forceinline__ void dma_b128(const uint4* src, uint32_t lds_addr) {
 // s_waitcnt vmcnt(0): every vector memory operation of this wave has completed.
 __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// NCB column blocks of 16 pairs per wave (64 or 32 pairs); 4 waves per block.
+// NCB column blocks of 16 pairs per wave (64 or 32 pairs); WAVES waves per
+// block, so that a block always covers 256 pairs: 4 waves of 64 pairs (one
+// wave per SIMD) or 8 waves of 32 pairs (two per SIMD, half the registers).
 //
 // Weight ring: kSlots LDS slots of one 32 KiB step each. The step q + 2 is
 // copied global -> LDS directly (global_load_lds, no registers) at the start of
@@ -105,14 +109,15 @@ __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0
 // + bf16 conversion into the next layer's act[c'] is issued among the MFMAs of
 // the following tile (one column block per two fragments) instead of after
 // the layer; the last pair is converted during the next layer's first tile.
-template <int NCB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void
+template <int NCB, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4))) void
 mlp_bf16_kernel(Bf16Args a) {
     typedef __attribute__((address_space(3))) void* lds_ptr;
     constexpr int kPairsPerWave = 16 * NCB;
-    constexpr int kPairsPerBlock = 4 * kPairsPerWave;
+    constexpr int kPairsPerBlock = WAVES * kPairsPerWave;
+    static_assert(kPairsPerBlock == 256, "a block covers 256 pairs");
     __shared__ __attribute__((aligned(16))) uint4 ring[kSlots * kChunkU4];
-    __shared__ float outs[4][kPairsPerWave][8];
+    __shared__ float outs[WAVES][kPairsPerWave][8];
     // Layer-1 TX term of the current and the next tile's query, hidden and
     // output biases: C operands read from LDS.
     __shared__ __attribute__((aligned(16))) float qs_s[2][256];
@@ -131,9 +136,11 @@ mlp_bf16_kernel(Bf16Args a) {
     const int my_tiles = a.n_tiles > (int)blockIdx.x ? (a.n_tiles - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
     if (my_tiles == 0) return;
     const int q_end = my_tiles * S;  // ring steps of this workgroup
-    for (int l = 0; l < n_mid; ++l) bias_s[l][tid] = a.bias_h[l][tid];
-    if (tid < 16) bias_o_s[tid] = tid < kOut ? a.bias_o[tid] : 0.0f;
-    qs_s[0][tid] = a.m.qs[(size_t)((int)blockIdx.x / a.tiles_per_query) * 256 + tid];
+    if (tid < 256) {
+        for (int l = 0; l < n_mid; ++l) bias_s[l][tid] = a.bias_h[l][tid];
+        if (tid < 16) bias_o_s[tid] = tid < kOut ? a.bias_o[tid] : 0.0f;
+        qs_s[0][tid] = a.m.qs[(size_t)((int)blockIdx.x / a.tiles_per_query) * 256 + tid];
+    }
 
     int fetch = 0;  // stream step of the next copy
     const uint32_t ring_lds = (uint32_t)(uintptr_t)(lds_ptr)ring;  // LDS byte address of the ring
@@ -141,7 +148,8 @@ mlp_bf16_kernel(Bf16Args a) {
     do {                                                                                                   \
         const uint4* src_ = a.stream + (size_t)fetch * kChunkU4 + tid;                                     \
         const uint32_t dst_ = ring_lds + (uint32_t)((slot_) * kChunkBytes + wave * 1024);                  \
-        _Pragma("unroll") for (int i_ = 0; i_ < kPF; ++i_) dma_b128(src_ + i_ * 256, dst_ + i_ * 4096);   \
+        _Pragma("unroll") for (int i_ = 0; i_ < 32 / WAVES; ++i_)                                          \
+            dma_b128(src_ + i_ * 64 * WAVES, dst_ + i_ * 1024 * WAVES);                                    \
         fetch = fetch + 1 == S ? 0 : fetch + 1;                                                            \
     } while (0)
     SWF_DMA(0);
@@ -271,7 +279,7 @@ mlp_bf16_kernel(Bf16Args a) {
         // last barrier (the other buffer is read by this tile's layer 1 only)
         const int next_tile = tile + (int)gridDim.x;
         const float qs_next =
-            it + 1 < my_tiles ? a.m.qs[(size_t)(next_tile / a.tiles_per_query) * 256 + tid] : 0.0f;
+            it + 1 < my_tiles && tid < 256 ? a.m.qs[(size_t)(next_tile / a.tiles_per_query) * 256 + tid] : 0.0f;
         // ---- hidden layers, two per iteration so the act buffers alternate statically ----
         int l = 0;
         for (; l + 1 < n_mid; l += 2) {
@@ -284,7 +292,7 @@ mlp_bf16_kernel(Bf16Args a) {
         } else {
             SWF_OUTPUT(0);
         }
-        qs_s[(it + 1) & 1][tid] = qs_next;
+        if (tid < 256) qs_s[(it + 1) & 1][tid] = qs_next;
         SWF_NEXT_STEP();
         if (lane < kPairsPerWave) {
             const int p = p0 + lane;
@@ -335,8 +343,8 @@ void compute_mean_features_bf16(DevScene& s, hipStream_t st) {
 // the grid is persistent, so launching more would only queue them).
 int occupancy_query(int ncb) {
     int n = 0;
-    const hipError_t e = ncb == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mlp_bf16_kernel<2>, 256, 0)
-                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mlp_bf16_kernel<4>, 256, 0);
+    const hipError_t e = ncb == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mlp_bf16_kernel<2, 8>, 512, 0)
+                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mlp_bf16_kernel<4, 4>, 256, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
@@ -355,16 +363,16 @@ void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, b
     a.mfeat = reinterpret_cast<const bf16x8*>(s.bf_mfeat);
     for (int l = 0; l + 1 < s.n_hidden && l < 7; ++l) a.bias_h[l] = s.b[l + 1];
     a.bias_o = s.b[s.n_hidden];
-    const int ncb = pairs_per_wave == 32 ? 2 : 4;
-    const int per_block = 64 * ncb;
+    const int ncb = pairs_per_wave == 64 ? 4 : 2;  // default: 32 pairs per wave
+    const int per_block = 256;  // pairs per block for both variants
     a.tiles_per_query = (s.n + per_block - 1) / per_block;
     a.n_tiles = a.tiles_per_query * B;
     if (!a.n_tiles) return;
     const int blocks = std::min(a.n_tiles, n_compute_units() * resident_blocks(ncb));
     if (ncb == 2)
-        mlp_bf16_kernel<2><<<blocks, 256, 0, st>>>(a);
+        mlp_bf16_kernel<2, 8><<<blocks, 512, 0, st>>>(a);
     else
-        mlp_bf16_kernel<4><<<blocks, 256, 0, st>>>(a);
+        mlp_bf16_kernel<4, 4><<<blocks, 256, 0, st>>>(a);
 }
 
 }  // namespace swf
