@@ -27,6 +27,13 @@ sys.path.insert(0, ROOT)
 METRIC = "spectra/s at N=100k, 90x360 (batched vs plain); p50/p99 query latency us"
 FLOP_PER_PAIR = 2 * (26 * 256 + 3 * 256 * 256 + 256 * 7)  # MLP per (query, Gaussian) pair
 PEAK = {"bf16": 2500.0, "fp32": 157.3}  # dense TFLOP/s (MFMA bf16; fp32 vector incl. packed)
+HBM_PEAK_GBS = 8000.0
+# FP32 lane-operations per second without FMA doubling or packing: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# VALU lane-op slots per (pixel, list entry) evaluation of the blend: 2 sub, 4 mul/fma (whitened offset), 2 (q),
+# 1 compare, 1 mul + v_exp_f32 at quarter rate (4), 1 mul, 1 min, 1 compare, 2 (1 - a, T'), 1 compare, 2 (C), 1
+# (index) ~ 20
+BLEND_OPS_PER_EVAL = 20
 # MLP kernel HBM bytes per pair that the algorithm needs: BF16 gamma(mu) (64 B) and 7 FP32 scene parameters (28 B)
 # read, one 52 B pair record written; the weight stream is per tile and L2-resident.
 MLP_ALGO_BYTES_PER_PAIR = 64 + 28 + 52
@@ -331,6 +338,35 @@ def main():
                 "algorithmic_bytes_per_launch": MLP_ALGO_BYTES_PER_PAIR * N * Bq,
                 "avg_launch_ms": avg_mlp_ms, "flop_per_launch": flops}
 
+    # per-stage rooflines of the list building and the blend, from the last timed batch's work counts
+    work = ctx.blend_work()
+    st_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+    T_tiles = -(-a.width // 16) * -(-a.height // 16)
+    binned = T_tiles <= 256
+    pairs = N * Bq
+    if binned:
+        hist_entries = Bq * 256 * -(-N // 1024)
+        bin_bytes = pairs * 24 + work["entries"] * 4 + hist_entries * 12 + Bq * T_tiles * 8
+        bin_ms = st_ms["scan"] + st_ms["radix_sort"] + st_ms["tile_ranges"]
+        bin_note = ("binning: rect+count read twice (24 B/pair), 4 B/list entry written, histogram scan 12 B/entry, "
+                    "ranges 8 B/tile")
+    else:
+        bin_bytes = pairs * 12 + work["entries"] * (8 + 20 + 4) + pairs * 20
+        bin_ms = st_ms["scan"] + st_ms["emit_keys"] + st_ms["radix_sort"] + st_ms["tile_ranges"]
+        bin_note = "emit + radix sort + ranges (per-pass traffic not itemised)"
+    blend_ms = st_ms["blend"]
+    stage_rooflines = {
+        "lists": {"bound": "hbm", "achieved": bin_bytes / (bin_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": bin_bytes / (bin_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "algorithmic_bytes": bin_bytes, "ms": bin_ms, "list_entries": work["entries"], "note": bin_note},
+        "blend": {"bound": "alu", "achieved": work["evaluations"] * BLEND_OPS_PER_EVAL / (blend_ms * 1e-3) / 1e12,
+                  "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+                  "frac": work["evaluations"] * BLEND_OPS_PER_EVAL / (blend_ms * 1e-3) / VALU_PEAK_LANE_OPS,
+                  "evaluations": work["evaluations"], "ops_per_evaluation": BLEND_OPS_PER_EVAL, "ms": blend_ms,
+                  "staged_records": work["staged"],
+                  "gather_GBs": work["staged"] * 44 / (blend_ms * 1e-3) / 1e9},
+    }
+
     rec = {
         "metric": METRIC, "value": value, "unit": "spectra/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -342,6 +378,7 @@ def main():
                        "note": "closed-loop: every query of a batch completes with its batch"},
         "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "roofline": roofline,
+        "stage_rooflines": stage_rooflines,
     }
     if a.copy_probe_mib:
         src = torch.ones(a.copy_probe_mib * 2 ** 18, device="cuda", dtype=torch.float32)

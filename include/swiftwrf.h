@@ -203,6 +203,13 @@ swf_status swf_debug_deform(swf_ctx *ctx, int32_t scene_id, const float *tx, int
                             float *delta, void *stream);
 swf_status swf_debug_keys(swf_ctx *ctx, uint32_t *counts, uint32_t *offsets, uint64_t *keys, uint64_t *values,
                           uint32_t *ranges, uint64_t *n_keys, uint64_t capacity);
+/* swf_debug_blend_work: the work of the last swf_render's blend stage (Sec. 3.2
+ * front-to-back rule), for roofline accounting: re-walks the same tile lists
+ * without writing a spectrum and returns, in host memory, the number of (pixel,
+ * list entry) evaluations (entries a pixel examines up to and including the one
+ * that ends it), the number of records staged into LDS, and the number of list
+ * entries. Synchronous; any output may be NULL. */
+swf_status swf_debug_blend_work(swf_ctx *ctx, uint64_t *evaluations, uint64_t *staged, uint64_t *n_entries);
 
 /* Stable LSD radix sort of n (key, value) pairs in place, device memory, on
  * the key bits [begin_bit, end_bit). key_bytes is 4 (uint32 keys) or 8 (uint64

@@ -94,6 +94,7 @@ def lib():
             "swf_stage_times": [P, P, P, P],
             "swf_debug_deform": [P, I32, P, I32, I32, P, P],
             "swf_debug_keys": [P, P, P, P, P, P, P, ctypes.c_uint64],
+            "swf_debug_blend_work": [P, P, P, P],
             "swf_radix_sort": [P, P, P, I64, I32, I32, I32, P],
             "swf_exclusive_scan": [P, P, P, P, I64, P],
             "swf_serve_start": [P, P],
@@ -300,6 +301,12 @@ class Context:
         self._check(self._L.swf_debug_keys(self._h, P(counts), P(offsets), P(keys), P(vals), P(ranges),
                                            ctypes.byref(nk), nkeys))
         return dict(counts=counts, offsets=offsets, keys=keys[:nkeys], values=vals[:nkeys], ranges=ranges)
+
+    def blend_work(self):
+        """Work of the last render's blend: (pixel, entry) evaluations, staged records, list entries."""
+        ev, st, ne = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._L.swf_debug_blend_work(self._h, ctypes.byref(ev), ctypes.byref(st), ctypes.byref(ne)))
+        return dict(evaluations=ev.value, staged=st.value, entries=ne.value)
 
     def radix_sort(self, keys, values, begin_bit=0, end_bit=None):
         kb = keys.element_size()

@@ -14,7 +14,10 @@ namespace swf {
 
 namespace {
 
-template <int TILE>
+// kCount: instead of writing the spectrum, add to work[0] the number of (pixel,
+// list entry) evaluations (every entry a pixel examines up to and including the
+// one that ends it) and to work[1] the number of records staged in LDS.
+template <int TILE, bool kCount = false>
 __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ vals,
                                                                     const float4* __restrict__ geo,
@@ -22,7 +25,8 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
                                                                     const float2* __restrict__ oa, int H, int W,
                                                                     int TW, int tiles, float* __restrict__ out,
                                                                     float* __restrict__ aux_T,
-                                                                    uint32_t* __restrict__ aux_last) {
+                                                                    uint32_t* __restrict__ aux_last,
+                                                                    unsigned long long* __restrict__ work = nullptr) {
     constexpr int kN = TILE * TILE;
     __shared__ float2 s_pos[kN];
     __shared__ float4 s_wm[kN];
@@ -45,6 +49,7 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     float T = 1.0f, C = 0.0f;
     uint32_t last = 0;
     bool done = !inside;
+    uint32_t evals = 0, staged = 0;
 
     for (uint32_t start = rg.x; start < rg.y; start += kN) {
         if (__syncthreads_count(done) == kN) break;
@@ -58,8 +63,10 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)kN, rg.y - start);
+        if (kCount) staged += (uint32_t)cnt;
         if (!done) {
             for (int j = 0; j < cnt; ++j) {
+                if (kCount) ++evals;
                 float dx, dy, u, w;
                 const float q = blend_q(fx, fy, s_pos[j], s_wm[j], dx, dy, u, w);
                 if (q > kQMax) continue;
@@ -77,6 +84,18 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
             }
         }
     }
+    if (kCount) {
+        __shared__ unsigned long long s_ev;
+        if (threadIdx.x == 0) s_ev = 0;
+        __syncthreads();
+        atomicAdd(&s_ev, (unsigned long long)evals);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            atomicAdd(&work[0], s_ev);
+            atomicAdd(&work[1], (unsigned long long)staged);
+        }
+        return;
+    }
     if (inside) {
         const size_t pix = (size_t)b * H * W + (size_t)py * W + px;
         out[pix] = C;
@@ -88,6 +107,18 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
 }
 
 }  // namespace
+
+void launch_blend_work(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
+                       unsigned long long* work, hipStream_t st) {
+    const unsigned blocks = (unsigned)(B * g.tiles);
+    if (!blocks) return;
+    if (g.tile == 8)
+        blend_forward_kernel<8, true><<<blocks, 64, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW,
+                                                             g.tiles, nullptr, nullptr, nullptr, work);
+    else
+        blend_forward_kernel<16, true><<<blocks, 256, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW,
+                                                               g.tiles, nullptr, nullptr, nullptr, work);
+}
 
 void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
                           float* out, float* aux_T, uint32_t* aux_last, hipStream_t st) {

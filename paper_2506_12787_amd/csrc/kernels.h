@@ -108,5 +108,8 @@ void launch_mean_features_f32(const DevScene& s, float* out, hipStream_t st);
 // blend.hip
 void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
                           float* out, float* aux_T, uint32_t* aux_last, hipStream_t st);
+// work[0] += (pixel, entry) evaluations, work[1] += records staged (counting run, no output)
+void launch_blend_work(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
+                       unsigned long long* work, hipStream_t st);
 
 }  // namespace swf

@@ -810,6 +810,26 @@ swf_status swf_debug_keys(swf_ctx* h, uint32_t* counts, uint32_t* offsets, uint6
     return SWF_OK;
 }
 
+swf_status swf_debug_blend_work(swf_ctx* h, uint64_t* evaluations, uint64_t* staged, uint64_t* n_entries) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    if (!c->ws.last.valid) return c->fail(SWF_E_STATE, "no render to inspect");
+    if (!c->scene(c->ws.last.scene)) return c->fail(SWF_E_STATE, "scene of the last render was released");
+    const auto& L = c->ws.last;
+    if (n_entries) *n_entries = L.n_keys;
+    swf_status s = c->hip(hipDeviceSynchronize(), "sync");
+    if (s) return s;
+    if ((s = c->ws.work.reserve(c, 2 * sizeof(unsigned long long), nullptr))) return s;
+    unsigned long long* d = (unsigned long long*)c->ws.work.ptr;
+    launch_clear_u32((uint32_t*)d, 4, nullptr);
+    launch_blend_work((const uint2*)c->ws.ranges.ptr, L.vals, c->ws.rec, L.B, L.grid, d, nullptr);
+    unsigned long long hw[2] = {0, 0};
+    if ((s = c->hip(hipMemcpy(hw, d, sizeof(hw), hipMemcpyDeviceToHost), "D2H work"))) return s;
+    if (evaluations) *evaluations = hw[0];
+    if (staged) *staged = hw[1];
+    return SWF_OK;
+}
+
 swf_status swf_radix_sort(swf_ctx* h, void* keys, uint32_t* values, int64_t n, int32_t key_bytes, int32_t begin_bit,
                           int32_t end_bit, void* stream) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
