@@ -28,6 +28,7 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
                                                                     uint32_t* __restrict__ aux_last,
                                                                     unsigned long long* __restrict__ work = nullptr) {
     constexpr int kN = TILE * TILE;
+    constexpr int kUnroll = 8;  // entries per unrolled group (kN is a multiple)
     __shared__ float2 s_pos[kN];
     __shared__ float4 s_wm[kN];
     __shared__ float2 s_oa[kN];
@@ -54,33 +55,46 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     for (uint32_t start = rg.x; start < rg.y; start += kN) {
         if (__syncthreads_count(done) == kN) break;
         const uint32_t i = start + threadIdx.x;
+        const int cnt = (int)min((uint32_t)kN, rg.y - start);
         if (i < rg.y) {
             const uint32_t v = vals[i];
             const float4 g = geo[v];
             s_pos[threadIdx.x] = make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
             s_wm[threadIdx.x] = wm[v];
             s_oa[threadIdx.x] = oa[v];
+        } else if ((int)threadIdx.x < ((cnt + kUnroll - 1) & ~(kUnroll - 1))) {
+            // padding up to the unrolled length: opacity 0 never contributes
+            s_pos[threadIdx.x] = make_float2(0.0f, 0.0f);
+            s_wm[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            s_oa[threadIdx.x] = make_float2(0.0f, 0.0f);
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)kN, rg.y - start);
         if (kCount) staged += (uint32_t)cnt;
-        if (!done) {
-            for (int j = 0; j < cnt; ++j) {
-                if (kCount) ++evals;
+        const uint32_t base = start - rg.x + 1u;  // 1-based list position of entry 0 of the batch
+        // Branch-free walk: every lane evaluates every entry and commits it only
+        // if it passes the cutoff, the alpha skip and the termination test. The
+        // committed arithmetic is exactly the rule's; what is skipped is the
+        // per-entry divergent control flow (scalar exec-mask work that would
+        // otherwise outweigh the vector work). A wave leaves the batch once all
+        // its pixels are done.
+        for (int j0 = 0; j0 < cnt; j0 += kUnroll) {
+            if (__all(done)) break;
+#pragma unroll
+            for (int jj = 0; jj < kUnroll; ++jj) {
+                const int j = j0 + jj;
                 float dx, dy, u, w;
                 const float q = blend_q(fx, fy, s_pos[j], s_wm[j], dx, dy, u, w);
-                if (q > kQMax) continue;
                 const float2 o = s_oa[j];
                 const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
-                if (a < kAlphaMin) continue;
+                const bool use = !done && q <= kQMax && a >= kAlphaMin;
                 const float Tn = T * (1.0f - a);
-                if (Tn < kTMin) {
-                    done = true;
-                    break;
-                }
-                C = fmaf(o.y * a, T, C);
-                T = Tn;
-                last = start + (uint32_t)j + 1u - rg.x;
+                const bool stop = use && Tn < kTMin;
+                const bool take = use && !stop;
+                if (kCount) evals += (!done && j < cnt) ? 1u : 0u;
+                C = take ? fmaf(o.y * a, T, C) : C;
+                T = take ? Tn : T;
+                last = take ? base + (uint32_t)j : last;
+                done = done || stop;
             }
         }
     }
