@@ -14,10 +14,13 @@ namespace swf {
 
 namespace {
 
+__device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
+
 // kCount: instead of writing the spectrum, add to work[0] the number of (pixel,
-// list entry) evaluations (every entry a pixel examines up to and including the
-// one that ends it) and to work[1] the number of records staged in LDS.
-template <int TILE, bool kCount = false>
+// list entry) evaluations (every entry of the pixel's tile list up to and
+// including the one that ends it, whether or not a wave skips it by the row
+// test below) and to work[1] the number of records staged in LDS.
+template <int TILE, bool kCount = false, bool kAux = true>
 __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ vals,
                                                                     const float4* __restrict__ geo,
@@ -29,9 +32,24 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
                                                                     unsigned long long* __restrict__ work = nullptr) {
     constexpr int kN = TILE * TILE;
     constexpr int kUnroll = 8;  // entries per unrolled group (kN is a multiple)
-    __shared__ float2 s_pos[kN];
-    __shared__ float4 s_wm[kN];
-    __shared__ float2 s_oa[kN];
+    static_assert(kN % 64 == 0, "whole waves per tile");
+    // entry kN is a never-contributing dummy (opacity 0) used as padding
+    __shared__ float2 s_pos[kN + 1];
+    __shared__ float4 s_wm[kN + 1];
+    __shared__ float2 s_oa[kN + 1];
+    // 16x16 tiles: bit w of s_strip[j] is set if entry j's 3-sigma band in y
+    // (with a margin) meets the 4 pixel rows of wave w; each wave walks only
+    // those entries (the others fail the cutoff at every one of its pixels),
+    // from its own compacted list s_idx[w] padded with the dummy.
+    constexpr bool kCull = TILE == 16 && !kCount;
+    constexpr int kWaves = kN / 64;
+    __shared__ uint8_t s_strip[kCull ? kN : 1];
+    __shared__ __attribute__((aligned(16))) uint16_t s_idx[kCull ? kWaves : 1][kN + kUnroll];
+    if (threadIdx.x == 0) {
+        s_pos[kN] = make_float2(0.0f, 0.0f);
+        s_wm[kN] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        s_oa[kN] = make_float2(0.0f, 0.0f);
+    }
 
     const int gtile = blockIdx.x;
     const int b = gtile / tiles;
@@ -59,9 +77,22 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
         if (i < rg.y) {
             const uint32_t v = vals[i];
             const float4 g = geo[v];
-            s_pos[threadIdx.x] = make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
-            s_wm[threadIdx.x] = wm[v];
+            const float2 pos = make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
+            const float4 m = wm[v];
+            s_pos[threadIdx.x] = pos;
+            s_wm[threadIdx.x] = m;
             s_oa[threadIdx.x] = oa[v];
+            if (kCull) {
+                // Sigma = (M^T M)^-1, so Sigma_yy = (m00^2 + m10^2) / det(M)^2
+                const float det = fabsf(m.x * m.w - m.y * m.z);
+                const float hy = 3.0f * sqrtf(m.x * m.x + m.z * m.z) / det * 1.001f + 0.01f;
+                const float r0 = (float)(ty * TILE - by0);  // first row of the tile, block-relative
+                uint32_t bits = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    bits |= (pos.y + hy >= r0 + 4.0f * k && pos.y - hy <= r0 + 4.0f * k + 3.0f) ? 1u << k : 0u;
+                s_strip[threadIdx.x] = (uint8_t)bits;
+            }
         } else if ((int)threadIdx.x < ((cnt + kUnroll - 1) & ~(kUnroll - 1))) {
             // padding up to the unrolled length: opacity 0 never contributes
             s_pos[threadIdx.x] = make_float2(0.0f, 0.0f);
@@ -71,30 +102,69 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
         __syncthreads();
         if (kCount) staged += (uint32_t)cnt;
         const uint32_t base = start - rg.x + 1u;  // 1-based list position of entry 0 of the batch
-        // Branch-free walk: every lane evaluates every entry and commits it only
-        // if it passes the cutoff, the alpha skip and the termination test. The
-        // committed arithmetic is exactly the rule's; what is skipped is the
-        // per-entry divergent control flow (scalar exec-mask work that would
-        // otherwise outweigh the vector work). A wave leaves the batch once all
-        // its pixels are done.
-        for (int j0 = 0; j0 < cnt; j0 += kUnroll) {
-            if (__all(done)) break;
+        // Branch-free walk: every lane evaluates each entry its wave visits and
+        // commits it only if it passes the cutoff, the alpha skip and the
+        // termination test. The committed arithmetic is exactly the rule's; what
+        // is avoided is per-entry divergent control flow (scalar exec-mask work
+        // that would otherwise outweigh the vector work). With 16x16 tiles a
+        // wave visits only the entries whose band meets its rows (the set bits of
+        // a ballot, in list order). A wave leaves the batch once all its pixels
+        // are done.
+        if (kCull) {
+            const int wv = threadIdx.x >> 6;
+            uint16_t* idx = s_idx[wv];
+            int nlist = 0;
 #pragma unroll
-            for (int jj = 0; jj < kUnroll; ++jj) {
-                const int j = j0 + jj;
-                float dx, dy, u, w;
-                const float q = blend_q(fx, fy, s_pos[j], s_wm[j], dx, dy, u, w);
-                const float2 o = s_oa[j];
-                const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
-                const bool use = !done && q <= kQMax && a >= kAlphaMin;
-                const float Tn = T * (1.0f - a);
-                const bool stop = use && Tn < kTMin;
-                const bool take = use && !stop;
-                if (kCount) evals += (!done && j < cnt) ? 1u : 0u;
-                C = take ? fmaf(o.y * a, T, C) : C;
-                T = take ? Tn : T;
-                last = take ? base + (uint32_t)j : last;
-                done = done || stop;
+            for (int c = 0; c < kWaves; ++c) {
+                const int jl = c * 64 + (int)lane_id();
+                const bool f = jl < cnt && ((s_strip[jl] >> wv) & 1u);
+                const uint64_t bal = __ballot(f);
+                if (f) idx[nlist + __popcll(bal & ((1ull << lane_id()) - 1ull))] = (uint16_t)jl;
+                nlist += __popcll(bal);
+            }
+            if ((int)lane_id() < kUnroll) idx[nlist + lane_id()] = (uint16_t)kN;  // padding
+            __builtin_amdgcn_wave_barrier();
+            for (int j0 = 0; j0 < nlist; j0 += kUnroll) {
+                if (__all(done)) break;
+                const uint4 jv = *reinterpret_cast<const uint4*>(idx + j0);  // 8 entry indices
+                const uint32_t jw[4] = {jv.x, jv.y, jv.z, jv.w};
+#pragma unroll
+                for (int jj = 0; jj < kUnroll; ++jj) {
+                    const int j = (int)((jw[jj >> 1] >> (16 * (jj & 1))) & 0xffffu);
+                    float dx, dy, u, w;
+                    const float q = blend_q(fx, fy, s_pos[j], s_wm[j], dx, dy, u, w);
+                    const float2 o = s_oa[j];
+                    const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
+                    const float ae = (!done && q <= kQMax && a >= kAlphaMin) ? a : 0.0f;
+                    const float Tn = T * (1.0f - ae);
+                    const bool stop = Tn < kTMin;
+                    C = stop ? C : fmaf(o.y * ae, T, C);
+                    if (kAux) last = (!stop && ae > 0.0f) ? base + (uint32_t)j : last;
+                    T = stop ? T : Tn;
+                    done = done || stop;
+                }
+            }
+        } else {
+            for (int j0 = 0; j0 < cnt; j0 += kUnroll) {
+                if (__all(done)) break;
+#pragma unroll
+                for (int jj = 0; jj < kUnroll; ++jj) {
+                    const int j = j0 + jj;
+                    if (kCount) evals += (!done && j < cnt) ? 1u : 0u;
+                    float dx, dy, u, w;
+                    const float q = blend_q(fx, fy, s_pos[j], s_wm[j], dx, dy, u, w);
+                    const float2 o = s_oa[j];
+                    const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
+                    // a skipped entry (cutoff, alpha floor, or a finished pixel) acts
+                    // with alpha 0: T * (1 - 0) and C + 0 * T are exact no-ops
+                    const float ae = (!done && q <= kQMax && a >= kAlphaMin) ? a : 0.0f;
+                    const float Tn = T * (1.0f - ae);
+                    const bool stop = Tn < kTMin;  // only reachable through ae > 0
+                    C = stop ? C : fmaf(o.y * ae, T, C);
+                    if (kAux) last = (!stop && ae > 0.0f) ? base + (uint32_t)j : last;
+                    T = stop ? T : Tn;
+                    done = done || stop;
+                }
             }
         }
     }
@@ -113,7 +183,7 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     if (inside) {
         const size_t pix = (size_t)b * H * W + (size_t)py * W + px;
         out[pix] = C;
-        if (aux_T) {
+        if (kAux) {
             aux_T[pix] = T;
             aux_last[pix] = last;
         }
@@ -138,12 +208,22 @@ void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Recor
                           float* out, float* aux_T, uint32_t* aux_last, hipStream_t st) {
     const unsigned blocks = (unsigned)(B * g.tiles);
     if (!blocks) return;
-    if (g.tile == 8)
-        blend_forward_kernel<8><<<blocks, 64, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles, out,
-                                                       aux_T, aux_last);
-    else
-        blend_forward_kernel<16><<<blocks, 256, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles,
-                                                         out, aux_T, aux_last);
+    const bool aux = aux_T != nullptr;
+    if (g.tile == 8) {
+        if (aux)
+            blend_forward_kernel<8, false, true><<<blocks, 64, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W,
+                                                                        g.TW, g.tiles, out, aux_T, aux_last);
+        else
+            blend_forward_kernel<8, false, false><<<blocks, 64, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W,
+                                                                         g.TW, g.tiles, out, nullptr, nullptr);
+    } else {
+        if (aux)
+            blend_forward_kernel<16, false, true><<<blocks, 256, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W,
+                                                                          g.TW, g.tiles, out, aux_T, aux_last);
+        else
+            blend_forward_kernel<16, false, false><<<blocks, 256, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W,
+                                                                           g.TW, g.tiles, out, nullptr, nullptr);
+    }
 }
 
 }  // namespace swf
