@@ -67,6 +67,9 @@ def parse():
                    help="summarise rocprofv3 counter CSVs (FETCH_SIZE / WRITE_SIZE runs of a --copy-probe-mib run) "
                         "into HBM bytes per launch of the MLP kernel, then exit")
     p.add_argument("--copy-mib", type=int, default=1024, help="copy size used by the counted run (for --pmc-summary)")
+    p.add_argument("--workload", choices=("headline", "large"), default="headline",
+                   help="large: N=500k Gaussians (log-scales in [log 0.5, log 20] px), 360x1440 spectra, batch 256; "
+                        "BF16 and FP32 MLP; prints its own JSON line (at most 5 timed steps, 1 warm-up)")
     return p.parse_args()
 
 
@@ -278,6 +281,93 @@ def serve_sweep(a):
     ctx.close()
 
 
+def timed_renders(ctx, sid, tx_dev, flags, out, steps, warmup):
+    """Renders tx_dev[0:warmup] untimed, then tx_dev[warmup:warmup+steps] timed with stage events;
+    returns (elapsed_s, per-step ms, stage table)."""
+    import torch
+    for i in range(warmup):
+        ctx.render(sid, tx_dev[i], flags=flags, out=out)
+    torch.cuda.synchronize()
+    ctx.stage_timing(True)
+    ctx.stage_times()  # reset
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        ctx.render(sid, tx_dev[warmup + i], flags=flags, out=out)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.stage_timing(False)
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return max(wall, sum(step_ms) / 1e3), step_ms, {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+
+
+def bench_large(a):
+    """Large scene: N = 500k, 360 x 1440, batch 256, BF16 (timed steps) and FP32 (one timed step) MLP."""
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+
+    H, W, N, Bq = 360, 1440, 500_000, 256
+    steps, warmup = max(1, min(a.steps, 5)), min(a.warmup, 1)
+    g = synth.gaussians(N, H, W, seed=1004, scale_range=(0.5, 20.0))
+    Ws, bs = synth.mlp_weights(seed=3004)
+    nbat = warmup + steps
+    txs = synth.tx_positions(nbat * Bq, seed=2004)
+    ctx = B.Context(0, mlp_pairs_per_wave=a.pairs_per_wave)
+    sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
+    tx_dev = torch.from_numpy(txs).cuda().view(nbat, Bq, 3)
+    out = torch.empty((Bq, H, W), device="cuda", dtype=torch.float32)
+    el, step_ms, st = timed_renders(ctx, sid, tx_dev, B.MLP_BF16, out, steps, warmup)
+    work = ctx.blend_work()
+    value = steps * Bq / el
+    bf16_last = out.clone()
+    el32, step32, st32 = timed_renders(ctx, sid, tx_dev[nbat - 1:], B.MLP_FP32, out, 1, 0)
+    # same batch (the last timed one) in both precisions
+    err = float((bf16_last - out).abs().max() / out.abs().max().clamp_min(1e-30))
+    pairs = N * Bq
+    T_tiles = -(-W // 16) * -(-H // 16)
+    tbits = max(1, int(np.ceil(np.log2(Bq * T_tiles))))
+    passes = -(-tbits // 8)
+    keys = work["entries"]
+    list_bytes = pairs * (8 + 16) + keys * (8 + passes * 20 + 4) + Bq * T_tiles * 8
+    list_ms = st["scan"] + st["emit_keys"] + st["radix_sort"] + st["tile_ranges"]
+    flops = float(FLOP_PER_PAIR) * pairs
+    rec = {
+        "metric": "spectra/s at N=500k, 360x1440, batch 256 (large scene)", "value": value, "unit": "spectra/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "large scene: N=500000 Gaussians, log-scales U(log 0.5, log 20) px, 360x1440 spectra "
+                               "(0.25 deg/px), batch 256 TX positions, MLP 89-4x256-7",
+                   "n_gaussians": N, "height": H, "width": W, "batch": Bq},
+        "fp32_mlp": {"value": Bq / el32, "ms_per_step": 1e3 * el32, "mlp_ms": st32["mlp_preprocess"],
+                     "bf16_speedup": value / (Bq / el32),
+                     "bf16_vs_fp32_normwise_max_err": err},
+        "stages_ms_per_step": st,
+        "roofline": {"kernel": "mlp_bf16_deform_preprocess", "bound": "mfma",
+                     "achieved": flops / (st["mlp_preprocess"] * 1e-3) / 1e12, "peak": PEAK["bf16"],
+                     "unit": "TFLOP/s", "frac": flops / (st["mlp_preprocess"] * 1e-3) / 1e12 / PEAK["bf16"],
+                     "traffic": None, "avg_launch_ms": st["mlp_preprocess"]},
+        "stage_rooflines": {
+            "lists": {"bound": "hbm", "achieved": list_bytes / (list_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": list_bytes / (list_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "algorithmic_bytes": list_bytes, "ms": list_ms, "list_entries": keys, "sort_passes": passes,
+                      "note": "scan 8 B/pair, emit 16 B/pair + 8 B/key, radix 20 B/key/pass, ranges 4 B/key + 8 B/tile"},
+            "blend": {"bound": "alu", "evaluations": work["evaluations"], "ops_per_evaluation": BLEND_OPS_PER_EVAL,
+                      "achieved": work["evaluations"] * BLEND_OPS_PER_EVAL / (st["blend"] * 1e-3) / 1e12,
+                      "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+                      "frac": work["evaluations"] * BLEND_OPS_PER_EVAL / (st["blend"] * 1e-3) / VALU_PEAK_LANE_OPS,
+                      "ms": st["blend"]}},
+        "latency_us": {"batched_p50": 1e3 * pct(step_ms, 50), "batched_p99": 1e3 * pct(step_ms, 99)},
+    }
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -288,6 +378,9 @@ def main():
         return
     if a.serve_sweep:
         serve_sweep(a)
+        return
+    if a.workload == "large":
+        bench_large(a)
         return
     import torch
     from paper_2506_12787_amd import binding as B
