@@ -331,10 +331,11 @@ def bench_large(a):
     err = float((bf16_last - out).abs().max() / out.abs().max().clamp_min(1e-30))
     pairs = N * Bq
     T_tiles = -(-W // 16) * -(-H // 16)
-    tbits = max(1, int(np.ceil(np.log2(Bq * T_tiles))))
-    passes = -(-tbits // 8)
+    seg = 256 if T_tiles <= 256 else 2048
+    segs = -(-T_tiles // seg)
     keys = work["entries"]
-    list_bytes = pairs * (8 + 16) + keys * (8 + passes * 20 + 4) + Bq * T_tiles * 8
+    hist_entries = Bq * segs * seg * -(-N // (1024 if seg == 256 else 8192))
+    list_bytes = pairs * 24 + keys * 4 + hist_entries * 12 + Bq * T_tiles * 8
     list_ms = st["scan"] + st["emit_keys"] + st["radix_sort"] + st["tile_ranges"]
     flops = float(FLOP_PER_PAIR) * pairs
     rec = {
@@ -355,8 +356,9 @@ def bench_large(a):
         "stage_rooflines": {
             "lists": {"bound": "hbm", "achieved": list_bytes / (list_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                       "unit": "GB/s", "frac": list_bytes / (list_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                      "algorithmic_bytes": list_bytes, "ms": list_ms, "list_entries": keys, "sort_passes": passes,
-                      "note": "scan 8 B/pair, emit 16 B/pair + 8 B/key, radix 20 B/key/pass, ranges 4 B/key + 8 B/tile"},
+                      "algorithmic_bytes": list_bytes, "ms": list_ms, "list_entries": keys, "segments": segs,
+                      "note": "binning: rect+count read twice (24 B/pair), 4 B/list entry written, histogram scan "
+                              "12 B/entry, ranges 8 B/tile"},
             "blend": {"bound": "alu", "evaluations": work["evaluations"], "ops_per_evaluation": BLEND_OPS_PER_EVAL,
                       "achieved": work["evaluations"] * BLEND_OPS_PER_EVAL / (st["blend"] * 1e-3) / 1e12,
                       "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
@@ -435,10 +437,12 @@ def main():
     work = ctx.blend_work()
     st_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
     T_tiles = -(-a.width // 16) * -(-a.height // 16)
-    binned = T_tiles <= 256
+    seg = 256 if T_tiles <= 256 else 2048  # tiles per binning segment (one digit)
+    segs = -(-T_tiles // seg)
+    binned = Bq * segs <= 65535
     pairs = N * Bq
     if binned:
-        hist_entries = Bq * 256 * -(-N // 1024)
+        hist_entries = Bq * segs * seg * -(-N // (1024 if seg == 256 else 8192))
         bin_bytes = pairs * 24 + work["entries"] * 4 + hist_entries * 12 + Bq * T_tiles * 8
         bin_ms = st_ms["scan"] + st_ms["radix_sort"] + st_ms["tile_ranges"]
         bin_note = ("binning: rect+count read twice (24 B/pair), 4 B/list entry written, histogram scan 12 B/entry, "

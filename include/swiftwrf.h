@@ -179,10 +179,10 @@ swf_status swf_l1_loss(swf_ctx *ctx, const float *pred, const float *target, int
  * render stream. swf_stage_times waits for them and returns, per stage, the
  * summed milliseconds and the number of launches since the last reset:
  * stage 0 tx features, 1 MLP+deform+preprocess, 2 scan, 3 emit keys,
- * 4 radix sort, 5 tile ranges, 6 blend. With at most 256 tiles per query and
- * without SWF_FULL_SORT the lists are built by binning instead: stage 2 is then
- * the per-block tile histograms and their scan, stage 3 is empty and stage 4
- * the stable placement of the pair indices (same lists as the sort).
+ * 4 radix sort, 5 tile ranges, 6 blend. Without SWF_FULL_SORT the lists are
+ * built by binning instead: stage 2 is then the per-block tile histograms and
+ * their scan, stage 3 is empty and stage 4 the stable placement of the pair
+ * indices (same lists as the sort).
  * n_stages is in/out (capacity/used). */
 enum { SWF_STAGE_TX = 0, SWF_STAGE_MLP, SWF_STAGE_SCAN, SWF_STAGE_EMIT, SWF_STAGE_SORT, SWF_STAGE_RANGES,
        SWF_STAGE_BLEND, SWF_N_STAGES };

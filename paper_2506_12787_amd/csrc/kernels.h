@@ -77,12 +77,11 @@ void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gt
 void launch_clear_u32(uint32_t* p, int n, hipStream_t st);
 // n_eff = total if total <= cap else 0 (then bit 0 of *status is set)
 void launch_effective_count(const uint64_t* total, uint64_t cap, uint64_t* n_eff, uint32_t* status, hipStream_t st);
-// Binning path (at most 256 tiles per query): per-block tile histograms, then
+// Binning path: per-block histograms of each tile segment of a query, then
 // (after an exclusive scan of the histogram, in place) the stable placement of
 // pair indices into per-tile lists and the tile ranges.
-constexpr int kBinMaxTiles = 256;
-int bin_blocks_per_query(int N);
-size_t bin_hist_entries(int B, int N);
+bool bin_fits(int B, int N, const Grid& g);  // the segment grid fits one launch
+size_t bin_hist_entries(int B, int N, const Grid& g);
 void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hist, hipStream_t st);
 void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* hist_scanned,
                         const uint64_t* n_dev, uint32_t* vals, hipStream_t st);

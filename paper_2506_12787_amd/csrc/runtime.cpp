@@ -471,7 +471,8 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     const bool full = (flags & SWF_FULL_SORT) != 0;
     const int64_t n_gt = (int64_t)B * g.tiles;
     if ((s = w.ranges.reserve(this, (size_t)n_gt * sizeof(uint2), st))) return s;
-    if (!full && g.tiles <= kBinMaxTiles)
+    // binning unless the full 64-bit sort is asked for (or the segment grid would exceed the launch limit)
+    if (!full && bin_fits(B, d.n, g))
         s = lists_binned(w, d, B, g, st, key_cap);
     else
         s = lists_sorted(w, d, B, g, full, st, key_cap);
@@ -508,12 +509,12 @@ swf_status Ctx::key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64
     return SWF_OK;
 }
 
-// Lists by binning (at most 256 tiles per query): tile histograms per block of
+// Lists by binning (per tile segment of a query): tile histograms per block of
 // pairs, their scan, stable placement, ranges. Same lists as the full sort.
 swf_status Ctx::lists_binned(Workspace& w, const DevScene& d, int B, const Grid& g, hipStream_t st,
                              uint64_t key_cap) {
     swf_status s;
-    const int64_t nh = (int64_t)bin_hist_entries(B, d.n);
+    const int64_t nh = (int64_t)bin_hist_entries(B, d.n, g);
     if ((s = w.bins.reserve(this, (size_t)nh * sizeof(uint32_t) + 16, st))) return s;
     if ((s = w.scan.reserve(this, scan_scratch_bytes(nh) + 64, st))) return s;
     uint32_t* bins = (uint32_t*)w.bins.ptr;

@@ -102,8 +102,10 @@ void drop_graphs(Slot* s) {
 uint64_t estimate_bytes(const DevScene& d, int bucket, uint64_t key_cap) {
     const uint64_t pairs = (uint64_t)bucket * d.n;
     const uint64_t tiles = (uint64_t)bucket * ((d.W + 15) / 16) * ((d.H + 15) / 16);
+    // binning histogram bounded with the finer (8-pixel) tiling
+    const uint64_t bins = bin_hist_entries(bucket, d.n, make_grid(d.H, d.W, 8)) * 4;
     const uint64_t raw = pairs * 56 + key_cap * 16 + tiles * 8 + (uint64_t)bucket * ((uint64_t)d.H * d.W * 4 + 1024) +
-                         (uint64_t)bucket * 256 * 4 + bin_hist_entries(bucket, d.n) * 4 + (1u << 20);
+                         (uint64_t)bucket * 256 * 4 + bins + (1u << 20);
     return raw + raw / 4 + 64 * 256;
 }
 

@@ -291,85 +291,125 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const K* __rest
 
 // ---- binning: per-query stable counting sort by tile -----------------------
 // Pairs are stored in (query, depth) order and a pair covers a tile at most
-// once, so the list of a tile is the pairs covering it in pair order. With at
-// most 256 tiles per query the tile index is one 8-bit digit: one counting
-// pass per query segment gives exactly the order of the full (tile, depth)
-// sort, without materialising keys in memory.
-//   bin_hist:    block (j, q) histograms the tiles covered by pairs
-//                [j * kBinPairs, (j + 1) * kBinPairs) of query q;
-//                hist[(q * 256 + tile) * nbq + j]
+// once, so the list of a tile is the pairs covering it in pair order. A query's
+// tiles are split into segments of 2^DB tiles (DB = 8 for up to 256 tiles per
+// query, else 11); every (query, segment) is binned by one stable counting pass
+// on a DB-bit digit, which gives exactly the order of the full (tile, depth)
+// sort without materialising keys in memory.
+//   bin_hist:    block (j, q, s) histograms the tiles of segment s covered by
+//                pairs [j * pb, (j + 1) * pb) of query q;
+//                hist[((q * S + s) * 2^DB + tile - s 2^DB) * nbq + j]
 //   scan:        one exclusive scan over that (query, tile, block) order gives
 //                every block's first output position per tile
 //   bin_scatter: the same block regenerates its keys in LDS (pair order) and
 //                writes each pair index to its position, ranked stably with
-//                the wave-ballot scheme of the radix scatter
+//                the wave-ballot scheme of the radix scatter (DB ballots)
 //   bin_ranges:  tile (q, t) spans [hist(q, t, 0), hist(q, t + 1, 0))
-constexpr int kBinPairs = 1024;
+struct BinGeom {
+    int N, TW, tiles, db, S, pb, nbq;  // pairs per query, tile grid, digit bits, segments, pairs/block, blocks/query
+};
 
-__global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restrict__ rect,
-                                                            const uint32_t* __restrict__ count, int N, int TW,
-                                                            int nbq, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kWaves][256];
-    for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&h[0][0])[i] = 0;
-    __syncthreads();
-    const int w = threadIdx.x >> 6;
-    const int j = blockIdx.x, q = blockIdx.y;
-    const int p_beg = j * kBinPairs, p_end = min(p_beg + kBinPairs, N);
-    const size_t row0 = (size_t)q * N;
-    for (int p = p_beg + (int)threadIdx.x; p < p_end; p += kThreads) {
-        if (count[row0 + p] == 0) continue;
-        const uint2 r = rect[row0 + p];
-        const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&h[w][ty * TW + tx], 1u);
-    }
-    __syncthreads();
-    for (int d = threadIdx.x; d < 256; d += kThreads) {
-        uint32_t s = 0;
-#pragma unroll
-        for (int k = 0; k < kWaves; ++k) s += h[k][d];
-        hist[((size_t)q * 256 + d) * nbq + j] = s;
+BinGeom bin_geom(int N, const Grid& g) {
+    BinGeom b;
+    b.N = N;
+    b.TW = g.TW;
+    b.tiles = g.tiles;
+    b.db = g.tiles <= 256 ? 8 : 11;
+    b.S = std::max(1, (g.tiles + (1 << b.db) - 1) >> b.db);
+    b.pb = b.db == 8 ? 1024 : 8192;  // larger blocks keep the wide histogram small
+    b.nbq = std::max(1, (N + b.pb - 1) / b.pb);
+    return b;
+}
+
+// Keys of one pair inside segment [t0, t0 + seg): visits them in row-major
+// tile order (the pair's key order) and calls f(local index, tile - t0).
+template <typename F>
+__device__ __forceinline__ void for_seg_tiles(uint2 r, int TW, int t0, int seg, F&& f) {
+    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+    if (ty1 * TW + tx1 < t0 || ty0 * TW + tx0 >= t0 + seg) return;
+    uint32_t m = 0;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        const int a = max(ty * TW + tx0, t0), b = min(ty * TW + tx1, t0 + seg - 1);
+        for (int t = a; t <= b; ++t) f(m++, (uint32_t)(t - t0));
     }
 }
 
+__device__ __forceinline__ uint32_t seg_count(uint2 r, int TW, int t0, int seg) {
+    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+    if (ty1 * TW + tx1 < t0 || ty0 * TW + tx0 >= t0 + seg) return 0;
+    uint32_t c = 0;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        const int a = max(ty * TW + tx0, t0), b = min(ty * TW + tx1, t0 + seg - 1);
+        c += b >= a ? (uint32_t)(b - a + 1) : 0u;
+    }
+    return c;
+}
+
+template <int DB>
+__global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restrict__ rect,
+                                                            const uint32_t* __restrict__ count, BinGeom G,
+                                                            uint32_t* __restrict__ hist) {
+    constexpr int kSeg = 1 << DB;
+    constexpr int kCopies = DB == 8 ? kWaves : 1;  // per-wave copies while they are small
+    __shared__ uint32_t h[kCopies][kSeg];
+    for (int i = threadIdx.x; i < kCopies * kSeg; i += kThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int w = kCopies == 1 ? 0 : (int)(threadIdx.x >> 6);
+    const int j = blockIdx.x, q = blockIdx.y / G.S, sg = blockIdx.y - q * G.S;
+    const int t0 = sg * kSeg;
+    const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, G.N);
+    const size_t row0 = (size_t)q * G.N;
+    for (int p = p_beg + (int)threadIdx.x; p < p_end; p += kThreads) {
+        if (count[row0 + p] == 0) continue;
+        for_seg_tiles(rect[row0 + p], G.TW, t0, kSeg, [&](uint32_t, uint32_t tl) { atomicAdd(&h[w][tl], 1u); });
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kSeg; d += kThreads) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < kCopies; ++k) s += h[k][d];
+        hist[((size_t)blockIdx.y * kSeg + d) * G.nbq + j] = s;
+    }
+}
+
+template <int DB>
 __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __restrict__ rect,
-                                                               const uint32_t* __restrict__ count, int N, int TW,
-                                                               int nbq, const uint32_t* __restrict__ hs,
+                                                               const uint32_t* __restrict__ count, BinGeom G,
+                                                               const uint32_t* __restrict__ hs,
                                                                const uint64_t* __restrict__ n_dev,
                                                                uint32_t* __restrict__ vals) {
+    constexpr int kSeg = 1 << DB;
     // fixed-capacity run that overflowed: nothing is placed (block-uniform)
     if (n_dev && *n_dev == 0) return;
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t wcnt[kWaves][256];
-    __shared__ uint32_t ttot[256];
+    __shared__ uint32_t base[kSeg];
+    __shared__ uint32_t wcnt[kWaves][kSeg];
+    __shared__ uint32_t ttot[kSeg];
     __shared__ uint32_t lds[kWaves + 1];
-    __shared__ uint16_t kbuf[kTile];  // tile << 8 | pair within the 256-pair batch
+    __shared__ uint32_t kbuf[kTile];  // (tile - t0) << 8 | pair within the 256-pair batch
     const int w = threadIdx.x >> 6;
-    const int j = blockIdx.x, q = blockIdx.y;
-    const int p_beg = j * kBinPairs, p_end = min(p_beg + kBinPairs, N);
-    const size_t row0 = (size_t)q * N;
-    base[threadIdx.x] = hs[((size_t)q * 256 + threadIdx.x) * nbq + j];
+    const int j = blockIdx.x, q = blockIdx.y / G.S, sg = blockIdx.y - q * G.S;
+    const int t0 = sg * kSeg;
+    const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, G.N);
+    const size_t row0 = (size_t)q * G.N;
+    for (int d = threadIdx.x; d < kSeg; d += kThreads) base[d] = hs[((size_t)blockIdx.y * kSeg + d) * G.nbq + j];
     for (int s0 = p_beg; s0 < p_end; s0 += kThreads) {
         const int p = s0 + (int)threadIdx.x;
         uint32_t c = 0;
         uint2 r = make_uint2(0u, 0u);
-        if (p < p_end) {
-            c = count[row0 + p];
-            if (c) r = rect[row0 + p];
+        if (p < p_end && count[row0 + p] != 0) {
+            r = rect[row0 + p];
+            c = G.S == 1 ? count[row0 + p] : seg_count(r, G.TW, t0, kSeg);
         }
         uint32_t K;
         const uint32_t o = block_exclusive_scan<uint32_t>(c, lds, &K);  // synchronises
-        const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff;
-        const uint32_t wdt = (uint32_t)(tx1 - tx0 + 1);
         for (uint32_t c0 = 0; c0 < K; c0 += kTile) {
-            for (int i = threadIdx.x; i < kWaves * 256; i += kThreads) (&wcnt[0][0])[i] = 0;
+            for (int i = threadIdx.x; i < kWaves * kSeg; i += kThreads) (&wcnt[0][0])[i] = 0;
             // this thread's keys with batch positions in [c0, c0 + kTile)
-            const int64_t m0 = (int64_t)c0 > (int64_t)o ? (int64_t)c0 - (int64_t)o : 0;
-            const int64_t m1 = min((int64_t)c, (int64_t)c0 + kTile - (int64_t)o);
-            for (int64_t m = m0; m < m1; ++m) {
-                const uint32_t tile = (ty0 + (uint32_t)m / wdt) * (uint32_t)TW + tx0 + (uint32_t)m % wdt;
-                kbuf[o + m - c0] = (uint16_t)((tile << 8) | threadIdx.x);
-            }
+            if (c && o + c > c0 && o < c0 + kTile)
+                for_seg_tiles(r, G.TW, t0, kSeg, [&](uint32_t m, uint32_t tl) {
+                    const int64_t at = (int64_t)o + m - c0;
+                    if (at >= 0 && at < kTile) kbuf[at] = (tl << 8) | threadIdx.x;
+                });
             __syncthreads();
             const uint32_t n_here = min(K - c0, (uint32_t)kTile);
             uint32_t dig[kItems], lr[kItems], pl[kItems];
@@ -384,7 +424,7 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
                 pl[jj] = k & 255u;
                 uint64_t match = __ballot(ok[jj]);
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {
+                for (int b = 0; b < DB; ++b) {
                     const bool bit = (d >> b) & 1u;
                     const uint64_t bal = __ballot(bit && ok[jj]);
                     match &= bit ? bal : ~bal;
@@ -399,8 +439,7 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
                 __builtin_amdgcn_wave_barrier();
             }
             __syncthreads();
-            {
-                const int d = threadIdx.x;  // one thread per digit
+            for (int d = threadIdx.x; d < kSeg; d += kThreads) {
                 uint32_t run = 0;
 #pragma unroll
                 for (int k = 0; k < kWaves; ++k) {
@@ -415,25 +454,25 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
             for (int jj = 0; jj < kItems; ++jj)
                 if (ok[jj]) vals[base[dig[jj]] + wcnt[w][dig[jj]] + lr[jj]] = (uint32_t)(row0 + s0 + pl[jj]);
             __syncthreads();
-            base[threadIdx.x] += ttot[threadIdx.x];
+            for (int d = threadIdx.x; d < kSeg; d += kThreads) base[d] += ttot[d];
             __syncthreads();
         }
     }
 }
 
-__global__ void bin_ranges_kernel(const uint32_t* __restrict__ hs, int B, int T, int nbq,
+__global__ void bin_ranges_kernel(const uint32_t* __restrict__ hs, int B, BinGeom G,
                                   const uint64_t* __restrict__ total, const uint64_t* __restrict__ n_dev,
                                   uint2* __restrict__ ranges) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)B * T) return;
+    if (i >= (int64_t)B * G.tiles) return;
     if (n_dev && *n_dev == 0) {
         ranges[i] = make_uint2(0u, 0u);
         return;
     }
-    const int64_t q = i / T, t = i - q * T;
-    const size_t e = (size_t)q * 256 + t;
-    const uint32_t a = hs[e * nbq];
-    const uint32_t b = e + 1 < (size_t)B * 256 ? hs[(e + 1) * nbq] : (uint32_t)*total;
+    const int64_t q = i / G.tiles, t = i - q * G.tiles;
+    const size_t e = ((size_t)q * G.S << G.db) + t;  // (q, segment t >> db, t mod 2^db)
+    const uint32_t a = hs[e * G.nbq];
+    const uint32_t b = e + 1 < ((size_t)B * G.S << G.db) ? hs[(e + 1) * G.nbq] : (uint32_t)*total;
     ranges[i] = a < b ? make_uint2(a, b) : make_uint2(0u, 0u);
 }
 
@@ -582,33 +621,44 @@ void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gt
         tile_ranges_kernel<false><<<blocks, 256, 0, st>>>(keys, n, ranges, n_dev);
 }
 
-int bin_blocks_per_query(int N) { return std::max(1, (N + kBinPairs - 1) / kBinPairs); }
+bool bin_fits(int B, int N, const Grid& g) { return (int64_t)B * bin_geom(N, g).S <= 65535; }
 
-size_t bin_hist_entries(int B, int N) { return (size_t)B * 256 * (size_t)bin_blocks_per_query(N); }
+size_t bin_hist_entries(int B, int N, const Grid& g) {
+    const BinGeom G = bin_geom(N, g);
+    return ((size_t)B * G.S << G.db) * (size_t)G.nbq;
+}
 
 void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hist, hipStream_t st) {
     if (B <= 0) return;
-    const int nbq = bin_blocks_per_query(N);
+    const BinGeom G = bin_geom(N, g);
     if (N <= 0) {
-        launch_clear_u32(hist, (int)bin_hist_entries(B, N), st);
+        launch_clear_u32(hist, (int)bin_hist_entries(B, N, g), st);
         return;
     }
-    bin_hist_kernel<<<dim3(nbq, B), kThreads, 0, st>>>(r.rect, r.count, N, g.TW, nbq, hist);
+    if (G.db == 8)
+        bin_hist_kernel<8><<<dim3(G.nbq, B * G.S), kThreads, 0, st>>>(r.rect, r.count, G, hist);
+    else
+        bin_hist_kernel<11><<<dim3(G.nbq, B * G.S), kThreads, 0, st>>>(r.rect, r.count, G, hist);
 }
 
 void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* hist_scanned,
                         const uint64_t* n_dev, uint32_t* vals, hipStream_t st) {
     if (B <= 0 || N <= 0) return;
-    const int nbq = bin_blocks_per_query(N);
-    bin_scatter_kernel<<<dim3(nbq, B), kThreads, 0, st>>>(r.rect, r.count, N, g.TW, nbq, hist_scanned, n_dev, vals);
+    const BinGeom G = bin_geom(N, g);
+    if (G.db == 8)
+        bin_scatter_kernel<8><<<dim3(G.nbq, B * G.S), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev,
+                                                                         vals);
+    else
+        bin_scatter_kernel<11><<<dim3(G.nbq, B * G.S), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev,
+                                                                          vals);
 }
 
 void launch_bin_ranges(const uint32_t* hist_scanned, int B, int N, const Grid& g, const uint64_t* total,
                        const uint64_t* n_dev, uint2* ranges, hipStream_t st) {
     const int64_t m = (int64_t)B * g.tiles;
     if (m <= 0) return;
-    bin_ranges_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(hist_scanned, B, g.tiles,
-                                                                    bin_blocks_per_query(N), total, n_dev, ranges);
+    bin_ranges_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(hist_scanned, B, bin_geom(N, g), total, n_dev,
+                                                                    ranges);
 }
 
 }  // namespace swf

@@ -83,20 +83,21 @@ def test_tile8_and_full_sort_are_bitwise_equal(ctx):
     ctx.release_scene(sid)
 
 
-@pytest.mark.parametrize("n,scale,batch", [(2500, (1.0, 12.0), 3), (1100, (20.0, 60.0), 2), (1024, (2.0, 8.0), 1),
-                                           (1, (1.0, 3.0), 2)])
-def test_binned_lists_equal_full_sort(ctx, n, scale, batch):
-    """The binning path (default for <= 256 tiles per query) builds the same
-    per-tile lists as the full 64-bit (tile, depth) radix sort: counts, keys,
-    values and ranges bitwise, and the same images. Large Gaussians put tens of
-    thousands of keys into one 256-pair batch (several 2048-key chunks); N is
-    ragged against the 1024-pair blocks; deformation differs per query."""
+@pytest.mark.parametrize("n,scale,batch,H,W", [(2500, (1.0, 12.0), 3, 90, 360), (1100, (20.0, 60.0), 2, 90, 360),
+                                               (1024, (2.0, 8.0), 1, 90, 360), (1, (1.0, 3.0), 2, 90, 360),
+                                               (5000, (1.0, 40.0), 2, 180, 720), (4097, (0.5, 20.0), 3, 250, 1100)])
+def test_binned_lists_equal_full_sort(ctx, n, scale, batch, H, W):
+    """The binning path (the default) builds the same per-tile lists as the
+    full 64-bit (tile, depth) radix sort: counts, keys, values and ranges
+    bitwise, and the same images. Large Gaussians put tens of thousands of keys
+    into one 256-pair batch (several 2048-key chunks); N is ragged against the
+    pair blocks (1024, or 8192 with 11-bit tile digits); 180 x 720 (540 tiles)
+    and 250 x 1100 (1104 tiles) take the 11-bit digit; deformation differs per
+    query."""
     import torch
     from paper_2506_12787_amd import binding as B
     from paper_2506_12787_amd import synth
-    H, W = 90, 360
     T = -(-W // 16) * -(-H // 16)
-    assert T <= 256
     g, s = Hh.problem(n, H, W, seed=41 + n, scale_range=scale)
     Ws, bs = synth.mlp_weights(seed=7, out_scale=1.0)
     sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
@@ -112,6 +113,8 @@ def test_binned_lists_equal_full_sort(ctx, n, scale, batch):
     np.testing.assert_array_equal(outs[0], outs[1])
     if scale[0] >= 20.0:
         assert int(a["counts"].max()) > 8  # a 256-pair batch then exceeds one 2048-key chunk
+    if T > 256:  # tiles beyond one 8-bit digit
+        assert int(a["keys"][-1] >> np.uint64(32)) % T >= 256
     ctx.release_scene(sid)
 
 
