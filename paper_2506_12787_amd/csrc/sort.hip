@@ -392,13 +392,23 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
     const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, G.N);
     const size_t row0 = (size_t)q * G.N;
     for (int d = threadIdx.x; d < kSeg; d += kThreads) base[d] = hs[((size_t)blockIdx.y * kSeg + d) * G.nbq + j];
+    // the next batch's (count, rect) are loaded while this one is placed
+    uint32_t c_next = 0;
+    uint2 r_next = make_uint2(0u, 0u);
+    if (p_beg + (int)threadIdx.x < p_end) {
+        c_next = count[row0 + p_beg + threadIdx.x];
+        r_next = rect[row0 + p_beg + threadIdx.x];
+    }
     for (int s0 = p_beg; s0 < p_end; s0 += kThreads) {
-        const int p = s0 + (int)threadIdx.x;
-        uint32_t c = 0;
-        uint2 r = make_uint2(0u, 0u);
-        if (p < p_end && count[row0 + p] != 0) {
-            r = rect[row0 + p];
-            c = G.S == 1 ? count[row0 + p] : seg_count(r, G.TW, t0, kSeg);
+        const uint2 r = c_next ? r_next : make_uint2(0u, 0u);
+        const uint32_t c = !c_next ? 0u : (G.S == 1 ? c_next : seg_count(r, G.TW, t0, kSeg));
+        {
+            const int pn = s0 + kThreads + (int)threadIdx.x;
+            c_next = 0;
+            if (pn < p_end) {
+                c_next = count[row0 + pn];
+                r_next = rect[row0 + pn];
+            }
         }
         uint32_t K;
         const uint32_t o = block_exclusive_scan<uint32_t>(c, lds, &K);  // synchronises
