@@ -60,6 +60,8 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=3000, help="requests per serving measurement")
     p.add_argument("--serve-sweep", action="store_true",
                    help="8 resident scenes, Poisson arrivals at a rate sweep (prints one JSON line per rate)")
+    p.add_argument("--hbm-budget-gb", type=float, default=2.0,
+                   help="serving sweep: bound on the transient workspace of all slots (GB), so admission binds")
     p.add_argument("--copy-probe-mib", type=int, default=0,
                    help="after the timed steps, run a plain FP32 copy kernel (x*1) over this many MiB three times: "
                         "the reference kernel that scales HBM byte counters")
@@ -67,9 +69,11 @@ def parse():
                    help="summarise rocprofv3 counter CSVs (FETCH_SIZE / WRITE_SIZE runs of a --copy-probe-mib run) "
                         "into HBM bytes per launch of the MLP kernel, then exit")
     p.add_argument("--copy-mib", type=int, default=1024, help="copy size used by the counted run (for --pmc-summary)")
-    p.add_argument("--workload", choices=("headline", "large"), default="headline",
+    p.add_argument("--workload", choices=("headline", "large", "train"), default="headline",
                    help="large: N=500k Gaussians (log-scales in [log 0.5, log 20] px), 360x1440 spectra, batch 256; "
-                        "BF16 and FP32 MLP; prints its own JSON line (at most 5 timed steps, 1 warm-up)")
+                        "BF16 and FP32 MLP; prints its own JSON line (at most 5 timed steps, 1 warm-up). "
+                        "train: training steps at N=50k, batch 16, 90x360 (forward with the blend state kept, L1 "
+                        "loss, hand-written backward, Adam on Gaussians and MLP); prints its own JSON line")
     return p.parse_args()
 
 
@@ -267,16 +271,38 @@ def serve_sweep(a):
     R = a.serve_requests
     txs = synth.tx_positions(R, seed=2003)
     plan = [(sids[int(k)], txs[j]) for j, k in enumerate(rng.integers(0, len(scenes), R))]
-    ctx.serve_start(max_batch=64, n_slots=2, flags=B.MLP_BF16)
+    # plain path: the same request mix, one FP32 query per launch, synchronously
+    import torch
+    q = min(R, 64)
+    t_dev = torch.from_numpy(np.stack([t for _, t in plan[:q]])).cuda()
+    outs = {sid: torch.empty((1,) + shapes[sid], device="cuda") for sid in sids}
+    for k in range(min(q, 8)):
+        ctx.render(plan[k][0], t_dev[k:k + 1], flags=B.MLP_FP32, out=outs[plan[k][0]])
+    torch.cuda.synchronize()
+    lat_plain = []
+    t0 = time.perf_counter()
+    for k in range(q):
+        s0 = time.perf_counter()
+        ctx.render(plan[k][0], t_dev[k:k + 1], flags=B.MLP_FP32, out=outs[plan[k][0]])
+        torch.cuda.synchronize()
+        lat_plain.append(1e6 * (time.perf_counter() - s0))
+    plain = q / (time.perf_counter() - t0)
+    print(json.dumps({"serve_sweep": "plain", "throughput": plain, "p50_us": pct(lat_plain, 50),
+                      "p99_us": pct(lat_plain, 99), "queries": q,
+                      "note": "one FP32 query per launch over the same scene mix"}), flush=True)
+    budget = int(a.hbm_budget_gb * 1e9)
+    ctx.serve_start(max_batch=64, n_slots=2, flags=B.MLP_BF16, hbm_budget=budget)
     serve_run(ctx, plan[:512], shapes)  # warm-up: graphs for the common buckets
     sat, lat, _ = serve_run(ctx, plan, shapes)
-    print(json.dumps({"serve_sweep": "saturation", "rate": None, "throughput": sat,
-                      "p50_us": pct(lat, 50), "p99_us": pct(lat, 99)}), flush=True)
+    print(json.dumps({"serve_sweep": "saturation", "rate": None, "throughput": sat, "over_plain": sat / plain,
+                      "p50_us": pct(lat, 50), "p99_us": pct(lat, 99), "hbm_budget_bytes": budget}), flush=True)
     for f in (0.1, 0.25, 0.5, 0.75, 0.9, 1.1):
         thr, lat, st = serve_run(ctx, plan, shapes, rate=f * sat, depth=1 << 30)
         print(json.dumps({"serve_sweep": "poisson", "rate_fraction": f, "rate": f * sat, "throughput": thr,
                           "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
                           "mean_batch": float(np.mean([s["batch"] for s in st]))}), flush=True)
+    cnt = ctx.serve_counters()
+    print(json.dumps({"serve_sweep": "counters", **cnt}), flush=True)
     ctx.serve_stop()
     ctx.close()
 
@@ -370,6 +396,69 @@ def bench_large(a):
     print(json.dumps(rec), flush=True)
 
 
+def bench_train(a):
+    """Training steps: N = 50k Gaussians, batch 16 TX positions, 90 x 360; BF16 MLP, FP32 rasterizer."""
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+    from paper_2506_12787_amd.autograd import Renderer
+
+    N, H, W, Bq = 50_000, 90, 360, 16
+    steps, warmup = a.steps, a.warmup
+    g = synth.gaussians(N, H, W, seed=1002)
+    g_true = synth.gaussians(N, H, W, seed=4002)
+    Ws, bs = synth.mlp_weights(seed=3002)
+    ctx = B.Context(0, mlp_pairs_per_wave=a.pairs_per_wave)
+    model = Renderer(g, H, W, mlp=(Ws, bs), lib=ctx)
+    nbat = warmup + steps
+    tx_dev = torch.from_numpy(synth.tx_positions(nbat * Bq, seed=2002)).cuda().view(nbat, Bq, 3)
+    # targets: the separately seeded ground-truth set rendered at the same TX positions (by this library; the
+    # bench does not run the oracle outside its CPU baseline)
+    gsid = ctx.upload_scene(g_true, H, W, mlp=(Ws, bs))
+    targets = [ctx.render(gsid, tx_dev[i], flags=B.MLP_BF16).clone() for i in range(nbat)]
+    opt = torch.optim.Adam(model.parameters(), lr=1e-3, foreach=True)
+    losses = []
+
+    def step(i):
+        out = model(tx_dev[i], flags=B.MLP_BF16)
+        loss, grad = ctx.l1_loss(out.detach(), targets[i])
+        out.backward(grad)
+        opt.step()
+        opt.zero_grad(set_to_none=False)
+        return loss
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        losses.append(step(warmup + i))
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    el = max(wall, sum(step_ms) / 1e3)
+    lv = [float(l) for l in losses]
+    rec = {
+        "metric": "training steps/s at N=50k, batch 16, 90x360", "value": steps / el, "unit": "steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "training step: N=50000 Gaussians, batch 16 TX positions, 90x360, BF16 MLP "
+                               "89-4x256-7, FP32 rasterizer, L1 loss, hand-written backward, Adam (lr 1e-3) on the "
+                               "Gaussians and the MLP", "n_gaussians": N, "batch": Bq, "height": H, "width": W},
+        "spectra_per_s": steps * Bq / el,
+        "loss_first": lv[0], "loss_last": lv[-1],
+        "latency_us": {"step_p50": 1e3 * pct(step_ms, 50), "step_p99": 1e3 * pct(step_ms, 99)},
+        "note": "targets: a separately seeded ground-truth Gaussian set rendered by this library at the same TX "
+                "positions",
+    }
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -383,6 +472,9 @@ def main():
         return
     if a.workload == "large":
         bench_large(a)
+        return
+    if a.workload == "train":
+        bench_train(a)
         return
     import torch
     from paper_2506_12787_amd import binding as B
