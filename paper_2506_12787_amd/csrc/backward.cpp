@@ -1,7 +1,150 @@
 // Backward pass orchestration (blend -> preprocess -> MLP) and its C ABI entry.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+
 #include "runtime.h"
 
 namespace swf {
+
+namespace {
+
+rocblas_handle blas_of(Ctx* c) { return reinterpret_cast<rocblas_handle>(c->blas); }
+
+// C = op(A) op(B) (+ beta C) for row-major matrices: op(A) is M x K, op(B) is
+// K x N, C is M x N with leading dimension ldc. rocBLAS is column-major, where
+// a row-major matrix reads as its transpose, so C^T = op(B)^T op(A)^T.
+rocblas_status gemm_rm(rocblas_handle h, bool ta, bool tb, int64_t M, int64_t N, int64_t K, const float* A,
+                       int64_t lda, const float* Bm, int64_t ldb, float* C, int64_t ldc, float beta = 0.0f) {
+    const float one = 1.0f;
+    return rocblas_sgemm(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
+                         ta ? rocblas_operation_transpose : rocblas_operation_none, (rocblas_int)N, (rocblas_int)M,
+                         (rocblas_int)K, &one, Bm, (rocblas_int)ldb, A, (rocblas_int)lda, &beta, C,
+                         (rocblas_int)ldc);
+}
+
+constexpr int kMaxSplit = 64;  // K-slices of a weight-gradient GEMM
+
+int split_of(int64_t P) { return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSplit, P / 16384)); }
+
+// dW (M x N, row-major) = dz^T act over K = P rows (dz: P x M, act: P x N), as
+// split-K: per-slice partial products in rocBLAS, then their sum. part holds
+// split_of(P) * M * N floats, tmp colsum_blocks(split) * M * N.
+rocblas_status wgrad_rm(rocblas_handle h, int64_t M, int64_t N, int64_t P, const float* dz, const float* act,
+                        float* dW, float* part, float* tmp, hipStream_t st) {
+    const int sp = split_of(P);
+    const int64_t kc = P / sp, last = P - kc * (sp - 1);
+    const float one = 1.0f, zero = 0.0f;
+    rocblas_status r = rocblas_status_success;
+    if (sp > 1)
+        r = rocblas_sgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)N,
+                                          (rocblas_int)M, (rocblas_int)kc, &one, act, (rocblas_int)N,
+                                          (rocblas_stride)(kc * N), dz, (rocblas_int)M, (rocblas_stride)(kc * M), &zero,
+                                          part, (rocblas_int)N, (rocblas_stride)(M * N), sp - 1);
+    if (r != rocblas_status_success) return r;
+    r = gemm_rm(h, true, false, M, N, last, dz + (sp - 1) * kc * M, M, act + (sp - 1) * kc * N, N,
+                part + (int64_t)(sp - 1) * M * N, N);
+    if (r != rocblas_status_success) return r;
+    launch_colsum(part, sp, M * N, 1, 0, tmp, dW, 0, st);
+    return rocblas_status_success;
+}
+
+}  // namespace
+
+void blas_release(Ctx* c) {
+    if (c->blas) rocblas_destroy_handle(blas_of(c));
+    c->blas = nullptr;
+}
+
+// MLP backward in FP32 with the layer GEMMs in rocBLAS (plain GEMMs; the ReLU
+// and bias steps are small kernels). Activations are recomputed: layer 1 from
+// its per-Gaussian mean part W1m gamma(mu_hat) plus the per-query TX part (the
+// forward's `qs`), later layers as act_l = ReLU(act_{l-1} W_l^T + b_l). Then
+// from dy (gradients of the 7 residuals per pair):
+//   dW_l = dz_l^T act_{l-1}, db_l = colsum(dz_l), dz_{l-1} = (dz_l W_l) * [act_{l-1} > 0],
+// and for layer 1 the weight gradient splits into the mean part
+// (sum over queries of dz_0 per Gaussian)^T gamma(mu_hat) and the TX part
+// (sum over Gaussians of dz_0 per query)^T gamma(s_hat).
+swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,
+                             const swf_grads* gr, hipStream_t st) {
+    swf_status s = SWF_OK;
+    if (!blas) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) return fail(SWF_E_DEVICE, "rocblas_create_handle");
+        blas = h;
+    }
+    rocblas_handle h = blas_of(this);
+    rocblas_set_stream(h, st);
+    const int64_t N = d.n, P = (int64_t)B * N;
+    const int nh = d.n_hidden, Hd = 256, I = d.in_dim;
+    const size_t actb = (size_t)P * Hd * sizeof(float);
+    if ((s = w.act.reserve(this, actb * nh + 16, st))) return s;
+    if ((s = w.dz.reserve(this, actb * 2 + 16, st))) return s;
+    // scratch: Pm / S (N x 256), R (B x 256), split-K partials, column-sum partials
+    const size_t n_split = (size_t)split_of(P) * Hd * Hd;
+    const size_t n_cs = std::max<size_t>({(size_t)colsum_blocks(P) * Hd, (size_t)colsum_blocks(B) * N * Hd,
+                                          (size_t)colsum_blocks(N) * Hd * B, (size_t)colsum_blocks(kMaxSplit) * Hd * Hd});
+    const size_t small = ((size_t)N * Hd + (size_t)B * Hd + n_split + n_cs + 64) * sizeof(float);
+    if ((s = w.part.reserve(this, small, st))) return s;
+    if ((s = w.fmean.reserve(this, (size_t)N * kMeanFeat * sizeof(float) + 16, st))) return s;
+    if ((s = w.ftx.reserve(this, (size_t)B * kTxFeat * sizeof(float) + 16, st))) return s;
+    if ((s = w.dmu.reserve(this, (size_t)N * 2 * sizeof(float) + 16, st))) return s;
+    if ((s = w.qs.reserve(this, (size_t)B * Hd * sizeof(float), st))) return s;
+    float* act[8] = {};
+    for (int l = 0; l < nh; ++l) act[l] = (float*)((char*)w.act.ptr + actb * l);
+    float* dz[2] = {(float*)w.dz.ptr, (float*)((char*)w.dz.ptr + actb)};
+    float* Pm = (float*)w.part.ptr;             // N x 256: W1m gamma(mu_hat), later S
+    float* R = Pm + (size_t)N * Hd;              // B x 256
+    float* part = R + (size_t)B * Hd;            // split-K partials
+    float* tmp = part + n_split;                 // column-sum partials
+    float* fmean = (float*)w.fmean.ptr, *ftx = (float*)w.ftx.ptr, *qs = (float*)w.qs.ptr;
+    launch_tx_features(d, tx, B, qs, st, ftx);
+    launch_mean_features_f32(d, fmean, st);
+    auto ok = [&](rocblas_status r, const char* what) -> swf_status {
+        return r == rocblas_status_success ? SWF_OK : fail(SWF_E_DEVICE, what);
+    };
+    // ---- recompute the hidden activations
+    if ((s = ok(gemm_rm(h, false, true, N, Hd, kMeanFeat, fmean, kMeanFeat, d.w[0], I, Pm, Hd), "sgemm W1m"))) return s;
+    launch_layer1_act(Pm, qs, (int)N, P, act[0], st);
+    for (int l = 1; l < nh; ++l) {
+        if ((s = ok(gemm_rm(h, false, true, P, Hd, Hd, act[l - 1], Hd, d.w[l], Hd, act[l], Hd), "sgemm fwd")))
+            return s;
+        launch_bias_relu(act[l], d.b[l], P, st);
+    }
+    // ---- output layer (7 outputs)
+    if (gr->weight[nh] && (s = ok(wgrad_rm(h, kOut, Hd, P, dy, act[nh - 1], gr->weight[nh], part, tmp, st), "dWo")))
+        return s;
+    if (gr->bias[nh]) launch_colsum(dy, P, kOut, 1, 0, tmp, gr->bias[nh], 0, st);
+    if ((s = ok(gemm_rm(h, false, false, P, Hd, kOut, dy, kOut, d.w[nh], Hd, dz[0], Hd), "sgemm dz"))) return s;
+    launch_relu_mask(dz[0], act[nh - 1], P, st);
+    int cur = 0;
+    for (int l = nh - 1; l >= 1; --l) {
+        if (gr->weight[l] && (s = ok(wgrad_rm(h, Hd, Hd, P, dz[cur], act[l - 1], gr->weight[l], part, tmp, st), "dW")))
+            return s;
+        if (gr->bias[l]) launch_colsum(dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
+        if ((s = ok(gemm_rm(h, false, false, P, Hd, Hd, dz[cur], Hd, d.w[l], Hd, dz[cur ^ 1], Hd), "sgemm dz")))
+            return s;
+        launch_relu_mask(dz[cur ^ 1], act[l - 1], P, st);
+        cur ^= 1;
+    }
+    // ---- layer 1: dz[cur] is the gradient of its pre-activations
+    const float* dz0 = dz[cur];
+    if (gr->bias[0]) launch_colsum(dz0, P, Hd, 1, 0, tmp, gr->bias[0], 0, st);
+    if (gr->weight[0]) {
+        float* S = Pm;  // per Gaussian, summed over the batch (N x 256)
+        launch_colsum(dz0, B, N * Hd, 1, 0, tmp, S, 0, st);
+        // per query, summed over the Gaussians (B x 256)
+        launch_colsum(dz0, N, Hd, B, N * Hd, tmp, R, Hd, st);
+        // dW1 [256 x 89] = [S^T gamma(mu_hat) | R^T gamma(s_hat)]
+        if ((s = ok(gemm_rm(h, true, false, Hd, kMeanFeat, N, S, Hd, fmean, kMeanFeat, gr->weight[0], I), "dW1m")))
+            return s;
+        if ((s = ok(gemm_rm(h, true, false, Hd, kTxFeat, B, R, Hd, ftx, kTxFeat, gr->weight[0] + kMeanFeat, I),
+                    "dW1s")))
+            return s;
+    }
+    launch_pe_backward(dz0, d, B, (float*)w.dmu.ptr, st);
+    return hip(hipGetLastError(), "mlp backward");
+}
 
 swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out, const void* aux,
                          const swf_grads* gr, hipStream_t st) {
@@ -32,39 +175,10 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     }
     launch_preprocess_backward((const float*)w.dpair.ptr, w.rec, P, (flags & SWF_PAPER_DEFORM) != 0,
                                (float*)w.dbase.ptr, dy, st);
-    // 4. MLP backward (FP32, activations recomputed)
+    // 4. MLP backward (FP32: activations recomputed, GEMMs in rocBLAS)
     float* dmu = nullptr;
     if (want_mlp) {
-        const int nh = d.n_hidden;
-        const size_t actb = (size_t)P * 256 * sizeof(float);
-        if ((s = w.act.reserve(this, actb * nh + 16, st))) return s;
-        if ((s = w.dz.reserve(this, actb * 2 + 16, st))) return s;
-        if ((s = w.part.reserve(this, (size_t)wgrad_chunks(P) * 256 * 256 * sizeof(float) + 16, st))) return s;
-        if ((s = w.fmean.reserve(this, (size_t)d.n * kMeanFeat * sizeof(float) + 16, st))) return s;
-        if ((s = w.ftx.reserve(this, (size_t)B * kTxFeat * sizeof(float) + 16, st))) return s;
-        if ((s = w.dmu.reserve(this, (size_t)d.n * 2 * sizeof(float) + 16, st))) return s;
-        if ((s = w.qs.reserve(this, (size_t)B * d.hidden * sizeof(float), st))) return s;
-        float* act[8] = {};
-        for (int l = 0; l < nh; ++l) act[l] = (float*)((char*)w.act.ptr + actb * l);
-        launch_tx_features(d, tx, B, (float*)w.qs.ptr, st, (float*)w.ftx.ptr);
-        const Grid g = w.last.grid;
-        Records none;
-        launch_mlp_fp32(d, (const float*)w.qs.ptr, B, g, false, none, nullptr, st, act);
-        launch_mean_features_f32(d, (float*)w.fmean.ptr, st);
-        float* dz[2] = {(float*)w.dz.ptr, (float*)((char*)w.dz.ptr + actb)};
-        float* part = (float*)w.part.ptr;
-        // output layer
-        launch_wgrad(dy, kOut, act[nh - 1], 256, nullptr, nullptr, d.n, P, part, gr->weight[nh], gr->bias[nh], st);
-        launch_dgrad(dy, kOut, d.w[nh], act[nh - 1], P, dz[0], st);
-        int cur = 0;
-        for (int l = nh - 1; l >= 1; --l) {
-            launch_wgrad(dz[cur], 256, act[l - 1], 256, nullptr, nullptr, d.n, P, part, gr->weight[l], gr->bias[l], st);
-            launch_dgrad(dz[cur], 256, d.w[l], act[l - 1], P, dz[cur ^ 1], st);
-            cur ^= 1;
-        }
-        launch_wgrad(dz[cur], 256, nullptr, d.in_dim, (const float*)w.fmean.ptr, (const float*)w.ftx.ptr, d.n, P,
-                     part, gr->weight[0], gr->bias[0], st);
-        launch_pe_backward(dz[cur], d, B, (float*)w.dmu.ptr, st);
+        if ((s = mlp_backward(w, d, tx, B, dy, gr, st))) return s;
         dmu = (float*)w.dmu.ptr;
     }
     // 5. base parameters: sum over the batch, original ids

@@ -182,144 +182,76 @@ __global__ void base_reduce_kernel(const float* __restrict__ dbase, const float*
         if (out[k]) out[k][id] = s[k];
 }
 
-// out[r][j] = sum_{k<K} in[r][k] * Wrm[k][j] (* [H[r][j] > 0] when H), r < P,
-// j < 256. Wrm is a layer weight read as [K][256] (row-major [out][in] of the
-// layer whose output dimension is K). 32 rows per block, thread owns 4 x 8.
-__global__ __launch_bounds__(256) void dgrad_kernel(const float* __restrict__ in, int K, const float* __restrict__ Wrm,
-                                                    const float* __restrict__ Hm, int64_t P,
-                                                    float* __restrict__ out) {
-    __shared__ __attribute__((aligned(16))) float xs[32][36];
-    __shared__ __attribute__((aligned(16))) float ws[32][256];
-    const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
-    const int64_t r0 = (int64_t)blockIdx.x * 32;
-    float acc[4][8];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc[i][c] = 0.f;
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        __syncthreads();
-        for (int e = tid; e < 32 * 32; e += 256) {
-            const int rr = e >> 5, kk = e & 31;
-            const int64_t r = r0 + rr;
-            xs[rr][kk] = (r < P && k0 + kk < K) ? in[r * K + k0 + kk] : 0.f;
-        }
-        for (int e = tid; e < 32 * 256; e += 256) {
-            const int kk = e >> 8, j = e & 255;
-            ws[kk][j] = (k0 + kk < K) ? Wrm[(size_t)(k0 + kk) * 256 + j] : 0.f;
-        }
-        __syncthreads();
-        const int kn = min(32, K - k0);
-        for (int kk = 0; kk < kn; ++kk) {
-            const float4 w0 = *reinterpret_cast<const float4*>(&ws[kk][tc * 8]);
-            const float4 w1 = *reinterpret_cast<const float4*>(&ws[kk][tc * 8 + 4]);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float x = xs[tr * 4 + i][kk];
-                acc[i][0] = fmaf(x, w0.x, acc[i][0]); acc[i][1] = fmaf(x, w0.y, acc[i][1]);
-                acc[i][2] = fmaf(x, w0.z, acc[i][2]); acc[i][3] = fmaf(x, w0.w, acc[i][3]);
-                acc[i][4] = fmaf(x, w1.x, acc[i][4]); acc[i][5] = fmaf(x, w1.y, acc[i][5]);
-                acc[i][6] = fmaf(x, w1.z, acc[i][6]); acc[i][7] = fmaf(x, w1.w, acc[i][7]);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t r = r0 + tr * 4 + i;
-        if (r >= P) continue;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int j = tc * 8 + c;
-            float v = acc[i][c];
-            if (Hm && !(Hm[r * 256 + j] > 0.f)) v = 0.f;
-            out[r * 256 + j] = v;
-        }
-    }
+// ---- MLP backward helpers (the GEMMs run in rocBLAS) --------------------------
+// act0[p][k] = ReLU(Pm[p mod N][k] + qs[p / N][k]): layer-1 activations from
+// the per-Gaussian mean part and the per-query TX part (with the bias)
+__global__ void layer1_act_kernel(const float* __restrict__ Pm, const float* __restrict__ qs, int N, int64_t P,
+                                  float* __restrict__ act) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * 64) return;
+    const int64_t p = i >> 6;
+    const int k = (int)(i & 63) * 4;
+    const int64_t q = p / N, n = p - q * N;
+    const float4 a = *reinterpret_cast<const float4*>(Pm + n * 256 + k);
+    const float4 b = *reinterpret_cast<const float4*>(qs + q * 256 + k);
+    *reinterpret_cast<float4*>(act + p * 256 + k) =
+        make_float4(fmaxf(a.x + b.x, 0.f), fmaxf(a.y + b.y, 0.f), fmaxf(a.z + b.z, 0.f), fmaxf(a.w + b.w, 0.f));
 }
 
-// Partial weight gradients dW[o][i] = sum_{r in chunk} dz[r][o] X[r][i] for a
-// 64 x 64 output tile (thread owns 4 x 4). X rows come from one matrix
-// (ld = I) or, for layer 1, from the per-Gaussian mean features (26) and the
-// per-query transceiver features (63). part is [chunks][O][I].
-__global__ __launch_bounds__(256) void wgrad_partial_kernel(const float* __restrict__ dz, int O,
-                                                            const float* __restrict__ X, int I,
-                                                            const float* __restrict__ fmean,
-                                                            const float* __restrict__ ftx, int N, int64_t P,
-                                                            int64_t rows_per_chunk, float* __restrict__ part) {
-    __shared__ float zs[32][65];
-    __shared__ float xs[32][65];
-    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-    const int o0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
-    const int64_t rb = (int64_t)blockIdx.z * rows_per_chunk;
-    const int64_t re = min(rb + rows_per_chunk, P);
-    float acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = 0.f;
-    for (int64_t r0 = rb; r0 < re; r0 += 32) {
-        __syncthreads();
-        for (int e = tid; e < 32 * 64; e += 256) {
-            const int rr = e >> 6, cc = e & 63;
-            const int64_t r = r0 + rr;
-            const bool okr = r < re;
-            zs[rr][cc] = (okr && o0 + cc < O) ? dz[r * O + o0 + cc] : 0.f;
-            float xv = 0.f;
-            const int ii = i0 + cc;
-            if (okr && ii < I) {
-                if (X) {
-                    xv = X[r * I + ii];
-                } else {
-                    xv = ii < kMeanFeat ? fmean[(r % N) * kMeanFeat + ii] : ftx[(r / N) * kTxFeat + ii - kMeanFeat];
-                }
-            }
-            xs[rr][cc] = xv;
-        }
-        __syncthreads();
-#pragma unroll 4
-        for (int rr = 0; rr < 32; ++rr) {
-            float zv[4], xv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) zv[a] = zs[rr][ty * 4 + a];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) xv[c] = xs[rr][tx * 4 + c];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(zv[a], xv[c], acc[a][c]);
-        }
-    }
-    float* dst = part + (size_t)blockIdx.z * O * I;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int o = o0 + ty * 4 + a;
-        if (o >= O) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = i0 + tx * 4 + c;
-            if (i < I) dst[(size_t)o * I + i] = acc[a][c];
-        }
-    }
+// z[p][k] = ReLU(z[p][k] + bias[k]) in place (256 columns)
+__global__ void bias_relu_kernel(float* __restrict__ z, const float* __restrict__ bias, int64_t P) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * 64) return;
+    const int k = (int)(i & 63) * 4;
+    float4 v = *reinterpret_cast<float4*>(z + i * 4);
+    const float4 b = *reinterpret_cast<const float4*>(bias + k);
+    v = make_float4(fmaxf(v.x + b.x, 0.f), fmaxf(v.y + b.y, 0.f), fmaxf(v.z + b.z, 0.f), fmaxf(v.w + b.w, 0.f));
+    *reinterpret_cast<float4*>(z + i * 4) = v;
 }
 
-__global__ void chunk_sum_kernel(const float* __restrict__ part, int chunks, int64_t m, float* __restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
+// d[p][k] *= (act[p][k] > 0): back through the ReLU (256 columns)
+__global__ void relu_mask_kernel(float* __restrict__ d, const float* __restrict__ act, int64_t P) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * 64) return;
+    float4 v = *reinterpret_cast<float4*>(d + i * 4);
+    const float4 a = *reinterpret_cast<const float4*>(act + i * 4);
+    v = make_float4(a.x > 0.f ? v.x : 0.f, a.y > 0.f ? v.y : 0.f, a.z > 0.f ? v.z : 0.f, a.w > 0.f ? v.w : 0.f);
+    *reinterpret_cast<float4*>(d + i * 4) = v;
+}
+
+// Column sums of row-major [rows x cols] matrices (one per z, batch stride
+// bs), in two stages: part[z][y][c] over row block y, then out[z][c].
+__global__ __launch_bounds__(256) void colsum_stage1_kernel(const float* __restrict__ A, int64_t rows, int64_t cols,
+                                                            int64_t rpb, int64_t bs, float* __restrict__ part) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= cols) return;
+    const float* Az = A + (int64_t)blockIdx.z * bs;
+    const int64_t r0 = (int64_t)blockIdx.y * rpb, r1 = min(rows, r0 + rpb);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int64_t r = r0;
+    for (; r + 4 <= r1; r += 4) {
+        s0 += Az[r * cols + c];
+        s1 += Az[(r + 1) * cols + c];
+        s2 += Az[(r + 2) * cols + c];
+        s3 += Az[(r + 3) * cols + c];
+    }
+    for (; r < r1; ++r) s0 += Az[r * cols + c];
+    part[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * cols + c] = (s0 + s1) + (s2 + s3);
+}
+
+__global__ __launch_bounds__(256) void colsum_stage2_kernel(const float* __restrict__ part, int nblk, int64_t cols,
+                                                            float* __restrict__ out, int64_t out_bs) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= cols) return;
+    const float* pz = part + (int64_t)blockIdx.y * nblk * cols;
     float s = 0.f;
-    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * m + e];
-    out[e] = s;
+    for (int b = 0; b < nblk; ++b) s += pz[(int64_t)b * cols + c];
+    out[(int64_t)blockIdx.y * out_bs + c] = s;
 }
 
-// Column sums of dz (P x O) per row chunk: part[chunk][o].
-__global__ __launch_bounds__(256) void colsum_partial_kernel(const float* __restrict__ dz, int O, int64_t P,
-                                                             int64_t rows_per_chunk, float* __restrict__ part) {
-    const int o = blockIdx.x * 256 + threadIdx.x;
-    if (o >= O) return;
-    const int64_t rb = (int64_t)blockIdx.y * rows_per_chunk;
-    const int64_t re = min(rb + rows_per_chunk, P);
-    float s = 0.f;
-    for (int64_t r = rb; r < re; ++r) s += dz[r * O + o];
-    part[(size_t)blockIdx.y * O + o] = s;
+__global__ void fill_kernel(float* __restrict__ p, float v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // d gamma(mu_hat) (26 per row) -> d mu0 per Gaussian, summed over the batch.
@@ -368,6 +300,7 @@ __global__ void mean_features_f32_kernel(const float* __restrict__ mx, const flo
     for (int k = 0; k < kMeanFeat; ++k) out[(size_t)p * kMeanFeat + k] = f[k];
 }
 
+
 }  // namespace
 
 void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
@@ -395,28 +328,32 @@ void launch_base_reduce(const float* dbase, const float* dmu_pe, const uint32_t*
     if (N > 0) base_reduce_kernel<<<(N + 255) / 256, 256, 0, st>>>(dbase, dmu_pe, perm, B, N, out_dev);
 }
 
-void launch_dgrad(const float* in, int K, const float* Wrm, const float* Hmask, int64_t P, float* out,
-                  hipStream_t st) {
-    if (P > 0) dgrad_kernel<<<(unsigned)((P + 31) / 32), 256, 0, st>>>(in, K, Wrm, Hmask, P, out);
+void launch_layer1_act(const float* Pm, const float* qs, int N, int64_t P, float* act, hipStream_t st) {
+    if (P > 0) layer1_act_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(Pm, qs, N, P, act);
 }
 
-int64_t wgrad_chunks(int64_t P) { return std::max<int64_t>(1, std::min<int64_t>(256, (P + 4095) / 4096)); }
+void launch_bias_relu(float* z, const float* bias, int64_t P, hipStream_t st) {
+    if (P > 0) bias_relu_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(z, bias, P);
+}
 
-void launch_wgrad(const float* dz, int O, const float* X, int I, const float* fmean, const float* ftx, int N, int64_t P,
-                  float* part, float* dW, float* db, hipStream_t st) {
-    const int64_t chunks = wgrad_chunks(P);
-    const int64_t rpc = (P + chunks - 1) / chunks;
-    if (dW) {
-        dim3 grid((O + 63) / 64, (I + 63) / 64, (unsigned)chunks);
-        wgrad_partial_kernel<<<grid, 256, 0, st>>>(dz, O, X, I, fmean, ftx, N, P, rpc, part);
-        const int64_t m = (int64_t)O * I;
-        chunk_sum_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(part, (int)chunks, m, dW);
-    }
-    if (db) {
-        dim3 grid((O + 255) / 256, (unsigned)chunks);
-        colsum_partial_kernel<<<grid, 256, 0, st>>>(dz, O, P, rpc, part);
-        chunk_sum_kernel<<<(unsigned)((O + 255) / 256), 256, 0, st>>>(part, (int)chunks, O, db);
-    }
+void launch_relu_mask(float* d, const float* act, int64_t P, hipStream_t st) {
+    if (P > 0) relu_mask_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(d, act, P);
+}
+
+int colsum_blocks(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, (rows + 511) / 512)); }
+
+void launch_colsum(const float* A, int64_t rows, int64_t cols, int nz, int64_t bs, float* part, float* out,
+                   int64_t out_bs, hipStream_t st) {
+    if (cols <= 0 || nz <= 0) return;
+    const int nblk = colsum_blocks(rows);
+    const int64_t rpb = (rows + nblk - 1) / nblk;
+    const unsigned gx = (unsigned)((cols + 255) / 256);
+    colsum_stage1_kernel<<<dim3(gx, nblk, nz), 256, 0, st>>>(A, rows, cols, rpb, bs, part);
+    colsum_stage2_kernel<<<dim3(gx, nz), 256, 0, st>>>(part, nblk, cols, out, out_bs);
+}
+
+void launch_fill(float* p, float v, int64_t n, hipStream_t st) {
+    if (n > 0) fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, v, n);
 }
 
 void launch_pe_backward(const float* dz0, const DevScene& s, int B, float* dmu, hipStream_t st) {

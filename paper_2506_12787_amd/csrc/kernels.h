@@ -96,11 +96,16 @@ void launch_preprocess_backward(const float* dpair, const Records& r, int64_t P,
                                 float* dy, hipStream_t st);
 void launch_base_reduce(const float* dbase, const float* dmu_pe, const uint32_t* perm, int B, int N,
                         float* const* out_dev, hipStream_t st);
-void launch_dgrad(const float* in, int K, const float* Wrm, const float* Hmask, int64_t P, float* out,
-                  hipStream_t st);
-int64_t wgrad_chunks(int64_t P);
-void launch_wgrad(const float* dz, int O, const float* X, int I, const float* fmean, const float* ftx, int N, int64_t P,
-                  float* part, float* dW, float* db, hipStream_t st);
+// MLP backward helpers (the GEMMs themselves run in rocBLAS)
+void launch_layer1_act(const float* Pm, const float* qs, int N, int64_t P, float* act, hipStream_t st);
+void launch_bias_relu(float* z, const float* bias, int64_t P, hipStream_t st);
+void launch_relu_mask(float* d, const float* act, int64_t P, hipStream_t st);
+void launch_fill(float* p, float v, int64_t n, hipStream_t st);
+// out[z * out_bs + c] = sum_r A[z * bs + r * cols + c] for z < nz; part holds
+// colsum_blocks(rows) * cols * nz floats
+int colsum_blocks(int64_t rows);
+void launch_colsum(const float* A, int64_t rows, int64_t cols, int nz, int64_t bs, float* part, float* out,
+                   int64_t out_bs, hipStream_t st);
 void launch_pe_backward(const float* dz0, const DevScene& s, int B, float* dmu, hipStream_t st);
 void launch_mean_features_f32(const DevScene& s, float* out, hipStream_t st);
 

@@ -651,6 +651,7 @@ swf_status swf_destroy(swf_ctx* h) {
     }
     c->scenes.clear();
     c->ws.release();
+    blas_release(c);
     c->resolve_timing();
     for (auto e : c->event_pool) hipEventDestroy(e);
     delete c;
