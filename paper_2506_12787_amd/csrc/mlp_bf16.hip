@@ -35,15 +35,24 @@ typedef short short2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// One v_cvt_pk_bf16_f32 (round to nearest even). Written as a vector
+// conversion: two scalar conversions would each take an instruction and a
+// v_perm_b32 would then merge them.
 __device__ __forceinline__ uint32_t cvt_pk_bf16(float a, float b) {
-    const bf16x2 v = {(__bf16)a, (__bf16)b};  // v_cvt_pk_bf16_f32, round to nearest even
-    return __builtin_bit_cast(uint32_t, v);
+    const f32x2 f = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
 }
 
 constexpr int kChunkBytes = 32768;          // one ring step: 32 fragments of 1 KiB
 constexpr int kChunkU4 = kChunkBytes / 16;  // uint4 per step (2048)
 constexpr int kPF = kChunkU4 / 256;         // uint4 per thread per step (8)
 constexpr int kSlots = 3;
+#ifndef SWF_PF_DEPTH
+#define SWF_PF_DEPTH 2
+#endif
+constexpr int kDepth = SWF_PF_DEPTH;  // weight fragments read ahead of the MFMA using them (<= 8)
 
 struct Bf16Args {
     MlpArgs m;
@@ -101,7 +110,7 @@ __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0
 // copied global -> LDS directly (global_load_lds, no registers) at the start of
 // step q into the slot read during step q - 1; each wave waits for its copies
 // before the barrier ending step q, so the slot is complete from step q + 1 on.
-// Fragment reads run two fragments ahead, into the next slot past the end of a
+// Fragment reads run kDepth fragments ahead, into the next slot past the end of a
 // step.
 //
 // Hidden layers run output-tile-major: tile t (16 features) accumulates its
@@ -163,13 +172,17 @@ mlp_bf16_kernel(Bf16Args a) {
         if (q + 2 < q_end) SWF_DMA(slot == 0 ? 2 : slot - 1); \
     } while (0)
 #define SWF_FRAG_AT(s_, t_) __builtin_bit_cast(bf16x8, ring[(s_) * kChunkU4 + (t_) * 64 + lane])
-    bf16x8 w_a = SWF_FRAG_AT(0, 0), w_b = SWF_FRAG_AT(0, 1);
+    // fragments f + 1 .. f + kDepth of the stream, read ahead
+    bf16x8 wq[kDepth];
+#pragma unroll
+    for (int i = 0; i < kDepth; ++i) wq[i] = SWF_FRAG_AT(0, i);
 #define SWF_TAKE(dst_, f_, nf_)                                                                          \
     do {                                                                                                 \
-        dst_ = w_a;                                                                                      \
-        w_a = w_b;                                                                                       \
+        dst_ = wq[0];                                                                                    \
+        _Pragma("unroll") for (int i_ = 0; i_ + 1 < kDepth; ++i_) wq[i_] = wq[i_ + 1];                  \
         const int nxt_ = slot == 2 ? 0 : slot + 1;                                                       \
-        w_b = (f_) + 2 < (nf_) ? SWF_FRAG_AT(slot, (f_) + 2) : SWF_FRAG_AT(nxt_, (f_) + 2 - (nf_));      \
+        wq[kDepth - 1] = (f_) + kDepth < (nf_) ? SWF_FRAG_AT(slot, (f_) + kDepth)                        \
+                                                : SWF_FRAG_AT(nxt_, (f_) + kDepth - (nf_));              \
     } while (0)
 #define SWF_NEXT_STEP()                  \
     do {                                 \
