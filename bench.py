@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--width", type=int, default=360)
     p.add_argument("--mlp", choices=("bf16", "fp32"), default="bf16")
     p.add_argument("--plain-queries", type=int, default=16)
-    p.add_argument("--pairs-per-wave", type=int, default=0, help="BF16 MLP pairs per wave (32, the default, or 64)")
+    p.add_argument("--pairs-per-wave", type=int, default=0, help="BF16 MLP pairs per wave (48, the default, 32 or 64)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--quick", action="store_true", help="timed steps only (for profiler runs)")
@@ -86,7 +86,7 @@ def mlp_sources_hash():
 
 
 def workload_key(a):
-    ppw = a.pairs_per_wave or 32
+    ppw = a.pairs_per_wave or 48
     return f"n{a.n}_h{a.height}_w{a.width}_b{a.batch}_{a.mlp}_ppw{ppw}"
 
 

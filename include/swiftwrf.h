@@ -83,8 +83,8 @@ typedef struct swf_ctx swf_ctx;
 
 typedef struct {
     int32_t device;             /* HIP device ordinal                             */
-    int32_t mlp_pairs_per_wave; /* BF16 MLP tuning: pairs per wave, 32 (default
-                                   or 0: two waves per SIMD) or 64 (one wave)     */
+    int32_t mlp_pairs_per_wave; /* BF16 MLP tuning: pairs per wave, 48 (default
+                                   or 0) or 32 (two waves per SIMD), or 64 (one)  */
     int32_t reserved[6];
 } swf_config;
 

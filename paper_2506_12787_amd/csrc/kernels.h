@@ -23,7 +23,7 @@ struct DevScene {
     float *w1m_t = nullptr;         // [26][hidden]   layer-1 mean part, in-major
     float *wh_t[8] = {};            // [hidden][hidden] hidden->hidden, in-major
     float *wo_t = nullptr;          // [hidden][7]
-    uint16_t *bf_stream = nullptr;  // BF16 weights in MFMA fragment order (16 KiB chunks)
+    uint16_t *bf_stream = nullptr;  // BF16 weights in MFMA fragment order (16 KiB units)
     uint16_t *bf_mfeat = nullptr;   // [n][32] BF16 gamma(mu_hat), zero padded
     float room_lo[3] = {0, 0, 0}, room_hi[3] = {6, 6, 3};
     uint64_t bytes = 0;

@@ -12,13 +12,15 @@
 // f(g, j) = j < 4 ? 4g + j : 16 + 4g + (j - 4). Activations never leave the
 // registers between layers.
 //
-// A workgroup owns 256 pairs: 8 waves of 32 pairs (2 column blocks of 16, two
-// waves per SIMD; the default) or 4 waves of 64 pairs (one wave per SIMD, each
-// weight fragment read from LDS feeds twice the MFMAs). Weight fragments (1 KiB
-// each: 64 lanes x 8 bf16, in lane order) are streamed from a packed global
-// buffer through a 3-slot LDS ring of 32 KiB steps with one barrier per step;
-// the workgroups are persistent so the weight stream never drains between
-// tiles.
+// A workgroup owns 384 pairs by default: 8 waves (two per SIMD, all 256
+// VGPRs each) of 48 pairs, 3 column blocks of 16, so each weight fragment read
+// from LDS feeds 3 MFMAs and each weight step copied into LDS serves 384 pairs.
+// Both LDS traffic terms bound this kernel: 8 waves reading every fragment and
+// the copies writing them. Variants: 8 waves of 32 pairs or 4 waves of 64
+// (256-pair workgroups). Weight fragments (1 KiB each: 64 lanes x 8 bf16, in
+// lane order) are streamed from a packed global buffer through a 3-slot LDS ring
+// of 32-fragment steps with one barrier per step; the workgroups are persistent
+// so the weight stream never drains between tiles.
 #include "kernels.h"
 #include "mlp_common.h"
 #include "swf_device.h"
@@ -45,9 +47,7 @@ __device__ __forceinline__ uint32_t cvt_pk_bf16(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
 }
 
-constexpr int kChunkBytes = 32768;          // one ring step: 32 fragments of 1 KiB
-constexpr int kChunkU4 = kChunkBytes / 16;  // uint4 per step (2048)
-constexpr int kPF = kChunkU4 / 256;         // uint4 per thread per step (8)
+constexpr int kUnitU4 = 1024;  // uint4 per 16 KiB unit of the weight stream
 constexpr int kSlots = 3;
 #ifndef SWF_PF_DEPTH
 #define SWF_PF_DEPTH 2
@@ -57,7 +57,7 @@ constexpr int kDepth = SWF_PF_DEPTH;  // weight fragments read ahead of the MFMA
 struct Bf16Args {
     MlpArgs m;
     const uint4* stream;      // packed weight chunks
-    int n_chunks;             // ring steps per tile: 2 + 4 * (n_hidden - 1)
+    int n_steps;              // ring steps per tile: 2 + (128 / STEP) * (n_hidden - 1)
     const bf16x8* mfeat;      // [N][32] bf16 mean features (4 x bf16x8 per Gaussian)
     const float* bias_h[7];   // biases of hidden layers 1..n_hidden-1
     const float* bias_o;      // output bias
@@ -102,11 +102,10 @@ __device__ __forceinline__ void dma_b128(const uint4* src, uint32_t lds_addr) {
 // s_waitcnt vmcnt(0): every vector memory operation of this wave has completed.
 __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-// NCB column blocks of 16 pairs per wave (64 or 32 pairs); WAVES waves per
-// block, so that a block always covers 256 pairs: 4 waves of 64 pairs (one
-// wave per SIMD) or 8 waves of 32 pairs (two per SIMD, half the registers).
+// NCB column blocks of 16 pairs per wave; WAVES waves per block; ring steps of
+// STEP fragments; WPE waves per SIMD.
 //
-// Weight ring: kSlots LDS slots of one 32 KiB step each. The step q + 2 is
+// Weight ring: kSlots LDS slots of one step each. The step q + 2 is
 // copied global -> LDS directly (global_load_lds, no registers) at the start of
 // step q into the slot read during step q - 1; each wave waits for its copies
 // before the barrier ending step q, so the slot is complete from step q + 1 on.
@@ -118,14 +117,16 @@ __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0
 // + bf16 conversion into the next layer's act[c'] is issued among the MFMAs of
 // the following tile (one column block per two fragments) instead of after
 // the layer; the last pair is converted during the next layer's first tile.
-template <int NCB, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES / 4, WAVES / 4))) void
+template <int NCB, int WAVES, int STEP, int WPE>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void
 mlp_bf16_kernel(Bf16Args a) {
     typedef __attribute__((address_space(3))) void* lds_ptr;
     constexpr int kPairsPerWave = 16 * NCB;
     constexpr int kPairsPerBlock = WAVES * kPairsPerWave;
-    static_assert(kPairsPerBlock == 256, "a block covers 256 pairs");
-    __shared__ __attribute__((aligned(16))) uint4 ring[kSlots * kChunkU4];
+    static_assert(kPairsPerBlock % 64 == 0, "whole 64-pair groups per block");
+    static_assert(STEP == 16 || STEP == 32, "ring steps of 16 or 32 fragments");
+    constexpr int kStepU4 = STEP * 64;  // uint4 per ring slot
+    __shared__ __attribute__((aligned(16))) uint4 ring[kSlots * kStepU4];
     __shared__ float outs[WAVES][kPairsPerWave][8];
     // Layer-1 TX term of the current and the next tile's query, hidden and
     // output biases: C operands read from LDS.
@@ -138,7 +139,7 @@ mlp_bf16_kernel(Bf16Args a) {
     const int lane = tid & 63;
     const int g = lane >> 4;       // lane group (k / feature sub-block)
     const int n16 = lane & 15;     // pair column inside a 16-wide block
-    const int S = a.n_chunks;
+    const int S = a.n_steps;
     const int n_mid = a.m.n_mid;
 
     // tiles of this persistent workgroup
@@ -153,12 +154,17 @@ mlp_bf16_kernel(Bf16Args a) {
 
     int fetch = 0;  // stream step of the next copy
     const uint32_t ring_lds = (uint32_t)(uintptr_t)(lds_ptr)ring;  // LDS byte address of the ring
+    // Step `fetch` of the stream: layer 1 (16 fragments) is step 0, the output
+    // layer (8 fragments) step S - 1; only the fragments a step holds are copied.
+    // Fragment i * WAVES + wave of the step is piece i of the wave.
 #define SWF_DMA(slot_)                                                                                     \
     do {                                                                                                   \
-        const uint4* src_ = a.stream + (size_t)fetch * kChunkU4 + tid;                                     \
-        const uint32_t dst_ = ring_lds + (uint32_t)((slot_) * kChunkBytes + wave * 1024);                  \
-        _Pragma("unroll") for (int i_ = 0; i_ < 32 / WAVES; ++i_)                                          \
-            dma_b128(src_ + i_ * 64 * WAVES, dst_ + i_ * 1024 * WAVES);                                    \
+        const int unit_ = STEP == 32 ? (fetch == 0 ? 0 : 2 * fetch - 1) : fetch;                           \
+        const int nf_ = fetch == 0 ? 16 : (fetch == S - 1 ? 8 : STEP);                                    \
+        const uint4* src_ = a.stream + (size_t)unit_ * kUnitU4 + tid;                                      \
+        const uint32_t dst_ = ring_lds + (uint32_t)((slot_) * STEP * 1024 + wave * 1024);                  \
+        _Pragma("unroll") for (int i_ = 0; i_ < STEP / WAVES; ++i_)                                        \
+            if (i_ * WAVES + wave < nf_) dma_b128(src_ + i_ * 64 * WAVES, dst_ + i_ * 1024 * WAVES);       \
         fetch = fetch + 1 == S ? 0 : fetch + 1;                                                            \
     } while (0)
     SWF_DMA(0);
@@ -171,7 +177,7 @@ mlp_bf16_kernel(Bf16Args a) {
     do {                                                      \
         if (q + 2 < q_end) SWF_DMA(slot == 0 ? 2 : slot - 1); \
     } while (0)
-#define SWF_FRAG_AT(s_, t_) __builtin_bit_cast(bf16x8, ring[(s_) * kChunkU4 + (t_) * 64 + lane])
+#define SWF_FRAG_AT(s_, t_) __builtin_bit_cast(bf16x8, ring[(s_) * kStepU4 + (t_) * 64 + lane])
     // fragments f + 1 .. f + kDepth of the stream, read ahead
     bf16x8 wq[kDepth];
 #pragma unroll
@@ -211,10 +217,10 @@ mlp_bf16_kernel(Bf16Args a) {
         const float* bias_ = &bias_s[(L_)][4 * g];                                                       \
         _Pragma("unroll") for (int t = 0; t < 16; ++t) {                                                 \
             _Pragma("unroll") for (int c = 0; c < 8; ++c) {                                              \
-                const int f = t * 8 + c;                                                                 \
-                if ((f & 31) == 0) SWF_ADVANCE();                                                        \
+                const int f = (t * 8 + c) % STEP;                                                        \
+                if (f == 0) SWF_ADVANCE();                                                               \
                 bf16x8 w;                                                                                \
-                SWF_TAKE(w, f & 31, 32);                                                                 \
+                SWF_TAKE(w, f, STEP);                                                                    \
                 if (c == 0) {                                                                            \
                     const float4 b4 = *reinterpret_cast<const float4*>(bias_ + 16 * t);                 \
                     const f32x4 c0 = {b4.x, b4.y, b4.z, b4.w};                                           \
@@ -228,7 +234,7 @@ mlp_bf16_kernel(Bf16Args a) {
                 if (t >= 2 && (t & 1) == 0 && (c & 1) == 0 && c / 2 < NCB)                               \
                     SWF_PACK(act[OUT_], (t - 2) / 2, c / 2);                                             \
                 __builtin_amdgcn_sched_barrier(0);                                                       \
-                if ((f & 31) == 31) SWF_NEXT_STEP();                                                     \
+                if (f == STEP - 1) SWF_NEXT_STEP();                                                      \
             }                                                                                            \
         }                                                                                                \
     } while (0)
@@ -352,19 +358,25 @@ void compute_mean_features_bf16(DevScene& s, hipStream_t st) {
                                                                       reinterpret_cast<__bf16*>(s.bf_mfeat));
 }
 
-// Workgroups of one variant that fit on a CU at once (registers and LDS decide;
-// the grid is persistent, so launching more would only queue them).
-int occupancy_query(int ncb) {
-    int n = 0;
-    const hipError_t e = ncb == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mlp_bf16_kernel<2, 8>, 512, 0)
-                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, mlp_bf16_kernel<4, 4>, 256, 0);
-    return (e == hipSuccess && n > 0) ? n : 1;
-}
-
-int resident_blocks(int ncb) {
-    static const int c2 = occupancy_query(2);  // thread-safe one-time initialisation
-    static const int c4 = occupancy_query(4);
-    return ncb == 2 ? c2 : c4;
+// One kernel variant: NCB column blocks of 16 pairs per wave, WAVES waves per
+// workgroup, ring steps of STEP fragments, WPE waves per SIMD. The grid is
+// persistent: as many workgroups as fit on the CUs at once (registers and LDS
+// decide; launching more would only queue them).
+template <int NCB, int WAVES, int STEP, int WPE>
+void launch_variant(Bf16Args a, int n, int B, int n_hidden, hipStream_t st) {
+    constexpr int kPerBlock = 16 * NCB * WAVES;
+    static const int resident = [] {  // thread-safe one-time initialisation
+        int r = 0;
+        const hipError_t e =
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, mlp_bf16_kernel<NCB, WAVES, STEP, WPE>, 64 * WAVES, 0);
+        return (e == hipSuccess && r > 0) ? r : 1;
+    }();
+    a.n_steps = 2 + (128 / STEP) * (n_hidden - 1);
+    a.tiles_per_query = (n + kPerBlock - 1) / kPerBlock;
+    a.n_tiles = a.tiles_per_query * B;
+    if (!a.n_tiles) return;
+    const int blocks = std::min(a.n_tiles, n_compute_units() * resident);
+    mlp_bf16_kernel<NCB, WAVES, STEP, WPE><<<blocks, 64 * WAVES, 0, st>>>(a);
 }
 
 void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
@@ -372,20 +384,15 @@ void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, b
     Bf16Args a{};
     a.m = make_args(s, qs, B, g, paper_mask, r, delta_out);
     a.stream = reinterpret_cast<const uint4*>(s.bf_stream);
-    a.n_chunks = 2 + 4 * (s.n_hidden - 1);
     a.mfeat = reinterpret_cast<const bf16x8*>(s.bf_mfeat);
     for (int l = 0; l + 1 < s.n_hidden && l < 7; ++l) a.bias_h[l] = s.b[l + 1];
     a.bias_o = s.b[s.n_hidden];
-    const int ncb = pairs_per_wave == 64 ? 4 : 2;  // default: 32 pairs per wave
-    const int per_block = 256;  // pairs per block for both variants
-    a.tiles_per_query = (s.n + per_block - 1) / per_block;
-    a.n_tiles = a.tiles_per_query * B;
-    if (!a.n_tiles) return;
-    const int blocks = std::min(a.n_tiles, n_compute_units() * resident_blocks(ncb));
-    if (ncb == 2)
-        mlp_bf16_kernel<2, 8><<<blocks, 512, 0, st>>>(a);
+    if (pairs_per_wave == 64)
+        launch_variant<4, 4, 32, 1>(a, s.n, B, s.n_hidden, st);  // 256 pairs, one wave per SIMD
+    else if (pairs_per_wave == 32)
+        launch_variant<2, 8, 32, 2>(a, s.n, B, s.n_hidden, st);  // 256 pairs, two waves per SIMD
     else
-        mlp_bf16_kernel<4, 4><<<blocks, 256, 0, st>>>(a);
+        launch_variant<3, 8, 32, 2>(a, s.n, B, s.n_hidden, st);  // default: 384 pairs, two waves per SIMD
 }
 
 }  // namespace swf

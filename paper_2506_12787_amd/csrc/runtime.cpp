@@ -323,9 +323,9 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
         // layout of the previous layer's output tiles. The output layer (7 rows
         // padded to 16): its 8 k-chunk fragments.
         if (!st) {
-            // steps of 32 KiB: [layer 1 | pad] [hidden chunks in pairs] [output | pad]
-            const int n_chunks = 2 + 8 * (d.n_hidden - 1) + 2;  // in 16 KiB units, padded
-            std::vector<uint16_t> t((size_t)n_chunks * 8192, 0);
+            // 16 KiB units: [layer 1] [hidden layers, 8 units each] [output | pad]
+            const int n_units = 2 + 8 * (d.n_hidden - 1);
+            std::vector<uint16_t> t((size_t)n_units * 8192, 0);
             auto fk = [](int c, int g, int j) { return 32 * c + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4)); };
             for (int tt = 0; tt < 16; ++tt)
                 for (int l = 0; l < 64; ++l)
@@ -338,7 +338,7 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
                 for (int tt = 0; tt < 16; ++tt)
                     for (int c = 0; c < 8; ++c) {
                         const int f = 8 * tt + c;  // output-tile-major fragment order
-                        const size_t at = (size_t)(2 + 8 * (L - 1)) * 8192 + (size_t)f * 512;
+                        const size_t at = (size_t)(1 + 8 * (L - 1)) * 8192 + (size_t)f * 512;
                         for (int l = 0; l < 64; ++l)
                             for (int j = 0; j < 8; ++j) {
                                 const int row = 16 * tt + (l & 15), k = fk(c, l >> 4, j);
@@ -346,7 +346,7 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
                             }
                     }
             {
-                const size_t ch = (size_t)(n_chunks - 2) * 8192;
+                const size_t ch = (size_t)(n_units - 1) * 8192;
                 for (int c = 0; c < 8; ++c)
                     for (int l = 0; l < 64; ++l)
                         for (int j = 0; j < 8; ++j) {

@@ -92,7 +92,7 @@ struct Ctx {
     int64_t stage_n[SWF_N_STAGES] = {};
 
     ServeState* serve = nullptr;
-    int mlp_pairs_per_wave = 0;  // BF16 MLP register tile: 64 (default) or 32
+    int mlp_pairs_per_wave = 0;  // BF16 MLP register tile: 48 (default, 0), 32 or 64 pairs per wave
 
     swf_status fail(swf_status s, const std::string& msg);
     swf_status hip(hipError_t e, const char* what);

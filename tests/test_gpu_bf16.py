@@ -13,9 +13,10 @@ pytestmark = pytest.mark.gpu
 H0, W0 = 90, 360
 
 
-@pytest.fixture(scope="module", params=[64, 32], ids=["ppw64", "ppw32"])
+@pytest.fixture(scope="module", params=[0, 32, 64], ids=["ppw48", "ppw32", "ppw64"])
 def ctx(request):
-    """Both register-tile variants of the MFMA kernel (64 or 32 pairs per wave)."""
+    """The three register-tile variants of the MFMA kernel: 48 pairs per wave
+    (the default; 384-pair workgroups), 32 and 64 (256-pair workgroups)."""
     import torch
     from paper_2506_12787_amd import binding
     assert torch.cuda.is_available()
