@@ -292,31 +292,33 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const K* __rest
 // ---- binning: per-query stable counting sort by tile -----------------------
 // Pairs are stored in (query, depth) order and a pair covers a tile at most
 // once, so the list of a tile is the pairs covering it in pair order. A query's
-// tiles are split into segments of 2^DB tiles (DB = 8 for up to 256 tiles per
-// query, else 11); every (query, segment) is binned by one stable counting pass
-// on a DB-bit digit, which gives exactly the order of the full (tile, depth)
-// sort without materialising keys in memory.
-//   bin_hist:    block (j, q, s) histograms the tiles of segment s covered by
-//                pairs [j * pb, (j + 1) * pb) of query q;
-//                hist[((q * S + s) * 2^DB + tile - s 2^DB) * nbq + j]
+// tiles are split into S segments of 256 (one 8-bit digit each); every query is
+// binned by a stable counting pass per segment, which gives exactly the order
+// of the full (tile, depth) sort without materialising keys in memory.
+//   bin_hist:    block (j, q) histograms the tiles covered by pairs
+//                [j * pb, (j + 1) * pb) of query q, for every segment s;
+//                hist[((q * S + s) * 256 + tile - 256 s) * nbq + j]
 //   scan:        one exclusive scan over that (query, tile, block) order gives
 //                every block's first output position per tile
-//   bin_scatter: the same block regenerates its keys in LDS (pair order) and
-//                writes each pair index to its position, ranked stably with
-//                the wave-ballot scheme of the radix scatter (DB ballots)
+//   bin_scatter: the same block, segment by segment, computes its keys in pair
+//                order and writes each pair index to its position, ranked
+//                stably with wave64 ballots over the 8 digit bits
 //   bin_ranges:  tile (q, t) spans [hist(q, t, 0), hist(q, t + 1, 0))
 struct BinGeom {
     int N, TW, tiles, db, S, pb, nbq;  // pairs per query, tile grid, digit bits, segments, pairs/block, blocks/query
 };
+
+constexpr int kSegTiles = 256;  // tiles per segment: one 8-bit digit
+constexpr int kMaxSegs = 16;    // segments one block handles (tiles per query <= 4096)
 
 BinGeom bin_geom(int N, const Grid& g) {
     BinGeom b;
     b.N = N;
     b.TW = g.TW;
     b.tiles = g.tiles;
-    b.db = g.tiles <= 256 ? 8 : 11;
-    b.S = std::max(1, (g.tiles + (1 << b.db) - 1) >> b.db);
-    b.pb = b.db == 8 ? 1024 : 8192;  // larger blocks keep the wide histogram small
+    b.db = 8;
+    b.S = std::max(1, (g.tiles + kSegTiles - 1) / kSegTiles);
+    b.pb = b.S == 1 ? 1024 : 8192;  // larger blocks keep the (S x 256 x blocks) histogram small
     b.nbq = std::max(1, (N + b.pb - 1) / b.pb);
     return b;
 }
@@ -345,127 +347,230 @@ __device__ __forceinline__ uint32_t seg_count(uint2 r, int TW, int t0, int seg) 
     return c;
 }
 
-template <int DB>
+// Tile histogram of one block of pairs of one query, for every tile segment:
+// hist[((q * S + segment) * 256 + tile % 256) * nbq + block]. With one segment
+// the counts are kept per wave (less atomic contention).
 __global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restrict__ rect,
                                                             const uint32_t* __restrict__ count, BinGeom G,
                                                             uint32_t* __restrict__ hist) {
-    constexpr int kSeg = 1 << DB;
-    constexpr int kCopies = DB == 8 ? kWaves : 1;  // per-wave copies while they are small
-    __shared__ uint32_t h[kCopies][kSeg];
-    for (int i = threadIdx.x; i < kCopies * kSeg; i += kThreads) (&h[0][0])[i] = 0;
+    __shared__ uint32_t h[kMaxSegs * kSegTiles];
+    const bool one = G.S == 1;
+    const int n = one ? kWaves * kSegTiles : G.S * kSegTiles;
+    for (int i = threadIdx.x; i < n; i += kThreads) h[i] = 0;
     __syncthreads();
-    const int w = kCopies == 1 ? 0 : (int)(threadIdx.x >> 6);
-    const int j = blockIdx.x, q = blockIdx.y / G.S, sg = blockIdx.y - q * G.S;
-    const int t0 = sg * kSeg;
+    uint32_t* hw = one ? h + (threadIdx.x >> 6) * kSegTiles : h;
+    const int j = blockIdx.x, q = blockIdx.y;
     const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, G.N);
     const size_t row0 = (size_t)q * G.N;
     for (int p = p_beg + (int)threadIdx.x; p < p_end; p += kThreads) {
         if (count[row0 + p] == 0) continue;
-        for_seg_tiles(rect[row0 + p], G.TW, t0, kSeg, [&](uint32_t, uint32_t tl) { atomicAdd(&h[w][tl], 1u); });
+        for_seg_tiles(rect[row0 + p], G.TW, 0, G.tiles, [&](uint32_t, uint32_t t) { atomicAdd(&hw[t], 1u); });
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kSeg; d += kThreads) {
-        uint32_t s = 0;
+    for (int i = threadIdx.x; i < G.S * kSegTiles; i += kThreads) {
+        uint32_t v = h[i];
+        if (one)
 #pragma unroll
-        for (int k = 0; k < kCopies; ++k) s += h[k][d];
-        hist[((size_t)blockIdx.y * kSeg + d) * G.nbq + j] = s;
+            for (int k = 1; k < kWaves; ++k) v += h[k * kSegTiles + i];
+        const int sg = i / kSegTiles, d = i - sg * kSegTiles;
+        hist[((size_t)(q * G.S + sg) * kSegTiles + d) * G.nbq + j] = v;
     }
 }
 
+// Lanes of the wave (among those with `ok`) whose DB-bit digit equals this
+// lane's: the AND over the digit's bits of the bit's ballot where this lane's
+// bit is 1 and of its complement where it is 0, written as ~(ballot ^ s) with s
+// the lane's bit sign-extended to a word. Returns (rank among them in lane
+// order, their number).
 template <int DB>
+__device__ __forceinline__ uint2 digit_match(uint32_t d, bool ok) {
+    const uint64_t v = __ballot(ok);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int b = 0; b < DB; ++b) {
+        const uint32_t sb = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // 0 or ~0
+        const uint64_t bal = __ballot(sb != 0u);
+        lo &= ~((uint32_t)bal ^ sb);
+        hi &= ~((uint32_t)(bal >> 32) ^ sb);
+    }
+    const uint64_t m = ((uint64_t)hi << 32) | lo;
+    return make_uint2((uint32_t)__popcll(m & lanemask_lt()), (uint32_t)__popcll(m));
+}
+
+// Enumeration of the keys a pair has in a tile segment [t0, t0 + seg), in the
+// row-major order of for_seg_tiles: the first intersecting row of the rectangle
+// (possibly clipped by the segment start) gives keys 0 .. n0 - 1 at tiles
+// a0 + m; the later rows are whole (only the last can be clipped by the segment
+// end, which the key count already excludes) and hold key n0 + q * w + c at
+// tile rb + q * TW + c. Tiles are relative to t0.
+struct SegRun {
+    int a0, rb;
+    uint32_t n0, w;
+    float rw;  // 1 / w
+};
+
+__device__ __forceinline__ SegRun seg_run(uint2 r, int TW, int t0, int seg) {
+    const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff;
+    const int ya = ty0 * TW + tx1 >= t0 ? ty0 : (t0 - tx1 + TW - 1) / TW;
+    const int a = max(ya * TW + tx0, t0), e = min(ya * TW + tx1, t0 + seg - 1);
+    SegRun s;
+    s.a0 = a - t0;
+    s.n0 = (uint32_t)(e - a + 1);
+    s.rb = (ya + 1) * TW + tx0 - t0;
+    s.w = (uint32_t)(tx1 - tx0 + 1);
+    s.rw = 1.0f / (float)s.w;
+    return s;
+}
+
+// Tile (relative to t0) of key m < the pair's key count in the segment.
+__device__ __forceinline__ uint32_t seg_tile_at(int a0, int rb, uint32_t n0, uint32_t w, float rw, int TW,
+                                                uint32_t m) {
+    if (m < n0) return (uint32_t)(a0 + (int)m);
+    const uint32_t mm = m - n0;
+    uint32_t q = (uint32_t)((float)mm * rw);  // m < 2^24: exact operands, at most one below
+    uint32_t c = mm - q * w;
+    if (c >= w) {
+        ++q;
+        c -= w;
+    }
+    return (uint32_t)(rb + (int)q * TW + (int)c);
+}
+
+// Stable placement of one block of pairs of one query, segment by segment
+// (the block's output positions then lie in 256 tile lists at a time). Pairs
+// are taken in batches of 256 * PPT (PPT consecutive pairs per thread; several
+// when a query has several segments, so that a batch still holds many keys of
+// one segment); the batch's keys in the segment, in pair order, are processed
+// in chunks of kTile positions, split into whole 64-key items over the waves in
+// order. Every lane computes the key at its position directly (load-balanced:
+// the owning pair is found by binary search over the batch's key offsets),
+// ranks it among equal tiles with wave64 ballots, and the ranks are offset per
+// wave and per tile through LDS counters; base[] holds each tile's next output
+// position for this block.
+template <int PPT>
 __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __restrict__ rect,
                                                                const uint32_t* __restrict__ count, BinGeom G,
                                                                const uint32_t* __restrict__ hs,
                                                                const uint64_t* __restrict__ n_dev,
                                                                uint32_t* __restrict__ vals) {
-    constexpr int kSeg = 1 << DB;
+    constexpr int kSeg = kSegTiles;
+    constexpr int kBatch = kThreads * PPT;
     // fixed-capacity run that overflowed: nothing is placed (block-uniform)
     if (n_dev && *n_dev == 0) return;
     __shared__ uint32_t base[kSeg];
     __shared__ uint32_t wcnt[kWaves][kSeg];
     __shared__ uint32_t ttot[kSeg];
     __shared__ uint32_t lds[kWaves + 1];
-    __shared__ uint32_t kbuf[kTile];  // (tile - t0) << 8 | pair within the 256-pair batch
+    // per pair of the batch: first key offset and the enumeration of its keys
+    __shared__ uint32_t s_o[kBatch], s_n0[kBatch], s_w[kBatch];
+    __shared__ int s_a0[kBatch], s_rb[kBatch];
+    __shared__ float s_rw[kBatch];
     const int w = threadIdx.x >> 6;
-    const int j = blockIdx.x, q = blockIdx.y / G.S, sg = blockIdx.y - q * G.S;
-    const int t0 = sg * kSeg;
+    const int j = blockIdx.x, q = blockIdx.y;
     const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, G.N);
     const size_t row0 = (size_t)q * G.N;
-    for (int d = threadIdx.x; d < kSeg; d += kThreads) base[d] = hs[((size_t)blockIdx.y * kSeg + d) * G.nbq + j];
-    // the next batch's (count, rect) are loaded while this one is placed
-    uint32_t c_next = 0;
-    uint2 r_next = make_uint2(0u, 0u);
-    if (p_beg + (int)threadIdx.x < p_end) {
-        c_next = count[row0 + p_beg + threadIdx.x];
-        r_next = rect[row0 + p_beg + threadIdx.x];
-    }
-    for (int s0 = p_beg; s0 < p_end; s0 += kThreads) {
-        const uint2 r = c_next ? r_next : make_uint2(0u, 0u);
-        const uint32_t c = !c_next ? 0u : (G.S == 1 ? c_next : seg_count(r, G.TW, t0, kSeg));
-        {
-            const int pn = s0 + kThreads + (int)threadIdx.x;
-            c_next = 0;
-            if (pn < p_end) {
-                c_next = count[row0 + pn];
-                r_next = rect[row0 + pn];
-            }
+    for (int sg = 0; sg < G.S; ++sg) {
+        const int t0 = sg * kSeg;
+        __syncthreads();  // the previous segment is placed
+        for (int d = threadIdx.x; d < kSeg; d += kThreads)
+            base[d] = hs[((size_t)(q * G.S + sg) * kSeg + d) * G.nbq + j];
+        // the next batch's (count, rect) are loaded while this one is placed
+        uint32_t c_next[PPT];
+        uint2 r_next[PPT];
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const int p = p_beg + (int)threadIdx.x * PPT + i;
+            c_next[i] = p < p_end ? count[row0 + p] : 0u;
+            r_next[i] = p < p_end ? rect[row0 + p] : make_uint2(0u, 0u);
         }
-        uint32_t K;
-        const uint32_t o = block_exclusive_scan<uint32_t>(c, lds, &K);  // synchronises
-        for (uint32_t c0 = 0; c0 < K; c0 += kTile) {
-            for (int i = threadIdx.x; i < kWaves * kSeg; i += kThreads) (&wcnt[0][0])[i] = 0;
-            // this thread's keys with batch positions in [c0, c0 + kTile)
-            if (c && o + c > c0 && o < c0 + kTile)
-                for_seg_tiles(r, G.TW, t0, kSeg, [&](uint32_t m, uint32_t tl) {
-                    const int64_t at = (int64_t)o + m - c0;
-                    if (at >= 0 && at < kTile) kbuf[at] = (tl << 8) | threadIdx.x;
-                });
-            __syncthreads();
-            const uint32_t n_here = min(K - c0, (uint32_t)kTile);
-            uint32_t dig[kItems], lr[kItems], pl[kItems];
-            bool ok[kItems];
+        for (int s0 = p_beg; s0 < p_end; s0 += kBatch) {
+            uint32_t c[PPT];
+            uint2 r[PPT];
+            uint32_t csum = 0;
 #pragma unroll
-            for (int jj = 0; jj < kItems; ++jj) {
-                const uint32_t idx = (uint32_t)(w * kItems + jj) * 64 + lane_id();
-                ok[jj] = idx < n_here;
-                const uint32_t k = ok[jj] ? kbuf[idx] : 0u;
-                const uint32_t d = k >> 8;
-                dig[jj] = d;
-                pl[jj] = k & 255u;
-                uint64_t match = __ballot(ok[jj]);
-#pragma unroll
-                for (int b = 0; b < DB; ++b) {
-                    const bool bit = (d >> b) & 1u;
-                    const uint64_t bal = __ballot(bit && ok[jj]);
-                    match &= bit ? bal : ~bal;
-                }
-                const uint32_t rank = (uint32_t)__popcll(match & lanemask_lt());
-                const uint32_t cnt = (uint32_t)__popcll(match);
-                uint32_t prev = 0;
-                if (ok[jj]) prev = wcnt[w][d];
-                lr[jj] = prev + rank;
-                __builtin_amdgcn_wave_barrier();
-                if (ok[jj] && rank == 0) wcnt[w][d] = prev + cnt;
-                __builtin_amdgcn_wave_barrier();
+            for (int i = 0; i < PPT; ++i) {
+                r[i] = r_next[i];
+                c[i] = !c_next[i] ? 0u : (G.S == 1 ? c_next[i] : seg_count(r[i], G.TW, t0, kSeg));
+                csum += c[i];
+                const int pn = s0 + kBatch + (int)threadIdx.x * PPT + i;
+                c_next[i] = pn < p_end ? count[row0 + pn] : 0u;
+                if (pn < p_end) r_next[i] = rect[row0 + pn];
             }
-            __syncthreads();
-            for (int d = threadIdx.x; d < kSeg; d += kThreads) {
-                uint32_t run = 0;
+            uint32_t K;
+            uint32_t o = block_exclusive_scan<uint32_t>(csum, lds, &K);  // synchronises
+            if (K == 0) continue;
 #pragma unroll
-                for (int k = 0; k < kWaves; ++k) {
-                    const uint32_t cc = wcnt[k][d];
-                    wcnt[k][d] = run;
-                    run += cc;
+            for (int i = 0; i < PPT; ++i) {
+                const int e = (int)threadIdx.x * PPT + i;  // pair within the batch
+                s_o[e] = o;
+                if (c[i]) {
+                    const SegRun sr = seg_run(r[i], G.TW, t0, kSeg);
+                    s_a0[e] = sr.a0;
+                    s_rb[e] = sr.rb;
+                    s_n0[e] = sr.n0;
+                    s_w[e] = sr.w;
+                    s_rw[e] = sr.rw;
                 }
-                ttot[d] = run;
+                o += c[i];
             }
-            __syncthreads();
+            for (uint32_t c0 = 0; c0 < K; c0 += kTile) {
+                for (int i = threadIdx.x; i < kWaves * kSeg; i += kThreads) (&wcnt[0][0])[i] = 0;
+                __syncthreads();  // counters cleared; the batch's pair table is complete
+                const uint32_t n_here = min(K - c0, (uint32_t)kTile);
+                const uint32_t ipw = ((n_here + 63) / 64 + kWaves - 1) / kWaves;  // items per wave
+                uint32_t dig[kItems], lr[kItems], pl[kItems];
+                bool ok[kItems];
 #pragma unroll
-            for (int jj = 0; jj < kItems; ++jj)
-                if (ok[jj]) vals[base[dig[jj]] + wcnt[w][dig[jj]] + lr[jj]] = (uint32_t)(row0 + s0 + pl[jj]);
-            __syncthreads();
-            for (int d = threadIdx.x; d < kSeg; d += kThreads) base[d] += ttot[d];
-            __syncthreads();
+                for (int jj = 0; jj < kItems; ++jj) {
+                    const uint32_t idx0 = ((uint32_t)w * ipw + (uint32_t)jj) * 64;
+                    ok[jj] = false;
+                    dig[jj] = lr[jj] = pl[jj] = 0;
+                    if ((uint32_t)jj >= ipw || idx0 >= n_here) continue;  // wave-uniform
+                    const uint32_t idx = idx0 + lane_id();
+                    ok[jj] = idx < n_here;
+                    uint32_t d = 0, pr = 0;
+                    if (ok[jj]) {
+                        const uint32_t gp = c0 + idx;  // key position in the batch
+                        // last pair whose first key is at or before gp (s_o is
+                        // non-decreasing; a pair without keys shares its offset
+                        // with the next pair, so the last one is the owner)
+                        int lo = 0;
+#pragma unroll
+                        for (int step = kBatch / 2; step > 0; step >>= 1)
+                            if (s_o[lo + step] <= gp) lo += step;
+                        pr = (uint32_t)lo;
+                        d = seg_tile_at(s_a0[lo], s_rb[lo], s_n0[lo], s_w[lo], s_rw[lo], G.TW, gp - s_o[lo]);
+                    }
+                    dig[jj] = d;
+                    pl[jj] = pr;
+                    const uint2 rc = digit_match<8>(d, ok[jj]);
+                    const uint32_t rank = rc.x, cnt = rc.y;
+                    uint32_t prev = 0;
+                    if (ok[jj]) prev = wcnt[w][d];
+                    lr[jj] = prev + rank;
+                    __builtin_amdgcn_wave_barrier();
+                    if (ok[jj] && rank == 0) wcnt[w][d] = prev + cnt;
+                    __builtin_amdgcn_wave_barrier();
+                }
+                __syncthreads();
+                for (int d = threadIdx.x; d < kSeg; d += kThreads) {
+                    uint32_t run = 0;
+#pragma unroll
+                    for (int k = 0; k < kWaves; ++k) {
+                        const uint32_t cc = wcnt[k][d];
+                        wcnt[k][d] = run;
+                        run += cc;
+                    }
+                    ttot[d] = run;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int jj = 0; jj < kItems; ++jj)
+                    if (ok[jj]) vals[base[dig[jj]] + wcnt[w][dig[jj]] + lr[jj]] = (uint32_t)(row0 + s0 + pl[jj]);
+                __syncthreads();
+                for (int d = threadIdx.x; d < kSeg; d += kThreads) base[d] += ttot[d];
+                __syncthreads();
+            }
         }
     }
 }
@@ -631,7 +736,7 @@ void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gt
         tile_ranges_kernel<false><<<blocks, 256, 0, st>>>(keys, n, ranges, n_dev);
 }
 
-bool bin_fits(int B, int N, const Grid& g) { return (int64_t)B * bin_geom(N, g).S <= 65535; }
+bool bin_fits(int B, int N, const Grid& g) { return B <= 65535 && bin_geom(N, g).S <= kMaxSegs; }
 
 size_t bin_hist_entries(int B, int N, const Grid& g) {
     const BinGeom G = bin_geom(N, g);
@@ -645,22 +750,17 @@ void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hi
         launch_clear_u32(hist, (int)bin_hist_entries(B, N, g), st);
         return;
     }
-    if (G.db == 8)
-        bin_hist_kernel<8><<<dim3(G.nbq, B * G.S), kThreads, 0, st>>>(r.rect, r.count, G, hist);
-    else
-        bin_hist_kernel<11><<<dim3(G.nbq, B * G.S), kThreads, 0, st>>>(r.rect, r.count, G, hist);
+    bin_hist_kernel<<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist);
 }
 
 void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* hist_scanned,
                         const uint64_t* n_dev, uint32_t* vals, hipStream_t st) {
     if (B <= 0 || N <= 0) return;
     const BinGeom G = bin_geom(N, g);
-    if (G.db == 8)
-        bin_scatter_kernel<8><<<dim3(G.nbq, B * G.S), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev,
-                                                                         vals);
+    if (G.S == 1)
+        bin_scatter_kernel<1><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev, vals);
     else
-        bin_scatter_kernel<11><<<dim3(G.nbq, B * G.S), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev,
-                                                                          vals);
+        bin_scatter_kernel<4><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev, vals);
 }
 
 void launch_bin_ranges(const uint32_t* hist_scanned, int B, int N, const Grid& g, const uint64_t* total,

@@ -91,9 +91,9 @@ def test_binned_lists_equal_full_sort(ctx, n, scale, batch, H, W):
     full 64-bit (tile, depth) radix sort: counts, keys, values and ranges
     bitwise, and the same images. Large Gaussians put tens of thousands of keys
     into one 256-pair batch (several 2048-key chunks); N is ragged against the
-    pair blocks (1024, or 8192 with 11-bit tile digits); 180 x 720 (540 tiles)
-    and 250 x 1100 (1104 tiles) take the 11-bit digit; deformation differs per
-    query."""
+    pair blocks (1024, or 8192 with several tile segments); 180 x 720 (540
+    tiles, 3 segments of 256) and 250 x 1100 (1104 tiles, 5 segments) bin segment
+    by segment; deformation differs per query."""
     import torch
     from paper_2506_12787_amd import binding as B
     from paper_2506_12787_amd import synth
@@ -113,7 +113,7 @@ def test_binned_lists_equal_full_sort(ctx, n, scale, batch, H, W):
     np.testing.assert_array_equal(outs[0], outs[1])
     if scale[0] >= 20.0:
         assert int(a["counts"].max()) > 8  # a 256-pair batch then exceeds one 2048-key chunk
-    if T > 256:  # tiles beyond one 8-bit digit
+    if T > 256:  # tiles beyond the first segment
         assert int(a["keys"][-1] >> np.uint64(32)) % T >= 256
     ctx.release_scene(sid)
 
