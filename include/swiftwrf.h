@@ -206,9 +206,10 @@ swf_status swf_debug_keys(swf_ctx *ctx, uint32_t *counts, uint32_t *offsets, uin
 /* swf_debug_blend_work: the work of the last swf_render's blend stage (Sec. 3.2
  * front-to-back rule), for roofline accounting: re-walks the same tile lists
  * without writing a spectrum and returns, in host memory, the number of (pixel,
- * list entry) evaluations (entries a pixel examines up to and including the one
- * that ends it), the number of records staged into LDS, and the number of list
- * entries. Synchronous; any output may be NULL. */
+ * list entry) evaluations the rule needs (entries inside the pixel's 3-sigma
+ * cutoff, up to and including the one that ends the pixel), the number of
+ * records staged into LDS, and the number of list entries. Synchronous; any
+ * output may be NULL. */
 swf_status swf_debug_blend_work(swf_ctx *ctx, uint64_t *evaluations, uint64_t *staged, uint64_t *n_entries);
 
 /* Stable LSD radix sort of n (key, value) pairs in place, device memory, on

@@ -303,7 +303,8 @@ class Context:
         return dict(counts=counts, offsets=offsets, keys=keys[:nkeys], values=vals[:nkeys], ranges=ranges)
 
     def blend_work(self):
-        """Work of the last render's blend: (pixel, entry) evaluations, staged records, list entries."""
+        """Work of the last render's blend: (pixel, entry) evaluations inside the 3-sigma cutoff before the pixel
+        ends, staged records, list entries."""
         ev, st, ne = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
         self._check(self._L.swf_debug_blend_work(self._h, ctypes.byref(ev), ctypes.byref(st), ctypes.byref(ne)))
         return dict(evaluations=ev.value, staged=st.value, entries=ne.value)

@@ -49,6 +49,41 @@ rocblas_status wgrad_rm(rocblas_handle h, int64_t M, int64_t N, int64_t P, const
     return rocblas_status_success;
 }
 
+// The same with BF16 operands and FP32 accumulation (rocblas_gemm_ex); C is
+// FP32 (c_bf16 = false) or BF16.
+rocblas_status gemm_rm_bf16(rocblas_handle h, bool ta, bool tb, int64_t M, int64_t N, int64_t K, const void* A,
+                            int64_t lda, const void* Bm, int64_t ldb, void* C, int64_t ldc, bool c_bf16 = false) {
+    const float one = 1.0f, zero = 0.0f;
+    const rocblas_datatype ct = c_bf16 ? rocblas_datatype_bf16_r : rocblas_datatype_f32_r;
+    return rocblas_gemm_ex(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
+                           ta ? rocblas_operation_transpose : rocblas_operation_none, (rocblas_int)N, (rocblas_int)M,
+                           (rocblas_int)K, &one, Bm, rocblas_datatype_bf16_r, (rocblas_int)ldb, A,
+                           rocblas_datatype_bf16_r, (rocblas_int)lda, &zero, C, ct, (rocblas_int)ldc, C, ct,
+                           (rocblas_int)ldc, rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0);
+}
+
+// wgrad_rm with BF16 dz and act (FP32 partials and result).
+rocblas_status wgrad_rm_bf16(rocblas_handle h, int64_t M, int64_t N, int64_t P, const uint16_t* dz,
+                             const uint16_t* act, float* dW, float* part, float* tmp, hipStream_t st) {
+    const int sp = split_of(P);
+    const int64_t kc = P / sp, last = P - kc * (sp - 1);
+    const float one = 1.0f, zero = 0.0f;
+    rocblas_status r = rocblas_status_success;
+    if (sp > 1)
+        r = rocblas_gemm_strided_batched_ex(
+            h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)N, (rocblas_int)M, (rocblas_int)kc,
+            &one, act, rocblas_datatype_bf16_r, (rocblas_int)N, (rocblas_stride)(kc * N), dz, rocblas_datatype_bf16_r,
+            (rocblas_int)M, (rocblas_stride)(kc * M), &zero, part, rocblas_datatype_f32_r, (rocblas_int)N,
+            (rocblas_stride)(M * N), part, rocblas_datatype_f32_r, (rocblas_int)N, (rocblas_stride)(M * N), sp - 1,
+            rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0);
+    if (r != rocblas_status_success) return r;
+    r = gemm_rm_bf16(h, true, false, M, N, last, dz + (sp - 1) * kc * M, M, act + (sp - 1) * kc * N, N,
+                     part + (int64_t)(sp - 1) * M * N, N);
+    if (r != rocblas_status_success) return r;
+    launch_colsum(part, sp, M * N, 1, 0, tmp, dW, 0, st);
+    return rocblas_status_success;
+}
+
 }  // namespace
 
 void blas_release(Ctx* c) {
@@ -56,17 +91,22 @@ void blas_release(Ctx* c) {
     c->blas = nullptr;
 }
 
-// MLP backward in FP32 with the layer GEMMs in rocBLAS (plain GEMMs; the ReLU
-// and bias steps are small kernels). Activations are recomputed: layer 1 from
-// its per-Gaussian mean part W1m gamma(mu_hat) plus the per-query TX part (the
+// MLP backward with the layer GEMMs in rocBLAS (plain GEMMs; the ReLU and bias
+// steps are small kernels). Activations are recomputed: layer 1 from its
+// per-Gaussian mean part W1m gamma(mu_hat) plus the per-query TX part (the
 // forward's `qs`), later layers as act_l = ReLU(act_{l-1} W_l^T + b_l). Then
 // from dy (gradients of the 7 residuals per pair):
 //   dW_l = dz_l^T act_{l-1}, db_l = colsum(dz_l), dz_{l-1} = (dz_l W_l) * [act_{l-1} > 0],
 // and for layer 1 the weight gradient splits into the mean part
-// (sum over queries of dz_0 per Gaussian)^T gamma(mu_hat) and the TX part
-// (sum over Gaussians of dz_0 per query)^T gamma(s_hat).
+// (sum over queries of dz_0 per Gaussian = S)^T gamma(mu_hat) and the TX part
+// (sum over Gaussians of dz_0 per query)^T gamma(s_hat); the mean features'
+// gradient is S W1m, taken through the sin / cos features to d mu.
+// bf16: the backward of a BF16 forward. Activations and dz are stored in BF16
+// (rounded like the forward kernel: FP32 sums, bias, ReLU, then one rounding)
+// and every large GEMM runs on BF16 operands with FP32 accumulation; weight
+// and bias gradients are accumulated in FP32.
 swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,
-                             const swf_grads* gr, hipStream_t st) {
+                             const swf_grads* gr, bool bf16, hipStream_t st) {
     swf_status s = SWF_OK;
     if (!blas) {
         rocblas_handle h = nullptr;
@@ -77,64 +117,132 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     rocblas_set_stream(h, st);
     const int64_t N = d.n, P = (int64_t)B * N;
     const int nh = d.n_hidden, Hd = 256, I = d.in_dim;
-    const size_t actb = (size_t)P * Hd * sizeof(float);
+    const size_t esz = bf16 ? 2 : 4;                 // activation / dz element size
+    const size_t actb = (size_t)P * Hd * esz;
+    const size_t f32b = (size_t)P * Hd * sizeof(float);
     if ((s = w.act.reserve(this, actb * nh + 16, st))) return s;
-    if ((s = w.dz.reserve(this, actb * 2 + 16, st))) return s;
-    // scratch: Pm / S (N x 256), R (B x 256), split-K partials, column-sum partials
+    // FP32: dz ping-pong. BF16: dz ping-pong in BF16 + one FP32 GEMM result.
+    if ((s = w.dz.reserve(this, bf16 ? actb * 2 + f32b + 16 : actb * 2 + 16, st))) return s;
+    // scratch: Pm / S (N x 256), R (B x 256), dg (N x 26), split-K partials, column-sum partials, BF16 weights
     const size_t n_split = (size_t)split_of(P) * Hd * Hd;
     const size_t n_cs = std::max<size_t>({(size_t)colsum_blocks(P) * Hd, (size_t)colsum_blocks(B) * N * Hd,
                                           (size_t)colsum_blocks(N) * Hd * B, (size_t)colsum_blocks(kMaxSplit) * Hd * Hd});
-    const size_t small = ((size_t)N * Hd + (size_t)B * Hd + n_split + n_cs + 64) * sizeof(float);
+    const size_t n_wb = bf16 ? ((size_t)(nh - 1) * Hd * Hd + (size_t)kOut * Hd + (size_t)P * kOut + 64) / 2 + 64 : 0;
+    const size_t small =
+        ((size_t)N * Hd + (size_t)B * Hd + (size_t)N * kMeanFeat + n_split + n_cs + n_wb + 64) * sizeof(float);
     if ((s = w.part.reserve(this, small, st))) return s;
     if ((s = w.fmean.reserve(this, (size_t)N * kMeanFeat * sizeof(float) + 16, st))) return s;
     if ((s = w.ftx.reserve(this, (size_t)B * kTxFeat * sizeof(float) + 16, st))) return s;
     if ((s = w.dmu.reserve(this, (size_t)N * 2 * sizeof(float) + 16, st))) return s;
     if ((s = w.qs.reserve(this, (size_t)B * Hd * sizeof(float), st))) return s;
-    float* act[8] = {};
-    for (int l = 0; l < nh; ++l) act[l] = (float*)((char*)w.act.ptr + actb * l);
-    float* dz[2] = {(float*)w.dz.ptr, (float*)((char*)w.dz.ptr + actb)};
+    void* act[8] = {};
+    for (int l = 0; l < nh; ++l) act[l] = (char*)w.act.ptr + actb * l;
+    void* dz[2] = {w.dz.ptr, (char*)w.dz.ptr + actb};
+    float* zf = bf16 ? (float*)((char*)w.dz.ptr + actb * 2) : nullptr;  // FP32 GEMM result (BF16 path)
     float* Pm = (float*)w.part.ptr;             // N x 256: W1m gamma(mu_hat), later S
     float* R = Pm + (size_t)N * Hd;              // B x 256
-    float* part = R + (size_t)B * Hd;            // split-K partials
+    float* dg = R + (size_t)B * Hd;              // N x 26
+    float* part = dg + (size_t)N * kMeanFeat;    // split-K partials
     float* tmp = part + n_split;                 // column-sum partials
+    uint16_t* wb = (uint16_t*)(tmp + n_cs);      // BF16 weights: hidden layers 1.., output, then dy
     float* fmean = (float*)w.fmean.ptr, *ftx = (float*)w.ftx.ptr, *qs = (float*)w.qs.ptr;
     launch_tx_features(d, tx, B, qs, st, ftx);
     launch_mean_features_f32(d, fmean, st);
     auto ok = [&](rocblas_status r, const char* what) -> swf_status {
         return r == rocblas_status_success ? SWF_OK : fail(SWF_E_DEVICE, what);
     };
+    uint16_t* wl[8] = {};
+    uint16_t* dyb = nullptr;
+    if (bf16) {
+        for (int l = 1; l < nh; ++l) {
+            wl[l] = wb + (size_t)(l - 1) * Hd * Hd;
+            launch_to_bf16(d.w[l], (int64_t)Hd * Hd, wl[l], st);
+        }
+        wl[nh] = wb + (size_t)(nh - 1) * Hd * Hd;
+        launch_to_bf16(d.w[nh], (int64_t)kOut * Hd, wl[nh], st);
+        dyb = wl[nh] + (size_t)kOut * Hd;
+        launch_to_bf16(dy, P * kOut, dyb, st);
+    }
     // ---- recompute the hidden activations
     if ((s = ok(gemm_rm(h, false, true, N, Hd, kMeanFeat, fmean, kMeanFeat, d.w[0], I, Pm, Hd), "sgemm W1m"))) return s;
-    launch_layer1_act(Pm, qs, (int)N, P, act[0], st);
+    if (bf16)
+        launch_layer1_act_bf16(Pm, qs, (int)N, P, act[0], st);
+    else
+        launch_layer1_act(Pm, qs, (int)N, P, (float*)act[0], st);
     for (int l = 1; l < nh; ++l) {
-        if ((s = ok(gemm_rm(h, false, true, P, Hd, Hd, act[l - 1], Hd, d.w[l], Hd, act[l], Hd), "sgemm fwd")))
-            return s;
-        launch_bias_relu(act[l], d.b[l], P, st);
+        if (bf16) {
+            if ((s = ok(gemm_rm_bf16(h, false, true, P, Hd, Hd, act[l - 1], Hd, wl[l], Hd, zf, Hd), "gemm fwd")))
+                return s;
+            launch_bias_relu_bf16(zf, d.b[l], P, act[l], st);
+        } else {
+            if ((s = ok(gemm_rm(h, false, true, P, Hd, Hd, (float*)act[l - 1], Hd, d.w[l], Hd, (float*)act[l], Hd),
+                        "sgemm fwd")))
+                return s;
+            launch_bias_relu((float*)act[l], d.b[l], P, st);
+        }
     }
     // ---- output layer (7 outputs)
-    if (gr->weight[nh] && (s = ok(wgrad_rm(h, kOut, Hd, P, dy, act[nh - 1], gr->weight[nh], part, tmp, st), "dWo")))
-        return s;
+    if (gr->weight[nh]) {
+        const rocblas_status r =
+            bf16 ? wgrad_rm_bf16(h, kOut, Hd, P, dyb, (const uint16_t*)act[nh - 1], gr->weight[nh], part, tmp, st)
+                 : wgrad_rm(h, kOut, Hd, P, dy, (const float*)act[nh - 1], gr->weight[nh], part, tmp, st);
+        if ((s = ok(r, "dWo"))) return s;
+    }
     if (gr->bias[nh]) launch_colsum(dy, P, kOut, 1, 0, tmp, gr->bias[nh], 0, st);
-    if ((s = ok(gemm_rm(h, false, false, P, Hd, kOut, dy, kOut, d.w[nh], Hd, dz[0], Hd), "sgemm dz"))) return s;
-    launch_relu_mask(dz[0], act[nh - 1], P, st);
+    if (bf16) {
+        if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, kOut, dyb, kOut, wl[nh], Hd, zf, Hd), "gemm dz"))) return s;
+        if (nh > 1)
+            launch_relu_mask_bf16(zf, act[nh - 1], P, dz[0], st);
+        else
+            launch_relu_mask_f32_bf16act(zf, act[0], P, st);  // layer-1 gradient kept in FP32
+    } else {
+        if ((s = ok(gemm_rm(h, false, false, P, Hd, kOut, dy, kOut, d.w[nh], Hd, (float*)dz[0], Hd), "sgemm dz")))
+            return s;
+        launch_relu_mask((float*)dz[0], (const float*)act[nh - 1], P, st);
+    }
     int cur = 0;
     for (int l = nh - 1; l >= 1; --l) {
-        if (gr->weight[l] && (s = ok(wgrad_rm(h, Hd, Hd, P, dz[cur], act[l - 1], gr->weight[l], part, tmp, st), "dW")))
-            return s;
-        if (gr->bias[l]) launch_colsum(dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
-        if ((s = ok(gemm_rm(h, false, false, P, Hd, Hd, dz[cur], Hd, d.w[l], Hd, dz[cur ^ 1], Hd), "sgemm dz")))
-            return s;
-        launch_relu_mask(dz[cur ^ 1], act[l - 1], P, st);
+        if (gr->weight[l]) {
+            const rocblas_status r =
+                bf16 ? wgrad_rm_bf16(h, Hd, Hd, P, (const uint16_t*)dz[cur], (const uint16_t*)act[l - 1],
+                                     gr->weight[l], part, tmp, st)
+                     : wgrad_rm(h, Hd, Hd, P, (const float*)dz[cur], (const float*)act[l - 1], gr->weight[l], part,
+                                tmp, st);
+            if ((s = ok(r, "dW"))) return s;
+        }
+        if (gr->bias[l]) {
+            if (bf16)
+                launch_colsum_bf16(dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
+            else
+                launch_colsum((const float*)dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
+        }
+        if (bf16) {
+            if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, Hd, dz[cur], Hd, wl[l], Hd, zf, Hd), "gemm dz")))
+                return s;
+            if (l > 1)
+                launch_relu_mask_bf16(zf, act[l - 1], P, dz[cur ^ 1], st);
+            else
+                launch_relu_mask_f32_bf16act(zf, act[0], P, st);  // layer-1 gradient kept in FP32
+        } else {
+            if ((s = ok(gemm_rm(h, false, false, P, Hd, Hd, (const float*)dz[cur], Hd, d.w[l], Hd,
+                                (float*)dz[cur ^ 1], Hd),
+                        "sgemm dz")))
+                return s;
+            launch_relu_mask((float*)dz[cur ^ 1], (const float*)act[l - 1], P, st);
+        }
         cur ^= 1;
     }
-    // ---- layer 1: dz[cur] is the gradient of its pre-activations
-    const float* dz0 = dz[cur];
-    if (gr->bias[0]) launch_colsum(dz0, P, Hd, 1, 0, tmp, gr->bias[0], 0, st);
+    // ---- layer 1: the gradient of its pre-activations, FP32 (in zf on the BF16 path)
+    const float* dz0 = bf16 ? zf : (const float*)dz[cur];
+    auto colsum_any = [&](int64_t rows, int64_t cols, int nz, int64_t bs, float* out, int64_t out_bs) {
+        launch_colsum(dz0, rows, cols, nz, bs, tmp, out, out_bs, st);
+    };
+    if (gr->bias[0]) colsum_any(P, Hd, 1, 0, gr->bias[0], 0);
+    float* S = Pm;  // per Gaussian, summed over the batch (N x 256)
+    colsum_any(B, N * Hd, 1, 0, S, 0);
     if (gr->weight[0]) {
-        float* S = Pm;  // per Gaussian, summed over the batch (N x 256)
-        launch_colsum(dz0, B, N * Hd, 1, 0, tmp, S, 0, st);
         // per query, summed over the Gaussians (B x 256)
-        launch_colsum(dz0, N, Hd, B, N * Hd, tmp, R, Hd, st);
+        colsum_any(N, Hd, B, N * Hd, R, Hd);
         // dW1 [256 x 89] = [S^T gamma(mu_hat) | R^T gamma(s_hat)]
         if ((s = ok(gemm_rm(h, true, false, Hd, kMeanFeat, N, S, Hd, fmean, kMeanFeat, gr->weight[0], I), "dW1m")))
             return s;
@@ -142,7 +250,9 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
                     "dW1s")))
             return s;
     }
-    launch_pe_backward(dz0, d, B, (float*)w.dmu.ptr, st);
+    // d gamma(mu_hat) = S W1m (N x 26), then through the features to d mu
+    if ((s = ok(gemm_rm(h, false, false, N, kMeanFeat, Hd, S, Hd, d.w[0], I, dg, kMeanFeat), "dgm"))) return s;
+    launch_pe_chain(dg, d, (float*)w.dmu.ptr, st);
     return hip(hipGetLastError(), "mlp backward");
 }
 
@@ -175,10 +285,10 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     }
     launch_preprocess_backward((const float*)w.dpair.ptr, w.rec, P, (flags & SWF_PAPER_DEFORM) != 0,
                                (float*)w.dbase.ptr, dy, st);
-    // 4. MLP backward (FP32: activations recomputed, GEMMs in rocBLAS)
+    // 4. MLP backward (activations recomputed, GEMMs in rocBLAS; BF16 operands after a BF16 forward)
     float* dmu = nullptr;
     if (want_mlp) {
-        if ((s = mlp_backward(w, d, tx, B, dy, gr, st))) return s;
+        if ((s = mlp_backward(w, d, tx, B, dy, gr, (flags & SWF_MLP_BF16) != 0, st))) return s;
         dmu = (float*)w.dmu.ptr;
     }
     // 5. base parameters: sum over the batch, original ids

@@ -254,25 +254,13 @@ __global__ void fill_kernel(float* __restrict__ p, float v, int64_t n) {
     if (i < n) p[i] = v;
 }
 
-// d gamma(mu_hat) (26 per row) -> d mu0 per Gaussian, summed over the batch.
-__global__ void pe_backward_kernel(const float* __restrict__ dz0, const float* __restrict__ W0, int in_dim,
-                                   const float* __restrict__ mx, const float* __restrict__ my, int B, int N, int Wd,
-                                   int Hd, float* __restrict__ dmu) {
+// d mu0 per Gaussian from dg = d gamma(mu_hat) (26 per Gaussian, already
+// summed over the batch): the chain rule through the sin / cos features.
+__global__ void pe_chain_kernel(const float* __restrict__ dgm, const float* __restrict__ mx,
+                                const float* __restrict__ my, int N, int Wd, int Hd, float* __restrict__ dmu) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    float dg[kMeanFeat];
-#pragma unroll
-    for (int i = 0; i < kMeanFeat; ++i) dg[i] = 0.f;
-    for (int b = 0; b < B; ++b) {
-        const float* z = dz0 + ((size_t)b * N + p) * 256;
-        for (int o = 0; o < 256; ++o) {
-            const float zo = z[o];
-            if (zo == 0.f) continue;
-            const float* w = W0 + (size_t)o * in_dim;
-#pragma unroll
-            for (int i = 0; i < kMeanFeat; ++i) dg[i] = fmaf(zo, w[i], dg[i]);
-        }
-    }
+    const float* dg = dgm + (size_t)p * kMeanFeat;
     float hx, lx, hy, ly;
     div_two(mx[p], (float)Wd, hx, lx);
     div_two(my[p], (float)Hd, hy, ly);
@@ -288,6 +276,92 @@ __global__ void pe_backward_kernel(const float* __restrict__ dz0, const float* _
     }
     dmu[(size_t)p * 2] = gx / (float)Wd;
     dmu[(size_t)p * 2 + 1] = gy / (float)Hd;
+}
+
+// ---- BF16 variants (the MLP backward of a BF16 forward) ----------------------
+__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }  // round to nearest even
+
+// act[p][k] = bf16(ReLU(Pm[p mod N][k] + qs[p / N][k]))
+__global__ void layer1_act_bf16_kernel(const float* __restrict__ Pm, const float* __restrict__ qs, int N, int64_t P,
+                                       __bf16* __restrict__ act) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * 64) return;
+    const int64_t p = i >> 6;
+    const int k = (int)(i & 63) * 4;
+    const int64_t q = p / N, n = p - q * N;
+    const float4 a = *reinterpret_cast<const float4*>(Pm + n * 256 + k);
+    const float4 b = *reinterpret_cast<const float4*>(qs + q * 256 + k);
+    __bf16* o = act + p * 256 + k;
+    o[0] = to_bf16(fmaxf(a.x + b.x, 0.f));
+    o[1] = to_bf16(fmaxf(a.y + b.y, 0.f));
+    o[2] = to_bf16(fmaxf(a.z + b.z, 0.f));
+    o[3] = to_bf16(fmaxf(a.w + b.w, 0.f));
+}
+
+// out[p][k] = bf16(ReLU(z[p][k] + bias[k])): a recomputed hidden layer
+__global__ void bias_relu_bf16_kernel(const float* __restrict__ z, const float* __restrict__ bias, int64_t P,
+                                      __bf16* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * 64) return;
+    const int k = (int)(i & 63) * 4;
+    const float4 v = *reinterpret_cast<const float4*>(z + i * 4);
+    const float4 b = *reinterpret_cast<const float4*>(bias + k);
+    __bf16* o = out + i * 4;
+    o[0] = to_bf16(fmaxf(v.x + b.x, 0.f));
+    o[1] = to_bf16(fmaxf(v.y + b.y, 0.f));
+    o[2] = to_bf16(fmaxf(v.z + b.z, 0.f));
+    o[3] = to_bf16(fmaxf(v.w + b.w, 0.f));
+}
+
+// out[p][k] = bf16(d[p][k] * [act[p][k] > 0]): back through the ReLU
+__global__ void relu_mask_bf16_kernel(const float* __restrict__ d, const __bf16* __restrict__ act, int64_t P,
+                                      __bf16* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * 64) return;
+    const float4 v = *reinterpret_cast<const float4*>(d + i * 4);
+    const __bf16* a = act + i * 4;
+    __bf16* o = out + i * 4;
+    o[0] = (float)a[0] > 0.f ? to_bf16(v.x) : to_bf16(0.f);
+    o[1] = (float)a[1] > 0.f ? to_bf16(v.y) : to_bf16(0.f);
+    o[2] = (float)a[2] > 0.f ? to_bf16(v.z) : to_bf16(0.f);
+    o[3] = (float)a[3] > 0.f ? to_bf16(v.w) : to_bf16(0.f);
+}
+
+// d[p][k] *= [act[p][k] > 0] in place, FP32 d, BF16 act (the layer-1 gradient
+// stays in FP32: its column sums feed the first layer's weight gradient)
+__global__ void relu_mask_f32_bf16act_kernel(float* __restrict__ d, const __bf16* __restrict__ act, int64_t P) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * 64) return;
+    float4 v = *reinterpret_cast<float4*>(d + i * 4);
+    const __bf16* a = act + i * 4;
+    v = make_float4((float)a[0] > 0.f ? v.x : 0.f, (float)a[1] > 0.f ? v.y : 0.f, (float)a[2] > 0.f ? v.z : 0.f,
+                    (float)a[3] > 0.f ? v.w : 0.f);
+    *reinterpret_cast<float4*>(d + i * 4) = v;
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, __bf16* __restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = to_bf16(x[i]);
+}
+
+// Column sums of row-major BF16 matrices, first stage (FP32 partial sums).
+__global__ __launch_bounds__(256) void colsum_stage1_bf16_kernel(const __bf16* __restrict__ A, int64_t rows,
+                                                                 int64_t cols, int64_t rpb, int64_t bs,
+                                                                 float* __restrict__ part) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= cols) return;
+    const __bf16* Az = A + (int64_t)blockIdx.z * bs;
+    const int64_t r0 = (int64_t)blockIdx.y * rpb, r1 = min(rows, r0 + rpb);
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    int64_t r = r0;
+    for (; r + 4 <= r1; r += 4) {
+        s0 += (float)Az[r * cols + c];
+        s1 += (float)Az[(r + 1) * cols + c];
+        s2 += (float)Az[(r + 2) * cols + c];
+        s3 += (float)Az[(r + 3) * cols + c];
+    }
+    for (; r < r1; ++r) s0 += (float)Az[r * cols + c];
+    part[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * cols + c] = (s0 + s1) + (s2 + s3);
 }
 
 __global__ void mean_features_f32_kernel(const float* __restrict__ mx, const float* __restrict__ my, int n, int W,
@@ -356,10 +430,42 @@ void launch_fill(float* p, float v, int64_t n, hipStream_t st) {
     if (n > 0) fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, v, n);
 }
 
-void launch_pe_backward(const float* dz0, const DevScene& s, int B, float* dmu, hipStream_t st) {
-    if (s.n > 0)
-        pe_backward_kernel<<<(s.n + 127) / 128, 128, 0, st>>>(dz0, s.w[0], s.in_dim, s.mx, s.my, B, s.n, s.W, s.H,
-                                                              dmu);
+void launch_pe_chain(const float* dg, const DevScene& s, float* dmu, hipStream_t st) {
+    if (s.n > 0) pe_chain_kernel<<<(s.n + 255) / 256, 256, 0, st>>>(dg, s.mx, s.my, s.n, s.W, s.H, dmu);
+}
+
+void launch_layer1_act_bf16(const float* Pm, const float* qs, int N, int64_t P, void* act, hipStream_t st) {
+    if (P > 0)
+        layer1_act_bf16_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(Pm, qs, N, P, (__bf16*)act);
+}
+
+void launch_bias_relu_bf16(const float* z, const float* bias, int64_t P, void* out, hipStream_t st) {
+    if (P > 0) bias_relu_bf16_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(z, bias, P, (__bf16*)out);
+}
+
+void launch_relu_mask_bf16(const float* d, const void* act, int64_t P, void* out, hipStream_t st) {
+    if (P > 0)
+        relu_mask_bf16_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(d, (const __bf16*)act, P,
+                                                                                 (__bf16*)out);
+}
+
+void launch_relu_mask_f32_bf16act(float* d, const void* act, int64_t P, hipStream_t st) {
+    if (P > 0)
+        relu_mask_f32_bf16act_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(d, (const __bf16*)act, P);
+}
+
+void launch_to_bf16(const float* x, int64_t n, void* y, hipStream_t st) {
+    if (n > 0) to_bf16_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(x, n, (__bf16*)y);
+}
+
+void launch_colsum_bf16(const void* A, int64_t rows, int64_t cols, int nz, int64_t bs, float* part, float* out,
+                        int64_t out_bs, hipStream_t st) {
+    if (cols <= 0 || nz <= 0) return;
+    const int nblk = colsum_blocks(rows);
+    const int64_t rpb = (rows + nblk - 1) / nblk;
+    const unsigned gx = (unsigned)((cols + 255) / 256);
+    colsum_stage1_bf16_kernel<<<dim3(gx, nblk, nz), 256, 0, st>>>((const __bf16*)A, rows, cols, rpb, bs, part);
+    colsum_stage2_kernel<<<dim3(gx, nz), 256, 0, st>>>(part, nblk, cols, out, out_bs);
 }
 
 void launch_mean_features_f32(const DevScene& s, float* out, hipStream_t st) {

@@ -17,9 +17,9 @@ namespace {
 __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
 
 // kCount: instead of writing the spectrum, add to work[0] the number of (pixel,
-// list entry) evaluations (every entry of the pixel's tile list up to and
-// including the one that ends it, whether or not a wave skips it by the row
-// test below) and to work[1] the number of records staged in LDS.
+// list entry) evaluations the rule needs (entries whose quadratic form is
+// within the 3-sigma cutoff at the pixel, up to and including the one that ends
+// it) and to work[1] the number of records staged in LDS.
 template <int TILE, bool kCount = false, bool kAux = true>
 __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ vals,
@@ -150,9 +150,9 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
 #pragma unroll
                 for (int jj = 0; jj < kUnroll; ++jj) {
                     const int j = j0 + jj;
-                    if (kCount) evals += (!done && j < cnt) ? 1u : 0u;
                     float dx, dy, u, w;
                     const float q = blend_q(fx, fy, s_pos[j], s_wm[j], dx, dy, u, w);
+                    if (kCount) evals += (!done && j < cnt && q <= kQMax) ? 1u : 0u;
                     const float2 o = s_oa[j];
                     const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
                     // a skipped entry (cutoff, alpha floor, or a finished pixel) acts

@@ -117,7 +117,7 @@ struct Ctx {
     swf_status backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out,
                         const void* aux, const swf_grads* grads, hipStream_t st);
     swf_status mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,
-                            const swf_grads* gr, hipStream_t st);
+                            const swf_grads* gr, bool bf16, hipStream_t st);
     void* blas = nullptr;  // rocBLAS handle of the MLP backward (created on first use)
     void stage_begin(int stage, hipStream_t st);
     void stage_end(hipStream_t st);
