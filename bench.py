@@ -167,6 +167,30 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
 
+def measured_peaks(ctx):
+    """Rates this GPU sustains in plain loops (after the timed region): BF16 MFMA, FP32 FMA and LDS reads from the
+    library's probes, HBM from a 1 GiB device copy timed with events (2 GiB moved)."""
+    import torch
+    pk = ctx.measure_peaks()
+    src = torch.ones(2 ** 28, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    pk["hbm_gbs"] = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return pk
+
+
+def add_measured(rec_roof, achieved, peak_measured):
+    rec_roof["measured_peak"] = peak_measured
+    rec_roof["frac_of_measured"] = achieved / peak_measured if peak_measured else None
+
+
 def cpu_baseline(g, Ws, bs, H, W, txs, budget_s):
     """The FP64 oracle timed on the host: whole spectra (MLP + brute-force
     compositing over all Gaussians in depth order) until the budget is used."""
@@ -391,6 +415,11 @@ def bench_large(a):
                       "ms": st["blend"]}},
         "latency_us": {"batched_p50": 1e3 * pct(step_ms, 50), "batched_p99": 1e3 * pct(step_ms, 99)},
     }
+    pk = measured_peaks(ctx)
+    add_measured(rec["roofline"], rec["roofline"]["achieved"], pk["mfma_bf16_tflops"])
+    add_measured(rec["stage_rooflines"]["lists"], rec["stage_rooflines"]["lists"]["achieved"], pk["hbm_gbs"])
+    add_measured(rec["stage_rooflines"]["blend"], rec["stage_rooflines"]["blend"]["achieved"], pk["fma_tops"])
+    rec["measured_peaks"] = pk
     ctx.close()
     print(json.dumps(rec), flush=True)
 
@@ -554,6 +583,12 @@ def main():
                   "gather_GBs": work["staged"] * 44 / (blend_ms * 1e-3) / 1e9},
     }
 
+    pk = measured_peaks(ctx)
+    if a.mlp == "bf16":
+        add_measured(roofline, achieved, pk["mfma_bf16_tflops"])
+    add_measured(stage_rooflines["lists"], stage_rooflines["lists"]["achieved"], pk["hbm_gbs"])
+    add_measured(stage_rooflines["blend"], stage_rooflines["blend"]["achieved"], pk["fma_tops"])
+
     rec = {
         "metric": METRIC, "value": value, "unit": "spectra/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -566,6 +601,8 @@ def main():
         "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "roofline": roofline,
         "stage_rooflines": stage_rooflines,
+        "measured_peaks": dict(pk, note="plain loops on this GPU after the timed region: BF16 MFMA chains in "
+                                        "registers, FP32 FMA, conflict-free LDS reads, a 1 GiB device copy"),
     }
     if a.copy_probe_mib:
         src = torch.ones(a.copy_probe_mib * 2 ** 18, device="cuda", dtype=torch.float32)

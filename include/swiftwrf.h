@@ -211,6 +211,13 @@ swf_status swf_debug_keys(swf_ctx *ctx, uint32_t *counts, uint32_t *offsets, uin
  * records staged into LDS, and the number of list entries. Synchronous; any
  * output may be NULL. */
 swf_status swf_debug_blend_work(swf_ctx *ctx, uint64_t *evaluations, uint64_t *staged, uint64_t *n_entries);
+/* swf_measure_peaks: on-device peaks for roofline accounting (not part of the
+ * method): the rates this GPU sustains in plain loops of BF16 MFMA
+ * (v_mfma_f32_16x16x32_bf16 chains held in registers, TFLOP/s), FP32 FMA
+ * (T lane-ops/s, one per FMA) and conflict-free 16-byte LDS reads (TB/s), with
+ * one 8-wave workgroup per compute unit. Synchronous on the context's device
+ * (a few milliseconds); any output may be NULL. */
+swf_status swf_measure_peaks(swf_ctx *ctx, double *mfma_bf16_tflops, double *fma_tops, double *lds_tbps);
 
 /* Stable LSD radix sort of n (key, value) pairs in place, device memory, on
  * the key bits [begin_bit, end_bit). key_bytes is 4 (uint32 keys) or 8 (uint64

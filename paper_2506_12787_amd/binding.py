@@ -95,6 +95,7 @@ def lib():
             "swf_debug_deform": [P, I32, P, I32, I32, P, P],
             "swf_debug_keys": [P, P, P, P, P, P, P, ctypes.c_uint64],
             "swf_debug_blend_work": [P, P, P, P],
+            "swf_measure_peaks": [P, P, P, P],
             "swf_radix_sort": [P, P, P, I64, I32, I32, I32, P],
             "swf_exclusive_scan": [P, P, P, P, I64, P],
             "swf_serve_start": [P, P],
@@ -308,6 +309,12 @@ class Context:
         ev, st, ne = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
         self._check(self._L.swf_debug_blend_work(self._h, ctypes.byref(ev), ctypes.byref(st), ctypes.byref(ne)))
         return dict(evaluations=ev.value, staged=st.value, entries=ne.value)
+
+    def measure_peaks(self):
+        """On-device peaks: BF16 MFMA TFLOP/s, FP32 FMA T lane-ops/s, LDS read TB/s (plain loops)."""
+        m, f, l = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self._L.swf_measure_peaks(self._h, ctypes.byref(m), ctypes.byref(f), ctypes.byref(l)))
+        return dict(mfma_bf16_tflops=m.value, fma_tops=f.value, lds_tbps=l.value)
 
     def radix_sort(self, keys, values, begin_bit=0, end_bit=None):
         kb = keys.element_size()

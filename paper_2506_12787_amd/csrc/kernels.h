@@ -125,4 +125,10 @@ void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Recor
 void launch_blend_work(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
                        unsigned long long* work, hipStream_t st);
 
+// peak probes (probe.hip)
+size_t probe_scratch_bytes(int blocks);
+hipError_t run_probes(int blocks, void* scratch, hipStream_t st, double* mfma_tflops, double* fma_tops,
+                      double* lds_tbps);
+int n_compute_units();
+
 }  // namespace swf

@@ -339,18 +339,17 @@ __global__ void mean_features_bf16_kernel(const float* __restrict__ mx, const fl
     for (int k = 0; k < 32; ++k) out[(size_t)p * 32 + k] = (__bf16)(k < kMeanFeat ? f[k] : 0.f);
 }
 
+}  // namespace
+
 int n_compute_units() {
-    static int n = 0;
-    if (!n) {
+    static const int n = [] {  // thread-safe one-time initialisation
         int dev = 0, cus = 0;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        n = cus > 0 ? cus : 256;
-    }
+        return cus > 0 ? cus : 256;
+    }();
     return n;
 }
-
-}  // namespace
 
 void compute_mean_features_bf16(DevScene& s, hipStream_t st) {
     if (s.n > 0)

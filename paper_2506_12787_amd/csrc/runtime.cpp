@@ -832,6 +832,18 @@ swf_status swf_debug_blend_work(swf_ctx* h, uint64_t* evaluations, uint64_t* sta
     return SWF_OK;
 }
 
+swf_status swf_measure_peaks(swf_ctx* h, double* mfma_bf16_tflops, double* fma_tops, double* lds_tbps) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    const int blocks = n_compute_units();
+    swf_status s = c->hip(hipDeviceSynchronize(), "sync");
+    if (s) return s;
+    if ((s = c->ws.work.reserve(c, probe_scratch_bytes(blocks), nullptr))) return s;
+    if ((s = c->hip(run_probes(blocks, c->ws.work.ptr, nullptr, mfma_bf16_tflops, fma_tops, lds_tbps), "probes")))
+        return s;
+    return c->hip(hipDeviceSynchronize(), "sync");
+}
+
 swf_status swf_radix_sort(swf_ctx* h, void* keys, uint32_t* values, int64_t n, int32_t key_bytes, int32_t begin_bit,
                           int32_t end_bit, void* stream) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
