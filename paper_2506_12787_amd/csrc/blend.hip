@@ -16,6 +16,19 @@ namespace {
 
 __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
 
+// Minimum over the box [x0, x1] x [y0, y1] (offsets from the mean) of the
+// quadratic form a x^2 + 2 b x y + c y^2 (positive definite): 0 if the box
+// holds the origin, else the least of the four edge minima (on an edge x = X
+// the form is smallest at y = -b X / c, clamped to the edge).
+__device__ __forceinline__ float box_min_q(float a, float b, float c, float x0, float x1, float y0, float y1) {
+    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return 0.0f;
+    const float ra = -b / a, rc = -b / c;
+    auto qf = [&](float x, float y) { return fmaf(a * x, x, fmaf(2.0f * b * x, y, c * y * y)); };
+    const float ya = fminf(fmaxf(rc * x0, y0), y1), yb = fminf(fmaxf(rc * x1, y0), y1);
+    const float xa = fminf(fmaxf(ra * y0, x0), x1), xb = fminf(fmaxf(ra * y1, x0), x1);
+    return fminf(fminf(qf(x0, ya), qf(x1, yb)), fminf(qf(xa, y0), qf(xb, y1)));
+}
+
 // kCount: instead of writing the spectrum, add to work[0] the number of (pixel,
 // list entry) evaluations the rule needs (entries whose quadratic form is
 // within the 3-sigma cutoff at the pixel, up to and including the one that ends
@@ -37,10 +50,11 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     __shared__ float2 s_pos[kN + 1];
     __shared__ float4 s_wm[kN + 1];
     __shared__ float2 s_oa[kN + 1];
-    // 16x16 tiles: bit w of s_strip[j] is set if entry j's 3-sigma band in y
-    // (with a margin) meets the 4 pixel rows of wave w; each wave walks only
-    // those entries (the others fail the cutoff at every one of its pixels),
-    // from its own compacted list s_idx[w] padded with the dummy.
+    // 16x16 tiles: bit w of s_strip[j] is set unless entry j's quadratic form
+    // exceeds the cutoff (with a margin) everywhere on the rectangle spanned by
+    // the 4 x 16 pixels of wave w; each wave walks only those entries (the others
+    // fail the cutoff at every one of its pixels), from its own compacted list
+    // s_idx[w] padded with the dummy.
     constexpr bool kCull = TILE == 16 && !kCount;
     constexpr int kWaves = kN / 64;
     __shared__ uint8_t s_strip[kCull ? kN : 1];
@@ -83,14 +97,17 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
             s_wm[threadIdx.x] = m;
             s_oa[threadIdx.x] = oa[v];
             if (kCull) {
-                // Sigma = (M^T M)^-1, so Sigma_yy = (m00^2 + m10^2) / det(M)^2
-                const float det = fabsf(m.x * m.w - m.y * m.z);
-                const float hy = 3.0f * sqrtf(m.x * m.x + m.z * m.z) / det * 1.001f + 0.01f;
-                const float r0 = (float)(ty * TILE - by0);  // first row of the tile, block-relative
+                // q = |M d|^2 = d^T A d with A = M^T M
+                const float a = fmaf(m.x, m.x, m.z * m.z), bq = fmaf(m.x, m.y, m.z * m.w),
+                            c = fmaf(m.y, m.y, m.w * m.w);
+                const float x0 = (float)(tx * TILE - bx0) - pos.x;  // block-relative tile columns - mean
+                const float r0 = (float)(ty * TILE - by0) - pos.y;  // first row of the tile - mean
                 uint32_t bits = 0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    bits |= (pos.y + hy >= r0 + 4.0f * k && pos.y - hy <= r0 + 4.0f * k + 3.0f) ? 1u << k : 0u;
+                for (int k = 0; k < 4; ++k) {
+                    const float qm = box_min_q(a, bq, c, x0, x0 + (float)(TILE - 1), r0 + 4.0f * k, r0 + 4.0f * k + 3.0f);
+                    bits |= !(qm > kQMax * 1.001f + 1e-3f) ? 1u << k : 0u;  // keeps NaN (never culls in doubt)
+                }
                 s_strip[threadIdx.x] = (uint8_t)bits;
             }
         } else if ((int)threadIdx.x < ((cnt + kUnroll - 1) & ~(kUnroll - 1))) {
