@@ -70,6 +70,8 @@ swf_status Workspace::init(Ctx* c) {
     if (hipMalloc(&total_dev, 64) != hipSuccess) return c->fail(SWF_E_OOM, "hipMalloc(status)");
     if (hipHostMalloc(&total_host, 64, 0) != hipSuccess) return c->fail(SWF_E_OOM, "hipHostMalloc(status)");
     status_dev = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(total_dev) + 16);
+    if (hipEventCreateWithFlags(&total_ev, hipEventDisableTiming) != hipSuccess)
+        return c->fail(SWF_E_DEVICE, "hipEventCreate");
     return c->hip(hipMemset(total_dev, 0, 64), "hipMemset(status)");
 }
 
@@ -77,8 +79,10 @@ void Workspace::release() {
     for (Buf* b : bufs()) b->release();
     if (total_dev) hipFree(total_dev);
     if (total_host) hipHostFree(total_host);
+    if (total_ev) hipEventDestroy(total_ev);
     total_dev = nullptr;
     total_host = nullptr;
+    total_ev = nullptr;
 }
 
 void Buf::release() {
@@ -457,7 +461,8 @@ swf_status Ctx::enqueue_preprocess(Workspace& w, Scene* sc, const float* tx, int
 // Forward up to the per-tile lists: preprocess (+ MLP), scan, keys, sort,
 // tile ranges. Records the result in `last`.
 swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int flags, hipStream_t st,
-                              uint64_t key_cap) {
+                              uint64_t key_cap, uint64_t spec_cap, bool* spec_used) {
+    if (spec_used) *spec_used = false;
     Scene* sc = scene(sid);
     if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
     if (B < 1) return fail(SWF_E_INVALID, "batch must be >= 1");
@@ -472,9 +477,11 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     const int64_t n_gt = (int64_t)B * g.tiles;
     if ((s = w.ranges.reserve(this, (size_t)n_gt * sizeof(uint2), st))) return s;
     // binning unless the full 64-bit sort is asked for (or the segment grid would exceed the launch limit)
-    if (!full && bin_fits(B, d.n, g))
-        s = lists_binned(w, d, B, g, st, key_cap);
-    else
+    if (!full && bin_fits(B, d.n, g)) {
+        const bool spec = key_cap == 0 && spec_cap > 0 && spec_used;
+        s = lists_binned(w, d, B, g, st, spec ? spec_cap : key_cap, spec);
+        if (spec) *spec_used = true;
+    } else
         s = lists_sorted(w, d, B, g, full, st, key_cap);
     if (s) return s;
     w.last.valid = true;
@@ -489,7 +496,8 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
 // Key count after an exclusive scan whose 64-bit total is in w.total_dev:
 // read back (key_cap == 0), or kept on the device as the effective count
 // (total if it fits key_cap, else 0 with the overflow bit set).
-swf_status Ctx::key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64_t& nk, const uint64_t*& n_dev) {
+swf_status Ctx::key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64_t& nk, const uint64_t*& n_dev,
+                          bool readback) {
     nk = key_cap;
     n_dev = nullptr;
     if (key_cap == 0) {
@@ -504,6 +512,13 @@ swf_status Ctx::key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64
         uint64_t* n_eff = w.total_dev + 1;  // the word after the scan total
         launch_effective_count(w.total_dev, key_cap, n_eff, w.status_dev, st);
         n_dev = n_eff;
+        if (readback) {
+            swf_status s;
+            if ((s = hip(hipMemcpyAsync(w.total_host, w.total_dev, sizeof(uint64_t), hipMemcpyDeviceToHost, st),
+                         "total D2H")))
+                return s;
+            if ((s = hip(hipEventRecord(w.total_ev, st), "total event"))) return s;
+        }
     }
     if (nk >= (1ull << 32)) return fail(SWF_E_OVERFLOW, "more than 2^32 - 1 keys; render a smaller batch");
     return SWF_OK;
@@ -512,7 +527,7 @@ swf_status Ctx::key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64
 // Lists by binning (per tile segment of a query): tile histograms per block of
 // pairs, their scan, stable placement, ranges. Same lists as the full sort.
 swf_status Ctx::lists_binned(Workspace& w, const DevScene& d, int B, const Grid& g, hipStream_t st,
-                             uint64_t key_cap) {
+                             uint64_t key_cap, bool readback) {
     swf_status s;
     const int64_t nh = (int64_t)bin_hist_entries(B, d.n, g);
     if ((s = w.bins.reserve(this, (size_t)nh * sizeof(uint32_t) + 16, st))) return s;
@@ -524,7 +539,7 @@ swf_status Ctx::lists_binned(Workspace& w, const DevScene& d, int B, const Grid&
     stage_end(st);
     uint64_t nk;
     const uint64_t* n_dev;
-    if ((s = key_count(w, st, key_cap, nk, n_dev))) return s;
+    if ((s = key_count(w, st, key_cap, nk, n_dev, readback))) return s;
     if ((s = w.vals.reserve(this, nk * 4 + 16, st))) return s;
     stage_begin(SWF_STAGE_SORT, st);
     launch_bin_scatter(w.rec, B, d.n, g, bins, n_dev, (uint32_t*)w.vals.ptr, st);
@@ -585,11 +600,13 @@ swf_status Ctx::lists_sorted(Workspace& w, const DevScene& d, int B, const Grid&
 }
 
 swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux,
-                       hipStream_t st, uint64_t key_cap) {
+                       hipStream_t st, uint64_t key_cap, bool speculate) {
     if (!out) return fail(SWF_E_INVALID, "out is NULL");
     if ((flags & SWF_KEEP_AUX) && !aux) return fail(SWF_E_INVALID, "SWF_KEEP_AUX needs aux");
     hipSetDevice(device);
-    swf_status s = forward_lists(w, sid, tx, B, flags, st, key_cap);
+    const uint64_t spec_cap = speculate && key_cap == 0 && w.vals.cap >= 16 + 4 * 4096 ? (w.vals.cap - 16) / 4 : 0;
+    bool spec = false;
+    swf_status s = forward_lists(w, sid, tx, B, flags, st, key_cap, spec_cap, &spec);
     if (s) return s;
     const DevScene& d = scene(sid)->d;
     float* auxT = nullptr;
@@ -601,7 +618,19 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
     stage_begin(SWF_STAGE_BLEND, st);
     launch_blend_forward((const uint2*)w.ranges.ptr, w.last.vals, w.rec, B, w.last.grid, out, auxT, auxL, st);
     stage_end(st);
-    return hip(hipGetLastError(), "render launch");
+    if ((s = hip(hipGetLastError(), "render launch"))) return s;
+    if (spec) {
+        // the GPU runs the lists and the blend while the count comes back
+        if ((s = hip(hipEventSynchronize(w.total_ev), "total event"))) return s;
+        const uint64_t total = *w.total_host;
+        if (total > spec_cap) {
+            // did not fit: nothing was placed and the spectrum is zero; again at the exact size
+            launch_clear_u32(w.status_dev, 1, st);
+            return render(w, sid, tx, B, flags, out, aux, st, 0, false);
+        }
+        w.last.n_keys = total;
+    }
+    return SWF_OK;
 }
 
 }  // namespace swf
@@ -697,7 +726,7 @@ swf_status swf_render(swf_ctx* h, int32_t scene_id, const float* tx, int32_t bat
                       void* aux, void* stream) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     CTX_GUARD(c);
-    return c->render(c->ws, scene_id, tx, batch, flags, out, aux, (hipStream_t)stream);
+    return c->render(c->ws, scene_id, tx, batch, flags, out, aux, (hipStream_t)stream, 0, true);
 }
 
 swf_status swf_stage_timing(swf_ctx* h, int32_t enable) {

@@ -56,6 +56,7 @@ struct Workspace {
     uint64_t* total_dev = nullptr;   // device: scan total, then the status word
     uint32_t* status_dev = nullptr;
     uint64_t* total_host = nullptr;  // pinned
+    hipEvent_t total_ev = nullptr;   // the scan total has reached total_host (speculative renders)
     LastRender last;
     std::vector<Buf*> bufs() {
         return {&qs, &geo, &wm, &oa, &rect, &count, &off, &scan, &keys, &keys2, &vals, &vals2, &hist, &ranges, &bins,
@@ -106,14 +107,23 @@ struct Ctx {
     // key_cap == 0: size the key buffers from the scan total (one 8-byte
     // device-to-host read and a stream wait). key_cap > 0: fixed capacity, no
     // host synchronisation (graph-capturable); overflow sets the status word.
+    // spec_cap > 0 (direct renders only): when the lists are built by binning,
+    // build them at that fixed capacity with the scan total copied back
+    // asynchronously (w.total_ev); *spec_used tells whether that happened.
     swf_status forward_lists(Workspace& w, int sid, const float* tx, int B, int flags, hipStream_t st,
-                             uint64_t key_cap = 0);
-    swf_status key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64_t& nk, const uint64_t*& n_dev);
-    swf_status lists_binned(Workspace& w, const DevScene& d, int B, const Grid& g, hipStream_t st, uint64_t key_cap);
+                             uint64_t key_cap = 0, uint64_t spec_cap = 0, bool* spec_used = nullptr);
+    swf_status key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64_t& nk, const uint64_t*& n_dev,
+                         bool readback = false);
+    swf_status lists_binned(Workspace& w, const DevScene& d, int B, const Grid& g, hipStream_t st, uint64_t key_cap,
+                            bool readback = false);
     swf_status lists_sorted(Workspace& w, const DevScene& d, int B, const Grid& g, bool full, hipStream_t st,
                             uint64_t key_cap);
+    // speculate: a direct render whose key buffer is already sized by an
+    // earlier one builds its lists at that capacity while the exact count is
+    // read back, instead of waiting for the count first; it renders again at
+    // the exact size if the count did not fit.
     swf_status render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st,
-                      uint64_t key_cap = 0);
+                      uint64_t key_cap = 0, bool speculate = false);
     swf_status backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out,
                         const void* aux, const swf_grads* grads, hipStream_t st);
     swf_status mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,

@@ -83,6 +83,31 @@ def test_tile8_and_full_sort_are_bitwise_equal(ctx):
     ctx.release_scene(sid)
 
 
+def test_speculative_capacity_overflow_renders_again(ctx):
+    """A direct render whose key buffer was sized by an earlier, smaller render
+    builds its lists at that capacity while the count is read back; when the
+    count does not fit it renders again at the exact size. Small scene, then a
+    larger one (overflow and re-render), then the small one again (fits): each
+    result equals a render of the same scene on a fresh context."""
+    from paper_2506_12787_amd import binding as B
+    scenes = [Hh.problem(n, H0, W0, seed=90 + n, scale_range=(1.0, 12.0))[0] for n in (300, 6000)]
+    got = []
+    for g in (scenes[0], scenes[1], scenes[0]):
+        sid = ctx.upload_scene(g, H0, W0)
+        got.append(ctx.render(sid, None, flags=B.NO_DEFORM, batch=1).cpu().numpy())
+        ctx.release_scene(sid)
+    fresh = B.Context(0)
+    try:
+        for g, img in zip((scenes[0], scenes[1], scenes[0]), got):
+            sid = fresh.upload_scene(g, H0, W0)
+            ref = fresh.render(sid, None, flags=B.NO_DEFORM, batch=1).cpu().numpy()
+            np.testing.assert_array_equal(img, ref)
+            fresh.release_scene(sid)
+    finally:
+        fresh.close()
+    assert np.abs(got[1]).max() > 0
+
+
 @pytest.mark.parametrize("n,scale,batch,H,W", [(2500, (1.0, 12.0), 3, 90, 360), (1100, (20.0, 60.0), 2, 90, 360),
                                                (1024, (2.0, 8.0), 1, 90, 360), (1, (1.0, 3.0), 2, 90, 360),
                                                (5000, (1.0, 40.0), 2, 180, 720), (4097, (0.5, 20.0), 3, 250, 1100)])
