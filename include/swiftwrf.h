@@ -153,8 +153,11 @@ swf_status swf_scene_bytes(swf_ctx *ctx, int32_t scene_id, uint64_t *bytes);
  * SWF_NO_DEFORM, may be NULL then). out: device float32 [batch][H][W].
  * aux: device buffer of 8*batch*H*W bytes when SWF_KEEP_AUX, else NULL.
  * Enqueued on `stream`; the call returns after enqueueing, except that it waits
- * once on the stream for the total key count (a 8-byte device-to-host read)
- * to size the key buffers. */
+ * once for the total key count (an 8-byte device-to-host read after the key
+ * scan). The first render of a context sizes the key buffers from that count
+ * before enqueueing the rest; later ones enqueue the rest at the buffers'
+ * capacity and wait for the count meanwhile, rendering again at the exact size
+ * (the same call, still on `stream`) if it did not fit. */
 swf_status swf_render(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags, float *out,
                       void *aux, void *stream);
 
