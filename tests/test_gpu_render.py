@@ -143,6 +143,30 @@ def test_binned_lists_equal_full_sort(ctx, n, scale, batch, H, W):
     ctx.release_scene(sid)
 
 
+@pytest.mark.parametrize("H,W", [(1024, 1024), (4096, 4096)])
+def test_maximum_grids_sampled_pixels(ctx, H, W):
+    """The largest grids: 1024 x 1024 is 4096 tiles per query, the most the
+    binning path takes (16 segments of 256); 4096 x 4096 (the largest accepted
+    size, 65536 tiles) takes the sort path. Static FP32 render, sampled pixels
+    against the FP64 oracle; the 1024 grid also against the full sort, bitwise."""
+    from paper_2506_12787_amd import binding as B
+    g, s = Hh.problem(3000, H, W, seed=61, scale_range=(1.0, 40.0))
+    sid = ctx.upload_scene(g, H, W)
+    img = ctx.render(sid, None, flags=B.NO_DEFORM, batch=1)[0]
+    rng = np.random.default_rng(62)
+    px = np.concatenate([rng.integers(0, W, 200), [0, W - 1, 0, W - 1]]).astype(np.int32)
+    py = np.concatenate([rng.integers(0, H, 200), [0, 0, H - 1, H - 1]]).astype(np.int32)
+    import torch
+    gpu = img[torch.from_numpy(py.astype(np.int64)).cuda(), torch.from_numpy(px.astype(np.int64)).cuda()]
+    res, _, _, _ = M.render_query(s, None, None, pix=(px, py))
+    print(f"{H}x{W}", Hh.parity(gpu.cpu().numpy(), res))
+    assert float(img.abs().max()) > 0
+    if H * W <= 1024 * 1024:
+        full = ctx.render(sid, None, flags=B.NO_DEFORM | B.FULL_SORT, batch=1)[0]
+        assert torch.equal(img, full)
+    ctx.release_scene(sid)
+
+
 def _oracle_keys(s, H, W, tile=16):
     gm = M.deform(s, None)
     rg = M.gaussians_for_raster(gm, s.depth)
