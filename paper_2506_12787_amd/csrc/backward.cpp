@@ -129,7 +129,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
                                           (size_t)colsum_blocks(N) * Hd * B, (size_t)colsum_blocks(kMaxSplit) * Hd * Hd});
     const size_t n_wb = bf16 ? ((size_t)(nh - 1) * Hd * Hd + (size_t)kOut * Hd + (size_t)P * kOut + 64) / 2 + 64 : 0;
     const size_t small =
-        ((size_t)N * Hd + (size_t)B * Hd + (size_t)N * kMeanFeat + n_split + n_cs + n_wb + 64) * sizeof(float);
+        ((size_t)N * Hd + (size_t)B * Hd + (size_t)N * kMeanFeat + 4 + n_split + n_cs + n_wb + 64) * sizeof(float);
     if ((s = w.part.reserve(this, small, st))) return s;
     if ((s = w.fmean.reserve(this, (size_t)N * kMeanFeat * sizeof(float) + 16, st))) return s;
     if ((s = w.ftx.reserve(this, (size_t)B * kTxFeat * sizeof(float) + 16, st))) return s;
@@ -142,7 +142,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     float* Pm = (float*)w.part.ptr;             // N x 256: W1m gamma(mu_hat), later S
     float* R = Pm + (size_t)N * Hd;              // B x 256
     float* dg = R + (size_t)B * Hd;              // N x 26
-    float* part = dg + (size_t)N * kMeanFeat;    // split-K partials
+    float* part = dg + ((size_t)N * kMeanFeat + 3) / 4 * 4;  // split-K partials (16-byte aligned)
     float* tmp = part + n_split;                 // column-sum partials
     uint16_t* wb = (uint16_t*)(tmp + n_cs);      // BF16 weights: hidden layers 1.., output, then dy
     float* fmean = (float*)w.fmean.ptr, *ftx = (float*)w.ftx.ptr, *qs = (float*)w.qs.ptr;

@@ -239,14 +239,77 @@ __global__ __launch_bounds__(256) void colsum_stage1_kernel(const float* __restr
     part[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * cols + c] = (s0 + s1) + (s2 + s3);
 }
 
-__global__ __launch_bounds__(256) void colsum_stage2_kernel(const float* __restrict__ part, int nblk, int64_t cols,
-                                                            float* __restrict__ out, int64_t out_bs) {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= cols) return;
+// Column sums, vectorised (cols % 4 == 0): 4 consecutive columns per thread,
+// 64 threads over 256 columns, 4 row groups per block summed through LDS in a
+// fixed order (deterministic). One row block writes the result directly.
+__device__ __forceinline__ float4 load4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ float4 load4(const __bf16* p) {
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u), __uint_as_float(u.y << 16),
+                       __uint_as_float(u.y & 0xffff0000u));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void colsum4_stage1_kernel(const T* __restrict__ A, int64_t rows, int64_t cols,
+                                                             int64_t rpb, int64_t bs, float* __restrict__ part,
+                                                             float* __restrict__ out, int64_t out_bs) {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t c = (int64_t)blockIdx.x * 256 + tx * 4;
+    const T* Az = A + (int64_t)blockIdx.z * bs;
+    const int64_t r0 = (int64_t)blockIdx.y * rpb, r1 = min(rows, r0 + rpb);
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c < cols) {
+#pragma unroll 4
+        for (int64_t r = r0 + ty; r < r1; r += 4) {
+            const float4 v = load4(Az + r * cols + c);
+            s.x += v.x;
+            s.y += v.y;
+            s.z += v.z;
+            s.w += v.w;
+        }
+    }
+    __shared__ float4 red[4][64];
+    red[ty][tx] = s;
+    __syncthreads();
+    if (ty != 0 || c >= cols) return;
+    float4 t = red[0][tx];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        const float4 u = red[k][tx];
+        t.x += u.x;
+        t.y += u.y;
+        t.z += u.z;
+        t.w += u.w;
+    }
+    if (gridDim.y == 1) {
+        float* o = out + (int64_t)blockIdx.z * out_bs + c;
+        o[0] = t.x;
+        o[1] = t.y;
+        o[2] = t.z;
+        o[3] = t.w;
+    } else {
+        *reinterpret_cast<float4*>(part + ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * cols + c) = t;
+    }
+}
+
+// Second stage: 8 columns per block, 32 groups of row blocks each, summed
+// through LDS in a fixed order.
+__global__ __launch_bounds__(256) void colsum8_stage2_kernel(const float* __restrict__ part, int nblk, int64_t cols,
+                                                             float* __restrict__ out, int64_t out_bs) {
+    const int cc = threadIdx.x & 7, g = threadIdx.x >> 3;
+    const int64_t c = (int64_t)blockIdx.x * 8 + cc;
     const float* pz = part + (int64_t)blockIdx.y * nblk * cols;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += pz[(int64_t)b * cols + c];
-    out[(int64_t)blockIdx.y * out_bs + c] = s;
+    if (c < cols)
+        for (int b = g; b < nblk; b += 32) s += pz[(int64_t)b * cols + c];
+    __shared__ float red[32][8];
+    red[g][cc] = s;
+    __syncthreads();
+    if (g != 0 || c >= cols) return;
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) t += red[k][cc];
+    out[(int64_t)blockIdx.y * out_bs + c] = t;
 }
 
 __global__ void fill_kernel(float* __restrict__ p, float v, int64_t n) {
@@ -414,16 +477,33 @@ void launch_relu_mask(float* d, const float* act, int64_t P, hipStream_t st) {
     if (P > 0) relu_mask_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(d, act, P);
 }
 
-int colsum_blocks(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(512, (rows + 511) / 512)); }
+int colsum_blocks(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(2048, (rows + 255) / 256)); }
+
+namespace {
+template <typename T>
+void colsum4(const T* A, int64_t rows, int64_t cols, int nz, int64_t bs, float* part, float* out, int64_t out_bs,
+             hipStream_t st) {
+    const int nblk = colsum_blocks(rows);
+    const int64_t rpb = (rows + nblk - 1) / nblk;
+    colsum4_stage1_kernel<T><<<dim3((unsigned)((cols + 255) / 256), nblk, nz), 256, 0, st>>>(A, rows, cols, rpb, bs,
+                                                                                          part, out, out_bs);
+    if (nblk > 1)
+        colsum8_stage2_kernel<<<dim3((unsigned)((cols + 7) / 8), nz), 256, 0, st>>>(part, nblk, cols, out, out_bs);
+}
+}  // namespace
 
 void launch_colsum(const float* A, int64_t rows, int64_t cols, int nz, int64_t bs, float* part, float* out,
                    int64_t out_bs, hipStream_t st) {
     if (cols <= 0 || nz <= 0) return;
+    if (cols % 4 == 0 && bs % 4 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0) {
+        colsum4(A, rows, cols, nz, bs, part, out, out_bs, st);
+        return;
+    }
     const int nblk = colsum_blocks(rows);
     const int64_t rpb = (rows + nblk - 1) / nblk;
     const unsigned gx = (unsigned)((cols + 255) / 256);
     colsum_stage1_kernel<<<dim3(gx, nblk, nz), 256, 0, st>>>(A, rows, cols, rpb, bs, part);
-    colsum_stage2_kernel<<<dim3(gx, nz), 256, 0, st>>>(part, nblk, cols, out, out_bs);
+    colsum8_stage2_kernel<<<dim3((unsigned)((cols + 7) / 8), nz), 256, 0, st>>>(part, nblk, cols, out, out_bs);
 }
 
 void launch_fill(float* p, float v, int64_t n, hipStream_t st) {
@@ -461,11 +541,15 @@ void launch_to_bf16(const float* x, int64_t n, void* y, hipStream_t st) {
 void launch_colsum_bf16(const void* A, int64_t rows, int64_t cols, int nz, int64_t bs, float* part, float* out,
                         int64_t out_bs, hipStream_t st) {
     if (cols <= 0 || nz <= 0) return;
+    if (cols % 4 == 0 && bs % 4 == 0 && (reinterpret_cast<uintptr_t>(A) & 7) == 0) {
+        colsum4((const __bf16*)A, rows, cols, nz, bs, part, out, out_bs, st);
+        return;
+    }
     const int nblk = colsum_blocks(rows);
     const int64_t rpb = (rows + nblk - 1) / nblk;
     const unsigned gx = (unsigned)((cols + 255) / 256);
     colsum_stage1_bf16_kernel<<<dim3(gx, nblk, nz), 256, 0, st>>>((const __bf16*)A, rows, cols, rpb, bs, part);
-    colsum_stage2_kernel<<<dim3(gx, nz), 256, 0, st>>>(part, nblk, cols, out, out_bs);
+    colsum8_stage2_kernel<<<dim3((unsigned)((cols + 7) / 8), nz), 256, 0, st>>>(part, nblk, cols, out, out_bs);
 }
 
 void launch_mean_features_f32(const DevScene& s, float* out, hipStream_t st) {
