@@ -190,11 +190,16 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     }
     if (gr->bias[nh]) launch_colsum(dy, P, kOut, 1, 0, tmp, gr->bias[nh], 0, st);
     if (bf16) {
-        if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, kOut, dyb, kOut, wl[nh], Hd, zf, Hd), "gemm dz"))) return s;
-        if (nh > 1)
-            launch_relu_mask_bf16(zf, act[nh - 1], P, dz[0], st);
-        else
-            launch_relu_mask_f32_bf16act(zf, act[0], P, st);  // layer-1 gradient kept in FP32
+        // BF16 result (masking after rounding equals rounding after masking); the layer-1 gradient stays FP32
+        if (nh > 1) {
+            if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, kOut, dyb, kOut, wl[nh], Hd, dz[0], Hd, true), "gemm dz")))
+                return s;
+            launch_relu_mask_inplace_bf16(dz[0], act[nh - 1], P, st);
+        } else {
+            if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, kOut, dyb, kOut, wl[nh], Hd, zf, Hd), "gemm dz")))
+                return s;
+            launch_relu_mask_f32_bf16act(zf, act[0], P, st);
+        }
     } else {
         if ((s = ok(gemm_rm(h, false, false, P, Hd, kOut, dy, kOut, d.w[nh], Hd, (float*)dz[0], Hd), "sgemm dz")))
             return s;
@@ -217,12 +222,16 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
                 launch_colsum((const float*)dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
         }
         if (bf16) {
-            if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, Hd, dz[cur], Hd, wl[l], Hd, zf, Hd), "gemm dz")))
-                return s;
-            if (l > 1)
-                launch_relu_mask_bf16(zf, act[l - 1], P, dz[cur ^ 1], st);
-            else
+            if (l > 1) {
+                if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, Hd, dz[cur], Hd, wl[l], Hd, dz[cur ^ 1], Hd, true),
+                            "gemm dz")))
+                    return s;
+                launch_relu_mask_inplace_bf16(dz[cur ^ 1], act[l - 1], P, st);
+            } else {
+                if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, Hd, dz[cur], Hd, wl[l], Hd, zf, Hd), "gemm dz")))
+                    return s;
                 launch_relu_mask_f32_bf16act(zf, act[0], P, st);  // layer-1 gradient kept in FP32
+            }
         } else {
             if ((s = ok(gemm_rm(h, false, false, P, Hd, Hd, (const float*)dz[cur], Hd, d.w[l], Hd,
                                 (float*)dz[cur ^ 1], Hd),

@@ -376,20 +376,6 @@ __global__ void bias_relu_bf16_kernel(const float* __restrict__ z, const float* 
     o[3] = to_bf16(fmaxf(v.w + b.w, 0.f));
 }
 
-// out[p][k] = bf16(d[p][k] * [act[p][k] > 0]): back through the ReLU
-__global__ void relu_mask_bf16_kernel(const float* __restrict__ d, const __bf16* __restrict__ act, int64_t P,
-                                      __bf16* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * 64) return;
-    const float4 v = *reinterpret_cast<const float4*>(d + i * 4);
-    const __bf16* a = act + i * 4;
-    __bf16* o = out + i * 4;
-    o[0] = (float)a[0] > 0.f ? to_bf16(v.x) : to_bf16(0.f);
-    o[1] = (float)a[1] > 0.f ? to_bf16(v.y) : to_bf16(0.f);
-    o[2] = (float)a[2] > 0.f ? to_bf16(v.z) : to_bf16(0.f);
-    o[3] = (float)a[3] > 0.f ? to_bf16(v.w) : to_bf16(0.f);
-}
-
 // d[p][k] *= [act[p][k] > 0] in place, FP32 d, BF16 act (the layer-1 gradient
 // stays in FP32: its column sums feed the first layer's weight gradient)
 __global__ void relu_mask_f32_bf16act_kernel(float* __restrict__ d, const __bf16* __restrict__ act, int64_t P) {
@@ -400,6 +386,24 @@ __global__ void relu_mask_f32_bf16act_kernel(float* __restrict__ d, const __bf16
     v = make_float4((float)a[0] > 0.f ? v.x : 0.f, (float)a[1] > 0.f ? v.y : 0.f, (float)a[2] > 0.f ? v.z : 0.f,
                     (float)a[3] > 0.f ? v.w : 0.f);
     *reinterpret_cast<float4*>(d + i * 4) = v;
+}
+
+// d[p][k] = [act[p][k] > 0] ? d[p][k] : 0 in place, BF16 d and act (8 per thread)
+__global__ void relu_mask_inplace_bf16_kernel(__bf16* __restrict__ d, const __bf16* __restrict__ act, int64_t n8) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    uint4 v = reinterpret_cast<uint4*>(d)[i];
+    const uint4 a = reinterpret_cast<const uint4*>(act)[i];
+    auto m = [](uint32_t x, uint32_t y) {  // per 16-bit half: keep x where the bf16 in y is > 0
+        const uint32_t lo = ((y & 0x8000u) == 0 && (y & 0x7fffu) != 0) ? 0x0000ffffu : 0u;
+        const uint32_t hi = ((y & 0x80000000u) == 0 && (y & 0x7fff0000u) != 0) ? 0xffff0000u : 0u;
+        return x & (lo | hi);
+    };
+    v.x = m(v.x, a.x);
+    v.y = m(v.y, a.y);
+    v.z = m(v.z, a.z);
+    v.w = m(v.w, a.w);
+    reinterpret_cast<uint4*>(d)[i] = v;
 }
 
 __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, __bf16* __restrict__ y) {
@@ -523,15 +527,16 @@ void launch_bias_relu_bf16(const float* z, const float* bias, int64_t P, void* o
     if (P > 0) bias_relu_bf16_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(z, bias, P, (__bf16*)out);
 }
 
-void launch_relu_mask_bf16(const float* d, const void* act, int64_t P, void* out, hipStream_t st) {
-    if (P > 0)
-        relu_mask_bf16_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(d, (const __bf16*)act, P,
-                                                                                 (__bf16*)out);
-}
-
 void launch_relu_mask_f32_bf16act(float* d, const void* act, int64_t P, hipStream_t st) {
     if (P > 0)
         relu_mask_f32_bf16act_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(d, (const __bf16*)act, P);
+}
+
+void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStream_t st) {
+    const int64_t n8 = P * 32;  // 256 columns = 32 groups of 8
+    if (n8 > 0)
+        relu_mask_inplace_bf16_kernel<<<(unsigned)((n8 + 255) / 256), 256, 0, st>>>((__bf16*)d, (const __bf16*)act,
+                                                                                   n8);
 }
 
 void launch_to_bf16(const float* x, int64_t n, void* y, hipStream_t st) {
