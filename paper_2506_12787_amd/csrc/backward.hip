@@ -9,11 +9,14 @@
 // through alpha = min(0.99, o exp(-q/2)) (zero derivative when clamped),
 // q = |M d|^2, into per-pair gradients of (mean, M, opacity, amplitude).
 // Per entry the 64 lanes of a wave are reduced before one atomic per value.
+// With 16x16 tiles a wave skips the entries that miss the cutoff on all of its
+// pixels.
 //
 // Preprocess backward maps d(M, opacity) to the 7 residual coordinates
 // (d_mean, d_log_scale, d_rotation, d_logit, d_amp); the MLP backward is a
 // chain of row-parallel products (dZ_{l-1} = (dZ_l W_l) . [H_{l-1} > 0]) and
 // split-K weight-gradient reductions (dW_l = dZ_l^T H_{l-1}) in FP32.
+#include "cull.h"
 #include "kernels.h"
 #include "swf_device.h"
 
@@ -21,12 +24,45 @@ namespace swf {
 
 namespace {
 
-__device__ __forceinline__ float wave_sum(float v) {
+__device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
+
+// Wave sums of 8 values at once: three halving exchanges leave each lane one
+// value summed over 8 lanes, three more finish the sum over the wave (10
+// shuffles instead of 48). Lane l < 8 returns the total of value index
+// 4 (l & 1) + 2 ((l >> 1) & 1) + ((l >> 2) & 1).
+__device__ __forceinline__ float wave_sum8(float (&a)[8]) {
+    const unsigned l = lane_id();
+    {
+        const bool hi = l & 1u;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        for (int k = 0; k < 4; ++k) {
+            const float send = hi ? a[k] : a[k + 4], keep = hi ? a[k + 4] : a[k];
+            a[k] = keep + __shfl_xor(send, 1, 64);
+        }
+    }
+    {
+        const bool hi = l & 2u;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float send = hi ? a[k] : a[k + 2], keep = hi ? a[k + 2] : a[k];
+            a[k] = keep + __shfl_xor(send, 2, 64);
+        }
+    }
+    {
+        const bool hi = l & 4u;
+        const float send = hi ? a[0] : a[1], keep = hi ? a[1] : a[0];
+        a[0] = keep + __shfl_xor(send, 4, 64);
+    }
+    float v = a[0];
+    v += __shfl_xor(v, 8, 64);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
     return v;
 }
 
+// With 16x16 tiles each wave (4 pixel rows) walks only the entries that can
+// reach the cutoff on its rectangle (the forward kernel's culling): the others
+// leave every one of its pixels unchanged.
 template <int TILE>
 __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals, const float4* __restrict__ geo,
@@ -34,10 +70,14 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     const float* __restrict__ grad_out, const float* __restrict__ aux_T, const uint32_t* __restrict__ aux_last,
     float* __restrict__ dpair) {
     constexpr int kN = TILE * TILE;
+    constexpr bool kCull = TILE == 16;
+    constexpr int kWaves = kN / 64;
     __shared__ float2 s_pos[kN];
     __shared__ float4 s_wm[kN];
     __shared__ float2 s_oa[kN];
     __shared__ uint32_t s_v[kN];
+    __shared__ uint8_t s_strip[kCull ? kN : 1];
+    __shared__ uint16_t s_idx[kCull ? kWaves : 1][kN];
     __shared__ uint32_t s_max;
 
     const int gtile = blockIdx.x;
@@ -69,6 +109,50 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     const int lmax = (int)s_max;
     float S = 0.0f;
 
+    auto entry = [&](int beg, int jj) {
+        const int j = beg + jj;
+        float gv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        bool contrib = false;
+        if (j < (int)last) {
+            const float4 m = s_wm[jj];
+            float dx, dy, u, w;
+            const float q = blend_q(fx, fy, s_pos[jj], m, dx, dy, u, w);
+            if (q <= kQMax) {
+                const float2 o = s_oa[jj];
+                const float raw = blend_raw_alpha(q, o.x);
+                const float a = fminf(kAlphaMax, raw);
+                if (a >= kAlphaMin) {
+                    contrib = true;
+                    const float om = 1.0f - a;
+                    const float Tb = T / om;
+                    const float dC_da = o.y * Tb - S / om;
+                    S = fmaf(o.y * a, Tb, S);
+                    T = Tb;
+                    gv[7] = G * a * Tb;
+                    if (!(raw > kAlphaMax)) {
+                        const float ga = G * dC_da;
+                        gv[6] = ga * (raw / o.x);           // d alpha / d opacity = exp(-q/2)
+                        const float dq = ga * (-0.5f * a);  // d alpha / d q = -alpha / 2
+                        const float du = 2.0f * dq * u, dw = 2.0f * dq * w;
+                        gv[2] = du * dx;
+                        gv[3] = du * dy;
+                        gv[4] = dw * dx;
+                        gv[5] = dw * dy;
+                        gv[0] = -(du * m.x + dw * m.z);
+                        gv[1] = -(du * m.y + dw * m.w);
+                    }
+                }
+            }
+        }
+        if (__ballot(contrib) == 0ull) return;
+        const float v = wave_sum8(gv);
+        const unsigned l = lane_id();
+        if (l < 8u && v != 0.0f) {
+            const int k = 4 * (int)(l & 1u) + 2 * (int)((l >> 1) & 1u) + (int)((l >> 2) & 1u);
+            atomicAdd(dpair + (size_t)s_v[jj] * 8 + k, v);
+        }
+    };
+
     for (int end = lmax; end > 0; end -= kN) {
         const int beg = end > kN ? end - kN : 0;
         __syncthreads();
@@ -77,57 +161,35 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
             if (j < end) {
                 const uint32_t v = vals[rg.x + j];
                 const float4 g = geo[v];
-                s_pos[threadIdx.x] = make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
-                s_wm[threadIdx.x] = wm[v];
+                const float2 pos = make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
+                const float4 m = wm[v];
+                s_pos[threadIdx.x] = pos;
+                s_wm[threadIdx.x] = m;
                 s_oa[threadIdx.x] = oa[v];
                 s_v[threadIdx.x] = v;
+                if (kCull)
+                    s_strip[threadIdx.x] =
+                        (uint8_t)wave_rows_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
             }
         }
         __syncthreads();
-        for (int jj = end - beg - 1; jj >= 0; --jj) {
-            const int j = beg + jj;
-            float gv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            bool contrib = false;
-            if (j < (int)last) {
-                const float4 m = s_wm[jj];
-                float dx, dy, u, w;
-                const float q = blend_q(fx, fy, s_pos[jj], m, dx, dy, u, w);
-                if (q <= kQMax) {
-                    const float2 o = s_oa[jj];
-                    const float raw = blend_raw_alpha(q, o.x);
-                    const float a = fminf(kAlphaMax, raw);
-                    if (a >= kAlphaMin) {
-                        contrib = true;
-                        const float om = 1.0f - a;
-                        const float Tb = T / om;
-                        const float dC_da = o.y * Tb - S / om;
-                        S = fmaf(o.y * a, Tb, S);
-                        T = Tb;
-                        gv[7] = G * a * Tb;
-                        if (!(raw > kAlphaMax)) {
-                            const float ga = G * dC_da;
-                            gv[6] = ga * (raw / o.x);       // d alpha / d opacity = exp(-q/2)
-                            const float dq = ga * (-0.5f * a);  // d alpha / d q = -alpha / 2
-                            const float du = 2.0f * dq * u, dw = 2.0f * dq * w;
-                            gv[2] = du * dx;
-                            gv[3] = du * dy;
-                            gv[4] = dw * dx;
-                            gv[5] = dw * dy;
-                            gv[0] = -(du * m.x + dw * m.z);
-                            gv[1] = -(du * m.y + dw * m.w);
-                        }
-                    }
-                }
-            }
-            if (__ballot(contrib) == 0ull) continue;
+        const int cnt = end - beg;
+        if (kCull) {
+            const int wv = threadIdx.x >> 6;
+            uint16_t* idx = s_idx[wv];
+            int nlist = 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) gv[k] = wave_sum(gv[k]);
-            if ((threadIdx.x & 63) == 0) {
-                float* dst = dpair + (size_t)s_v[jj] * 8;
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if (gv[k] != 0.0f) atomicAdd(dst + k, gv[k]);
+            for (int c = 0; c < kWaves; ++c) {
+                const int jl = c * 64 + (int)lane_id();
+                const bool f = jl < cnt && ((s_strip[jl] >> wv) & 1u);
+                const uint64_t bal = __ballot(f);
+                if (f) idx[nlist + __popcll(bal & ((1ull << lane_id()) - 1ull))] = (uint16_t)jl;
+                nlist += __popcll(bal);
             }
+            __builtin_amdgcn_wave_barrier();
+            for (int n = nlist - 1; n >= 0; --n) entry(beg, (int)idx[n]);
+        } else {
+            for (int jj = cnt - 1; jj >= 0; --jj) entry(beg, jj);
         }
     }
 }

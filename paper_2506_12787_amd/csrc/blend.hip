@@ -7,6 +7,7 @@
 // 64-pixel block, in full precision from the hi + lo pair), then every thread composites its
 // pixel over the batch. A block-wide vote ends the walk once every pixel has
 // reached the transmittance floor.
+#include "cull.h"
 #include "kernels.h"
 #include "swf_device.h"
 
@@ -15,19 +16,6 @@ namespace swf {
 namespace {
 
 __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
-
-// Minimum over the box [x0, x1] x [y0, y1] (offsets from the mean) of the
-// quadratic form a x^2 + 2 b x y + c y^2 (positive definite): 0 if the box
-// holds the origin, else the least of the four edge minima (on an edge x = X
-// the form is smallest at y = -b X / c, clamped to the edge).
-__device__ __forceinline__ float box_min_q(float a, float b, float c, float x0, float x1, float y0, float y1) {
-    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return 0.0f;
-    const float ra = -b / a, rc = -b / c;
-    auto qf = [&](float x, float y) { return fmaf(a * x, x, fmaf(2.0f * b * x, y, c * y * y)); };
-    const float ya = fminf(fmaxf(rc * x0, y0), y1), yb = fminf(fmaxf(rc * x1, y0), y1);
-    const float xa = fminf(fmaxf(ra * y0, x0), x1), xb = fminf(fmaxf(ra * y1, x0), x1);
-    return fminf(fminf(qf(x0, ya), qf(x1, yb)), fminf(qf(xa, y0), qf(xb, y1)));
-}
 
 // kCount: instead of writing the spectrum, add to work[0] the number of (pixel,
 // list entry) evaluations the rule needs (entries whose quadratic form is
@@ -96,20 +84,9 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
             s_pos[threadIdx.x] = pos;
             s_wm[threadIdx.x] = m;
             s_oa[threadIdx.x] = oa[v];
-            if (kCull) {
-                // q = |M d|^2 = d^T A d with A = M^T M
-                const float a = fmaf(m.x, m.x, m.z * m.z), bq = fmaf(m.x, m.y, m.z * m.w),
-                            c = fmaf(m.y, m.y, m.w * m.w);
-                const float x0 = (float)(tx * TILE - bx0) - pos.x;  // block-relative tile columns - mean
-                const float r0 = (float)(ty * TILE - by0) - pos.y;  // first row of the tile - mean
-                uint32_t bits = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float qm = box_min_q(a, bq, c, x0, x0 + (float)(TILE - 1), r0 + 4.0f * k, r0 + 4.0f * k + 3.0f);
-                    bits |= !(qm > kQMax * 1.001f + 1e-3f) ? 1u << k : 0u;  // keeps NaN (never culls in doubt)
-                }
-                s_strip[threadIdx.x] = (uint8_t)bits;
-            }
+            if (kCull)  // block-relative first column and row of the tile
+                s_strip[threadIdx.x] =
+                    (uint8_t)wave_rows_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
         } else if ((int)threadIdx.x < ((cnt + kUnroll - 1) & ~(kUnroll - 1))) {
             // padding up to the unrolled length: opacity 0 never contributes
             s_pos[threadIdx.x] = make_float2(0.0f, 0.0f);
