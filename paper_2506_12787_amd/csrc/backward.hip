@@ -60,7 +60,7 @@ __device__ __forceinline__ float wave_sum8(float (&a)[8]) {
     return v;
 }
 
-// With 16x16 tiles each wave (4 pixel rows) walks only the entries that can
+// With 16x16 tiles each wave (an 8x8 quadrant) walks only the entries that can
 // reach the cutoff on its rectangle (the forward kernel's culling): the others
 // leave every one of its pixels unchanged.
 template <int TILE>
@@ -84,7 +84,10 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     const int b = gtile / tiles;
     const int t = gtile - b * tiles;
     const int tx = t % TW, ty = t / TW;
-    const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+    // culled 16x16 tiles: wave w covers the 8x8 quadrant (w & 1, w >> 1)
+    const int wq = (int)(threadIdx.x >> 6), lq = (int)(threadIdx.x & 63);
+    const int lx = kCull ? (wq & 1) * 8 + (lq & 7) : (int)threadIdx.x % TILE;
+    const int ly = kCull ? (wq >> 1) * 8 + (lq >> 3) : (int)threadIdx.x / TILE;
     const int px = tx * TILE + lx, py = ty * TILE + ly;
     const bool inside = px < W && py < H;
     const int bx0 = (tx * TILE) & ~63, by0 = (ty * TILE) & ~63;
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
                 s_v[threadIdx.x] = v;
                 if (kCull)
                     s_strip[threadIdx.x] =
-                        (uint8_t)wave_rows_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
+                        (uint8_t)wave_quads_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
             }
         }
         __syncthreads();

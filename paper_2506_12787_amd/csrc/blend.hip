@@ -39,8 +39,8 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     __shared__ float4 s_wm[kN + 1];
     __shared__ float2 s_oa[kN + 1];
     // 16x16 tiles: bit w of s_strip[j] is set unless entry j's quadratic form
-    // exceeds the cutoff (with a margin) everywhere on the rectangle spanned by
-    // the 4 x 16 pixels of wave w; each wave walks only those entries (the others
+    // exceeds the cutoff (with a margin) everywhere on the 8 x 8 quadrant of
+    // wave w; each wave walks only those entries (the others
     // fail the cutoff at every one of its pixels), from its own compacted list
     // s_idx[w] padded with the dummy.
     constexpr bool kCull = TILE == 16 && !kCount;
@@ -57,7 +57,11 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     const int b = gtile / tiles;
     const int t = gtile - b * tiles;
     const int tx = t % TW, ty = t / TW;
-    const int lx = threadIdx.x % TILE, ly = threadIdx.x / TILE;
+    // culled 16x16 tiles: wave w covers the 8x8 quadrant (w & 1, w >> 1) and
+    // lane l its pixel (l & 7, l >> 3); otherwise pixels are row-major
+    const int wq = (int)(threadIdx.x >> 6), lq = (int)(threadIdx.x & 63);
+    const int lx = kCull ? (wq & 1) * 8 + (lq & 7) : (int)threadIdx.x % TILE;
+    const int ly = kCull ? (wq >> 1) * 8 + (lq >> 3) : (int)threadIdx.x / TILE;
     const int px = tx * TILE + lx, py = ty * TILE + ly;
     const bool inside = px < W && py < H;
     // Offsets are taken relative to the enclosing 64-pixel block, the same for
@@ -86,7 +90,7 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
             s_oa[threadIdx.x] = oa[v];
             if (kCull)  // block-relative first column and row of the tile
                 s_strip[threadIdx.x] =
-                    (uint8_t)wave_rows_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
+                    (uint8_t)wave_quads_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
         } else if ((int)threadIdx.x < ((cnt + kUnroll - 1) & ~(kUnroll - 1))) {
             // padding up to the unrolled length: opacity 0 never contributes
             s_pos[threadIdx.x] = make_float2(0.0f, 0.0f);

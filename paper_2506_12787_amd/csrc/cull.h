@@ -18,16 +18,17 @@ __device__ __forceinline__ float box_min_q(float a, float b, float c, float x0, 
 }
 
 // Bit k set unless the entry (block-relative mean `pos`, whitening factor m,
-// q = |m d|^2) exceeds the cutoff, with a margin, on the whole rectangle of
-// pixel rows r0 + 4k .. r0 + 4k + 3 and columns c0 .. c0 + 15 (k < 4: the
-// four waves of a 16 x 16 tile). NaN never culls.
-__device__ __forceinline__ uint32_t wave_rows_mask(float4 m, float2 pos, float c0, float r0, float qmax) {
+// q = |m d|^2) exceeds the cutoff, with a margin, on the whole 8 x 8 quadrant
+// k of a 16 x 16 tile (k = 2 * row half + column half; c0, r0: its first
+// column and row). NaN never culls.
+__device__ __forceinline__ uint32_t wave_quads_mask(float4 m, float2 pos, float c0, float r0, float qmax) {
     const float a = fmaf(m.x, m.x, m.z * m.z), b = fmaf(m.x, m.y, m.z * m.w), c = fmaf(m.y, m.y, m.w * m.w);
     const float x0 = c0 - pos.x, y0 = r0 - pos.y;
     uint32_t bits = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const float qm = box_min_q(a, b, c, x0, x0 + 15.0f, y0 + 4.0f * k, y0 + 4.0f * k + 3.0f);
+        const float xa = x0 + 8.0f * (k & 1), ya = y0 + 8.0f * (k >> 1);
+        const float qm = box_min_q(a, b, c, xa, xa + 7.0f, ya, ya + 7.0f);
         bits |= !(qm > qmax * 1.001f + 1e-3f) ? 1u << k : 0u;
     }
     return bits;
