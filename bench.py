@@ -381,9 +381,10 @@ def bench_large(a):
     err = float((bf16_last - out).abs().max() / out.abs().max().clamp_min(1e-30))
     pairs = N * Bq
     T_tiles = -(-W // 16) * -(-H // 16)
-    segs = -(-T_tiles // 256)  # binning segments of 256 tiles (one 8-bit digit)
+    seg = 256 if T_tiles <= 256 else 512  # binning segment: one 8- or 9-bit digit
+    segs = -(-T_tiles // seg)
     keys = work["entries"]
-    hist_entries = Bq * segs * 256 * -(-N // (1024 if segs == 1 else 8192))
+    hist_entries = Bq * segs * seg * -(-N // (1024 if seg == 256 else 8192))
     list_bytes = pairs * 24 + keys * 4 + hist_entries * 12 + Bq * T_tiles * 8
     list_ms = st["scan"] + st["emit_keys"] + st["radix_sort"] + st["tile_ranges"]
     flops = float(FLOP_PER_PAIR) * pairs
@@ -557,11 +558,12 @@ def main():
     work = ctx.blend_work()
     st_ms = {k: v[0] / max(v[1], 1) for k, v in stages.items()}
     T_tiles = -(-a.width // 16) * -(-a.height // 16)
-    segs = -(-T_tiles // 256)  # binning segments of 256 tiles (one 8-bit digit)
-    binned = Bq <= 65535 and segs <= 16
+    seg = 256 if T_tiles <= 256 else 512  # binning segment: one 8- or 9-bit digit
+    segs = -(-T_tiles // seg)
+    binned = Bq <= 65535 and T_tiles <= 4096
     pairs = N * Bq
     if binned:
-        hist_entries = Bq * segs * 256 * -(-N // (1024 if segs == 1 else 8192))
+        hist_entries = Bq * segs * seg * -(-N // (1024 if seg == 256 else 8192))
         bin_bytes = pairs * 24 + work["entries"] * 4 + hist_entries * 12 + Bq * T_tiles * 8
         bin_ms = st_ms["scan"] + st_ms["radix_sort"] + st_ms["tile_ranges"]
         bin_note = ("binning: rect+count read twice (24 B/pair), 4 B/list entry written, histogram scan 12 B/entry, "

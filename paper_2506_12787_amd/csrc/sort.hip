@@ -292,32 +292,33 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const K* __rest
 // ---- binning: per-query stable counting sort by tile -----------------------
 // Pairs are stored in (query, depth) order and a pair covers a tile at most
 // once, so the list of a tile is the pairs covering it in pair order. A query's
-// tiles are split into S segments of 256 (one 8-bit digit each); every query is
+// tiles are split into S segments of 2^db tiles (one db-bit digit each: db = 8
+// with at most 256 tiles per query, else 9); every query is
 // binned by a stable counting pass per segment, which gives exactly the order
 // of the full (tile, depth) sort without materialising keys in memory.
 //   bin_hist:    block (j, q) histograms the tiles covered by pairs
 //                [j * pb, (j + 1) * pb) of query q, for every segment s;
-//                hist[((q * S + s) * 256 + tile - 256 s) * nbq + j]
+//                hist[((q * S + s) * 2^db + tile - 2^db s) * nbq + j]
 //   scan:        one exclusive scan over that (query, tile, block) order gives
 //                every block's first output position per tile
 //   bin_scatter: the same block, segment by segment, computes its keys in pair
 //                order and writes each pair index to its position, ranked
-//                stably with wave64 ballots over the 8 digit bits
+//                stably with wave64 ballots over the db digit bits
 //   bin_ranges:  tile (q, t) spans [hist(q, t, 0), hist(q, t + 1, 0))
 struct BinGeom {
     int N, TW, tiles, db, S, pb, nbq;  // pairs per query, tile grid, digit bits, segments, pairs/block, blocks/query
 };
 
-constexpr int kSegTiles = 256;  // tiles per segment: one 8-bit digit
-constexpr int kMaxSegs = 16;    // segments one block handles (tiles per query <= 4096)
+constexpr int kWideDb = 9;       // digit bits when a query has more than 256 tiles (segments of 512)
+constexpr int kMaxTiles = 4096;           // tiles per query the binning path takes
 
 BinGeom bin_geom(int N, const Grid& g) {
     BinGeom b;
     b.N = N;
     b.TW = g.TW;
     b.tiles = g.tiles;
-    b.db = 8;
-    b.S = std::max(1, (g.tiles + kSegTiles - 1) / kSegTiles);
+    b.db = g.tiles <= 256 ? 8 : kWideDb;
+    b.S = std::max(1, (g.tiles + (1 << b.db) - 1) >> b.db);
     b.pb = b.S == 1 ? 1024 : 8192;  // larger blocks keep the (S x 256 x blocks) histogram small
     b.nbq = std::max(1, (N + b.pb - 1) / b.pb);
     return b;
@@ -353,7 +354,8 @@ __device__ __forceinline__ uint32_t seg_count(uint2 r, int TW, int t0, int seg) 
 __global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restrict__ rect,
                                                             const uint32_t* __restrict__ count, BinGeom G,
                                                             uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kMaxSegs * kSegTiles];
+    __shared__ uint32_t h[kMaxTiles + 1024];  // S segments of 2^db tiles: at most kMaxTiles + 2^db - 1
+    const int kSegTiles = 1 << G.db;
     const bool one = G.S == 1;
     const int n = one ? kWaves * kSegTiles : G.S * kSegTiles;
     for (int i = threadIdx.x; i < n; i += kThreads) h[i] = 0;
@@ -447,13 +449,13 @@ __device__ __forceinline__ uint32_t seg_tile_at(int a0, int rb, uint32_t n0, uin
 // ranks it among equal tiles with wave64 ballots, and the ranks are offset per
 // wave and per tile through LDS counters; base[] holds each tile's next output
 // position for this block.
-template <int PPT>
+template <int PPT, int DB>
 __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __restrict__ rect,
                                                                const uint32_t* __restrict__ count, BinGeom G,
                                                                const uint32_t* __restrict__ hs,
                                                                const uint64_t* __restrict__ n_dev,
                                                                uint32_t* __restrict__ vals) {
-    constexpr int kSeg = kSegTiles;
+    constexpr int kSeg = 1 << DB;
     constexpr int kBatch = kThreads * PPT;
     // fixed-capacity run that overflowed: nothing is placed (block-uniform)
     if (n_dev && *n_dev == 0) return;
@@ -543,7 +545,7 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
                     }
                     dig[jj] = d;
                     pl[jj] = pr;
-                    const uint2 rc = digit_match<8>(d, ok[jj]);
+                    const uint2 rc = digit_match<DB>(d, ok[jj]);
                     const uint32_t rank = rc.x, cnt = rc.y;
                     uint32_t prev = 0;
                     if (ok[jj]) prev = wcnt[w][d];
@@ -736,7 +738,7 @@ void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gt
         tile_ranges_kernel<false><<<blocks, 256, 0, st>>>(keys, n, ranges, n_dev);
 }
 
-bool bin_fits(int B, int N, const Grid& g) { return B <= 65535 && bin_geom(N, g).S <= kMaxSegs; }
+bool bin_fits(int B, int N, const Grid& g) { return B <= 65535 && g.tiles <= kMaxTiles; }
 
 size_t bin_hist_entries(int B, int N, const Grid& g) {
     const BinGeom G = bin_geom(N, g);
@@ -757,10 +759,11 @@ void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uin
                         const uint64_t* n_dev, uint32_t* vals, hipStream_t st) {
     if (B <= 0 || N <= 0) return;
     const BinGeom G = bin_geom(N, g);
-    if (G.S == 1)
-        bin_scatter_kernel<1><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev, vals);
+    if (G.S == 1 && G.db == 8)
+        bin_scatter_kernel<1, 8><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev, vals);
     else
-        bin_scatter_kernel<4><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev, vals);
+        bin_scatter_kernel<4, kWideDb><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev,
+                                                                          vals);
 }
 
 void launch_bin_ranges(const uint32_t* hist_scanned, int B, int N, const Grid& g, const uint64_t* total,

@@ -5,7 +5,7 @@ render 256 full spectra, so sampled pixels of a few queries are compared one by
 one (the oracle composites an arbitrary pixel list over all N Gaussians): the
 FP32 MLP against the FP64 oracle, the BF16 MLP against the oracle that rounds
 like the kernel. With 2070 tiles per query the lists are built by binning in
-9 segments of 256 tiles."""
+5 segments of 512 tiles."""
 import numpy as np
 import pytest
 

@@ -116,9 +116,9 @@ def test_binned_lists_equal_full_sort(ctx, n, scale, batch, H, W):
     full 64-bit (tile, depth) radix sort: counts, keys, values and ranges
     bitwise, and the same images. Large Gaussians put tens of thousands of keys
     into one 256-pair batch (several 2048-key chunks); N is ragged against the
-    pair blocks (1024, or 8192 with several tile segments); 180 x 720 (540
-    tiles, 3 segments of 256) and 250 x 1100 (1104 tiles, 5 segments) bin segment
-    by segment; deformation differs per query."""
+    pair blocks (1024, or 8192 beyond 256 tiles); 180 x 720 (540 tiles, 2
+    segments of 512) and 250 x 1100 (1104 tiles, 3 segments) bin segment by
+    segment; deformation differs per query."""
     import torch
     from paper_2506_12787_amd import binding as B
     from paper_2506_12787_amd import synth
@@ -146,7 +146,7 @@ def test_binned_lists_equal_full_sort(ctx, n, scale, batch, H, W):
 @pytest.mark.parametrize("H,W", [(1024, 1024), (4096, 4096)])
 def test_maximum_grids_sampled_pixels(ctx, H, W):
     """The largest grids: 1024 x 1024 is 4096 tiles per query, the most the
-    binning path takes (16 segments of 256); 4096 x 4096 (the largest accepted
+    binning path takes (8 segments of 512); 4096 x 4096 (the largest accepted
     size, 65536 tiles) takes the sort path. Static FP32 render, sampled pixels
     against the FP64 oracle; the 1024 grid also against the full sort, bitwise."""
     from paper_2506_12787_amd import binding as B
