@@ -124,7 +124,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     // FP32: dz ping-pong. BF16: dz ping-pong in BF16 + one FP32 GEMM result.
     if ((s = w.dz.reserve(this, bf16 ? actb * 2 + f32b + 16 : actb * 2 + 16, st))) return s;
     // scratch: Pm / S (N x 256), R (B x 256), dg (N x 26), split-K partials, column-sum partials, BF16 weights
-    const size_t n_split = (size_t)split_of(P) * Hd * Hd;
+    const size_t n_split = std::max((size_t)split_of(P) * Hd * Hd, (size_t)layer1_sums_blocks((int)N) * B * Hd);
     const size_t n_cs = std::max<size_t>({(size_t)colsum_blocks(P) * Hd, (size_t)colsum_blocks(B) * N * Hd,
                                           (size_t)colsum_blocks(N) * Hd * B, (size_t)colsum_blocks(kMaxSplit) * Hd * Hd});
     const size_t n_wb = bf16 ? ((size_t)(nh - 1) * Hd * Hd + (size_t)kOut * Hd + (size_t)P * kOut + 64) / 2 + 64 : 0;
@@ -195,10 +195,9 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
             if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, kOut, dyb, kOut, wl[nh], Hd, dz[0], Hd, true), "gemm dz")))
                 return s;
             launch_relu_mask_inplace_bf16(dz[0], act[nh - 1], P, st);
-        } else {
+        } else {  // the layer-1 gradient, masked inside its sums below
             if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, kOut, dyb, kOut, wl[nh], Hd, zf, Hd), "gemm dz")))
                 return s;
-            launch_relu_mask_f32_bf16act(zf, act[0], P, st);
         }
     } else {
         if ((s = ok(gemm_rm(h, false, false, P, Hd, kOut, dy, kOut, d.w[nh], Hd, (float*)dz[0], Hd), "sgemm dz")))
@@ -227,10 +226,9 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
                             "gemm dz")))
                     return s;
                 launch_relu_mask_inplace_bf16(dz[cur ^ 1], act[l - 1], P, st);
-            } else {
+            } else {  // the layer-1 gradient, FP32, masked inside its sums below
                 if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, Hd, dz[cur], Hd, wl[l], Hd, zf, Hd), "gemm dz")))
                     return s;
-                launch_relu_mask_f32_bf16act(zf, act[0], P, st);  // layer-1 gradient kept in FP32
             }
         } else {
             if ((s = ok(gemm_rm(h, false, false, P, Hd, Hd, (const float*)dz[cur], Hd, d.w[l], Hd,
@@ -241,17 +239,21 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
         }
         cur ^= 1;
     }
-    // ---- layer 1: the gradient of its pre-activations, FP32 (in zf on the BF16 path)
-    const float* dz0 = bf16 ? zf : (const float*)dz[cur];
-    auto colsum_any = [&](int64_t rows, int64_t cols, int nz, int64_t bs, float* out, int64_t out_bs) {
-        launch_colsum(dz0, rows, cols, nz, bs, tmp, out, out_bs, st);
-    };
-    if (gr->bias[0]) colsum_any(P, Hd, 1, 0, gr->bias[0], 0);
-    float* S = Pm;  // per Gaussian, summed over the batch (N x 256)
-    colsum_any(B, N * Hd, 1, 0, S, 0);
+    // ---- layer 1: the gradient of its pre-activations dz0, FP32; S = its sum over the batch per Gaussian
+    // (N x 256), R = its sum over the Gaussians per query (B x 256), b0 = its sum over all pairs
+    float* S = Pm;
+    if (bf16) {
+        // zf is dz0 before the ReLU mask: one pass gives S and per-block partial sums of R
+        launch_layer1_sums(zf, act[0], (int)B, (int)N, S, part, st);
+        if (gr->weight[0]) launch_colsum(part, layer1_sums_blocks((int)N), B * Hd, 1, 0, tmp, R, 0, st);
+        if (gr->bias[0]) launch_colsum(S, N, Hd, 1, 0, tmp, gr->bias[0], 0, st);
+    } else {
+        const float* dz0 = (const float*)dz[cur];
+        if (gr->bias[0]) launch_colsum(dz0, P, Hd, 1, 0, tmp, gr->bias[0], 0, st);
+        launch_colsum(dz0, B, N * Hd, 1, 0, tmp, S, 0, st);
+        if (gr->weight[0]) launch_colsum(dz0, N, Hd, B, N * Hd, tmp, R, Hd, st);
+    }
     if (gr->weight[0]) {
-        // per query, summed over the Gaussians (B x 256)
-        colsum_any(N, Hd, B, N * Hd, R, Hd);
         // dW1 [256 x 89] = [S^T gamma(mu_hat) | R^T gamma(s_hat)]
         if ((s = ok(gemm_rm(h, true, false, Hd, kMeanFeat, N, S, Hd, fmean, kMeanFeat, gr->weight[0], I), "dW1m")))
             return s;

@@ -441,18 +441,6 @@ __global__ void bias_relu_bf16_kernel(const float* __restrict__ z, const float* 
     o[3] = to_bf16(fmaxf(v.w + b.w, 0.f));
 }
 
-// d[p][k] *= [act[p][k] > 0] in place, FP32 d, BF16 act (the layer-1 gradient
-// stays in FP32: its column sums feed the first layer's weight gradient)
-__global__ void relu_mask_f32_bf16act_kernel(float* __restrict__ d, const __bf16* __restrict__ act, int64_t P) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * 64) return;
-    float4 v = *reinterpret_cast<float4*>(d + i * 4);
-    const __bf16* a = act + i * 4;
-    v = make_float4((float)a[0] > 0.f ? v.x : 0.f, (float)a[1] > 0.f ? v.y : 0.f, (float)a[2] > 0.f ? v.z : 0.f,
-                    (float)a[3] > 0.f ? v.w : 0.f);
-    *reinterpret_cast<float4*>(d + i * 4) = v;
-}
-
 // d[p][k] = [act[p][k] > 0] ? d[p][k] : 0 in place, BF16 d and act (8 per thread)
 __global__ void relu_mask_inplace_bf16_kernel(__bf16* __restrict__ d, const __bf16* __restrict__ act, int64_t n8) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -469,6 +457,66 @@ __global__ void relu_mask_inplace_bf16_kernel(__bf16* __restrict__ d, const __bf
     v.z = m(v.z, a.z);
     v.w = m(v.w, a.w);
     reinterpret_cast<uint4*>(d)[i] = v;
+}
+
+// Layer-1 gradient sums of a BF16 backward in one pass over the unmasked FP32
+// gradient z [B][N][256] and the BF16 activations act [B][N][256]: with
+// dz = z * [act > 0], S[n][k] = sum_b dz[b][n][k] (complete: the block owns
+// Gaussians n0 .. n0 + 63, summed over b in order) and Rpart[block][b][k] =
+// sum over the block's Gaussians of dz[b][n][k] (4 row groups through LDS).
+constexpr int kSumRows = 64;
+
+__global__ __launch_bounds__(256) void layer1_sums_kernel(const float* __restrict__ z, const __bf16* __restrict__ act,
+                                                          int B, int N, float* __restrict__ S,
+                                                          float* __restrict__ Rpart) {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int c = tx * 4;
+    const int n0 = blockIdx.x * kSumRows;
+    float4 sacc[kSumRows / 4];
+#pragma unroll
+    for (int i = 0; i < kSumRows / 4; ++i) sacc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __shared__ float4 red[4][64];
+    for (int b = 0; b < B; ++b) {
+        float4 racc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < kSumRows / 4; ++i) {
+            const int n = n0 + ty + 4 * i;
+            if (n < N) {
+                const size_t off = ((size_t)b * N + n) * 256 + c;
+                const float4 v = load4(z + off);
+                const float4 a = load4(act + off);
+                const float4 m = make_float4(a.x > 0.f ? v.x : 0.f, a.y > 0.f ? v.y : 0.f, a.z > 0.f ? v.z : 0.f,
+                                             a.w > 0.f ? v.w : 0.f);
+                sacc[i].x += m.x;
+                sacc[i].y += m.y;
+                sacc[i].z += m.z;
+                sacc[i].w += m.w;
+                racc.x += m.x;
+                racc.y += m.y;
+                racc.z += m.z;
+                racc.w += m.w;
+            }
+        }
+        red[ty][tx] = racc;
+        __syncthreads();
+        if (ty == 0) {
+            float4 t = red[0][tx];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) {
+                t.x += red[k][tx].x;
+                t.y += red[k][tx].y;
+                t.z += red[k][tx].z;
+                t.w += red[k][tx].w;
+            }
+            *reinterpret_cast<float4*>(Rpart + ((size_t)blockIdx.x * B + b) * 256 + c) = t;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < kSumRows / 4; ++i) {
+        const int n = n0 + ty + 4 * i;
+        if (n < N) *reinterpret_cast<float4*>(S + (size_t)n * 256 + c) = sacc[i];
+    }
 }
 
 __global__ void to_bf16_kernel(const float* __restrict__ x, int64_t n, __bf16* __restrict__ y) {
@@ -592,16 +640,18 @@ void launch_bias_relu_bf16(const float* z, const float* bias, int64_t P, void* o
     if (P > 0) bias_relu_bf16_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(z, bias, P, (__bf16*)out);
 }
 
-void launch_relu_mask_f32_bf16act(float* d, const void* act, int64_t P, hipStream_t st) {
-    if (P > 0)
-        relu_mask_f32_bf16act_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(d, (const __bf16*)act, P);
-}
-
 void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStream_t st) {
     const int64_t n8 = P * 32;  // 256 columns = 32 groups of 8
     if (n8 > 0)
         relu_mask_inplace_bf16_kernel<<<(unsigned)((n8 + 255) / 256), 256, 0, st>>>((__bf16*)d, (const __bf16*)act,
                                                                                    n8);
+}
+
+int layer1_sums_blocks(int N) { return (N + kSumRows - 1) / kSumRows; }
+
+void launch_layer1_sums(const float* z, const void* act, int B, int N, float* S, float* Rpart, hipStream_t st) {
+    if (N > 0 && B > 0)
+        layer1_sums_kernel<<<layer1_sums_blocks(N), 256, 0, st>>>(z, (const __bf16*)act, B, N, S, Rpart);
 }
 
 void launch_to_bf16(const float* x, int64_t n, void* y, hipStream_t st) {

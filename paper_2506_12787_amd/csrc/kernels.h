@@ -111,8 +111,10 @@ void launch_pe_chain(const float* dg, const DevScene& s, float* dmu, hipStream_t
 // BF16 operands of the MLP backward of a BF16 forward (void* = __bf16 arrays)
 void launch_layer1_act_bf16(const float* Pm, const float* qs, int N, int64_t P, void* act, hipStream_t st);
 void launch_bias_relu_bf16(const float* z, const float* bias, int64_t P, void* out, hipStream_t st);
-void launch_relu_mask_f32_bf16act(float* d, const void* act, int64_t P, hipStream_t st);
 void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStream_t st);
+// S [N][256] = sum_b of z * [act > 0] and Rpart [layer1_sums_blocks(N)][B][256] partial sums over Gaussians
+int layer1_sums_blocks(int N);
+void launch_layer1_sums(const float* z, const void* act, int B, int N, float* S, float* Rpart, hipStream_t st);
 void launch_to_bf16(const float* x, int64_t n, void* y, hipStream_t st);
 void launch_colsum_bf16(const void* A, int64_t rows, int64_t cols, int nz, int64_t bs, float* part, float* out,
                         int64_t out_bs, hipStream_t st);
