@@ -45,3 +45,56 @@ def parity(gpu: np.ndarray, res: M.RenderResult, tol_rel=TOL_REL):
         raise AssertionError(f"parity failed at {rep['failures']} pixels; first {bad.tolist()} "
                              f"gpu={g[bad].tolist()} oracle={res.C[bad].tolist()} report={rep}")
     return rep
+
+
+# ---------------------------------------------------------------------------
+# Hand-worked fixtures under tests/golden/: expected values are closed forms
+# written as small arithmetic expressions (numbers, + - * / **, exp, sqrt, and
+# names bound by the case's "let").
+# ---------------------------------------------------------------------------
+GOLDEN_DIR = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def golden(name: str) -> dict:
+    import json
+    import os
+    with open(os.path.join(GOLDEN_DIR, name)) as f:
+        return json.load(f)
+
+
+def closed_form(expr: str, env: dict | None = None) -> float:
+    """Evaluate a fixture's closed form in float64 (no other names or calls)."""
+    import ast
+    import math
+    funcs = {"exp": math.exp, "sqrt": math.sqrt}
+    env = env or {}
+    ops = {ast.Add: lambda a, b: a + b, ast.Sub: lambda a, b: a - b, ast.Mult: lambda a, b: a * b,
+           ast.Div: lambda a, b: a / b, ast.Pow: lambda a, b: a ** b}
+
+    def ev(n):
+        if isinstance(n, ast.Expression):
+            return ev(n.body)
+        if isinstance(n, ast.Constant) and isinstance(n.value, (int, float)):
+            return float(n.value)
+        if isinstance(n, ast.BinOp) and type(n.op) in ops:
+            return ops[type(n.op)](ev(n.left), ev(n.right))
+        if isinstance(n, ast.UnaryOp) and isinstance(n.op, (ast.USub, ast.UAdd)):
+            v = ev(n.operand)
+            return -v if isinstance(n.op, ast.USub) else v
+        if isinstance(n, ast.Name) and n.id in env:
+            return env[n.id]
+        if isinstance(n, ast.Call) and isinstance(n.func, ast.Name) and n.func.id in funcs and len(n.args) == 1:
+            return funcs[n.func.id](ev(n.args[0]))
+        raise ValueError(f"unsupported closed form: {expr!r}")
+
+    return ev(ast.parse(expr, mode="eval"))
+
+
+def golden_pixel(px: dict) -> tuple:
+    """(C, T) of one fixture pixel, its 'let' names bound first."""
+    env = {k: closed_form(v) for k, v in px.get("let", {}).items()}
+    return closed_form(px["C"], env), closed_form(px["T"], env)
+
+
+def golden_scene(case: dict) -> dict:
+    return {k: np.asarray(v, np.float32) for k, v in case["gaussians"].items()}
