@@ -133,9 +133,12 @@ mlp_bf16_kernel(Bf16Args a) {
     __shared__ __attribute__((aligned(16))) float qs_s[2][256];
     __shared__ __attribute__((aligned(16))) float bias_s[7][256];
     __shared__ __attribute__((aligned(16))) float bias_o_s[16];
+    // Layer-1 B operand of the wave's pairs (bf16 gamma(mu_hat), lane order),
+    // copied global -> LDS one tile ahead.
+    __shared__ __attribute__((aligned(16))) uint4 bm_s[WAVES][NCB][64];
 
     const int tid = threadIdx.x;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar registers
     const int lane = tid & 63;
     const int g = lane >> 4;       // lane group (k / feature sub-block)
     const int n16 = lane & 15;     // pair column inside a 16-wide block
@@ -167,6 +170,20 @@ mlp_bf16_kernel(Bf16Args a) {
             if (i_ * WAVES + wave < nf_) dma_b128(src_ + i_ * 64 * WAVES, dst_ + i_ * 1024 * WAVES);       \
         fetch = fetch + 1 == S ? 0 : fetch + 1;                                                            \
     } while (0)
+    // gamma(mu_hat) of the pairs of tile t_ into bm_s (rows past N read row
+    // N - 1; layer 1 zeroes them); awaited by the wait before the next barrier.
+    const uint32_t bm_lds = (uint32_t)(uintptr_t)(lds_ptr)&bm_s[wave][0][0];
+#define SWF_FETCH_BM(tile_)                                                                              \
+    do {                                                                                                 \
+        const int t_ = (tile_);                                                                          \
+        const int qy_ = t_ / a.tiles_per_query;                                                          \
+        const int pp_ = (t_ - qy_ * a.tiles_per_query) * kPairsPerBlock + wave * kPairsPerWave;          \
+        _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) {                                             \
+            const int p_ = min(pp_ + cb * 16 + n16, a.m.N - 1);                                          \
+            dma_b128(reinterpret_cast<const uint4*>(a.mfeat) + (size_t)p_ * 4 + g, bm_lds + cb * 1024);  \
+        }                                                                                                \
+    } while (0)
+    SWF_FETCH_BM((int)blockIdx.x);
     SWF_DMA(0);
     if (q_end > 1) SWF_DMA(1);
     vmem_wait_all();
@@ -271,7 +288,7 @@ mlp_bf16_kernel(Bf16Args a) {
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             const int p = p0 + cb * 16 + n16;
-            bm[cb] = p < a.m.N ? a.mfeat[(size_t)p * 4 + g] : bf16x8{};
+            bm[cb] = p < a.m.N ? __builtin_bit_cast(bf16x8, bm_s[wave][cb][lane]) : bf16x8{};
         }
         SWF_ADVANCE();
         {
@@ -294,6 +311,9 @@ mlp_bf16_kernel(Bf16Args a) {
             }
         }
         SWF_NEXT_STEP();
+        // the next tile's layer-1 operand (this wave's reads of bm_s are complete:
+        // the MFMAs of layer 1 consumed them)
+        if (it + 1 < my_tiles) SWF_FETCH_BM(tile + (int)gridDim.x);
         // TX term of the next tile's query, stored to LDS before this tile's
         // last barrier (the other buffer is read by this tile's layer 1 only)
         const int next_tile = tile + (int)gridDim.x;
@@ -327,6 +347,7 @@ mlp_bf16_kernel(Bf16Args a) {
 #undef SWF_PACK
 #undef SWF_HIDDEN
 #undef SWF_OUTPUT
+#undef SWF_FETCH_BM
 }
 
 __global__ void mean_features_bf16_kernel(const float* __restrict__ mx, const float* __restrict__ my, int n, int W,
