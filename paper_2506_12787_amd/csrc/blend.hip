@@ -34,23 +34,22 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     constexpr int kN = TILE * TILE;
     constexpr int kUnroll = 8;  // entries per unrolled group (kN is a multiple)
     static_assert(kN % 64 == 0, "whole waves per tile");
-    // entry kN is a never-contributing dummy (opacity 0) used as padding
-    __shared__ float2 s_pos[kN + 1];
-    __shared__ float4 s_wm[kN + 1];
-    __shared__ float2 s_oa[kN + 1];
+    // Staged record j, 32 bytes: s_rec[2j] = (block-relative mean x, y, opacity,
+    // amplitude), s_rec[2j + 1] = the whitening rows M. Entry kN is a
+    // never-contributing dummy (opacity 0) used as padding.
+    __shared__ float4 s_rec[2 * (kN + 1)];
     // 16x16 tiles: bit w of s_strip[j] is set unless entry j's quadratic form
     // exceeds the cutoff (with a margin) everywhere on the 8 x 8 quadrant of
     // wave w; each wave walks only those entries (the others
     // fail the cutoff at every one of its pixels), from its own compacted list
-    // s_idx[w] padded with the dummy.
+    // s_idx[w] (byte offsets of the records in s_rec) padded with the dummy.
     constexpr bool kCull = TILE == 16 && !kCount;
     constexpr int kWaves = kN / 64;
     __shared__ uint8_t s_strip[kCull ? kN : 1];
-    __shared__ __attribute__((aligned(16))) uint16_t s_idx[kCull ? kWaves : 1][kN + kUnroll];
+    __shared__ __attribute__((aligned(16))) uint32_t s_idx[kCull ? kWaves : 1][kN + kUnroll];
     if (threadIdx.x == 0) {
-        s_pos[kN] = make_float2(0.0f, 0.0f);
-        s_wm[kN] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        s_oa[kN] = make_float2(0.0f, 0.0f);
+        s_rec[2 * kN] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        s_rec[2 * kN + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
 
     const int gtile = blockIdx.x;
@@ -85,17 +84,16 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
             const float4 g = geo[v];
             const float2 pos = make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
             const float4 m = wm[v];
-            s_pos[threadIdx.x] = pos;
-            s_wm[threadIdx.x] = m;
-            s_oa[threadIdx.x] = oa[v];
+            const float2 o = oa[v];
+            s_rec[2 * threadIdx.x] = make_float4(pos.x, pos.y, o.x, o.y);
+            s_rec[2 * threadIdx.x + 1] = m;
             if (kCull)  // block-relative first column and row of the tile
                 s_strip[threadIdx.x] =
                     (uint8_t)wave_quads_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
         } else if ((int)threadIdx.x < ((cnt + kUnroll - 1) & ~(kUnroll - 1))) {
             // padding up to the unrolled length: opacity 0 never contributes
-            s_pos[threadIdx.x] = make_float2(0.0f, 0.0f);
-            s_wm[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            s_oa[threadIdx.x] = make_float2(0.0f, 0.0f);
+            s_rec[2 * threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            s_rec[2 * threadIdx.x + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
         __syncthreads();
         if (kCount) staged += (uint32_t)cnt;
@@ -110,28 +108,32 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
         // are done.
         if (kCull) {
             const int wv = threadIdx.x >> 6;
-            uint16_t* idx = s_idx[wv];
+            uint32_t* idx = s_idx[wv];
             int nlist = 0;
 #pragma unroll
             for (int c = 0; c < kWaves; ++c) {
                 const int jl = c * 64 + (int)lane_id();
                 const bool f = jl < cnt && ((s_strip[jl] >> wv) & 1u);
                 const uint64_t bal = __ballot(f);
-                if (f) idx[nlist + __popcll(bal & ((1ull << lane_id()) - 1ull))] = (uint16_t)jl;
+                if (f) idx[nlist + __popcll(bal & ((1ull << lane_id()) - 1ull))] = (uint32_t)jl * 32u;
                 nlist += __popcll(bal);
             }
-            if ((int)lane_id() < kUnroll) idx[nlist + lane_id()] = (uint16_t)kN;  // padding
+            if ((int)lane_id() < kUnroll) idx[nlist + lane_id()] = (uint32_t)kN * 32u;  // padding
             __builtin_amdgcn_wave_barrier();
             for (int j0 = 0; j0 < nlist; j0 += kUnroll) {
                 if (__all(done)) break;
-                const uint4 jv = *reinterpret_cast<const uint4*>(idx + j0);  // 8 entry indices
-                const uint32_t jw[4] = {jv.x, jv.y, jv.z, jv.w};
+                const uint4 ja = *reinterpret_cast<const uint4*>(idx + j0);  // 8 record offsets
+                const uint4 jb = *reinterpret_cast<const uint4*>(idx + j0 + 4);
+                const uint32_t jw[8] = {ja.x, ja.y, ja.z, ja.w, jb.x, jb.y, jb.z, jb.w};
 #pragma unroll
                 for (int jj = 0; jj < kUnroll; ++jj) {
-                    const int j = (int)((jw[jj >> 1] >> (16 * (jj & 1))) & 0xffffu);
+                    const char* rp = reinterpret_cast<const char*>(s_rec) + jw[jj];
+                    const float4 r0 = *reinterpret_cast<const float4*>(rp);
+                    const float4 m = *reinterpret_cast<const float4*>(rp + 16);
+                    const int j = (int)(jw[jj] >> 5);
                     float dx, dy, u, w;
-                    const float q = blend_q(fx, fy, s_pos[j], s_wm[j], dx, dy, u, w);
-                    const float2 o = s_oa[j];
+                    const float q = blend_q(fx, fy, make_float2(r0.x, r0.y), m, dx, dy, u, w);
+                    const float2 o = make_float2(r0.z, r0.w);
                     const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
                     const float ae = (!done && q <= kQMax && a >= kAlphaMin) ? a : 0.0f;
                     const float Tn = T * (1.0f - ae);
@@ -148,10 +150,11 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
 #pragma unroll
                 for (int jj = 0; jj < kUnroll; ++jj) {
                     const int j = j0 + jj;
+                    const float4 r0 = s_rec[2 * j];
                     float dx, dy, u, w;
-                    const float q = blend_q(fx, fy, s_pos[j], s_wm[j], dx, dy, u, w);
+                    const float q = blend_q(fx, fy, make_float2(r0.x, r0.y), s_rec[2 * j + 1], dx, dy, u, w);
                     if (kCount) evals += (!done && j < cnt && q <= kQMax) ? 1u : 0u;
-                    const float2 o = s_oa[j];
+                    const float2 o = make_float2(r0.z, r0.w);
                     const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
                     // a skipped entry (cutoff, alpha floor, or a finished pixel) acts
                     // with alpha 0: T * (1 - 0) and C + 0 * T are exact no-ops
