@@ -140,7 +140,9 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
                     const bool stop = Tn < kTMin;
                     C = stop ? C : fmaf(o.y * ae, T, C);
                     if (kAux) last = (!stop && ae > 0.0f) ? base + (uint32_t)j : last;
-                    T = stop ? T : Tn;
+                    // without aux the final T is not kept: a stopped lane may
+                    // take Tn (< the floor), it adds nothing afterwards either way
+                    T = (kAux && stop) ? T : Tn;
                     done = done || stop;
                 }
             }
