@@ -106,7 +106,7 @@ void blas_release(Ctx* c) {
 // and every large GEMM runs on BF16 operands with FP32 accumulation; weight
 // and bias gradients are accumulated in FP32.
 swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,
-                             const swf_grads* gr, bool bf16, hipStream_t st) {
+                             const swf_grads* gr, bool bf16, bool acts_ready, hipStream_t st) {
     swf_status s = SWF_OK;
     if (!blas) {
         rocblas_handle h = nullptr;
@@ -163,22 +163,25 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
         dyb = wl[nh] + (size_t)kOut * Hd;
         launch_to_bf16(dy, P * kOut, dyb, st);
     }
-    // ---- recompute the hidden activations
-    if ((s = ok(gemm_rm(h, false, true, N, Hd, kMeanFeat, fmean, kMeanFeat, d.w[0], I, Pm, Hd), "sgemm W1m"))) return s;
-    if (bf16)
-        launch_layer1_act_bf16(Pm, qs, (int)N, P, act[0], st);
-    else
-        launch_layer1_act(Pm, qs, (int)N, P, (float*)act[0], st);
-    for (int l = 1; l < nh; ++l) {
-        if (bf16) {
-            if ((s = ok(gemm_rm_bf16(h, false, true, P, Hd, Hd, act[l - 1], Hd, wl[l], Hd, zf, Hd), "gemm fwd")))
-                return s;
-            launch_bias_relu_bf16(zf, d.b[l], P, act[l], st);
-        } else {
-            if ((s = ok(gemm_rm(h, false, true, P, Hd, Hd, (float*)act[l - 1], Hd, d.w[l], Hd, (float*)act[l], Hd),
-                        "sgemm fwd")))
-                return s;
-            launch_bias_relu((float*)act[l], d.b[l], P, st);
+    // ---- the hidden activations: stored by the forward pass (BF16), else recomputed
+    if (!(bf16 && acts_ready)) {
+        if ((s = ok(gemm_rm(h, false, true, N, Hd, kMeanFeat, fmean, kMeanFeat, d.w[0], I, Pm, Hd), "sgemm W1m")))
+            return s;
+        if (bf16)
+            launch_layer1_act_bf16(Pm, qs, (int)N, P, act[0], st);
+        else
+            launch_layer1_act(Pm, qs, (int)N, P, (float*)act[0], st);
+        for (int l = 1; l < nh; ++l) {
+            if (bf16) {
+                if ((s = ok(gemm_rm_bf16(h, false, true, P, Hd, Hd, act[l - 1], Hd, wl[l], Hd, zf, Hd), "gemm fwd")))
+                    return s;
+                launch_bias_relu_bf16(zf, d.b[l], P, act[l], st);
+            } else {
+                if ((s = ok(gemm_rm(h, false, true, P, Hd, Hd, (float*)act[l - 1], Hd, d.w[l], Hd, (float*)act[l], Hd),
+                            "sgemm fwd")))
+                    return s;
+                launch_bias_relu((float*)act[l], d.b[l], P, st);
+            }
         }
     }
     // ---- output layer (7 outputs)
@@ -274,8 +277,20 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
     const DevScene& d = sc->d;
     const bool deform = !(flags & SWF_NO_DEFORM);
+    const bool want_mlp = deform && d.has_mlp;
+    // After a BF16 forward the MLP kernel of the forward pass below also stores the
+    // hidden activations the MLP backward needs (the same values the forward used).
+    const bool bf16 = (flags & SWF_MLP_BF16) != 0;
+    const bool acts_ready = want_mlp && bf16 && B >= 1 && (uint64_t)B * (uint64_t)d.n < (1ull << 32);
+    swf_status s = SWF_OK;
+    if (acts_ready) {
+        const size_t actb = (size_t)B * d.n * 256 * sizeof(uint16_t);
+        if ((s = w.act.reserve(this, actb * d.n_hidden + 16, st))) return s;
+        w.act_out = w.act.ptr;
+    }
     // 1. the forward lists again (deterministic: identical to the forward's)
-    swf_status s = forward_lists(w, sid, tx, B, flags & ~SWF_KEEP_AUX, st);
+    s = forward_lists(w, sid, tx, B, flags & ~SWF_KEEP_AUX, st);
+    w.act_out = nullptr;
     if (s) return s;
     const int64_t P = (int64_t)B * d.n;
     const size_t npix = (size_t)B * d.H * d.W;
@@ -288,7 +303,6 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     launch_blend_backward((const uint2*)w.ranges.ptr, w.last.vals, w.rec, B, w.last.grid, grad_out, auxT, auxL,
                           (float*)w.dpair.ptr, st);
     // 3. preprocess backward -> residual-coordinate gradients
-    const bool want_mlp = deform && d.has_mlp;
     float* dy = nullptr;
     if (want_mlp) {
         if ((s = w.dy.reserve(this, (size_t)P * kOut * sizeof(float) + 16, st))) return s;
@@ -299,7 +313,7 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     // 4. MLP backward (activations recomputed, GEMMs in rocBLAS; BF16 operands after a BF16 forward)
     float* dmu = nullptr;
     if (want_mlp) {
-        if ((s = mlp_backward(w, d, tx, B, dy, gr, (flags & SWF_MLP_BF16) != 0, st))) return s;
+        if ((s = mlp_backward(w, d, tx, B, dy, gr, bf16, acts_ready, st))) return s;
         dmu = (float*)w.dmu.ptr;
     }
     // 5. base parameters: sum over the batch, original ids

@@ -54,8 +54,9 @@ void launch_permute_delta(const float* delta_sorted, const uint32_t* perm, int B
 // mlp_bf16.hip
 bool bf16_available();
 void compute_mean_features_bf16(DevScene& s, hipStream_t st);
+// act_out (optional): also store the hidden activations, BF16 [n_hidden][B * N][256] (the backward's operands)
 void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
-                     float* delta_out, hipStream_t st, int pairs_per_wave);
+                     float* delta_out, hipStream_t st, int pairs_per_wave, void* act_out = nullptr);
 
 // sort.hip
 int scan_grid(int64_t n);

@@ -63,6 +63,8 @@ struct Bf16Args {
     const float* bias_o;      // output bias
     int n_tiles;              // B * tiles_per_query
     int tiles_per_query;      // ceil(N / pairs per block): tiles never straddle two queries
+    uint16_t* act_out;        // kAct: hidden activations (bf16 bits) [n_hidden][B * N][256]
+    int64_t act_stride;       // elements per activation layer: B * N * 256
 };
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -103,7 +105,9 @@ __device__ __forceinline__ void dma_b128(const uint4* src, uint32_t lds_addr) {
 __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // NCB column blocks of 16 pairs per wave; WAVES waves per block; ring steps of
-// STEP fragments; WPE waves per SIMD.
+// STEP fragments; WPE waves per SIMD. kAct: also store every hidden activation
+// (after the ReLU, in BF16, exactly the next layer's operand) row-major per
+// pair, for the backward pass.
 //
 // Weight ring: kSlots LDS slots of one step each. The step q + 2 is
 // copied global -> LDS directly (global_load_lds, no registers) at the start of
@@ -117,7 +121,7 @@ __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0
 // + bf16 conversion into the next layer's act[c'] is issued among the MFMAs of
 // the following tile (one column block per two fragments) instead of after
 // the layer; the last pair is converted during the next layer's first tile.
-template <int NCB, int WAVES, int STEP, int WPE>
+template <int NCB, int WAVES, int STEP, int WPE, bool kAct>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void
 mlp_bf16_kernel(Bf16Args a) {
     typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -215,12 +219,24 @@ mlp_bf16_kernel(Bf16Args a) {
         slot = slot == 2 ? 0 : slot + 1; \
     } while (0)
     // the empty asm pins the conversion where it is written (it would
-    // otherwise be sunk next to its first use, after the MFMAs it should overlap)
-#define SWF_PACK(dst_, cp_, cb_)                                                      \
+    // otherwise be sunk next to its first use, after the MFMAs it should overlap).
+    // lay_: index of the activation (0 = layer 1's output). With kAct the lane's
+    // 8 values (features 32 cp + 4 g + 0..3 and 32 cp + 16 + 4 g + 0..3 of its
+    // pair) are also stored.
+#define SWF_PACK(dst_, cp_, cb_, lay_)                                                \
     do {                                                                              \
         u32x4 u_ = __builtin_bit_cast(u32x4, pack_relu(acc[2 * (cp_)][cb_], acc[2 * (cp_) + 1][cb_])); \
         asm volatile("" : "+v"(u_));                                                  \
         dst_[cp_][cb_] = __builtin_bit_cast(bf16x8, u_);                              \
+        if (kAct) {                                                                   \
+            const int pa_ = p0 + (cb_) * 16 + n16;                                    \
+            if (pa_ < a.m.N) {                                                        \
+                uint2* d_ = reinterpret_cast<uint2*>(a.act_out + (size_t)(lay_) * a.act_stride + \
+                                                     (row0 + pa_) * 256 + 32 * (cp_) + 4 * g);  \
+                d_[0] = make_uint2(u_.x, u_.y);                                       \
+                d_[4] = make_uint2(u_.z, u_.w);                                       \
+            }                                                                         \
+        }                                                                             \
     } while (0)
 
     f32x4 acc[16][NCB];
@@ -247,9 +263,9 @@ mlp_bf16_kernel(Bf16Args a) {
                     _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) acc[t][cb] =                      \
                         mfma(w, act[IN_][c][cb], acc[t][cb]);                                            \
                 }                                                                                        \
-                if (t == 0 && c < NCB) SWF_PACK(act[IN_], 7, c);                                         \
+                if (t == 0 && c < NCB) SWF_PACK(act[IN_], 7, c, (L_));                                   \
                 if (t >= 2 && (t & 1) == 0 && (c & 1) == 0 && c / 2 < NCB)                               \
-                    SWF_PACK(act[OUT_], (t - 2) / 2, c / 2);                                             \
+                    SWF_PACK(act[OUT_], (t - 2) / 2, c / 2, (L_) + 1);                                   \
                 __builtin_amdgcn_sched_barrier(0);                                                       \
                 if (f == STEP - 1) SWF_NEXT_STEP();                                                      \
             }                                                                                            \
@@ -267,7 +283,7 @@ mlp_bf16_kernel(Bf16Args a) {
         _Pragma("unroll") for (int c = 0; c < 8; ++c) {                                                  \
             bf16x8 w;                                                                                    \
             SWF_TAKE(w, c, 8);                                                                           \
-            if (c < NCB) SWF_PACK(act[IN_], 7, c);                                                       \
+            if (c < NCB) SWF_PACK(act[IN_], 7, c, n_mid);                                                \
             _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) o[cb] = mfma(w, act[IN_][c][cb], o[cb]);  \
             __builtin_amdgcn_sched_barrier(0);                                                           \
         }                                                                                                \
@@ -306,7 +322,7 @@ mlp_bf16_kernel(Bf16Args a) {
                 if (t >= 2)
 #pragma unroll
                     for (int u = (t - 2) * NCB / 2; u < (t - 1) * NCB / 2; ++u)
-                        SWF_PACK(act[0], u / NCB, u % NCB);
+                        SWF_PACK(act[0], u / NCB, u % NCB, 0);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
@@ -382,13 +398,13 @@ void compute_mean_features_bf16(DevScene& s, hipStream_t st) {
 // workgroup, ring steps of STEP fragments, WPE waves per SIMD. The grid is
 // persistent: as many workgroups as fit on the CUs at once (registers and LDS
 // decide; launching more would only queue them).
-template <int NCB, int WAVES, int STEP, int WPE>
+template <int NCB, int WAVES, int STEP, int WPE, bool kAct = false>
 void launch_variant(Bf16Args a, int n, int B, int n_hidden, hipStream_t st) {
     constexpr int kPerBlock = 16 * NCB * WAVES;
     static const int resident = [] {  // thread-safe one-time initialisation
         int r = 0;
         const hipError_t e =
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, mlp_bf16_kernel<NCB, WAVES, STEP, WPE>, 64 * WAVES, 0);
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, mlp_bf16_kernel<NCB, WAVES, STEP, WPE, kAct>, 64 * WAVES, 0);
         return (e == hipSuccess && r > 0) ? r : 1;
     }();
     a.n_steps = 2 + (128 / STEP) * (n_hidden - 1);
@@ -396,18 +412,22 @@ void launch_variant(Bf16Args a, int n, int B, int n_hidden, hipStream_t st) {
     a.n_tiles = a.tiles_per_query * B;
     if (!a.n_tiles) return;
     const int blocks = std::min(a.n_tiles, n_compute_units() * resident);
-    mlp_bf16_kernel<NCB, WAVES, STEP, WPE><<<blocks, 64 * WAVES, 0, st>>>(a);
+    mlp_bf16_kernel<NCB, WAVES, STEP, WPE, kAct><<<blocks, 64 * WAVES, 0, st>>>(a);
 }
 
 void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
-                     float* delta_out, hipStream_t st, int pairs_per_wave) {
+                     float* delta_out, hipStream_t st, int pairs_per_wave, void* act_out) {
     Bf16Args a{};
     a.m = make_args(s, qs, B, g, paper_mask, r, delta_out);
     a.stream = reinterpret_cast<const uint4*>(s.bf_stream);
     a.mfeat = reinterpret_cast<const bf16x8*>(s.bf_mfeat);
     for (int l = 0; l + 1 < s.n_hidden && l < 7; ++l) a.bias_h[l] = s.b[l + 1];
     a.bias_o = s.b[s.n_hidden];
-    if (pairs_per_wave == 64)
+    if (act_out) {  // the default variant (every variant computes the same values)
+        a.act_out = reinterpret_cast<uint16_t*>(act_out);
+        a.act_stride = (int64_t)B * s.n * 256;
+        launch_variant<3, 8, 32, 2, true>(a, s.n, B, s.n_hidden, st);
+    } else if (pairs_per_wave == 64)
         launch_variant<4, 4, 32, 1>(a, s.n, B, s.n_hidden, st);  // 256 pairs, one wave per SIMD
     else if (pairs_per_wave == 32)
         launch_variant<2, 8, 32, 2>(a, s.n, B, s.n_hidden, st);  // 256 pairs, two waves per SIMD

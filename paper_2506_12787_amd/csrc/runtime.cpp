@@ -446,7 +446,7 @@ swf_status Ctx::enqueue_preprocess(Workspace& w, Scene* sc, const float* tx, int
         stage_begin(SWF_STAGE_MLP, st);
         if (flags & SWF_MLP_BF16)
             launch_mlp_bf16(d, (const float*)w.qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, w.rec, delta_sorted, st,
-                            mlp_pairs_per_wave);
+                            mlp_pairs_per_wave, w.act_out);
         else
             launch_mlp_fp32(d, (const float*)w.qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, w.rec, delta_sorted, st);
         stage_end(st);

@@ -57,6 +57,7 @@ struct Workspace {
     uint32_t* status_dev = nullptr;
     uint64_t* total_host = nullptr;  // pinned
     hipEvent_t total_ev = nullptr;   // the scan total has reached total_host (speculative renders)
+    void* act_out = nullptr;         // set during the backward's forward pass: BF16 hidden activations go here
     LastRender last;
     std::vector<Buf*> bufs() {
         return {&qs, &geo, &wm, &oa, &rect, &count, &off, &scan, &keys, &keys2, &vals, &vals2, &hist, &ranges, &bins,
@@ -127,7 +128,7 @@ struct Ctx {
     swf_status backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out,
                         const void* aux, const swf_grads* grads, hipStream_t st);
     swf_status mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,
-                            const swf_grads* gr, bool bf16, hipStream_t st);
+                            const swf_grads* gr, bool bf16, bool acts_ready, hipStream_t st);
     void* blas = nullptr;  // rocBLAS handle of the MLP backward (created on first use)
     void stage_begin(int stage, hipStream_t st);
     void stage_end(hipStream_t st);
