@@ -142,7 +142,9 @@ swf_status swf_scene_release(swf_ctx *ctx, int32_t scene_id);
  * NULL) must have the uploaded n; its depth array is ignored: the scene keeps
  * the (depth, id) order it was uploaded with (depth gets no gradient; upload a
  * new scene to change depths). mlp (may be NULL) must have the uploaded shape.
- * Sources are host or device (src_is_device). Waits for `stream`. */
+ * Sources are host or device (src_is_device). Host sources: the call waits
+ * for `stream`. Device sources: the copies and the rebuilt BF16 weight stream
+ * are enqueued on `stream` and the call returns without waiting. */
 swf_status swf_scene_update(swf_ctx *ctx, int32_t scene_id, const swf_gaussians *g, const swf_mlp *mlp,
                             int32_t src_is_device, void *stream);
 /* Device bytes held by a scene (its Gaussians, presort data and weights). */
@@ -167,7 +169,10 @@ swf_status swf_render(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t b
  * call that produced `aux` (flags must include SWF_KEEP_AUX there). Every
  * discrete decision is held at its forward outcome; where the 0.99 alpha clamp
  * is active the derivative through opacity and q is zero. Depth gets no
- * gradient. Recomputes the forward intermediates it needs. */
+ * gradient. Recomputes the forward intermediates it needs (after a BF16
+ * forward its forward pass also keeps the MLP's hidden activations). Enqueued
+ * on `stream`; like swf_render it waits once for the key count of the forward
+ * pass it repeats, and otherwise returns after enqueueing. */
 swf_status swf_render_backward(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags,
                                const float *grad_out, const void *aux, const swf_grads *grads, void *stream);
 

@@ -317,12 +317,9 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
         dmu = (float*)w.dmu.ptr;
     }
     // 5. base parameters: sum over the batch, original ids
-    float* outs[kOut] = {gr->mean_x, gr->mean_y, gr->log_scale_x, gr->log_scale_y, gr->rotation, gr->opacity_logit,
-                         gr->amplitude};
-    if ((s = w.ptrs.reserve(this, sizeof(outs), st))) return s;
-    if ((s = hip(hipMemcpyAsync(w.ptrs.ptr, outs, sizeof(outs), hipMemcpyHostToDevice, st), "ptrs H2D"))) return s;
-    launch_base_reduce((const float*)w.dbase.ptr, dmu, d.perm, B, d.n, (float* const*)w.ptrs.ptr, st);
-    if ((s = hip(hipStreamSynchronize(st), "backward sync"))) return s;  // `outs` lives on this stack
+    const BaseGrads outs = {{gr->mean_x, gr->mean_y, gr->log_scale_x, gr->log_scale_y, gr->rotation,
+                             gr->opacity_logit, gr->amplitude}};
+    launch_base_reduce((const float*)w.dbase.ptr, dmu, d.perm, B, d.n, outs, st);
     return hip(hipGetLastError(), "backward launch");
 }
 

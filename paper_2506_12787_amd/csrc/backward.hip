@@ -228,7 +228,7 @@ __global__ void preprocess_backward_kernel(const float* __restrict__ dpair, cons
 
 // Base-parameter gradients: sum over the batch, scatter to original ids.
 __global__ void base_reduce_kernel(const float* __restrict__ dbase, const float* __restrict__ dmu_pe,
-                                   const uint32_t* __restrict__ perm, int B, int N, float* const* __restrict__ out) {
+                                   const uint32_t* __restrict__ perm, int B, int N, BaseGrads out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     float s[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -244,7 +244,7 @@ __global__ void base_reduce_kernel(const float* __restrict__ dbase, const float*
     const uint32_t id = perm[p];
 #pragma unroll
     for (int k = 0; k < kOut; ++k)
-        if (out[k]) out[k][id] = s[k];
+        if (out.p[k]) out.p[k][id] = s[k];
 }
 
 // ---- MLP backward helpers (the GEMMs run in rocBLAS) --------------------------
@@ -578,8 +578,8 @@ void launch_preprocess_backward(const float* dpair, const Records& r, int64_t P,
 }
 
 void launch_base_reduce(const float* dbase, const float* dmu_pe, const uint32_t* perm, int B, int N,
-                        float* const* out_dev, hipStream_t st) {
-    if (N > 0) base_reduce_kernel<<<(N + 255) / 256, 256, 0, st>>>(dbase, dmu_pe, perm, B, N, out_dev);
+                        const BaseGrads& out, hipStream_t st) {
+    if (N > 0) base_reduce_kernel<<<(N + 255) / 256, 256, 0, st>>>(dbase, dmu_pe, perm, B, N, out);
 }
 
 void launch_layer1_act(const float* Pm, const float* qs, int N, int64_t P, float* act, hipStream_t st) {

@@ -54,6 +54,10 @@ void launch_permute_delta(const float* delta_sorted, const uint32_t* perm, int B
 // mlp_bf16.hip
 bool bf16_available();
 void compute_mean_features_bf16(DevScene& s, hipStream_t st);
+// pack.hip: rebuild the in-major FP32 copies and the BF16 weight stream from the
+// FP32 master weights d.w[] on the device (after a device-side MLP update)
+void launch_pack_mlp(const DevScene& d, hipStream_t st);
+
 // act_out (optional): also store the hidden activations, BF16 [n_hidden][B * N][256] (the backward's operands)
 void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
                      float* delta_out, hipStream_t st, int pairs_per_wave, void* act_out = nullptr);
@@ -95,8 +99,11 @@ void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Reco
                            hipStream_t st);
 void launch_preprocess_backward(const float* dpair, const Records& r, int64_t P, bool paper_mask, float* dbase,
                                 float* dy, hipStream_t st);
+struct BaseGrads {  // destinations of the 7 base-parameter gradients (device; NULL skips one)
+    float* p[7];
+};
 void launch_base_reduce(const float* dbase, const float* dmu_pe, const uint32_t* perm, int B, int N,
-                        float* const* out_dev, hipStream_t st);
+                        const BaseGrads& out, hipStream_t st);
 // MLP backward helpers (the GEMMs themselves run in rocBLAS)
 void launch_layer1_act(const float* Pm, const float* qs, int N, int64_t P, float* act, hipStream_t st);
 void launch_bias_relu(float* z, const float* bias, int64_t P, hipStream_t st);

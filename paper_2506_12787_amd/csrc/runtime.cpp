@@ -361,7 +361,7 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
             }
             st = put(&d.bf_stream, t.data(), t.size());
         }
-        if (!st) {
+        if (!st && alloc) {  // BF16 mean features: set up once (they depend on the means only)
             std::vector<uint16_t> z((size_t)n * 32, 0);
             st = put(&d.bf_mfeat, z.data(), z.size());
             if (!st) {
@@ -396,13 +396,37 @@ swf_status Ctx::update_scene(int id, const swf_gaussians* g, const swf_mlp* mlp,
         for (int k = 0; k < 7; ++k) tmps[k] = (float*)((char*)ws.stage.ptr + k * bytes);
         launch_gather_params(tmps, d.perm, d.n, dst, st);
         if (d.has_mlp) compute_mean_features_bf16(d, st);
-        if ((r = hip(hipStreamSynchronize(st), "update sync"))) return r;
+        // host sources: the copies read pageable memory; device sources stay stream-ordered
+        if (!dev && (r = hip(hipStreamSynchronize(st), "update sync"))) return r;
     }
     if (mlp) {
         if (!d.has_mlp) return fail(SWF_E_STATE, "scene was uploaded without an MLP");
         if (mlp->n_hidden != d.n_hidden || mlp->hidden != d.hidden) return fail(SWF_E_INVALID, "MLP shape differs");
-        if ((r = hip(hipStreamSynchronize(st), "update sync"))) return r;
-        if ((r = pack_mlp(s, mlp, dev, false))) return r;
+        for (int l = 0; l <= mlp->n_hidden; ++l)
+            if (!mlp->weight[l] || !mlp->bias[l]) return fail(SWF_E_INVALID, "null MLP weight or bias");
+        for (int k = 0; k < 3; ++k)
+            if (!(mlp->room_hi[k] > mlp->room_lo[k])) return fail(SWF_E_INVALID, "room_hi must exceed room_lo");
+        if (dev) {
+            // device sources: copy the masters and rebuild the derived layouts on `st`
+            for (int l = 0; l <= d.n_hidden; ++l) {
+                const size_t rows = l == d.n_hidden ? kOut : d.hidden, cols = l == 0 ? d.in_dim : d.hidden;
+                if ((r = hip(hipMemcpyAsync(d.w[l], mlp->weight[l], rows * cols * sizeof(float),
+                                            hipMemcpyDeviceToDevice, st), "update copy")))
+                    return r;
+                if ((r = hip(hipMemcpyAsync(d.b[l], mlp->bias[l], rows * sizeof(float), hipMemcpyDeviceToDevice, st),
+                             "update copy")))
+                    return r;
+            }
+            for (int k = 0; k < 3; ++k) {
+                d.room_lo[k] = mlp->room_lo[k];
+                d.room_hi[k] = mlp->room_hi[k];
+            }
+            launch_pack_mlp(d, st);
+            if ((r = hip(hipGetLastError(), "mlp repack"))) return r;
+        } else {
+            if ((r = hip(hipStreamSynchronize(st), "update sync"))) return r;
+            if ((r = pack_mlp(s, mlp, dev, false))) return r;
+        }
     }
     ws.last.valid = false;
     return SWF_OK;

@@ -51,7 +51,7 @@ struct LastRender {
 // Scratch memory of one render stream: every pipeline stage writes here.
 struct Workspace {
     Buf qs, geo, wm, oa, rect, count, off, scan, keys, keys2, vals, vals2, hist, ranges, bins, delta, sortk, sortv,
-        grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, ptrs, stage, work;
+        grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, stage, work;
     Records rec;
     uint64_t* total_dev = nullptr;   // device: scan total, then the status word
     uint32_t* status_dev = nullptr;
@@ -61,7 +61,7 @@ struct Workspace {
     LastRender last;
     std::vector<Buf*> bufs() {
         return {&qs, &geo, &wm, &oa, &rect, &count, &off, &scan, &keys, &keys2, &vals, &vals2, &hist, &ranges, &bins,
-                &delta, &sortk, &sortv, &grad, &dpair, &dbase, &dy, &act, &dz, &part, &fmean, &ftx, &dmu, &ptrs,
+                &delta, &sortk, &sortv, &grad, &dpair, &dbase, &dy, &act, &dz, &part, &fmean, &ftx, &dmu,
                 &stage, &work};
     }
     uint64_t generation() {

@@ -126,3 +126,27 @@ def test_bf16_render_parity_with_bf16_oracle(ctx):
         e32 = float(np.abs(out16[b] - out32[b]).max() / np.abs(out32[b]).max())
         print("BF16 render: parity vs BF16 oracle", rep, "| normwise vs FP64 oracle", e64, "vs FP32 GPU", e32)
     ctx.release_scene(sid)
+
+
+def test_device_side_mlp_update_matches_upload(ctx):
+    """An MLP update from device tensors rebuilds the BF16 weight stream and the
+    FP32 in-major copies on the device. Renders after it (BF16 and FP32 MLP) are
+    bitwise those of the same weights packed on the host at upload; a scene
+    updated to other weights and back gives the original renders again."""
+    import torch
+    from paper_2506_12787_amd import binding as B
+    g, s = Hh.problem(3000, H0, W0, seed=77)
+    Ws, bs = synth.mlp_weights(seed=78, out_scale=1.0)
+    W2, b2 = synth.mlp_weights(seed=79, out_scale=1.0)
+    tx = torch.from_numpy(synth.tx_positions(3, seed=80)).cuda()
+    ref = ctx.upload_scene(g, H0, W0, mlp=(Ws, bs))
+    want = {f: ctx.render(ref, tx, flags=f).cpu() for f in (B.MLP_BF16, B.MLP_FP32)}
+    sid = ctx.upload_scene(g, H0, W0, mlp=(W2, b2))
+    other = ctx.render(sid, tx, flags=B.MLP_BF16).cpu()
+    assert not torch.equal(other, want[B.MLP_BF16])
+    dev = lambda a: [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in a]
+    ctx.update_scene(sid, mlp=(dev(Ws), dev(bs)))
+    for f, w in want.items():
+        assert torch.equal(ctx.render(sid, tx, flags=f).cpu(), w), f
+    ctx.release_scene(sid)
+    ctx.release_scene(ref)
