@@ -353,7 +353,8 @@ def timed_renders(ctx, sid, tx_dev, flags, out, steps, warmup):
     stages = ctx.stage_times()
     ctx.stage_timing(False)
     step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
-    return max(wall, sum(step_ms) / 1e3), step_ms, {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+    return max(wall, sum(step_ms) / 1e3), step_ms, {k: v[0] / max(v[1], 1) for k, v in stages.items()
+                                                    if not k.endswith("_backward")}
 
 
 def bench_large(a):
@@ -471,6 +472,20 @@ def bench_train(a):
     step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
     el = max(wall, sum(step_ms) / 1e3)
     lv = [float(l) for l in losses]
+    # per-stage times: a few more steps with the library's stage events on (after the timed region)
+    n_inst = min(steps, 5)
+    ctx.stage_timing(True)
+    ctx.stage_times()  # reset
+    for i in range(n_inst):
+        step(warmup + i)
+    torch.cuda.synchronize()
+    stages = {k: v[0] / n_inst for k, v in ctx.stage_times().items() if v[1] > 0}
+    ctx.stage_timing(False)
+    # MLP backward FLOPs per pair: weight gradients and input gradients of the output layer (7 x 256) and of the
+    # three 256 x 256 layers, 2 FLOP per multiply-add each (layer 1's gradients are per Gaussian and per query)
+    bwd_flop = Bq * N * 2 * 2 * (7 * 256 + 3 * 256 * 256)
+    t_bwd = stages.get("mlp_backward", 0.0)
+    ach = bwd_flop / (t_bwd * 1e-3) / 1e12 if t_bwd > 0 else None
     rec = {
         "metric": "training steps/s at N=50k, batch 16, 90x360", "value": steps / el, "unit": "steps/s",
         "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
@@ -481,8 +496,14 @@ def bench_train(a):
         "spectra_per_s": steps * Bq / el,
         "loss_first": lv[0], "loss_last": lv[-1],
         "latency_us": {"step_p50": 1e3 * pct(step_ms, 50), "step_p99": 1e3 * pct(step_ms, 99)},
+        "stages_ms_per_step": stages,
+        "roofline": {"kernel": "mlp_backward (BF16 layer GEMMs with FP32 accumulation, ReLU masks, column sums)",
+                     "bound": "mfma", "achieved": ach, "peak": PEAK["bf16"], "unit": "TFLOP/s",
+                     "frac": None if ach is None else ach / PEAK["bf16"], "traffic": None,
+                     "flop_per_step": bwd_flop, "avg_ms": t_bwd},
         "note": "targets: a separately seeded ground-truth Gaussian set rendered by this library at the same TX "
-                "positions",
+                "positions; stage times from 5 more steps with stage events on (the forward stages count both the "
+                "forward render and the forward pass the backward repeats)",
     }
     ctx.close()
     print(json.dumps(rec), flush=True)
@@ -600,7 +621,7 @@ def main():
                    "n_gaussians": N, "height": H, "width": W, "batch": Bq, "mlp": a.mlp},
         "latency_us": {"batched_p50": 1e3 * pct(step_ms, 50), "batched_p99": 1e3 * pct(step_ms, 99),
                        "note": "closed-loop: every query of a batch completes with its batch"},
-        "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+        "stages_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items() if not k.endswith("_backward")},
         "roofline": roofline,
         "stage_rooflines": stage_rooflines,
         "measured_peaks": dict(pk, note="plain loops on this GPU after the timed region: BF16 MFMA chains in "

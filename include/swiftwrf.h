@@ -190,10 +190,13 @@ swf_status swf_l1_loss(swf_ctx *ctx, const float *pred, const float *target, int
  * 4 radix sort, 5 tile ranges, 6 blend. Without SWF_FULL_SORT the lists are
  * built by binning instead: stage 2 is then the per-block tile histograms and
  * their scan, stage 3 is empty and stage 4 the stable placement of the pair
- * indices (same lists as the sort).
+ * indices (same lists as the sort). swf_render_backward adds stage 7 blend
+ * backward, 8 preprocess backward and 9 MLP backward (layer GEMMs, masks,
+ * column sums, the positional-encoding chain), besides the forward stages of
+ * the forward pass it repeats.
  * n_stages is in/out (capacity/used). */
 enum { SWF_STAGE_TX = 0, SWF_STAGE_MLP, SWF_STAGE_SCAN, SWF_STAGE_EMIT, SWF_STAGE_SORT, SWF_STAGE_RANGES,
-       SWF_STAGE_BLEND, SWF_N_STAGES };
+       SWF_STAGE_BLEND, SWF_STAGE_BWD_BLEND, SWF_STAGE_BWD_PREPROCESS, SWF_STAGE_BWD_MLP, SWF_N_STAGES };
 swf_status swf_stage_timing(swf_ctx *ctx, int32_t enable);
 swf_status swf_stage_times(swf_ctx *ctx, double *ms, int64_t *launches, int32_t *n_stages);
 

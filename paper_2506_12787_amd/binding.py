@@ -23,7 +23,8 @@ FULL_SORT = 1 << 3
 TILE8 = 1 << 4
 PAPER_DEFORM = 1 << 5
 
-STAGES = ("tx_features", "mlp_preprocess", "scan", "emit_keys", "radix_sort", "tile_ranges", "blend")
+STAGES = ("tx_features", "mlp_preprocess", "scan", "emit_keys", "radix_sort", "tile_ranges", "blend",
+          "blend_backward", "preprocess_backward", "mlp_backward")
 MAX_LAYERS = 8
 PARAMS = ("mean_x", "mean_y", "log_scale_x", "log_scale_y", "rotation", "opacity_logit", "amplitude", "depth")
 

@@ -300,20 +300,27 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     if ((s = w.dpair.reserve(this, (size_t)P * 8 * sizeof(float) + 16, st))) return s;
     if ((s = w.dbase.reserve(this, (size_t)P * kOut * sizeof(float) + 16, st))) return s;
     if ((s = hip(hipMemsetAsync(w.dpair.ptr, 0, (size_t)P * 8 * sizeof(float), st), "memset dpair"))) return s;
+    stage_begin(SWF_STAGE_BWD_BLEND, st);
     launch_blend_backward((const uint2*)w.ranges.ptr, w.last.vals, w.rec, B, w.last.grid, grad_out, auxT, auxL,
                           (float*)w.dpair.ptr, st);
+    stage_end(st);
     // 3. preprocess backward -> residual-coordinate gradients
     float* dy = nullptr;
     if (want_mlp) {
         if ((s = w.dy.reserve(this, (size_t)P * kOut * sizeof(float) + 16, st))) return s;
         dy = (float*)w.dy.ptr;
     }
+    stage_begin(SWF_STAGE_BWD_PREPROCESS, st);
     launch_preprocess_backward((const float*)w.dpair.ptr, w.rec, P, (flags & SWF_PAPER_DEFORM) != 0,
                                (float*)w.dbase.ptr, dy, st);
+    stage_end(st);
     // 4. MLP backward (activations recomputed, GEMMs in rocBLAS; BF16 operands after a BF16 forward)
     float* dmu = nullptr;
     if (want_mlp) {
-        if ((s = mlp_backward(w, d, tx, B, dy, gr, bf16, acts_ready, st))) return s;
+        stage_begin(SWF_STAGE_BWD_MLP, st);
+        s = mlp_backward(w, d, tx, B, dy, gr, bf16, acts_ready, st);
+        stage_end(st);
+        if (s) return s;
         dmu = (float*)w.dmu.ptr;
     }
     // 5. base parameters: sum over the batch, original ids
