@@ -195,9 +195,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     if (bf16) {
         // BF16 result (masking after rounding equals rounding after masking); the layer-1 gradient stays FP32
         if (nh > 1) {
-            if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, kOut, dyb, kOut, wl[nh], Hd, dz[0], Hd, true), "gemm dz")))
-                return s;
-            launch_relu_mask_inplace_bf16(dz[0], act[nh - 1], P, st);
+            launch_dz_out_bf16(dyb, wl[nh], act[nh - 1], P, dz[0], st);  // K = 7: one fused pass
         } else {  // the layer-1 gradient, masked inside its sums below
             if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, kOut, dyb, kOut, wl[nh], Hd, zf, Hd), "gemm dz")))
                 return s;

@@ -442,6 +442,52 @@ __global__ void bias_relu_bf16_kernel(const float* __restrict__ z, const float* 
 }
 
 // d[p][k] = [act[p][k] > 0] ? d[p][k] : 0 in place, BF16 d and act (8 per thread)
+// Gradient of the last hidden layer's pre-activations after a BF16 forward:
+// dz[p][f] = (sum_o dy[p][o] Wo[o][f]) rounded to BF16, zero where act[p][f]
+// (the BF16 activation) is not > 0. dy [P][7], Wo [7][256], act and dz
+// [P][256], all BF16; FP32 sums (the products of BF16 values are exact). One
+// thread per pair and 8 features. A library GEMM with K = 7 followed by a
+// separate masking pass moved the same bytes twice.
+__global__ __launch_bounds__(256) void dz_out_bf16_kernel(const __bf16* __restrict__ dy, const __bf16* __restrict__ wo,
+                                                          const __bf16* __restrict__ act, int64_t P,
+                                                          __bf16* __restrict__ dz) {
+    __shared__ __attribute__((aligned(16))) float s_w[kOut][256];
+    for (int i = threadIdx.x; i < kOut * 256; i += 256) s_w[i / 256][i % 256] = (float)wo[i];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= P * 32) return;
+    const int64_t p = i >> 5;
+    const int f0 = (int)(i & 31) * 8;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) {
+        const float y = (float)dy[p * kOut + o];
+        const float4 w0 = *reinterpret_cast<const float4*>(&s_w[o][f0]);
+        const float4 w1 = *reinterpret_cast<const float4*>(&s_w[o][f0 + 4]);
+        acc[0] = fmaf(y, w0.x, acc[0]);
+        acc[1] = fmaf(y, w0.y, acc[1]);
+        acc[2] = fmaf(y, w0.z, acc[2]);
+        acc[3] = fmaf(y, w0.w, acc[3]);
+        acc[4] = fmaf(y, w1.x, acc[4]);
+        acc[5] = fmaf(y, w1.y, acc[5]);
+        acc[6] = fmaf(y, w1.z, acc[6]);
+        acc[7] = fmaf(y, w1.w, acc[7]);
+    }
+    const uint4 a = reinterpret_cast<const uint4*>(act)[i];
+    const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+    uint32_t ow[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t lo = __builtin_bit_cast(uint16_t, to_bf16(acc[2 * k]));
+        const uint32_t hi = __builtin_bit_cast(uint16_t, to_bf16(acc[2 * k + 1]));
+        const uint32_t x = aw[k];
+        const uint32_t ml = ((x & 0x8000u) == 0 && (x & 0x7fffu) != 0) ? 0x0000ffffu : 0u;
+        const uint32_t mh = ((x & 0x80000000u) == 0 && (x & 0x7fff0000u) != 0) ? 0xffff0000u : 0u;
+        ow[k] = (lo | (hi << 16)) & (ml | mh);
+    }
+    reinterpret_cast<uint4*>(dz)[i] = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+}
+
 __global__ void relu_mask_inplace_bf16_kernel(__bf16* __restrict__ d, const __bf16* __restrict__ act, int64_t n8) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n8) return;
@@ -645,6 +691,13 @@ void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStrea
     if (n8 > 0)
         relu_mask_inplace_bf16_kernel<<<(unsigned)((n8 + 255) / 256), 256, 0, st>>>((__bf16*)d, (const __bf16*)act,
                                                                                    n8);
+}
+
+void launch_dz_out_bf16(const void* dy, const void* wo, const void* act, int64_t P, void* dz, hipStream_t st) {
+    const int64_t n8 = P * 32;
+    if (n8 > 0)
+        dz_out_bf16_kernel<<<(unsigned)((n8 + 255) / 256), 256, 0, st>>>((const __bf16*)dy, (const __bf16*)wo,
+                                                                         (const __bf16*)act, P, (__bf16*)dz);
 }
 
 int layer1_sums_blocks(int N) { return (N + kSumRows - 1) / kSumRows; }

@@ -120,6 +120,8 @@ void launch_pe_chain(const float* dg, const DevScene& s, float* dmu, hipStream_t
 void launch_layer1_act_bf16(const float* Pm, const float* qs, int N, int64_t P, void* act, hipStream_t st);
 void launch_bias_relu_bf16(const float* z, const float* bias, int64_t P, void* out, hipStream_t st);
 void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStream_t st);
+// BF16 gradient of the last hidden pre-activations: (dy Wo) masked by act > 0 (dy [P][7], Wo [7][256])
+void launch_dz_out_bf16(const void* dy, const void* wo, const void* act, int64_t P, void* dz, hipStream_t st);
 // S [N][256] = sum_b of z * [act > 0] and Rpart [layer1_sums_blocks(N)][B][256] partial sums over Gaussians
 int layer1_sums_blocks(int N);
 void launch_layer1_sums(const float* z, const void* act, int B, int N, float* S, float* Rpart, hipStream_t st);
