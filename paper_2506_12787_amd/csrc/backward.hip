@@ -109,7 +109,8 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     __syncthreads();
     if (last) atomicMax(&s_max, last);
     __syncthreads();
-    const int lmax = (int)s_max;
+    // never past the tile's list, even for an aux that does not belong to these lists
+    const int lmax = (int)min(s_max, rg.y - rg.x);
     float S = 0.0f;
 
     auto entry = [&](int beg, int jj) {
