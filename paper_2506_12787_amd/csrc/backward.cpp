@@ -124,7 +124,8 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     // FP32: dz ping-pong. BF16: dz ping-pong in BF16 + one FP32 GEMM result.
     if ((s = w.dz.reserve(this, bf16 ? actb * 2 + f32b + 16 : actb * 2 + 16, st))) return s;
     // scratch: Pm / S (N x 256), R (B x 256), dg (N x 26), split-K partials, column-sum partials, BF16 weights
-    const size_t n_split = std::max((size_t)split_of(P) * Hd * Hd, (size_t)layer1_sums_blocks((int)N) * B * Hd);
+    const size_t n_split = std::max({(size_t)split_of(P) * Hd * Hd, (size_t)layer1_sums_blocks((int)N) * B * Hd,
+                                     (size_t)wgrad_out_blocks(P) * kOut * Hd});
     const size_t n_cs = std::max<size_t>({(size_t)colsum_blocks(P) * Hd, (size_t)colsum_blocks(B) * N * Hd,
                                           (size_t)colsum_blocks(N) * Hd * B, (size_t)colsum_blocks(kMaxSplit) * Hd * Hd});
     const size_t n_wb = bf16 ? ((size_t)(nh - 1) * Hd * Hd + (size_t)kOut * Hd + (size_t)P * kOut + 64) / 2 + 64 : 0;
@@ -186,10 +187,12 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     }
     // ---- output layer (7 outputs)
     if (gr->weight[nh]) {
-        const rocblas_status r =
-            bf16 ? wgrad_rm_bf16(h, kOut, Hd, P, dyb, (const uint16_t*)act[nh - 1], gr->weight[nh], part, tmp, st)
-                 : wgrad_rm(h, kOut, Hd, P, dy, (const float*)act[nh - 1], gr->weight[nh], part, tmp, st);
-        if ((s = ok(r, "dWo"))) return s;
+        if (bf16) {
+            launch_wgrad_out_bf16(dyb, act[nh - 1], P, part, tmp, gr->weight[nh], st);  // one pass over act
+        } else if ((s = ok(wgrad_rm(h, kOut, Hd, P, dy, (const float*)act[nh - 1], gr->weight[nh], part, tmp, st),
+                           "dWo"))) {
+            return s;
+        }
     }
     if (gr->bias[nh]) launch_colsum(dy, P, kOut, 1, 0, tmp, gr->bias[nh], 0, st);
     if (bf16) {
@@ -222,15 +225,12 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
                 launch_colsum((const float*)dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
         }
         if (bf16) {
-            if (l > 1) {
-                if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, Hd, dz[cur], Hd, wl[l], Hd, dz[cur ^ 1], Hd, true),
-                            "gemm dz")))
-                    return s;
-                launch_relu_mask_inplace_bf16(dz[cur ^ 1], act[l - 1], P, st);
-            } else {  // the layer-1 gradient, FP32, masked inside its sums below
-                if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, Hd, dz[cur], Hd, wl[l], Hd, zf, Hd), "gemm dz")))
-                    return s;
-            }
+            // dz W on MFMA in one pass: BF16 and masked by the previous ReLU, or FP32 for the layer-1
+            // gradient (masked inside its sums below)
+            if (l > 1)
+                launch_dz_gemm(dz[cur], wl[l], act[l - 1], P, dz[cur ^ 1], false, st);
+            else
+                launch_dz_gemm(dz[cur], wl[l], nullptr, P, zf, true, st);
         } else {
             if ((s = ok(gemm_rm(h, false, false, P, Hd, Hd, (const float*)dz[cur], Hd, d.w[l], Hd,
                                 (float*)dz[cur ^ 1], Hd),

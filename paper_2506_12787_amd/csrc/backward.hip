@@ -443,6 +443,165 @@ __global__ void bias_relu_bf16_kernel(const float* __restrict__ z, const float* 
 }
 
 // d[p][k] = [act[p][k] > 0] ? d[p][k] : 0 in place, BF16 d and act (8 per thread)
+// Input gradient of a 256 x 256 layer on BF16 MFMA (v_mfma_f32_16x16x32_bf16,
+// FP32 accumulation): out[p][i] = sum_o dz[p][o] W[o][i] for every pair p, W
+// row-major [o][i] (the layer's [out][in] weights). kF32: FP32 result (the
+// layer-1 gradient, masked later inside its sums). Otherwise the result is
+// rounded to BF16 and zeroed where act[p][i] (the BF16 activation) is not > 0,
+// the previous layer's ReLU: one pass instead of a library GEMM and a masking
+// pass. The whole W sits in LDS in MFMA A-fragment order (fragment (t, c), lane
+// 16 g + r, element j = W[32 c + 8 g + j][16 t + r]). Each wave takes groups of
+// kDzPairs pairs: their dz rows are the B operands, in registers (16 bytes per
+// lane per 32-wide k chunk), the ReLU masks a per-wave bitmap in LDS; the next
+// group's rows and activations are loaded while the current one is computed,
+// and 16 x 16 output tiles are written as they finish.
+constexpr int kDzWaves = 8;
+constexpr int kDzNcb = 2;
+constexpr int kDzPairs = 16 * kDzNcb;
+
+typedef __bf16 dz_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float dz_f32x4 __attribute__((ext_vector_type(4)));
+typedef float dz_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 dz_bf16x2 __attribute__((ext_vector_type(2)));
+
+template <bool kF32>
+__global__ __launch_bounds__(64 * kDzWaves) void dz_gemm_kernel(const __bf16* __restrict__ dz,
+                                                                const __bf16* __restrict__ W,
+                                                                const __bf16* __restrict__ act, int64_t P,
+                                                                void* __restrict__ out) {
+    __shared__ __attribute__((aligned(16))) uint4 s_a[16 * 8 * 64];  // 128 fragments of 1 KiB
+    __shared__ uint8_t s_m[kF32 ? 1 : kDzWaves][kDzPairs][32];        // ReLU mask bits, pair-major
+    const uint16_t* Wb = reinterpret_cast<const uint16_t*>(W);
+    for (int e = threadIdx.x; e < 16 * 8 * 64; e += 64 * kDzWaves) {
+        const int f = e >> 6, l = e & 63, t = f >> 3, c = f & 7, g = l >> 4, r = l & 15;
+        const uint16_t* col = Wb + (size_t)(32 * c + 8 * g) * 256 + 16 * t + r;
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = (uint32_t)col[(2 * q) * 256] | ((uint32_t)col[(2 * q + 1) * 256] << 16);
+        s_a[e] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    __syncthreads();
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63), g = lane >> 4, n = lane & 15;
+    const int64_t groups = (P + kDzPairs - 1) / kDzPairs;
+    const int64_t stride = (int64_t)gridDim.x * kDzWaves;
+    // rows (B layout: pair cb*16 + n, k = 32 c + 8 g + j) of group q; zero past P
+    auto load_rows = [&](const __bf16* src, int64_t q, dz_bf16x8 (&dst)[8][kDzNcb]) {
+#pragma unroll
+        for (int cb = 0; cb < kDzNcb; ++cb) {
+            const int64_t p = q * kDzPairs + cb * 16 + n;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                dst[c][cb] = (q < groups && p < P) ? *reinterpret_cast<const dz_bf16x8*>(src + p * 256 + 32 * c + 8 * g)
+                                                   : dz_bf16x8{};
+        }
+    };
+    // mask byte of 8 activations (bit j set where element j is > 0)
+    auto mask_byte = [](dz_bf16x8 v) {
+        const uint4 u = __builtin_bit_cast(uint4, v);
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+        uint32_t m = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            m |= (((w[k] & 0x8000u) == 0 && (w[k] & 0x7fffu) != 0) ? 1u : 0u) << (2 * k);
+            m |= (((w[k] & 0x80000000u) == 0 && (w[k] & 0x7fff0000u) != 0) ? 1u : 0u) << (2 * k + 1);
+        }
+        return (uint8_t)m;
+    };
+    auto store_masks = [&](dz_bf16x8 (&a)[8][kDzNcb]) {
+#pragma unroll
+        for (int cb = 0; cb < kDzNcb; ++cb)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s_m[kF32 ? 0 : wave][cb * 16 + n][4 * c + g] = mask_byte(a[c][cb]);
+        __builtin_amdgcn_wave_barrier();
+    };
+    int64_t grp = (int64_t)blockIdx.x * kDzWaves + wave;
+    dz_bf16x8 b[8][kDzNcb], bn[8][kDzNcb], an[8][kDzNcb];
+    load_rows(dz, grp, b);
+    if (!kF32) {
+        load_rows(act, grp, an);
+        store_masks(an);
+    }
+    for (; grp < groups; grp += stride) {
+        const int64_t p0 = grp * kDzPairs;
+        load_rows(dz, grp + stride, bn);  // the next group, while this one is computed
+        if (!kF32) load_rows(act, grp + stride, an);
+#pragma unroll 1
+        for (int t = 0; t < 16; ++t) {
+            dz_f32x4 acc[kDzNcb];
+#pragma unroll
+            for (int cb = 0; cb < kDzNcb; ++cb) acc[cb] = dz_f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const dz_bf16x8 a = __builtin_bit_cast(dz_bf16x8, s_a[(t * 8 + c) * 64 + lane]);
+#pragma unroll
+                for (int cb = 0; cb < kDzNcb; ++cb)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[c][cb], acc[cb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int cb = 0; cb < kDzNcb; ++cb) {
+                const int64_t p = p0 + cb * 16 + n;
+                if (p >= P) continue;
+                if (kF32) {
+                    *reinterpret_cast<float4*>(reinterpret_cast<float*>(out) + p * 256 + 16 * t + 4 * g) =
+                        make_float4(acc[cb][0], acc[cb][1], acc[cb][2], acc[cb][3]);
+                } else {
+                    // features 16 t + 4 g + 0..3: bits 4 (g & 1) + 0..3 of mask byte 2 t + g / 2
+                    const uint32_t nib = ((uint32_t)s_m[wave][cb * 16 + n][2 * t + (g >> 1)] >> (4 * (g & 1))) & 15u;
+                    const dz_f32x2 lo2 = {acc[cb][0], acc[cb][1]}, hi2 = {acc[cb][2], acc[cb][3]};
+                    uint32_t v0 = __builtin_bit_cast(uint32_t, __builtin_convertvector(lo2, dz_bf16x2));
+                    uint32_t v1 = __builtin_bit_cast(uint32_t, __builtin_convertvector(hi2, dz_bf16x2));
+                    v0 &= ((nib & 1u) ? 0x0000ffffu : 0u) | ((nib & 2u) ? 0xffff0000u : 0u);
+                    v1 &= ((nib & 4u) ? 0x0000ffffu : 0u) | ((nib & 8u) ? 0xffff0000u : 0u);
+                    *reinterpret_cast<uint2*>(reinterpret_cast<__bf16*>(out) + p * 256 + 16 * t + 4 * g) =
+                        make_uint2(v0, v1);
+                }
+            }
+        }
+        if (!kF32) {
+            __builtin_amdgcn_wave_barrier();  // this group's mask reads come before the next group's writes
+            store_masks(an);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+#pragma unroll
+            for (int cb = 0; cb < kDzNcb; ++cb) b[c][cb] = bn[c][cb];
+    }
+}
+
+// Output-layer weight gradient after a BF16 forward, per block of pairs:
+// part[b][o][i] = sum over the block's pairs p of dy[p][o] act[p][i] (dy [P][7]
+// and act [P][256] BF16, so every product is exact in FP32; FP32 sums). The
+// caller adds the per-block partials. A library GEMM with M = 7 ran far below
+// the bandwidth this pass needs (one read of act).
+__global__ __launch_bounds__(256) void wgrad_out_bf16_kernel(const __bf16* __restrict__ dy,
+                                                             const __bf16* __restrict__ act, int64_t P, int64_t rpb,
+                                                             float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) float s_y[256][8];
+    const int i = (int)threadIdx.x;
+    const int64_t beg = (int64_t)blockIdx.x * rpb, end = min(P, beg + rpb);
+    float acc[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t c0 = beg; c0 < end; c0 += 256) {
+        const int nb = (int)min((int64_t)256, end - c0);
+        __syncthreads();
+        for (int e = i; e < nb * kOut; e += 256) s_y[e / kOut][e % kOut] = (float)dy[c0 * kOut + e];
+        __syncthreads();
+        for (int k = 0; k < nb; ++k) {
+            const float a = (float)act[(c0 + k) * 256 + i];
+            const float4 y0 = *reinterpret_cast<const float4*>(&s_y[k][0]);
+            const float4 y1 = *reinterpret_cast<const float4*>(&s_y[k][4]);
+            acc[0] = fmaf(y0.x, a, acc[0]);
+            acc[1] = fmaf(y0.y, a, acc[1]);
+            acc[2] = fmaf(y0.z, a, acc[2]);
+            acc[3] = fmaf(y0.w, a, acc[3]);
+            acc[4] = fmaf(y1.x, a, acc[4]);
+            acc[5] = fmaf(y1.y, a, acc[5]);
+            acc[6] = fmaf(y1.z, a, acc[6]);
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) part[((size_t)blockIdx.x * kOut + o) * 256 + i] = acc[o];
+}
+
 // Gradient of the last hidden layer's pre-activations after a BF16 forward:
 // dz[p][f] = (sum_o dy[p][o] Wo[o][f]) rounded to BF16, zero where act[p][f]
 // (the BF16 activation) is not > 0. dy [P][7], Wo [7][256], act and dz
@@ -699,6 +858,29 @@ void launch_dz_out_bf16(const void* dy, const void* wo, const void* act, int64_t
     if (n8 > 0)
         dz_out_bf16_kernel<<<(unsigned)((n8 + 255) / 256), 256, 0, st>>>((const __bf16*)dy, (const __bf16*)wo,
                                                                          (const __bf16*)act, P, (__bf16*)dz);
+}
+
+void launch_dz_gemm(const void* dz, const void* W, const void* act, int64_t P, void* out, bool f32_out,
+                    hipStream_t st) {
+    if (P <= 0) return;
+    const int64_t groups = (P + kDzPairs - 1) / kDzPairs;
+    const int blocks = (int)std::min<int64_t>(n_compute_units(), (groups + kDzWaves - 1) / kDzWaves);
+    if (f32_out)
+        dz_gemm_kernel<true><<<blocks, 64 * kDzWaves, 0, st>>>((const __bf16*)dz, (const __bf16*)W, nullptr, P, out);
+    else
+        dz_gemm_kernel<false><<<blocks, 64 * kDzWaves, 0, st>>>((const __bf16*)dz, (const __bf16*)W,
+                                                                (const __bf16*)act, P, out);
+}
+
+int wgrad_out_blocks(int64_t P) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (P + 255) / 256)); }
+
+void launch_wgrad_out_bf16(const void* dy, const void* act, int64_t P, float* part, float* tmp, float* dWo,
+                           hipStream_t st) {
+    if (P <= 0) return;
+    const int nblk = wgrad_out_blocks(P);
+    const int64_t rpb = (P + nblk - 1) / nblk;
+    wgrad_out_bf16_kernel<<<nblk, 256, 0, st>>>((const __bf16*)dy, (const __bf16*)act, P, rpb, part);
+    launch_colsum(part, nblk, (int64_t)kOut * 256, 1, 0, tmp, dWo, 0, st);
 }
 
 int layer1_sums_blocks(int N) { return (N + kSumRows - 1) / kSumRows; }

@@ -120,6 +120,15 @@ void launch_pe_chain(const float* dg, const DevScene& s, float* dmu, hipStream_t
 void launch_layer1_act_bf16(const float* Pm, const float* qs, int N, int64_t P, void* act, hipStream_t st);
 void launch_bias_relu_bf16(const float* z, const float* bias, int64_t P, void* out, hipStream_t st);
 void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStream_t st);
+// Input gradient of a 256 x 256 layer on MFMA: out = dz W (dz [P][256] BF16, W [256][256] BF16 row-major
+// [out][in]); FP32 output (f32_out) or BF16 output masked by act > 0 (act [P][256] BF16)
+void launch_dz_gemm(const void* dz, const void* W, const void* act, int64_t P, void* out, bool f32_out,
+                    hipStream_t st);
+// Output-layer weight gradient dWo [7][256] = dy^T act (dy [P][7], act [P][256], BF16; FP32 sums).
+// part: wgrad_out_blocks(P) * 7 * 256 floats; tmp: column-sum scratch.
+int wgrad_out_blocks(int64_t P);
+void launch_wgrad_out_bf16(const void* dy, const void* act, int64_t P, float* part, float* tmp, float* dWo,
+                           hipStream_t st);
 // BF16 gradient of the last hidden pre-activations: (dy Wo) masked by act > 0 (dy [P][7], Wo [7][256])
 void launch_dz_out_bf16(const void* dy, const void* wo, const void* act, int64_t P, void* dz, hipStream_t st);
 // S [N][256] = sum_b of z * [act > 0] and Rpart [layer1_sums_blocks(N)][B][256] partial sums over Gaussians
