@@ -876,8 +876,7 @@ int wgrad_out_blocks(int64_t P) { return (int)std::max<int64_t>(1, std::min<int6
 
 void launch_wgrad_out_bf16(const void* dy, const void* act, int64_t P, float* part, float* tmp, float* dWo,
                            hipStream_t st) {
-    if (P <= 0) return;
-    const int nblk = wgrad_out_blocks(P);
+    const int nblk = wgrad_out_blocks(P);  // P = 0: one block writes zeros
     const int64_t rpb = (P + nblk - 1) / nblk;
     wgrad_out_bf16_kernel<<<nblk, 256, 0, st>>>((const __bf16*)dy, (const __bf16*)act, P, rpb, part);
     launch_colsum(part, nblk, (int64_t)kOut * 256, 1, 0, tmp, dWo, 0, st);
