@@ -125,6 +125,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     if ((s = w.dz.reserve(this, bf16 ? actb * 2 + f32b + 16 : actb * 2 + 16, st))) return s;
     // scratch: Pm / S (N x 256), R (B x 256), dg (N x 26), split-K partials, column-sum partials, BF16 weights
     const size_t n_split = std::max({(size_t)split_of(P) * Hd * Hd, (size_t)layer1_sums_blocks((int)N) * B * Hd,
+                                     (size_t)layer1_grad_blocks((int)N) * B * Hd,
                                      (size_t)wgrad_out_blocks(P) * kOut * Hd});
     const size_t n_cs = std::max<size_t>({(size_t)colsum_blocks(P) * Hd, (size_t)colsum_blocks(B) * N * Hd,
                                           (size_t)colsum_blocks(N) * Hd * B, (size_t)colsum_blocks(kMaxSplit) * Hd * Hd});
@@ -209,6 +210,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
         launch_relu_mask((float*)dz[0], (const float*)act[nh - 1], P, st);
     }
     int cur = 0;
+    const void* dz1 = nullptr;  // BF16: the second layer's pre-activation gradient
     for (int l = nh - 1; l >= 1; --l) {
         if (gr->weight[l]) {
             const rocblas_status r =
@@ -230,7 +232,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
             if (l > 1)
                 launch_dz_gemm(dz[cur], wl[l], act[l - 1], P, dz[cur ^ 1], false, st);
             else
-                launch_dz_gemm(dz[cur], wl[l], nullptr, P, zf, true, st);
+                dz1 = dz[cur];  // the layer-1 gradient is formed inside its sums below
         } else {
             if ((s = ok(gemm_rm(h, false, false, P, Hd, Hd, (const float*)dz[cur], Hd, d.w[l], Hd,
                                 (float*)dz[cur ^ 1], Hd),
@@ -244,9 +246,15 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     // (N x 256), R = its sum over the Gaussians per query (B x 256), b0 = its sum over all pairs
     float* S = Pm;
     if (bf16) {
-        // zf is dz0 before the ReLU mask: one pass gives S and per-block partial sums of R
-        launch_layer1_sums(zf, act[0], (int)B, (int)N, S, part, st);
-        if (gr->weight[0]) launch_colsum(part, layer1_sums_blocks((int)N), B * Hd, 1, 0, tmp, R, 0, st);
+        if (dz1) {
+            // dz0 = (dz1 W1) masked, never stored: one pass gives S and per-block partial sums of R
+            launch_layer1_grad(dz1, wl[1], act[0], (int)B, (int)N, S, part, st);
+            if (gr->weight[0]) launch_colsum(part, layer1_grad_blocks((int)N), B * Hd, 1, 0, tmp, R, 0, st);
+        } else {
+            // one hidden layer: zf is dz0 before the ReLU mask
+            launch_layer1_sums(zf, act[0], (int)B, (int)N, S, part, st);
+            if (gr->weight[0]) launch_colsum(part, layer1_sums_blocks((int)N), B * Hd, 1, 0, tmp, R, 0, st);
+        }
         if (gr->bias[0]) launch_colsum(S, N, Hd, 1, 0, tmp, gr->bias[0], 0, st);
     } else {
         const float* dz0 = (const float*)dz[cur];

@@ -568,6 +568,114 @@ __global__ __launch_bounds__(64 * kDzWaves) void dz_gemm_kernel(const __bf16* __
     }
 }
 
+// Layer-1 gradient of a BF16 backward without storing it. For the block's
+// Gaussians n0 .. n0 + kL1Rows - 1 and every query b in order: z[b][n] =
+// dz1[b][n] W (FP32 accumulation on MFMA; dz1 [B][N][256] BF16, the gradient of
+// the second layer's pre-activations; W its 256 x 256 BF16 weights, row-major
+// [out][in]), masked by act[b][n] > 0 (the layer-1 ReLU), gives S[n][:] = the sum
+// over b (complete, in order) and Rpart[block][b][:] = the sum over the block's
+// Gaussians. Pairs are the MFMA rows here (A = a wave's 16 dz1 rows, B = W
+// fragments from LDS, laid out as in dz_gemm_kernel), so a lane holds 4 pairs
+// of one feature per output tile: S accumulates in registers and the R partial
+// is a sum over those 4 and over the wave's 4 lane groups.
+constexpr int kL1Waves = 8;
+constexpr int kL1Rows = 16 * kL1Waves;
+
+__global__ __launch_bounds__(64 * kL1Waves) void layer1_grad_kernel(const __bf16* __restrict__ dz1,
+                                                                    const __bf16* __restrict__ W,
+                                                                    const __bf16* __restrict__ act, int B, int N,
+                                                                    float* __restrict__ S,
+                                                                    float* __restrict__ Rpart) {
+    __shared__ __attribute__((aligned(16))) uint4 s_a[16 * 8 * 64];
+    __shared__ uint8_t s_m[kL1Waves][16][32];  // ReLU mask bits of the wave's 16 pairs, current query
+    __shared__ float s_r[kL1Waves][256];        // per-wave R partial, current query
+    const uint16_t* Wb = reinterpret_cast<const uint16_t*>(W);
+    for (int e = threadIdx.x; e < 16 * 8 * 64; e += 64 * kL1Waves) {
+        const int f = e >> 6, l = e & 63, t = f >> 3, c = f & 7, g = l >> 4, r = l & 15;
+        const uint16_t* col = Wb + (size_t)(32 * c + 8 * g) * 256 + 16 * t + r;
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = (uint32_t)col[(2 * q) * 256] | ((uint32_t)col[(2 * q + 1) * 256] << 16);
+        s_a[e] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63), g = lane >> 4, r = lane & 15;
+    const int nw = blockIdx.x * kL1Rows + wave * 16;  // the wave's first Gaussian
+    const int na = nw + r;                            // this lane's A row
+    // dz1 or act row of this lane's A row for query b (B layout of dz_gemm: k = 32 c + 8 g + j); zero past N
+    auto load_rows = [&](const __bf16* src, int b, dz_bf16x8 (&dst)[8]) {
+        const int64_t p = (int64_t)b * N + na;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            dst[c] = (b < B && na < N) ? *reinterpret_cast<const dz_bf16x8*>(src + p * 256 + 32 * c + 8 * g)
+                                       : dz_bf16x8{};
+    };
+    auto store_masks = [&](const dz_bf16x8 (&a)[8]) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint4 u = __builtin_bit_cast(uint4, a[c]);
+            const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+            uint32_t m = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                m |= (((w[k] & 0x8000u) == 0 && (w[k] & 0x7fffu) != 0) ? 1u : 0u) << (2 * k);
+                m |= (((w[k] & 0x80000000u) == 0 && (w[k] & 0x7fff0000u) != 0) ? 1u : 0u) << (2 * k + 1);
+            }
+            s_m[wave][r][4 * c + g] = (uint8_t)m;
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+    dz_bf16x8 a_cur[8], a_nxt[8], m_nxt[8];
+    load_rows(dz1, 0, a_cur);
+    load_rows(act, 0, m_nxt);
+    store_masks(m_nxt);
+    __syncthreads();  // s_a complete
+    dz_f32x4 sacc[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) sacc[t] = dz_f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < B; ++b) {
+        load_rows(dz1, b + 1, a_nxt);  // the next query's rows while this one is computed
+        load_rows(act, b + 1, m_nxt);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            dz_f32x4 acc = dz_f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    a_cur[c], __builtin_bit_cast(dz_bf16x8, s_a[(t * 8 + c) * 64 + lane]), acc, 0, 0, 0);
+            // lane (g, r) holds pairs 4 g + jj of feature 16 t + r: mask bit r % 8 of byte 2 t + r / 8
+            float v = 0.f;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const uint32_t bit = ((uint32_t)s_m[wave][4 * g + jj][2 * t + (r >> 3)] >> (r & 7)) & 1u;
+                const float x = bit ? acc[jj] : 0.f;
+                sacc[t][jj] += x;
+                v += x;
+            }
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (g == 0) s_r[wave][16 * t + r] = v;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < 256; k += 64 * kL1Waves) {
+            float v = 0.f;
+#pragma unroll
+            for (int w = 0; w < kL1Waves; ++w) v += s_r[w][k];
+            Rpart[((size_t)blockIdx.x * B + b) * 256 + k] = v;
+        }
+        store_masks(m_nxt);  // this wave's reads of the query-b masks are complete
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a_cur[c] = a_nxt[c];
+        __syncthreads();  // s_r is rewritten for the next query
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int n = nw + 4 * g + jj;
+            if (n < N) S[(size_t)n * 256 + 16 * t + r] = sacc[t][jj];
+        }
+}
+
 // Output-layer weight gradient after a BF16 forward, per block of pairs:
 // part[b][o][i] = sum over the block's pairs p of dy[p][o] act[p][i] (dy [P][7]
 // and act [P][256] BF16, so every product is exact in FP32; FP32 sums). The
@@ -880,6 +988,15 @@ void launch_wgrad_out_bf16(const void* dy, const void* act, int64_t P, float* pa
     const int64_t rpb = (P + nblk - 1) / nblk;
     wgrad_out_bf16_kernel<<<nblk, 256, 0, st>>>((const __bf16*)dy, (const __bf16*)act, P, rpb, part);
     launch_colsum(part, nblk, (int64_t)kOut * 256, 1, 0, tmp, dWo, 0, st);
+}
+
+int layer1_grad_blocks(int N) { return (N + kL1Rows - 1) / kL1Rows; }
+
+void launch_layer1_grad(const void* dz1, const void* W, const void* act, int B, int N, float* S, float* Rpart,
+                        hipStream_t st) {
+    if (N > 0 && B > 0)
+        layer1_grad_kernel<<<layer1_grad_blocks(N), 64 * kL1Waves, 0, st>>>(
+            (const __bf16*)dz1, (const __bf16*)W, (const __bf16*)act, B, N, S, Rpart);
 }
 
 int layer1_sums_blocks(int N) { return (N + kSumRows - 1) / kSumRows; }

@@ -124,6 +124,12 @@ void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStrea
 // [out][in]); FP32 output (f32_out) or BF16 output masked by act > 0 (act [P][256] BF16)
 void launch_dz_gemm(const void* dz, const void* W, const void* act, int64_t P, void* out, bool f32_out,
                     hipStream_t st);
+// Layer-1 gradient sums of a BF16 backward straight from dz1 [B][N][256] (the second layer's pre-activation
+// gradient, BF16) and W (its 256 x 256 BF16 weights): S [N][256] = sum over b of (dz1 W) masked by act > 0, and
+// Rpart [layer1_grad_blocks(N)][B][256] per-block sums over the Gaussians.
+int layer1_grad_blocks(int N);
+void launch_layer1_grad(const void* dz1, const void* W, const void* act, int B, int N, float* S, float* Rpart,
+                        hipStream_t st);
 // Output-layer weight gradient dWo [7][256] = dy^T act (dy [P][7], act [P][256], BF16; FP32 sums).
 // part: wgrad_out_blocks(P) * 7 * 256 floats; tmp: column-sum scratch.
 int wgrad_out_blocks(int64_t P);
