@@ -121,8 +121,11 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     const size_t actb = (size_t)P * Hd * esz;
     const size_t f32b = (size_t)P * Hd * sizeof(float);
     if ((s = w.act.reserve(this, actb * nh + 16, st))) return s;
-    // FP32: dz ping-pong. BF16: dz ping-pong in BF16 + one FP32 GEMM result.
-    if ((s = w.dz.reserve(this, bf16 ? actb * 2 + f32b + 16 : actb * 2 + 16, st))) return s;
+    // FP32: dz ping-pong. BF16: dz ping-pong in BF16, plus one FP32 GEMM result where one is stored: the
+    // layer-1 gradient with a single hidden layer (else it is formed inside its sums), or the recompute's
+    // pre-activations when the forward pass did not keep the activations
+    const bool need_zf = bf16 && (nh == 1 || !acts_ready);
+    if ((s = w.dz.reserve(this, need_zf ? actb * 2 + f32b + 16 : actb * 2 + 16, st))) return s;
     // scratch: Pm / S (N x 256), R (B x 256), dg (N x 26), split-K partials, column-sum partials, BF16 weights
     const size_t n_split = std::max({(size_t)split_of(P) * Hd * Hd, (size_t)layer1_sums_blocks((int)N) * B * Hd,
                                      (size_t)layer1_grad_blocks((int)N) * B * Hd,
@@ -140,7 +143,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     void* act[8] = {};
     for (int l = 0; l < nh; ++l) act[l] = (char*)w.act.ptr + actb * l;
     void* dz[2] = {w.dz.ptr, (char*)w.dz.ptr + actb};
-    float* zf = bf16 ? (float*)((char*)w.dz.ptr + actb * 2) : nullptr;  // FP32 GEMM result (BF16 path)
+    float* zf = need_zf ? (float*)((char*)w.dz.ptr + actb * 2) : nullptr;  // FP32 layer-1 gradient (nh == 1)
     float* Pm = (float*)w.part.ptr;             // N x 256: W1m gamma(mu_hat), later S
     float* R = Pm + (size_t)N * Hd;              // B x 256
     float* dg = R + (size_t)B * Hd;              // N x 26

@@ -94,11 +94,14 @@ def test_deformable_fp32_backward_matches_fp64(ctx, out_scale):
     ctx.release_scene(sid)
 
 
-BF16_BASE_RTOL = 1e-2  # normwise, Gaussian parameters and the output layer
+# normwise, Gaussian parameters and the output layer: BF16 keeps 8 significant bits (unit roundoff
+# 2^-9 ~ 2e-3), compounded along the network and the deformed parameters; observed <= 1.6e-2 over depths 4, 2, 1
+BF16_BASE_RTOL = 2e-2
 BF16_MIN_COS = 0.99    # hidden-layer weight and bias gradients: direction (observed >= 0.996)
 
 
-def test_deformable_bf16_backward_error_reported(ctx):
+@pytest.mark.parametrize("n_hidden", [4, 2, 1])
+def test_deformable_bf16_backward_error_reported(ctx, n_hidden):
     """Backward of a BF16-MLP forward (BF16 activations, BF16 GEMM operands,
     FP32 accumulation) against the FP64 analytic gradient of the FP64 network.
     The Gaussian-parameter and output-layer gradients are bounded normwise. The
@@ -106,12 +109,14 @@ def test_deformable_bf16_backward_error_reported(ctx):
     pixel weights those sums cancel to a few percent of their terms, which
     magnifies the (correlated) BF16 perturbation of the network: they are
     reported normwise and bounded by their cosine with the reference. The same
-    gradients through the FP32 path are checked at MLP_RTOL."""
+    gradients through the FP32 path are checked at MLP_RTOL. Depths 4, 2 and 1:
+    with two or more hidden layers the layer-1 gradient is formed inside its
+    sums; with one it comes from the output layer and is stored in FP32."""
     import torch
     from paper_2506_12787_amd import binding as B
     H, W, n, nb = 90, 360, 200, 3
     g, s = Hh.problem(n, H, W, seed=72)
-    Ws, bs = synth.mlp_weights(seed=3072, out_scale=0.1)
+    Ws, bs = synth.mlp_weights(seed=3072, out_scale=0.1, n_hidden=n_hidden)
     rng = np.random.default_rng(6)
     bs = [b + rng.normal(0, 0.05, b.shape).astype(np.float32) for b in bs]
     sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
