@@ -128,7 +128,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     if ((s = w.dz.reserve(this, need_zf ? actb * 2 + f32b + 16 : actb * 2 + 16, st))) return s;
     // scratch: Pm / S (N x 256), R (B x 256), dg (N x 26), split-K partials, column-sum partials, BF16 weights
     const size_t n_split = std::max({(size_t)split_of(P) * Hd * Hd, (size_t)layer1_sums_blocks((int)N) * B * Hd,
-                                     (size_t)layer1_grad_blocks((int)N) * B * Hd,
+                                     (size_t)layer1_grad_blocks((int)N) * B * Hd, (size_t)wgrad_mfma_blocks(P) * Hd * Hd,
                                      (size_t)wgrad_out_blocks(P) * kOut * Hd});
     const size_t n_cs = std::max<size_t>({(size_t)colsum_blocks(P) * Hd, (size_t)colsum_blocks(B) * N * Hd,
                                           (size_t)colsum_blocks(N) * Hd * B, (size_t)colsum_blocks(kMaxSplit) * Hd * Hd});
@@ -216,12 +216,13 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     const void* dz1 = nullptr;  // BF16: the second layer's pre-activation gradient
     for (int l = nh - 1; l >= 1; --l) {
         if (gr->weight[l]) {
-            const rocblas_status r =
-                bf16 ? wgrad_rm_bf16(h, Hd, Hd, P, (const uint16_t*)dz[cur], (const uint16_t*)act[l - 1],
-                                     gr->weight[l], part, tmp, st)
-                     : wgrad_rm(h, Hd, Hd, P, (const float*)dz[cur], (const float*)act[l - 1], gr->weight[l], part,
-                                tmp, st);
-            if ((s = ok(r, "dW"))) return s;
+            if (bf16) {
+                launch_wgrad_mfma(dz[cur], act[l - 1], P, part, tmp, gr->weight[l], st);  // contraction over pairs
+            } else if ((s = ok(wgrad_rm(h, Hd, Hd, P, (const float*)dz[cur], (const float*)act[l - 1], gr->weight[l],
+                                        part, tmp, st),
+                               "dW"))) {
+                return s;
+            }
         }
         if (gr->bias[l]) {
             if (bf16)

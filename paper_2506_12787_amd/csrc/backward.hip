@@ -676,6 +676,86 @@ __global__ __launch_bounds__(64 * kL1Waves) void layer1_grad_kernel(const __bf16
         }
 }
 
+// Weight gradient of a 256 x 256 layer on BF16 MFMA over one slice of pairs:
+// part[blk][o][i] = sum over the slice's pairs p of dz[p][o] act[p][i] (dz, act
+// [P][256] BF16; FP32 accumulation); the caller adds the slices. The
+// contraction runs over pairs, so both operands are staged through LDS
+// transposed, feature-major, 32 pairs at a time (rows padded to 80 bytes: the
+// 16-byte fragment reads of 16 consecutive features and the 2-byte staging
+// writes of consecutive pairs fall in distinct banks). Wave w accumulates the
+// 4 x 8 output tiles o in [64 (w % 4), +64), i in [128 (w / 4), +128) in
+// registers; the next 32 pairs are loaded while the current ones are multiplied.
+constexpr int kWgWaves = 8;
+constexpr int kWgRow = 40;  // bf16 per staged feature row: 32 pairs + padding
+
+__global__ __launch_bounds__(64 * kWgWaves) void wgrad_mfma_kernel(const __bf16* __restrict__ dz,
+                                                                   const __bf16* __restrict__ act, int64_t P,
+                                                                   int64_t rpb, float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) uint16_t t_dz[256 * kWgRow];
+    __shared__ __attribute__((aligned(16))) uint16_t t_act[256 * kWgRow];
+    const int tid = (int)threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, g = lane >> 4, n = lane & 15;
+    const int o0 = 64 * (wave & 3), i0 = 128 * (wave >> 2);
+    const int64_t beg = (int64_t)blockIdx.x * rpb, end = min(P, beg + rpb);
+    // staging: thread -> pair q = tid % 32 of the chunk, 8-feature pieces c = tid / 32 and c + 16
+    const int q = tid & 31, c0 = tid >> 5;
+    uint4 rd[2], ra[2];
+    auto load = [&](int64_t p0) {
+        const int64_t p = p0 + q;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = c0 + 16 * h;
+            rd[h] = p < end ? *reinterpret_cast<const uint4*>(dz + p * 256 + 8 * c) : make_uint4(0u, 0u, 0u, 0u);
+            ra[h] = p < end ? *reinterpret_cast<const uint4*>(act + p * 256 + 8 * c) : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = c0 + 16 * h;
+            const uint32_t wd[4] = {rd[h].x, rd[h].y, rd[h].z, rd[h].w};
+            const uint32_t wa[4] = {ra[h].x, ra[h].y, ra[h].z, ra[h].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                t_dz[(8 * c + 2 * k) * kWgRow + q] = (uint16_t)(wd[k] & 0xffffu);
+                t_dz[(8 * c + 2 * k + 1) * kWgRow + q] = (uint16_t)(wd[k] >> 16);
+                t_act[(8 * c + 2 * k) * kWgRow + q] = (uint16_t)(wa[k] & 0xffffu);
+                t_act[(8 * c + 2 * k + 1) * kWgRow + q] = (uint16_t)(wa[k] >> 16);
+            }
+        }
+    };
+    dz_f32x4 acc[4][8];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = dz_f32x4{0.f, 0.f, 0.f, 0.f};
+    if (beg < end) load(beg);
+    for (int64_t p0 = beg; p0 < end; p0 += 32) {
+        __syncthreads();  // the previous chunk's fragment reads are complete
+        stage();
+        __syncthreads();
+        if (p0 + 32 < end) load(p0 + 32);
+        dz_bf16x8 fa[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)  // A(o, k = pair): 8 consecutive pairs of feature o
+            fa[a] = *reinterpret_cast<const dz_bf16x8*>(&t_dz[(o0 + 16 * a + n) * kWgRow + 8 * g]);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const dz_bf16x8 fb = *reinterpret_cast<const dz_bf16x8*>(&t_act[(i0 + 16 * b + n) * kWgRow + 8 * g]);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb, acc[a][b], 0, 0, 0);
+        }
+    }
+    // D(row 4 g + jj, col n) of tile (a, b) is dW[o0 + 16 a + 4 g + jj][i0 + 16 b + n]
+    float* out = part + (size_t)blockIdx.x * 65536;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) out[(size_t)(o0 + 16 * a + 4 * g + jj) * 256 + i0 + 16 * b + n] = acc[a][b][jj];
+}
+
 // Output-layer weight gradient after a BF16 forward, per block of pairs:
 // part[b][o][i] = sum over the block's pairs p of dy[p][o] act[p][i] (dy [P][7]
 // and act [P][256] BF16, so every product is exact in FP32; FP32 sums). The
@@ -988,6 +1068,16 @@ void launch_wgrad_out_bf16(const void* dy, const void* act, int64_t P, float* pa
     const int64_t rpb = (P + nblk - 1) / nblk;
     wgrad_out_bf16_kernel<<<nblk, 256, 0, st>>>((const __bf16*)dy, (const __bf16*)act, P, rpb, part);
     launch_colsum(part, nblk, (int64_t)kOut * 256, 1, 0, tmp, dWo, 0, st);
+}
+
+int wgrad_mfma_blocks(int64_t P) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (P + 1023) / 1024)); }
+
+void launch_wgrad_mfma(const void* dz, const void* act, int64_t P, float* part, float* tmp, float* dW,
+                       hipStream_t st) {
+    const int nblk = wgrad_mfma_blocks(P);  // P = 0: one block writes zeros
+    const int64_t rpb = ((P + nblk - 1) / nblk + 31) / 32 * 32;
+    wgrad_mfma_kernel<<<nblk, 64 * kWgWaves, 0, st>>>((const __bf16*)dz, (const __bf16*)act, P, rpb, part);
+    launch_colsum(part, nblk, 65536, 1, 0, tmp, dW, 0, st);
 }
 
 int layer1_grad_blocks(int N) { return (N + kL1Rows - 1) / kL1Rows; }
