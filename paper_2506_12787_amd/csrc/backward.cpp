@@ -128,7 +128,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     if ((s = w.dz.reserve(this, need_zf ? actb * 2 + f32b + 16 : actb * 2 + 16, st))) return s;
     // scratch: Pm / S (N x 256), R (B x 256), dg (N x 26), split-K partials, column-sum partials, BF16 weights
     const size_t n_split = std::max({(size_t)split_of(P) * Hd * Hd, (size_t)layer1_sums_blocks((int)N) * B * Hd,
-                                     (size_t)layer1_grad_blocks((int)N) * B * Hd, (size_t)wgrad_mfma_blocks(P) * Hd * Hd,
+                                     (size_t)layer1_grad_blocks((int)N) * B * Hd, (size_t)wgrad_mfma_blocks(P) * (Hd * Hd + Hd),
                                      (size_t)wgrad_out_blocks(P) * kOut * Hd});
     const size_t n_cs = std::max<size_t>({(size_t)colsum_blocks(P) * Hd, (size_t)colsum_blocks(B) * N * Hd,
                                           (size_t)colsum_blocks(N) * Hd * B, (size_t)colsum_blocks(kMaxSplit) * Hd * Hd});
@@ -217,14 +217,15 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     for (int l = nh - 1; l >= 1; --l) {
         if (gr->weight[l]) {
             if (bf16) {
-                launch_wgrad_mfma(dz[cur], act[l - 1], P, part, tmp, gr->weight[l], st);  // contraction over pairs
+                // contraction over pairs; the bias gradient (column sums of dz) rides along
+                launch_wgrad_mfma(dz[cur], act[l - 1], P, part, tmp, gr->weight[l], gr->bias[l], st);
             } else if ((s = ok(wgrad_rm(h, Hd, Hd, P, (const float*)dz[cur], (const float*)act[l - 1], gr->weight[l],
                                         part, tmp, st),
                                "dW"))) {
                 return s;
             }
         }
-        if (gr->bias[l]) {
+        if (gr->bias[l] && !(bf16 && gr->weight[l])) {
             if (bf16)
                 launch_colsum_bf16(dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
             else

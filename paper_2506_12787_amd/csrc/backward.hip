@@ -685,9 +685,13 @@ __global__ __launch_bounds__(64 * kL1Waves) void layer1_grad_kernel(const __bf16
 // writes of consecutive pairs fall in distinct banks). Wave w accumulates the
 // 4 x 8 output tiles o in [64 (w % 4), +64), i in [128 (w / 4), +128) in
 // registers; the next 32 pairs are loaded while the current ones are multiplied.
+// With kBias the layer's bias gradient (the column sums of dz) comes along: waves
+// 0..3 multiply their dz fragments by a fragment of ones as well and write
+// part[nblk * 65536 + blk * 256 + o].
 constexpr int kWgWaves = 8;
 constexpr int kWgRow = 40;  // bf16 per staged feature row: 32 pairs + padding
 
+template <bool kBias>
 __global__ __launch_bounds__(64 * kWgWaves) void wgrad_mfma_kernel(const __bf16* __restrict__ dz,
                                                                    const __bf16* __restrict__ act, int64_t P,
                                                                    int64_t rpb, float* __restrict__ part) {
@@ -724,11 +728,16 @@ __global__ __launch_bounds__(64 * kWgWaves) void wgrad_mfma_kernel(const __bf16*
             }
         }
     };
-    dz_f32x4 acc[4][8];
+    dz_f32x4 acc[4][8], accb[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
+        accb[a] = dz_f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[a][b] = dz_f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const bool bias_wave = kBias && (wave >> 2) == 0;  // waves 0..3 cover the 16 o-tiles once
+    const uint4 one4 = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);  // bf16 1.0 x 8
+    const dz_bf16x8 ones = __builtin_bit_cast(dz_bf16x8, one4);
     if (beg < end) load(beg);
     for (int64_t p0 = beg; p0 < end; p0 += 32) {
         __syncthreads();  // the previous chunk's fragment reads are complete
@@ -745,6 +754,16 @@ __global__ __launch_bounds__(64 * kWgWaves) void wgrad_mfma_kernel(const __bf16*
 #pragma unroll
             for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb, acc[a][b], 0, 0, 0);
         }
+        if (bias_wave)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) accb[a] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], ones, accb[a], 0, 0, 0);
+    }
+    if (bias_wave && n == 0) {  // every column of the ones product is the row sum
+        float* ob = part + (size_t)gridDim.x * 65536 + (size_t)blockIdx.x * 256;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) ob[o0 + 16 * a + 4 * g + jj] = accb[a][jj];
     }
     // D(row 4 g + jj, col n) of tile (a, b) is dW[o0 + 16 a + 4 g + jj][i0 + 16 b + n]
     float* out = part + (size_t)blockIdx.x * 65536;
@@ -1072,12 +1091,16 @@ void launch_wgrad_out_bf16(const void* dy, const void* act, int64_t P, float* pa
 
 int wgrad_mfma_blocks(int64_t P) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (P + 1023) / 1024)); }
 
-void launch_wgrad_mfma(const void* dz, const void* act, int64_t P, float* part, float* tmp, float* dW,
+void launch_wgrad_mfma(const void* dz, const void* act, int64_t P, float* part, float* tmp, float* dW, float* db,
                        hipStream_t st) {
     const int nblk = wgrad_mfma_blocks(P);  // P = 0: one block writes zeros
     const int64_t rpb = ((P + nblk - 1) / nblk + 31) / 32 * 32;
-    wgrad_mfma_kernel<<<nblk, 64 * kWgWaves, 0, st>>>((const __bf16*)dz, (const __bf16*)act, P, rpb, part);
+    if (db)
+        wgrad_mfma_kernel<true><<<nblk, 64 * kWgWaves, 0, st>>>((const __bf16*)dz, (const __bf16*)act, P, rpb, part);
+    else
+        wgrad_mfma_kernel<false><<<nblk, 64 * kWgWaves, 0, st>>>((const __bf16*)dz, (const __bf16*)act, P, rpb, part);
     launch_colsum(part, nblk, 65536, 1, 0, tmp, dW, 0, st);
+    if (db) launch_colsum(part + (size_t)nblk * 65536, nblk, 256, 1, 0, tmp, db, 0, st);
 }
 
 int layer1_grad_blocks(int N) { return (N + kL1Rows - 1) / kL1Rows; }

@@ -124,10 +124,11 @@ void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStrea
 // [out][in]); FP32 output (f32_out) or BF16 output masked by act > 0 (act [P][256] BF16)
 void launch_dz_gemm(const void* dz, const void* W, const void* act, int64_t P, void* out, bool f32_out,
                     hipStream_t st);
-// Weight gradient of a 256 x 256 layer on MFMA: dW [256][256] = dz^T act (dz, act [P][256] BF16; FP32 sums).
-// part: wgrad_mfma_blocks(P) * 65536 floats; tmp: column-sum scratch.
+// Weight gradient of a 256 x 256 layer on MFMA: dW [256][256] = dz^T act (dz, act [P][256] BF16; FP32 sums),
+// and, when db is not NULL, the bias gradient db [256] = the column sums of dz.
+// part: wgrad_mfma_blocks(P) * (65536 + 256) floats; tmp: column-sum scratch.
 int wgrad_mfma_blocks(int64_t P);
-void launch_wgrad_mfma(const void* dz, const void* act, int64_t P, float* part, float* tmp, float* dW,
+void launch_wgrad_mfma(const void* dz, const void* act, int64_t P, float* part, float* tmp, float* dW, float* db,
                        hipStream_t st);
 // Layer-1 gradient sums of a BF16 backward straight from dz1 [B][N][256] (the second layer's pre-activation
 // gradient, BF16) and W (its 256 x 256 BF16 weights): S [N][256] = sum over b of (dz1 W) masked by act > 0, and
