@@ -190,20 +190,19 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
         }
     }
     // ---- output layer (7 outputs)
-    if (gr->weight[nh]) {
-        if (bf16) {
-            launch_wgrad_out_bf16(dyb, act[nh - 1], P, part, tmp, gr->weight[nh], st);  // one pass over act
-        } else if ((s = ok(wgrad_rm(h, kOut, Hd, P, dy, (const float*)act[nh - 1], gr->weight[nh], part, tmp, st),
-                           "dWo"))) {
-            return s;
-        }
+    if (bf16) {
+        // one pass over the last activations: the weight gradient and, with more than one hidden layer, the
+        // masked BF16 gradient of the last hidden pre-activations (K = 7)
+        launch_out_bwd_bf16(dyb, wl[nh], act[nh - 1], P, nh > 1 ? dz[0] : nullptr, part, tmp, gr->weight[nh], st);
+    } else if (gr->weight[nh] &&
+               (s = ok(wgrad_rm(h, kOut, Hd, P, dy, (const float*)act[nh - 1], gr->weight[nh], part, tmp, st),
+                       "dWo"))) {
+        return s;
     }
     if (gr->bias[nh]) launch_colsum(dy, P, kOut, 1, 0, tmp, gr->bias[nh], 0, st);
     if (bf16) {
         // BF16 result (masking after rounding equals rounding after masking); the layer-1 gradient stays FP32
-        if (nh > 1) {
-            launch_dz_out_bf16(dyb, wl[nh], act[nh - 1], P, dz[0], st);  // K = 7: one fused pass
-        } else {  // the layer-1 gradient, masked inside its sums below
+        if (nh == 1) {  // the layer-1 gradient, masked inside its sums below
             if ((s = ok(gemm_rm_bf16(h, false, false, P, Hd, kOut, dyb, kOut, wl[nh], Hd, zf, Hd), "gemm dz")))
                 return s;
         }

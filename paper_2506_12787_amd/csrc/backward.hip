@@ -775,84 +775,88 @@ __global__ __launch_bounds__(64 * kWgWaves) void wgrad_mfma_kernel(const __bf16*
             for (int jj = 0; jj < 4; ++jj) out[(size_t)(o0 + 16 * a + 4 * g + jj) * 256 + i0 + 16 * b + n] = acc[a][b][jj];
 }
 
-// Output-layer weight gradient after a BF16 forward, per block of pairs:
-// part[b][o][i] = sum over the block's pairs p of dy[p][o] act[p][i] (dy [P][7]
-// and act [P][256] BF16, so every product is exact in FP32; FP32 sums). The
-// caller adds the per-block partials. A library GEMM with M = 7 ran far below
-// the bandwidth this pass needs (one read of act).
-__global__ __launch_bounds__(256) void wgrad_out_bf16_kernel(const __bf16* __restrict__ dy,
-                                                             const __bf16* __restrict__ act, int64_t P, int64_t rpb,
-                                                             float* __restrict__ part) {
-    __shared__ __attribute__((aligned(16))) float s_y[256][8];
-    const int i = (int)threadIdx.x;
-    const int64_t beg = (int64_t)blockIdx.x * rpb, end = min(P, beg + rpb);
-    float acc[kOut] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int64_t c0 = beg; c0 < end; c0 += 256) {
-        const int nb = (int)min((int64_t)256, end - c0);
-        __syncthreads();
-        for (int e = i; e < nb * kOut; e += 256) s_y[e / kOut][e % kOut] = (float)dy[c0 * kOut + e];
-        __syncthreads();
-        for (int k = 0; k < nb; ++k) {
-            const float a = (float)act[(c0 + k) * 256 + i];
-            const float4 y0 = *reinterpret_cast<const float4*>(&s_y[k][0]);
-            const float4 y1 = *reinterpret_cast<const float4*>(&s_y[k][4]);
-            acc[0] = fmaf(y0.x, a, acc[0]);
-            acc[1] = fmaf(y0.y, a, acc[1]);
-            acc[2] = fmaf(y0.z, a, acc[2]);
-            acc[3] = fmaf(y0.w, a, acc[3]);
-            acc[4] = fmaf(y1.x, a, acc[4]);
-            acc[5] = fmaf(y1.y, a, acc[5]);
-            acc[6] = fmaf(y1.z, a, acc[6]);
-        }
-    }
-#pragma unroll
-    for (int o = 0; o < kOut; ++o) part[((size_t)blockIdx.x * kOut + o) * 256 + i] = acc[o];
-}
-
-// Gradient of the last hidden layer's pre-activations after a BF16 forward:
-// dz[p][f] = (sum_o dy[p][o] Wo[o][f]) rounded to BF16, zero where act[p][f]
-// (the BF16 activation) is not > 0. dy [P][7], Wo [7][256], act and dz
-// [P][256], all BF16; FP32 sums (the products of BF16 values are exact). One
-// thread per pair and 8 features. A library GEMM with K = 7 followed by a
-// separate masking pass moved the same bytes twice.
-__global__ __launch_bounds__(256) void dz_out_bf16_kernel(const __bf16* __restrict__ dy, const __bf16* __restrict__ wo,
-                                                          const __bf16* __restrict__ act, int64_t P,
-                                                          __bf16* __restrict__ dz) {
+// Output layer of a BF16 backward in one pass over the last hidden activations
+// act [P][256] (BF16), per block of pairs (one slice of rpb pairs): with dy
+// [P][7] and Wo [7][256] BF16 (every product exact in FP32),
+//   dz[p][f] = BF16(sum_o dy[p][o] Wo[o][f]), zero where act[p][f] is not > 0
+//     (the gradient of the last hidden pre-activations; skipped if dz is NULL),
+//   part[blk][o][f] = sum over the slice of dy[p][o] act[p][f] (the weight
+//     gradient's partial; skipped if part is NULL; the caller adds the slices).
+// Thread: 8 features (16-byte loads and stores) of every 8th pair of the slice.
+__global__ __launch_bounds__(256) void out_bwd_bf16_kernel(const __bf16* __restrict__ dy,
+                                                           const __bf16* __restrict__ wo,
+                                                           const __bf16* __restrict__ act, int64_t P, int64_t rpb,
+                                                           __bf16* __restrict__ dz, float* __restrict__ part) {
     __shared__ __attribute__((aligned(16))) float s_w[kOut][256];
+    __shared__ float s_red[8][kOut][256 + 4];
     for (int i = threadIdx.x; i < kOut * 256; i += 256) s_w[i / 256][i % 256] = (float)wo[i];
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= P * 32) return;
-    const int64_t p = i >> 5;
-    const int f0 = (int)(i & 31) * 8;
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int f0 = (int)(threadIdx.x & 31) * 8, row = (int)(threadIdx.x >> 5);
+    const int64_t beg = (int64_t)blockIdx.x * rpb, end = min(P, beg + rpb);
+    float acc[kOut][8];
 #pragma unroll
-    for (int o = 0; o < kOut; ++o) {
-        const float y = (float)dy[p * kOut + o];
-        const float4 w0 = *reinterpret_cast<const float4*>(&s_w[o][f0]);
-        const float4 w1 = *reinterpret_cast<const float4*>(&s_w[o][f0 + 4]);
-        acc[0] = fmaf(y, w0.x, acc[0]);
-        acc[1] = fmaf(y, w0.y, acc[1]);
-        acc[2] = fmaf(y, w0.z, acc[2]);
-        acc[3] = fmaf(y, w0.w, acc[3]);
-        acc[4] = fmaf(y, w1.x, acc[4]);
-        acc[5] = fmaf(y, w1.y, acc[5]);
-        acc[6] = fmaf(y, w1.z, acc[6]);
-        acc[7] = fmaf(y, w1.w, acc[7]);
-    }
-    const uint4 a = reinterpret_cast<const uint4*>(act)[i];
-    const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
-    uint32_t ow[4];
+    for (int o = 0; o < kOut; ++o)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t lo = __builtin_bit_cast(uint16_t, to_bf16(acc[2 * k]));
-        const uint32_t hi = __builtin_bit_cast(uint16_t, to_bf16(acc[2 * k + 1]));
-        const uint32_t x = aw[k];
-        const uint32_t ml = ((x & 0x8000u) == 0 && (x & 0x7fffu) != 0) ? 0x0000ffffu : 0u;
-        const uint32_t mh = ((x & 0x80000000u) == 0 && (x & 0x7fff0000u) != 0) ? 0xffff0000u : 0u;
-        ow[k] = (lo | (hi << 16)) & (ml | mh);
+        for (int j = 0; j < 8; ++j) acc[o][j] = 0.f;
+    for (int64_t p = beg + row; p < end; p += 8) {
+        float y[kOut];
+#pragma unroll
+        for (int o = 0; o < kOut; ++o) y[o] = (float)dy[p * kOut + o];
+        const uint4 a = *reinterpret_cast<const uint4*>(act + p * 256 + f0);
+        const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+        float av[8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            av[2 * k] = __uint_as_float(aw[k] << 16);
+            av[2 * k + 1] = __uint_as_float(aw[k] & 0xffff0000u);
+        }
+        if (part) {
+#pragma unroll
+            for (int o = 0; o < kOut; ++o)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc[o][j] = fmaf(y[o], av[j], acc[o][j]);
+        }
+        if (dz) {
+            float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int o = 0; o < kOut; ++o) {
+                const float4 w0 = *reinterpret_cast<const float4*>(&s_w[o][f0]);
+                const float4 w1 = *reinterpret_cast<const float4*>(&s_w[o][f0 + 4]);
+                z[0] = fmaf(y[o], w0.x, z[0]);
+                z[1] = fmaf(y[o], w0.y, z[1]);
+                z[2] = fmaf(y[o], w0.z, z[2]);
+                z[3] = fmaf(y[o], w0.w, z[3]);
+                z[4] = fmaf(y[o], w1.x, z[4]);
+                z[5] = fmaf(y[o], w1.y, z[5]);
+                z[6] = fmaf(y[o], w1.z, z[6]);
+                z[7] = fmaf(y[o], w1.w, z[7]);
+            }
+            uint32_t ow[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t lo = __builtin_bit_cast(uint16_t, to_bf16(z[2 * k]));
+                const uint32_t hi = __builtin_bit_cast(uint16_t, to_bf16(z[2 * k + 1]));
+                const uint32_t x = aw[k];
+                const uint32_t ml = ((x & 0x8000u) == 0 && (x & 0x7fffu) != 0) ? 0x0000ffffu : 0u;
+                const uint32_t mh = ((x & 0x80000000u) == 0 && (x & 0x7fff0000u) != 0) ? 0xffff0000u : 0u;
+                ow[k] = (lo | (hi << 16)) & (ml | mh);
+            }
+            *reinterpret_cast<uint4*>(dz + p * 256 + f0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+        }
     }
-    reinterpret_cast<uint4*>(dz)[i] = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+    if (!part) return;  // block-uniform
+#pragma unroll
+    for (int o = 0; o < kOut; ++o)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s_red[row][o][f0 + j] = acc[o][j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < kOut * 256; e += 256) {
+        const int o = e / 256, f = e % 256;
+        float v = 0.f;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v += s_red[r][o][f];
+        part[(size_t)blockIdx.x * kOut * 256 + e] = v;
+    }
 }
 
 __global__ void relu_mask_inplace_bf16_kernel(__bf16* __restrict__ d, const __bf16* __restrict__ act, int64_t n8) {
@@ -1060,13 +1064,6 @@ void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStrea
                                                                                    n8);
 }
 
-void launch_dz_out_bf16(const void* dy, const void* wo, const void* act, int64_t P, void* dz, hipStream_t st) {
-    const int64_t n8 = P * 32;
-    if (n8 > 0)
-        dz_out_bf16_kernel<<<(unsigned)((n8 + 255) / 256), 256, 0, st>>>((const __bf16*)dy, (const __bf16*)wo,
-                                                                         (const __bf16*)act, P, (__bf16*)dz);
-}
-
 void launch_dz_gemm(const void* dz, const void* W, const void* act, int64_t P, void* out, bool f32_out,
                     hipStream_t st) {
     if (P <= 0) return;
@@ -1081,12 +1078,14 @@ void launch_dz_gemm(const void* dz, const void* W, const void* act, int64_t P, v
 
 int wgrad_out_blocks(int64_t P) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (P + 255) / 256)); }
 
-void launch_wgrad_out_bf16(const void* dy, const void* act, int64_t P, float* part, float* tmp, float* dWo,
-                           hipStream_t st) {
+void launch_out_bwd_bf16(const void* dy, const void* wo, const void* act, int64_t P, void* dz, float* part,
+                         float* tmp, float* dWo, hipStream_t st) {
+    if (!dz && !dWo) return;
     const int nblk = wgrad_out_blocks(P);  // P = 0: one block writes zeros
-    const int64_t rpb = (P + nblk - 1) / nblk;
-    wgrad_out_bf16_kernel<<<nblk, 256, 0, st>>>((const __bf16*)dy, (const __bf16*)act, P, rpb, part);
-    launch_colsum(part, nblk, (int64_t)kOut * 256, 1, 0, tmp, dWo, 0, st);
+    const int64_t rpb = ((P + nblk - 1) / nblk + 7) / 8 * 8;
+    out_bwd_bf16_kernel<<<nblk, 256, 0, st>>>((const __bf16*)dy, (const __bf16*)wo, (const __bf16*)act, P, rpb,
+                                              (__bf16*)dz, dWo ? part : nullptr);
+    if (dWo) launch_colsum(part, nblk, (int64_t)kOut * 256, 1, 0, tmp, dWo, 0, st);
 }
 
 int wgrad_mfma_blocks(int64_t P) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, (P + 1023) / 1024)); }

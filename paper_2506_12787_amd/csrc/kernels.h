@@ -136,13 +136,11 @@ void launch_wgrad_mfma(const void* dz, const void* act, int64_t P, float* part, 
 int layer1_grad_blocks(int N);
 void launch_layer1_grad(const void* dz1, const void* W, const void* act, int B, int N, float* S, float* Rpart,
                         hipStream_t st);
-// Output-layer weight gradient dWo [7][256] = dy^T act (dy [P][7], act [P][256], BF16; FP32 sums).
-// part: wgrad_out_blocks(P) * 7 * 256 floats; tmp: column-sum scratch.
-int wgrad_out_blocks(int64_t P);
-void launch_wgrad_out_bf16(const void* dy, const void* act, int64_t P, float* part, float* tmp, float* dWo,
-                           hipStream_t st);
-// BF16 gradient of the last hidden pre-activations: (dy Wo) masked by act > 0 (dy [P][7], Wo [7][256])
-void launch_dz_out_bf16(const void* dy, const void* wo, const void* act, int64_t P, void* dz, hipStream_t st);
+// Output layer of a BF16 backward in one pass over act [P][256]: dz (may be NULL) = (dy Wo) rounded to BF16 and
+// masked by act > 0; dWo [7][256] (may be NULL) = dy^T act. part: wgrad_out_blocks(P) * 7 * 256 floats.
+void launch_out_bwd_bf16(const void* dy, const void* wo, const void* act, int64_t P, void* dz, float* part,
+                         float* tmp, float* dWo, hipStream_t st);
+int wgrad_out_blocks(int64_t P);  // blocks (pair slices) of launch_out_bwd_bf16
 // S [N][256] = sum_b of z * [act > 0] and Rpart [layer1_sums_blocks(N)][B][256] partial sums over Gaussians
 int layer1_sums_blocks(int N);
 void launch_layer1_sums(const float* z, const void* act, int B, int N, float* S, float* Rpart, hipStream_t st);
