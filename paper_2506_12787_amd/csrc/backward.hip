@@ -788,7 +788,7 @@ __global__ __launch_bounds__(256) void out_bwd_bf16_kernel(const __bf16* __restr
                                                            const __bf16* __restrict__ act, int64_t P, int64_t rpb,
                                                            __bf16* __restrict__ dz, float* __restrict__ part) {
     __shared__ __attribute__((aligned(16))) float s_w[kOut][256];
-    __shared__ float s_red[8][kOut][256 + 4];
+    __shared__ float s_red[4][kOut][256];  // one row per wave after the in-wave pair of rows is added
     for (int i = threadIdx.x; i < kOut * 256; i += 256) s_w[i / 256][i % 256] = (float)wo[i];
     __syncthreads();
     const int f0 = (int)(threadIdx.x & 31) * 8, row = (int)(threadIdx.x >> 5);
@@ -845,17 +845,19 @@ __global__ __launch_bounds__(256) void out_bwd_bf16_kernel(const __bf16* __restr
         }
     }
     if (!part) return;  // block-uniform
+    // rows 2 w and 2 w + 1 are the two halves of wave w: add them across lanes l and l + 32
+    const int wv = (int)(threadIdx.x >> 6);
 #pragma unroll
     for (int o = 0; o < kOut; ++o)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) s_red[row][o][f0 + j] = acc[o][j];
+        for (int j = 0; j < 8; ++j) {
+            const float v = acc[o][j] + __shfl_xor(acc[o][j], 32);
+            if ((threadIdx.x & 32) == 0) s_red[wv][o][f0 + j] = v;
+        }
     __syncthreads();
     for (int e = threadIdx.x; e < kOut * 256; e += 256) {
         const int o = e / 256, f = e % 256;
-        float v = 0.f;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) v += s_red[r][o][f];
-        part[(size_t)blockIdx.x * kOut * 256 + e] = v;
+        part[(size_t)blockIdx.x * kOut * 256 + e] = s_red[0][o][f] + s_red[1][o][f] + s_red[2][o][f] + s_red[3][o][f];
     }
 }
 
