@@ -178,3 +178,52 @@ def loss_only(scene: M.Scene, mlp, txs, targets, room=M.DEFAULT_ROOM):
         sigs.append(res.sig.copy())
         signs.append(np.sign(res.C - t))
     return loss, np.concatenate(sigs), np.concatenate(signs)
+
+
+def held_state(scene: M.Scene, mlp, txs, targets, room=M.DEFAULT_ROOM):
+    """Decisions of the base point, per query: the compositor's inputs (which fix
+    every cutoff, skip, clamp and stop decision), the MLP's ReLU patterns and
+    the residual signs."""
+    H, W = scene.H, scene.W
+    pix = M.full_grid(H, W)
+    order = M.depth_order(scene.depth)
+    xm = M.posenc(M.normalize_mean(scene.mx, scene.my, H, W), M.MEAN_BANDS) if mlp is not None else None
+    st = []
+    for b in range(len(txs)):
+        masks, delta = None, None
+        if mlp is not None:
+            xs = M.posenc(M.normalize_tx(txs[b], room), M.TX_BANDS)
+            delta, pres, _ = M.mlp_forward(xm, xs, mlp)
+            masks = [p > 0 for p in pres]
+        g = M.deform(scene, delta)
+        rg = M.gaussians_for_raster(g, scene.depth)
+        res = M.composite(rg, order, pix[0], pix[1], margins=None)
+        sign = np.sign(res.C - np.asarray(targets[b], np.float64).ravel())
+        st.append(dict(rg=rg, masks=masks, sign=sign))
+    return st
+
+
+def loss_held(scene: M.Scene, mlp, txs, targets, state, room=M.DEFAULT_ROOM):
+    """The L1 loss with every discrete decision held at the base point `state`
+    (held_state): compositing decisions, ReLU patterns and residual signs, so
+    the loss is sum_p sign0_p (C_p - target_p) / (B H W). It equals the L1 loss
+    at the base point and is smooth around it; its derivative there is the
+    gradient of loss_and_grad (Sec. 4.4 l1 term, decisions held)."""
+    B = len(txs)
+    H, W = scene.H, scene.W
+    count = B * H * W
+    pix = M.full_grid(H, W)
+    order = M.depth_order(scene.depth)
+    xm = M.posenc(M.normalize_mean(scene.mx, scene.my, H, W), M.MEAN_BANDS) if mlp is not None else None
+    loss = 0.0
+    for b in range(B):
+        delta = None
+        if mlp is not None:
+            xs = M.posenc(M.normalize_tx(txs[b], room), M.TX_BANDS)
+            delta, _, _ = M.mlp_forward(xm, xs, mlp, relu_masks=state[b]["masks"])
+        g = M.deform(scene, delta)
+        rg = M.gaussians_for_raster(g, scene.depth)
+        C = M.composite_held(state[b]["rg"], rg, order, pix[0], pix[1])
+        t = np.asarray(targets[b], np.float64).ravel()
+        loss += float((state[b]["sign"] * (C - t)).sum()) / count
+    return loss

@@ -72,6 +72,8 @@ def _raster():
         lib.oracle_grad.argtypes = [ctypes.c_int64] + [P] * 11 + [ctypes.c_int64] + [P] * 5
         lib.oracle_grad.restype = None
         lib.oracle_max_leaves.restype = ctypes.c_int
+        lib.oracle_render_held.argtypes = [ctypes.c_int64] + [P] * 16 + [ctypes.c_int64] + [P] * 3
+        lib.oracle_render_held.restype = None
         _lib = lib
     return _lib
 
@@ -131,7 +133,7 @@ class MLP:
         return len(self.W)
 
 
-def mlp_forward(x_mean: np.ndarray, x_tx: np.ndarray, mlp: MLP, bf16: bool = False):
+def mlp_forward(x_mean: np.ndarray, x_tx: np.ndarray, mlp: MLP, bf16: bool = False, relu_masks=None):
     """Run F_theta on rows. x_mean: (R, 26) gamma of the canonical mean; x_tx:
     (R, 63) or (63,) gamma of the transceiver position. Returns (out, pre, act)
     where pre[l] / act[l] are the pre-activation and post-ReLU of hidden l.
@@ -139,19 +141,25 @@ def mlp_forward(x_mean: np.ndarray, x_tx: np.ndarray, mlp: MLP, bf16: bool = Fal
     bf16=True emulates the BF16 kernel's operand rounding: the mean features,
     all weight matrices acting on activations and every hidden activation are
     rounded to bfloat16 (ties to even); the transceiver part of layer 1, the
-    biases and all accumulation stay exact (float64 here)."""
+    biases and all accumulation stay exact (float64 here).
+
+    relu_masks (one boolean array per hidden layer, shaped like its
+    pre-activation) replaces each ReLU by multiplication with the given mask:
+    the network with its activation pattern held, used by finite differences
+    of the decisions-held objective."""
     d_mean = x_mean.shape[-1]
     W1 = mlp.W[0]
     W1m, W1s = W1[:, :d_mean], W1[:, d_mean:]
     rnd = bf16_round if bf16 else (lambda a: a)
     xs = np.atleast_2d(x_tx)
+    relu = (lambda p, l: np.maximum(p, 0.0)) if relu_masks is None else (lambda p, l: p * relu_masks[l])
     pre0 = rnd(x_mean) @ rnd(W1m).T + xs @ W1s.T + mlp.b[0]
-    pres, acts = [pre0], [np.maximum(pre0, 0.0)]
+    pres, acts = [pre0], [relu(pre0, 0)]
     h = acts[-1]
     for l in range(1, mlp.n_layers - 1):
         p = rnd(h) @ rnd(mlp.W[l]).T + mlp.b[l]
         pres.append(p)
-        acts.append(np.maximum(p, 0.0))
+        acts.append(relu(p, l))
         h = acts[-1]
     out = rnd(h) @ rnd(mlp.W[-1]).T + mlp.b[-1]
     return out, pres, acts
@@ -316,6 +324,23 @@ def composite(rg: dict, order: np.ndarray, pix_x: np.ndarray, pix_y: np.ndarray,
                       _ptr(nc), _ptr(last), _ptr(sig), _ptr(mono), _ptr(nflags), _ptr(leaves),
                       _ptr(nleaves), _ptr(bound), _ptr(overflow))
     return RenderResult(C, T, nc, last, sig, mono, nflags, leaves, nleaves, bound, overflow)
+
+
+def composite_held(rg0: dict, rg: dict, order: np.ndarray, pix_x: np.ndarray, pix_y: np.ndarray) -> np.ndarray:
+    """Composite with every decision taken on rg0 and every value on rg (see
+    oracle_render_held in raster.c). Returns C per listed pixel."""
+    lib = _raster()
+    n = len(rg["mx"])
+    order = np.ascontiguousarray(order, np.int64)
+    px = np.ascontiguousarray(pix_x, np.int32)
+    py = np.ascontiguousarray(pix_y, np.int32)
+    consts = np.array([ALPHA_MAX, ALPHA_MIN, T_MIN, Q_MAX], np.float64)
+    C = np.zeros(len(px))
+    a0 = [np.ascontiguousarray(rg0[k], np.float64) for k in ("mx", "my", "ixx", "ixy", "iyy", "op")]
+    a1 = [np.ascontiguousarray(rg[k], np.float64) for k in ("mx", "my", "ixx", "ixy", "iyy", "op", "amp")]
+    lib.oracle_render_held(n, *[_ptr(a) for a in a0], *[_ptr(a) for a in a1], _ptr(rg0["live"]), _ptr(order),
+                           _ptr(consts), len(px), _ptr(px), _ptr(py), _ptr(C))
+    return C
 
 
 def render_query(scene: Scene, mlp: MLP | None, tx, room=DEFAULT_ROOM, pix=None, margins=DEFAULT_MARGINS,

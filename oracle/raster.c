@@ -324,3 +324,47 @@ void oracle_grad(int64_t n, const double *mx, const double *my, const double *ix
 }
 
 int oracle_max_leaves(void) { return ORACLE_MAX_LEAVES; }
+
+/* Composite the listed pixels with every discrete decision taken from a base
+ * scene and every value from a second one (same Gaussians, same order): the
+ * 3-sigma cutoff, the alpha skip, the 0.99 clamp state and the transmittance
+ * stop are decided on the base parameters (q0, alpha0, T0 of the base walk),
+ * while the added terms amp alpha T use the value parameters, with alpha held
+ * at 0.99 wherever the base clamp was active. At equal scenes this is the
+ * primary walk of oracle_render. Around the base point it is a smooth function
+ * of the value parameters whose derivative is the decisions-held gradient of
+ * oracle_grad, so central differences can check that gradient without
+ * rejecting samples whose perturbation flips a decision somewhere. */
+void oracle_render_held(int64_t n, const double *mx0, const double *my0, const double *ixx0, const double *ixy0,
+                        const double *iyy0, const double *op0, const double *mx, const double *my,
+                        const double *ixx, const double *ixy, const double *iyy, const double *op,
+                        const double *amp, const int8_t *live, const int64_t *order, const double *consts,
+                        int64_t npix, const int32_t *pix_x, const int32_t *pix_y, double *C_out)
+{
+    const double amax = consts[0], amin = consts[1], tmin = consts[2], qmax = consts[3];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < npix; ++p) {
+        const double px = (double)pix_x[p], py = (double)pix_y[p];
+        double T0 = 1.0, T = 1.0, C = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t g = order[k];
+            if (!live[g]) continue;
+            const double ex = px - mx0[g], ey = py - my0[g];
+            const double q0 = ixx0[g] * ex * ex + 2.0 * ixy0[g] * ex * ey + iyy0[g] * ey * ey;
+            if (!(q0 <= qmax)) continue;
+            double a0 = op0[g] * exp(-0.5 * q0);
+            const int clamped = a0 > amax;
+            if (clamped) a0 = amax;
+            if (!(a0 >= amin)) continue;
+            const double Tn0 = T0 * (1.0 - a0);
+            if (Tn0 < tmin) break;
+            T0 = Tn0;
+            const double dx = px - mx[g], dy = py - my[g];
+            const double q = ixx[g] * dx * dx + 2.0 * ixy[g] * dx * dy + iyy[g] * dy * dy;
+            const double a = clamped ? amax : op[g] * exp(-0.5 * q);
+            C += amp[g] * a * T;
+            T *= 1.0 - a;
+        }
+        C_out[p] = C;
+    }
+}

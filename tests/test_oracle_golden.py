@@ -64,3 +64,58 @@ def test_posenc_by_hand(case):
     # float64: allow a few units in the last place of the argument
     arg = np.r_[np.zeros(len(p)), np.tile(np.outer(2.0 ** np.arange(c["bands"]), np.pi * p).ravel(), 2)]
     assert np.all(np.abs(g - expect) <= 4 * np.finfo(np.float64).eps * (1 + np.abs(arg)))
+
+
+def _mlp_fixture():
+    from fractions import Fraction
+    fx = Hh.golden("mlp_bf16_by_hand.json")
+    fr = lambda s: float(Fraction(s))
+    xm = np.zeros((1, 26))
+    for k, v in fx["x_mean"].items():
+        xm[0, int(k)] = fr(v)
+    xs = np.zeros(63)
+    for k, v in fx["x_tx"].items():
+        xs[int(k)] = fr(v)
+    Ws, bs = [], []
+    for lay in fx["layers"]:
+        w = np.zeros((lay["out"], lay["in"]))
+        for k, v in lay["weight"].items():
+            i, j = (int(t) for t in k.split(","))
+            w[i, j] = fr(v)
+        Ws.append(w)
+        bs.append(np.array([fr(v) for v in lay["bias"]]))
+    return fx, xm, xs, M.MLP(Ws, bs), fr
+
+
+def test_bf16_mlp_emulation_by_hand():
+    # Every rounding point of the BF16 emulation (mean features, weights,
+    # hidden activations, ties to even) and the unrounded transceiver term and
+    # biases change an expected value of the hand-derived network.
+    fx, xm, xs, mlp, fr = _mlp_fixture()
+    out, pres, _ = M.mlp_forward(xm, xs, mlp, bf16=True)
+    e = fx["expected_bf16"]
+    for l in range(2):
+        np.testing.assert_array_equal(pres[l][0], [fr(v) for v in e["pre"][l]])
+    np.testing.assert_array_equal(out[0], [fr(v) for v in e["out"]])
+    out, pres, _ = M.mlp_forward(xm, xs, mlp, bf16=False)
+    e = fx["expected_fp64"]
+    for l in range(2):
+        np.testing.assert_allclose(pres[l][0], [fr(v) for v in e["pre"][l]], rtol=2e-16, atol=0)
+    np.testing.assert_allclose(out[0], [fr(v) for v in e["out"]], rtol=2e-16, atol=0)
+
+
+def test_bf16_mlp_fixture_detects_planted_rounding_mistakes(monkeypatch):
+    # The fixture must fail an emulation that rounds ties away from zero or one
+    # that skips rounding altogether.
+    fx, xm, xs, mlp, fr = _mlp_fixture()
+    want = [fr(v) for v in fx["expected_bf16"]["pre"][0]] + [fr(v) for v in fx["expected_bf16"]["out"]]
+
+    def ties_away(x):
+        x = np.asarray(x, np.float64)
+        m, ex = np.frexp(x)
+        return np.ldexp(np.sign(m) * np.floor(np.abs(m) * 256.0 + 0.5) / 256.0, ex)
+
+    for wrong in (ties_away, lambda x: np.asarray(x, np.float64)):
+        monkeypatch.setattr(M, "bf16_round", wrong)
+        out, pres, _ = M.mlp_forward(xm, xs, mlp, bf16=True)
+        assert not np.array_equal(np.concatenate([pres[0][0], out[0]]), want)

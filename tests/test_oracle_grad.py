@@ -43,6 +43,53 @@ def _perturb(s, mlp, kind, idx, delta):
     return s2, m2
 
 
+def _samples(mlp, grads, rng):
+    """Sample pools: per Gaussian attribute, and the MLP layers interleaved so
+    that every layer (weights and a bias) is represented."""
+    gb = grads["base"]
+    pools = {}
+    for j, name in enumerate(PARAMS):
+        cand = np.nonzero(np.abs(gb[:, j]) > 1e-9)[0]
+        pools[name] = [(name, int(i), gb[i, j]) for i in rng.permutation(cand)]
+    mlp_pool = []
+    for l in range(mlp.n_layers):
+        W = grads["W"][l]
+        nz = np.argwhere(np.abs(W) > 1e-9)
+        lay = [("W", (l, int(nz[r][0]), int(nz[r][1])), W[nz[r][0], nz[r][1]]) for r in rng.permutation(len(nz))]
+        bi = int(np.argmax(np.abs(grads["b"][l])))
+        lay.insert(1, ("b", (l, bi), grads["b"][l][bi]))
+        mlp_pool.append(lay)
+    pools["mlp"] = [x for grp in zip(*[p[:40] for p in mlp_pool]) for x in grp]
+    return pools
+
+
+def test_fd_held_matches_analytic_gradient_training_config():
+    # The gradient-check configuration of the training workload: N = 200, a
+    # batch of 16 spectra at 90x360, the 4 x 256 network (output scale 0.1 so
+    # that the residuals move the Gaussians). At this size almost every eps =
+    # 1e-3 perturbation of an MLP weight flips some 3-sigma cutoff somewhere, so
+    # instead of rejecting samples the objective is the loss with every discrete
+    # decision held at the base point (compositing decisions, ReLU patterns,
+    # residual signs): a smooth function equal to the L1 loss at the base point
+    # whose derivative is the analytic gradient (decisions held, Sec. 4.4 l1
+    # term). 64 parameters: 8 of each Gaussian attribute, 8 MLP weights and
+    # biases covering every layer; none is rejected.
+    s, mlp, txs, targets = _problem(B=16, hidden=256)
+    loss, grads = G.loss_and_grad(s, mlp, txs, targets)
+    st = G.held_state(s, mlp, txs, targets)
+    assert G.loss_held(s, mlp, txs, targets, st) == pytest.approx(loss, rel=1e-13)
+    pools = _samples(mlp, grads, np.random.default_rng(321))
+    checked = 0
+    for key, pool in pools.items():
+        for kind, idx, ana in pool[:8]:
+            sp, mp = _perturb(s, mlp, kind, idx, EPS)
+            sm, mm = _perturb(s, mlp, kind, idx, -EPS)
+            fd = (G.loss_held(sp, mp, txs, targets, st) - G.loss_held(sm, mm, txs, targets, st)) / (2 * EPS)
+            assert abs(ana - fd) <= RTOL * abs(fd) + ATOL, (kind, idx, ana, fd)
+            checked += 1
+    assert checked == 64
+
+
 def test_fd_matches_analytic_gradient():
     # 64 parameters: 8 of each Gaussian attribute and 8 MLP weights/biases (at
     # least one per layer); a sample whose perturbation changes any decision or
