@@ -98,7 +98,7 @@ typedef struct {
 typedef struct {
     int32_t mean_bands;      /* L of gamma(mu_hat); 6                             */
     int32_t tx_bands;        /* L of gamma(s_hat); 10                             */
-    int32_t hidden;          /* hidden width; 256 (multiple of 32, <= 256)        */
+    int32_t hidden;          /* hidden width; must be 256                         */
     int32_t n_hidden;        /* number of hidden layers; 1..SWF_MAX_LAYERS-1      */
     const float *weight[SWF_MAX_LAYERS]; /* W_l row-major [out][in], l = 0..n_hidden */
     const float *bias[SWF_MAX_LAYERS];   /* b_l [out]                                */
@@ -164,6 +164,9 @@ swf_status swf_render(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t b
                       void *aux, void *stream);
 
 /* ---- backward (hand-written; transmittance replayed back to front) --------
+ * The gradient that training by back-propagation needs (Sec. 4.4, the loss
+ * minimised over the Gaussians and the MLP; the derivative of the Sec. 3.2
+ * blending rule with the Sec. 4.1 kernel, through the Sec. 4.2 deformation).
  * Gradient of sum(grad_out * out) with respect to the scene's base parameters
  * and MLP weights, for the same (scene, tx, batch, flags) as the swf_render
  * call that produced `aux` (flags must include SWF_KEEP_AUX there). Every
@@ -181,6 +184,33 @@ swf_status swf_render_backward(swf_ctx *ctx, int32_t scene_id, const float *tx, 
  * receives sign(pred - target) / n with sign(0) = 0. */
 swf_status swf_l1_loss(swf_ctx *ctx, const float *pred, const float *target, int64_t n, float *loss, float *grad,
                        void *stream);
+
+/* ---- device status of the last render --------------------------------------
+ * What the device saw during the last swf_render (or the forward pass of the
+ * last swf_render_backward) on this context, for the problem statement's
+ * render(gaussians, tx) -> spectrum (Sec. 3.3): Gaussians that take no part
+ * because a deformed parameter is not finite (or the covariance degenerates,
+ * or the depth is NaN) and Gaussians whose 3-sigma box misses the grid are
+ * culled, not errors; a key count over a fixed capacity is an overflow that
+ * the call recovers from by rendering again at the exact size. Counts are
+ * over (query, Gaussian) pairs. Waits for the stream of that render.
+ * SWF_E_STATE before the first render. */
+enum {
+    SWF_DEV_KEY_OVERFLOW = 1u << 0,     /* the last list build overflowed its capacity  */
+    SWF_DEV_RERENDERED = 1u << 1,       /* ... so the call rendered again, exactly sized */
+    SWF_DEV_CULLED_NONFINITE = 1u << 2, /* culled_nonfinite > 0                          */
+    SWF_DEV_CULLED_OFFGRID = 1u << 3,   /* culled_offgrid > 0                            */
+};
+typedef struct {
+    uint32_t flags;             /* SWF_DEV_* bits                                     */
+    uint32_t rerenders;         /* exact-size re-renders of the call (0 or 1)         */
+    uint64_t pairs;             /* (query, Gaussian) pairs of the render: batch * n   */
+    uint64_t culled_nonfinite;  /* pairs with a non-finite or degenerate Gaussian     */
+    uint64_t culled_offgrid;    /* pairs whose 3-sigma box misses the grid            */
+    uint64_t list_entries;      /* tile-list entries (keys) of the render             */
+    uint64_t reserved[3];
+} swf_device_status;
+swf_status swf_last_device_status(swf_ctx *ctx, swf_device_status *out);
 
 /* ---- stage timing ----------------------------------------------------------
  * When enabled, swf_render records a HIP event pair around each stage on the
@@ -241,6 +271,9 @@ swf_status swf_exclusive_scan(swf_ctx *ctx, const uint32_t *counts, uint32_t *of
                               void *stream);
 
 /* ---- serving loop (continuous batching over resident scenes) --------------
+ * The paper defines no serving interface; these calls serve the problem
+ * statement's mapping s -> F(s) (Sec. 3.3) to many concurrent requesters: each
+ * request is one render of one transmitter position of a resident scene.
  * A scheduler thread owns n_slots execution slots (own stream + workspace);
  * launches of different slots overlap on the device. Whenever a slot is free,
  * the oldest waiting request's scene is served: up to max_batch of its waiting

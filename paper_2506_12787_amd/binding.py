@@ -64,6 +64,14 @@ class _ReqStats(ctypes.Structure):
                 ("slot", ctypes.c_int32)]
 
 
+class _DevStatus(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("rerenders", ctypes.c_uint32), ("pairs", ctypes.c_uint64),
+                ("culled_nonfinite", ctypes.c_uint64), ("culled_offgrid", ctypes.c_uint64),
+                ("list_entries", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 3)]
+
+
+DEV_KEY_OVERFLOW, DEV_RERENDERED, DEV_CULLED_NONFINITE, DEV_CULLED_OFFGRID = 1, 2, 4, 8
+
 SERVE_COUNTERS = ("launches", "completed", "fallbacks", "graph_builds", "budget_shrinks", "workspace_bytes")
 PENDING = -7
 
@@ -96,6 +104,7 @@ def lib():
             "swf_debug_deform": [P, I32, P, I32, I32, P, P],
             "swf_debug_keys": [P, P, P, P, P, P, P, ctypes.c_uint64],
             "swf_debug_blend_work": [P, P, P, P],
+            "swf_last_device_status": [P, P],
             "swf_measure_peaks": [P, P, P, P],
             "swf_radix_sort": [P, P, P, I64, I32, I32, I32, P],
             "swf_exclusive_scan": [P, P, P, P, I64, P],
@@ -310,6 +319,14 @@ class Context:
         ev, st, ne = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
         self._check(self._L.swf_debug_blend_work(self._h, ctypes.byref(ev), ctypes.byref(st), ctypes.byref(ne)))
         return dict(evaluations=ev.value, staged=st.value, entries=ne.value)
+
+    def device_status(self):
+        """What the device saw during the last render: flags (DEV_* bits), exact-size re-renders, pairs, culled
+        pairs (non-finite, off the grid) and list entries. Waits for that render."""
+        st = _DevStatus()
+        self._check(self._L.swf_last_device_status(self._h, ctypes.byref(st)))
+        return dict(flags=st.flags, rerenders=st.rerenders, pairs=st.pairs, culled_nonfinite=st.culled_nonfinite,
+                    culled_offgrid=st.culled_offgrid, list_entries=st.list_entries)
 
     def measure_peaks(self):
         """On-device peaks: BF16 MFMA TFLOP/s, FP32 FMA T lane-ops/s, LDS read TB/s (plain loops)."""

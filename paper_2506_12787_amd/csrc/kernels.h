@@ -69,7 +69,7 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t* total, i
                            hipStream_t st);
 void launch_emit_keys(const Records& r, const uint32_t* offsets, const uint32_t* dbits, int B, int N,
                       const Grid& g, uint64_t capacity, bool full_keys, void* keys, uint32_t* vals,
-                      uint32_t* status, hipStream_t st);
+                      uint32_t* status, unsigned long long* cull, hipStream_t st);
 size_t radix_scratch_bytes(int64_t n);
 // Sorts (keys, vals) on bits [begin_bit, end_bit); returns 1 if the result
 // ended in the alternate buffers (kalt, valt), 0 if in (keys, vals).
@@ -87,7 +87,10 @@ void launch_effective_count(const uint64_t* total, uint64_t cap, uint64_t* n_eff
 // pair indices into per-tile lists and the tile ranges.
 bool bin_fits(int B, int N, const Grid& g);  // the segment grid fits one launch
 size_t bin_hist_entries(int B, int N, const Grid& g);
-void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hist, hipStream_t st);
+// cull (may be null): two device counters that receive the number of culled
+// pairs, non-finite / degenerate and off the grid (also launch_emit_keys)
+void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hist, unsigned long long* cull,
+                     hipStream_t st);
 void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* hist_scanned,
                         const uint64_t* n_dev, uint32_t* vals, hipStream_t st);
 void launch_bin_ranges(const uint32_t* hist_scanned, int B, int N, const Grid& g, const uint64_t* total,

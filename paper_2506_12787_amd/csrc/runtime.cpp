@@ -70,6 +70,7 @@ swf_status Workspace::init(Ctx* c) {
     if (hipMalloc(&total_dev, 64) != hipSuccess) return c->fail(SWF_E_OOM, "hipMalloc(status)");
     if (hipHostMalloc(&total_host, 64, 0) != hipSuccess) return c->fail(SWF_E_OOM, "hipHostMalloc(status)");
     status_dev = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(total_dev) + 16);
+    cull_dev = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(total_dev) + 32);
     if (hipEventCreateWithFlags(&total_ev, hipEventDisableTiming) != hipSuccess)
         return c->fail(SWF_E_DEVICE, "hipEventCreate");
     return c->hip(hipMemset(total_dev, 0, 64), "hipMemset(status)");
@@ -495,6 +496,9 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     const Grid g = make_grid(d.H, d.W, (flags & SWF_TILE8) ? 8 : 16);
     if ((uint64_t)B * g.tiles >= (1ull << 31)) return fail(SWF_E_INVALID, "batch * tiles too large");
     w.last.valid = false;
+    w.last.stream = st;
+    // the status word and the culled-pair counters start at zero for every render
+    launch_clear_u32(w.status_dev, 8, st);
     swf_status s = enqueue_preprocess(w, sc, tx, B, flags, g, nullptr, st);
     if (s) return s;
     const bool full = (flags & SWF_FULL_SORT) != 0;
@@ -514,6 +518,8 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     w.last.N = d.n;
     w.last.flags = flags;
     w.last.grid = g;
+    w.last.rerenders = 0;
+    w.last.nan_depth_pairs = (uint64_t)B * (uint64_t)(d.n - d.n_live);
     return hip(hipGetLastError(), "forward launch");
 }
 
@@ -558,7 +564,7 @@ swf_status Ctx::lists_binned(Workspace& w, const DevScene& d, int B, const Grid&
     if ((s = w.scan.reserve(this, scan_scratch_bytes(nh) + 64, st))) return s;
     uint32_t* bins = (uint32_t*)w.bins.ptr;
     stage_begin(SWF_STAGE_SCAN, st);
-    launch_bin_hist(w.rec, B, d.n, g, bins, st);
+    launch_bin_hist(w.rec, B, d.n, g, bins, w.cull_dev, st);
     launch_exclusive_scan(bins, bins, w.total_dev, nh, w.scan.ptr, st);
     stage_end(st);
     uint64_t nk;
@@ -603,7 +609,7 @@ swf_status Ctx::lists_sorted(Workspace& w, const DevScene& d, int B, const Grid&
     const int64_t n_gt = (int64_t)B * g.tiles;
     stage_begin(SWF_STAGE_EMIT, st);
     launch_emit_keys(w.rec, (const uint32_t*)w.off.ptr, d.dbits, B, d.n, g, nk, full, w.keys.ptr,
-                     (uint32_t*)w.vals.ptr, w.status_dev, st);
+                     (uint32_t*)w.vals.ptr, w.status_dev, w.cull_dev, st);
     stage_end(st);
     const int tbits = bits_for((uint64_t)n_gt);
     stage_begin(SWF_STAGE_SORT, st);
@@ -649,8 +655,9 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
         const uint64_t total = *w.total_host;
         if (total > spec_cap) {
             // did not fit: nothing was placed and the spectrum is zero; again at the exact size
-            launch_clear_u32(w.status_dev, 1, st);
-            return render(w, sid, tx, B, flags, out, aux, st, 0, false);
+            s = render(w, sid, tx, B, flags, out, aux, st, 0, false);
+            w.last.rerenders = 1;
+            return s;
         }
         w.last.n_keys = total;
     }
@@ -862,6 +869,30 @@ swf_status swf_debug_keys(swf_ctx* h, uint32_t* counts, uint32_t* offsets, uint6
         const size_t m = (size_t)L.B * L.grid.tiles;
         if ((s = c->hip(hipMemcpy(ranges, c->ws.ranges.ptr, m * 8, hipMemcpyDeviceToHost), "D2H ranges"))) return s;
     }
+    return SWF_OK;
+}
+
+swf_status swf_last_device_status(swf_ctx* h, swf_device_status* out) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    if (!out) return SWF_E_INVALID;
+    CTX_GUARD(c);
+    Workspace& w = c->ws;
+    if (!w.last.valid) return c->fail(SWF_E_STATE, "no render on this context yet");
+    swf_status s;
+    if ((s = c->hip(hipStreamSynchronize(w.last.stream), "stream sync"))) return s;
+    uint32_t word = 0;
+    unsigned long long cull[2] = {0, 0};
+    if ((s = c->hip(hipMemcpy(&word, w.status_dev, sizeof(word), hipMemcpyDeviceToHost), "status D2H"))) return s;
+    if ((s = c->hip(hipMemcpy(cull, w.cull_dev, sizeof(cull), hipMemcpyDeviceToHost), "status D2H"))) return s;
+    std::memset(out, 0, sizeof(*out));
+    out->flags = (word & 1u ? SWF_DEV_KEY_OVERFLOW : 0u) | (w.last.rerenders ? SWF_DEV_RERENDERED : 0u);
+    out->rerenders = w.last.rerenders;
+    out->pairs = (uint64_t)w.last.B * (uint64_t)w.last.N;
+    out->culled_nonfinite = cull[0] + w.last.nan_depth_pairs;
+    out->culled_offgrid = cull[1];
+    out->list_entries = w.last.n_keys;
+    if (out->culled_nonfinite) out->flags |= SWF_DEV_CULLED_NONFINITE;
+    if (out->culled_offgrid) out->flags |= SWF_DEV_CULLED_OFFGRID;
     return SWF_OK;
 }
 

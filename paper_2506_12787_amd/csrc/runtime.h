@@ -46,6 +46,9 @@ struct LastRender {
     bool binned = false;    // lists built by the binning path (no key array)
     void* keys = nullptr;
     uint32_t* vals = nullptr;
+    hipStream_t stream = nullptr;  // stream of the last render (status reads wait for it)
+    uint32_t rerenders = 0;        // exact-size re-renders after a speculative key overflow
+    uint64_t nan_depth_pairs = 0;  // pairs of Gaussians with a NaN depth (never preprocessed)
 };
 
 // Scratch memory of one render stream: every pipeline stage writes here.
@@ -53,8 +56,9 @@ struct Workspace {
     Buf qs, geo, wm, oa, rect, count, off, scan, keys, keys2, vals, vals2, hist, ranges, bins, delta, sortk, sortv,
         grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, stage, work;
     Records rec;
-    uint64_t* total_dev = nullptr;   // device: scan total, then the status word
-    uint32_t* status_dev = nullptr;
+    uint64_t* total_dev = nullptr;           // device status block: scan total, effective count, then:
+    uint32_t* status_dev = nullptr;          //   status word (bit 0: key overflow at a fixed capacity)
+    unsigned long long* cull_dev = nullptr;  //   culled pairs: [0] non-finite/degenerate, [1] off the grid
     uint64_t* total_host = nullptr;  // pinned
     hipEvent_t total_ev = nullptr;   // the scan total has reached total_host (speculative renders)
     void* act_out = nullptr;         // set during the backward's forward pass: BF16 hidden activations go here

@@ -115,6 +115,18 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* __r
     }
 }
 
+// Culled pairs of a wave by reason (the reason a record with no tiles keeps in
+// rect.y; 0 for pairs that are not culled): one atomic per reason and wave into
+// cull[0] (non-finite or degenerate) and cull[1] (off the grid). Every lane of
+// the wave must call it. cull may be null.
+__device__ __forceinline__ void tally_culled(uint32_t why, unsigned long long* cull) {
+    const uint64_t nf = __ballot(why == kCullNonFinite), og = __ballot(why == kCullOffGrid);
+    if (cull && lane_id() == 0) {
+        if (nf) atomicAdd(&cull[0], (unsigned long long)__popcll(nf));
+        if (og) atomicAdd(&cull[1], (unsigned long long)__popcll(og));
+    }
+}
+
 // ---- key emission -----------------------------------------------------------
 // One thread per pair: one key per tile of the pair's rectangle, row-major.
 // key = global tile (query * tiles + ty * TW + tx), or with full keys
@@ -126,11 +138,13 @@ __global__ __launch_bounds__(kThreads) void emit_keys_kernel(const uint2* __rest
                                                              const uint32_t* __restrict__ dbits, int N, int64_t total,
                                                              int TW, int tiles, uint64_t capacity,
                                                              void* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                             uint32_t* __restrict__ status) {
+                                                             uint32_t* __restrict__ status,
+                                                             unsigned long long* __restrict__ cull) {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= total) return;
-    const uint32_t c = count[i];
-    if (c == 0) return;
+    const bool in = i < total;
+    const uint32_t c = in ? count[i] : 0u;
+    tally_culled(in && c == 0 ? rect[i].y : 0u, cull);
+    if (!in || c == 0) return;
     const uint64_t off = offsets[i];
     if (off + c > capacity) {
         atomicOr(status, 1u);
@@ -353,22 +367,34 @@ __device__ __forceinline__ uint32_t seg_count(uint2 r, int TW, int t0, int seg) 
 // the counts are kept per wave (less atomic contention).
 __global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restrict__ rect,
                                                             const uint32_t* __restrict__ count, BinGeom G,
-                                                            uint32_t* __restrict__ hist) {
+                                                            uint32_t* __restrict__ hist,
+                                                            unsigned long long* __restrict__ cull) {
     __shared__ uint32_t h[kMaxTiles + 1024];  // S segments of 2^db tiles: at most kMaxTiles + 2^db - 1
+    __shared__ uint32_t nculled[2];
     const int kSegTiles = 1 << G.db;
     const bool one = G.S == 1;
     const int n = one ? kWaves * kSegTiles : G.S * kSegTiles;
     for (int i = threadIdx.x; i < n; i += kThreads) h[i] = 0;
+    if (threadIdx.x < 2) nculled[threadIdx.x] = 0;
     __syncthreads();
     uint32_t* hw = one ? h + (threadIdx.x >> 6) * kSegTiles : h;
     const int j = blockIdx.x, q = blockIdx.y;
     const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, G.N);
     const size_t row0 = (size_t)q * G.N;
+    uint32_t nf = 0, og = 0;  // culled pairs seen by this thread, by reason
     for (int p = p_beg + (int)threadIdx.x; p < p_end; p += kThreads) {
-        if (count[row0 + p] == 0) continue;
-        for_seg_tiles(rect[row0 + p], G.TW, 0, G.tiles, [&](uint32_t, uint32_t t) { atomicAdd(&hw[t], 1u); });
+        const uint2 r = rect[row0 + p];
+        if (count[row0 + p] == 0) {
+            nf += r.y == kCullNonFinite;
+            og += r.y == kCullOffGrid;
+            continue;
+        }
+        for_seg_tiles(r, G.TW, 0, G.tiles, [&](uint32_t, uint32_t t) { atomicAdd(&hw[t], 1u); });
     }
+    if (nf) atomicAdd(&nculled[0], nf);
+    if (og) atomicAdd(&nculled[1], og);
     __syncthreads();
+    if (cull && threadIdx.x < 2 && nculled[threadIdx.x]) atomicAdd(&cull[threadIdx.x], (unsigned long long)nculled[threadIdx.x]);
     for (int i = threadIdx.x; i < G.S * kSegTiles; i += kThreads) {
         uint32_t v = h[i];
         if (one)
@@ -673,16 +699,16 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t* total, i
 
 void launch_emit_keys(const Records& r, const uint32_t* offsets, const uint32_t* dbits, int B, int N, const Grid& g,
                       uint64_t capacity, bool full_keys, void* keys, uint32_t* vals, uint32_t* status,
-                      hipStream_t st) {
+                      unsigned long long* cull, hipStream_t st) {
     const int64_t total = (int64_t)B * N;
     if (total <= 0) return;
     const unsigned blocks = (unsigned)((total + kThreads - 1) / kThreads);
     if (full_keys)
         emit_keys_kernel<true><<<blocks, kThreads, 0, st>>>(r.rect, r.count, offsets, dbits, N, total, g.TW, g.tiles,
-                                                            capacity, keys, vals, status);
+                                                            capacity, keys, vals, status, cull);
     else
         emit_keys_kernel<false><<<blocks, kThreads, 0, st>>>(r.rect, r.count, offsets, dbits, N, total, g.TW,
-                                                             g.tiles, capacity, keys, vals, status);
+                                                             g.tiles, capacity, keys, vals, status, cull);
 }
 
 size_t radix_scratch_bytes(int64_t n) { return sizeof(uint32_t) * 256 * ((size_t)radix_grid(n) + 1); }
@@ -745,14 +771,15 @@ size_t bin_hist_entries(int B, int N, const Grid& g) {
     return ((size_t)B * G.S << G.db) * (size_t)G.nbq;
 }
 
-void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hist, hipStream_t st) {
+void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hist, unsigned long long* cull,
+                     hipStream_t st) {
     if (B <= 0) return;
     const BinGeom G = bin_geom(N, g);
     if (N <= 0) {
         launch_clear_u32(hist, (int)bin_hist_entries(B, N, g), st);
         return;
     }
-    bin_hist_kernel<<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist);
+    bin_hist_kernel<<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist, cull);
 }
 
 void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* hist_scanned,

@@ -21,6 +21,11 @@ constexpr int kMeanFeat = 2 * (2 * kMeanBands + 1);  // 26
 constexpr int kTxFeat = 3 * (2 * kTxBands + 1);      // 63
 constexpr int kOut = 7;
 
+// Reason a pair was culled, kept in rect_y of a record whose count is 0 (0: a
+// padding pair of a Gaussian with a NaN depth, never preprocessed).
+constexpr uint32_t kCullNonFinite = 1;  // a non-finite deformed parameter or a degenerate covariance
+constexpr uint32_t kCullOffGrid = 2;    // the 3-sigma box misses the pixel grid
+
 // Per (query, Gaussian) pair record, three arrays of vectors:
 //   geo  float4 (mx_hi, my_hi, mx_lo, my_lo): deformed mean as an unevaluated
 //        sum hi + lo (exact value of mu0 + d_mu), so that tile-relative offsets
@@ -68,12 +73,14 @@ __device__ __forceinline__ PairOut preprocess_pair(float mx0, float my0, float d
     r.wm = make_float4(c * isx, s * isx, -s * isy, c * isy);
     r.oa = make_float2(op, amp);
     const float x0 = mxh - hx, x1 = mxh + hx, y0 = myh - hy, y1 = myh + hy;
-    const bool ok = finitef(x0) && finitef(x1) && finitef(y0) && finitef(y1) && finitef(r.wm.x) &&
-                    finitef(r.wm.y) && finitef(r.wm.z) && finitef(r.wm.w) && finitef(op) && finitef(amp) &&
-                    finitef(mxl) && finitef(myl) && !(x1 < 0.0f) && !(x0 > (float)(W - 1)) && !(y1 < 0.0f) &&
-                    !(y0 > (float)(H - 1));
-    if (!ok) {
-        r.rect_x = r.rect_y = 0;
+    const bool fin = finitef(x0) && finitef(x1) && finitef(y0) && finitef(y1) && finitef(r.wm.x) &&
+                     finitef(r.wm.y) && finitef(r.wm.z) && finitef(r.wm.w) && finitef(op) && finitef(amp) &&
+                     finitef(mxl) && finitef(myl);
+    const bool on = !(x1 < 0.0f) && !(x0 > (float)(W - 1)) && !(y1 < 0.0f) && !(y0 > (float)(H - 1));
+    if (!(fin && on)) {
+        // culled: no tiles; rect_y keeps the reason for the status counters
+        r.rect_x = 0;
+        r.rect_y = fin ? kCullOffGrid : kCullNonFinite;
         r.count = 0;
         return r;
     }
