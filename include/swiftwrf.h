@@ -175,7 +175,11 @@ swf_status swf_render(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t b
  * gradient. Recomputes the forward intermediates it needs (after a BF16
  * forward its forward pass also keeps the MLP's hidden activations). Enqueued
  * on `stream`; like swf_render it waits once for the key count of the forward
- * pass it repeats, and otherwise returns after enqueueing. */
+ * pass it repeats, and otherwise returns after enqueueing. aux must be the
+ * buffer such a render on this context filled (the context remembers the last
+ * 1024): SWF_E_STATE if it is unknown or the scene's parameters were updated
+ * (swf_scene_update) since, SWF_E_INVALID if scene, batch or flags (other
+ * than SWF_KEEP_AUX) differ from that render's. */
 swf_status swf_render_backward(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags,
                                const float *grad_out, const void *aux, const swf_grads *grads, void *stream);
 
@@ -244,6 +248,12 @@ swf_status swf_debug_deform(swf_ctx *ctx, int32_t scene_id, const float *tx, int
                             float *delta, void *stream);
 swf_status swf_debug_keys(swf_ctx *ctx, uint32_t *counts, uint32_t *offsets, uint64_t *keys, uint64_t *values,
                           uint32_t *ranges, uint64_t *n_keys, uint64_t capacity);
+/* swf_debug_rects: after a render on this context, copies to the HOST buffer
+ * rects [batch*n][4] (int32, pairs in (query, original Gaussian id) order) the
+ * tile rectangle of every pair as the device computed it (Sec. 4.1 tile
+ * partitioning): tx0, ty0, tx1, ty1 (inclusive tile indices), or four -1 for a
+ * culled pair. capacity = number of pairs rects holds. Synchronous. */
+swf_status swf_debug_rects(swf_ctx *ctx, int32_t *rects, uint64_t capacity);
 /* swf_debug_blend_work: the work of the last swf_render's blend stage (Sec. 3.2
  * front-to-back rule), for roofline accounting: re-walks the same tile lists
  * without writing a spectrum and returns, in host memory, the number of (pixel,

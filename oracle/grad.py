@@ -22,9 +22,11 @@ def _pixel_weights(C, target, count):
     return np.sign(C - target) / float(count)
 
 
-def raster_grad(rg: dict, order, pix, w, flags_out=None):
+def raster_grad(rg: dict, order, pix, w, flags_out=None, abs_out=None):
     """d(sum_p w_p C_p) / d(mx, my, ixx, ixy, iyy, opacity, amp) per Gaussian.
-    flags_out (int8 array of n), if given, receives the near-threshold marks."""
+    flags_out (int8 array of n), if given, receives the near-threshold marks;
+    abs_out ((n, 7) float64), if given, the magnitude sums of the terms (the
+    scale of a componentwise rounding-error bound, see raster.c)."""
     lib = M._raster()
     n = len(rg["mx"])
     grad = np.zeros((n, 7))
@@ -37,7 +39,7 @@ def raster_grad(rg: dict, order, pix, w, flags_out=None):
     marg = np.array(M.DEFAULT_MARGINS, np.float64)
     lib.oracle_grad(n, P(rg["mx"]), P(rg["my"]), P(rg["ixx"]), P(rg["ixy"]), P(rg["iyy"]), P(rg["op"]),
                     P(rg["amp"]), P(rg["live"]), P(order), P(consts), P(marg), len(px), P(px), P(py), P(w), P(grad),
-                    None if flags_out is None else P(flags_out))
+                    None if flags_out is None else P(flags_out), None if abs_out is None else P(abs_out))
     return grad
 
 
@@ -72,25 +74,50 @@ def chain_to_params(g: dict, rg: dict, graster: np.ndarray) -> np.ndarray:
     return out
 
 
-def mlp_backward(x_mean, x_tx, mlp: M.MLP, dout):
+def mlp_backward(x_mean, x_tx, mlp: M.MLP, dout, bf16=False, dabs=None):
     """Backward of F_theta for rows sharing one TX feature vector. Returns
-    (dW list, db list, d x_mean)."""
-    out, pres, acts = M.mlp_forward(x_mean, x_tx, mlp)
+    (dW list, db list, d x_mean).
+
+    bf16=True differentiates the BF16-rounding network of mlp_forward(bf16=True)
+    with its rounded operands (weights, mean features, hidden activations) as
+    the operands of every product, arithmetic exact; a rounding has derivative
+    one (its operand is treated as the value the forward used).
+
+    dabs (magnitudes >= |dout|, same shape), if given, also runs the same chain
+    on absolute values, D_L = dabs, D_l = mask_l * (D_{l+1} |W_{l+1}|), and
+    returns as a fourth item (A_W, A_b, D_xm): A_W[l] = sum over rows of
+    D_l^T |a_{l-1}|, A_b[l] = sum of D_l, D_xm = D_1 |W1m|: the scales of
+    componentwise bounds on rounding errors made along the chain."""
+    out, pres, acts = M.mlp_forward(x_mean, x_tx, mlp, bf16=bf16)
+    rnd = M.bf16_round if bf16 else (lambda a: a)
     L = mlp.n_layers
     dW = [None] * L
     db = [None] * L
-    d = dout
+    AW, Ab = [None] * L, [None] * L
+    d, D = dout, dabs
     for l in range(L - 1, 0, -1):
-        h = acts[l - 1]
+        h = rnd(acts[l - 1])
         dW[l] = d.T @ h
         db[l] = d.sum(0)
-        dh = d @ mlp.W[l]
-        d = dh * (pres[l - 1] > 0)
-    x_full = np.concatenate([x_mean, np.broadcast_to(np.atleast_2d(x_tx), (x_mean.shape[0], x_tx.shape[-1]))], -1)
+        Wl = rnd(mlp.W[l])
+        mask = pres[l - 1] > 0
+        d = (d @ Wl) * mask
+        if D is not None:
+            AW[l] = D.T @ np.abs(h)
+            Ab[l] = D.sum(0)
+            D = (D @ np.abs(Wl)) * mask
+    dm = x_mean.shape[1]
+    x_full = np.concatenate([rnd(x_mean), np.broadcast_to(np.atleast_2d(x_tx), (x_mean.shape[0], x_tx.shape[-1]))],
+                            -1)
     dW[0] = d.T @ x_full
     db[0] = d.sum(0)
-    dxm = d @ mlp.W[0][:, : x_mean.shape[1]]
-    return dW, db, dxm
+    W1m = rnd(mlp.W[0][:, :dm])
+    dxm = d @ W1m
+    if D is None:
+        return dW, db, dxm
+    AW[0] = D.T @ np.abs(x_full)
+    Ab[0] = D.sum(0)
+    return dW, db, dxm, (AW, Ab, D @ np.abs(W1m))
 
 
 def posenc_backward(v, L, dgamma):
@@ -105,14 +132,63 @@ def posenc_backward(v, L, dgamma):
     return out
 
 
+def chain_to_params_abs(g: dict, rg: dict, gabs: np.ndarray) -> np.ndarray:
+    """chain_to_params on magnitudes: every linear map of the chain replaced by
+    its entrywise absolute value, applied to raster magnitudes gabs (n, 7)."""
+    ixx, ixy, iyy = np.abs(rg["ixx"]), np.abs(rg["ixy"]), np.abs(rg["iyy"])
+    Ga = np.stack([np.stack([gabs[:, 2], 0.5 * gabs[:, 3]], -1), np.stack([0.5 * gabs[:, 3], gabs[:, 4]], -1)], -2)
+    I = np.stack([np.stack([ixx, ixy], -1), np.stack([ixy, iyy], -1)], -2)
+    GS = np.einsum("nab,nbc,ncd->nad", I, Ga, I)
+    c, s = np.abs(np.cos(g["rot"])), np.abs(np.sin(g["rot"]))
+    ex, ey = np.exp(2.0 * g["lsx"]), np.exp(2.0 * g["lsy"])
+    dS = {
+        "lsx": (2 * c * c * ex, 2 * c * s * ex, 2 * s * s * ex),
+        "lsy": (2 * s * s * ey, 2 * c * s * ey, 2 * c * c * ey),
+        "rot": (2 * c * s * (ey + ex), (c * c + s * s) * (ex + ey), 2 * c * s * (ex + ey)),
+    }
+    out = np.zeros((len(c), 7))
+    out[:, 0:2] = gabs[:, 0:2]
+    for j, k in ((2, "lsx"), (3, "lsy"), (4, "rot")):
+        dxx, dxy, dyy = dS[k]
+        out[:, j] = GS[:, 0, 0] * dxx + 2.0 * GS[:, 0, 1] * dxy + GS[:, 1, 1] * dyy
+    op = g["opacity"]
+    out[:, 5] = gabs[:, 5] * op * (1.0 - op)
+    out[:, 6] = gabs[:, 6]
+    out[~rg["live"].astype(bool)] = 0.0
+    return out
+
+
+def posenc_backward_abs(v, L, dabs):
+    """posenc_backward on magnitudes (absolute value of every factor)."""
+    v = np.asarray(v, np.float64)
+    d = v.shape[-1]
+    out = dabs[..., :d].copy()
+    for k in range(L):
+        f = (2.0 ** k) * np.pi
+        out += dabs[..., d * (1 + k): d * (2 + k)] * f * np.abs(np.cos(f * v))
+        out += dabs[..., d * (1 + L + k): d * (2 + L + k)] * f * np.abs(np.sin(f * v))
+    return out
+
+
 def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAULT_ROOM, stop_grad_pos=False,
-                  pixel_weights=None):
+                  pixel_weights=None, bf16=False, deltas=None, bounds=False):
     """L1 loss over a batch of queries and its FP64 gradient.
 
     Returns (loss, grads) where grads has 'base' (n, 7) for
     (mx, my, lsx, lsy, rot, logit, amp) and, with an MLP, 'W'/'b' lists.
     With pixel_weights (one array of H*W per query) the objective is instead
-    sum_b sum_p w_bp C_bp, and the returned loss is that sum."""
+    sum_b sum_p w_bp C_bp, and the returned loss is that sum; only the pixels
+    with a non-zero weight are composited.
+
+    bf16: the forward and backward of the BF16-rounding network. deltas (one
+    (n, 7) array per query, optional): deform with these residuals instead of
+    the network's own (e.g. the residuals another implementation computed); the
+    MLP backward still uses the network's activations. bounds: grads also holds
+    magnitude sums for componentwise error bounds: 'base_abs' (n, 7) of the
+    compositing-and-covariance part, 'pe_abs' (n, 2) of the mean features' part
+    through the network, 'W_abs' / 'b_abs' of the network's gradients (each the
+    absolute-value chain of the same computation), and 'replay' = the largest
+    number of Gaussians composited at a weighted pixel."""
     B = len(txs)
     H, W = scene.H, scene.W
     count = B * H * W
@@ -122,28 +198,47 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
     gflag = np.zeros(scene.n, np.int8)
     gW = [np.zeros_like(w) for w in mlp.W] if mlp is not None else None
     gb = [np.zeros_like(b) for b in mlp.b] if mlp is not None else None
+    if bounds:
+        base_abs = np.zeros((scene.n, 7))
+        pe_abs = np.zeros((scene.n, 2))
+        W_abs = [np.zeros_like(w) for w in mlp.W] if mlp is not None else None
+        b_abs = [np.zeros_like(b) for b in mlp.b] if mlp is not None else None
+        replay = 0
     loss = 0.0
     xm = M.posenc(M.normalize_mean(scene.mx, scene.my, H, W), M.MEAN_BANDS) if mlp is not None else None
     for b in range(B):
-        delta = M.deltas(scene, mlp, txs[b], room) if mlp is not None else None
+        if deltas is not None:
+            delta = np.asarray(deltas[b], np.float64)
+        else:
+            delta = M.deltas(scene, mlp, txs[b], room, bf16=bf16) if mlp is not None else None
         g = M.deform(scene, delta)
         rg = M.gaussians_for_raster(g, scene.depth)
-        res = M.composite(rg, order, pix[0], pix[1], margins=None)
         if pixel_weights is not None:
             w = np.asarray(pixel_weights[b], np.float64).ravel()
-            loss += float((w * res.C).sum())
+            sel = np.nonzero(w)[0]
+            res = M.composite(rg, order, pix[0][sel], pix[1][sel], margins=None)
+            loss += float((w[sel] * res.C).sum())
         else:
+            res = M.composite(rg, order, pix[0], pix[1], margins=None)
             t = np.asarray(targets[b], np.float64).ravel()
             loss += np.abs(res.C - t).sum() / count
             w = _pixel_weights(res.C, t, count)
+            sel = np.nonzero(w)[0]
         fl = np.zeros(scene.n, np.int8)
-        gr = raster_grad(rg, order, pix, w, fl)
+        ga = np.zeros((scene.n, 7)) if bounds else None
+        gr = raster_grad(rg, order, pix, w, fl, ga)
         gflag |= fl
         gp = chain_to_params(g, rg, gr)
         gbase += gp
+        if bounds:
+            gpa = chain_to_params_abs(g, rg, ga)
+            base_abs += gpa
+            if len(sel):
+                replay = max(replay, int(res.ncontrib.max()))
         if mlp is not None:
             xs = M.posenc(M.normalize_tx(txs[b], room), M.TX_BANDS)
-            dW, db, dxm = mlp_backward(xm, xs, mlp, gp)
+            r = mlp_backward(xm, xs, mlp, gp, bf16=bf16, dabs=gpa if bounds else None)
+            dW, db, dxm = r[:3]
             for l in range(mlp.n_layers):
                 gW[l] += dW[l]
                 gb[l] += db[l]
@@ -151,9 +246,20 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
             dmu_hat = posenc_backward(mu_hat, M.MEAN_BANDS, dxm)
             gbase[:, 0] += dmu_hat[:, 0] / W
             gbase[:, 1] += dmu_hat[:, 1] / H
+            if bounds:
+                AW, Ab, Dxm = r[3]
+                for l in range(mlp.n_layers):
+                    W_abs[l] += AW[l]
+                    b_abs[l] += Ab[l]
+                pa = posenc_backward_abs(mu_hat, M.MEAN_BANDS, Dxm)
+                pe_abs[:, 0] += pa[:, 0] / W
+                pe_abs[:, 1] += pa[:, 1] / H
     if stop_grad_pos:
         gbase[:, 0:2] = 0.0
-    return loss, dict(base=gbase, W=gW, b=gb, flagged=gflag.astype(bool))
+    out = dict(base=gbase, W=gW, b=gb, flagged=gflag.astype(bool))
+    if bounds:
+        out.update(base_abs=base_abs, pe_abs=pe_abs, W_abs=W_abs, b_abs=b_abs, replay=replay)
+    return loss, out
 
 
 def loss_only(scene: M.Scene, mlp, txs, targets, room=M.DEFAULT_ROOM):

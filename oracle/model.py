@@ -69,7 +69,7 @@ def _raster():
         P = ctypes.c_void_p
         lib.oracle_render.argtypes = [ctypes.c_int64] + [P] * 10 + [P, ctypes.c_int64] + [P] * 13
         lib.oracle_render.restype = None
-        lib.oracle_grad.argtypes = [ctypes.c_int64] + [P] * 11 + [ctypes.c_int64] + [P] * 5
+        lib.oracle_grad.argtypes = [ctypes.c_int64] + [P] * 11 + [ctypes.c_int64] + [P] * 6
         lib.oracle_grad.restype = None
         lib.oracle_max_leaves.restype = ctypes.c_int
         lib.oracle_render_held.argtypes = [ctypes.c_int64] + [P] * 16 + [ctypes.c_int64] + [P] * 3

@@ -248,18 +248,26 @@ void oracle_render(int64_t n, const double *mx, const double *my, const double *
  * off-diagonal entry, so d q / d ixy = 2 dx dy. `grad` is overwritten. With
  * margins and gflag, gflag[g] = 1 marks Gaussians with a near-threshold decision
  * at some weighted pixel (writes of 1 only, so concurrent marking is benign). */
+/* With grad_abs (nullable) the same loop also accumulates, per Gaussian and
+ * component, the sum over pixels of |w| times the magnitude of each term: the
+ * scale of a componentwise rounding-error bound. There dC/dalpha_i is taken as
+ * |amp_i| T_i + S_i' / (1 - alpha_i) with S_i' the sum of |amp_j| alpha_j T_j
+ * over later contributors, and every other factor by its absolute value. */
 void oracle_grad(int64_t n, const double *mx, const double *my, const double *ixx, const double *ixy,
                  const double *iyy, const double *op, const double *amp, const int8_t *live,
                  const int64_t *order, const double *consts, const double *margins, int64_t npix,
-                 const int32_t *pix_x, const int32_t *pix_y, const double *w, double *grad, int8_t *gflag)
+                 const int32_t *pix_x, const int32_t *pix_y, const double *w, double *grad, int8_t *gflag,
+                 double *grad_abs)
 {
     scene_t s;
     fill_scene(&s, n, mx, my, ixx, ixy, iyy, op, amp, live, order, consts, margins);
     memset(grad, 0, sizeof(double) * (size_t)n * 7);
+    if (grad_abs) memset(grad_abs, 0, sizeof(double) * (size_t)n * 7);
     if (gflag) memset(gflag, 0, (size_t)n);
 #pragma omp parallel
     {
         double *acc = (double *)calloc((size_t)n * 7, sizeof(double));
+        double *acca = grad_abs ? (double *)calloc((size_t)n * 7, sizeof(double)) : NULL;
         int64_t *cg = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
         double *ca = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
         double *cT = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
@@ -292,34 +300,52 @@ void oracle_grad(int64_t n, const double *mx, const double *my, const double *ix
                 ++m;
                 T = Tn;
             }
-            double S = 0.0; /* sum over later contributors of amp_j alpha_j T_j */
+            double S = 0.0;  /* sum over later contributors of amp_j alpha_j T_j */
+            double Sa = 0.0; /* the same with |amp_j| */
+            const double aw = fabs(w[p]);
             for (int64_t i = m - 1; i >= 0; --i) {
                 const int64_t g = cg[i];
                 const double a = ca[i], Ti = cT[i];
                 const double dC_damp = a * Ti;
                 const double dC_da = s.amp[g] * Ti - S / (1.0 - a);
+                const double dC_da_abs = fabs(s.amp[g]) * Ti + Sa / (1.0 - a);
                 S += s.amp[g] * a * Ti;
+                Sa += fabs(s.amp[g]) * a * Ti;
                 double *G = acc + g * 7;
+                double *GA = acca ? acca + g * 7 : NULL;
                 G[6] += w[p] * dC_damp;
+                if (GA) GA[6] += aw * dC_damp;
                 if (cc[i]) continue;
                 const double dx = px - s.mx[g], dy = py - s.my[g];
                 const double q = s.ixx[g] * dx * dx + 2.0 * s.ixy[g] * dx * dy + s.iyy[g] * dy * dy;
                 const double Gk = exp(-0.5 * q);
                 const double dC_dop = dC_da * Gk;
                 const double dC_dq = dC_da * (-0.5 * s.op[g] * Gk);
-                G[0] += w[p] * dC_dq * (-2.0 * (s.ixx[g] * dx + s.ixy[g] * dy));
-                G[1] += w[p] * dC_dq * (-2.0 * (s.ixy[g] * dx + s.iyy[g] * dy));
+                const double ux = -2.0 * (s.ixx[g] * dx + s.ixy[g] * dy), uy = -2.0 * (s.ixy[g] * dx + s.iyy[g] * dy);
+                G[0] += w[p] * dC_dq * ux;
+                G[1] += w[p] * dC_dq * uy;
                 G[2] += w[p] * dC_dq * dx * dx;
                 G[3] += w[p] * dC_dq * 2.0 * dx * dy;
                 G[4] += w[p] * dC_dq * dy * dy;
                 G[5] += w[p] * dC_dop;
+                if (GA) {
+                    const double mq = aw * dC_da_abs * 0.5 * s.op[g] * Gk;
+                    GA[0] += mq * fabs(ux);
+                    GA[1] += mq * fabs(uy);
+                    GA[2] += mq * dx * dx;
+                    GA[3] += mq * 2.0 * fabs(dx * dy);
+                    GA[4] += mq * dy * dy;
+                    GA[5] += aw * dC_da_abs * Gk;
+                }
             }
         }
 #pragma omp critical
         {
             for (int64_t i = 0; i < n * 7; ++i) grad[i] += acc[i];
+            if (acca)
+                for (int64_t i = 0; i < n * 7; ++i) grad_abs[i] += acca[i];
         }
-        free(acc); free(cg); free(ca); free(cT); free(cc);
+        free(acc); free(acca); free(cg); free(ca); free(cT); free(cc);
     }
 }
 

@@ -104,6 +104,7 @@ def lib():
             "swf_debug_deform": [P, I32, P, I32, I32, P, P],
             "swf_debug_keys": [P, P, P, P, P, P, P, ctypes.c_uint64],
             "swf_debug_blend_work": [P, P, P, P],
+            "swf_debug_rects": [P, P, ctypes.c_uint64],
             "swf_last_device_status": [P, P],
             "swf_measure_peaks": [P, P, P, P],
             "swf_radix_sort": [P, P, P, I64, I32, I32, I32, P],
@@ -267,7 +268,17 @@ class Context:
             gr.weight[l] = w.data_ptr() if w is not None else None
         for l, b in enumerate(grads.get("bias", []) or []):
             gr.bias[l] = b.data_ptr() if b is not None else None
+        torch = self.torch
+        H, W, n, _ = self._keep[sid]
         batch = tx.shape[0] if tx is not None else grad_out.shape[0]
+        if grad_out.dtype != torch.float32 or not grad_out.is_contiguous() or grad_out.numel() != batch * H * W:
+            raise SwfError(f"grad_out must be contiguous float32 with {batch}*{H}*{W} values")
+        if aux is None or not aux.is_contiguous() or aux.numel() * aux.element_size() != 8 * batch * H * W:
+            raise SwfError(f"aux must be the contiguous {8 * batch * H * W}-byte buffer of the forward render")
+        for k in PARAMS[:7]:
+            t = grads.get(k)
+            if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n):
+                raise SwfError(f"grads[{k!r}] must be contiguous float32 with {n} values")
         self._check(self._L.swf_render_backward(self._h, sid, _ptr(tx), batch, flags, _ptr(grad_out), _ptr(aux),
                                                 ctypes.byref(gr), _stream()))
 
@@ -297,6 +308,12 @@ class Context:
         d = torch.empty((tx.shape[0], n, 7), device=self.device, dtype=torch.float32)
         self._check(self._L.swf_debug_deform(self._h, sid, _ptr(tx), tx.shape[0], flags, _ptr(d), _stream()))
         return d
+
+    def debug_rects(self, batch: int, n: int):
+        """Tile rectangles of the last render's pairs, (batch, n, 4) int32 (tx0, ty0, tx1, ty1; -1 if culled)."""
+        r = np.zeros((batch, n, 4), np.int32)
+        self._check(self._L.swf_debug_rects(self._h, r.ctypes.data_as(ctypes.c_void_p), batch * n))
+        return r
 
     def debug_keys(self, batch: int, n: int, tiles: int, capacity: int | None = None):
         self.torch.cuda.synchronize()
@@ -346,6 +363,7 @@ class Context:
         tot = torch.zeros(1, device=self.device, dtype=torch.int64)
         self._check(self._L.swf_exclusive_scan(self._h, _ptr(counts), _ptr(off), _ptr(tot), counts.numel(), _stream()))
         return off, tot
+
 
     # ---- serving ------------------------------------------------------------------
     def serve_start(self, max_batch=64, n_slots=2, flags=MLP_BF16, key_factor=1.5, hbm_budget=0, use_graphs=True):

@@ -165,8 +165,10 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
         }
         wl[nh] = wb + (size_t)(nh - 1) * Hd * Hd;
         launch_to_bf16(d.w[nh], (int64_t)kOut * Hd, wl[nh], st);
-        dyb = wl[nh] + (size_t)kOut * Hd;
-        launch_to_bf16(dy, P * kOut, dyb, st);
+        if (nh == 1) {  // the library GEMM of the single-hidden-layer path takes BF16 operands
+            dyb = wl[nh] + (size_t)kOut * Hd;
+            launch_to_bf16(dy, P * kOut, dyb, st);
+        }
     }
     // ---- the hidden activations: stored by the forward pass (BF16), else recomputed
     if (!(bf16 && acts_ready)) {
@@ -193,7 +195,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     if (bf16) {
         // one pass over the last activations: the weight gradient and, with more than one hidden layer, the
         // masked BF16 gradient of the last hidden pre-activations (K = 7)
-        launch_out_bwd_bf16(dyb, wl[nh], act[nh - 1], P, nh > 1 ? dz[0] : nullptr, part, tmp, gr->weight[nh], st);
+        launch_out_bwd_bf16(dy, wl[nh], act[nh - 1], P, nh > 1 ? dz[0] : nullptr, part, tmp, gr->weight[nh], st);
     } else if (gr->weight[nh] &&
                (s = ok(wgrad_rm(h, kOut, Hd, P, dy, (const float*)act[nh - 1], gr->weight[nh], part, tmp, st),
                        "dWo"))) {
@@ -285,6 +287,17 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     if (!grad_out || !aux || !gr) return fail(SWF_E_INVALID, "grad_out, aux and grads are required");
     Scene* sc = scene(sid);
     if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
+    {
+        // the forward pass below must be the one that filled aux
+        auto it = aux_tags.find(aux);
+        if (it == aux_tags.end())
+            return fail(SWF_E_STATE, "aux was not filled by a swf_render with SWF_KEEP_AUX on this context");
+        const AuxTag& t = it->second;
+        if (t.scene != sid || t.B != B || t.flags != (flags & ~SWF_KEEP_AUX))
+            return fail(SWF_E_INVALID, "scene, batch or flags differ from the render that filled aux");
+        if (t.gen != sc->gen)
+            return fail(SWF_E_STATE, "the scene's parameters were updated after the render that filled aux");
+    }
     const DevScene& d = sc->d;
     const bool deform = !(flags & SWF_NO_DEFORM);
     const bool want_mlp = deform && d.has_mlp;

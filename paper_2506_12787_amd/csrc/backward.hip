@@ -777,13 +777,14 @@ __global__ __launch_bounds__(64 * kWgWaves) void wgrad_mfma_kernel(const __bf16*
 
 // Output layer of a BF16 backward in one pass over the last hidden activations
 // act [P][256] (BF16), per block of pairs (one slice of rpb pairs): with dy
-// [P][7] and Wo [7][256] BF16 (every product exact in FP32),
+// [P][7] FP32 (the upstream gradient as computed, not rounded) and Wo [7][256]
+// BF16,
 //   dz[p][f] = BF16(sum_o dy[p][o] Wo[o][f]), zero where act[p][f] is not > 0
 //     (the gradient of the last hidden pre-activations; skipped if dz is NULL),
 //   part[blk][o][f] = sum over the slice of dy[p][o] act[p][f] (the weight
 //     gradient's partial; skipped if part is NULL; the caller adds the slices).
 // Thread: 8 features (16-byte loads and stores) of every 8th pair of the slice.
-__global__ __launch_bounds__(256) void out_bwd_bf16_kernel(const __bf16* __restrict__ dy,
+__global__ __launch_bounds__(256) void out_bwd_bf16_kernel(const float* __restrict__ dy,
                                                            const __bf16* __restrict__ wo,
                                                            const __bf16* __restrict__ act, int64_t P, int64_t rpb,
                                                            __bf16* __restrict__ dz, float* __restrict__ part) {
@@ -801,7 +802,7 @@ __global__ __launch_bounds__(256) void out_bwd_bf16_kernel(const __bf16* __restr
     for (int64_t p = beg + row; p < end; p += 8) {
         float y[kOut];
 #pragma unroll
-        for (int o = 0; o < kOut; ++o) y[o] = (float)dy[p * kOut + o];
+        for (int o = 0; o < kOut; ++o) y[o] = dy[p * kOut + o];
         const uint4 a = *reinterpret_cast<const uint4*>(act + p * 256 + f0);
         const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
         float av[8];
@@ -1080,12 +1081,12 @@ void launch_dz_gemm(const void* dz, const void* W, const void* act, int64_t P, v
 
 int wgrad_out_blocks(int64_t P) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (P + 255) / 256)); }
 
-void launch_out_bwd_bf16(const void* dy, const void* wo, const void* act, int64_t P, void* dz, float* part,
+void launch_out_bwd_bf16(const float* dy, const void* wo, const void* act, int64_t P, void* dz, float* part,
                          float* tmp, float* dWo, hipStream_t st) {
     if (!dz && !dWo) return;
     const int nblk = wgrad_out_blocks(P);  // P = 0: one block writes zeros
     const int64_t rpb = ((P + nblk - 1) / nblk + 7) / 8 * 8;
-    out_bwd_bf16_kernel<<<nblk, 256, 0, st>>>((const __bf16*)dy, (const __bf16*)wo, (const __bf16*)act, P, rpb,
+    out_bwd_bf16_kernel<<<nblk, 256, 0, st>>>(dy, (const __bf16*)wo, (const __bf16*)act, P, rpb,
                                               (__bf16*)dz, dWo ? part : nullptr);
     if (dWo) launch_colsum(part, nblk, (int64_t)kOut * 256, 1, 0, tmp, dWo, 0, st);
 }

@@ -141,7 +141,7 @@ void launch_layer1_grad(const void* dz1, const void* W, const void* act, int B, 
                         hipStream_t st);
 // Output layer of a BF16 backward in one pass over act [P][256]: dz (may be NULL) = (dy Wo) rounded to BF16 and
 // masked by act > 0; dWo [7][256] (may be NULL) = dy^T act. part: wgrad_out_blocks(P) * 7 * 256 floats.
-void launch_out_bwd_bf16(const void* dy, const void* wo, const void* act, int64_t P, void* dz, float* part,
+void launch_out_bwd_bf16(const float* dy, const void* wo, const void* act, int64_t P, void* dz, float* part,
                          float* tmp, float* dWo, hipStream_t st);
 int wgrad_out_blocks(int64_t P);  // blocks (pair slices) of launch_out_bwd_bf16
 // S [N][256] = sum_b of z * [act > 0] and Rpart [layer1_sums_blocks(N)][B][256] partial sums over Gaussians

@@ -149,6 +149,18 @@ void Ctx::resolve_timing() {
     pending.clear();
 }
 
+void Ctx::tag_aux(const void* aux, const AuxTag& t) {
+    constexpr size_t kMaxTags = 1024;
+    if (!aux_tags.count(aux)) {
+        aux_order.push_back(aux);
+        if (aux_order.size() > kMaxTags) {
+            aux_tags.erase(aux_order.front());
+            aux_order.erase(aux_order.begin());
+        }
+    }
+    aux_tags[aux] = t;
+}
+
 Scene* Ctx::scene(int id) {
     auto it = scenes.find(id);
     return it == scenes.end() ? nullptr : it->second;
@@ -379,6 +391,7 @@ swf_status Ctx::update_scene(int id, const swf_gaussians* g, const swf_mlp* mlp,
     if (!s) return fail(SWF_E_NOT_FOUND, "unknown scene id");
     DevScene& d = s->d;
     swf_status r = SWF_OK;
+    if (g || mlp) ++s->gen;
     if (g) {
         if (g->n != d.n) return fail(SWF_E_INVALID, "n differs from the uploaded scene");
         const float* src[7] = {g->mean_x, g->mean_y, g->log_scale_x, g->log_scale_y, g->rotation, g->opacity_logit,
@@ -641,6 +654,14 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
     const DevScene& d = scene(sid)->d;
     float* auxT = nullptr;
     uint32_t* auxL = nullptr;
+    if ((flags & SWF_KEEP_AUX) && &w == &ws) {
+        AuxTag t;
+        t.scene = sid;
+        t.B = B;
+        t.flags = flags & ~SWF_KEEP_AUX;
+        t.gen = scene(sid)->gen;
+        tag_aux(aux, t);
+    }
     if (flags & SWF_KEEP_AUX) {
         auxT = (float*)aux;
         auxL = (uint32_t*)((char*)aux + sizeof(float) * (size_t)B * d.H * d.W);
@@ -803,6 +824,38 @@ swf_status swf_debug_deform(swf_ctx* h, int32_t scene_id, const float* tx, int32
     launch_permute_delta((const float*)c->ws.delta.ptr, d.perm, batch, d.n, delta, st);
     c->ws.last.valid = false;
     return c->hip(hipGetLastError(), "debug deform");
+}
+
+swf_status swf_debug_rects(swf_ctx* h, int32_t* rects, uint64_t capacity) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    if (!rects) return c->fail(SWF_E_INVALID, "rects is NULL");
+    if (!c->ws.last.valid) return c->fail(SWF_E_STATE, "no render to inspect");
+    Scene* sc = c->scene(c->ws.last.scene);
+    if (!sc) return c->fail(SWF_E_STATE, "scene of the last render was released");
+    const auto& L = c->ws.last;
+    const size_t pairs = (size_t)L.B * L.N;
+    if (capacity < pairs) return c->fail(SWF_E_OVERFLOW, "capacity below batch * n");
+    swf_status s;
+    if ((s = c->hip(hipStreamSynchronize(L.stream), "stream sync"))) return s;
+    std::vector<uint32_t> r(2 * pairs), cnt(pairs);
+    if (pairs && (s = c->hip(hipMemcpy(r.data(), c->ws.rec.rect, pairs * 8, hipMemcpyDeviceToHost), "D2H rects")))
+        return s;
+    if (pairs && (s = c->hip(hipMemcpy(cnt.data(), c->ws.rec.count, pairs * 4, hipMemcpyDeviceToHost), "D2H counts")))
+        return s;
+    for (size_t i = 0; i < pairs; ++i) {
+        const size_t q = i / L.N, id = sc->host_perm[i % L.N];
+        int32_t* o = rects + 4 * (q * L.N + id);
+        if (!cnt[i]) {
+            o[0] = o[1] = o[2] = o[3] = -1;
+        } else {
+            o[0] = (int32_t)(r[2 * i] & 0xffffu);
+            o[1] = (int32_t)(r[2 * i + 1] & 0xffffu);
+            o[2] = (int32_t)(r[2 * i] >> 16);
+            o[3] = (int32_t)(r[2 * i + 1] >> 16);
+        }
+    }
+    return SWF_OK;
 }
 
 swf_status swf_debug_keys(swf_ctx* h, uint32_t* counts, uint32_t* offsets, uint64_t* keys, uint64_t* values,

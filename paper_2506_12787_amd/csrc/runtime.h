@@ -27,6 +27,7 @@ struct Buf {
 
 struct Scene {
     DevScene d;
+    uint64_t gen = 0;  // parameter generation: incremented by every swf_scene_update
     std::vector<void*> allocs;
     std::vector<uint32_t> host_dbits;  // per sorted position
     std::vector<uint32_t> host_perm;   // sorted position -> original id
@@ -77,6 +78,13 @@ struct Workspace {
     void release();
 };
 
+// What a render with SWF_KEEP_AUX wrote into a caller's aux buffer: the
+// backward re-runs that forward pass and must see the same scene parameters.
+struct AuxTag {
+    int scene = -1, B = 0, flags = 0;
+    uint64_t gen = 0;
+};
+
 struct ServeState;
 struct Ctx;
 void blas_release(Ctx* c);  // destroys the rocBLAS handle (backward.cpp)
@@ -96,6 +104,12 @@ struct Ctx {
     std::vector<hipEvent_t> event_pool;
     double stage_ms[SWF_N_STAGES] = {};
     int64_t stage_n[SWF_N_STAGES] = {};
+
+    // aux buffers filled by direct renders (device address -> tag), newest last;
+    // bounded, the oldest forgotten first
+    std::map<const void*, AuxTag> aux_tags;
+    std::vector<const void*> aux_order;
+    void tag_aux(const void* aux, const AuxTag& t);
 
     ServeState* serve = nullptr;
     int mlp_pairs_per_wave = 0;  // BF16 MLP register tile: 48 (default, 0), 32 or 64 pairs per wave

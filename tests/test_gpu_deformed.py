@@ -1,0 +1,133 @@
+"""Deformable renders through the C ABI:
+  * the per-tile lists of deformed, batched renders against the oracle's key
+    lists built from the GPU's own tile rectangles and depth bits (bit-exact:
+    counts, offsets, sorted keys, values, tile ranges), at 180x720 (two tile
+    segments per query) with 4 queries, BF16 and FP32 MLPs, binned and fully
+    sorted lists; and the GPU's rectangles against the oracle's FP64 ones for
+    the same residuals (equal unless the oracle flags an edge as ambiguous,
+    then one of its alternatives) -- Sec. 4.1 tile partitioning;
+  * the paper's deformation (no covariance residual, Sec. 4.2) against the
+    oracle with those residuals zeroed;
+  * sampled-pixel parity at the deformable-forward workload's shape: N = 20,000,
+    a batch of 64 TX positions in one launch, BF16 and FP32 MLPs."""
+import numpy as np
+import pytest
+
+from oracle import model as M
+from paper_2506_12787_amd import synth
+from tests import helpers as Hh
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2506_12787_amd import binding
+    assert torch.cuda.is_available(), "GPU test on a machine without a GPU"
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("mlp", ["bf16", "fp32"])
+@pytest.mark.parametrize("full", [False, True], ids=["binned", "full_sort"])
+def test_deformed_lists_match_oracle_keys_on_gpu_rects(ctx, mlp, full):
+    import torch
+    from paper_2506_12787_amd import binding as B
+    H, W, n, nb = 180, 720, 3000, 4
+    g, s = Hh.problem(n, H, W, seed=111)
+    Ws, bs = synth.mlp_weights(seed=3111, out_scale=1.0)
+    sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
+    tx = torch.from_numpy(synth.tx_positions(nb, seed=2111)).cuda()
+    flags = (B.MLP_BF16 if mlp == "bf16" else B.MLP_FP32) | (B.FULL_SORT if full else 0)
+    ctx.render(sid, tx, flags=flags)
+    TW, TH = -(-W // 16), -(-H // 16)
+    tiles = TW * TH
+    rg = ctx.debug_rects(nb, n)
+    dk = ctx.debug_keys(nb, n, tiles)
+    deltas = ctx.debug_deform(sid, tx, flags & ~B.FULL_SORT).cpu().numpy().astype(np.float64)
+    order = M.depth_order(s.depth)
+    counts, gts, dbs, vals, ranges = [], [], [], [], []
+    base = 0
+    flagged_total = 0
+    for q in range(nb):
+        rect = rg[q].astype(np.int64)
+        # the GPU's rectangles against the oracle's FP64 ones for the GPU's residuals
+        gm = M.deform(s, deltas[q])
+        rgq = M.gaussians_for_raster(gm, s.depth)
+        orect, flagged, alts = M.tile_rects(gm, rgq, H, W, 16)
+        np.testing.assert_array_equal(rect[~flagged], orect[~flagged])
+        for i in np.nonzero(flagged)[0]:
+            assert tuple(int(v) for v in rect[i]) in alts[int(i)], (q, i, rect[i], alts[int(i)])
+        flagged_total += int(flagged.sum())
+        # the oracle's lists from the GPU's own rectangles and depth bits
+        counts.append(M.rect_count(rect)[order])
+        gt, db, ids, rq = M.key_list(rect, s.depth, H, W, tile_base=q * tiles)
+        gts.append(gt)
+        dbs.append(db)
+        vals.append((np.uint64(q) << np.uint64(32)) | ids.astype(np.uint64))
+        ranges.append(rq + base)
+        base += len(gt)
+    counts = np.concatenate(counts)
+    offs, tot = M.exclusive_scan(counts)
+    print(f"{mlp} full={full}: {tot} list entries, {flagged_total} ambiguous rectangles", flush=True)
+    np.testing.assert_array_equal(dk["counts"], counts.astype(np.uint32))
+    np.testing.assert_array_equal(dk["offsets"], offs.astype(np.uint32))
+    assert len(dk["keys"]) == tot
+    np.testing.assert_array_equal(dk["keys"], (np.concatenate(gts) << np.uint64(32)) | np.concatenate(dbs))
+    np.testing.assert_array_equal(dk["values"], np.concatenate(vals))
+    np.testing.assert_array_equal(dk["ranges"].astype(np.int64), np.concatenate(ranges))
+    ctx.release_scene(sid)
+
+
+@pytest.mark.parametrize("mlp", ["bf16", "fp32"])
+def test_paper_deformation_matches_oracle(ctx, mlp):
+    # SWF_PAPER_DEFORM keeps the residuals of the mean, opacity and amplitude
+    # and drops those of the covariance (the paper deforms no covariance).
+    import torch
+    from paper_2506_12787_amd import binding as B
+    H, W, n, nb = 90, 360, 2000, 2
+    g, s = Hh.problem(n, H, W, seed=112)
+    Ws, bs = synth.mlp_weights(seed=3112, out_scale=1.0)
+    sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
+    tx = torch.from_numpy(synth.tx_positions(nb, seed=2112)).cuda()
+    bf16 = mlp == "bf16"
+    flags = (B.MLP_BF16 if bf16 else B.MLP_FP32) | B.PAPER_DEFORM
+    out = ctx.render(sid, tx, flags=flags).cpu().numpy()
+    full = ctx.render(sid, tx, flags=flags & ~B.PAPER_DEFORM).cpu().numpy()
+    assert np.abs(out - full).max() > 1e-3 * np.abs(full).max()  # the covariance residuals matter here
+    m64 = Hh.mlp_f64(Ws, bs)
+    for q, t in enumerate(tx.cpu().numpy().astype(np.float64)):
+        d = M.deltas(s, m64, t, bf16=bf16)
+        d[:, 2:5] = 0.0
+        res, _, _, _ = M.render_query(s, None, None, delta=d)
+        rep = Hh.parity(out[q], res)
+        print(f"paper deformation {mlp} query {q}: {rep}", flush=True)
+    ctx.release_scene(sid)
+
+
+@pytest.mark.parametrize("mlp", ["bf16", "fp32"])
+def test_deformable_forward_workload_sampled_pixels(ctx, mlp):
+    # N = 20,000 Gaussians, 64 TX positions in one launch, 90x360.
+    import torch
+    from paper_2506_12787_amd import binding as B
+    N, H, W, nb = 20_000, 90, 360, 64
+    g = synth.gaussians(N, H, W, seed=1001)
+    Ws, bs = synth.mlp_weights(seed=3001)
+    s = M.Scene.from_arrays(g, H, W)
+    sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
+    tx = torch.from_numpy(synth.tx_positions(nb, seed=2001)).cuda()
+    bf16 = mlp == "bf16"
+    out = ctx.render(sid, tx, flags=B.MLP_BF16 if bf16 else B.MLP_FP32)
+    m64 = Hh.mlp_f64(Ws, bs)
+    txh = tx.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(9001)
+    for q in (0, 31, 63):
+        px = rng.integers(0, W, 160).astype(np.int32)
+        py = rng.integers(0, H, 160).astype(np.int32)
+        got = out[q][torch.from_numpy(py.astype(np.int64)).cuda(), torch.from_numpy(px.astype(np.int64)).cuda()]
+        res, _, _, _ = M.render_query(s, m64, txh[q], pix=(px, py), bf16=bf16)
+        rep = Hh.parity(got.cpu().numpy(), res)
+        print(f"N=20k batch 64 {mlp} query {q}: {rep}", flush=True)
+    ctx.release_scene(sid)

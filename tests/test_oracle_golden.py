@@ -119,3 +119,35 @@ def test_bf16_mlp_fixture_detects_planted_rounding_mistakes(monkeypatch):
         monkeypatch.setattr(M, "bf16_round", wrong)
         out, pres, _ = M.mlp_forward(xm, xs, mlp, bf16=True)
         assert not np.array_equal(np.concatenate([pres[0][0], out[0]]), want)
+
+
+def test_bf16_mlp_backward_by_hand():
+    # Upstream gradient 1 on output 0 of the hand network. Through the
+    # BF16-rounding network each product uses the forward's rounded operands:
+    # d out0 / d pre1 = (bf(1025/1024), bf(1)) = (1, 1), both pre1 > 0; so
+    # dW2[0] = bf(act1) = (89/64, 1/4), dW1 rows = bf(act0) = (1/2, 0);
+    # d act0 = (1, 1) bf(W1) = (97/32, 1), masked by pre0 = (+, -) -> (97/32, 0);
+    # dW0[0, 0] = 97/32 bf(515/512) = 97/32 * 129/128, dW0[0, 1] = 97/32 bf(257/256)
+    # = 97/32, dW0[0, 26] = 97/32 (1 + 2^-20) (the transceiver feature is exact);
+    # d x_mean = 97/32 * (bf(1029/1024), bf(-259/256)) = 97/32 * (129/128, -65/64).
+    from fractions import Fraction as F
+    from oracle import grad as G
+    _, xm, xs, mlp, _ = _mlp_fixture()
+    dout = np.zeros((1, 7))
+    dout[0, 0] = 1.0
+    dW, db, dxm = G.mlp_backward(xm, xs, mlp, dout, bf16=True)
+    f = lambda q: float(q)
+    np.testing.assert_array_equal(dW[2][0], [89 / 64, 1 / 4])
+    np.testing.assert_array_equal(dW[2][1:], 0.0)
+    np.testing.assert_array_equal(db[2], dout[0])
+    np.testing.assert_array_equal(dW[1], [[0.5, 0.0], [0.5, 0.0]])
+    np.testing.assert_array_equal(db[1], [1.0, 1.0])
+    expect0 = np.zeros(89)
+    expect0[0] = f(F(97, 32) * F(129, 128))
+    expect0[1] = f(F(97, 32))
+    expect0[26] = f(F(97, 32) * (1 + F(1, 2 ** 20)))
+    np.testing.assert_array_equal(dW[0][0], expect0)
+    np.testing.assert_array_equal(dW[0][1], 0.0)
+    np.testing.assert_array_equal(db[0], [97 / 32, 0.0])
+    np.testing.assert_array_equal(dxm[0, :2], [f(F(97, 32) * F(129, 128)), f(F(97, 32) * F(-65, 64))])
+    np.testing.assert_array_equal(dxm[0, 2:], 0.0)

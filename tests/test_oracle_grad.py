@@ -152,3 +152,38 @@ def test_single_gaussian_gradient_closed_form():
     dmu = gm["amp"][0] * alpha * (I @ dv)
     np.testing.assert_allclose(gr[0, 0:2], dmu, rtol=1e-13)
     assert gr[0, 5] == pytest.approx(gm["amp"][0] * math.exp(-q / 2), rel=1e-14)
+
+
+def test_magnitude_sums_dominate_the_gradient():
+    # The magnitude sums behind the componentwise error bounds are sums of
+    # absolute values of the same terms: they dominate the gradient entrywise,
+    # and where every term is non-negative (dC/damp = alpha T >= 0 with
+    # non-negative pixel weights) they equal it.
+    s, mlp, txs, _ = _problem(n=150, B=2)
+    rng = np.random.default_rng(4)
+    w = [rng.uniform(0, 1, s.H * s.W) * (rng.uniform(0, 1, s.H * s.W) < 0.2) for _ in txs]
+    _, ref = G.loss_and_grad(s, mlp, txs, None, pixel_weights=w, bounds=True)
+    assert np.all(np.abs(ref["base"][:, 2:]) <= ref["base_abs"][:, 2:] * (1 + 1e-12) + 1e-300)
+    np.testing.assert_allclose(ref["base_abs"][:, 6], ref["base"][:, 6], rtol=1e-12, atol=1e-300)
+    assert np.all(np.abs(ref["base"][:, :2]) <= (ref["base_abs"][:, :2] + ref["pe_abs"]) * (1 + 1e-12) + 1e-300)
+    for l in range(mlp.n_layers):
+        assert np.all(np.abs(ref["W"][l]) <= ref["W_abs"][l] * (1 + 1e-12) + 1e-300)
+        assert np.all(np.abs(ref["b"][l]) <= ref["b_abs"][l] * (1 + 1e-12) + 1e-300)
+    assert ref["replay"] > 0
+    # the same with mixed-sign weights: only domination
+    w = [rng.normal(0, 1, s.H * s.W) * (rng.uniform(0, 1, s.H * s.W) < 0.2) for _ in txs]
+    _, ref = G.loss_and_grad(s, mlp, txs, None, pixel_weights=w, bounds=True)
+    assert np.all(np.abs(ref["base"][:, 2:]) <= ref["base_abs"][:, 2:] * (1 + 1e-12) + 1e-300)
+    for l in range(mlp.n_layers):
+        assert np.all(np.abs(ref["W"][l]) <= ref["W_abs"][l] * (1 + 1e-12) + 1e-300)
+
+
+def test_residual_override_reproduces_the_network():
+    # Feeding the network's own residuals through `deltas` changes nothing (up
+    # to the order in which the compositor's threads add their partial sums).
+    s, mlp, txs, targets = _problem(n=120, B=2)
+    l0, r0 = G.loss_and_grad(s, mlp, txs, targets)
+    d = [M.deltas(s, mlp, t) for t in txs]
+    l1, r1 = G.loss_and_grad(s, mlp, txs, targets, deltas=d)
+    assert l0 == l1
+    np.testing.assert_allclose(r0["base"], r1["base"], rtol=1e-12, atol=1e-15 * np.abs(r0["base"]).max())
