@@ -280,6 +280,17 @@ swf_status swf_radix_sort(swf_ctx *ctx, void *keys, uint32_t *values, int64_t n,
 swf_status swf_exclusive_scan(swf_ctx *ctx, const uint32_t *counts, uint32_t *offsets, uint64_t *total, int64_t n,
                               void *stream);
 
+/* Allocation-free variant of swf_exclusive_scan, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, same result. It calls no
+ * allocating routine; its scratch is a static 32 KiB device array per GPU
+ * (4096 + 8 block sums; the scan grid is capped at 4096 blocks, so every n
+ * fits, and a larger requirement would fail with SWF_E_OVERFLOW). All calls on
+ * one GPU share that array, so calls that overlap on one GPU race: order them
+ * (one stream, or events). Nothing in it needs to start at zero. */
+swf_status swf_exclusive_scan_noalloc(swf_ctx *ctx, const uint32_t *counts, uint32_t *offsets, uint64_t *total,
+                                      int64_t n, void *stream);
+
 /* ---- serving loop (continuous batching over resident scenes) --------------
  * The paper defines no serving interface; these calls serve the problem
  * statement's mapping s -> F(s) (Sec. 3.3) to many concurrent requesters: each

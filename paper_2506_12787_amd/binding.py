@@ -109,6 +109,7 @@ def lib():
             "swf_measure_peaks": [P, P, P, P],
             "swf_radix_sort": [P, P, P, I64, I32, I32, I32, P],
             "swf_exclusive_scan": [P, P, P, P, I64, P],
+            "swf_exclusive_scan_noalloc": [P, P, P, P, I64, P],
             "swf_serve_start": [P, P],
             "swf_serve_submit": [P, I32, P, P, ctypes.c_double, P],
             "swf_serve_poll": [P, ctypes.c_uint64, P],
@@ -364,6 +365,13 @@ class Context:
         self._check(self._L.swf_exclusive_scan(self._h, _ptr(counts), _ptr(off), _ptr(tot), counts.numel(), _stream()))
         return off, tot
 
+    def exclusive_scan_noalloc(self, counts, off, tot):
+        """The allocation-free scan into caller-owned off (uint32 like counts) and tot (one int64)."""
+        torch = self.torch
+        assert counts.dtype == torch.int32 and off.dtype == torch.int32 and off.numel() >= counts.numel()
+        assert tot.dtype == torch.int64 and tot.numel() >= 1 and counts.is_contiguous() and off.is_contiguous()
+        self._check(self._L.swf_exclusive_scan_noalloc(self._h, _ptr(counts), _ptr(off), _ptr(tot), counts.numel(),
+                                                       _stream()))
 
     # ---- serving ------------------------------------------------------------------
     def serve_start(self, max_batch=64, n_slots=2, flags=MLP_BF16, key_factor=1.5, hbm_budget=0, use_graphs=True):

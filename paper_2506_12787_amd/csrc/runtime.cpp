@@ -716,6 +716,11 @@ swf_status swf_create(swf_ctx** out, const swf_config* cfg) {
         delete c;
         return SWF_E_OOM;
     }
+    if (noalloc_setup(c) != SWF_OK) {
+        c->ws.release();
+        delete c;
+        return SWF_E_DEVICE;
+    }
     *out = reinterpret_cast<swf_ctx*>(c);
     return SWF_OK;
 }

@@ -148,12 +148,14 @@ struct Ctx {
     swf_status mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,
                             const swf_grads* gr, bool bf16, bool acts_ready, hipStream_t st);
     void* blas = nullptr;  // rocBLAS handle of the MLP backward (created on first use)
+    void* noalloc_scratch = nullptr;  // device address of the static scan scratch (noalloc.hip) on `device`
     void stage_begin(int stage, hipStream_t st);
     void stage_end(hipStream_t st);
     void resolve_timing();
 };
 
 Grid make_grid(int H, int W, int tile);
+swf_status noalloc_setup(Ctx* c);  // resolves Ctx::noalloc_scratch (noalloc.hip)
 const char* status_name(swf_status s);
 void serve_shutdown(Ctx* c);
 bool serve_timing_disabled();  // true on the serving scheduler thread
