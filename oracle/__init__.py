@@ -6,3 +6,4 @@ with the HIP library. See model.py for what each function follows in the paper.
 """
 from . import model  # noqa: F401
 from . import grad  # noqa: F401
+from . import beamscan  # noqa: F401

@@ -5,7 +5,7 @@ positions, MLP weights). It holds none of the method's arithmetic, and both the
 HIP path's tests and the FP64 oracle consume its output.
 
 Workload recipe (stand-in for the paper's indoor scenes, which are not
-available): means uniform over the pixel grid; log-scales uniform in
+available; multipath() stands in for ray-traced path lists): means uniform over the pixel grid; log-scales uniform in
 [log a, log b] pixels; rotation uniform in [0, pi); opacity logit ~ N(0, 1);
 amplitude uniform in [0, 1); depth uniform in [0.5, 10); transceiver positions
 uniform in a 6 x 6 x 3 m room. MLP weights are Xavier-uniform (gain 1) with zero
@@ -63,3 +63,50 @@ def mlp_weights(seed: int, mean_bands: int = 6, tx_bands: int = 10, hidden: int 
 def targets_like(shape, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(rng.uniform(0.0, 1.0, shape), dtype=np.float32)
+
+
+def multipath(b: int, seed: int, rx=(3.0, 0.5, 1.2), room=((0.0, 0.0, 0.0), (6.0, 6.0, 3.0)), max_order: int = 2,
+              gamma: float = 0.6, jitter: float = 0.05):
+    """Multipath lists of b transmitter positions seen from a fixed receiver in
+    a box room (a stand-in for ray-traced path lists): the line-of-sight path
+    and the specular reflections off the six walls up to `max_order` bounces,
+    by mirror images of the transmitter. Path l arrives from the direction of
+    its image source; its power coefficient is gamma^bounces / length times a
+    seeded factor in [1 - jitter, 1 + jitter]. Returns (paths, counts, tx):
+    paths float32 [b][L][3] = (rho, azimuth in [0, 2 pi), elevation in
+    [0, pi/2]) with unused slots zero, counts int32 [b], tx float32 [b][3].
+    Elevation is the angle above the array plane; a source below it arrives at
+    the mirrored elevation (a planar array cannot tell them apart)."""
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(room[0], np.float64)
+    hi = np.asarray(room[1], np.float64)
+    rx = np.asarray(rx, np.float64)
+    tx = lo + (hi - lo) * rng.uniform(0.05, 0.95, (b, 3))
+    images = [((0, 0, 0), 0)]
+    # image index k per axis (|k| reflections off that axis' two walls); total bounces = |kx| + |ky| + |kz|
+    for kx in range(-max_order, max_order + 1):
+        for ky in range(-max_order, max_order + 1):
+            for kz in range(-max_order, max_order + 1):
+                if (kx, ky, kz) == (0, 0, 0):
+                    continue
+                if abs(kx) + abs(ky) + abs(kz) <= max_order:
+                    images.append(((kx, ky, kz), abs(kx) + abs(ky) + abs(kz)))
+    L = len(images)
+    paths = np.zeros((b, L, 3), np.float64)
+    for i in range(b):
+        for l, (k, order) in enumerate(images):
+            src = np.empty(3)
+            for a in range(3):
+                size = hi[a] - lo[a]
+                x = tx[i, a] - lo[a]
+                # mirror images of a point in [0, size]: for k even x + k size, for k odd (k + 1) size - x
+                src[a] = lo[a] + (k[a] * size + x if k[a] % 2 == 0 else (k[a] + 1) * size - x)
+            d = src - rx
+            dist = float(np.linalg.norm(d))
+            rho = gamma ** order / dist * rng.uniform(1.0 - jitter, 1.0 + jitter)
+            az = np.arctan2(d[1], d[0]) % (2.0 * np.pi)
+            el = abs(np.arctan2(d[2], np.hypot(d[0], d[1])))
+            paths[i, l] = (rho, az, el)
+    counts = np.full(b, L, np.int32)
+    return (np.ascontiguousarray(paths, dtype=np.float32), counts,
+            np.ascontiguousarray(tx, dtype=np.float32))
