@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "spectra/s at N=100k, 90x360 (batched vs plain); p50/p99 query latency us"
 FLOP_PER_PAIR = 2 * (26 * 256 + 3 * 256 * 256 + 256 * 7)  # MLP per (query, Gaussian) pair
 PEAK = {"bf16": 2500.0, "fp32": 157.3}  # dense TFLOP/s (MFMA bf16; fp32 vector incl. packed)
+FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # FP32 FMA TFLOP/s without packed instructions
 HBM_PEAK_GBS = 8000.0
 # FP32 lane-operations per second without FMA doubling or packing: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -53,6 +54,8 @@ def parse():
     p.add_argument("--width", type=int, default=360)
     p.add_argument("--mlp", choices=("bf16", "fp32"), default="bf16")
     p.add_argument("--plain-queries", type=int, default=16)
+    p.add_argument("--fp32-steps", type=int, default=3,
+                   help="timed batched steps with the FP32 MLP beside the BF16 headline (0: skip)")
     p.add_argument("--pairs-per-wave", type=int, default=0, help="BF16 MLP pairs per wave (48, the default, 32 or 64)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -69,11 +72,14 @@ def parse():
                    help="summarise rocprofv3 counter CSVs (FETCH_SIZE / WRITE_SIZE runs of a --copy-probe-mib run) "
                         "into HBM bytes per launch of the MLP kernel, then exit")
     p.add_argument("--copy-mib", type=int, default=1024, help="copy size used by the counted run (for --pmc-summary)")
-    p.add_argument("--workload", choices=("headline", "large", "train"), default="headline",
+    p.add_argument("--workload", choices=("headline", "large", "train", "beamscan", "rssi", "wrap", "protocol"), default="headline",
                    help="large: N=500k Gaussians (log-scales in [log 0.5, log 20] px), 360x1440 spectra, batch 256; "
                         "BF16 and FP32 MLP; prints its own JSON line (at most 5 timed steps, 1 warm-up). "
                         "train: training steps at N=50k, batch 16, 90x360 (forward with the blend state kept, L1 "
-                        "loss, hand-written backward, Adam on Gaussians and MLP); prints its own JSON line")
+                        "loss, hand-written backward, Adam on Gaussians and MLP); prints its own JSON line. "
+                        "beamscan: beam-scan spectra from multipath lists (batch 256, 90x360). rssi: the RSSI head "
+                        "(16x16, 50 Gaussians, batch 1024). wrap: the headline batch with periodic azimuth. protocol: the "
+                        "paper's training protocol (fine stage) with beam-scan targets")
     return p.parse_args()
 
 
@@ -191,13 +197,29 @@ def add_measured(rec_roof, achieved, peak_measured):
     rec_roof["frac_of_measured"] = achieved / peak_measured if peak_measured else None
 
 
-def cpu_baseline(g, Ws, bs, H, W, txs, budget_s):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(g, Ws, bs, H, W, txs, budget_s, one_thread_spectra=2):
     """The FP64 oracle timed on the host: whole spectra (MLP + brute-force
-    compositing over all Gaussians in depth order) until the budget is used."""
+    compositing over all Gaussians in depth order) until the budget is used,
+    on every host thread, then `one_thread_spectra` whole spectra on one thread
+    (compositor and BLAS both limited to one)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import model as M
     s = M.Scene.from_arrays(g, H, W)
     mlp = M.MLP([w.astype(np.float64) for w in Ws], [b.astype(np.float64) for b in bs])
     pix = M.full_grid(H, W)
+    threads = M.set_threads(0)
+    blas_threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
     t0 = time.perf_counter()
     done = 0
     while True:
@@ -206,9 +228,20 @@ def cpu_baseline(g, Ws, bs, H, W, txs, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    threads = min(threads, os.cpu_count() or threads)
+    one = None
+    if one_thread_spectra > 0:
+        M.set_threads(1)
+        with threadpool_limits(1):
+            t1 = time.perf_counter()
+            for k in range(one_thread_spectra):
+                M.render_query(s, mlp, txs[k % len(txs)].astype(np.float64), pix=pix, margins=None)
+            dt1 = time.perf_counter() - t1
+        M.set_threads(threads)
+        one = {"value": one_thread_spectra / dt1, "unit": "spectra/s", "cores": 1,
+               "sample": f"{one_thread_spectra} full spectra, {dt1:.1f} s"}
     return {"value": done / dt, "unit": "spectra/s", "cores": threads, "kind": "oracle",
+            "blas_threads": blas_threads, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "one_thread": one,
             "sample": f"{done} full {H}x{W} spectra at N={len(g['mean_x'])} (FP64 MLP + brute-force compositing), "
                       f"{dt:.1f} s"}
 
@@ -427,11 +460,11 @@ def bench_large(a):
 
 
 def bench_train(a):
-    """Training steps: N = 50k Gaussians, batch 16 TX positions, 90 x 360; BF16 MLP, FP32 rasterizer."""
+    """Training steps: N = 50k Gaussians, batch 16 TX positions, 90 x 360; BF16 MLP, FP32 rasterizer, L1 loss,
+    hand-written backward, Adam in the library (the hyperparameter table's learning rates)."""
     import torch
     from paper_2506_12787_amd import binding as B
     from paper_2506_12787_amd import synth
-    from paper_2506_12787_amd.autograd import Renderer
 
     N, H, W, Bq = 50_000, 90, 360, 16
     steps, warmup = a.steps, a.warmup
@@ -439,22 +472,36 @@ def bench_train(a):
     g_true = synth.gaussians(N, H, W, seed=4002)
     Ws, bs = synth.mlp_weights(seed=3002)
     ctx = B.Context(0, mlp_pairs_per_wave=a.pairs_per_wave)
-    model = Renderer(g, H, W, mlp=(Ws, bs), lib=ctx)
+    sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
     nbat = warmup + steps
     tx_dev = torch.from_numpy(synth.tx_positions(nbat * Bq, seed=2002)).cuda().view(nbat, Bq, 3)
-    # targets: the separately seeded ground-truth set rendered at the same TX positions (by this library; the
-    # bench does not run the oracle outside its CPU baseline)
+    # targets: the separately seeded ground-truth set rendered at the same TX positions (by this library, whose
+    # renders the parity tests hold to the oracle; the bench does not run the oracle outside its CPU baseline)
     gsid = ctx.upload_scene(g_true, H, W, mlp=(Ws, bs))
     targets = [ctx.render(gsid, tx_dev[i], flags=B.MLP_BF16).clone() for i in range(nbat)]
-    opt = torch.optim.Adam(model.parameters(), lr=1e-3, foreach=True)
+    gp = {k: torch.from_numpy(np.ascontiguousarray(g[k])).cuda() for k in B.PARAMS[:7]}
+    Wd = [torch.from_numpy(w).cuda() for w in Ws]
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+    params = [gp[k] for k in B.PARAMS[:7]] + Wd + bd
+    grads = [torch.zeros_like(t) for t in params]
+    mom = [torch.zeros_like(t) for t in params]
+    vel = [torch.zeros_like(t) for t in params]
+    lrs = [1e-2] * 7 + [8e-3] * (len(Wd) + len(bd))
+    gd = dict(zip(B.PARAMS[:7], grads[:7]))
+    gd["weight"] = grads[7:7 + len(Wd)]
+    gd["bias"] = grads[7 + len(Wd):]
     losses = []
+    count = [0]
 
     def step(i):
-        out = model(tx_dev[i], flags=B.MLP_BF16)
-        loss, grad = ctx.l1_loss(out.detach(), targets[i])
-        out.backward(grad)
-        opt.step()
-        opt.zero_grad(set_to_none=False)
+        out, aux = ctx.render(sid, tx_dev[i], flags=B.MLP_BF16 | B.KEEP_AUX)
+        loss, grad = ctx.l1_loss(out, targets[i])
+        for t in grads:
+            t.zero_()
+        ctx.render_backward(sid, tx_dev[i], B.MLP_BF16, grad, aux, gd)
+        count[0] += 1
+        ctx.adam_step(params, grads, mom, vel, lrs, count[0])
+        ctx.update_scene(sid, gaussians=gp, mlp=(Wd, bd))
         return loss
 
     for i in range(warmup):
@@ -491,8 +538,8 @@ def bench_train(a):
         "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
         "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "training step: N=50000 Gaussians, batch 16 TX positions, 90x360, BF16 MLP "
-                               "89-4x256-7, FP32 rasterizer, L1 loss, hand-written backward, Adam (lr 1e-3) on the "
-                               "Gaussians and the MLP", "n_gaussians": N, "batch": Bq, "height": H, "width": W},
+                               "89-4x256-7, FP32 rasterizer, L1 loss, hand-written backward, Adam (Gaussians 1e-2, "
+                               "MLP 8e-3) in the library", "n_gaussians": N, "batch": Bq, "height": H, "width": W},
         "spectra_per_s": steps * Bq / el,
         "loss_first": lv[0], "loss_last": lv[-1],
         "latency_us": {"step_p50": 1e3 * pct(step_ms, 50), "step_p99": 1e3 * pct(step_ms, 99)},
@@ -505,6 +552,212 @@ def bench_train(a):
                 "positions; stage times from 5 more steps with stage events on (the forward stages count both the "
                 "forward render and the forward pass the backward repeats)",
     }
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+def bench_protocol(a):
+    """The paper's training protocol in its fine stage (Sec. 4.4): N = 50k Gaussians, batch 16 positions, 90 x 360,
+    anneal-smoothed positions, BF16 deformation, hybrid l1 + SSIM loss, frozen canonical positions, Adam (1e-2 /
+    8e-3); targets are beam-scan spectra of multipath lists at the same positions (Sec. 3.1)."""
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+    from paper_2506_12787_amd.train import Trainer
+
+    N, H, W, Bq = 50_000, 90, 360, 16
+    steps, warmup = a.steps, a.warmup
+    ctx = B.Context(0, mlp_pairs_per_wave=a.pairs_per_wave)
+    nbat = warmup + steps
+    paths, counts, txh = synth.multipath(nbat * Bq, seed=6002)
+    tx_all = torch.from_numpy(txh).cuda().view(nbat, Bq, 3)
+    targets = ctx.beamscan(torch.from_numpy(paths).cuda(), torch.from_numpy(counts).cuda(), H, W).view(nbat, Bq, H, W)
+    tr = Trainer(ctx, synth.gaussians(N, H, W, seed=1002), H, W, synth.mlp_weights(seed=3002),
+                 n_positions=nbat * Bq, coarse_iters=2, bf16=True, seed=7)
+    losses = []
+    for i in range(2):  # the coarse stage (static Gaussians), untimed
+        tr.step(tx_all[i % nbat], targets[i % nbat].contiguous())
+    el, ms = _event_time(lambda: losses.append(tr.step(tx_all[len(losses) % nbat],
+                                                       targets[len(losses) % nbat].contiguous())),
+                         steps, warmup)
+    lv = [float(l[0]) for l in losses]
+    rec = {"metric": "training steps/s of the paper's protocol (fine stage), N=50k, batch 16, 90x360",
+           "value": steps / el, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": 1e3 * el / steps, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "training protocol fine stage: N=50000 Gaussians, batch 16 positions, 90x360, "
+                                  "anneal smoothing (gamma 1, tau 10k), BF16 MLP 89-4x256-7, hybrid loss 0.7 l1 + "
+                                  "0.3 (1 - SSIM), frozen canonical positions, Adam 1e-2 / 8e-3; targets: beam-scan "
+                                  "spectra of 25-path multipath lists", "n_gaussians": N, "batch": Bq,
+                      "height": H, "width": W},
+           "spectra_per_s": steps * Bq / el, "loss_first": lv[0], "loss_last": lv[-1],
+           "latency_us": {"step_p50": 1e3 * pct(ms, 50), "step_p99": 1e3 * pct(ms, 99)}}
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+def _event_time(fn, steps, warmup):
+    """Runs fn() warmup times, then times `steps` calls with HIP events on the current stream; returns
+    (elapsed seconds = max(wall, event sum), per-call ms)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return max(wall, sum(ms) / 1e3), ms
+
+
+def bench_beamscan(a):
+    """Beam-scan spectra from multipath lists (Sec. 3.1): a batch of 256 receivers' worth of mirror-image path
+    lists (25 paths: line of sight and wall reflections up to second order), 4 x 4 array at half-wavelength
+    spacing, 90 x 360 spectra."""
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+    H, W, Bq, side = 90, 360, 256, 4
+    paths, counts, _ = synth.multipath(Bq, seed=6003)
+    ctx = B.Context(0)
+    p, c = torch.from_numpy(paths).cuda(), torch.from_numpy(counts).cuda()
+    out = torch.empty((Bq, H, W), device="cuda")
+    el, ms = _event_time(lambda: ctx.beamscan(p, c, H, W, side=side, out=out), a.steps, a.warmup)
+    K = side * side
+    # the contraction of the beam-scan equation: K complex multiply-adds per (pixel, query), 8 FLOP each
+    flop = 8.0 * K * Bq * H * W
+    avg = sum(ms) / len(ms)
+    rec = {"metric": "beam-scan spectra/s (90x360, 4x4 array, 25-path lists, batch 256)", "value": a.steps * Bq / el,
+           "unit": "spectra/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * el / a.steps,
+           "higher_is_better": True, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": "beam-scan spectrum synthesis from mirror-image multipath lists (line of sight + "
+                                  "wall reflections up to order 2, 25 paths) in a 6x6x3 m room, 4x4 array, D = "
+                                  "lambda/2, 90x360 spectra, batch 256", "batch": Bq, "height": H, "width": W,
+                      "array_side": side, "paths": int(paths.shape[1])},
+           "roofline": {"kernel": "beamscan spectrum (channel_kernel + spectrum_kernel)", "bound": "alu",
+                        "achieved": flop / (avg * 1e-3) / 1e12, "peak": FP32_VALU_PEAK, "unit": "TFLOP/s",
+                        "frac": flop / (avg * 1e-3) / 1e12 / FP32_VALU_PEAK, "traffic": None,
+                        "avg_call_ms": avg, "flop_per_call": flop,
+                        "output_GBs": Bq * H * W * 4 / (avg * 1e-3) / 1e9,
+                        "note": "8 K FLOP per (pixel, query): the steering-vector contraction; the per-pixel sincospi "
+                                "(shared by 8 queries) and the per-query FP64 channel are not counted"}}
+    if not a.no_cpu_baseline:
+        from oracle import beamscan as Bs
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < min(a.cpu_seconds, 10.0):
+            Bs.spectrum(paths[n % Bq].astype(np.float64), int(counts[n % Bq]), H, W, side)
+            n += 1
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": n / dt, "unit": "spectra/s", "cores": 1, "kind": "oracle",
+                               "cpu_model": cpu_model(), "sample": f"{n} full spectra (numpy FP64), {dt:.1f} s"}
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+def bench_rssi(a):
+    """RSSI head (Sec. 7.2): 16 x 16 spectra of 50 Gaussians pooled to one value per query, batch 1024."""
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+    H, W, N, Bq = 16, 16, 50, 1024
+    g = synth.gaussians(N, H, W, seed=1005, scale_range=(0.7, 4.0))
+    Ws, bs = synth.mlp_weights(seed=3005)
+    ctx = B.Context(0)
+    sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
+    nb = a.warmup + a.steps
+    tx = torch.from_numpy(synth.tx_positions(nb * Bq, seed=2005)).cuda().view(nb, Bq, 3)
+    it = [0]
+
+    def call(flags):
+        ctx.render_rssi(sid, tx[it[0] % nb], flags=flags)
+        it[0] += 1
+
+    rec = {"metric": "RSSI queries/s (16x16 spectra, 50 Gaussians, batch 1024)", "unit": "queries/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "RSSI head: deformable render of a 16x16 spectrum from 50 Gaussians, global average "
+                                  "pooling, batch 1024 TX positions, MLP 89-4x256-7", "n_gaussians": N, "height": H,
+                      "width": W, "batch": Bq}}
+    for name, flags in (("bf16", B.MLP_BF16), ("fp32", B.MLP_FP32)):
+        ctx.stage_timing(True)
+        ctx.stage_times()
+        el, ms = _event_time(lambda: call(flags), a.steps, a.warmup)
+        st = {k: v[0] / max(v[1], 1) for k, v in ctx.stage_times().items() if v[1] > 0}
+        ctx.stage_timing(False)
+        leg = {"value": a.steps * Bq / el, "ms_per_step": 1e3 * el / a.steps, "p50_ms": pct(ms, 50),
+               "p99_ms": pct(ms, 99), "stages_ms_per_step": st}
+        if name == "bf16":
+            rec.update(value=leg["value"], ms_per_step=leg["ms_per_step"], stages_ms_per_step=st,
+                       latency_us={"batch_p50": 1e3 * leg["p50_ms"], "batch_p99": 1e3 * leg["p99_ms"]})
+            flops = float(FLOP_PER_PAIR) * N * Bq
+            mlp_ms = st.get("mlp_preprocess", 0.0)
+            rec["roofline"] = {"kernel": "mlp_bf16_deform_preprocess", "bound": "mfma",
+                               "achieved": flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms else None, "peak": PEAK["bf16"],
+                               "unit": "TFLOP/s", "traffic": None, "avg_launch_ms": mlp_ms,
+                               "note": "51k pairs per batch: the MLP launch is too small to fill the chip"}
+            if mlp_ms:
+                rec["roofline"]["frac"] = rec["roofline"]["achieved"] / PEAK["bf16"]
+        else:
+            rec["fp32"] = leg
+    if not a.no_cpu_baseline:
+        from oracle import model as M
+        from oracle import rssi as R
+        s = M.Scene.from_arrays(g, H, W)
+        mlp = M.MLP([w.astype(np.float64) for w in Ws], [b.astype(np.float64) for b in bs])
+        txh = tx[0].cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < min(a.cpu_seconds, 10.0):
+            R.rssi_query(s, mlp, txh[n % Bq])
+            n += 1
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": n / dt, "unit": "queries/s", "cores": M.set_threads(0), "kind": "oracle",
+                               "cpu_model": cpu_model(), "sample": f"{n} queries (FP64 MLP + render + pooling), "
+                                                                   f"{dt:.1f} s"}
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+def bench_wrap(a):
+    """The headline batch (N = 100k, 90 x 360, batch 64, BF16) with periodic azimuth: lists by key sorting."""
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+    H, W, N, Bq = 90, 360, 100_000, 64
+    g = synth.gaussians(N, H, W, seed=1003)
+    ctx = B.Context(0)
+    sid = ctx.upload_scene(g, H, W, mlp=synth.mlp_weights(seed=3003))
+    nbat = a.warmup + a.steps
+    tx_dev = torch.from_numpy(synth.tx_positions(nbat * Bq, seed=2003)).cuda().view(nbat, Bq, 3)
+    out = torch.empty((Bq, H, W), device="cuda")
+    rec = {"metric": "spectra/s at N=100k, 90x360, batch 64, periodic azimuth", "unit": "spectra/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "higher_is_better": True, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "batched deformable render with azimuth wrap-around, N=100000, 90x360, batch 64, "
+                                  "BF16 MLP 89-4x256-7", "n_gaussians": N, "height": H, "width": W, "batch": Bq}}
+    for name, flags in (("wrap", B.MLP_BF16 | B.WRAP_AZIMUTH), ("plane", B.MLP_BF16)):
+        el, step_ms, st = timed_renders(ctx, sid, tx_dev, flags, out, a.steps, a.warmup)
+        work = ctx.blend_work()
+        lists_ms = st["scan"] + st["emit_keys"] + st["radix_sort"] + st["tile_ranges"]
+        leg = {"value": a.steps * Bq / el, "ms_per_step": 1e3 * el / a.steps, "stages_ms_per_step": st,
+               "list_entries": work["entries"], "lists_ms": lists_ms}
+        if name == "wrap":
+            pairs = N * Bq
+            nk = work["entries"]
+            # scan 8 B/pair, emit 12 B/pair read + 8 B/key written, 2 radix passes x 16 B/key + ranges 4 B/key
+            lb = pairs * 20 + nk * (8 + 2 * 16 + 4)
+            rec.update(value=leg["value"], ms_per_step=leg["ms_per_step"], stages_ms_per_step=st,
+                       list_entries=nk)
+            rec["roofline"] = {"kernel": "list building (scan, key emission, 2-pass radix sort, ranges)",
+                               "bound": "hbm", "achieved": lb / (lists_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": lb / (lists_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "traffic": None, "algorithmic_bytes": lb, "ms": lists_ms}
+        else:
+            rec["plane"] = leg
     ctx.close()
     print(json.dumps(rec), flush=True)
 
@@ -525,6 +778,9 @@ def main():
         return
     if a.workload == "train":
         bench_train(a)
+        return
+    if a.workload in ("beamscan", "rssi", "wrap", "protocol"):
+        {"beamscan": bench_beamscan, "rssi": bench_rssi, "wrap": bench_wrap, "protocol": bench_protocol}[a.workload](a)
         return
     import torch
     from paper_2506_12787_amd import binding as B
@@ -634,6 +890,24 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if not a.quick and a.mlp == "bf16" and a.fp32_steps > 0:
+        # the same batched render with the FP32 MLP (the paper's arithmetic), so that the batching gain and the
+        # precision gain separate
+        nb32 = min(nbat, a.fp32_steps + 1)
+        el32, step32, st32 = timed_renders(ctx, sid, tx_dev, B.MLP_FP32, out, nb32 - 1, 1)
+        v32 = (nb32 - 1) * Bq / el32
+        mlp32 = st32["mlp_preprocess"]
+        ach32 = flops / (mlp32 * 1e-3) / 1e12
+        rec["fp32_batched"] = {
+            "value": v32, "unit": "spectra/s", "dtype": "fp32", "batch": Bq, "steps": nb32 - 1,
+            "ms_per_step": 1e3 * el32 / (nb32 - 1), "stages_ms_per_step": st32,
+            "roofline": {"kernel": "mlp_fp32_deform_preprocess", "bound": "alu", "achieved": ach32,
+                         "peak": FP32_VALU_PEAK, "unit": "TFLOP/s", "frac": ach32 / FP32_VALU_PEAK,
+                         "peak_packed": PEAK["fp32"], "frac_of_packed": ach32 / PEAK["fp32"],
+                         "avg_launch_ms": mlp32, "flop_per_launch": flops,
+                         "note": "FP32 FMA without packed FP32 instructions (disabled in this build): 256 CUs x 4 "
+                                 "SIMDs x 16 lanes x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s; 157.3 is the packed figure"}}
+        rec["bf16_over_fp32_batched"] = value / v32
     if not a.quick:
         # plain one-query-per-launch FP32 path
         q = a.plain_queries
@@ -654,6 +928,8 @@ def main():
         rec["plain"] = {"value": plain, "unit": "spectra/s", "dtype": "fp32", "batch": 1,
                         "p50_us": pct(lat, 50), "p99_us": pct(lat, 99)}
         rec["batched_over_plain"] = value / plain
+        if "fp32_batched" in rec:
+            rec["fp32_batched_over_plain"] = rec["fp32_batched"]["value"] / plain
         # serving loop on the same scene: captured graphs, continuous batching
         ctx.serve_start(max_batch=Bq, n_slots=2, flags=flags)
         R = a.serve_requests

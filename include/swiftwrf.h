@@ -75,8 +75,14 @@ enum {
                                 instead of eliding the depth digits (same
                                 result; used to check the elision)               */
     SWF_TILE8 = 1 << 4,      /* 8x8 tiles instead of 16x16 (same result)         */
-    SWF_PAPER_DEFORM = 1 << 5/* zero the covariance residuals (outputs 2..4), as
+    SWF_PAPER_DEFORM = 1 << 5,/* zero the covariance residuals (outputs 2..4), as
                                 the paper does not deform the covariance         */
+    SWF_WRAP_AZIMUTH = 1 << 6 /* periodic azimuth: columns 0 and W-1 are
+                                neighbours (0 and 360 degrees are one direction,
+                                Sec. 3.1 spectrum grid); a Gaussian acts at each
+                                pixel through the image of its mean (shifted by a
+                                whole number of grid widths) nearest to it. Lists
+                                are built by key sorting (no binning)             */
 };
 
 typedef struct swf_ctx swf_ctx;
@@ -183,11 +189,153 @@ swf_status swf_render(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t b
 swf_status swf_render_backward(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags,
                                const float *grad_out, const void *aux, const swf_grads *grads, void *stream);
 
+/* Hybrid loss of the training objective (paper Sec. 4.4, hybrid-loss
+ * equation): loss = lambda1 * mean |pred - target| + (1 - lambda1) *
+ * (1 - SSIM(pred, target)), with lambda1 = 0.7 in the paper's hyperparameter
+ * table. pred, target: device float32 [batch][height][width] spectra. SSIM
+ * (parameters not given by the paper; the common reading): an 11 x 11
+ * Gaussian window of standard deviation 1.5 normalised to sum 1, local means,
+ * variances and covariance by window sums with zero padding outside the grid,
+ * C1 = 0.01^2, C2 = 0.03^2 (data range 1), the map averaged over every pixel
+ * of every spectrum. Window sums and the map are formed in FP64.
+ * loss: device float32 [3] <- (total, mean l1, mean SSIM). grad (device, may be
+ * NULL) <- d loss / d pred, float32 like pred. SWF_E_INVALID (nothing enqueued)
+ * for batch outside [1, 65535], height or width outside [1, 4096], lambda1
+ * outside [0, 1] or a NULL pred / target / loss. Deterministic (fixed-order
+ * reductions). Enqueued on `stream`; scratch 12 bytes per pixel. */
+swf_status swf_hybrid_loss(swf_ctx *ctx, const float *pred, const float *target, int32_t batch, int32_t height,
+                           int32_t width, float lambda1, float *loss, float *grad, void *stream);
+
+/* Adam update of up to 32 parameter tensors in one launch (the optimiser of
+ * the paper's training protocol, Sec. 4.4, at the hyperparameter table's
+ * learning rates: Gaussians 1e-2, MLP 8e-3). For tensor k (count of them;
+ * params[k], grads[k], m[k], v[k] device float32 arrays of sizes[k] elements;
+ * the five arrays of pointers, sizes and lrs are host arrays):
+ * m = beta1 m + (1 - beta1) g, v = beta2 v + (1 - beta2) g^2,
+ * p -= lrs[k] (m / (1 - beta1^step)) / (sqrt(v) / sqrt(1 - beta2^step) + eps),
+ * in place. step >= 1 is the update's number (bias correction). Moments start
+ * at zero (the caller clears them). SWF_E_INVALID for count outside [0, 32],
+ * step < 1, betas outside [0, 1), eps <= 0 or a NULL entry. Enqueued on
+ * `stream`. */
+swf_status swf_adam_step(swf_ctx *ctx, float *const *params, const float *const *grads, float *const *m,
+                         float *const *v, const int64_t *sizes, const float *lrs, int32_t count, float beta1,
+                         float beta2, float eps, int32_t step, void *stream);
+
+/* Anneal smoothing of the moving positions (paper Sec. 4.4, anneal-smoothing
+ * equations): tx_out = tx + gamma * noise * (2 / cbrt(n_positions)) *
+ * max(0, 1 - iter / tau) * (room_hi - room_lo), i.e. the paper's perturbation
+ * of the position in the unit cube the positions are normalised to, expressed
+ * in metres; the decay is clamped at zero from tau on. tx, noise, tx_out:
+ * device float32 [batch][3]; noise holds standard normal draws (the caller's
+ * random numbers). room_lo, room_hi: host float[3]. The paper uses gamma = 1
+ * and tau = 10,000. SWF_E_INVALID for batch < 1, tau < 1, n_positions < 1,
+ * iter < 0, a non-finite gamma or a NULL pointer. Enqueued on `stream`. */
+swf_status swf_anneal_tx(swf_ctx *ctx, const float *tx, const float *noise, int32_t batch, int32_t iter, float gamma,
+                         int32_t tau, int32_t n_positions, const float *room_lo, const float *room_hi, float *tx_out,
+                         void *stream);
+
 /* L1 loss (paper Sec. 4.4, the l1 term): loss = mean |pred - target| over n
  * values, written to *loss (device float32); grad (device, may be NULL)
  * receives sign(pred - target) / n with sign(0) = 0. */
 swf_status swf_l1_loss(swf_ctx *ctx, const float *pred, const float *target, int64_t n, float *loss, float *grad,
                        void *stream);
+
+/* ---- the paper's own spectrum model -------------------------------------------
+ * The model as the paper writes it (Sec. 4.1, 4.2, 6.1): a Gaussian n has a raw
+ * centre (c_x, c_y) mapped by the hyperbolic normalisation to pixel units,
+ * x = (W / 2)(tanh(c_x) + 1), y = (H / 2)(tanh(c_y) + 1) (azimuth onto the
+ * grid's columns, elevation onto its rows); a covariance Sigma = L L^T from its
+ * Cholesky factor L = [[l1, 0], [l2, l3]] (pixels); an attenuation gate
+ * delta = sigmoid(atten_logit); and a complex response psi = (psi_re, psi_im).
+ * The spectrum is the order-free GMM sum A(p) = | sum_n psi_n delta_n
+ * exp(-q_n(p) / 2) | over the Gaussians with q_n(p) = d^T Sigma^-1 d <= 9 (the
+ * 3-sigma support the tiles are built from): no depth, no opacity clamp, no
+ * termination. With an MLP the Gaussians are deformed per position s: the MLP
+ * maps [gamma(mu_hat) (10 bands, 42) | gamma(s_hat) (6 bands, 39)] through eight
+ * ReLU layers of 156 units, the input concatenated after the hidden state
+ * entering layers 3, 5 and 7 (skip connections every two layers), to the
+ * residuals (d_mu_x, d_mu_y, d_psi_re, d_psi_im, d_delta): centre + d_mu (pixels),
+ * psi + d_psi, delta = sigmoid(atten_logit) + d_delta; the covariance is not
+ * deformed. FP32 throughout (the paper's precision), forward only. */
+typedef struct {
+    int32_t n;
+    const float *center_x, *center_y;           /* raw centres (before the tanh map)      */
+    const float *chol_l1, *chol_l2, *chol_l3;   /* Cholesky factor of Sigma, pixels        */
+    const float *atten_logit;                   /* delta = sigmoid(atten_logit)            */
+    const float *psi_re, *psi_im;               /* complex response                        */
+} swf_paper_gaussians;
+typedef struct {
+    /* row-major (out, in): 156 x 81, 156 x 156, 156 x 237, 156 x 156, 156 x 237,
+       156 x 156, 156 x 237, 156 x 156, then the output layer 5 x 156; inputs of
+       layers 3, 5, 7 are [h (156) | x (81)] */
+    const float *weight[9];
+    const float *bias[9];
+    float room_lo[3], room_hi[3]; /* s_hat = (s - room_lo) / (room_hi - room_lo) */
+} swf_paper_mlp;
+/* Uploads a paper-model scene (copies; n Gaussians in id order; mlp may be NULL
+ * for static renders only). A Gaussian with l1 l3 = 0 or a non-finite parameter
+ * takes no part (culled). Errors as swf_scene_upload. */
+swf_status swf_scene_upload_paper(swf_ctx *ctx, const swf_paper_gaussians *g, const swf_paper_mlp *mlp,
+                                  int32_t height, int32_t width, int32_t src_is_device, int32_t *scene_id);
+/* Renders a paper-model scene: out [batch][H][W] = |sum| (device, caller-owned);
+ * channels (device, may be NULL) [batch][2][H][W] = the real and imaginary sums.
+ * flags: SWF_MLP_FP32 (deformable, tx required) or SWF_NO_DEFORM, optionally
+ * SWF_FULL_SORT and SWF_WRAP_AZIMUTH; SWF_MLP_BF16, SWF_TILE8 and SWF_KEEP_AUX
+ * are SWF_E_INVALID (as is the render backward and swf_scene_update on such a
+ * scene). swf_render on a paper-model scene renders the magnitude only. Lists,
+ * status word, stream semantics and errors otherwise as swf_render. */
+swf_status swf_render_paper(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags, float *out,
+                            float *channels, void *stream);
+
+/* ---- RSSI head --------------------------------------------------------------
+ * The RSSI case study (paper Sec. 7.2): the rendered spectrum map is reduced by
+ * global average pooling to one received-signal-strength value per query,
+ * rssi[b] = (1 / (H W)) sum over the H x W pixels of spectrum b (the paper uses
+ * a 16 x 16 spectrum of 50 Gaussians for this head). Renders like swf_render
+ * (same scene, tx, batch, flags and aux semantics) into `out` when it is not
+ * NULL (B x H x W, caller-owned) or into context scratch otherwise, then pools
+ * with an FP64 sum per query in a fixed order (deterministic, independent of
+ * the batch). rssi: device float32 [batch], caller-owned. Errors as
+ * swf_render, plus SWF_E_INVALID for a NULL rssi. Enqueued on `stream`. */
+swf_status swf_render_rssi(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags,
+                           float *rssi, float *out, void *aux, void *stream);
+/* Backward of swf_render_rssi: the gradient of sum(grad_rssi * rssi), i.e.
+ * swf_render_backward with grad_out[b][y][x] = grad_rssi[b] / (H W) (formed on
+ * the device in context scratch). grad_rssi: device float32 [batch]. aux, flags
+ * and the other arguments as in swf_render_backward, for the swf_render_rssi
+ * call (with SWF_KEEP_AUX) that filled aux. */
+swf_status swf_render_rssi_backward(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags,
+                                    const float *grad_rssi, const void *aux, const swf_grads *grads, void *stream);
+
+/* ---- beam-scan spectrum from multipath lists -------------------------------
+ * The spatial spectrum a receiver's sqrt(K) x sqrt(K) planar array measures by
+ * beam scanning (paper Sec. 3.1: element positions, the path-length and phase
+ * differences, the received-signal equation h_mn = sum_l rho_l
+ * exp(j dalpha_mn(theta_l, phi_l)), and the beam-scan equation A(theta, phi) =
+ * |(1/K) sum_mn exp(-j dalpha_mn(theta, phi)) exp(j angle h_mn)|). A physically
+ * shaped target for the renderer.
+ *  paths   device float32 [batch][max_paths][3]: (rho, azimuth theta in
+ *          radians, elevation phi in radians) per path; slots past a query's
+ *          count are not read. May be NULL when max_paths is 0.
+ *  counts  device int32 [batch]: paths per query; a count outside
+ *          [0, max_paths] is clamped into it. A query with no paths (or an
+ *          element whose channel is exactly zero, whose angle is undefined)
+ *          contributes zero.
+ *  side    sqrt(K), 1..8; element (m, n) at radius D sqrt((m-1)^2 + (n-1)^2)
+ *          and angle atan2(m-1, n-1); spacing_over_lambda = D / lambda > 0.
+ *  out     device float32 [batch][height][width], caller-owned; row y =
+ *          elevation phi = (pi/2) y / height, column x = azimuth
+ *          theta = 2 pi x / width (1 degree per pixel at 90 x 360).
+ * The per-element channel is formed in FP64, the per-pixel sum in FP32.
+ * SWF_E_INVALID (nothing enqueued) for batch outside [1, 65535], side outside
+ * [1, 8], max_paths < 0, a non-positive or non-finite spacing, height or
+ * width outside [1, 4096], or a NULL counts / out (or paths with
+ * max_paths > 0). Enqueued on `stream`; the context's scratch holds
+ * batch * K * 8 bytes. Non-finite path values give non-finite outputs for
+ * that query. */
+swf_status swf_beamscan(swf_ctx *ctx, const float *paths, const int32_t *counts, int32_t batch, int32_t max_paths,
+                        int32_t side, float spacing_over_lambda, int32_t height, int32_t width, float *out,
+                        void *stream);
 
 /* ---- device status of the last render --------------------------------------
  * What the device saw during the last swf_render (or the forward pass of the

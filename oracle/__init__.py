@@ -7,3 +7,7 @@ with the HIP library. See model.py for what each function follows in the paper.
 from . import model  # noqa: F401
 from . import grad  # noqa: F401
 from . import beamscan  # noqa: F401
+from . import rssi  # noqa: F401
+from . import ssim  # noqa: F401
+from . import train  # noqa: F401
+from . import paper  # noqa: F401

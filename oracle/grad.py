@@ -22,7 +22,7 @@ def _pixel_weights(C, target, count):
     return np.sign(C - target) / float(count)
 
 
-def raster_grad(rg: dict, order, pix, w, flags_out=None, abs_out=None):
+def raster_grad(rg: dict, order, pix, w, flags_out=None, abs_out=None, period: float = 0.0):
     """d(sum_p w_p C_p) / d(mx, my, ixx, ixy, iyy, opacity, amp) per Gaussian.
     flags_out (int8 array of n), if given, receives the near-threshold marks;
     abs_out ((n, 7) float64), if given, the magnitude sums of the terms (the
@@ -34,7 +34,7 @@ def raster_grad(rg: dict, order, pix, w, flags_out=None, abs_out=None):
     px = np.ascontiguousarray(pix[0], np.int32)
     py = np.ascontiguousarray(pix[1], np.int32)
     w = np.ascontiguousarray(w, np.float64)
-    consts = np.array([M.ALPHA_MAX, M.ALPHA_MIN, M.T_MIN, M.Q_MAX], np.float64)
+    consts = np.array([M.ALPHA_MAX, M.ALPHA_MIN, M.T_MIN, M.Q_MAX, float(period)], np.float64)
     P = M._ptr
     marg = np.array(M.DEFAULT_MARGINS, np.float64)
     lib.oracle_grad(n, P(rg["mx"]), P(rg["my"]), P(rg["ixx"]), P(rg["ixy"]), P(rg["iyy"]), P(rg["op"]),
@@ -171,7 +171,7 @@ def posenc_backward_abs(v, L, dabs):
 
 
 def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAULT_ROOM, stop_grad_pos=False,
-                  pixel_weights=None, bf16=False, deltas=None, bounds=False):
+                  pixel_weights=None, bf16=False, deltas=None, bounds=False, wrap=False):
     """L1 loss over a batch of queries and its FP64 gradient.
 
     Returns (loss, grads) where grads has 'base' (n, 7) for
@@ -188,7 +188,8 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
     compositing-and-covariance part, 'pe_abs' (n, 2) of the mean features' part
     through the network, 'W_abs' / 'b_abs' of the network's gradients (each the
     absolute-value chain of the same computation), and 'replay' = the largest
-    number of Gaussians composited at a weighted pixel."""
+    number of Gaussians composited at a weighted pixel. wrap: periodic azimuth
+    (period W, nearest image of each mean)."""
     B = len(txs)
     H, W = scene.H, scene.W
     count = B * H * W
@@ -205,6 +206,7 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
         b_abs = [np.zeros_like(b) for b in mlp.b] if mlp is not None else None
         replay = 0
     loss = 0.0
+    period = float(W) if wrap else 0.0
     xm = M.posenc(M.normalize_mean(scene.mx, scene.my, H, W), M.MEAN_BANDS) if mlp is not None else None
     for b in range(B):
         if deltas is not None:
@@ -216,17 +218,17 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
         if pixel_weights is not None:
             w = np.asarray(pixel_weights[b], np.float64).ravel()
             sel = np.nonzero(w)[0]
-            res = M.composite(rg, order, pix[0][sel], pix[1][sel], margins=None)
+            res = M.composite(rg, order, pix[0][sel], pix[1][sel], margins=None, period=period)
             loss += float((w[sel] * res.C).sum())
         else:
-            res = M.composite(rg, order, pix[0], pix[1], margins=None)
+            res = M.composite(rg, order, pix[0], pix[1], margins=None, period=period)
             t = np.asarray(targets[b], np.float64).ravel()
             loss += np.abs(res.C - t).sum() / count
             w = _pixel_weights(res.C, t, count)
             sel = np.nonzero(w)[0]
         fl = np.zeros(scene.n, np.int8)
         ga = np.zeros((scene.n, 7)) if bounds else None
-        gr = raster_grad(rg, order, pix, w, fl, ga)
+        gr = raster_grad(rg, order, pix, w, fl, ga, period=period)
         gflag |= fl
         gp = chain_to_params(g, rg, gr)
         gbase += gp

@@ -72,10 +72,17 @@ def _raster():
         lib.oracle_grad.argtypes = [ctypes.c_int64] + [P] * 11 + [ctypes.c_int64] + [P] * 6
         lib.oracle_grad.restype = None
         lib.oracle_max_leaves.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = ctypes.c_int
         lib.oracle_render_held.argtypes = [ctypes.c_int64] + [P] * 16 + [ctypes.c_int64] + [P] * 3
         lib.oracle_render_held.restype = None
         _lib = lib
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Set the compositor's OpenMP thread count (n <= 0 leaves it); returns the count in effect."""
+    return int(_raster().oracle_set_threads(int(n)))
 
 
 def _ptr(a):
@@ -302,8 +309,10 @@ def full_grid(H: int, W: int):
 
 
 def composite(rg: dict, order: np.ndarray, pix_x: np.ndarray, pix_y: np.ndarray,
-              margins=DEFAULT_MARGINS) -> RenderResult:
-    """FP64 brute-force compositing of the listed pixels (see raster.c)."""
+              margins=DEFAULT_MARGINS, period: float = 0.0) -> RenderResult:
+    """FP64 brute-force compositing of the listed pixels (see raster.c). period:
+    the grid width W when azimuth wraps around (nearest image of each mean), 0
+    for a plain plane."""
     lib = _raster()
     n = len(rg["mx"])
     npix = len(pix_x)
@@ -311,7 +320,7 @@ def composite(rg: dict, order: np.ndarray, pix_x: np.ndarray, pix_y: np.ndarray,
     order = np.ascontiguousarray(order, np.int64)
     px = np.ascontiguousarray(pix_x, np.int32)
     py = np.ascontiguousarray(pix_y, np.int32)
-    consts = np.array([ALPHA_MAX, ALPHA_MIN, T_MIN, Q_MAX], np.float64)
+    consts = np.array([ALPHA_MAX, ALPHA_MIN, T_MIN, Q_MAX, float(period)], np.float64)
     marg = None if margins is None else np.array(margins, np.float64)
     C = np.zeros(npix); T = np.zeros(npix)
     nc = np.zeros(npix, np.int64); last = np.zeros(npix, np.int64)
@@ -326,7 +335,8 @@ def composite(rg: dict, order: np.ndarray, pix_x: np.ndarray, pix_y: np.ndarray,
     return RenderResult(C, T, nc, last, sig, mono, nflags, leaves, nleaves, bound, overflow)
 
 
-def composite_held(rg0: dict, rg: dict, order: np.ndarray, pix_x: np.ndarray, pix_y: np.ndarray) -> np.ndarray:
+def composite_held(rg0: dict, rg: dict, order: np.ndarray, pix_x: np.ndarray, pix_y: np.ndarray,
+                   period: float = 0.0) -> np.ndarray:
     """Composite with every decision taken on rg0 and every value on rg (see
     oracle_render_held in raster.c). Returns C per listed pixel."""
     lib = _raster()
@@ -334,7 +344,7 @@ def composite_held(rg0: dict, rg: dict, order: np.ndarray, pix_x: np.ndarray, pi
     order = np.ascontiguousarray(order, np.int64)
     px = np.ascontiguousarray(pix_x, np.int32)
     py = np.ascontiguousarray(pix_y, np.int32)
-    consts = np.array([ALPHA_MAX, ALPHA_MIN, T_MIN, Q_MAX], np.float64)
+    consts = np.array([ALPHA_MAX, ALPHA_MIN, T_MIN, Q_MAX, float(period)], np.float64)
     C = np.zeros(len(px))
     a0 = [np.ascontiguousarray(rg0[k], np.float64) for k in ("mx", "my", "ixx", "ixy", "iyy", "op")]
     a1 = [np.ascontiguousarray(rg[k], np.float64) for k in ("mx", "my", "ixx", "ixy", "iyy", "op", "amp")]
@@ -344,8 +354,10 @@ def composite_held(rg0: dict, rg: dict, order: np.ndarray, pix_x: np.ndarray, pi
 
 
 def render_query(scene: Scene, mlp: MLP | None, tx, room=DEFAULT_ROOM, pix=None, margins=DEFAULT_MARGINS,
-                 bf16=False, delta=None):
-    """Render one spectrum (the listed pixels, default the full H x W grid)."""
+                 bf16=False, delta=None, wrap=False):
+    """Render one spectrum (the listed pixels, default the full H x W grid).
+    wrap: azimuth is periodic with period W (each Gaussian acts through the
+    image of its mean nearest to the pixel)."""
     if delta is None:
         delta = deltas(scene, mlp, tx, room, bf16=bf16) if mlp is not None else None
     g = deform(scene, delta)
@@ -353,42 +365,58 @@ def render_query(scene: Scene, mlp: MLP | None, tx, room=DEFAULT_ROOM, pix=None,
     order = depth_order(scene.depth)
     if pix is None:
         pix = full_grid(scene.H, scene.W)
-    res = composite(rg, order, pix[0], pix[1], margins)
+    res = composite(rg, order, pix[0], pix[1], margins, period=scene.W if wrap else 0.0)
     return res, g, rg, delta
 
 
 # ---------------------------------------------------------------------------
 # Tile binning and keys (gsplat-style tile lists; Sec. 4.1 tile partitioning)
 # ---------------------------------------------------------------------------
-def _rect_at(mx, my, hx, hy, H, W, tile):
+def _rect_at(mx, my, hx, hy, H, W, tile, wrap=False):
     TW, TH = -(-W // tile), -(-H // tile)
     x0, x1, y0, y1 = mx - hx, mx + hx, my - hy, my + hy
-    culled = (x1 < 0) | (x0 > W - 1) | (y1 < 0) | (y0 > H - 1)
-    tx0 = np.clip(np.floor(x0 / tile), 0, TW - 1).astype(np.int64)
-    tx1 = np.clip(np.floor(x1 / tile), 0, TW - 1).astype(np.int64)
-    ty0 = np.clip(np.floor(y0 / tile), 0, TH - 1).astype(np.int64)
-    ty1 = np.clip(np.floor(y1 / tile), 0, TH - 1).astype(np.int64)
-    bad = ~(np.isfinite(x0) & np.isfinite(x1) & np.isfinite(y0) & np.isfinite(y1))
-    culled = culled | bad
-    r = np.stack([tx0, ty0, tx1, ty1], axis=-1)
-    r[culled] = -1
+    with np.errstate(invalid="ignore"):
+        culled = (y1 < 0) | (y0 > H - 1)
+        if not wrap:
+            culled = culled | (x1 < 0) | (x0 > W - 1)
+            tx0 = np.clip(np.floor(x0 / tile), 0, TW - 1)
+            tx1 = np.clip(np.floor(x1 / tile), 0, TW - 1)
+        else:
+            # periodic azimuth: the box's columns taken modulo W. Folded so that
+            # its left edge lies in [0, W); a box whose right edge then passes W
+            # continues at column 0 (encoded as tx1 < tx0); a box at least W wide,
+            # or whose two pieces meet, covers every column.
+            k = np.floor(x0 / W)
+            a, b = x0 - k * W, x1 - k * W
+            tx0 = np.minimum(np.floor(a / tile), TW - 1)
+            tx1 = np.where(b < W, np.minimum(np.floor(b / tile), TW - 1), np.floor((b - W) / tile))
+            full = (x1 - x0 >= W) | ((b >= W) & (tx1 >= tx0 - 1))
+            tx0 = np.where(full, 0, tx0)
+            tx1 = np.where(full, TW - 1, tx1)
+        ty0 = np.clip(np.floor(y0 / tile), 0, TH - 1)
+        ty1 = np.clip(np.floor(y1 / tile), 0, TH - 1)
+        bad = ~(np.isfinite(x0) & np.isfinite(x1) & np.isfinite(y0) & np.isfinite(y1))
+        culled = culled | bad
+        r = np.stack([np.where(culled, -1, v) for v in (tx0, ty0, tx1, ty1)], axis=-1).astype(np.int64)
     return r
 
 
-def tile_rects(g: dict, rg: dict, H: int, W: int, tile: int = 16, rel_margin: float = 2.0 ** -19):
+def tile_rects(g: dict, rg: dict, H: int, W: int, tile: int = 16, rel_margin: float = 2.0 ** -19, wrap=False):
     """Tile rectangle [tx0, tx1] x [ty0, ty1] of every Gaussian (-1 if culled).
 
     The half extents are 3 sqrt(Sigma_xx) + eps and 3 sqrt(Sigma_yy) + eps (the
     bounding box of the q <= 9 ellipse plus a small binning margin). A Gaussian
     whose box misses [0, W-1] x [0, H-1] is culled. Returns (rect, flagged, alts)
     where a Gaussian is flagged if moving any of its four box edges by the FP32
-    margin could change its rectangle; alts[i] lists every such rectangle."""
+    margin could change its rectangle; alts[i] lists every such rectangle.
+    wrap: periodic azimuth (see _rect_at); a wrapped rectangle has tx1 < tx0 and
+    covers columns tx0 .. TW-1 and 0 .. tx1."""
     live = rg["live"].astype(bool)
     with np.errstate(invalid="ignore"):
         hx = 3.0 * np.sqrt(np.where(live, rg["sxx"], 0.0)) + EXTENT_EPS
         hy = 3.0 * np.sqrt(np.where(live, rg["syy"], 0.0)) + EXTENT_EPS
     mx, my = g["mx"], g["my"]
-    rect = _rect_at(mx, my, hx, hy, H, W, tile)
+    rect = _rect_at(mx, my, hx, hy, H, W, tile, wrap)
     rect[~live] = -1
     mxm = rel_margin * (np.abs(mx) + hx + tile)
     mym = rel_margin * (np.abs(my) + hy + tile)
@@ -403,7 +431,7 @@ def tile_rects(g: dict, rg: dict, H: int, W: int, tile: int = 16, rel_margin: fl
                     y0 = my - hy + sy0 * mym
                     y1 = my + hy + sy1 * mym
                     cx, cy = 0.5 * (x0 + x1), 0.5 * (y0 + y1)
-                    r = _rect_at(cx, cy, 0.5 * (x1 - x0), 0.5 * (y1 - y0), H, W, tile)
+                    r = _rect_at(cx, cy, 0.5 * (x1 - x0), 0.5 * (y1 - y0), H, W, tile, wrap)
                     r[~live] = -1
                     alts_all.append(r)
     A = np.stack(alts_all, axis=1)  # (n, 16, 4)
@@ -414,8 +442,13 @@ def tile_rects(g: dict, rg: dict, H: int, W: int, tile: int = 16, rel_margin: fl
     return rect, flagged, alts
 
 
-def rect_count(rect: np.ndarray) -> np.ndarray:
-    c = (rect[:, 2] - rect[:, 0] + 1) * (rect[:, 3] - rect[:, 1] + 1)
+def rect_count(rect: np.ndarray, TW: int | None = None) -> np.ndarray:
+    """Tiles per rectangle (0 if culled); a wrapped one (tx1 < tx0, periodic
+    azimuth) spans TW - tx0 + tx1 + 1 columns."""
+    w = rect[:, 2] - rect[:, 0] + 1
+    if TW is not None:
+        w = np.where(rect[:, 2] < rect[:, 0], TW - rect[:, 0] + rect[:, 2] + 1, w)
+    c = w * (rect[:, 3] - rect[:, 1] + 1)
     return np.where(rect[:, 0] < 0, 0, c).astype(np.int64)
 
 
@@ -423,7 +456,8 @@ def key_list(rect: np.ndarray, depth: np.ndarray, H: int, W: int, tile: int = 16
              tile_base: int = 0):
     """Sorted (gtile, depth_bits, id) triples of one query, plus per-tile ranges.
 
-    Every Gaussian emits one entry per tile of its rectangle, with
+    Every Gaussian emits one entry per tile of its rectangle (a wrapped one,
+    tx1 < tx0, covers columns tx0 .. TW-1 and 0 .. tx1), with
     gtile = tile_base + ty * TW + tx. Sorting by (gtile, depth_bits, id) gives the
     per-tile front-to-back lists."""
     TW, TH = -(-W // tile), -(-H // tile)
@@ -433,8 +467,9 @@ def key_list(rect: np.ndarray, depth: np.ndarray, H: int, W: int, tile: int = 16
         tx0, ty0, tx1, ty1 = rect[i]
         if tx0 < 0:
             continue
+        cols = range(tx0, tx1 + 1) if tx1 >= tx0 else list(range(tx0, TW)) + list(range(0, tx1 + 1))
         for ty in range(ty0, ty1 + 1):
-            for tx in range(tx0, tx1 + 1):
+            for tx in cols:
                 gt.append(tile_base + ty * TW + tx)
                 dk.append(db[i])
                 ids.append(i)

@@ -21,6 +21,11 @@
  * The thresholds are the FP32 constants 0.99f, 1.0f/255.0f and 1e-4f, widened
  * to FP64 by the caller. Every Gaussian is visited (no binning, no tiles).
  *
+ * Azimuth wrap (optional, consts[4] = the grid width W in pixels, 0 = off):
+ * azimuth is periodic (0 and 360 degrees are one direction), so the
+ * horizontal displacement is taken to the nearest image of the mean,
+ * dx = (x - mx) - W round((x - mx) / W).
+ *
  * Decision ambiguity. FP32 and FP64 can disagree on a discrete decision whose
  * FP64 quantity lies very close to its threshold. Each such decision (q vs 9,
  * alpha vs 1/255, T' vs 1e-4, within a relative margin) is "flagged", and the
@@ -36,6 +41,7 @@
  *   alpha_i = opacity_i exp(-q_i/2)   (zero derivative where the 0.99 clamp holds)
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -50,6 +56,7 @@ typedef struct {
     const int8_t *live;             /* 0: culled (non-finite or det <= 0)    */
     const int64_t *order;           /* ascending (depth, id)                  */
     double amax, amin, tmin, qmax;  /* 0.99f, 1/255.f, 1e-4f, 9               */
+    double period;                  /* azimuth period W (0: no wrap)          */
     double mq, ma, mt;              /* relative flag margins                  */
     double ampmax;                  /* max |amp| over live Gaussians          */
 } scene_t;
@@ -60,6 +67,14 @@ typedef struct {
     int overflow;  /* number of flagged decisions that were not forked */
     double bound;  /* extra tolerance covering the unforked decisions  */
 } leaves_t;
+
+/* Horizontal displacement of pixel column px from a mean: with a period
+ * (azimuth wrap) the nearest image of the mean. */
+static double disp_x(double px, double mx, double period)
+{
+    const double d = px - mx;
+    return period > 0.0 ? d - period * nearbyint(d / period) : d;
+}
 
 static int near_threshold(double v, double thr, double rel)
 {
@@ -78,7 +93,7 @@ static double walk(const scene_t *s, double px, double py, int64_t k0, int nfix,
         const int64_t g = s->order[k];
         if (!s->live[g]) continue;
         const int nf = (k == k0) ? nfix : 0;
-        const double dx = px - s->mx[g], dy = py - s->my[g];
+        const double dx = disp_x(px, s->mx[g], s->period), dy = py - s->my[g];
         const double q = s->ixx[g] * dx * dx + 2.0 * s->ixy[g] * dx * dy + s->iyy[g] * dy * dy;
 
         /* decision 0: inside the 3-sigma ellipse */
@@ -155,7 +170,7 @@ static double primary(const scene_t *s, double px, double py, double *T_out, int
     for (int64_t k = 0; k < s->n; ++k) {
         const int64_t g = s->order[k];
         if (!s->live[g]) continue;
-        const double dx = px - s->mx[g], dy = py - s->my[g];
+        const double dx = disp_x(px, s->mx[g], s->period), dy = py - s->my[g];
         const double q = s->ixx[g] * dx * dx + 2.0 * s->ixy[g] * dx * dy + s->iyy[g] * dy * dy;
         if (!(q <= s->qmax)) continue;
         double a = s->op[g] * exp(-0.5 * q);
@@ -191,6 +206,7 @@ static void fill_scene(scene_t *s, int64_t n, const double *mx, const double *my
     s->n = n; s->mx = mx; s->my = my; s->ixx = ixx; s->ixy = ixy; s->iyy = iyy;
     s->op = op; s->amp = amp; s->live = live; s->order = order;
     s->amax = consts[0]; s->amin = consts[1]; s->tmin = consts[2]; s->qmax = consts[3];
+    s->period = consts[4];
     s->mq = margins ? margins[0] : 0.0;
     s->ma = margins ? margins[1] : 0.0;
     s->mt = margins ? margins[2] : 0.0;
@@ -281,7 +297,7 @@ void oracle_grad(int64_t n, const double *mx, const double *my, const double *ix
             for (int64_t k = 0; k < s.n; ++k) {
                 const int64_t g = s.order[k];
                 if (!s.live[g]) continue;
-                const double dx = px - s.mx[g], dy = py - s.my[g];
+                const double dx = disp_x(px, s.mx[g], s.period), dy = py - s.my[g];
                 const double q = s.ixx[g] * dx * dx + 2.0 * s.ixy[g] * dx * dy + s.iyy[g] * dy * dy;
                 /* a Gaussian whose cutoff or skip decision at a weighted pixel lies
                  * within the margin of its threshold is marked: its gradient may
@@ -316,7 +332,7 @@ void oracle_grad(int64_t n, const double *mx, const double *my, const double *ix
                 G[6] += w[p] * dC_damp;
                 if (GA) GA[6] += aw * dC_damp;
                 if (cc[i]) continue;
-                const double dx = px - s.mx[g], dy = py - s.my[g];
+                const double dx = disp_x(px, s.mx[g], s.period), dy = py - s.my[g];
                 const double q = s.ixx[g] * dx * dx + 2.0 * s.ixy[g] * dx * dy + s.iyy[g] * dy * dy;
                 const double Gk = exp(-0.5 * q);
                 const double dC_dop = dC_da * Gk;
@@ -351,6 +367,14 @@ void oracle_grad(int64_t n, const double *mx, const double *my, const double *ix
 
 int oracle_max_leaves(void) { return ORACLE_MAX_LEAVES; }
 
+/* Thread count of the OpenMP loops above (timing of the oracle on a given
+ * number of host cores); returns the count in effect afterwards. */
+int oracle_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
+
 /* Composite the listed pixels with every discrete decision taken from a base
  * scene and every value from a second one (same Gaussians, same order): the
  * 3-sigma cutoff, the alpha skip, the 0.99 clamp state and the transmittance
@@ -367,7 +391,7 @@ void oracle_render_held(int64_t n, const double *mx0, const double *my0, const d
                         const double *amp, const int8_t *live, const int64_t *order, const double *consts,
                         int64_t npix, const int32_t *pix_x, const int32_t *pix_y, double *C_out)
 {
-    const double amax = consts[0], amin = consts[1], tmin = consts[2], qmax = consts[3];
+    const double amax = consts[0], amin = consts[1], tmin = consts[2], qmax = consts[3], period = consts[4];
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t p = 0; p < npix; ++p) {
         const double px = (double)pix_x[p], py = (double)pix_y[p];
@@ -375,7 +399,7 @@ void oracle_render_held(int64_t n, const double *mx0, const double *my0, const d
         for (int64_t k = 0; k < n; ++k) {
             const int64_t g = order[k];
             if (!live[g]) continue;
-            const double ex = px - mx0[g], ey = py - my0[g];
+            const double ex = disp_x(px, mx0[g], period), ey = py - my0[g];
             const double q0 = ixx0[g] * ex * ex + 2.0 * ixy0[g] * ex * ey + iyy0[g] * ey * ey;
             if (!(q0 <= qmax)) continue;
             double a0 = op0[g] * exp(-0.5 * q0);
@@ -385,7 +409,7 @@ void oracle_render_held(int64_t n, const double *mx0, const double *my0, const d
             const double Tn0 = T0 * (1.0 - a0);
             if (Tn0 < tmin) break;
             T0 = Tn0;
-            const double dx = px - mx[g], dy = py - my[g];
+            const double dx = disp_x(px, mx[g], period), dy = py - my[g];
             const double q = ixx[g] * dx * dx + 2.0 * ixy[g] * dx * dy + iyy[g] * dy * dy;
             const double a = clamped ? amax : op[g] * exp(-0.5 * q);
             C += amp[g] * a * T;

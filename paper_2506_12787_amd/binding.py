@@ -22,6 +22,7 @@ KEEP_AUX = 1 << 2
 FULL_SORT = 1 << 3
 TILE8 = 1 << 4
 PAPER_DEFORM = 1 << 5
+WRAP_AZIMUTH = 1 << 6
 
 STAGES = ("tx_features", "mlp_preprocess", "scan", "emit_keys", "radix_sort", "tile_ranges", "blend",
           "blend_backward", "preprocess_backward", "mlp_backward")
@@ -44,6 +45,18 @@ class _Mlp(ctypes.Structure):
     _fields_ = [("mean_bands", ctypes.c_int32), ("tx_bands", ctypes.c_int32), ("hidden", ctypes.c_int32),
                 ("n_hidden", ctypes.c_int32), ("weight", ctypes.c_void_p * MAX_LAYERS),
                 ("bias", ctypes.c_void_p * MAX_LAYERS), ("room_lo", ctypes.c_float * 3),
+                ("room_hi", ctypes.c_float * 3)]
+
+
+PAPER_KEYS = ("center_x", "center_y", "chol_l1", "chol_l2", "chol_l3", "atten_logit", "psi_re", "psi_im")
+
+
+class _PaperGaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32)] + [(k, ctypes.c_void_p) for k in PAPER_KEYS]
+
+
+class _PaperMlp(ctypes.Structure):
+    _fields_ = [("weight", ctypes.c_void_p * 9), ("bias", ctypes.c_void_p * 9), ("room_lo", ctypes.c_float * 3),
                 ("room_hi", ctypes.c_float * 3)]
 
 
@@ -99,6 +112,14 @@ def lib():
             "swf_render": [P, I32, P, I32, I32, P, P, P],
             "swf_render_backward": [P, I32, P, I32, I32, P, P, P, P],
             "swf_l1_loss": [P, P, P, I64, P, P, P],
+            "swf_adam_step": [P, P, P, P, P, P, P, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, I32, P],
+            "swf_anneal_tx": [P, P, P, I32, I32, ctypes.c_float, I32, I32, P, P, P, P],
+            "swf_hybrid_loss": [P, P, P, I32, I32, I32, ctypes.c_float, P, P, P],
+            "swf_scene_upload_paper": [P, P, P, I32, I32, I32, P],
+            "swf_render_paper": [P, I32, P, I32, I32, P, P, P],
+            "swf_render_rssi": [P, I32, P, I32, I32, P, P, P, P],
+            "swf_render_rssi_backward": [P, I32, P, I32, I32, P, P, P, P],
+            "swf_beamscan": [P, P, P, I32, I32, I32, ctypes.c_float, I32, I32, P, P],
             "swf_stage_timing": [P, I32],
             "swf_stage_times": [P, P, P, P],
             "swf_debug_deform": [P, I32, P, I32, I32, P, P],
@@ -232,6 +253,54 @@ class Context:
         self._check(self._L.swf_scene_update(self._h, sid, ctypes.byref(g) if g is not None else None,
                                              ctypes.byref(m) if m is not None else None, 1, _stream()))
 
+    def upload_paper_scene(self, gaussians: dict, H: int, W: int, mlp=None, room=((0, 0, 0), (6, 6, 3))) -> int:
+        """Upload a paper-model scene: FP32 host arrays keyed by PAPER_KEYS, optional paper MLP (Ws, bs) of nine
+        layers (W_l of shape (out, in))."""
+        cols = {k: np.ascontiguousarray(gaussians[k], dtype=np.float32) for k in PAPER_KEYS}
+        n = len(cols["center_x"])
+        g = _PaperGaussians(n=n, **{k: cols[k].ctypes.data for k in PAPER_KEYS})
+        m = None
+        if mlp is not None:
+            Ws = [np.ascontiguousarray(w, dtype=np.float32) for w in mlp[0]]
+            bs = [np.ascontiguousarray(b, dtype=np.float32) for b in mlp[1]]
+            assert len(Ws) == 9 and len(bs) == 9
+            m = _PaperMlp()
+            for l in range(9):
+                m.weight[l] = Ws[l].ctypes.data
+                m.bias[l] = bs[l].ctypes.data
+            for k in range(3):
+                m.room_lo[k] = room[0][k]
+                m.room_hi[k] = room[1][k]
+        sid = ctypes.c_int32()
+        self._check(self._L.swf_scene_upload_paper(self._h, ctypes.byref(g), ctypes.byref(m) if m is not None else None,
+                                                   H, W, 0, ctypes.byref(sid)))
+        self._keep[sid.value] = (H, W, n, mlp is not None)
+        self._rooms[sid.value] = room
+        return sid.value
+
+    def render_paper(self, sid: int, tx=None, flags: int = 0, batch: int | None = None, out=None, channels=True):
+        """Paper-model spectra (batch, H, W) = |GMM sum| and, with channels, the (batch, 2, H, W) real and imaginary
+        sums."""
+        torch = self.torch
+        H, W, n, _ = self._keep[sid]
+        if tx is not None:
+            assert tx.is_cuda and tx.dtype == torch.float32 and tx.is_contiguous() and tx.shape[-1] == 3
+            batch = tx.shape[0]
+        batch = batch or 1
+        if out is None:
+            out = torch.empty((batch, H, W), device=self.device, dtype=torch.float32)
+        ch = torch.empty((batch, 2, H, W), device=self.device, dtype=torch.float32) if channels else None
+        self._check(self._L.swf_render_paper(self._h, sid, _ptr(tx), batch, flags, _ptr(out), _ptr(ch), _stream()))
+        return out, ch
+
+    def debug_deform_paper(self, sid: int, tx):
+        """The paper MLP's residuals (batch, n, 5) for a paper-model scene."""
+        torch = self.torch
+        H, W, n, _ = self._keep[sid]
+        d = torch.empty((tx.shape[0], n, 5), device=self.device, dtype=torch.float32)
+        self._check(self._L.swf_debug_deform(self._h, sid, _ptr(tx), tx.shape[0], MLP_FP32, _ptr(d), _stream()))
+        return d
+
     def release_scene(self, sid: int):
         self._check(self._L.swf_scene_release(self._h, sid))
         self._keep.pop(sid, None)
@@ -283,6 +352,93 @@ class Context:
         self._check(self._L.swf_render_backward(self._h, sid, _ptr(tx), batch, flags, _ptr(grad_out), _ptr(aux),
                                                 ctypes.byref(gr), _stream()))
 
+    def render_rssi(self, sid: int, tx, flags: int = 0, out=None, aux=None, keep_spectrum: bool = False):
+        """RSSI per query (global average of the rendered spectrum). Returns rssi (batch,), plus the spectrum if
+        keep_spectrum (or out) is given, plus aux with KEEP_AUX."""
+        torch = self.torch
+        H, W, n, _ = self._keep[sid]
+        assert tx.is_cuda and tx.dtype == torch.float32 and tx.is_contiguous() and tx.shape[-1] == 3
+        batch = tx.shape[0]
+        rssi = torch.empty((batch,), device=self.device, dtype=torch.float32)
+        if out is None and keep_spectrum:
+            out = torch.empty((batch, H, W), device=self.device, dtype=torch.float32)
+        if out is not None:
+            assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == batch * H * W
+        if (flags & KEEP_AUX) and aux is None:
+            aux = torch.empty((2, batch, H, W), device=self.device, dtype=torch.float32)
+        self._check(self._L.swf_render_rssi(self._h, sid, _ptr(tx), batch, flags, _ptr(rssi), _ptr(out), _ptr(aux),
+                                            _stream()))
+        res = (rssi,)
+        if out is not None:
+            res += (out,)
+        if flags & KEEP_AUX:
+            res += (aux,)
+        return res[0] if len(res) == 1 else res
+
+    def render_rssi_backward(self, sid: int, tx, flags: int, grad_rssi, aux, grads: dict):
+        """Gradients of sum(grad_rssi * rssi) into the device tensors of `grads` (as render_backward)."""
+        torch = self.torch
+        H, W, n, _ = self._keep[sid]
+        batch = tx.shape[0]
+        if grad_rssi.dtype != torch.float32 or not grad_rssi.is_contiguous() or grad_rssi.numel() != batch:
+            raise SwfError(f"grad_rssi must be contiguous float32 with {batch} values")
+        if aux is None or not aux.is_contiguous() or aux.numel() * aux.element_size() != 8 * batch * H * W:
+            raise SwfError(f"aux must be the contiguous {8 * batch * H * W}-byte buffer of the forward render")
+        gr = self._grads_struct(grads, n)
+        self._check(self._L.swf_render_rssi_backward(self._h, sid, _ptr(tx), batch, flags, _ptr(grad_rssi),
+                                                     _ptr(aux), ctypes.byref(gr), _stream()))
+
+    def _grads_struct(self, grads: dict, n: int):
+        torch = self.torch
+        gr = _Grads()
+        for k in PARAMS[:7]:
+            t = grads.get(k)
+            if t is not None and (t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n):
+                raise SwfError(f"grads[{k!r}] must be contiguous float32 with {n} values")
+            setattr(gr, k, t.data_ptr() if t is not None else None)
+        for l, w in enumerate(grads.get("weight", []) or []):
+            gr.weight[l] = w.data_ptr() if w is not None else None
+        for l, b in enumerate(grads.get("bias", []) or []):
+            gr.bias[l] = b.data_ptr() if b is not None else None
+        return gr
+
+    def hybrid_loss(self, pred, target, lambda1: float = 0.7, want_grad=True):
+        """(loss (3,) = total, l1, ssim; grad or None) of lambda1 * l1 + (1 - lambda1) * (1 - SSIM) over a batch of
+        spectra (B, H, W)."""
+        torch = self.torch
+        assert pred.dtype == torch.float32 and pred.is_contiguous() and pred.dim() == 3 and pred.is_cuda
+        assert target.shape == pred.shape and target.dtype == torch.float32 and target.is_contiguous()
+        loss = torch.empty(3, device=self.device, dtype=torch.float32)
+        grad = torch.empty_like(pred) if want_grad else None
+        B_, H, W = pred.shape
+        self._check(self._L.swf_hybrid_loss(self._h, _ptr(pred), _ptr(target), B_, H, W, float(lambda1), _ptr(loss),
+                                            _ptr(grad), _stream()))
+        return loss, grad
+
+    def adam_step(self, params, grads, m, v, lrs, step: int, beta1=0.9, beta2=0.999, eps=1e-8):
+        """In-place Adam update of lists of contiguous float32 device tensors (one learning rate each)."""
+        n = len(params)
+        for ts in (params, grads, m, v):
+            assert len(ts) == n and all(t.is_contiguous() and t.dtype == self.torch.float32 for t in ts)
+        P = ctypes.c_void_p * max(n, 1)
+        arr = [P(*[t.data_ptr() for t in ts]) for ts in (params, grads, m, v)]
+        sizes = (ctypes.c_int64 * max(n, 1))(*[t.numel() for t in params])
+        lr = (ctypes.c_float * max(n, 1))(*[float(x) for x in lrs])
+        self._check(self._L.swf_adam_step(self._h, *arr, sizes, lr, n, float(beta1), float(beta2), float(eps),
+                                          int(step), _stream()))
+
+    def anneal_tx(self, tx, noise, it: int, n_positions: int, gamma=1.0, tau=10_000,
+                  room=((0.0, 0.0, 0.0), (6.0, 6.0, 3.0)), out=None):
+        """Anneal-smoothed positions (batch, 3) from standard normal noise (batch, 3), both device float32."""
+        torch = self.torch
+        assert tx.is_contiguous() and noise.is_contiguous() and tx.shape == noise.shape and tx.shape[-1] == 3
+        out = torch.empty_like(tx) if out is None else out
+        lo = (ctypes.c_float * 3)(*room[0])
+        hi = (ctypes.c_float * 3)(*room[1])
+        self._check(self._L.swf_anneal_tx(self._h, _ptr(tx), _ptr(noise), tx.shape[0], int(it), float(gamma),
+                                          int(tau), int(n_positions), lo, hi, _ptr(out), _stream()))
+        return out
+
     def l1_loss(self, pred, target, want_grad=True):
         torch = self.torch
         loss = torch.empty((), device=self.device, dtype=torch.float32)
@@ -290,6 +446,22 @@ class Context:
         self._check(self._L.swf_l1_loss(self._h, _ptr(pred), _ptr(target), pred.numel(), _ptr(loss), _ptr(grad),
                                         _stream()))
         return loss, grad
+
+    def beamscan(self, paths, counts, H: int, W: int, side: int = 4, spacing_over_lambda: float = 0.5, out=None):
+        """Beam-scan spectra (batch, H, W) from device multipath lists: paths float32 (batch, max_paths, 3) of
+        (rho, azimuth, elevation), counts int32 (batch,)."""
+        torch = self.torch
+        assert paths.is_cuda and paths.dtype == torch.float32 and paths.is_contiguous() and paths.dim() == 3
+        assert paths.shape[2] == 3
+        assert counts.is_cuda and counts.dtype == torch.int32 and counts.is_contiguous()
+        batch, max_paths = paths.shape[0], paths.shape[1]
+        assert counts.numel() == batch
+        if out is None:
+            out = torch.empty((batch, H, W), device=self.device, dtype=torch.float32)
+        assert out.dtype == torch.float32 and out.is_contiguous() and out.numel() == batch * H * W
+        self._check(self._L.swf_beamscan(self._h, _ptr(paths), _ptr(counts), batch, max_paths, side,
+                                         float(spacing_over_lambda), H, W, _ptr(out), _stream()))
+        return out
 
     # ---- timing ---------------------------------------------------------------
     def stage_timing(self, enable: bool):

@@ -287,6 +287,7 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     if (!grad_out || !aux || !gr) return fail(SWF_E_INVALID, "grad_out, aux and grads are required");
     Scene* sc = scene(sid);
     if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
+    if (sc->d.kind == 1) return fail(SWF_E_INVALID, "paper-model scenes have no backward in this library");
     {
         // the forward pass below must be the one that filled aux
         auto it = aux_tags.find(aux);

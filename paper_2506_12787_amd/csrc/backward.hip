@@ -63,7 +63,9 @@ __device__ __forceinline__ float wave_sum8(float (&a)[8]) {
 // With 16x16 tiles each wave (an 8x8 quadrant) walks only the entries that can
 // reach the cutoff on its rectangle (the forward kernel's culling): the others
 // leave every one of its pixels unchanged.
-template <int TILE>
+// kWrap: periodic azimuth, as in the forward kernel (same staged image, same
+// displacement, same culling exemption), so that every decision replays exactly.
+template <int TILE, bool kWrap = false>
 __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals, const float4* __restrict__ geo,
     const float4* __restrict__ wm, const float2* __restrict__ oa, int H, int W, int TW, int tiles,
@@ -93,6 +95,8 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     const int bx0 = (tx * TILE) & ~63, by0 = (ty * TILE) & ~63;
     const float x0 = (float)bx0, y0 = (float)by0;
     const float fx = (float)(px - bx0), fy = (float)(py - by0);
+    const float Wf = kWrap ? (float)W : 0.0f, rw = kWrap ? 1.0f / (float)W : 0.0f;
+    const float cx = (float)(tx * TILE - bx0) + 0.5f * (float)(TILE - 1);
     const uint2 rg = ranges[gtile];
 
     float T = 1.0f, G = 0.0f;
@@ -120,7 +124,8 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
         if (j < (int)last) {
             const float4 m = s_wm[jj];
             float dx, dy, u, w;
-            const float q = blend_q(fx, fy, s_pos[jj], m, dx, dy, u, w);
+            const float q = kWrap ? blend_q_wrap(fx, fy, s_pos[jj], m, Wf, rw, dx, dy, u, w)
+                                  : blend_q(fx, fy, s_pos[jj], m, dx, dy, u, w);
             if (q <= kQMax) {
                 const float2 o = s_oa[jj];
                 const float raw = blend_raw_alpha(q, o.x);
@@ -165,7 +170,8 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
             if (j < end) {
                 const uint32_t v = vals[rg.x + j];
                 const float4 g = geo[v];
-                const float2 pos = make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
+                const float2 pos =
+                    kWrap ? staged_mean(g, x0, y0, Wf, cx) : make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
                 const float4 m = wm[v];
                 s_pos[threadIdx.x] = pos;
                 s_wm[threadIdx.x] = m;
@@ -173,7 +179,10 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
                 s_v[threadIdx.x] = v;
                 if (kCull)
                     s_strip[threadIdx.x] =
-                        (uint8_t)wave_quads_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
+                        (kWrap && fabsf(pos.x - cx) > 0.5f * Wf - (float)TILE)
+                            ? (uint8_t)0xf
+                            : (uint8_t)wave_quads_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0),
+                                                       kQMax);
             }
         }
         __syncthreads();
@@ -982,12 +991,22 @@ void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Reco
                            hipStream_t st) {
     const unsigned blocks = (unsigned)(B * g.tiles);
     if (!blocks) return;
-    if (g.tile == 8)
-        blend_backward_kernel<8><<<blocks, 64, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles,
-                                                        grad_out, aux_T, aux_last, dpair);
-    else
-        blend_backward_kernel<16><<<blocks, 256, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles,
-                                                          grad_out, aux_T, aux_last, dpair);
+#define SWF_BLEND_BWD(TILE, WRAP)                                                                              \
+    blend_backward_kernel<TILE, WRAP><<<blocks, TILE * TILE, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, \
+                                                                       g.TW, g.tiles, grad_out, aux_T, aux_last, \
+                                                                       dpair)
+    if (g.tile == 8) {
+        if (g.wrap)
+            SWF_BLEND_BWD(8, true);
+        else
+            SWF_BLEND_BWD(8, false);
+    } else {
+        if (g.wrap)
+            SWF_BLEND_BWD(16, true);
+        else
+            SWF_BLEND_BWD(16, false);
+    }
+#undef SWF_BLEND_BWD
 }
 
 void launch_preprocess_backward(const float* dpair, const Records& r, int64_t P, bool paper_mask, float* dbase,

@@ -21,7 +21,11 @@ __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
 // list entry) evaluations the rule needs (entries whose quadratic form is
 // within the 3-sigma cutoff at the pixel, up to and including the one that ends
 // it) and to work[1] the number of records staged in LDS.
-template <int TILE, bool kCount = false, bool kAux = true>
+//
+// kWrap: periodic azimuth (period W): each staged mean is the image nearest the
+// tile, every evaluation takes the displacement to the nearest image, and an
+// entry whose image lies nearly half a period from the tile is not culled.
+template <int TILE, bool kCount = false, bool kAux = true, bool kWrap = false>
 __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ vals,
                                                                     const float4* __restrict__ geo,
@@ -68,6 +72,8 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     const int bx0 = (tx * TILE) & ~63, by0 = (ty * TILE) & ~63;
     const float x0 = (float)bx0, y0 = (float)by0;
     const float fx = (float)(px - bx0), fy = (float)(py - by0);
+    const float Wf = kWrap ? (float)W : 0.0f, rw = kWrap ? 1.0f / (float)W : 0.0f;
+    const float cx = (float)(tx * TILE - bx0) + 0.5f * (float)(TILE - 1);  // tile centre, block-relative
 
     const uint2 rg = ranges[gtile];
     float T = 1.0f, C = 0.0f;
@@ -82,14 +88,16 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
         if (i < rg.y) {
             const uint32_t v = vals[i];
             const float4 g = geo[v];
-            const float2 pos = make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
+            const float2 pos = kWrap ? staged_mean(g, x0, y0, Wf, cx) : make_float2((g.x - x0) + g.z, (g.y - y0) + g.w);
             const float4 m = wm[v];
             const float2 o = oa[v];
             s_rec[2 * threadIdx.x] = make_float4(pos.x, pos.y, o.x, o.y);
             s_rec[2 * threadIdx.x + 1] = m;
             if (kCull)  // block-relative first column and row of the tile
                 s_strip[threadIdx.x] =
-                    (uint8_t)wave_quads_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
+                    (kWrap && fabsf(pos.x - cx) > 0.5f * Wf - (float)TILE)
+                        ? (uint8_t)0xf
+                        : (uint8_t)wave_quads_mask(m, pos, (float)(tx * TILE - bx0), (float)(ty * TILE - by0), kQMax);
         } else if ((int)threadIdx.x < ((cnt + kUnroll - 1) & ~(kUnroll - 1))) {
             // padding up to the unrolled length: opacity 0 never contributes
             s_rec[2 * threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -132,7 +140,8 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
                     const float4 m = *reinterpret_cast<const float4*>(rp + 16);
                     const int j = (int)(jw[jj] >> 5);
                     float dx, dy, u, w;
-                    const float q = blend_q(fx, fy, make_float2(r0.x, r0.y), m, dx, dy, u, w);
+                    const float q = kWrap ? blend_q_wrap(fx, fy, make_float2(r0.x, r0.y), m, Wf, rw, dx, dy, u, w)
+                                          : blend_q(fx, fy, make_float2(r0.x, r0.y), m, dx, dy, u, w);
                     const float2 o = make_float2(r0.z, r0.w);
                     const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
                     const float ae = (!done && q <= kQMax && a >= kAlphaMin) ? a : 0.0f;
@@ -154,7 +163,9 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
                     const int j = j0 + jj;
                     const float4 r0 = s_rec[2 * j];
                     float dx, dy, u, w;
-                    const float q = blend_q(fx, fy, make_float2(r0.x, r0.y), s_rec[2 * j + 1], dx, dy, u, w);
+                    const float q = kWrap ? blend_q_wrap(fx, fy, make_float2(r0.x, r0.y), s_rec[2 * j + 1], Wf, rw,
+                                                         dx, dy, u, w)
+                                          : blend_q(fx, fy, make_float2(r0.x, r0.y), s_rec[2 * j + 1], dx, dy, u, w);
                     if (kCount) evals += (!done && j < cnt && q <= kQMax) ? 1u : 0u;
                     const float2 o = make_float2(r0.z, r0.w);
                     const float a = fminf(kAlphaMax, blend_raw_alpha(q, o.x));
@@ -193,6 +204,17 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     }
 }
 
+template <int TILE, bool kCount, bool kAux>
+void blend_launch(const uint2* ranges, const uint32_t* vals, const Records& r, unsigned blocks, const Grid& g,
+                  float* out, float* aux_T, uint32_t* aux_last, unsigned long long* work, hipStream_t st) {
+    if (g.wrap)
+        blend_forward_kernel<TILE, kCount, kAux, true><<<blocks, TILE * TILE, 0, st>>>(
+            ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles, out, aux_T, aux_last, work);
+    else
+        blend_forward_kernel<TILE, kCount, kAux, false><<<blocks, TILE * TILE, 0, st>>>(
+            ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles, out, aux_T, aux_last, work);
+}
+
 }  // namespace
 
 void launch_blend_work(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
@@ -200,11 +222,9 @@ void launch_blend_work(const uint2* ranges, const uint32_t* vals, const Records&
     const unsigned blocks = (unsigned)(B * g.tiles);
     if (!blocks) return;
     if (g.tile == 8)
-        blend_forward_kernel<8, true><<<blocks, 64, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW,
-                                                             g.tiles, nullptr, nullptr, nullptr, work);
+        blend_launch<8, true, true>(ranges, vals, r, blocks, g, nullptr, nullptr, nullptr, work, st);
     else
-        blend_forward_kernel<16, true><<<blocks, 256, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW,
-                                                               g.tiles, nullptr, nullptr, nullptr, work);
+        blend_launch<16, true, true>(ranges, vals, r, blocks, g, nullptr, nullptr, nullptr, work, st);
 }
 
 void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
@@ -214,18 +234,14 @@ void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Recor
     const bool aux = aux_T != nullptr;
     if (g.tile == 8) {
         if (aux)
-            blend_forward_kernel<8, false, true><<<blocks, 64, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W,
-                                                                        g.TW, g.tiles, out, aux_T, aux_last);
+            blend_launch<8, false, true>(ranges, vals, r, blocks, g, out, aux_T, aux_last, nullptr, st);
         else
-            blend_forward_kernel<8, false, false><<<blocks, 64, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W,
-                                                                         g.TW, g.tiles, out, nullptr, nullptr);
+            blend_launch<8, false, false>(ranges, vals, r, blocks, g, out, nullptr, nullptr, nullptr, st);
     } else {
         if (aux)
-            blend_forward_kernel<16, false, true><<<blocks, 256, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W,
-                                                                          g.TW, g.tiles, out, aux_T, aux_last);
+            blend_launch<16, false, true>(ranges, vals, r, blocks, g, out, aux_T, aux_last, nullptr, st);
         else
-            blend_forward_kernel<16, false, false><<<blocks, 256, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W,
-                                                                           g.TW, g.tiles, out, nullptr, nullptr);
+            blend_launch<16, false, false>(ranges, vals, r, blocks, g, out, nullptr, nullptr, nullptr, st);
     }
 }
 

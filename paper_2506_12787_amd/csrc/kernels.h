@@ -27,7 +27,30 @@ struct DevScene {
     uint16_t *bf_mfeat = nullptr;   // [n][32] BF16 gamma(mu_hat), zero padded
     float room_lo[3] = {0, 0, 0}, room_hi[3] = {6, 6, 3};
     uint64_t bytes = 0;
+    // kind 1: the paper's own model (GMM sum over Cholesky Gaussians with tanh centres and complex responses,
+    // in id order; paper.hip). Raw parameters, the FP64-mapped centres (hi, lo) and their 10-band encoding, and
+    // the paper MLP: FP32 masters (out, in) and the packed in-major layers of the kernel.
+    int kind = 0;
+    float *pcx = nullptr, *pcy = nullptr, *pl1 = nullptr, *pl2 = nullptr, *pl3 = nullptr;
+    float *patt = nullptr, *ppre = nullptr, *ppim = nullptr;
+    float4* pcen = nullptr;
+    float* pfeat = nullptr;
+    float *pw[9] = {}, *pb[9] = {};
+    float *pwt[9] = {}, *pbt[9] = {};
+    int pK[8] = {};
 };
+
+// The paper's model (paper.hip): positional encoding bands, layer sizes and
+// padded layouts of its MLP.
+constexpr int kPaperCenterBands = 10;
+constexpr int kPaperTxBands = 6;
+constexpr int kPaperCenterFeat = 2 * (2 * kPaperCenterBands + 1);  // 42
+constexpr int kPaperTxFeat = 3 * (2 * kPaperTxBands + 1);          // 39
+constexpr int kPaperFeatStride = 48;
+constexpr int kPaperLayers = 8;
+constexpr int kPaperWidth = 156;
+constexpr int kPaperOut = 5;
+constexpr int kPaperOutPad = 8;
 
 struct Records {
     float4 *geo = nullptr;
@@ -39,7 +62,34 @@ struct Records {
 
 struct Grid {
     int H, W, tile, TW, TH, tiles;  // tiles per query
+    int wrap;                       // 1: periodic azimuth (period W)
 };
+
+struct PaperArgs {
+    int N, B, H, W, TW, TH, wrap;
+    float inv_tile;
+    const float4* cen;
+    const float *l1, *l2, *l3, *att, *pre, *pim;
+    const float* feat;  // [N][48] centre features
+    const float* txf;   // [B][48] position features
+    const float* wt[kPaperLayers];
+    const float* bt[kPaperLayers];
+    int K[kPaperLayers];
+    const float* wo;
+    const float* bo;
+    Records rec;
+    float* delta_out;  // [B * N][5] residuals (debug), or null
+};
+
+// paper.hip
+void launch_paper_centers(const DevScene& d, hipStream_t st);
+void launch_paper_tx(const DevScene& d, const float* tx, int B, float* txf, hipStream_t st);
+void launch_paper_static(const DevScene& d, int B, const Grid& g, const Records& r, hipStream_t st);
+void launch_paper_mlp(const DevScene& d, const float* txf, int B, const Grid& g, const Records& r, float* delta_out,
+                      hipStream_t st);
+// out [B][H][W] = |sum|; chan (may be null) [B][2][H][W] = (re, im)
+void launch_gmm_blend(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g, float* out,
+                      float* chan, hipStream_t st);
 
 // pe_mlp.hip
 void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hipStream_t st,

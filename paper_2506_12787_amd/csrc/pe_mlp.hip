@@ -210,7 +210,7 @@ __global__ void preprocess_static_kernel(MlpArgs a) {
     PairOut o;
     if (p < a.n_live) {
         o = preprocess_pair(a.mx[p], a.my[p], 0.f, 0.f, a.lsx[p], a.lsy[p], a.rot[p], a.logit[p], a.amp[p], a.W, a.H,
-                            a.TW, a.TH, a.inv_tile);
+                            a.TW, a.TH, a.inv_tile, a.wrap);
     } else {
         o.geo = make_float4(0, 0, 0, 0);
         o.wm = make_float4(0, 0, 0, 0);

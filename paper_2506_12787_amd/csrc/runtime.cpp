@@ -98,8 +98,9 @@ static int bits_for(uint64_t m) {
     return b;
 }
 
-Grid make_grid(int H, int W, int tile) {
+Grid make_grid(int H, int W, int tile, bool wrap) {
     Grid g;
+    g.wrap = wrap ? 1 : 0;
     g.H = H;
     g.W = W;
     g.tile = tile;
@@ -281,6 +282,117 @@ swf_status Ctx::upload_scene(const swf_gaussians* g, const swf_mlp* mlp, int H, 
     return SWF_OK;
 }
 
+// The paper's model: raw parameters in id order (the sum has no order), the
+// FP64 centre map and its encoding on the device, and the paper MLP packed for
+// paper_mlp_kernel: per layer an in-major [K][160] array whose row k multiplies
+// column k0 + k of the kernel's [h (160) | x (96)] row (layer 1: the x part,
+// K = 96; plain layers: h, K = 160; skip layers 3, 5, 7: both, K = 256), every
+// pad row and column zero; the output layer [160][8].
+swf_status Ctx::upload_paper_scene(const swf_paper_gaussians* g, const swf_paper_mlp* mlp, int H, int W, bool dev,
+                                   int* id) {
+    if (!g || !id || g->n < 0) return fail(SWF_E_INVALID, "null gaussians/id or n < 0");
+    if (H < 1 || H > 4096 || W < 1 || W > 4096) return fail(SWF_E_INVALID, "H and W must lie in [1, 4096]");
+    const size_t n = (size_t)g->n;
+    std::vector<float> col[8];
+    const float* src[8] = {g->center_x, g->center_y, g->chol_l1, g->chol_l2, g->chol_l3, g->atten_logit,
+                           g->psi_re, g->psi_im};
+    for (int k = 0; k < 8; ++k) {
+        swf_status st = fetch(this, col[k], src[k], n, dev);
+        if (st) return st;
+    }
+    static const int kIn[9] = {81, 156, 237, 156, 237, 156, 237, 156, 156};
+    static const int kOutDim[9] = {156, 156, 156, 156, 156, 156, 156, 156, 5};
+    std::vector<std::vector<float>> Wm(9), Bm(9);
+    if (mlp) {
+        for (int l = 0; l < 9; ++l) {
+            if (!mlp->weight[l] || !mlp->bias[l]) return fail(SWF_E_INVALID, "null paper MLP weight or bias");
+            swf_status st = fetch(this, Wm[l], mlp->weight[l], (size_t)kOutDim[l] * kIn[l], dev);
+            if (!st) st = fetch(this, Bm[l], mlp->bias[l], (size_t)kOutDim[l], dev);
+            if (st) return st;
+        }
+        for (int k = 0; k < 3; ++k)
+            if (!(mlp->room_hi[k] > mlp->room_lo[k])) return fail(SWF_E_INVALID, "room_hi must exceed room_lo");
+    }
+    Scene* s = new (std::nothrow) Scene();
+    if (!s) return fail(SWF_E_OOM, "host allocation");
+    DevScene& d = s->d;
+    d.kind = 1;
+    d.n = (int)n;
+    d.n_live = (int)n;
+    d.H = H;
+    d.W = W;
+    std::vector<uint32_t> perm(n), zero(n, 0u);
+    for (size_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+    swf_status st = SWF_OK;
+    float** dst[8] = {&d.pcx, &d.pcy, &d.pl1, &d.pl2, &d.pl3, &d.patt, &d.ppre, &d.ppim};
+    for (int k = 0; k < 8 && !st; ++k) st = upload(this, s, dst[k], col[k].data(), n);
+    if (!st) st = upload(this, s, &d.dbits, zero.data(), n);
+    if (!st) st = upload(this, s, &d.perm, perm.data(), n);
+    if (!st) st = upload(this, s, &d.inv_perm, perm.data(), n);
+    if (!st) {
+        std::vector<float4> c4(n);
+        st = upload(this, s, &d.pcen, c4.data(), n);
+    }
+    if (!st) {
+        std::vector<float> f(n * kPaperFeatStride);
+        st = upload(this, s, &d.pfeat, f.data(), f.size());
+    }
+    s->host_dbits = zero;
+    s->host_perm = perm;
+    if (!st && mlp) {
+        d.has_mlp = true;
+        for (int k = 0; k < 3; ++k) {
+            d.room_lo[k] = mlp->room_lo[k];
+            d.room_hi[k] = mlp->room_hi[k];
+        }
+        for (int l = 0; l < 9 && !st; ++l) {
+            st = upload(this, s, &d.pw[l], Wm[l].data(), Wm[l].size());
+            if (!st) st = upload(this, s, &d.pb[l], Bm[l].data(), Bm[l].size());
+        }
+        for (int l = 0; l < kPaperLayers && !st; ++l) {
+            const bool skip = l == 2 || l == 4 || l == 6;  // layers 3, 5, 7 (1-based)
+            const int K = l == 0 ? 96 : (skip ? 256 : 160);
+            d.pK[l] = K;
+            std::vector<float> t((size_t)K * 160, 0.0f), b(160, 0.0f);
+            for (int j = 0; j < kPaperWidth; ++j) {
+                b[j] = Bm[l][j];
+                for (int i = 0; i < kIn[l]; ++i) {
+                    // input column i of the layer -> packed row
+                    int r;
+                    if (l == 0)
+                        r = i;                                     // x[i] at kernel column 160 + i
+                    else
+                        r = i < kPaperWidth ? i : 160 + (i - kPaperWidth);  // h[i], then x[i - 156]
+                    t[(size_t)r * 160 + j] = Wm[l][(size_t)j * kIn[l] + i];
+                }
+            }
+            st = upload(this, s, &d.pwt[l], t.data(), t.size());
+            if (!st) st = upload(this, s, &d.pbt[l], b.data(), b.size());
+        }
+        if (!st) {
+            std::vector<float> t((size_t)160 * kPaperOutPad, 0.0f), b(kPaperOutPad, 0.0f);
+            for (int o = 0; o < kPaperOut; ++o) {
+                b[o] = Bm[8][o];
+                for (int k = 0; k < kPaperWidth; ++k) t[(size_t)k * kPaperOutPad + o] = Wm[8][(size_t)o * 156 + k];
+            }
+            st = upload(this, s, &d.pwt[8], t.data(), t.size());
+            if (!st) st = upload(this, s, &d.pbt[8], b.data(), b.size());
+        }
+    }
+    if (!st) {
+        launch_paper_centers(d, nullptr);
+        st = hip(hipDeviceSynchronize(), "paper centres");
+    }
+    if (st) {
+        free_scene(s);
+        return st;
+    }
+    const int sid = next_scene++;
+    scenes[sid] = s;
+    *id = sid;
+    return SWF_OK;
+}
+
 swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
     DevScene& d = s->d;
     const size_t n = (size_t)d.n;
@@ -389,6 +501,7 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
 swf_status Ctx::update_scene(int id, const swf_gaussians* g, const swf_mlp* mlp, bool dev, hipStream_t st) {
     Scene* s = scene(id);
     if (!s) return fail(SWF_E_NOT_FOUND, "unknown scene id");
+    if (s->d.kind == 1) return fail(SWF_E_INVALID, "paper-model scenes are uploaded, not updated");
     DevScene& d = s->d;
     swf_status r = SWF_OK;
     if (g || mlp) ++s->gen;
@@ -460,6 +573,8 @@ swf_status Ctx::enqueue_preprocess(Workspace& w, Scene* sc, const float* tx, int
                                    hipStream_t st) {
     const DevScene& d = sc->d;
     const bool deform = !(flags & SWF_NO_DEFORM);
+    if (d.kind == 1 && (flags & (SWF_MLP_BF16 | SWF_TILE8 | SWF_KEEP_AUX)))
+        return fail(SWF_E_INVALID, "paper-model scenes render with the FP32 MLP, 16x16 tiles and no aux");
     if (deform && (flags & SWF_MLP_BF16) && !bf16_available())
         return fail(SWF_E_STATE, "BF16 MLP kernel is not available in this build");
     const size_t pairs = (size_t)B * d.n;
@@ -474,6 +589,22 @@ swf_status Ctx::enqueue_preprocess(Workspace& w, Scene* sc, const float* tx, int
     w.rec.oa = (float2*)w.oa.ptr;
     w.rec.rect = (uint2*)w.rect.ptr;
     w.rec.count = (uint32_t*)w.count.ptr;
+    if (d.kind == 1) {
+        if (deform) {
+            if (!d.has_mlp) return fail(SWF_E_INVALID, "scene has no deformation MLP (use SWF_NO_DEFORM)");
+            if (!tx) return fail(SWF_E_INVALID, "tx is NULL");
+            if ((s = w.qs.reserve(this, (size_t)B * kPaperFeatStride * sizeof(float), st))) return s;
+        }
+        stage_begin(SWF_STAGE_MLP, st);
+        if (deform) {
+            launch_paper_tx(d, tx, B, (float*)w.qs.ptr, st);
+            launch_paper_mlp(d, (const float*)w.qs.ptr, B, g, w.rec, delta_sorted, st);
+        } else {
+            launch_paper_static(d, B, g, w.rec, st);
+        }
+        stage_end(st);
+        return hip(hipGetLastError(), "paper preprocess launch");
+    }
     if (deform) {
         if (!d.has_mlp) return fail(SWF_E_INVALID, "scene has no deformation MLP (use SWF_NO_DEFORM)");
         if (!tx) return fail(SWF_E_INVALID, "tx is NULL");
@@ -506,7 +637,7 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     if (B < 1) return fail(SWF_E_INVALID, "batch must be >= 1");
     const DevScene& d = sc->d;
     if ((uint64_t)B * (uint64_t)d.n >= (1ull << 32)) return fail(SWF_E_INVALID, "batch * n must be < 2^32");
-    const Grid g = make_grid(d.H, d.W, (flags & SWF_TILE8) ? 8 : 16);
+    const Grid g = make_grid(d.H, d.W, (flags & SWF_TILE8) ? 8 : 16, (flags & SWF_WRAP_AZIMUTH) != 0);
     if ((uint64_t)B * g.tiles >= (1ull << 31)) return fail(SWF_E_INVALID, "batch * tiles too large");
     w.last.valid = false;
     w.last.stream = st;
@@ -517,8 +648,9 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     const bool full = (flags & SWF_FULL_SORT) != 0;
     const int64_t n_gt = (int64_t)B * g.tiles;
     if ((s = w.ranges.reserve(this, (size_t)n_gt * sizeof(uint2), st))) return s;
-    // binning unless the full 64-bit sort is asked for (or the segment grid would exceed the launch limit)
-    if (!full && bin_fits(B, d.n, g)) {
+    // binning unless the full 64-bit sort is asked for (or the segment grid would exceed the launch limit); a
+    // wrapped rectangle (periodic azimuth) is two column runs per row, which only the key emission enumerates
+    if (!full && !g.wrap && bin_fits(B, d.n, g)) {
         const bool spec = key_cap == 0 && spec_cap > 0 && spec_used;
         s = lists_binned(w, d, B, g, st, spec ? spec_cap : key_cap, spec);
         if (spec) *spec_used = true;
@@ -643,7 +775,7 @@ swf_status Ctx::lists_sorted(Workspace& w, const DevScene& d, int B, const Grid&
 }
 
 swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux,
-                       hipStream_t st, uint64_t key_cap, bool speculate) {
+                       hipStream_t st, uint64_t key_cap, bool speculate, float* chan) {
     if (!out) return fail(SWF_E_INVALID, "out is NULL");
     if ((flags & SWF_KEEP_AUX) && !aux) return fail(SWF_E_INVALID, "SWF_KEEP_AUX needs aux");
     hipSetDevice(device);
@@ -667,7 +799,10 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
         auxL = (uint32_t*)((char*)aux + sizeof(float) * (size_t)B * d.H * d.W);
     }
     stage_begin(SWF_STAGE_BLEND, st);
-    launch_blend_forward((const uint2*)w.ranges.ptr, w.last.vals, w.rec, B, w.last.grid, out, auxT, auxL, st);
+    if (d.kind == 1)
+        launch_gmm_blend((const uint2*)w.ranges.ptr, w.last.vals, w.rec, B, w.last.grid, out, chan, st);
+    else
+        launch_blend_forward((const uint2*)w.ranges.ptr, w.last.vals, w.rec, B, w.last.grid, out, auxT, auxL, st);
     stage_end(st);
     if ((s = hip(hipGetLastError(), "render launch"))) return s;
     if (spec) {
@@ -676,7 +811,7 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
         const uint64_t total = *w.total_host;
         if (total > spec_cap) {
             // did not fit: nothing was placed and the spectrum is zero; again at the exact size
-            s = render(w, sid, tx, B, flags, out, aux, st, 0, false);
+            s = render(w, sid, tx, B, flags, out, aux, st, 0, false, chan);
             w.last.rerenders = 1;
             return s;
         }
@@ -786,6 +921,23 @@ swf_status swf_render(swf_ctx* h, int32_t scene_id, const float* tx, int32_t bat
     return c->render(c->ws, scene_id, tx, batch, flags, out, aux, (hipStream_t)stream, 0, true);
 }
 
+swf_status swf_scene_upload_paper(swf_ctx* h, const swf_paper_gaussians* g, const swf_paper_mlp* mlp,
+                                  int32_t height, int32_t width, int32_t src_is_device, int32_t* scene_id) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    return c->upload_paper_scene(g, mlp, height, width, src_is_device != 0, scene_id);
+}
+
+swf_status swf_render_paper(swf_ctx* h, int32_t scene_id, const float* tx, int32_t batch, int32_t flags, float* out,
+                            float* channels, void* stream) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    Scene* sc = c->scene(scene_id);
+    if (!sc) return c->fail(SWF_E_NOT_FOUND, "unknown scene id");
+    if (sc->d.kind != 1) return c->fail(SWF_E_INVALID, "not a paper-model scene");
+    return c->render(c->ws, scene_id, tx, batch, flags, out, nullptr, (hipStream_t)stream, 0, true, channels);
+}
+
 swf_status swf_stage_timing(swf_ctx* h, int32_t enable) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     CTX_GUARD(c);
@@ -820,6 +972,13 @@ swf_status swf_debug_deform(swf_ctx* h, int32_t scene_id, const float* tx, int32
     if (flags & SWF_NO_DEFORM) return c->fail(SWF_E_INVALID, "deform debug needs the MLP");
     hipStream_t st = (hipStream_t)stream;
     const DevScene& d = sc->d;
+    if (d.kind == 1) {
+        // paper-model scene: 5 residuals per pair, already in id order
+        const Grid g = make_grid(d.H, d.W, 16);
+        swf_status s = c->enqueue_preprocess(c->ws, sc, tx, batch, flags, g, delta, st);
+        c->ws.last.valid = false;
+        return s ? s : c->hip(hipGetLastError(), "debug deform");
+    }
     const size_t cnt = (size_t)batch * d.n * kOut;
     swf_status s = c->ws.delta.reserve(c, cnt * sizeof(float) + 16, st);
     if (s) return s;

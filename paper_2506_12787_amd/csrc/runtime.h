@@ -55,7 +55,7 @@ struct LastRender {
 // Scratch memory of one render stream: every pipeline stage writes here.
 struct Workspace {
     Buf qs, geo, wm, oa, rect, count, off, scan, keys, keys2, vals, vals2, hist, ranges, bins, delta, sortk, sortv,
-        grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, stage, work;
+        grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, stage, work, beam, pool, ssim;
     Records rec;
     uint64_t* total_dev = nullptr;           // device status block: scan total, effective count, then:
     uint32_t* status_dev = nullptr;          //   status word (bit 0: key overflow at a fixed capacity)
@@ -67,7 +67,7 @@ struct Workspace {
     std::vector<Buf*> bufs() {
         return {&qs, &geo, &wm, &oa, &rect, &count, &off, &scan, &keys, &keys2, &vals, &vals2, &hist, &ranges, &bins,
                 &delta, &sortk, &sortv, &grad, &dpair, &dbase, &dy, &act, &dz, &part, &fmean, &ftx, &dmu,
-                &stage, &work};
+                &stage, &work, &beam, &pool, &ssim};
     }
     uint64_t generation() {
         uint64_t g = 0;
@@ -142,7 +142,9 @@ struct Ctx {
     // read back, instead of waiting for the count first; it renders again at
     // the exact size if the count did not fit.
     swf_status render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st,
-                      uint64_t key_cap = 0, bool speculate = false);
+                      uint64_t key_cap = 0, bool speculate = false, float* chan = nullptr);
+    swf_status upload_paper_scene(const swf_paper_gaussians* g, const swf_paper_mlp* mlp, int H, int W, bool dev,
+                                  int* id);
     swf_status backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out,
                         const void* aux, const swf_grads* grads, hipStream_t st);
     swf_status mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,
@@ -154,7 +156,7 @@ struct Ctx {
     void resolve_timing();
 };
 
-Grid make_grid(int H, int W, int tile);
+Grid make_grid(int H, int W, int tile, bool wrap = false);
 swf_status noalloc_setup(Ctx* c);  // resolves Ctx::noalloc_scratch (noalloc.hip)
 const char* status_name(swf_status s);
 void serve_shutdown(Ctx* c);

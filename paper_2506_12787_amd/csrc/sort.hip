@@ -152,12 +152,15 @@ __global__ __launch_bounds__(kThreads) void emit_keys_kernel(const uint2* __rest
     }
     const uint2 r = rect[i];
     const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+    // a wrapped rectangle (periodic azimuth, tx1 < tx0) spans columns tx0 .. TW-1, then 0 .. tx1
+    const int ncol = tx1 >= tx0 ? tx1 - tx0 + 1 : TW - tx0 + tx1 + 1;
     const uint32_t q = (uint32_t)(i / N);
     const uint32_t base = q * (uint32_t)tiles;
     const uint32_t db = kFull ? dbits[i % N] : 0u;
     uint64_t o = off;
     for (int ty = ty0; ty <= ty1; ++ty) {
-        for (int tx = tx0; tx <= tx1; ++tx) {
+        for (int k = 0; k < ncol; ++k) {
+            const int tx = tx0 + k < TW ? tx0 + k : tx0 + k - TW;
             const uint32_t gt = base + (uint32_t)(ty * TW + tx);
             if (kFull)
                 reinterpret_cast<uint64_t*>(keys)[o] = ((uint64_t)gt << 32) | db;

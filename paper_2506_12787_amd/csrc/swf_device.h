@@ -52,10 +52,15 @@ __device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v);
 
 // Deformed Gaussian -> record. mean = (mx0 + dmx, my0 + dmy); all other
 // parameters already deformed. tile is 8 or 16 (power of two, so the division
-// of an edge coordinate by the tile size is exact).
+// of an edge coordinate by the tile size is exact). wrap: azimuth is periodic
+// with period W (0 and 360 degrees are one direction): the box's columns are
+// taken modulo W. The box is shifted by whole periods so that its left edge
+// lies in [0, W); if its right edge then reaches W it continues at column 0,
+// which the record encodes as tx1 < tx0 (columns tx0 .. TW-1, then 0 .. tx1); a
+// box at least W wide, or whose two pieces meet, covers every column.
 __device__ __forceinline__ PairOut preprocess_pair(float mx0, float my0, float dmx, float dmy, float lsx, float lsy,
                                                    float rot, float logit, float amp, int W, int H, int TW, int TH,
-                                                   float inv_tile) {
+                                                   float inv_tile, int wrap = 0) {
     PairOut r;
     float mxh, mxl, myh, myl;
     two_sum(mx0, dmx, mxh, mxl);
@@ -76,7 +81,7 @@ __device__ __forceinline__ PairOut preprocess_pair(float mx0, float my0, float d
     const bool fin = finitef(x0) && finitef(x1) && finitef(y0) && finitef(y1) && finitef(r.wm.x) &&
                      finitef(r.wm.y) && finitef(r.wm.z) && finitef(r.wm.w) && finitef(op) && finitef(amp) &&
                      finitef(mxl) && finitef(myl);
-    const bool on = !(x1 < 0.0f) && !(x0 > (float)(W - 1)) && !(y1 < 0.0f) && !(y0 > (float)(H - 1));
+    const bool on = !(y1 < 0.0f) && !(y0 > (float)(H - 1)) && (wrap || (!(x1 < 0.0f) && !(x0 > (float)(W - 1))));
     if (!(fin && on)) {
         // culled: no tiles; rect_y keeps the reason for the status counters
         r.rect_x = 0;
@@ -84,13 +89,27 @@ __device__ __forceinline__ PairOut preprocess_pair(float mx0, float my0, float d
         r.count = 0;
         return r;
     }
-    const int tx0 = max(0, min(TW - 1, (int)floorf(x0 * inv_tile)));
-    const int tx1 = max(0, min(TW - 1, (int)floorf(x1 * inv_tile)));
+    int tx0, tx1;
+    if (!wrap) {
+        tx0 = max(0, min(TW - 1, (int)floorf(x0 * inv_tile)));
+        tx1 = max(0, min(TW - 1, (int)floorf(x1 * inv_tile)));
+    } else {
+        const float Wf = (float)W;
+        const float k = floorf(x0 / Wf);
+        const float a = x0 - k * Wf, b = x1 - k * Wf;
+        tx0 = min(TW - 1, (int)floorf(a * inv_tile));
+        tx1 = b < Wf ? min(TW - 1, (int)floorf(b * inv_tile)) : (int)floorf((b - Wf) * inv_tile);
+        if (x1 - x0 >= Wf || (b >= Wf && tx1 >= tx0 - 1)) {
+            tx0 = 0;
+            tx1 = TW - 1;
+        }
+    }
     const int ty0 = max(0, min(TH - 1, (int)floorf(y0 * inv_tile)));
     const int ty1 = max(0, min(TH - 1, (int)floorf(y1 * inv_tile)));
     r.rect_x = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
     r.rect_y = (uint32_t)ty0 | ((uint32_t)ty1 << 16);
-    r.count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    const int cols = tx1 >= tx0 ? tx1 - tx0 + 1 : TW - tx0 + tx1 + 1;
+    r.count = (uint32_t)(cols * (ty1 - ty0 + 1));
     return r;
 }
 
@@ -105,6 +124,30 @@ __device__ __forceinline__ float blend_q(float fx, float fy, float2 p, float4 m,
     w = fmaf(m.z, dx, m.w * dy);
     return fmaf(u, u, w * w);
 }
+// The same with periodic azimuth (period Wf, 1/Wf = rw): dx is taken to the
+// nearest image of the staged mean, which the staging already chose for the
+// tile, so the correction is zero except for pixels more than half a period
+// from that image (only a Gaussian wider than about half the grid reaches them).
+__device__ __forceinline__ float blend_q_wrap(float fx, float fy, float2 p, float4 m, float Wf, float rw, float& dx,
+                                              float& dy, float& u, float& w) {
+    dx = fx - p.x;
+    dx = fmaf(-Wf, rintf(dx * rw), dx);
+    dy = fy - p.y;
+    u = fmaf(m.x, dx, m.y * dy);
+    w = fmaf(m.z, dx, m.w * dy);
+    return fmaf(u, u, w * w);
+}
+
+// Block-relative staged mean of a record: (hi - block origin) + lo in full
+// precision. With periodic azimuth (Wf > 0) the hi part first moves by whole
+// periods to the image nearest the tile centre cx (exact: a multiple of an
+// integer subtracted from a value of at most a few periods).
+__device__ __forceinline__ float2 staged_mean(float4 g, float x0, float y0, float Wf, float cx) {
+    float hx = g.x - x0;
+    if (Wf > 0.0f) hx = fmaf(-Wf, rintf((hx - cx) / Wf), hx);
+    return make_float2(hx + g.z, (g.y - y0) + g.w);
+}
+
 // opacity * exp(-q/2) before the 0.99 clamp
 __device__ __forceinline__ float blend_raw_alpha(float q, float op) {
     return op * __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
