@@ -72,14 +72,15 @@ def parse():
                    help="summarise rocprofv3 counter CSVs (FETCH_SIZE / WRITE_SIZE runs of a --copy-probe-mib run) "
                         "into HBM bytes per launch of the MLP kernel, then exit")
     p.add_argument("--copy-mib", type=int, default=1024, help="copy size used by the counted run (for --pmc-summary)")
-    p.add_argument("--workload", choices=("headline", "large", "train", "beamscan", "rssi", "wrap", "protocol"), default="headline",
+    p.add_argument("--workload", choices=("headline", "large", "train", "beamscan", "rssi", "wrap", "protocol", "paper"), default="headline",
                    help="large: N=500k Gaussians (log-scales in [log 0.5, log 20] px), 360x1440 spectra, batch 256; "
                         "BF16 and FP32 MLP; prints its own JSON line (at most 5 timed steps, 1 warm-up). "
                         "train: training steps at N=50k, batch 16, 90x360 (forward with the blend state kept, L1 "
                         "loss, hand-written backward, Adam on Gaussians and MLP); prints its own JSON line. "
                         "beamscan: beam-scan spectra from multipath lists (batch 256, 90x360). rssi: the RSSI head "
                         "(16x16, 50 Gaussians, batch 1024). wrap: the headline batch with periodic azimuth. protocol: the "
-                        "paper's training protocol (fine stage) with beam-scan targets")
+                        "paper's training protocol (fine stage) with beam-scan targets. paper: the paper's own model (10k "
+                        "Gaussians, GMM sum, 8x156 FP32 MLP, batch 64)")
     return p.parse_args()
 
 
@@ -762,6 +763,80 @@ def bench_wrap(a):
     print(json.dumps(rec), flush=True)
 
 
+def bench_paper(a):
+    """The paper's own model (Sec. 4.1/4.2/6.1): N = 10k Gaussians (the paper's count), 90 x 360, batch 64 positions,
+    FP32 paper MLP (8 x 156 with skips), order-free GMM sum of complex responses; the plain one-query path beside."""
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+    H, W, N, Bq = 90, 360, 10_000, 64
+    g = synth.paper_gaussians(N, seed=1006)
+    Ws, bs = synth.paper_mlp_weights(seed=3006, out_scale=0.3)
+    ctx = B.Context(0)
+    sid = ctx.upload_paper_scene(g, H, W, mlp=(Ws, bs))
+    nbat = a.warmup + a.steps
+    tx = torch.from_numpy(synth.tx_positions(nbat * Bq, seed=2006)).cuda().view(nbat, Bq, 3)
+    out = torch.empty((Bq, H, W), device="cuda")
+    it = [0]
+
+    def call():
+        ctx.render_paper(sid, tx[it[0] % nbat], flags=B.MLP_FP32, out=out, channels=False)
+        it[0] += 1
+
+    ctx.stage_timing(True)
+    ctx.stage_times()
+    el, ms = _event_time(call, a.steps, a.warmup)
+    st = {k: v[0] / max(v[1], 1) for k, v in ctx.stage_times().items() if v[1] > 0}
+    ctx.stage_timing(False)
+    flop_pair = 2 * sum(o * i for o, i in synth.PAPER_LAYER_SHAPES)
+    flops = float(flop_pair) * N * Bq
+    mlp_ms = st["mlp_preprocess"]
+    rec = {"metric": "paper-model spectra/s at N=10k, 90x360, batch 64 (FP32)", "value": a.steps * Bq / el,
+           "unit": "spectra/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": "the paper's model: 10000 Cholesky Gaussians with tanh centres and complex "
+                                  "responses, order-free GMM sum, deformation MLP 81-8x156 (input skips at layers "
+                                  "3, 5, 7)-5 in FP32, 90x360 spectra, batch 64 positions", "n_gaussians": N,
+                      "height": H, "width": W, "batch": Bq},
+           "stages_ms_per_step": st,
+           "latency_us": {"batch_p50": 1e3 * pct(ms, 50), "batch_p99": 1e3 * pct(ms, 99)},
+           "roofline": {"kernel": "paper_mlp_kernel (FP32 MLP + deform + preprocess)", "bound": "alu",
+                        "achieved": flops / (mlp_ms * 1e-3) / 1e12, "peak": FP32_VALU_PEAK, "unit": "TFLOP/s",
+                        "frac": flops / (mlp_ms * 1e-3) / 1e12 / FP32_VALU_PEAK, "traffic": None,
+                        "flop_per_pair": flop_pair, "avg_launch_ms": mlp_ms,
+                        "note": "algorithmic FLOPs of the unpadded 156-wide layers; the kernel pads to 160 (and the "
+                                "skip layers' inputs to 256)"}}
+    # plain: one query per launch
+    o1 = torch.empty((1, H, W), device="cuda")
+    for i in range(2):
+        ctx.render_paper(sid, tx[0, i:i + 1].contiguous(), flags=B.MLP_FP32, out=o1, channels=False)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(16):
+        s0 = time.perf_counter()
+        ctx.render_paper(sid, tx[1, i:i + 1].contiguous(), flags=B.MLP_FP32, out=o1, channels=False)
+        torch.cuda.synchronize()
+        lat.append(1e6 * (time.perf_counter() - s0))
+    plain = 16 / (time.perf_counter() - t0)
+    rec["plain"] = {"value": plain, "unit": "spectra/s", "p50_us": pct(lat, 50), "p99_us": pct(lat, 99)}
+    rec["batched_over_plain"] = rec["value"] / plain
+    if not a.no_cpu_baseline:
+        from oracle import paper as P
+        txh = tx[0].cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < min(a.cpu_seconds, 12.0):
+            P.render_query(g, H, W, mlp=(Ws, bs), tx=txh[n % Bq])
+            n += 1
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": n / dt, "unit": "spectra/s", "cores": os.cpu_count(), "kind": "oracle",
+                               "cpu_model": cpu_model(),
+                               "sample": f"{n} full spectra (numpy FP64 MLP and GMM sum), {dt:.1f} s"}
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -779,8 +854,9 @@ def main():
     if a.workload == "train":
         bench_train(a)
         return
-    if a.workload in ("beamscan", "rssi", "wrap", "protocol"):
-        {"beamscan": bench_beamscan, "rssi": bench_rssi, "wrap": bench_wrap, "protocol": bench_protocol}[a.workload](a)
+    if a.workload in ("beamscan", "rssi", "wrap", "protocol", "paper"):
+        {"beamscan": bench_beamscan, "rssi": bench_rssi, "wrap": bench_wrap, "protocol": bench_protocol,
+         "paper": bench_paper}[a.workload](a)
         return
     import torch
     from paper_2506_12787_amd import binding as B

@@ -169,6 +169,37 @@ swf_status swf_scene_bytes(swf_ctx *ctx, int32_t scene_id, uint64_t *bytes);
 swf_status swf_render(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags, float *out,
                       void *aux, void *stream);
 
+/* Render on another resolution of the same field of view: the grid of the
+ * call, height x width (each in [1, 4096]), covers the elevation x azimuth
+ * range of the scene's own grid (the matrix of Sec. 3.1, e.g. 180 x 720 at
+ * 0.5 degree per pixel for a scene uploaded at 90 x 360), so scene pixel
+ * coordinates scale by (width / W, height / H): means, 3-sigma extents and
+ * covariances (Sigma' = S Sigma S) follow, the deformation MLP is unchanged
+ * (its mean features are normalised by the scene's own grid). out is
+ * batch x height x width. Works for both scene kinds (a paper-model scene
+ * renders its magnitude). SWF_KEEP_AUX needs the scene's own grid (the
+ * backward renders there): SWF_E_INVALID otherwise. Everything else as
+ * swf_render. */
+swf_status swf_render_at(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t height, int32_t width,
+                         int32_t flags, float *out, void *aux, void *stream);
+
+/* One launch sequence for queries over several resident scenes, each with its
+ * own Gaussian count, grid and deformation MLP (the problem statement's
+ * render(gaussians, tx) -> spectrum, Sec. 3.3, for a batch whose queries name
+ * different scenes; the serving loop's mixed batches). scene_ids: host int32
+ * [batch]; tx: device float32 [batch][3] (NULL with SWF_NO_DEFORM); out: device
+ * float32, the batch's spectra concatenated in query order (query b's H_b x W_b
+ * values start at out_offsets[b]); out_offsets (host, may be NULL) receives the
+ * batch + 1 offsets (the last is the total). Every query renders exactly the
+ * values swf_render gives it alone. flags: SWF_MLP_BF16 (every scene with a
+ * 4 x 256 MLP) or SWF_NO_DEFORM, optionally SWF_PAPER_DEFORM; compositing-model
+ * scenes only; lists are built by key sorting over every global tile of the
+ * batch. SWF_E_INVALID for other flags or scenes, SWF_E_NOT_FOUND for an
+ * unknown scene. Waits once for the batch's key count, like swf_render; the
+ * device status then describes the batch as one query holding every pair. */
+swf_status swf_render_mixed(swf_ctx *ctx, const int32_t *scene_ids, const float *tx, int32_t batch, int32_t flags,
+                            float *out, uint64_t *out_offsets, void *stream);
+
 /* ---- backward (hand-written; transmittance replayed back to front) --------
  * The gradient that training by back-propagation needs (Sec. 4.4, the loss
  * minimised over the Gaussians and the MLP; the derivative of the Sec. 3.2

@@ -353,19 +353,37 @@ def composite_held(rg0: dict, rg: dict, order: np.ndarray, pix_x: np.ndarray, pi
     return C
 
 
+def at_grid(g: dict, rg: dict, sx: float, sy: float):
+    """The deformed Gaussians seen on another resolution of the same field of view: pixel coordinates scale by
+    (sx, sy), so the means do and Sigma' = S Sigma S (S = diag(sx, sy))."""
+    g2 = dict(g)
+    g2["mx"] = g["mx"] * sx
+    g2["my"] = g["my"] * sy
+    r2 = dict(rg)
+    r2["mx"], r2["my"] = rg["mx"] * sx, rg["my"] * sy
+    r2["ixx"], r2["ixy"], r2["iyy"] = rg["ixx"] / (sx * sx), rg["ixy"] / (sx * sy), rg["iyy"] / (sy * sy)
+    r2["sxx"], r2["sxy"], r2["syy"] = rg["sxx"] * sx * sx, rg["sxy"] * sx * sy, rg["syy"] * sy * sy
+    return g2, r2
+
+
 def render_query(scene: Scene, mlp: MLP | None, tx, room=DEFAULT_ROOM, pix=None, margins=DEFAULT_MARGINS,
-                 bf16=False, delta=None, wrap=False):
+                 bf16=False, delta=None, wrap=False, grid=None):
     """Render one spectrum (the listed pixels, default the full H x W grid).
     wrap: azimuth is periodic with period W (each Gaussian acts through the
-    image of its mean nearest to the pixel)."""
+    image of its mean nearest to the pixel). grid: (H', W'), another
+    resolution of the same field of view (the scene's own by default)."""
     if delta is None:
         delta = deltas(scene, mlp, tx, room, bf16=bf16) if mlp is not None else None
     g = deform(scene, delta)
     rg = gaussians_for_raster(g, scene.depth)
+    H, W = scene.H, scene.W
+    if grid is not None and tuple(grid) != (H, W):
+        H, W = grid
+        g, rg = at_grid(g, rg, W / scene.W, H / scene.H)
     order = depth_order(scene.depth)
     if pix is None:
-        pix = full_grid(scene.H, scene.W)
-    res = composite(rg, order, pix[0], pix[1], margins, period=scene.W if wrap else 0.0)
+        pix = full_grid(H, W)
+    res = composite(rg, order, pix[0], pix[1], margins, period=W if wrap else 0.0)
     return res, g, rg, delta
 
 

@@ -135,10 +135,25 @@ def render(dg: dict, H, W, pix=None, margin=1e-4, chunk=4096):
     return np.hypot(re, im), re, im, bound
 
 
-def render_query(g: dict, H, W, mlp=None, tx=None, room=M.DEFAULT_ROOM, pix=None):
-    """(A, re, im, bound, delta) of one query: deformed by the MLP ((Ws, bs) lists) when given."""
+def at_grid(dg: dict, sx: float, sy: float) -> dict:
+    """Deformed Gaussians on another resolution of the same field of view: coordinates scale by (sx, sy), so the
+    centres do and Sigma' = S Sigma S."""
+    d2 = dict(dg)
+    d2["x"], d2["y"] = dg["x"] * sx, dg["y"] * sy
+    d2["ixx"], d2["ixy"], d2["iyy"] = dg["ixx"] / (sx * sx), dg["ixy"] / (sx * sy), dg["iyy"] / (sy * sy)
+    d2["sxx"], d2["syy"] = dg["sxx"] * sx * sx, dg["syy"] * sy * sy
+    return d2
+
+
+def render_query(g: dict, H, W, mlp=None, tx=None, room=M.DEFAULT_ROOM, pix=None, grid=None):
+    """(A, re, im, bound, delta) of one query: deformed by the MLP ((Ws, bs) lists) when given; grid = (H', W')
+    renders another resolution of the same field of view."""
     delta = None
     if mlp is not None:
         delta = mlp_forward(features(g, tx, H, W, room), mlp[0], mlp[1])
-    A, re, im, bound = render(deformed(g, H, W, delta), H, W, pix)
+    dg = deformed(g, H, W, delta)
+    if grid is not None and tuple(grid) != (H, W):
+        dg = at_grid(dg, grid[1] / W, grid[0] / H)
+        H, W = grid
+    A, re, im, bound = render(dg, H, W, pix)
     return A, re, im, bound, delta

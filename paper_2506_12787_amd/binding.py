@@ -117,6 +117,8 @@ def lib():
             "swf_hybrid_loss": [P, P, P, I32, I32, I32, ctypes.c_float, P, P, P],
             "swf_scene_upload_paper": [P, P, P, I32, I32, I32, P],
             "swf_render_paper": [P, I32, P, I32, I32, P, P, P],
+            "swf_render_mixed": [P, P, P, I32, I32, P, P, P],
+            "swf_render_at": [P, I32, P, I32, I32, I32, I32, P, P, P],
             "swf_render_rssi": [P, I32, P, I32, I32, P, P, P, P],
             "swf_render_rssi_backward": [P, I32, P, I32, I32, P, P, P, P],
             "swf_beamscan": [P, P, P, I32, I32, I32, ctypes.c_float, I32, I32, P, P],
@@ -327,6 +329,40 @@ class Context:
             aux = torch.empty((2, batch, H, W), device=self.device, dtype=torch.float32)
         self._check(self._L.swf_render(self._h, sid, _ptr(tx), batch, flags, _ptr(out), _ptr(aux), _stream()))
         return (out, aux) if (flags & KEEP_AUX) else out
+
+    def render_at(self, sid: int, height: int, width: int, tx=None, flags: int = 0, batch: int | None = None,
+                  out=None):
+        """Render on another resolution (height x width) of the scene's field of view."""
+        torch = self.torch
+        if tx is not None:
+            assert tx.is_cuda and tx.dtype == torch.float32 and tx.is_contiguous() and tx.shape[-1] == 3
+            batch = tx.shape[0]
+        batch = batch or 1
+        if out is None:
+            out = torch.empty((batch, height, width), device=self.device, dtype=torch.float32)
+        self._check(self._L.swf_render_at(self._h, sid, _ptr(tx), batch, height, width, flags, _ptr(out), None,
+                                          _stream()))
+        return out
+
+    def render_mixed(self, scene_ids, tx=None, flags: int = MLP_BF16):
+        """Queries over several scenes in one launch sequence: returns the list of per-query spectra (H_b, W_b),
+        views into one flat device buffer."""
+        torch = self.torch
+        ids = np.ascontiguousarray(scene_ids, dtype=np.int32)
+        B_ = len(ids)
+        # an unknown scene id gets no room here: the library rejects the batch (SWF_E_NOT_FOUND)
+        sizes = [self._keep[int(s)][0] * self._keep[int(s)][1] if int(s) in self._keep else 0 for s in ids]
+        out = torch.empty(max(int(sum(sizes)), 1), device=self.device, dtype=torch.float32)
+        offs = np.zeros(B_ + 1, np.uint64)
+        if tx is not None:
+            assert tx.is_cuda and tx.dtype == torch.float32 and tx.is_contiguous() and tx.shape == (B_, 3)
+        self._check(self._L.swf_render_mixed(self._h, ids.ctypes.data_as(ctypes.c_void_p), _ptr(tx), B_, flags,
+                                             _ptr(out), offs.ctypes.data_as(ctypes.c_void_p), _stream()))
+        res = []
+        for b, s in enumerate(ids):
+            H, W = self._keep[int(s)][:2]
+            res.append(out[int(offs[b]):int(offs[b + 1])].view(H, W))
+        return res
 
     def render_backward(self, sid: int, tx, flags: int, grad_out, aux, grads: dict):
         """Gradients of sum(grad_out * out) into the caller's device tensors in

@@ -25,7 +25,10 @@ __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
 // kWrap: periodic azimuth (period W): each staged mean is the image nearest the
 // tile, every evaluation takes the displacement to the nearest image, and an
 // entry whose image lies nearly half a period from the tile is not culled.
-template <int TILE, bool kCount = false, bool kAux = true, bool kWrap = false>
+// kMix: the workgroup's global tile belongs to a query of a mixed batch (its
+// query, grid and output offset come from the batch's tables; workgroups past
+// the batch's tiles exit).
+template <int TILE, bool kCount = false, bool kAux = true, bool kWrap = false, bool kMix = false>
 __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ vals,
                                                                     const float4* __restrict__ geo,
@@ -34,7 +37,8 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
                                                                     int TW, int tiles, float* __restrict__ out,
                                                                     float* __restrict__ aux_T,
                                                                     uint32_t* __restrict__ aux_last,
-                                                                    unsigned long long* __restrict__ work = nullptr) {
+                                                                    unsigned long long* __restrict__ work = nullptr,
+                                                                    MixBatch mix = MixBatch{}) {
     constexpr int kN = TILE * TILE;
     constexpr int kUnroll = 8;  // entries per unrolled group (kN is a multiple)
     static_assert(kN % 64 == 0, "whole waves per tile");
@@ -57,8 +61,22 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     }
 
     const int gtile = blockIdx.x;
-    const int b = gtile / tiles;
-    const int t = gtile - b * tiles;
+    int b, t;
+    if constexpr (kMix) {
+        // uniform over the workgroup: a query of the batch and its scene's grid
+        if (gtile >= mix.queries[mix.B].tile_base) return;
+        const int q = mix_find(mix.queries, mix.B, gtile, [](const MixQuery& x) { return x.tile_base; });
+        const MixScene& sc = mix.scenes[mix.queries[q].scene];
+        H = sc.H;
+        W = sc.W;
+        TW = sc.TW;
+        t = gtile - mix.queries[q].tile_base;
+        out += mix.queries[q].out_base;
+        b = 0;
+    } else {
+        b = gtile / tiles;
+        t = gtile - b * tiles;
+    }
     const int tx = t % TW, ty = t / TW;
     // culled 16x16 tiles: wave w covers the 8x8 quadrant (w & 1, w >> 1) and
     // lane l its pixel (l & 7, l >> 3); otherwise pixels are row-major
@@ -216,6 +234,13 @@ void blend_launch(const uint2* ranges, const uint32_t* vals, const Records& r, u
 }
 
 }  // namespace
+
+void launch_mix_blend(const MixBatch& m, int tile_cap, const uint2* ranges, const uint32_t* vals, const Records& r,
+                      float* out, hipStream_t st) {
+    if (tile_cap <= 0) return;
+    blend_forward_kernel<16, false, false, false, true><<<(unsigned)tile_cap, 256, 0, st>>>(
+        ranges, vals, r.geo, r.wm, r.oa, 0, 0, 0, 0, out, nullptr, nullptr, nullptr, m);
+}
 
 void launch_blend_work(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
                        unsigned long long* work, hipStream_t st) {

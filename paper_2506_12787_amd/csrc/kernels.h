@@ -63,11 +63,12 @@ struct Records {
 struct Grid {
     int H, W, tile, TW, TH, tiles;  // tiles per query
     int wrap;                       // 1: periodic azimuth (period W)
+    float sx, sy;                   // render pixels per scene pixel (1 at the scene's own grid)
 };
 
 struct PaperArgs {
     int N, B, H, W, TW, TH, wrap;
-    float inv_tile;
+    float inv_tile, sx, sy;
     const float4* cen;
     const float *l1, *l2, *l3, *att, *pre, *pim;
     const float* feat;  // [N][48] centre features
@@ -80,6 +81,58 @@ struct PaperArgs {
     Records rec;
     float* delta_out;  // [B * N][5] residuals (debug), or null
 };
+
+// A batch of queries over several resident scenes, each with its own Gaussian
+// count and grid (mixed.hip): a table of the distinct scenes and one of the
+// queries (B + 1 entries; the last holds the totals), both in device memory.
+struct MixScene {
+    const float *mx, *my, *lsx, *lsy, *rot, *logit, *amp;  // canonical parameters, (depth, id) order
+    const float *w1, *b1;                                   // layer 1, row-major [256][89], for the TX term
+    const uint16_t* stream;                                 // BF16 weight stream
+    const uint16_t* mfeat;                                  // BF16 gamma(mu_hat) [N][32]
+    const float* bias_h[7];
+    const float* bias_o;
+    float room_lo[3], room_hi[3];
+    int N, n_live, H, W, TW, TH, tiles;
+};
+struct MixQuery {
+    int scene;          // index into the scene table
+    int pair_base;      // first record of the query
+    int tile_base;      // first global tile of the query
+    int out_base;       // first output value of the query (spectra concatenated in query order)
+    int mlp_tile_base;  // first MLP tile (block of pairs) of the query
+};
+struct MixBatch {
+    const MixScene* scenes;
+    const MixQuery* queries;
+    int B;
+};
+// Index q of the query whose range [field(q), field(q + 1)) holds v (B + 1 entries, non-decreasing).
+template <typename F>
+__device__ __forceinline__ int mix_find(const MixQuery* qs, int B, int v, F field) {
+    int lo = 0, hi = B;  // field(lo) <= v < field(hi)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (field(qs[mid]) <= v)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// mixed.hip
+void launch_mix_tx_features(const MixBatch& m, const float* tx, float* qs, hipStream_t st);
+void launch_mix_static(const MixBatch& m, int64_t pair_cap, const Grid& tile, const Records& r, hipStream_t st);
+void launch_mix_emit_keys(const MixBatch& m, const Records& r, const uint32_t* offsets, int64_t pair_cap,
+                          uint64_t capacity, uint32_t* keys, uint32_t* vals, uint32_t* status,
+                          unsigned long long* cull, hipStream_t st);
+// blend.hip: one workgroup per global tile of the batch, tile_cap of them (the extra ones exit)
+void launch_mix_blend(const MixBatch& m, int tile_cap, const uint2* ranges, const uint32_t* vals, const Records& r,
+                      float* out, hipStream_t st);
+// mlp_bf16.hip: the BF16 MLP over the batch's tiles of pairs (the default 384-pair variant)
+void launch_mix_mlp_bf16(const MixBatch& m, const float* qs, const Records& r, hipStream_t st, bool paper_mask,
+                         bool wrap);
 
 // paper.hip
 void launch_paper_centers(const DevScene& d, hipStream_t st);

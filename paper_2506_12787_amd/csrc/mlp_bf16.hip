@@ -65,7 +65,28 @@ struct Bf16Args {
     int tiles_per_query;      // ceil(N / pairs per block): tiles never straddle two queries
     uint16_t* act_out;        // kAct: hidden activations (bf16 bits) [n_hidden][B * N][256]
     int64_t act_stride;       // elements per activation layer: B * N * 256
+    MixBatch mix;             // kMix: the batch's scene and query tables (per tile: query, scene, stream, biases)
 };
+
+// Records of a mixed batch's pair: residuals -> deformed Gaussian -> record, with the pair's own scene.
+__device__ __forceinline__ void mix_epilogue(const MixScene& s, const MlpArgs& a, size_t row, int p, const float* d) {
+    float dv[kOut];
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) dv[k] = d[k];
+    if (a.paper_mask) dv[2] = dv[3] = dv[4] = 0.0f;
+    PairOut o;
+    if (p < s.n_live) {
+        o = preprocess_pair(s.mx[p], s.my[p], dv[0], dv[1], s.lsx[p] + dv[2], s.lsy[p] + dv[3], s.rot[p] + dv[4],
+                            s.logit[p] + dv[5], s.amp[p] + dv[6], s.W, s.H, s.TW, s.TH, a.inv_tile, a.wrap);
+    } else {
+        o.geo = make_float4(0, 0, 0, 0);
+        o.wm = make_float4(0, 0, 0, 0);
+        o.oa = make_float2(0, 0);
+        o.rect_x = o.rect_y = 0;
+        o.count = 0;
+    }
+    write_record(a.rec, row, o);
+}
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -121,7 +142,12 @@ __device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0
 // + bf16 conversion into the next layer's act[c'] is issued among the MFMAs of
 // the following tile (one column block per two fragments) instead of after
 // the layer; the last pair is converted during the next layer's first tile.
-template <int NCB, int WAVES, int STEP, int WPE, bool kAct>
+//
+// kMix: the tiles belong to the queries of a mixed batch (per tile its query,
+// scene, pair count, weight stream and biases from the batch's tables); the
+// ring fetches each step from the stream of the tile it belongs to, and the
+// next tile's biases are copied into the other half of a double buffer.
+template <int NCB, int WAVES, int STEP, int WPE, bool kAct, bool kMix = false>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void
 mlp_bf16_kernel(Bf16Args a) {
     typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -135,8 +161,9 @@ mlp_bf16_kernel(Bf16Args a) {
     // Layer-1 TX term of the current and the next tile's query, hidden and
     // output biases: C operands read from LDS.
     __shared__ __attribute__((aligned(16))) float qs_s[2][256];
-    __shared__ __attribute__((aligned(16))) float bias_s[7][256];
-    __shared__ __attribute__((aligned(16))) float bias_o_s[16];
+    constexpr int kBiasBufs = kMix ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) float bias_s[kBiasBufs][7][256];
+    __shared__ __attribute__((aligned(16))) float bias_o_s[kBiasBufs][16];
     // Layer-1 B operand of the wave's pairs (bf16 gamma(mu_hat), lane order),
     // copied global -> LDS one tile ahead.
     __shared__ __attribute__((aligned(16))) uint4 bm_s[WAVES][NCB][64];
@@ -150,14 +177,34 @@ mlp_bf16_kernel(Bf16Args a) {
     const int n_mid = a.m.n_mid;
 
     // tiles of this persistent workgroup
-    const int my_tiles = a.n_tiles > (int)blockIdx.x ? (a.n_tiles - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
+    const int n_tiles = kMix ? a.mix.queries[a.mix.B].mlp_tile_base : a.n_tiles;
+    const int my_tiles = n_tiles > (int)blockIdx.x ? (n_tiles - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
     if (my_tiles == 0) return;
     const int q_end = my_tiles * S;  // ring steps of this workgroup
+    // query of a tile (block-uniform)
+    auto tile_query = [&](int t) {
+        if constexpr (kMix)
+            return mix_find(a.mix.queries, a.mix.B, t, [](const MixQuery& x) { return x.mlp_tile_base; });
+        else
+            return t / a.tiles_per_query;
+    };
     if (tid < 256) {
-        for (int l = 0; l < n_mid; ++l) bias_s[l][tid] = a.bias_h[l][tid];
-        if (tid < 16) bias_o_s[tid] = tid < kOut ? a.bias_o[tid] : 0.0f;
-        qs_s[0][tid] = a.m.qs[(size_t)((int)blockIdx.x / a.tiles_per_query) * 256 + tid];
+        const int q0 = tile_query((int)blockIdx.x);
+        if constexpr (kMix) {
+            const MixScene& s0 = a.mix.scenes[a.mix.queries[q0].scene];
+            for (int l = 0; l < n_mid; ++l) bias_s[0][l][tid] = s0.bias_h[l][tid];
+            if (tid < 16) bias_o_s[0][tid] = tid < kOut ? s0.bias_o[tid] : 0.0f;
+        } else {
+            for (int l = 0; l < n_mid; ++l) bias_s[0][l][tid] = a.bias_h[l][tid];
+            if (tid < 16) bias_o_s[0][tid] = tid < kOut ? a.bias_o[tid] : 0.0f;
+        }
+        qs_s[0][tid] = a.m.qs[(size_t)q0 * 256 + tid];
     }
+    // weight stream of the tile the ring is fetching for (kMix: it changes with the tile's scene)
+    int fetch_it = 0;
+    const uint4* fstream = a.stream;
+    if constexpr (kMix) fstream = reinterpret_cast<const uint4*>(
+        a.mix.scenes[a.mix.queries[tile_query((int)blockIdx.x)].scene].stream);
 
     int fetch = 0;  // stream step of the next copy
     const uint32_t ring_lds = (uint32_t)(uintptr_t)(lds_ptr)ring;  // LDS byte address of the ring
@@ -168,11 +215,18 @@ mlp_bf16_kernel(Bf16Args a) {
     do {                                                                                                   \
         const int unit_ = STEP == 32 ? (fetch == 0 ? 0 : 2 * fetch - 1) : fetch;                           \
         const int nf_ = fetch == 0 ? 16 : (fetch == S - 1 ? 8 : STEP);                                    \
-        const uint4* src_ = a.stream + (size_t)unit_ * kUnitU4 + tid;                                      \
+        const uint4* src_ = fstream + (size_t)unit_ * kUnitU4 + tid;                                       \
         const uint32_t dst_ = ring_lds + (uint32_t)((slot_) * STEP * 1024 + wave * 1024);                  \
         _Pragma("unroll") for (int i_ = 0; i_ < STEP / WAVES; ++i_)                                        \
             if (i_ * WAVES + wave < nf_) dma_b128(src_ + i_ * 64 * WAVES, dst_ + i_ * 1024 * WAVES);       \
         fetch = fetch + 1 == S ? 0 : fetch + 1;                                                            \
+        if (kMix && fetch == 0) {                                                                          \
+            ++fetch_it;                                                                                    \
+            const int ft_ = (int)blockIdx.x + fetch_it * (int)gridDim.x;                                   \
+            if (ft_ < n_tiles)                                                                             \
+                fstream = reinterpret_cast<const uint4*>(                                                  \
+                    a.mix.scenes[a.mix.queries[tile_query(ft_)].scene].stream);                            \
+        }                                                                                                  \
     } while (0)
     // gamma(mu_hat) of the pairs of tile t_ into bm_s (rows past N read row
     // N - 1; layer 1 zeroes them); awaited by the wait before the next barrier.
@@ -180,11 +234,19 @@ mlp_bf16_kernel(Bf16Args a) {
 #define SWF_FETCH_BM(tile_)                                                                              \
     do {                                                                                                 \
         const int t_ = (tile_);                                                                          \
-        const int qy_ = t_ / a.tiles_per_query;                                                          \
-        const int pp_ = (t_ - qy_ * a.tiles_per_query) * kPairsPerBlock + wave * kPairsPerWave;          \
+        const int qy_ = tile_query(t_);                                                                  \
+        int tb_ = qy_ * a.tiles_per_query, nq_ = a.m.N;                                                  \
+        const bf16x8* mf_ = a.mfeat;                                                                     \
+        if (kMix) {                                                                                      \
+            const MixScene& sc_ = a.mix.scenes[a.mix.queries[qy_].scene];                                \
+            tb_ = a.mix.queries[qy_].mlp_tile_base;                                                      \
+            nq_ = sc_.N;                                                                                 \
+            mf_ = reinterpret_cast<const bf16x8*>(sc_.mfeat);                                            \
+        }                                                                                                \
+        const int pp_ = (t_ - tb_) * kPairsPerBlock + wave * kPairsPerWave;                              \
         _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) {                                             \
-            const int p_ = min(pp_ + cb * 16 + n16, a.m.N - 1);                                          \
-            dma_b128(reinterpret_cast<const uint4*>(a.mfeat) + (size_t)p_ * 4 + g, bm_lds + cb * 1024);  \
+            const int p_ = min(pp_ + cb * 16 + n16, nq_ - 1);                                            \
+            dma_b128(reinterpret_cast<const uint4*>(mf_) + (size_t)p_ * 4 + g, bm_lds + cb * 1024);      \
         }                                                                                                \
     } while (0)
     SWF_FETCH_BM((int)blockIdx.x);
@@ -247,7 +309,7 @@ mlp_bf16_kernel(Bf16Args a) {
     // layer is still unconverted; it becomes act[IN_][7] during tile 0.
 #define SWF_HIDDEN(IN_, OUT_, L_)                                                                        \
     do {                                                                                                 \
-        const float* bias_ = &bias_s[(L_)][4 * g];                                                       \
+        const float* bias_ = &bias_s[kMix ? (it & 1) : 0][(L_)][4 * g];                                  \
         _Pragma("unroll") for (int t = 0; t < 16; ++t) {                                                 \
             _Pragma("unroll") for (int c = 0; c < 8; ++c) {                                              \
                 const int f = (t * 8 + c) % STEP;                                                        \
@@ -278,7 +340,7 @@ mlp_bf16_kernel(Bf16Args a) {
     do {                                                                                                 \
         SWF_ADVANCE();                                                                                   \
         f32x4 o[NCB];                                                                                    \
-        const float4 b4 = *reinterpret_cast<const float4*>(&bias_o_s[4 * g]);                            \
+        const float4 b4 = *reinterpret_cast<const float4*>(&bias_o_s[kMix ? (it & 1) : 0][4 * g]);       \
         _Pragma("unroll") for (int cb = 0; cb < NCB; ++cb) o[cb] = f32x4{b4.x, b4.y, b4.z, b4.w};        \
         _Pragma("unroll") for (int c = 0; c < 8; ++c) {                                                  \
             bf16x8 w;                                                                                    \
@@ -296,15 +358,21 @@ mlp_bf16_kernel(Bf16Args a) {
 
     for (int it = 0; it < my_tiles; ++it) {
         const int tile = (int)blockIdx.x + it * (int)gridDim.x;
-        const int qry = tile / a.tiles_per_query;                  // block-uniform query
-        const int p0 = (tile - qry * a.tiles_per_query) * kPairsPerBlock + wave * kPairsPerWave;
-        const size_t row0 = (size_t)qry * a.m.N;                   // first pair of the query
+        const int qry = tile_query(tile);                          // block-uniform query
+        int Nq = a.m.N, tb = qry * a.tiles_per_query;              // its pairs and first tile
+        size_t row0 = (size_t)qry * a.m.N;                         // first pair of the query
+        if constexpr (kMix) {
+            Nq = a.mix.scenes[a.mix.queries[qry].scene].N;
+            tb = a.mix.queries[qry].mlp_tile_base;
+            row0 = (size_t)a.mix.queries[qry].pair_base;
+        }
+        const int p0 = (tile - tb) * kPairsPerBlock + wave * kPairsPerWave;
         // ---- layer 1 (mean part, K = 32): B = bf16 gamma(mu_hat); C = TX term of the query ----
         bf16x8 bm[NCB];
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             const int p = p0 + cb * 16 + n16;
-            bm[cb] = p < a.m.N ? __builtin_bit_cast(bf16x8, bm_s[wave][cb][lane]) : bf16x8{};
+            bm[cb] = p < Nq ? __builtin_bit_cast(bf16x8, bm_s[wave][cb][lane]) : bf16x8{};
         }
         SWF_ADVANCE();
         {
@@ -334,7 +402,7 @@ mlp_bf16_kernel(Bf16Args a) {
         // last barrier (the other buffer is read by this tile's layer 1 only)
         const int next_tile = tile + (int)gridDim.x;
         const float qs_next =
-            it + 1 < my_tiles && tid < 256 ? a.m.qs[(size_t)(next_tile / a.tiles_per_query) * 256 + tid] : 0.0f;
+            it + 1 < my_tiles && tid < 256 ? a.m.qs[(size_t)tile_query(next_tile) * 256 + tid] : 0.0f;
         // ---- hidden layers, two per iteration so the act buffers alternate statically ----
         int l = 0;
         for (; l + 1 < n_mid; l += 2) {
@@ -348,10 +416,28 @@ mlp_bf16_kernel(Bf16Args a) {
             SWF_OUTPUT(0);
         }
         if (tid < 256) qs_s[(it + 1) & 1][tid] = qs_next;
+        if constexpr (kMix) {
+            // the next tile's biases into the other half of the double buffer (its previous reader, the tile
+            // before this one, is done): hidden layers by wave, one 1 KiB piece each, global -> LDS, awaited
+            // before the barrier below
+            if (it + 1 < my_tiles) {
+                const MixScene& sn = a.mix.scenes[a.mix.queries[tile_query(next_tile)].scene];
+                const int nb = (it + 1) & 1;
+                if (wave < n_mid)
+                    dma_b128(reinterpret_cast<const uint4*>(sn.bias_h[wave]) + lane,
+                             (uint32_t)(uintptr_t)(lds_ptr)&bias_s[nb][wave][0]);
+                if (tid < 16) bias_o_s[nb][tid] = tid < kOut ? sn.bias_o[tid] : 0.0f;
+            }
+        }
         SWF_NEXT_STEP();
         if (lane < kPairsPerWave) {
             const int p = p0 + lane;
-            if (p < a.m.N) deform_epilogue(a.m, row0 + p, p, outs[wave][lane]);
+            if (p < Nq) {
+                if constexpr (kMix)
+                    mix_epilogue(a.mix.scenes[a.mix.queries[qry].scene], a.m, row0 + p, p, outs[wave][lane]);
+                else
+                    deform_epilogue(a.m, row0 + p, p, outs[wave][lane]);
+            }
         }
         // `outs` is rewritten only after the next tile's first barrier
     }
@@ -413,6 +499,29 @@ void launch_variant(Bf16Args a, int n, int B, int n_hidden, hipStream_t st) {
     if (!a.n_tiles) return;
     const int blocks = std::min(a.n_tiles, n_compute_units() * resident);
     mlp_bf16_kernel<NCB, WAVES, STEP, WPE, kAct><<<blocks, 64 * WAVES, 0, st>>>(a);
+}
+
+void launch_mix_mlp_bf16(const MixBatch& m, const float* qs, const Records& r, hipStream_t st, bool paper_mask,
+                         bool wrap) {
+    // the default variant (384-pair tiles, 8 waves of 48 pairs) over the batch's tiles; every scene of a mixed
+    // batch has four hidden layers of 256
+    constexpr int NCB = 3, WAVES = 8, STEP = 32, WPE = 2;
+    static const int resident = [] {
+        int rr = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &rr, mlp_bf16_kernel<NCB, WAVES, STEP, WPE, false, true>, 64 * WAVES, 0);
+        return (e == hipSuccess && rr > 0) ? rr : 1;
+    }();
+    Bf16Args a{};
+    a.m.rec = r;
+    a.m.qs = qs;
+    a.m.n_mid = 3;
+    a.m.inv_tile = 1.0f / 16.0f;
+    a.m.paper_mask = paper_mask ? 1 : 0;
+    a.m.wrap = wrap ? 1 : 0;
+    a.n_steps = 2 + (128 / STEP) * 3;
+    a.mix = m;
+    mlp_bf16_kernel<NCB, WAVES, STEP, WPE, false, true><<<n_compute_units() * resident, 64 * WAVES, 0, st>>>(a);
 }
 
 void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,

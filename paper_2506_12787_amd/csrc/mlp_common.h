@@ -19,6 +19,8 @@ struct MlpArgs {
     float inv_tile;
     int paper_mask;
     int wrap;            // periodic azimuth: tile rectangles wrap around the grid width
+    int sW, sH;          // the scene's own grid (the mean features' normalisation)
+    float sx, sy;        // render pixels per scene pixel
     const float *mx, *my, *lsx, *lsy, *rot, *logit, *amp;
     const float* qs;
     const float* w1m_t;
@@ -45,7 +47,8 @@ __device__ __forceinline__ void deform_epilogue(const MlpArgs& a, size_t row, in
     PairOut o;
     if (p < a.n_live) {
         o = preprocess_pair(a.mx[p], a.my[p], dv[0], dv[1], a.lsx[p] + dv[2], a.lsy[p] + dv[3], a.rot[p] + dv[4],
-                            a.logit[p] + dv[5], a.amp[p] + dv[6], a.W, a.H, a.TW, a.TH, a.inv_tile, a.wrap);
+                            a.logit[p] + dv[5], a.amp[p] + dv[6], a.W, a.H, a.TW, a.TH, a.inv_tile, a.wrap, a.sx,
+                            a.sy);
     } else {
         o.geo = make_float4(0, 0, 0, 0);
         o.wm = make_float4(0, 0, 0, 0);
@@ -69,6 +72,10 @@ inline MlpArgs make_args(const DevScene& s, const float* qs, int B, const Grid& 
     a.inv_tile = 1.0f / (float)g.tile;
     a.paper_mask = paper_mask ? 1 : 0;
     a.wrap = g.wrap;
+    a.sW = s.W;
+    a.sH = s.H;
+    a.sx = g.sx;
+    a.sy = g.sy;
     a.mx = s.mx; a.my = s.my; a.lsx = s.lsx; a.lsy = s.lsy; a.rot = s.rot; a.logit = s.logit; a.amp = s.amp;
     a.qs = qs;
     a.w1m_t = s.w1m_t;

@@ -32,8 +32,8 @@ __device__ __forceinline__ void write_rec(const Records& r, size_t row, const Pa
 // Deformed paper Gaussian -> record. cen = canonical centre (x_hi, y_hi, x_lo,
 // y_lo); d = residuals (d_mu_x, d_mu_y, d_psi_re, d_psi_im, d_delta) or null.
 __device__ __forceinline__ PairOut paper_pair(float4 cen, float l1, float l2, float l3, float a, float pr, float pi,
-                                              const float* d, int W, int H, int TW, int TH, float inv_tile,
-                                              int wrap) {
+                                              const float* d, int W, int H, int TW, int TH, float inv_tile, int wrap,
+                                              float gsx, float gsy) {
     PairOut r;
     float xh = cen.x, xl = cen.z, yh = cen.y, yl = cen.w;
     float dl = 1.0f / (1.0f + expf(-a));
@@ -60,11 +60,14 @@ __device__ __forceinline__ PairOut paper_pair(float4 cen, float l1, float l2, fl
         yl = e;
     }
     const float i1 = 1.0f / l1, i3 = 1.0f / l3;
+    float4 wmv = make_float4(i1, 0.0f, -l2 * i1 * i3, i3);
+    float hx = 3.0f * fabsf(l1), hy = 3.0f * sqrtf(fmaf(l2, l2, l3 * l3));
+    if (gsx != 1.0f || gsy != 1.0f) rescale_to_grid(gsx, gsy, xh, xl, yh, yl, hx, hy, wmv);
+    hx += kExtentEps;
+    hy += kExtentEps;
     r.geo = make_float4(xh, yh, xl, yl);
-    r.wm = make_float4(i1, 0.0f, -l2 * i1 * i3, i3);
+    r.wm = wmv;
     r.oa = make_float2(dl * pr, dl * pi);
-    const float hx = 3.0f * fabsf(l1) + kExtentEps;
-    const float hy = 3.0f * sqrtf(fmaf(l2, l2, l3 * l3)) + kExtentEps;
     const float x0 = xh - hx, x1 = xh + hx, y0 = yh - hy, y1 = yh + hy;
     const bool fin = l1 != 0.0f && l3 != 0.0f && finitef(x0) && finitef(x1) && finitef(y0) && finitef(y1) &&
                      finitef(r.wm.x) && finitef(r.wm.z) && finitef(r.wm.w) && finitef(r.oa.x) && finitef(r.oa.y) &&
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(256) void paper_static_kernel(PaperArgs a) {
     if (row >= total) return;
     const int p = (int)(row % a.N);
     const PairOut o = paper_pair(a.cen[p], a.l1[p], a.l2[p], a.l3[p], a.att[p], a.pre[p], a.pim[p], nullptr, a.W,
-                                 a.H, a.TW, a.TH, a.inv_tile, a.wrap);
+                                 a.H, a.TW, a.TH, a.inv_tile, a.wrap, a.sx, a.sy);
     write_rec(a.rec, row, o);
 }
 
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(160, 2) void paper_mlp_kernel(PaperArgs a) {
 #pragma unroll
                 for (int k = 0; k < kPaperOut; ++k) a.delta_out[row * kPaperOut + k] = d[k];
             const PairOut o = paper_pair(a.cen[p], a.l1[p], a.l2[p], a.l3[p], a.att[p], a.pre[p], a.pim[p], d, a.W,
-                                         a.H, a.TW, a.TH, a.inv_tile, a.wrap);
+                                         a.H, a.TW, a.TH, a.inv_tile, a.wrap, a.sx, a.sy);
             if (a.rec.geo) write_rec(a.rec, row, o);
         }
     }
@@ -399,6 +402,8 @@ static PaperArgs paper_args(const DevScene& d, int B, const Grid& g, const Recor
     a.TW = g.TW;
     a.TH = g.TH;
     a.wrap = g.wrap;
+    a.sx = g.sx;
+    a.sy = g.sy;
     a.inv_tile = 1.0f / (float)g.tile;
     a.cen = d.pcen;
     a.l1 = d.pl1;

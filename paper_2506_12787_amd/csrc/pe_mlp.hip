@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256, 2) void mlp_fp32_kernel(MlpArgs a) {
         float f[kMeanFeat];
         if (row < total) {
             const int p = (int)(row % a.N);
-            mean_features(a.mx[p], a.my[p], a.W, a.H, f);
+            mean_features(a.mx[p], a.my[p], a.sW, a.sH, f);
         } else {
 #pragma unroll
             for (int k = 0; k < kMeanFeat; ++k) f[k] = 0.f;
@@ -210,7 +210,7 @@ __global__ void preprocess_static_kernel(MlpArgs a) {
     PairOut o;
     if (p < a.n_live) {
         o = preprocess_pair(a.mx[p], a.my[p], 0.f, 0.f, a.lsx[p], a.lsy[p], a.rot[p], a.logit[p], a.amp[p], a.W, a.H,
-                            a.TW, a.TH, a.inv_tile, a.wrap);
+                            a.TW, a.TH, a.inv_tile, a.wrap, a.sx, a.sy);
     } else {
         o.geo = make_float4(0, 0, 0, 0);
         o.wm = make_float4(0, 0, 0, 0);

@@ -78,6 +78,9 @@ swf_status Workspace::init(Ctx* c) {
 
 void Workspace::release() {
     for (Buf* b : bufs()) b->release();
+    if (mix_host) hipHostFree(mix_host);
+    mix_host = nullptr;
+    mix_host_cap = 0;
     if (total_dev) hipFree(total_dev);
     if (total_host) hipHostFree(total_host);
     if (total_ev) hipEventDestroy(total_ev);
@@ -98,9 +101,11 @@ static int bits_for(uint64_t m) {
     return b;
 }
 
-Grid make_grid(int H, int W, int tile, bool wrap) {
+Grid make_grid(int H, int W, int tile, bool wrap, float sx, float sy) {
     Grid g;
     g.wrap = wrap ? 1 : 0;
+    g.sx = sx;
+    g.sy = sy;
     g.H = H;
     g.W = W;
     g.tile = tile;
@@ -630,14 +635,18 @@ swf_status Ctx::enqueue_preprocess(Workspace& w, Scene* sc, const float* tx, int
 // Forward up to the per-tile lists: preprocess (+ MLP), scan, keys, sort,
 // tile ranges. Records the result in `last`.
 swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int flags, hipStream_t st,
-                              uint64_t key_cap, uint64_t spec_cap, bool* spec_used) {
+                              uint64_t key_cap, uint64_t spec_cap, bool* spec_used, int rH, int rW) {
     if (spec_used) *spec_used = false;
     Scene* sc = scene(sid);
     if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
     if (B < 1) return fail(SWF_E_INVALID, "batch must be >= 1");
     const DevScene& d = sc->d;
     if ((uint64_t)B * (uint64_t)d.n >= (1ull << 32)) return fail(SWF_E_INVALID, "batch * n must be < 2^32");
-    const Grid g = make_grid(d.H, d.W, (flags & SWF_TILE8) ? 8 : 16, (flags & SWF_WRAP_AZIMUTH) != 0);
+    // the scene's own grid, or another resolution of the same field of view
+    const int gH = rH > 0 ? rH : d.H, gW = rW > 0 ? rW : d.W;
+    if (gH > 4096 || gW > 4096) return fail(SWF_E_INVALID, "height and width must lie in [1, 4096]");
+    const Grid g = make_grid(gH, gW, (flags & SWF_TILE8) ? 8 : 16, (flags & SWF_WRAP_AZIMUTH) != 0,
+                             gW == d.W ? 1.0f : (float)((double)gW / d.W), gH == d.H ? 1.0f : (float)((double)gH / d.H));
     if ((uint64_t)B * g.tiles >= (1ull << 31)) return fail(SWF_E_INVALID, "batch * tiles too large");
     w.last.valid = false;
     w.last.stream = st;
@@ -775,13 +784,18 @@ swf_status Ctx::lists_sorted(Workspace& w, const DevScene& d, int B, const Grid&
 }
 
 swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux,
-                       hipStream_t st, uint64_t key_cap, bool speculate, float* chan) {
+                       hipStream_t st, uint64_t key_cap, bool speculate, float* chan, int rH, int rW) {
     if (!out) return fail(SWF_E_INVALID, "out is NULL");
     if ((flags & SWF_KEEP_AUX) && !aux) return fail(SWF_E_INVALID, "SWF_KEEP_AUX needs aux");
+    if ((flags & SWF_KEEP_AUX) && (rH > 0 || rW > 0)) {
+        Scene* sc0 = scene(sid);
+        if (sc0 && ((rH > 0 && rH != sc0->d.H) || (rW > 0 && rW != sc0->d.W)))
+            return fail(SWF_E_INVALID, "SWF_KEEP_AUX (the backward) needs the scene's own grid");
+    }
     hipSetDevice(device);
     const uint64_t spec_cap = speculate && key_cap == 0 && w.vals.cap >= 16 + 4 * 4096 ? (w.vals.cap - 16) / 4 : 0;
     bool spec = false;
-    swf_status s = forward_lists(w, sid, tx, B, flags, st, key_cap, spec_cap, &spec);
+    swf_status s = forward_lists(w, sid, tx, B, flags, st, key_cap, spec_cap, &spec, rH, rW);
     if (s) return s;
     const DevScene& d = scene(sid)->d;
     float* auxT = nullptr;
@@ -811,13 +825,168 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
         const uint64_t total = *w.total_host;
         if (total > spec_cap) {
             // did not fit: nothing was placed and the spectrum is zero; again at the exact size
-            s = render(w, sid, tx, B, flags, out, aux, st, 0, false, chan);
+            s = render(w, sid, tx, B, flags, out, aux, st, 0, false, chan, rH, rW);
             w.last.rerenders = 1;
             return s;
         }
         w.last.n_keys = total;
     }
     return SWF_OK;
+}
+
+// Queries over several resident scenes in one launch sequence: per-query TX
+// term, BF16 MLP (or static preprocess) over the batch's tiles of pairs, one
+// scan over all records, key emission with per-query tile bases, one radix sort
+// over every global tile, ranges, and the blend with per-query grids and output
+// offsets. The tables go to the device through pinned staging.
+swf_status Ctx::render_mixed(Workspace& w, const int32_t* scene_ids, const float* tx, int B, int flags, float* out,
+                             uint64_t* out_offsets, hipStream_t st) {
+    if (B < 1 || B > 65535 || !scene_ids || !out) return fail(SWF_E_INVALID, "bad batch, scene ids or out");
+    const bool deform = !(flags & SWF_NO_DEFORM);
+    if (flags & ~(SWF_MLP_BF16 | SWF_NO_DEFORM | SWF_PAPER_DEFORM))
+        return fail(SWF_E_INVALID, "mixed batches take SWF_MLP_BF16 or SWF_NO_DEFORM (and SWF_PAPER_DEFORM)");
+    if (deform && !(flags & SWF_MLP_BF16)) return fail(SWF_E_INVALID, "mixed batches deform with the BF16 MLP");
+    if (deform && !tx) return fail(SWF_E_INVALID, "tx is NULL");
+    std::vector<MixScene> sc;
+    std::map<int, int> index;
+    std::vector<MixQuery> q(B + 1);
+    int64_t pairs = 0, tiles = 0, outs = 0, mtiles = 0;
+    for (int b = 0; b < B; ++b) {
+        Scene* s = scene(scene_ids[b]);
+        if (!s) return fail(SWF_E_NOT_FOUND, "unknown scene id in a mixed batch");
+        const DevScene& d = s->d;
+        if (d.kind != 0) return fail(SWF_E_INVALID, "mixed batches hold compositing-model scenes");
+        if (deform && (!d.has_mlp || d.n_hidden != 4 || d.hidden != 256))
+            return fail(SWF_E_INVALID, "mixed deformable batches need scenes with a 4 x 256 MLP");
+        auto it = index.find(scene_ids[b]);
+        if (it == index.end()) {
+            MixScene m{};
+            m.mx = d.mx; m.my = d.my; m.lsx = d.lsx; m.lsy = d.lsy; m.rot = d.rot; m.logit = d.logit; m.amp = d.amp;
+            m.w1 = d.w[0];
+            m.b1 = d.b[0];
+            m.stream = d.bf_stream;
+            m.mfeat = d.bf_mfeat;
+            for (int l = 0; l + 1 < d.n_hidden && l < 7; ++l) m.bias_h[l] = d.b[l + 1];
+            m.bias_o = d.has_mlp ? d.b[d.n_hidden] : nullptr;
+            for (int k = 0; k < 3; ++k) {
+                m.room_lo[k] = d.room_lo[k];
+                m.room_hi[k] = d.room_hi[k];
+            }
+            const Grid g = make_grid(d.H, d.W, 16);
+            m.N = d.n;
+            m.n_live = d.n_live;
+            m.H = d.H;
+            m.W = d.W;
+            m.TW = g.TW;
+            m.TH = g.TH;
+            m.tiles = g.tiles;
+            it = index.emplace(scene_ids[b], (int)sc.size()).first;
+            sc.push_back(m);
+        }
+        const MixScene& m = sc[it->second];
+        q[b] = MixQuery{it->second, (int)pairs, (int)tiles, (int)outs, (int)mtiles};
+        pairs += m.N;
+        tiles += m.tiles;
+        outs += (int64_t)m.H * m.W;
+        mtiles += (m.N + 383) / 384;
+    }
+    if (pairs >= (1ll << 31) || tiles >= (1ll << 31) || outs >= (1ll << 31))
+        return fail(SWF_E_INVALID, "mixed batch too large");
+    q[B] = MixQuery{0, (int)pairs, (int)tiles, (int)outs, (int)mtiles};
+    if (out_offsets)
+        for (int b = 0; b <= B; ++b) out_offsets[b] = (uint64_t)q[b].out_base;
+    // tables: pinned staging (the previous mixed call's copy has completed: its render waited for its key count)
+    const size_t sbytes = sc.size() * sizeof(MixScene), qbytes = q.size() * sizeof(MixQuery);
+    const size_t tbytes = ((sbytes + 255) & ~(size_t)255) + qbytes;
+    swf_status s;
+    if (w.mix_host_cap < tbytes) {
+        if (w.mix_host) hipHostFree(w.mix_host);
+        w.mix_host = nullptr;
+        w.mix_host_cap = 0;
+        if (hipHostMalloc(&w.mix_host, tbytes, 0) != hipSuccess) return fail(SWF_E_OOM, "hipHostMalloc(mix)");
+        w.mix_host_cap = tbytes;
+    }
+    if ((s = w.mix.reserve(this, tbytes, st))) return s;
+    std::memcpy(w.mix_host, sc.data(), sbytes);
+    std::memcpy((char*)w.mix_host + ((sbytes + 255) & ~(size_t)255), q.data(), qbytes);
+    if ((s = hip(hipMemcpyAsync(w.mix.ptr, w.mix_host, tbytes, hipMemcpyHostToDevice, st), "mix tables"))) return s;
+    MixBatch mb;
+    mb.scenes = (const MixScene*)w.mix.ptr;
+    mb.queries = (const MixQuery*)((char*)w.mix.ptr + ((sbytes + 255) & ~(size_t)255));
+    mb.B = B;
+    // records
+    if ((s = w.geo.reserve(this, pairs * sizeof(float4), st))) return s;
+    if ((s = w.wm.reserve(this, pairs * sizeof(float4), st))) return s;
+    if ((s = w.oa.reserve(this, pairs * sizeof(float2), st))) return s;
+    if ((s = w.rect.reserve(this, pairs * sizeof(uint2), st))) return s;
+    if ((s = w.count.reserve(this, pairs * sizeof(uint32_t), st))) return s;
+    w.rec.geo = (float4*)w.geo.ptr;
+    w.rec.wm = (float4*)w.wm.ptr;
+    w.rec.oa = (float2*)w.oa.ptr;
+    w.rec.rect = (uint2*)w.rect.ptr;
+    w.rec.count = (uint32_t*)w.count.ptr;
+    w.last.valid = false;
+    w.last.stream = st;
+    launch_clear_u32(w.status_dev, 8, st);
+    const Grid tg = make_grid(16, 16, 16);
+    stage_begin(SWF_STAGE_MLP, st);
+    if (deform) {
+        if ((s = w.qs.reserve(this, (size_t)B * 256 * sizeof(float), st))) return s;
+        launch_mix_tx_features(mb, tx, (float*)w.qs.ptr, st);
+        launch_mix_mlp_bf16(mb, (const float*)w.qs.ptr, w.rec, st, (flags & SWF_PAPER_DEFORM) != 0, false);
+    } else {
+        launch_mix_static(mb, pairs, tg, w.rec, st);
+    }
+    stage_end(st);
+    // lists: scan of every record's tile count, key emission, radix sort over the batch's global tiles, ranges
+    if ((s = w.off.reserve(this, (size_t)pairs * sizeof(uint32_t) + 16, st))) return s;
+    if ((s = w.scan.reserve(this, scan_scratch_bytes(pairs) + 64, st))) return s;
+    stage_begin(SWF_STAGE_SCAN, st);
+    launch_exclusive_scan(w.rec.count, (uint32_t*)w.off.ptr, w.total_dev, pairs, w.scan.ptr, st);
+    stage_end(st);
+    uint64_t nk;
+    const uint64_t* n_dev;
+    if ((s = key_count(w, st, 0, nk, n_dev))) return s;
+    if ((s = w.keys.reserve(this, nk * 4 + 16, st))) return s;
+    if ((s = w.keys2.reserve(this, nk * 4 + 16, st))) return s;
+    if ((s = w.vals.reserve(this, nk * 4 + 16, st))) return s;
+    if ((s = w.vals2.reserve(this, nk * 4 + 16, st))) return s;
+    if ((s = w.hist.reserve(this, radix_scratch_bytes((int64_t)nk) + 64, st))) return s;
+    if ((s = w.ranges.reserve(this, (size_t)tiles * sizeof(uint2), st))) return s;
+    stage_begin(SWF_STAGE_EMIT, st);
+    launch_mix_emit_keys(mb, w.rec, (const uint32_t*)w.off.ptr, pairs, nk, (uint32_t*)w.keys.ptr,
+                         (uint32_t*)w.vals.ptr, w.status_dev, w.cull_dev, st);
+    stage_end(st);
+    stage_begin(SWF_STAGE_SORT, st);
+    const int flip = launch_radix_sort(w.keys.ptr, (uint32_t*)w.vals.ptr, w.keys2.ptr, (uint32_t*)w.vals2.ptr,
+                                       (int64_t)nk, 4, 0, bits_for((uint64_t)tiles), w.hist.ptr, st);
+    stage_end(st);
+    void* skeys = flip ? w.keys2.ptr : w.keys.ptr;
+    uint32_t* svals = (uint32_t*)(flip ? w.vals2.ptr : w.vals.ptr);
+    stage_begin(SWF_STAGE_RANGES, st);
+    launch_tile_ranges(skeys, 4, (int64_t)nk, tiles, (uint2*)w.ranges.ptr, st);
+    stage_end(st);
+    stage_begin(SWF_STAGE_BLEND, st);
+    launch_mix_blend(mb, (int)tiles, (const uint2*)w.ranges.ptr, svals, w.rec, out, st);
+    stage_end(st);
+    // the last render, as the status query sees it: one "query" holding every pair of the batch
+    w.last.valid = true;
+    w.last.scene = scene_ids[0];
+    w.last.B = 1;
+    w.last.N = (int)pairs;
+    w.last.flags = flags;
+    w.last.grid = make_grid(16, 16 * (int)tiles, 16);
+    w.last.grid.tiles = (int)tiles;
+    w.last.n_keys = nk;
+    w.last.full = false;
+    w.last.binned = false;
+    w.last.keys = skeys;
+    w.last.vals = svals;
+    w.last.rerenders = 0;
+    uint64_t nan_pairs = 0;
+    for (int b = 0; b < B; ++b) nan_pairs += (uint64_t)(scene(scene_ids[b])->d.n - scene(scene_ids[b])->d.n_live);
+    w.last.nan_depth_pairs = nan_pairs;
+    return hip(hipGetLastError(), "mixed render");
 }
 
 }  // namespace swf
@@ -936,6 +1105,22 @@ swf_status swf_render_paper(swf_ctx* h, int32_t scene_id, const float* tx, int32
     if (!sc) return c->fail(SWF_E_NOT_FOUND, "unknown scene id");
     if (sc->d.kind != 1) return c->fail(SWF_E_INVALID, "not a paper-model scene");
     return c->render(c->ws, scene_id, tx, batch, flags, out, nullptr, (hipStream_t)stream, 0, true, channels);
+}
+
+swf_status swf_render_at(swf_ctx* h, int32_t scene_id, const float* tx, int32_t batch, int32_t height, int32_t width,
+                         int32_t flags, float* out, void* aux, void* stream) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    if (height < 1 || width < 1) return c->fail(SWF_E_INVALID, "height and width must lie in [1, 4096]");
+    return c->render(c->ws, scene_id, tx, batch, flags, out, aux, (hipStream_t)stream, 0, true, nullptr, height,
+                     width);
+}
+
+swf_status swf_render_mixed(swf_ctx* h, const int32_t* scene_ids, const float* tx, int32_t batch, int32_t flags,
+                            float* out, uint64_t* out_offsets, void* stream) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    return c->render_mixed(c->ws, scene_ids, tx, batch, flags, out, out_offsets, (hipStream_t)stream);
 }
 
 swf_status swf_stage_timing(swf_ctx* h, int32_t enable) {

@@ -55,7 +55,7 @@ struct LastRender {
 // Scratch memory of one render stream: every pipeline stage writes here.
 struct Workspace {
     Buf qs, geo, wm, oa, rect, count, off, scan, keys, keys2, vals, vals2, hist, ranges, bins, delta, sortk, sortv,
-        grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, stage, work, beam, pool, ssim;
+        grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, stage, work, beam, pool, ssim, mix;
     Records rec;
     uint64_t* total_dev = nullptr;           // device status block: scan total, effective count, then:
     uint32_t* status_dev = nullptr;          //   status word (bit 0: key overflow at a fixed capacity)
@@ -63,11 +63,13 @@ struct Workspace {
     uint64_t* total_host = nullptr;  // pinned
     hipEvent_t total_ev = nullptr;   // the scan total has reached total_host (speculative renders)
     void* act_out = nullptr;         // set during the backward's forward pass: BF16 hidden activations go here
+    void* mix_host = nullptr;        // pinned staging of a mixed batch's scene and query tables
+    size_t mix_host_cap = 0;
     LastRender last;
     std::vector<Buf*> bufs() {
         return {&qs, &geo, &wm, &oa, &rect, &count, &off, &scan, &keys, &keys2, &vals, &vals2, &hist, &ranges, &bins,
                 &delta, &sortk, &sortv, &grad, &dpair, &dbase, &dy, &act, &dz, &part, &fmean, &ftx, &dmu,
-                &stage, &work, &beam, &pool, &ssim};
+                &stage, &work, &beam, &pool, &ssim, &mix};
     }
     uint64_t generation() {
         uint64_t g = 0;
@@ -130,7 +132,8 @@ struct Ctx {
     // build them at that fixed capacity with the scan total copied back
     // asynchronously (w.total_ev); *spec_used tells whether that happened.
     swf_status forward_lists(Workspace& w, int sid, const float* tx, int B, int flags, hipStream_t st,
-                             uint64_t key_cap = 0, uint64_t spec_cap = 0, bool* spec_used = nullptr);
+                             uint64_t key_cap = 0, uint64_t spec_cap = 0, bool* spec_used = nullptr, int rH = 0,
+                             int rW = 0);
     swf_status key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64_t& nk, const uint64_t*& n_dev,
                          bool readback = false);
     swf_status lists_binned(Workspace& w, const DevScene& d, int B, const Grid& g, hipStream_t st, uint64_t key_cap,
@@ -142,9 +145,12 @@ struct Ctx {
     // read back, instead of waiting for the count first; it renders again at
     // the exact size if the count did not fit.
     swf_status render(Workspace& w, int sid, const float* tx, int B, int flags, float* out, void* aux, hipStream_t st,
-                      uint64_t key_cap = 0, bool speculate = false, float* chan = nullptr);
+                      uint64_t key_cap = 0, bool speculate = false, float* chan = nullptr, int rH = 0, int rW = 0);
     swf_status upload_paper_scene(const swf_paper_gaussians* g, const swf_paper_mlp* mlp, int H, int W, bool dev,
                                   int* id);
+    // One launch sequence for queries over several scenes (outputs concatenated in query order).
+    swf_status render_mixed(Workspace& w, const int32_t* scene_ids, const float* tx, int B, int flags, float* out,
+                            uint64_t* out_offsets, hipStream_t st);
     swf_status backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out,
                         const void* aux, const swf_grads* grads, hipStream_t st);
     swf_status mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,
@@ -156,7 +162,7 @@ struct Ctx {
     void resolve_timing();
 };
 
-Grid make_grid(int H, int W, int tile, bool wrap = false);
+Grid make_grid(int H, int W, int tile, bool wrap = false, float sx = 1.0f, float sy = 1.0f);
 swf_status noalloc_setup(Ctx* c);  // resolves Ctx::noalloc_scratch (noalloc.hip)
 const char* status_name(swf_status s);
 void serve_shutdown(Ctx* c);

@@ -50,6 +50,27 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 
 __device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v); }
 
+// A render at another resolution of the same field of view: scene pixel
+// coordinates scale by (sx, sy) per axis, so the mean (hi + lo, the product's
+// rounding error kept in lo), the 3-sigma half extents and Sigma' = S Sigma S
+// follow; the whitening factor becomes M S^-1 (its columns divided by sx, sy).
+__device__ __forceinline__ void rescale_to_grid(float sx, float sy, float& xh, float& xl, float& yh, float& yl,
+                                                float& hx, float& hy, float4& m) {
+    const float px = xh * sx, py = yh * sy;
+    const float ex = fmaf(xh, sx, -px), ey = fmaf(yh, sy, -py);
+    float s, e;
+    two_sum(px, fmaf(xl, sx, ex), s, e);
+    xh = s;
+    xl = e;
+    two_sum(py, fmaf(yl, sy, ey), s, e);
+    yh = s;
+    yl = e;
+    hx *= sx;
+    hy *= sy;
+    const float ix = 1.0f / sx, iy = 1.0f / sy;
+    m = make_float4(m.x * ix, m.y * iy, m.z * ix, m.w * iy);
+}
+
 // Deformed Gaussian -> record. mean = (mx0 + dmx, my0 + dmy); all other
 // parameters already deformed. tile is 8 or 16 (power of two, so the division
 // of an edge coordinate by the tile size is exact). wrap: azimuth is periodic
@@ -60,7 +81,8 @@ __device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v);
 // box at least W wide, or whose two pieces meet, covers every column.
 __device__ __forceinline__ PairOut preprocess_pair(float mx0, float my0, float dmx, float dmy, float lsx, float lsy,
                                                    float rot, float logit, float amp, int W, int H, int TW, int TH,
-                                                   float inv_tile, int wrap = 0) {
+                                                   float inv_tile, int wrap = 0, float gsx = 1.0f,
+                                                   float gsy = 1.0f) {
     PairOut r;
     float mxh, mxl, myh, myl;
     two_sum(mx0, dmx, mxh, mxl);
@@ -71,11 +93,21 @@ __device__ __forceinline__ PairOut preprocess_pair(float mx0, float my0, float d
     const float vx = expf(2.0f * lsx), vy = expf(2.0f * lsy);
     const float sxx = c * c * vx + s * s * vy;
     const float syy = s * s * vx + c * c * vy;
-    const float hx = 3.0f * sqrtf(sxx) + kExtentEps;
-    const float hy = 3.0f * sqrtf(syy) + kExtentEps;
+    float hx, hy;
+    float4 wmv = make_float4(c * isx, s * isx, -s * isy, c * isy);
+    if (gsx != 1.0f || gsy != 1.0f) {
+        hx = 3.0f * sqrtf(sxx);
+        hy = 3.0f * sqrtf(syy);
+        rescale_to_grid(gsx, gsy, mxh, mxl, myh, myl, hx, hy, wmv);
+        hx += kExtentEps;
+        hy += kExtentEps;
+    } else {
+        hx = 3.0f * sqrtf(sxx) + kExtentEps;
+        hy = 3.0f * sqrtf(syy) + kExtentEps;
+    }
     const float op = 1.0f / (1.0f + expf(-logit));
     r.geo = make_float4(mxh, myh, mxl, myl);
-    r.wm = make_float4(c * isx, s * isx, -s * isy, c * isy);
+    r.wm = wmv;
     r.oa = make_float2(op, amp);
     const float x0 = mxh - hx, x1 = mxh + hx, y0 = myh - hy, y1 = myh + hy;
     const bool fin = finitef(x0) && finitef(x1) && finitef(y0) && finitef(y1) && finitef(r.wm.x) &&

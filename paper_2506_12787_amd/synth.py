@@ -110,3 +110,34 @@ def multipath(b: int, seed: int, rx=(3.0, 0.5, 1.2), room=((0.0, 0.0, 0.0), (6.0
     counts = np.full(b, L, np.int32)
     return (np.ascontiguousarray(paths, dtype=np.float32), counts,
             np.ascontiguousarray(tx, dtype=np.float32))
+
+
+PAPER_KEYS = ("center_x", "center_y", "chol_l1", "chol_l2", "chol_l3", "atten_logit", "psi_re", "psi_im")
+# (out, in) of the paper MLP's layers: 81 inputs (10 centre bands, 6 position bands), eight layers of 156 whose
+# layers 3, 5 and 7 also take the 81 inputs, and an output layer of 5
+PAPER_LAYER_SHAPES = ((156, 81), (156, 156), (156, 237), (156, 156), (156, 237), (156, 156), (156, 237), (156, 156),
+                      (5, 156))
+
+
+def paper_gaussians(n: int, seed: int, diag=(1.0, 8.0)) -> dict:
+    """n raw paper-model Gaussians: centres whose tanh map spreads them over the grid, Cholesky diagonals of
+    `diag` pixels with random signs and shears in [-3, 3], gate logits ~ N(0, 1), complex responses ~ N(0, 1)^2."""
+    rng = np.random.default_rng(seed)
+    u = lambda lo, hi: rng.uniform(lo, hi, n)
+    sgn = lambda: np.where(rng.uniform(size=n) < 0.5, -1.0, 1.0)
+    g = {"center_x": np.arctanh(u(-0.98, 0.98)), "center_y": np.arctanh(u(-0.97, 0.97)),
+         "chol_l1": sgn() * u(*diag), "chol_l2": u(-3, 3), "chol_l3": sgn() * u(*diag),
+         "atten_logit": rng.normal(0, 1, n), "psi_re": rng.normal(0, 1, n), "psi_im": rng.normal(0, 1, n)}
+    return {k: np.ascontiguousarray(v, np.float32) for k, v in g.items()}
+
+
+def paper_mlp_weights(seed: int, out_scale: float = 1.0, bias_std: float = 0.05):
+    """Xavier-uniform weights of the paper MLP (output layer times out_scale) and N(0, bias_std) biases."""
+    rng = np.random.default_rng(seed)
+    Ws, bs = [], []
+    for o, i in PAPER_LAYER_SHAPES:
+        bound = np.sqrt(6.0 / (o + i))
+        w = rng.uniform(-bound, bound, (o, i)) * (out_scale if o == 5 else 1.0)
+        Ws.append(np.ascontiguousarray(w, np.float32))
+        bs.append(np.ascontiguousarray(rng.normal(0, bias_std, o), np.float32))
+    return Ws, bs

@@ -23,26 +23,13 @@ def ctx():
 
 
 def scene(n, seed, scale=(1.0, 8.0)):
-    """Raw paper-model Gaussians: centres spread over the grid, Cholesky diagonals of 1..8 px with random sign
-    and shear, gates around 0.5, unit-scale complex responses."""
-    rng = np.random.default_rng(seed)
-    u = lambda lo, hi: rng.uniform(lo, hi, n)
-    sgn = lambda: np.where(rng.uniform(size=n) < 0.5, -1.0, 1.0)
-    g = {"center_x": np.arctanh(u(-0.98, 0.98)), "center_y": np.arctanh(u(-0.97, 0.97)),
-         "chol_l1": sgn() * u(*scale), "chol_l2": u(-3, 3), "chol_l3": sgn() * u(*scale),
-         "atten_logit": rng.normal(0, 1, n), "psi_re": rng.normal(0, 1, n), "psi_im": rng.normal(0, 1, n)}
-    return {k: np.ascontiguousarray(v, np.float32) for k, v in g.items()}
+    from paper_2506_12787_amd import synth
+    return synth.paper_gaussians(n, seed, diag=scale)
 
 
 def mlp(seed, out_scale=1.0):
-    rng = np.random.default_rng(seed)
-    Ws, bs = [], []
-    for o, i in P.layer_shapes():
-        bound = np.sqrt(6.0 / (o + i))
-        w = rng.uniform(-bound, bound, (o, i))
-        Ws.append(np.ascontiguousarray(w * (out_scale if o == 5 else 1.0), np.float32))
-        bs.append(np.ascontiguousarray(rng.normal(0, 0.05, o), np.float32))
-    return Ws, bs
+    from paper_2506_12787_amd import synth
+    return synth.paper_mlp_weights(seed, out_scale=out_scale)
 
 
 def check(got, A, bound, tag):
