@@ -349,19 +349,23 @@ def serve_sweep(a):
                       "p99_us": pct(lat_plain, 99), "queries": q,
                       "note": "one FP32 query per launch over the same scene mix"}), flush=True)
     budget = int(a.hbm_budget_gb * 1e9)
-    ctx.serve_start(max_batch=64, n_slots=2, flags=B.MLP_BF16, hbm_budget=budget)
-    serve_run(ctx, plan[:512], shapes)  # warm-up: graphs for the common buckets
-    sat, lat, _ = serve_run(ctx, plan, shapes)
-    print(json.dumps({"serve_sweep": "saturation", "rate": None, "throughput": sat, "over_plain": sat / plain,
-                      "p50_us": pct(lat, 50), "p99_us": pct(lat, 99), "hbm_budget_bytes": budget}), flush=True)
-    for f in (0.1, 0.25, 0.5, 0.75, 0.9, 1.1):
-        thr, lat, st = serve_run(ctx, plan, shapes, rate=f * sat, depth=1 << 30)
-        print(json.dumps({"serve_sweep": "poisson", "rate_fraction": f, "rate": f * sat, "throughput": thr,
-                          "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
-                          "mean_batch": float(np.mean([s["batch"] for s in st]))}), flush=True)
-    cnt = ctx.serve_counters()
-    print(json.dumps({"serve_sweep": "counters", **cnt}), flush=True)
-    ctx.serve_stop()
+    # per-scene batches (one graph per scene and bucket), then batches across scenes (graphs keyed by capacities)
+    for mode in ("per_scene", "mixed"):
+        ctx.serve_start(max_batch=64, n_slots=2, flags=B.MLP_BF16, hbm_budget=budget, mixed=mode == "mixed")
+        serve_run(ctx, plan[:512], shapes)  # warm-up: graphs for the common buckets
+        sat, lat, st = serve_run(ctx, plan, shapes)
+        print(json.dumps({"serve_sweep": "saturation", "mode": mode, "rate": None, "throughput": sat,
+                          "over_plain": sat / plain, "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
+                          "mean_batch": float(np.mean([s["batch"] for s in st])), "hbm_budget_bytes": budget}),
+              flush=True)
+        for f in (0.1, 0.25, 0.5, 0.75, 0.9, 1.1):
+            thr, lat, st = serve_run(ctx, plan, shapes, rate=f * sat, depth=1 << 30)
+            print(json.dumps({"serve_sweep": "poisson", "mode": mode, "rate_fraction": f, "rate": f * sat,
+                              "throughput": thr, "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
+                              "mean_batch": float(np.mean([s["batch"] for s in st]))}), flush=True)
+        cnt = ctx.serve_counters()
+        print(json.dumps({"serve_sweep": "counters", "mode": mode, **cnt}), flush=True)
+        ctx.serve_stop()
     ctx.close()
 
 

@@ -484,7 +484,14 @@ swf_status swf_exclusive_scan_noalloc(swf_ctx *ctx, const uint32_t *counts, uint
  * with exact sizing (`fallback` in the stats). hbm_budget (bytes, 0 = none)
  * bounds the sum of all slot workspaces: a batch that does not fit is shrunk,
  * idle workspaces are released, or the requests wait; a single query that can
- * never fit fails with SWF_E_OOM. Scenes must stay uploaded while served. */
+ * never fit fails with SWF_E_OOM. Scenes must stay uploaded while served.
+ * mixed = 1 batches across scenes: the waiting requests in arrival order, of
+ * up to 64 distinct scenes sharing the oldest request's deformation mode (all
+ * with a 4 x 256 MLP and SWF_MLP_BF16, or all static), go into one mixed batch
+ * (swf_render_mixed's launches); its graph is keyed by capacities (queries,
+ * pairs, tiles, keys, rounded up to four steps per octave), not by scene, so
+ * any mix of scenes whose totals fit replays it. Scenes a mixed batch cannot
+ * hold (the paper model, other MLP shapes, SWF_TILE8) are served per scene. */
 typedef struct {
     int32_t max_batch;    /* largest batch per launch (default 64, <= 1024)    */
     int32_t n_slots;      /* execution slots in flight (default 2, <= 16)      */
@@ -492,7 +499,8 @@ typedef struct {
     float key_factor;     /* key capacity headroom (default 1.5)               */
     uint64_t hbm_budget;  /* workspace bytes over all slots, 0 = unlimited     */
     int32_t use_graphs;   /* 1: replay captured graphs; 0: direct launches     */
-    int32_t reserved[5];
+    int32_t mixed;        /* 1: batch requests of different scenes together    */
+    int32_t reserved[4];
 } swf_serve_config;
 
 typedef struct {
@@ -522,7 +530,8 @@ swf_status swf_serve_wait(swf_ctx *ctx, uint64_t ticket, swf_req_stats *stats);
 /* Finish in-flight launches and stop the scheduler. */
 swf_status swf_serve_stop(swf_ctx *ctx);
 /* counters[0..n): launches, completed requests, fallbacks, graph builds,
- * budget shrinks, workspace bytes over all slots. */
+ * budget shrinks, workspace bytes over all slots, mixed launches, and the
+ * distinct scenes summed over the mixed launches. */
 swf_status swf_serve_counters(swf_ctx *ctx, uint64_t *counters, int32_t n);
 /* The steady clock (seconds) that arrival times refer to. */
 double swf_serve_clock(void);

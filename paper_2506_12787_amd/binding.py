@@ -68,7 +68,7 @@ class _Grads(ctypes.Structure):
 class _ServeCfg(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("key_factor", ctypes.c_float), ("hbm_budget", ctypes.c_uint64), ("use_graphs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("mixed", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class _ReqStats(ctypes.Structure):
@@ -85,7 +85,8 @@ class _DevStatus(ctypes.Structure):
 
 DEV_KEY_OVERFLOW, DEV_RERENDERED, DEV_CULLED_NONFINITE, DEV_CULLED_OFFGRID = 1, 2, 4, 8
 
-SERVE_COUNTERS = ("launches", "completed", "fallbacks", "graph_builds", "budget_shrinks", "workspace_bytes")
+SERVE_COUNTERS = ("launches", "completed", "fallbacks", "graph_builds", "budget_shrinks", "workspace_bytes",
+                  "mixed_launches", "mixed_scenes")
 PENDING = -7
 
 _lib = None
@@ -582,9 +583,10 @@ class Context:
                                                        _stream()))
 
     # ---- serving ------------------------------------------------------------------
-    def serve_start(self, max_batch=64, n_slots=2, flags=MLP_BF16, key_factor=1.5, hbm_budget=0, use_graphs=True):
+    def serve_start(self, max_batch=64, n_slots=2, flags=MLP_BF16, key_factor=1.5, hbm_budget=0, use_graphs=True,
+                    mixed=False):
         cfg = _ServeCfg(max_batch=max_batch, n_slots=n_slots, flags=flags, key_factor=key_factor,
-                        hbm_budget=hbm_budget, use_graphs=1 if use_graphs else 0)
+                        hbm_budget=hbm_budget, use_graphs=1 if use_graphs else 0, mixed=1 if mixed else 0)
         self._check(self._L.swf_serve_start(self._h, ctypes.byref(cfg)))
 
     def serve_submit(self, sid: int, tx, out: np.ndarray, arrival: float = 0.0) -> int:

@@ -124,6 +124,7 @@ __device__ __forceinline__ int mix_find(const MixQuery* qs, int B, int v, F fiel
 // mixed.hip
 void launch_mix_tx_features(const MixBatch& m, const float* tx, float* qs, hipStream_t st);
 void launch_mix_static(const MixBatch& m, int64_t pair_cap, const Grid& tile, const Records& r, hipStream_t st);
+void launch_mix_clear_tail(const MixBatch& m, int64_t pair_cap, const Records& r, hipStream_t st);
 void launch_mix_emit_keys(const MixBatch& m, const Records& r, const uint32_t* offsets, int64_t pair_cap,
                           uint64_t capacity, uint32_t* keys, uint32_t* vals, uint32_t* status,
                           unsigned long long* cull, hipStream_t st);

@@ -137,7 +137,20 @@ __global__ __launch_bounds__(256) void mix_emit_keys_kernel(MixBatch m, const ui
     }
 }
 
+// Rows past the batch's pairs (up to the capacity) hold no tiles.
+__global__ __launch_bounds__(256) void mix_clear_tail_kernel(MixBatch m, int64_t pair_cap, Records r) {
+    const int64_t row = (int64_t)m.queries[m.B].pair_base + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= pair_cap) return;
+    r.count[row] = 0u;
+    r.rect[row] = make_uint2(0u, 0u);
+}
+
 }  // namespace
+
+void launch_mix_clear_tail(const MixBatch& m, int64_t pair_cap, const Records& r, hipStream_t st) {
+    // every row the tail can hold: launched at the capacity, the rows before the batch's total return at once
+    if (pair_cap > 0) mix_clear_tail_kernel<<<(unsigned)((pair_cap + 255) / 256), 256, 0, st>>>(m, pair_cap, r);
+}
 
 void launch_mix_tx_features(const MixBatch& m, const float* tx, float* qs, hipStream_t st) {
     if (m.B > 0) mix_tx_kernel<<<m.B, 256, 0, st>>>(m, tx, qs);

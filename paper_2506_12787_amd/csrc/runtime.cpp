@@ -838,19 +838,23 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
 // term, BF16 MLP (or static preprocess) over the batch's tiles of pairs, one
 // scan over all records, key emission with per-query tile bases, one radix sort
 // over every global tile, ranges, and the blend with per-query grids and output
-// offsets. The tables go to the device through pinned staging.
-swf_status Ctx::render_mixed(Workspace& w, const int32_t* scene_ids, const float* tx, int B, int flags, float* out,
-                             uint64_t* out_offsets, hipStream_t st) {
-    if (B < 1 || B > 65535 || !scene_ids || !out) return fail(SWF_E_INVALID, "bad batch, scene ids or out");
+// offsets. plan_mixed validates the batch and writes its tables into the
+// workspace's pinned staging (a fixed layout: kMixScenes scene slots, then
+// B_cap + 1 queries, the ones past B empty); enqueue_mixed copies them to the
+// device and launches the stages, either exactly sized (one wait for the key
+// count) or at fixed capacities with no host wait (graph-capturable: a replay
+// copies whatever tables the staging holds by then).
+swf_status Ctx::plan_mixed(Workspace& w, const int32_t* scene_ids, int B, int flags, int B_cap, MixPlan& p) {
+    if (B < 1 || B > 65535 || B_cap < B || !scene_ids) return fail(SWF_E_INVALID, "bad batch or scene ids");
     const bool deform = !(flags & SWF_NO_DEFORM);
     if (flags & ~(SWF_MLP_BF16 | SWF_NO_DEFORM | SWF_PAPER_DEFORM))
         return fail(SWF_E_INVALID, "mixed batches take SWF_MLP_BF16 or SWF_NO_DEFORM (and SWF_PAPER_DEFORM)");
     if (deform && !(flags & SWF_MLP_BF16)) return fail(SWF_E_INVALID, "mixed batches deform with the BF16 MLP");
-    if (deform && !tx) return fail(SWF_E_INVALID, "tx is NULL");
     std::vector<MixScene> sc;
     std::map<int, int> index;
-    std::vector<MixQuery> q(B + 1);
+    std::vector<MixQuery> q(B_cap + 1);
     int64_t pairs = 0, tiles = 0, outs = 0, mtiles = 0;
+    p.out_off.assign(B + 1, 0);
     for (int b = 0; b < B; ++b) {
         Scene* s = scene(scene_ids[b]);
         if (!s) return fail(SWF_E_NOT_FOUND, "unknown scene id in a mixed batch");
@@ -860,6 +864,7 @@ swf_status Ctx::render_mixed(Workspace& w, const int32_t* scene_ids, const float
             return fail(SWF_E_INVALID, "mixed deformable batches need scenes with a 4 x 256 MLP");
         auto it = index.find(scene_ids[b]);
         if (it == index.end()) {
+            if ((int)sc.size() == kMixScenes) return fail(SWF_E_INVALID, "more than 64 scenes in a mixed batch");
             MixScene m{};
             m.mx = d.mx; m.my = d.my; m.lsx = d.lsx; m.lsy = d.lsy; m.rot = d.rot; m.logit = d.logit; m.amp = d.amp;
             m.w1 = d.w[0];
@@ -885,41 +890,69 @@ swf_status Ctx::render_mixed(Workspace& w, const int32_t* scene_ids, const float
         }
         const MixScene& m = sc[it->second];
         q[b] = MixQuery{it->second, (int)pairs, (int)tiles, (int)outs, (int)mtiles};
+        p.out_off[b] = (uint64_t)outs;
         pairs += m.N;
         tiles += m.tiles;
         outs += (int64_t)m.H * m.W;
         mtiles += (m.N + 383) / 384;
+        p.nan_pairs += (uint64_t)(d.n - d.n_live);
     }
     if (pairs >= (1ll << 31) || tiles >= (1ll << 31) || outs >= (1ll << 31))
         return fail(SWF_E_INVALID, "mixed batch too large");
-    q[B] = MixQuery{0, (int)pairs, (int)tiles, (int)outs, (int)mtiles};
-    if (out_offsets)
-        for (int b = 0; b <= B; ++b) out_offsets[b] = (uint64_t)q[b].out_base;
-    // tables: pinned staging (the previous mixed call's copy has completed: its render waited for its key count)
-    const size_t sbytes = sc.size() * sizeof(MixScene), qbytes = q.size() * sizeof(MixQuery);
-    const size_t tbytes = ((sbytes + 255) & ~(size_t)255) + qbytes;
-    swf_status s;
-    if (w.mix_host_cap < tbytes) {
-        if (w.mix_host) hipHostFree(w.mix_host);
+    for (int b = B; b <= B_cap; ++b) q[b] = MixQuery{0, (int)pairs, (int)tiles, (int)outs, (int)mtiles};
+    p.out_off[B] = (uint64_t)outs;
+    p.B = B;
+    p.B_cap = B_cap;
+    p.pairs = pairs;
+    p.tiles = tiles;
+    p.outs = outs;
+    p.first_scene = scene_ids[0];
+    const size_t qoff = ((size_t)kMixScenes * sizeof(MixScene) + 255) & ~(size_t)255;
+    p.query_off = qoff;
+    p.table_bytes = qoff + (size_t)(B_cap + 1) * sizeof(MixQuery);
+    if (w.mix_host_cap < p.table_bytes) {
+        if (w.mix_host) {
+            hipDeviceSynchronize();  // a previous copy may still read the old staging
+            hipHostFree(w.mix_host);
+        }
         w.mix_host = nullptr;
         w.mix_host_cap = 0;
-        if (hipHostMalloc(&w.mix_host, tbytes, 0) != hipSuccess) return fail(SWF_E_OOM, "hipHostMalloc(mix)");
-        w.mix_host_cap = tbytes;
+        if (hipHostMalloc(&w.mix_host, p.table_bytes, 0) != hipSuccess) return fail(SWF_E_OOM, "hipHostMalloc(mix)");
+        w.mix_host_cap = p.table_bytes;
     }
-    if ((s = w.mix.reserve(this, tbytes, st))) return s;
-    std::memcpy(w.mix_host, sc.data(), sbytes);
-    std::memcpy((char*)w.mix_host + ((sbytes + 255) & ~(size_t)255), q.data(), qbytes);
-    if ((s = hip(hipMemcpyAsync(w.mix.ptr, w.mix_host, tbytes, hipMemcpyHostToDevice, st), "mix tables"))) return s;
+    std::memset(w.mix_host, 0, qoff);
+    std::memcpy(w.mix_host, sc.data(), sc.size() * sizeof(MixScene));
+    std::memcpy((char*)w.mix_host + qoff, q.data(), q.size() * sizeof(MixQuery));
+    return SWF_OK;
+}
+
+swf_status Ctx::enqueue_mixed(Workspace& w, const MixPlan& p, const float* tx, int flags, float* out, hipStream_t st,
+                              uint64_t key_cap, int64_t pair_cap, int64_t tile_cap, bool copy_tables) {
+    if (!out) return fail(SWF_E_INVALID, "out is NULL");
+    const bool deform = !(flags & SWF_NO_DEFORM);
+    if (deform && !tx) return fail(SWF_E_INVALID, "tx is NULL");
+    const bool fixed = key_cap > 0;
+    if (!fixed) {
+        pair_cap = p.pairs;
+        tile_cap = p.tiles;
+    } else if (pair_cap < p.pairs || tile_cap < p.tiles) {
+        return fail(SWF_E_INVALID, "mixed batch exceeds its capacities");
+    }
+    swf_status s;
+    if ((s = w.mix.reserve(this, p.table_bytes, st))) return s;
+    if (copy_tables &&
+        (s = hip(hipMemcpyAsync(w.mix.ptr, w.mix_host, p.table_bytes, hipMemcpyHostToDevice, st), "mix tables")))
+        return s;
     MixBatch mb;
     mb.scenes = (const MixScene*)w.mix.ptr;
-    mb.queries = (const MixQuery*)((char*)w.mix.ptr + ((sbytes + 255) & ~(size_t)255));
-    mb.B = B;
+    mb.queries = (const MixQuery*)((char*)w.mix.ptr + p.query_off);
+    mb.B = p.B_cap;
     // records
-    if ((s = w.geo.reserve(this, pairs * sizeof(float4), st))) return s;
-    if ((s = w.wm.reserve(this, pairs * sizeof(float4), st))) return s;
-    if ((s = w.oa.reserve(this, pairs * sizeof(float2), st))) return s;
-    if ((s = w.rect.reserve(this, pairs * sizeof(uint2), st))) return s;
-    if ((s = w.count.reserve(this, pairs * sizeof(uint32_t), st))) return s;
+    if ((s = w.geo.reserve(this, pair_cap * sizeof(float4) + 16, st))) return s;
+    if ((s = w.wm.reserve(this, pair_cap * sizeof(float4) + 16, st))) return s;
+    if ((s = w.oa.reserve(this, pair_cap * sizeof(float2) + 16, st))) return s;
+    if ((s = w.rect.reserve(this, pair_cap * sizeof(uint2) + 16, st))) return s;
+    if ((s = w.count.reserve(this, pair_cap * sizeof(uint32_t) + 16, st))) return s;
     w.rec.geo = (float4*)w.geo.ptr;
     w.rec.wm = (float4*)w.wm.ptr;
     w.rec.oa = (float2*)w.oa.ptr;
@@ -928,65 +961,79 @@ swf_status Ctx::render_mixed(Workspace& w, const int32_t* scene_ids, const float
     w.last.valid = false;
     w.last.stream = st;
     launch_clear_u32(w.status_dev, 8, st);
-    const Grid tg = make_grid(16, 16, 16);
     stage_begin(SWF_STAGE_MLP, st);
     if (deform) {
-        if ((s = w.qs.reserve(this, (size_t)B * 256 * sizeof(float), st))) return s;
+        if ((s = w.qs.reserve(this, (size_t)p.B_cap * 256 * sizeof(float), st))) return s;
         launch_mix_tx_features(mb, tx, (float*)w.qs.ptr, st);
         launch_mix_mlp_bf16(mb, (const float*)w.qs.ptr, w.rec, st, (flags & SWF_PAPER_DEFORM) != 0, false);
+        launch_mix_clear_tail(mb, pair_cap, w.rec, st);  // rows past the batch's pairs: no tiles
     } else {
-        launch_mix_static(mb, pairs, tg, w.rec, st);
+        launch_mix_static(mb, pair_cap, make_grid(16, 16, 16), w.rec, st);
     }
     stage_end(st);
     // lists: scan of every record's tile count, key emission, radix sort over the batch's global tiles, ranges
-    if ((s = w.off.reserve(this, (size_t)pairs * sizeof(uint32_t) + 16, st))) return s;
-    if ((s = w.scan.reserve(this, scan_scratch_bytes(pairs) + 64, st))) return s;
+    if ((s = w.off.reserve(this, (size_t)pair_cap * sizeof(uint32_t) + 16, st))) return s;
+    if ((s = w.scan.reserve(this, scan_scratch_bytes(pair_cap) + 64, st))) return s;
     stage_begin(SWF_STAGE_SCAN, st);
-    launch_exclusive_scan(w.rec.count, (uint32_t*)w.off.ptr, w.total_dev, pairs, w.scan.ptr, st);
+    launch_exclusive_scan(w.rec.count, (uint32_t*)w.off.ptr, w.total_dev, pair_cap, w.scan.ptr, st);
     stage_end(st);
     uint64_t nk;
     const uint64_t* n_dev;
-    if ((s = key_count(w, st, 0, nk, n_dev))) return s;
+    if ((s = key_count(w, st, key_cap, nk, n_dev))) return s;
     if ((s = w.keys.reserve(this, nk * 4 + 16, st))) return s;
     if ((s = w.keys2.reserve(this, nk * 4 + 16, st))) return s;
     if ((s = w.vals.reserve(this, nk * 4 + 16, st))) return s;
     if ((s = w.vals2.reserve(this, nk * 4 + 16, st))) return s;
     if ((s = w.hist.reserve(this, radix_scratch_bytes((int64_t)nk) + 64, st))) return s;
-    if ((s = w.ranges.reserve(this, (size_t)tiles * sizeof(uint2), st))) return s;
+    if ((s = w.ranges.reserve(this, (size_t)tile_cap * sizeof(uint2) + 16, st))) return s;
     stage_begin(SWF_STAGE_EMIT, st);
-    launch_mix_emit_keys(mb, w.rec, (const uint32_t*)w.off.ptr, pairs, nk, (uint32_t*)w.keys.ptr,
+    launch_mix_emit_keys(mb, w.rec, (const uint32_t*)w.off.ptr, pair_cap, nk, (uint32_t*)w.keys.ptr,
                          (uint32_t*)w.vals.ptr, w.status_dev, w.cull_dev, st);
     stage_end(st);
     stage_begin(SWF_STAGE_SORT, st);
     const int flip = launch_radix_sort(w.keys.ptr, (uint32_t*)w.vals.ptr, w.keys2.ptr, (uint32_t*)w.vals2.ptr,
-                                       (int64_t)nk, 4, 0, bits_for((uint64_t)tiles), w.hist.ptr, st);
+                                       (int64_t)nk, 4, 0, bits_for((uint64_t)tile_cap), w.hist.ptr, st, n_dev);
     stage_end(st);
     void* skeys = flip ? w.keys2.ptr : w.keys.ptr;
     uint32_t* svals = (uint32_t*)(flip ? w.vals2.ptr : w.vals.ptr);
     stage_begin(SWF_STAGE_RANGES, st);
-    launch_tile_ranges(skeys, 4, (int64_t)nk, tiles, (uint2*)w.ranges.ptr, st);
+    launch_tile_ranges(skeys, 4, (int64_t)nk, tile_cap, (uint2*)w.ranges.ptr, st, n_dev);
     stage_end(st);
     stage_begin(SWF_STAGE_BLEND, st);
-    launch_mix_blend(mb, (int)tiles, (const uint2*)w.ranges.ptr, svals, w.rec, out, st);
+    launch_mix_blend(mb, (int)tile_cap, (const uint2*)w.ranges.ptr, svals, w.rec, out, st);
     stage_end(st);
     // the last render, as the status query sees it: one "query" holding every pair of the batch
     w.last.valid = true;
-    w.last.scene = scene_ids[0];
+    w.last.scene = p.first_scene;
     w.last.B = 1;
-    w.last.N = (int)pairs;
+    w.last.N = (int)p.pairs;
     w.last.flags = flags;
-    w.last.grid = make_grid(16, 16 * (int)tiles, 16);
-    w.last.grid.tiles = (int)tiles;
+    w.last.grid = make_grid(16, 16, 16);
+    w.last.grid.tiles = (int)p.tiles;
     w.last.n_keys = nk;
     w.last.full = false;
     w.last.binned = false;
     w.last.keys = skeys;
     w.last.vals = svals;
     w.last.rerenders = 0;
-    uint64_t nan_pairs = 0;
-    for (int b = 0; b < B; ++b) nan_pairs += (uint64_t)(scene(scene_ids[b])->d.n - scene(scene_ids[b])->d.n_live);
-    w.last.nan_depth_pairs = nan_pairs;
+    w.last.nan_depth_pairs = p.nan_pairs;
     return hip(hipGetLastError(), "mixed render");
+}
+
+swf_status Ctx::render_mixed(Workspace& w, const int32_t* scene_ids, const float* tx, int B, int flags, float* out,
+                             uint64_t* out_offsets, hipStream_t st) {
+    if (!out) return fail(SWF_E_INVALID, "out is NULL");
+    // the staging is about to be rewritten: the previous mixed batch's table copy must be done
+    if (w.mix_host && w.last.stream) {
+        swf_status s = hip(hipStreamSynchronize(w.last.stream), "stream sync");
+        if (s) return s;
+    }
+    MixPlan p;
+    swf_status s = plan_mixed(w, scene_ids, B, flags, B, p);
+    if (s) return s;
+    if (out_offsets)
+        for (int b = 0; b <= B; ++b) out_offsets[b] = p.out_off[b];
+    return enqueue_mixed(w, p, tx, flags, out, st);
 }
 
 }  // namespace swf

@@ -3,16 +3,26 @@
 // Requests (scene, tx) are queued by any thread. A scheduler thread owns
 // `n_slots` execution slots; each slot has its own stream and workspace, so
 // the launches of different slots overlap on the device. Whenever a slot is
-// free, the scheduler takes the scene of the oldest waiting request, admits up
-// to `max_batch` of that scene's waiting requests (FIFO), pads the batch to a
-// power-of-two bucket and replays the slot's captured graph for (scene,
-// bucket): TX upload -> the whole render (fixed key capacity, no host sync) ->
-// result and status download -> completion event. Completed slots are refilled
-// immediately (continuous batching). Admission is bounded by a device-memory
-// budget over all slot workspaces (a batch that does not fit is shrunk, idle
-// workspaces are released, or the requests wait). A key-capacity overflow is
-// detected from the status word and the batch is re-rendered with exact sizing.
-// Latency is measured from the request's scheduled arrival time.
+// free, the scheduler admits a batch and replays a captured graph of its whole
+// render (fixed capacities, no host sync), then queues the result and status
+// download and a completion event. Completed slots are refilled immediately
+// (continuous batching).
+//
+// Per-scene mode: the oldest waiting request's scene, up to `max_batch` of its
+// waiting requests (FIFO), padded to a power-of-two bucket; one graph per
+// (scene, bucket). Mixed mode: the waiting requests in arrival order, of any
+// scenes (at most 64 distinct) that share the oldest one's deformation mode,
+// rendered as one mixed batch; its scene and query tables are planned on the
+// host and copied ahead of the replay, so one graph serves every batch whose
+// totals fit its capacities (queries, pairs, tiles, keys: each rounded up to
+// four steps per octave). Scenes a mixed batch cannot hold (another MLP shape,
+// the paper model) are served per scene.
+//
+// Admission is bounded by a device-memory budget over all slot workspaces (a
+// batch that does not fit is shrunk, idle workspaces are released, or the
+// requests wait). A key-capacity overflow is detected from the status word and
+// the batch is re-rendered with exact sizing. Latency is measured from the
+// request's scheduled arrival time.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -20,7 +30,9 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 
 #include "runtime.h"
@@ -48,6 +60,16 @@ struct GraphEntry {
     uint64_t key_cap = 0;
 };
 
+// Capacities of a mixed batch's graph: queries, pairs, global tiles, keys.
+struct MixCaps {
+    int B_cap = 0;
+    int64_t pair_cap = 0, tile_cap = 0;
+    uint64_t key_cap = 0;
+    int64_t outs = 0;  // output floats of the batch (not part of the graph's key)
+    auto key(int flags) const { return std::make_tuple(flags, B_cap, pair_cap, tile_cap, key_cap); }
+};
+using MixKey = std::tuple<int, int, int64_t, int64_t, uint64_t>;
+
 struct Slot {
     int index = 0;
     hipStream_t stream = nullptr;
@@ -62,6 +84,12 @@ struct Slot {
     int scene = -1, bucket = 0;
     std::vector<Request*> reqs;
     std::map<std::pair<int, int>, GraphEntry> graphs;
+    // mixed batches
+    bool mixed = false;
+    int mix_flags = 0;
+    MixPlan plan;
+    std::vector<int32_t> ids;
+    std::map<MixKey, GraphEntry> mgraphs;
 };
 
 struct ServeState {
@@ -76,6 +104,7 @@ struct ServeState {
     std::vector<Slot*> slots;
     std::map<int, uint64_t> keys_per_query;  // calibrated per scene
     std::atomic<uint64_t> launched{0}, completed{0}, fallbacks{0}, graph_builds{0}, shrinks{0};
+    std::atomic<uint64_t> mixed_launches{0}, mixed_scenes{0};
 };
 
 namespace {
@@ -92,6 +121,33 @@ void drop_graphs(Slot* s) {
     for (auto& kv : s->graphs)
         if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
     s->graphs.clear();
+    for (auto& kv : s->mgraphs)
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+    s->mgraphs.clear();
+}
+
+int pow2_at_least(int64_t x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// x rounded up to one of four steps per octave (5/8, 6/8, 7/8, 8/8 of the next power of two), at least `lo`.
+int64_t round_cap(int64_t x, int64_t lo) {
+    x = std::max(x, lo);
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    const int64_t step = std::max<int64_t>(p / 8, 1);
+    return (x + step - 1) / step * step;
+}
+
+// Upper bound of a slot's workspace for a mixed batch at these capacities
+// (the terms of estimate_bytes below, at the batch's totals).
+uint64_t estimate_mixed_bytes(const MixCaps& k) {
+    const uint64_t raw = (uint64_t)k.pair_cap * 56 + k.key_cap * 16 + (uint64_t)k.tile_cap * 8 +
+                         (uint64_t)k.outs * 4 + (uint64_t)k.B_cap * (256 * 4 + 1024) + (uint64_t)k.pair_cap / 64 +
+                         (1u << 20);
+    return raw + raw / 4 + 64 * 256;
 }
 
 // Upper bound of a slot's workspace for (scene, bucket, key capacity): records
@@ -192,6 +248,7 @@ static swf_status launch_batch(Ctx* c, ServeState* S, Slot* sl, int scene, std::
         r->state = 1;
     }
     sl->busy = true;
+    sl->mixed = false;
     sl->scene = scene;
     sl->bucket = bucket;
     sl->reqs = reqs;
@@ -201,6 +258,17 @@ static swf_status launch_batch(Ctx* c, ServeState* S, Slot* sl, int scene, std::
 
 // Exact-size re-render of a finished slot's requests after a key overflow.
 static swf_status fallback_batch(Ctx* c, Slot* sl) {
+    if (sl->mixed) {
+        const int count = (int)sl->reqs.size();
+        swf_status s = c->render_mixed(sl->ws, sl->ids.data(), (const float*)sl->tx_dev.ptr, count, sl->mix_flags,
+                                       (float*)sl->out_dev.ptr, nullptr, sl->stream);
+        if (s) return s;
+        if ((s = c->hip(hipMemcpyAsync(sl->out_host, sl->out_dev.ptr, (size_t)sl->plan.outs * sizeof(float),
+                                       hipMemcpyDeviceToHost, sl->stream),
+                        "fallback D2H")))
+            return s;
+        return c->hip(hipStreamSynchronize(sl->stream), "fallback sync");
+    }
     const DevScene& d = c->scene(sl->scene)->d;
     const int count = (int)sl->reqs.size();
     int flags = c->serve->cfg.flags & (SWF_MLP_BF16 | SWF_PAPER_DEFORM | SWF_TILE8);
@@ -221,19 +289,29 @@ static void finish_slot(Ctx* c, ServeState* S, Slot* sl) {
     {
         std::lock_guard<std::recursive_mutex> lk(c->mu);
         if (*sl->status_host != 0u) {
-            // the next graph for this scene gets a larger key capacity
-            S->keys_per_query[sl->scene] = (uint64_t)(S->keys_per_query[sl->scene] * 1.5) + 1024;
+            // the next graph for these scenes gets a larger key capacity
+            if (sl->mixed) {
+                for (int id : std::set<int>(sl->ids.begin(), sl->ids.end()))
+                    S->keys_per_query[id] = (uint64_t)(S->keys_per_query[id] * 1.5) + 1024;
+            } else {
+                S->keys_per_query[sl->scene] = (uint64_t)(S->keys_per_query[sl->scene] * 1.5) + 1024;
+            }
             fb = fallback_batch(c, sl) == SWF_OK ? 1 : -1;
             ++S->fallbacks;
         }
-        const DevScene& d = c->scene(sl->scene)->d;
-        px = (size_t)d.H * d.W;
+        if (!sl->mixed) {
+            const DevScene& d = c->scene(sl->scene)->d;
+            px = (size_t)d.H * d.W;
+        }
     }
     // results to the callers' buffers (the requests are in state "running": no
     // other thread touches them), then publish under the lock
     if (fb >= 0)
-        for (size_t i = 0; i < sl->reqs.size(); ++i)
-            std::memcpy(sl->reqs[i]->out, sl->out_host + i * px, px * sizeof(float));
+        for (size_t i = 0; i < sl->reqs.size(); ++i) {
+            const size_t off = sl->mixed ? (size_t)sl->plan.out_off[i] : i * px;
+            const size_t n = sl->mixed ? (size_t)(sl->plan.out_off[i + 1] - sl->plan.out_off[i]) : px;
+            std::memcpy(sl->reqs[i]->out, sl->out_host + off, n * sizeof(float));
+        }
     const double now = serve_clock();
     std::lock_guard<std::mutex> lk(S->mu);
     for (size_t i = 0; i < sl->reqs.size(); ++i) {
@@ -246,6 +324,218 @@ static void finish_slot(Ctx* c, ServeState* S, Slot* sl) {
     sl->reqs.clear();
     sl->busy = false;
     S->cv.notify_all();
+}
+
+// Mixed mode of a scene: 1 deformable (a 4 x 256 MLP, BF16), 0 static (no MLP),
+// -1 served per scene (another MLP shape or model, or flags a mixed batch does
+// not take), -2 unknown.
+static int mix_mode(Ctx* c, const ServeState* S, int id) {
+    Scene* sc = c->scene(id);
+    if (!sc) return -2;
+    const DevScene& d = sc->d;
+    if (d.kind != 0 || (S->cfg.flags & SWF_TILE8)) return -1;
+    if (!d.has_mlp) return 0;
+    return (d.n_hidden == 4 && d.hidden == 256 && (S->cfg.flags & SWF_MLP_BF16)) ? 1 : -1;
+}
+
+// Grow a slot's pinned output staging to n floats.
+static swf_status reserve_out_host(Slot* sl, size_t n) {
+    if (sl->out_host_cap >= n) return SWF_OK;
+    if (sl->out_host) hipHostFree(sl->out_host);
+    sl->out_host = nullptr;
+    sl->out_host_cap = 0;
+    if (hipHostMalloc(&sl->out_host, n * sizeof(float), 0) != hipSuccess) return SWF_E_OOM;
+    sl->out_host_cap = n;
+    return SWF_OK;
+}
+
+// Render a mixed batch on a slot: tables planned into the workspace's staging,
+// TX (padded to B_cap with the last request's), tables and the graph of the
+// launches at these capacities.
+static swf_status launch_mixed(Ctx* c, ServeState* S, Slot* sl, std::vector<Request*>& reqs, int flags,
+                               const MixCaps& k) {
+    const int count = (int)reqs.size();
+    sl->ids.resize(count);
+    for (int i = 0; i < count; ++i) sl->ids[i] = reqs[i]->scene;
+    swf_status s = c->plan_mixed(sl->ws, sl->ids.data(), count, flags, k.B_cap, sl->plan);
+    if (s) return s;
+    const MixPlan& p = sl->plan;
+    for (int i = 0; i < k.B_cap; ++i) std::memcpy(sl->tx_host + 3 * i, reqs[std::min(i, count - 1)]->tx, 12);
+    hipStream_t st = sl->stream;
+    if ((s = sl->tx_dev.reserve(c, (size_t)k.B_cap * 3 * sizeof(float), st))) return s;
+    if ((s = sl->out_dev.reserve(c, (size_t)k.outs * sizeof(float), st))) return s;
+    if ((s = reserve_out_host(sl, (size_t)p.outs))) return s;
+    if ((s = c->hip(hipMemcpyAsync(sl->tx_dev.ptr, sl->tx_host, (size_t)k.B_cap * 3 * sizeof(float),
+                                   hipMemcpyHostToDevice, st),
+                    "serve tx H2D")))
+        return s;
+    const float* tx = (const float*)sl->tx_dev.ptr;
+    float* out = (float*)sl->out_dev.ptr;
+    if (S->cfg.use_graphs) {
+        GraphEntry& ge = sl->mgraphs[k.key(flags)];
+        auto gen = [&] { return sl->ws.generation() + sl->tx_dev.gen + sl->out_dev.gen; };
+        if (!ge.exec || ge.gen != gen()) {
+            if (ge.exec) hipGraphExecDestroy(ge.exec);
+            ge.exec = nullptr;
+            // an eager run (tables copied) sizes every buffer; the capture records the launches alone
+            if ((s = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, k.key_cap, k.pair_cap, k.tile_cap))) return s;
+            if ((s = c->hip(hipStreamSynchronize(st), "serve sync"))) return s;
+            hipGraph_t graph = nullptr;
+            if ((s = c->hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture"))) return s;
+            swf_status rs = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, k.key_cap, k.pair_cap, k.tile_cap, false);
+            hipError_t ce = hipStreamEndCapture(st, &graph);
+            if (rs) return rs;
+            if ((s = c->hip(ce, "end capture"))) return s;
+            hipError_t ie = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if ((s = c->hip(ie, "graph instantiate"))) return s;
+            ge.gen = gen();
+            ge.key_cap = k.key_cap;
+            ++S->graph_builds;
+        }
+        if ((s = c->hip(hipMemcpyAsync(sl->ws.mix.ptr, sl->ws.mix_host, p.table_bytes, hipMemcpyHostToDevice, st),
+                        "mix tables H2D")))
+            return s;
+        if ((s = c->hip(hipGraphLaunch(ge.exec, st), "graph launch"))) return s;
+    } else {
+        if ((s = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, k.key_cap, k.pair_cap, k.tile_cap))) return s;
+    }
+    if ((s = c->hip(hipMemcpyAsync(sl->out_host, out, (size_t)p.outs * sizeof(float), hipMemcpyDeviceToHost, st),
+                    "serve out D2H")))
+        return s;
+    if ((s = c->hip(hipMemcpyAsync(sl->status_host, sl->ws.status_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st),
+                    "serve status D2H")))
+        return s;
+    if ((s = c->hip(hipEventRecord(sl->done, st), "serve event"))) return s;
+    const double now = serve_clock();
+    for (Request* r : reqs) {
+        r->t_launch = now;
+        r->batch = count;
+        r->bucket = k.B_cap;
+        r->slot = sl->index;
+        r->state = 1;
+    }
+    sl->busy = true;
+    sl->mixed = true;
+    sl->mix_flags = flags;
+    sl->scene = reqs[0]->scene;
+    sl->bucket = k.B_cap;
+    sl->reqs = reqs;
+    ++S->launched;
+    ++S->mixed_launches;
+    S->mixed_scenes += std::set<int>(sl->ids.begin(), sl->ids.end()).size();
+    return SWF_OK;
+}
+
+// Mixed-mode admission into a free slot. Returns 0 (nothing to admit), 1 (a
+// batch launched or failed), 2 (the batch waits for memory) or 3 (the oldest
+// request is served per scene).
+static int admit_mixed(Ctx* c, ServeState* S, Slot* sl) {
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    std::vector<Request*> batch;
+    int mode;
+    {
+        std::lock_guard<std::mutex> lk2(S->mu);
+        if (S->stop || S->waiting.empty()) return 0;
+        mode = mix_mode(c, S, S->waiting.front()->scene);
+        if (mode < 0) return 3;
+        std::set<int> scenes;
+        for (auto it = S->waiting.begin(); it != S->waiting.end() && (int)batch.size() < S->cfg.max_batch;) {
+            const int id = (*it)->scene;
+            if (mix_mode(c, S, id) == mode && (scenes.count(id) || (int)scenes.size() < kMixScenes)) {
+                scenes.insert(id);
+                batch.push_back(*it);
+                it = S->waiting.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    const int flags = mode ? (S->cfg.flags & (SWF_MLP_BF16 | SWF_PAPER_DEFORM)) : SWF_NO_DEFORM;
+    swf_status st = SWF_OK;
+    // calibrate the key count per query of each new scene once: exact-size lists of one query
+    for (Request* r : batch) {
+        if (st || S->keys_per_query.count(r->scene)) continue;
+        st = sl->tx_dev.reserve(c, 3 * sizeof(float), sl->stream);
+        if (!st)
+            st = c->hip(hipMemcpyAsync(sl->tx_dev.ptr, r->tx, 3 * sizeof(float), hipMemcpyHostToDevice, sl->stream),
+                        "calibration tx");
+        if (!st)
+            st = c->forward_lists(sl->ws, r->scene, (const float*)sl->tx_dev.ptr, 1, mode ? SWF_MLP_BF16 : SWF_NO_DEFORM,
+                                  sl->stream, 0);
+        if (!st) S->keys_per_query[r->scene] = std::max<uint64_t>(sl->ws.last.n_keys, 1);
+    }
+    auto caps = [&](int n) {
+        MixCaps k;
+        int64_t pairs = 0, tiles = 0;
+        double keys = 0;
+        for (int i = 0; i < n; ++i) {
+            const DevScene& d = c->scene(batch[i]->scene)->d;
+            pairs += d.n;
+            tiles += (int64_t)((d.W + 15) / 16) * ((d.H + 15) / 16);
+            k.outs += (int64_t)d.H * d.W;
+            keys += (double)S->keys_per_query[batch[i]->scene];
+        }
+        k.B_cap = pow2_at_least(n);
+        k.pair_cap = round_cap(pairs, 1 << 14);
+        k.tile_cap = round_cap(tiles, 256);
+        k.key_cap = (uint64_t)round_cap((int64_t)std::ceil(keys * S->cfg.key_factor) + 4096, 1 << 16);
+        return k;
+    };
+    int count = (int)batch.size();
+    if (!st && S->cfg.hbm_budget) {
+        auto fits = [&](int n) {
+            uint64_t others = 0;
+            for (Slot* o : S->slots)
+                if (o != sl) others += slot_bytes(o);
+            return others + std::max<uint64_t>(slot_bytes(sl), estimate_mixed_bytes(caps(n))) <= S->cfg.hbm_budget;
+        };
+        if (!fits(count)) {
+            for (Slot* o : S->slots)
+                if (!o->busy && o != sl && slot_bytes(o)) {
+                    drop_graphs(o);
+                    o->ws.release();
+                    o->ws.init(c);
+                    o->tx_dev.release();
+                    o->out_dev.release();
+                }
+            while (count > 1 && !fits(count)) count = (count + 1) / 2;
+            if (!fits(count) && slot_bytes(sl)) {
+                drop_graphs(sl);
+                sl->ws.release();
+                sl->ws.init(c);
+                sl->tx_dev.release();
+                sl->out_dev.release();
+            }
+            if (!fits(count)) {
+                bool others_busy = false;
+                for (Slot* o : S->slots) others_busy = others_busy || (o != sl && o->busy);
+                if (others_busy) {
+                    std::lock_guard<std::mutex> lk2(S->mu);
+                    for (auto it = batch.rbegin(); it != batch.rend(); ++it) S->waiting.push_front(*it);
+                    return 2;
+                }
+                st = SWF_E_OOM;
+            }
+            if (!st && count < (int)batch.size()) {
+                // the tail goes back to the front of the queue, in its order
+                std::lock_guard<std::mutex> lk2(S->mu);
+                for (int i = (int)batch.size() - 1; i >= count; --i) S->waiting.push_front(batch[i]);
+                batch.resize(count);
+                ++S->shrinks;
+            }
+        }
+    }
+    if (!st) st = launch_mixed(c, S, sl, batch, flags, caps(count));
+    if (st) {
+        std::lock_guard<std::mutex> lk2(S->mu);
+        for (Request* r : batch) {
+            r->state = st;
+            r->t_done = serve_clock();
+        }
+        S->cv.notify_all();
+    }
+    return 1;
 }
 
 static void scheduler(Ctx* c) {
@@ -264,6 +554,14 @@ static void scheduler(Ctx* c) {
         // admission into free slots
         for (Slot* sl : S->slots) {
             if (sl->busy) continue;
+            if (S->cfg.mixed) {
+                const int r = admit_mixed(c, S, sl);
+                if (r == 1) {
+                    any_busy = any_busy || sl->busy;
+                    continue;
+                }
+                if (r != 3) break;
+            }
             std::vector<Request*> batch;
             int scene = -1;
             {
@@ -428,6 +726,7 @@ swf_status swf_serve_start(swf_ctx* h, const swf_serve_config* cfg) {
         if (cfg->key_factor > 0) S->cfg.key_factor = cfg->key_factor;
         S->cfg.hbm_budget = cfg->hbm_budget;
         S->cfg.use_graphs = cfg->use_graphs;
+        S->cfg.mixed = cfg->mixed;
     }
     if (S->cfg.max_batch > 1024 || S->cfg.n_slots > 16) {
         delete S;
@@ -438,7 +737,7 @@ swf_status swf_serve_start(swf_ctx* h, const swf_serve_config* cfg) {
         sl->index = i;
         bool ok = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) == hipSuccess &&
-                  hipHostMalloc(&sl->tx_host, sizeof(float) * 3 * S->cfg.max_batch, 0) == hipSuccess &&
+                  hipHostMalloc(&sl->tx_host, sizeof(float) * 3 * pow2_at_least(S->cfg.max_batch), 0) == hipSuccess &&
                   hipHostMalloc(&sl->status_host, 64, 0) == hipSuccess && sl->ws.init(c) == SWF_OK;
         S->slots.push_back(sl);
         if (!ok) {
@@ -535,11 +834,12 @@ swf_status swf_serve_counters(swf_ctx* h, uint64_t* counters, int32_t n) {
     if (!c || !counters) return SWF_E_INVALID;
     if (!c->serve) return SWF_E_STATE;
     ServeState* S = c->serve;
-    const uint64_t v[6] = {S->launched.load(), S->completed.load(), S->fallbacks.load(), S->graph_builds.load(),
-                           S->shrinks.load(), 0};
     uint64_t bytes = 0;
     for (Slot* sl : S->slots) bytes += slot_bytes(sl);
-    for (int i = 0; i < n && i < 6; ++i) counters[i] = i == 5 ? bytes : v[i];
+    const uint64_t v[8] = {S->launched.load(),     S->completed.load(), S->fallbacks.load(),
+                           S->graph_builds.load(), S->shrinks.load(),   bytes,
+                           S->mixed_launches.load(), S->mixed_scenes.load()};
+    for (int i = 0; i < n && i < 8; ++i) counters[i] = v[i];
     return SWF_OK;
 }
 

@@ -1,6 +1,7 @@
 """Serving loop (continuous batching, captured graphs, admission by memory):
-each result is bitwise identical alone and in a mixed stream, under forced
-shrinking and forced key overflow; error paths."""
+each result is bitwise identical alone and in a mixed stream, per-scene
+batches and batches across scenes (mixed mode, graphs keyed by capacities),
+under forced shrinking and forced key overflow; error paths."""
 import numpy as np
 import pytest
 
@@ -57,6 +58,68 @@ def test_mixed_stream_equals_alone(setup, graphs):
     assert max(s["batch"] for s in stats) > 1  # requests were actually batched
     if graphs:
         assert cnt["graph_builds"] >= 1
+    print("counters", cnt)
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_mixed_mode_batches_across_scenes(setup, graphs):
+    # one launch holds requests of several scenes (different sizes, grids and MLPs); every result is what the
+    # query renders alone, and a handful of capacity-keyed graphs serves all the batches
+    c, sids, reqs, alone = setup
+    outs, stats, cnt = _serve_all(c, sids, reqs, max_batch=16, n_slots=2, use_graphs=graphs, mixed=True)
+    for i, (o, a) in enumerate(zip(outs, alone)):
+        np.testing.assert_array_equal(o, a, err_msg=f"request {i}")
+    assert cnt["completed"] == len(reqs)
+    assert cnt["mixed_launches"] == cnt["launches"] >= 1
+    assert cnt["mixed_scenes"] > cnt["mixed_launches"]  # some launch held more than one scene
+    assert max(s["batch"] for s in stats) > 1
+    if graphs:
+        assert 1 <= cnt["graph_builds"] <= 2 * cnt["launches"]
+    print("counters", cnt)
+
+
+def test_mixed_mode_keeps_static_scenes_apart(setup):
+    # a scene without an MLP renders statically: it never shares a launch with the deformable scenes, and its
+    # requests still come back right
+    import torch
+    from paper_2506_12787_amd import binding as B
+    c, sids, reqs, alone = setup
+    g = synth.gaussians(1500, 45, 130, seed=510)
+    sid_s = c.upload_scene(g, 45, 130)
+    ref = c.render(sid_s, None, flags=B.NO_DEFORM, batch=1)[0].cpu().numpy()
+    c.serve_start(max_batch=16, n_slots=2, mixed=True)
+    outs, tks = [], []
+    for k, (si, tx) in enumerate(reqs[:20]):
+        for sid, shape in ((sids[si], SCENES[si][1:]), (sid_s, (45, 130))):
+            if sid == sid_s and k % 3:
+                continue
+            o = np.zeros(shape, np.float32)
+            tks.append((c.serve_submit(sid, tx, o), sid, k))
+            outs.append(o)
+    stats = [c.serve_wait(t) for t, _, _ in tks]
+    cnt = c.serve_counters()
+    c.serve_stop()
+    for o, (_, sid, k) in zip(outs, tks):
+        np.testing.assert_array_equal(o, ref if sid == sid_s else alone[k])
+    assert cnt["completed"] == len(tks) and cnt["mixed_launches"] == cnt["launches"]
+    c.release_scene(sid_s)
+    torch.cuda.synchronize()
+    print("counters", cnt, "batches", sorted({s["batch"] for s in stats}))
+
+
+def test_mixed_mode_under_budget_and_key_overflow(setup):
+    c, sids, reqs, alone = setup
+    # one slot: half of what it holds unconstrained forces the 16-query batches to shrink
+    _, _, cnt = _serve_all(c, sids, reqs, max_batch=16, n_slots=1, mixed=True)
+    budget = cnt["workspace_bytes"] // 2
+    outs, stats, cnt = _serve_all(c, sids, reqs, max_batch=16, n_slots=1, hbm_budget=budget, mixed=True)
+    for o, a in zip(outs, alone):
+        np.testing.assert_array_equal(o, a)
+    assert cnt["budget_shrinks"] >= 1 and cnt["workspace_bytes"] <= budget, (cnt, budget)
+    outs, stats, cnt = _serve_all(c, sids, reqs[:12], max_batch=4, n_slots=2, key_factor=0.05, mixed=True)
+    for o, a in zip(outs, alone[:12]):
+        np.testing.assert_array_equal(o, a)
+    assert cnt["fallbacks"] >= 1 and any(s["fallback"] for s in stats)
     print("counters", cnt)
 
 
