@@ -125,6 +125,17 @@ __device__ __forceinline__ int mix_find(const MixQuery* qs, int B, int v, F fiel
 void launch_mix_tx_features(const MixBatch& m, const float* tx, float* qs, hipStream_t st);
 void launch_mix_static(const MixBatch& m, int64_t pair_cap, const Grid& tile, const Records& r, hipStream_t st);
 void launch_mix_clear_tail(const MixBatch& m, int64_t pair_cap, const Records& r, hipStream_t st);
+// Lists of a mixed batch by binning (sort.hip), with the geometry of its largest query (max_n pairs, max_tiles
+// tiles) for every query; ranges over its global tiles.
+bool mix_bin_fits(int B, int max_tiles);
+size_t mix_bin_hist_entries(int B, int max_n, int max_tiles);
+void launch_mix_bin_hist(const MixBatch& m, int max_n, int max_tiles, const Records& r, uint32_t* hist,
+                         unsigned long long* cull, hipStream_t st);
+void launch_mix_bin_scatter(const MixBatch& m, int max_n, int max_tiles, const Records& r,
+                            const uint32_t* hist_scanned, const uint64_t* n_dev, uint32_t* vals, hipStream_t st);
+void launch_mix_bin_ranges(const MixBatch& m, int max_n, int max_tiles, const uint32_t* hist_scanned,
+                           const uint64_t* total, const uint64_t* n_dev, int64_t tile_cap, uint2* ranges,
+                           hipStream_t st);
 void launch_mix_emit_keys(const MixBatch& m, const Records& r, const uint32_t* offsets, int64_t pair_cap,
                           uint64_t capacity, uint32_t* keys, uint32_t* vals, uint32_t* status,
                           unsigned long long* cull, hipStream_t st);

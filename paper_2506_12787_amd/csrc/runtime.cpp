@@ -845,6 +845,7 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
 // count) or at fixed capacities with no host wait (graph-capturable: a replay
 // copies whatever tables the staging holds by then).
 swf_status Ctx::plan_mixed(Workspace& w, const int32_t* scene_ids, int B, int flags, int B_cap, MixPlan& p) {
+    p = MixPlan{};  // a caller may hand in the previous batch's plan
     if (B < 1 || B > 65535 || B_cap < B || !scene_ids) return fail(SWF_E_INVALID, "bad batch or scene ids");
     const bool deform = !(flags & SWF_NO_DEFORM);
     if (flags & ~(SWF_MLP_BF16 | SWF_NO_DEFORM | SWF_PAPER_DEFORM))
@@ -891,6 +892,8 @@ swf_status Ctx::plan_mixed(Workspace& w, const int32_t* scene_ids, int B, int fl
         const MixScene& m = sc[it->second];
         q[b] = MixQuery{it->second, (int)pairs, (int)tiles, (int)outs, (int)mtiles};
         p.out_off[b] = (uint64_t)outs;
+        p.max_n = std::max(p.max_n, m.N);
+        p.max_tiles = std::max(p.max_tiles, m.tiles);
         pairs += m.N;
         tiles += m.tiles;
         outs += (int64_t)m.H * m.W;
@@ -927,17 +930,26 @@ swf_status Ctx::plan_mixed(Workspace& w, const int32_t* scene_ids, int B, int fl
 }
 
 swf_status Ctx::enqueue_mixed(Workspace& w, const MixPlan& p, const float* tx, int flags, float* out, hipStream_t st,
-                              uint64_t key_cap, int64_t pair_cap, int64_t tile_cap, bool copy_tables) {
+                              const MixCaps* caps, bool copy_tables) {
     if (!out) return fail(SWF_E_INVALID, "out is NULL");
     const bool deform = !(flags & SWF_NO_DEFORM);
     if (deform && !tx) return fail(SWF_E_INVALID, "tx is NULL");
-    const bool fixed = key_cap > 0;
-    if (!fixed) {
-        pair_cap = p.pairs;
-        tile_cap = p.tiles;
-    } else if (pair_cap < p.pairs || tile_cap < p.tiles) {
-        return fail(SWF_E_INVALID, "mixed batch exceeds its capacities");
+    MixCaps k;
+    if (caps) {
+        k = *caps;
+        if (k.B_cap != p.B_cap || k.pair_cap < p.pairs || k.tile_cap < p.tiles || k.bin_n < p.max_n ||
+            k.bin_tiles < p.max_tiles || k.key_cap == 0)
+            return fail(SWF_E_INVALID, "mixed batch exceeds its capacities");
+    } else {
+        k.B_cap = p.B_cap;
+        k.pair_cap = p.pairs;
+        k.tile_cap = p.tiles;
+        k.bin_n = p.max_n;
+        k.bin_tiles = p.max_tiles;
     }
+    const int64_t pair_cap = k.pair_cap, tile_cap = k.tile_cap;
+    // lists by binning (per query, the geometry of the largest), else by key emission and radix sort
+    const bool binned = mix_bin_fits(k.B_cap, k.bin_tiles);
     swf_status s;
     if ((s = w.mix.reserve(this, p.table_bytes, st))) return s;
     if (copy_tables &&
@@ -966,39 +978,64 @@ swf_status Ctx::enqueue_mixed(Workspace& w, const MixPlan& p, const float* tx, i
         if ((s = w.qs.reserve(this, (size_t)p.B_cap * 256 * sizeof(float), st))) return s;
         launch_mix_tx_features(mb, tx, (float*)w.qs.ptr, st);
         launch_mix_mlp_bf16(mb, (const float*)w.qs.ptr, w.rec, st, (flags & SWF_PAPER_DEFORM) != 0, false);
-        launch_mix_clear_tail(mb, pair_cap, w.rec, st);  // rows past the batch's pairs: no tiles
+        // rows past the batch's pairs: no tiles (the scan of the sort path reads them)
+        if (!binned) launch_mix_clear_tail(mb, pair_cap, w.rec, st);
     } else {
         launch_mix_static(mb, pair_cap, make_grid(16, 16, 16), w.rec, st);
     }
     stage_end(st);
-    // lists: scan of every record's tile count, key emission, radix sort over the batch's global tiles, ranges
-    if ((s = w.off.reserve(this, (size_t)pair_cap * sizeof(uint32_t) + 16, st))) return s;
-    if ((s = w.scan.reserve(this, scan_scratch_bytes(pair_cap) + 64, st))) return s;
-    stage_begin(SWF_STAGE_SCAN, st);
-    launch_exclusive_scan(w.rec.count, (uint32_t*)w.off.ptr, w.total_dev, pair_cap, w.scan.ptr, st);
-    stage_end(st);
     uint64_t nk;
     const uint64_t* n_dev;
-    if ((s = key_count(w, st, key_cap, nk, n_dev))) return s;
-    if ((s = w.keys.reserve(this, nk * 4 + 16, st))) return s;
-    if ((s = w.keys2.reserve(this, nk * 4 + 16, st))) return s;
-    if ((s = w.vals.reserve(this, nk * 4 + 16, st))) return s;
-    if ((s = w.vals2.reserve(this, nk * 4 + 16, st))) return s;
-    if ((s = w.hist.reserve(this, radix_scratch_bytes((int64_t)nk) + 64, st))) return s;
+    void* skeys = nullptr;
+    uint32_t* svals = nullptr;
     if ((s = w.ranges.reserve(this, (size_t)tile_cap * sizeof(uint2) + 16, st))) return s;
-    stage_begin(SWF_STAGE_EMIT, st);
-    launch_mix_emit_keys(mb, w.rec, (const uint32_t*)w.off.ptr, pair_cap, nk, (uint32_t*)w.keys.ptr,
-                         (uint32_t*)w.vals.ptr, w.status_dev, w.cull_dev, st);
-    stage_end(st);
-    stage_begin(SWF_STAGE_SORT, st);
-    const int flip = launch_radix_sort(w.keys.ptr, (uint32_t*)w.vals.ptr, w.keys2.ptr, (uint32_t*)w.vals2.ptr,
-                                       (int64_t)nk, 4, 0, bits_for((uint64_t)tile_cap), w.hist.ptr, st, n_dev);
-    stage_end(st);
-    void* skeys = flip ? w.keys2.ptr : w.keys.ptr;
-    uint32_t* svals = (uint32_t*)(flip ? w.vals2.ptr : w.vals.ptr);
-    stage_begin(SWF_STAGE_RANGES, st);
-    launch_tile_ranges(skeys, 4, (int64_t)nk, tile_cap, (uint2*)w.ranges.ptr, st, n_dev);
-    stage_end(st);
+    if (binned) {
+        // tile histograms per block of pairs of each query, their scan, stable placement, ranges
+        const int64_t nh = (int64_t)mix_bin_hist_entries(k.B_cap, k.bin_n, k.bin_tiles);
+        if ((s = w.bins.reserve(this, (size_t)nh * sizeof(uint32_t) + 16, st))) return s;
+        if ((s = w.scan.reserve(this, scan_scratch_bytes(nh) + 64, st))) return s;
+        uint32_t* bins = (uint32_t*)w.bins.ptr;
+        stage_begin(SWF_STAGE_SCAN, st);
+        launch_mix_bin_hist(mb, k.bin_n, k.bin_tiles, w.rec, bins, w.cull_dev, st);
+        launch_exclusive_scan(bins, bins, w.total_dev, nh, w.scan.ptr, st);
+        stage_end(st);
+        if ((s = key_count(w, st, k.key_cap, nk, n_dev))) return s;
+        if ((s = w.vals.reserve(this, nk * 4 + 16, st))) return s;
+        stage_begin(SWF_STAGE_SORT, st);
+        launch_mix_bin_scatter(mb, k.bin_n, k.bin_tiles, w.rec, bins, n_dev, (uint32_t*)w.vals.ptr, st);
+        stage_end(st);
+        stage_begin(SWF_STAGE_RANGES, st);
+        launch_mix_bin_ranges(mb, k.bin_n, k.bin_tiles, bins, w.total_dev, n_dev, tile_cap, (uint2*)w.ranges.ptr,
+                              st);
+        stage_end(st);
+        svals = (uint32_t*)w.vals.ptr;
+    } else {
+        // scan of every record's tile count, key emission, radix sort over the batch's global tiles, ranges
+        if ((s = w.off.reserve(this, (size_t)pair_cap * sizeof(uint32_t) + 16, st))) return s;
+        if ((s = w.scan.reserve(this, scan_scratch_bytes(pair_cap) + 64, st))) return s;
+        stage_begin(SWF_STAGE_SCAN, st);
+        launch_exclusive_scan(w.rec.count, (uint32_t*)w.off.ptr, w.total_dev, pair_cap, w.scan.ptr, st);
+        stage_end(st);
+        if ((s = key_count(w, st, k.key_cap, nk, n_dev))) return s;
+        if ((s = w.keys.reserve(this, nk * 4 + 16, st))) return s;
+        if ((s = w.keys2.reserve(this, nk * 4 + 16, st))) return s;
+        if ((s = w.vals.reserve(this, nk * 4 + 16, st))) return s;
+        if ((s = w.vals2.reserve(this, nk * 4 + 16, st))) return s;
+        if ((s = w.hist.reserve(this, radix_scratch_bytes((int64_t)nk) + 64, st))) return s;
+        stage_begin(SWF_STAGE_EMIT, st);
+        launch_mix_emit_keys(mb, w.rec, (const uint32_t*)w.off.ptr, pair_cap, nk, (uint32_t*)w.keys.ptr,
+                             (uint32_t*)w.vals.ptr, w.status_dev, w.cull_dev, st);
+        stage_end(st);
+        stage_begin(SWF_STAGE_SORT, st);
+        const int flip = launch_radix_sort(w.keys.ptr, (uint32_t*)w.vals.ptr, w.keys2.ptr, (uint32_t*)w.vals2.ptr,
+                                           (int64_t)nk, 4, 0, bits_for((uint64_t)tile_cap), w.hist.ptr, st, n_dev);
+        stage_end(st);
+        skeys = flip ? w.keys2.ptr : w.keys.ptr;
+        svals = (uint32_t*)(flip ? w.vals2.ptr : w.vals.ptr);
+        stage_begin(SWF_STAGE_RANGES, st);
+        launch_tile_ranges(skeys, 4, (int64_t)nk, tile_cap, (uint2*)w.ranges.ptr, st, n_dev);
+        stage_end(st);
+    }
     stage_begin(SWF_STAGE_BLEND, st);
     launch_mix_blend(mb, (int)tile_cap, (const uint2*)w.ranges.ptr, svals, w.rec, out, st);
     stage_end(st);
@@ -1012,7 +1049,7 @@ swf_status Ctx::enqueue_mixed(Workspace& w, const MixPlan& p, const float* tx, i
     w.last.grid.tiles = (int)p.tiles;
     w.last.n_keys = nk;
     w.last.full = false;
-    w.last.binned = false;
+    w.last.binned = binned;
     w.last.keys = skeys;
     w.last.vals = svals;
     w.last.rerenders = 0;

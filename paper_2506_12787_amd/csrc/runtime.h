@@ -93,9 +93,19 @@ constexpr int kMixScenes = 64;  // distinct scenes per mixed batch
 struct MixPlan {
     int B = 0, B_cap = 0, first_scene = -1;
     int64_t pairs = 0, tiles = 0, outs = 0;
+    int max_n = 0, max_tiles = 0;  // the largest query's pairs and tiles
     uint64_t nan_pairs = 0;
     std::vector<uint64_t> out_off;  // B + 1 entries
     size_t query_off = 0, table_bytes = 0;
+};
+// Capacities a mixed batch is launched at: no host wait for the key count,
+// every grid fixed by these values (graph-capturable).
+struct MixCaps {
+    int B_cap = 0;
+    int64_t pair_cap = 0, tile_cap = 0;
+    uint64_t key_cap = 0;
+    int bin_n = 0, bin_tiles = 0;  // binning geometry: the largest query it covers
+    int64_t outs = 0;              // output floats of the batch (not a launch parameter)
 };
 
 struct ServeState;
@@ -163,12 +173,11 @@ struct Ctx {
     swf_status render_mixed(Workspace& w, const int32_t* scene_ids, const float* tx, int B, int flags, float* out,
                             uint64_t* out_offsets, hipStream_t st);
     swf_status plan_mixed(Workspace& w, const int32_t* scene_ids, int B, int flags, int B_cap, MixPlan& p);
-    // key_cap == 0: exactly sized (waits for the key count); else fixed capacities, no host wait.
+    // caps == NULL: exactly sized (waits for the key count); else launched at those capacities, no host wait.
     // copy_tables = false leaves the staging -> device copy of the tables to the caller (a graph of the
     // launches alone).
     swf_status enqueue_mixed(Workspace& w, const MixPlan& p, const float* tx, int flags, float* out, hipStream_t st,
-                             uint64_t key_cap = 0, int64_t pair_cap = 0, int64_t tile_cap = 0,
-                             bool copy_tables = true);
+                             const MixCaps* caps = nullptr, bool copy_tables = true);
     swf_status backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out,
                         const void* aux, const swf_grads* grads, hipStream_t st);
     swf_status mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,

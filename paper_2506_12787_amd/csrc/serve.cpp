@@ -60,15 +60,11 @@ struct GraphEntry {
     uint64_t key_cap = 0;
 };
 
-// Capacities of a mixed batch's graph: queries, pairs, global tiles, keys.
-struct MixCaps {
-    int B_cap = 0;
-    int64_t pair_cap = 0, tile_cap = 0;
-    uint64_t key_cap = 0;
-    int64_t outs = 0;  // output floats of the batch (not part of the graph's key)
-    auto key(int flags) const { return std::make_tuple(flags, B_cap, pair_cap, tile_cap, key_cap); }
-};
-using MixKey = std::tuple<int, int, int64_t, int64_t, uint64_t>;
+// A mixed batch's graph: flags and the capacities it was captured at.
+using MixKey = std::tuple<int, int, int64_t, int64_t, uint64_t, int, int>;
+MixKey mix_key(int flags, const MixCaps& k) {
+    return std::make_tuple(flags, k.B_cap, k.pair_cap, k.tile_cap, k.key_cap, k.bin_n, k.bin_tiles);
+}
 
 struct Slot {
     int index = 0;
@@ -90,6 +86,7 @@ struct Slot {
     MixPlan plan;
     std::vector<int32_t> ids;
     std::map<MixKey, GraphEntry> mgraphs;
+    std::map<int, MixCaps> mix_hw;  // per B_cap: the largest capacities launched so far (its graph's)
 };
 
 struct ServeState {
@@ -103,6 +100,7 @@ struct ServeState {
     uint64_t next_ticket = 1;
     std::vector<Slot*> slots;
     std::map<int, uint64_t> keys_per_query;  // calibrated per scene
+    Workspace cal;                           // mixed mode: calibration renders, released after each
     std::atomic<uint64_t> launched{0}, completed{0}, fallbacks{0}, graph_builds{0}, shrinks{0};
     std::atomic<uint64_t> mixed_launches{0}, mixed_scenes{0};
 };
@@ -124,6 +122,7 @@ void drop_graphs(Slot* s) {
     for (auto& kv : s->mgraphs)
         if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
     s->mgraphs.clear();
+    s->mix_hw.clear();
 }
 
 int pow2_at_least(int64_t x) {
@@ -146,7 +145,7 @@ int64_t round_cap(int64_t x, int64_t lo) {
 uint64_t estimate_mixed_bytes(const MixCaps& k) {
     const uint64_t raw = (uint64_t)k.pair_cap * 56 + k.key_cap * 16 + (uint64_t)k.tile_cap * 8 +
                          (uint64_t)k.outs * 4 + (uint64_t)k.B_cap * (256 * 4 + 1024) + (uint64_t)k.pair_cap / 64 +
-                         (1u << 20);
+                         mix_bin_hist_entries(k.B_cap, k.bin_n, k.bin_tiles) * 4 + (1u << 20);
     return raw + raw / 4 + 64 * 256;
 }
 
@@ -372,17 +371,17 @@ static swf_status launch_mixed(Ctx* c, ServeState* S, Slot* sl, std::vector<Requ
     const float* tx = (const float*)sl->tx_dev.ptr;
     float* out = (float*)sl->out_dev.ptr;
     if (S->cfg.use_graphs) {
-        GraphEntry& ge = sl->mgraphs[k.key(flags)];
+        GraphEntry& ge = sl->mgraphs[mix_key(flags, k)];
         auto gen = [&] { return sl->ws.generation() + sl->tx_dev.gen + sl->out_dev.gen; };
         if (!ge.exec || ge.gen != gen()) {
             if (ge.exec) hipGraphExecDestroy(ge.exec);
             ge.exec = nullptr;
             // an eager run (tables copied) sizes every buffer; the capture records the launches alone
-            if ((s = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, k.key_cap, k.pair_cap, k.tile_cap))) return s;
+            if ((s = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, &k))) return s;
             if ((s = c->hip(hipStreamSynchronize(st), "serve sync"))) return s;
             hipGraph_t graph = nullptr;
             if ((s = c->hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture"))) return s;
-            swf_status rs = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, k.key_cap, k.pair_cap, k.tile_cap, false);
+            swf_status rs = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, &k, false);
             hipError_t ce = hipStreamEndCapture(st, &graph);
             if (rs) return rs;
             if ((s = c->hip(ce, "end capture"))) return s;
@@ -398,7 +397,7 @@ static swf_status launch_mixed(Ctx* c, ServeState* S, Slot* sl, std::vector<Requ
             return s;
         if ((s = c->hip(hipGraphLaunch(ge.exec, st), "graph launch"))) return s;
     } else {
-        if ((s = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, k.key_cap, k.pair_cap, k.tile_cap))) return s;
+        if ((s = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, &k))) return s;
     }
     if ((s = c->hip(hipMemcpyAsync(sl->out_host, out, (size_t)p.outs * sizeof(float), hipMemcpyDeviceToHost, st),
                     "serve out D2H")))
@@ -453,17 +452,26 @@ static int admit_mixed(Ctx* c, ServeState* S, Slot* sl) {
     }
     const int flags = mode ? (S->cfg.flags & (SWF_MLP_BF16 | SWF_PAPER_DEFORM)) : SWF_NO_DEFORM;
     swf_status st = SWF_OK;
-    // calibrate the key count per query of each new scene once: exact-size lists of one query
+    // calibrate the key count per query of each new scene once: exact-size lists of one query, in a workspace of
+    // their own that is released afterwards (the slot's workspace holds only what its launches use, as the
+    // memory budget counts it)
+    bool calibrated = false;
     for (Request* r : batch) {
         if (st || S->keys_per_query.count(r->scene)) continue;
-        st = sl->tx_dev.reserve(c, 3 * sizeof(float), sl->stream);
+        if (!S->cal.total_dev) st = S->cal.init(c);
+        if (!st) st = sl->tx_dev.reserve(c, 3 * sizeof(float), sl->stream);
         if (!st)
             st = c->hip(hipMemcpyAsync(sl->tx_dev.ptr, r->tx, 3 * sizeof(float), hipMemcpyHostToDevice, sl->stream),
                         "calibration tx");
         if (!st)
-            st = c->forward_lists(sl->ws, r->scene, (const float*)sl->tx_dev.ptr, 1, mode ? SWF_MLP_BF16 : SWF_NO_DEFORM,
+            st = c->forward_lists(S->cal, r->scene, (const float*)sl->tx_dev.ptr, 1, mode ? SWF_MLP_BF16 : SWF_NO_DEFORM,
                                   sl->stream, 0);
-        if (!st) S->keys_per_query[r->scene] = std::max<uint64_t>(sl->ws.last.n_keys, 1);
+        if (!st) S->keys_per_query[r->scene] = std::max<uint64_t>(S->cal.last.n_keys, 1);
+        calibrated = true;
+    }
+    if (calibrated) {
+        hipStreamSynchronize(sl->stream);
+        S->cal.release();
     }
     auto caps = [&](int n) {
         MixCaps k;
@@ -471,15 +479,31 @@ static int admit_mixed(Ctx* c, ServeState* S, Slot* sl) {
         double keys = 0;
         for (int i = 0; i < n; ++i) {
             const DevScene& d = c->scene(batch[i]->scene)->d;
+            const int t = ((d.W + 15) / 16) * ((d.H + 15) / 16);
             pairs += d.n;
-            tiles += (int64_t)((d.W + 15) / 16) * ((d.H + 15) / 16);
+            tiles += t;
             k.outs += (int64_t)d.H * d.W;
             keys += (double)S->keys_per_query[batch[i]->scene];
+            k.bin_n = std::max(k.bin_n, d.n);
+            k.bin_tiles = std::max(k.bin_tiles, t);
         }
         k.B_cap = pow2_at_least(n);
         k.pair_cap = round_cap(pairs, 1 << 14);
         k.tile_cap = round_cap(tiles, 256);
+        k.bin_n = (int)round_cap(k.bin_n, 1024);
         k.key_cap = (uint64_t)round_cap((int64_t)std::ceil(keys * S->cfg.key_factor) + 4096, 1 << 16);
+        // capacities only grow per slot and batch size, so that after the largest batches one graph per size
+        // serves them all (the binning path's cost does not grow with them: its grids follow the largest
+        // query and the batch's own totals, read on the device)
+        auto it = sl->mix_hw.find(k.B_cap);
+        if (it != sl->mix_hw.end()) {
+            const MixCaps& h = it->second;
+            k.pair_cap = std::max(k.pair_cap, h.pair_cap);
+            k.tile_cap = std::max(k.tile_cap, h.tile_cap);
+            k.key_cap = std::max(k.key_cap, h.key_cap);
+            k.bin_n = std::max(k.bin_n, h.bin_n);
+            k.bin_tiles = std::max(k.bin_tiles, h.bin_tiles);
+        }
         return k;
     };
     int count = (int)batch.size();
@@ -526,7 +550,11 @@ static int admit_mixed(Ctx* c, ServeState* S, Slot* sl) {
             }
         }
     }
-    if (!st) st = launch_mixed(c, S, sl, batch, flags, caps(count));
+    if (!st) {
+        const MixCaps k = caps(count);
+        st = launch_mixed(c, S, sl, batch, flags, k);
+        if (!st) sl->mix_hw[k.B_cap] = k;
+    }
     if (st) {
         std::lock_guard<std::mutex> lk2(S->mu);
         for (Request* r : batch) {
@@ -693,6 +721,7 @@ void serve_shutdown(Ctx* c) {
         if (sl->stream) hipStreamDestroy(sl->stream);
         delete sl;
     }
+    if (S->cal.total_dev) S->cal.release();
     for (auto& kv : S->table) delete kv.second;
     for (Request* r : S->waiting)
         if (!S->table.count(r->ticket)) delete r;

@@ -365,13 +365,45 @@ __device__ __forceinline__ uint32_t seg_count(uint2 r, int TW, int t0, int seg) 
     return c;
 }
 
+// A query's pairs and tile grid for the binning kernels: uniform over a
+// single-scene batch (G), from the batch's tables for a mixed one, whose
+// geometry G (segments, block size, blocks per query) covers its largest
+// query: a smaller query leaves its extra blocks and segments empty.
+struct BinQuery {
+    int N, TW, tiles, S;
+    size_t row0;
+};
+
+template <bool kMix>
+__device__ __forceinline__ BinQuery bin_query(const BinGeom& G, const MixBatch& mix, int q) {
+    BinQuery b;
+    if constexpr (kMix) {
+        const MixQuery& a = mix.queries[q];
+        const MixQuery& e = mix.queries[q + 1];
+        b.N = e.pair_base - a.pair_base;  // 0 for the padding queries of a capacity-sized batch
+        b.tiles = e.tile_base - a.tile_base;
+        b.TW = mix.scenes[a.scene].TW;
+        b.S = (b.tiles + (1 << G.db) - 1) >> G.db;
+        b.row0 = (size_t)a.pair_base;
+    } else {
+        b.N = G.N;
+        b.tiles = G.tiles;
+        b.TW = G.TW;
+        b.S = G.S;
+        b.row0 = (size_t)q * G.N;
+    }
+    return b;
+}
+
 // Tile histogram of one block of pairs of one query, for every tile segment:
 // hist[((q * S + segment) * 256 + tile % 256) * nbq + block]. With one segment
 // the counts are kept per wave (less atomic contention).
+template <bool kMix = false>
 __global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restrict__ rect,
                                                             const uint32_t* __restrict__ count, BinGeom G,
                                                             uint32_t* __restrict__ hist,
-                                                            unsigned long long* __restrict__ cull) {
+                                                            unsigned long long* __restrict__ cull,
+                                                            MixBatch mix = MixBatch{}) {
     __shared__ uint32_t h[kMaxTiles + 1024];  // S segments of 2^db tiles: at most kMaxTiles + 2^db - 1
     __shared__ uint32_t nculled[2];
     const int kSegTiles = 1 << G.db;
@@ -382,8 +414,9 @@ __global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restr
     __syncthreads();
     uint32_t* hw = one ? h + (threadIdx.x >> 6) * kSegTiles : h;
     const int j = blockIdx.x, q = blockIdx.y;
-    const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, G.N);
-    const size_t row0 = (size_t)q * G.N;
+    const BinQuery Q = bin_query<kMix>(G, mix, q);
+    const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, Q.N);
+    const size_t row0 = Q.row0;
     uint32_t nf = 0, og = 0;  // culled pairs seen by this thread, by reason
     for (int p = p_beg + (int)threadIdx.x; p < p_end; p += kThreads) {
         const uint2 r = rect[row0 + p];
@@ -392,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restr
             og += r.y == kCullOffGrid;
             continue;
         }
-        for_seg_tiles(r, G.TW, 0, G.tiles, [&](uint32_t, uint32_t t) { atomicAdd(&hw[t], 1u); });
+        for_seg_tiles(r, Q.TW, 0, Q.tiles, [&](uint32_t, uint32_t t) { atomicAdd(&hw[t], 1u); });
     }
     if (nf) atomicAdd(&nculled[0], nf);
     if (og) atomicAdd(&nculled[1], og);
@@ -478,12 +511,13 @@ __device__ __forceinline__ uint32_t seg_tile_at(int a0, int rb, uint32_t n0, uin
 // ranks it among equal tiles with wave64 ballots, and the ranks are offset per
 // wave and per tile through LDS counters; base[] holds each tile's next output
 // position for this block.
-template <int PPT, int DB>
+template <int PPT, int DB, bool kMix = false>
 __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __restrict__ rect,
                                                                const uint32_t* __restrict__ count, BinGeom G,
                                                                const uint32_t* __restrict__ hs,
                                                                const uint64_t* __restrict__ n_dev,
-                                                               uint32_t* __restrict__ vals) {
+                                                               uint32_t* __restrict__ vals,
+                                                               MixBatch mix = MixBatch{}) {
     constexpr int kSeg = 1 << DB;
     constexpr int kBatch = kThreads * PPT;
     // fixed-capacity run that overflowed: nothing is placed (block-uniform)
@@ -498,9 +532,11 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
     __shared__ float s_rw[kBatch];
     const int w = threadIdx.x >> 6;
     const int j = blockIdx.x, q = blockIdx.y;
-    const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, G.N);
-    const size_t row0 = (size_t)q * G.N;
-    for (int sg = 0; sg < G.S; ++sg) {
+    const BinQuery Q = bin_query<kMix>(G, mix, q);
+    const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, Q.N);
+    const size_t row0 = Q.row0;
+    // segments past the query's tiles hold no keys (their histogram entries are zero)
+    for (int sg = 0; sg < Q.S; ++sg) {
         const int t0 = sg * kSeg;
         __syncthreads();  // the previous segment is placed
         for (int d = threadIdx.x; d < kSeg; d += kThreads)
@@ -521,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 r[i] = r_next[i];
-                c[i] = !c_next[i] ? 0u : (G.S == 1 ? c_next[i] : seg_count(r[i], G.TW, t0, kSeg));
+                c[i] = !c_next[i] ? 0u : (Q.S == 1 ? c_next[i] : seg_count(r[i], Q.TW, t0, kSeg));
                 csum += c[i];
                 const int pn = s0 + kBatch + (int)threadIdx.x * PPT + i;
                 c_next[i] = pn < p_end ? count[row0 + pn] : 0u;
@@ -535,7 +571,7 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
                 const int e = (int)threadIdx.x * PPT + i;  // pair within the batch
                 s_o[e] = o;
                 if (c[i]) {
-                    const SegRun sr = seg_run(r[i], G.TW, t0, kSeg);
+                    const SegRun sr = seg_run(r[i], Q.TW, t0, kSeg);
                     s_a0[e] = sr.a0;
                     s_rb[e] = sr.rb;
                     s_n0[e] = sr.n0;
@@ -570,7 +606,7 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
                         for (int step = kBatch / 2; step > 0; step >>= 1)
                             if (s_o[lo + step] <= gp) lo += step;
                         pr = (uint32_t)lo;
-                        d = seg_tile_at(s_a0[lo], s_rb[lo], s_n0[lo], s_w[lo], s_rw[lo], G.TW, gp - s_o[lo]);
+                        d = seg_tile_at(s_a0[lo], s_rb[lo], s_n0[lo], s_w[lo], s_rw[lo], Q.TW, gp - s_o[lo]);
                     }
                     dig[jj] = d;
                     pl[jj] = pr;
@@ -604,6 +640,25 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
             }
         }
     }
+}
+
+// Ranges of a mixed batch's global tiles: tile t of query q sits at histogram
+// entry (q, segment t >> db, t mod 2^db) of the batch geometry.
+__global__ void mix_bin_ranges_kernel(const uint32_t* __restrict__ hs, MixBatch mix, BinGeom G,
+                                      const uint64_t* __restrict__ total, const uint64_t* __restrict__ n_dev,
+                                      int64_t tile_cap, uint2* __restrict__ ranges) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tile_cap || i >= mix.queries[mix.B].tile_base) return;  // the blend skips tiles past the batch
+    if (n_dev && *n_dev == 0) {
+        ranges[i] = make_uint2(0u, 0u);
+        return;
+    }
+    const int q = mix_find(mix.queries, mix.B, (int)i, [](const MixQuery& x) { return x.tile_base; });
+    const int64_t t = i - mix.queries[q].tile_base;
+    const size_t e = ((size_t)q * G.S << G.db) + t;
+    const uint32_t a = hs[e * G.nbq];
+    const uint32_t b = e + 1 < ((size_t)mix.B * G.S << G.db) ? hs[(e + 1) * G.nbq] : (uint32_t)*total;
+    ranges[i] = a < b ? make_uint2(a, b) : make_uint2(0u, 0u);
 }
 
 __global__ void bin_ranges_kernel(const uint32_t* __restrict__ hs, int B, BinGeom G,
@@ -783,6 +838,47 @@ void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hi
         return;
     }
     bin_hist_kernel<<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist, cull);
+}
+
+// Mixed batches: the geometry of the batch's largest query (max_n pairs, max_tiles tiles) for every query.
+static BinGeom mix_geom(int max_n, int max_tiles) {
+    Grid g{};
+    g.tiles = max_tiles;
+    return bin_geom(max_n, g);
+}
+
+bool mix_bin_fits(int B, int max_tiles) { return B <= 65535 && max_tiles <= kMaxTiles; }
+
+size_t mix_bin_hist_entries(int B, int max_n, int max_tiles) {
+    const BinGeom G = mix_geom(max_n, max_tiles);
+    return ((size_t)B * G.S << G.db) * (size_t)G.nbq;
+}
+
+void launch_mix_bin_hist(const MixBatch& m, int max_n, int max_tiles, const Records& r, uint32_t* hist,
+                         unsigned long long* cull, hipStream_t st) {
+    if (m.B <= 0) return;
+    const BinGeom G = mix_geom(max_n, max_tiles);
+    bin_hist_kernel<true><<<dim3(G.nbq, m.B), kThreads, 0, st>>>(r.rect, r.count, G, hist, cull, m);
+}
+
+void launch_mix_bin_scatter(const MixBatch& m, int max_n, int max_tiles, const Records& r,
+                            const uint32_t* hist_scanned, const uint64_t* n_dev, uint32_t* vals, hipStream_t st) {
+    if (m.B <= 0) return;
+    const BinGeom G = mix_geom(max_n, max_tiles);
+    if (G.S == 1 && G.db == 8)
+        bin_scatter_kernel<1, 8, true><<<dim3(G.nbq, m.B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned,
+                                                                               n_dev, vals, m);
+    else
+        bin_scatter_kernel<4, kWideDb, true><<<dim3(G.nbq, m.B), kThreads, 0, st>>>(r.rect, r.count, G,
+                                                                                     hist_scanned, n_dev, vals, m);
+}
+
+void launch_mix_bin_ranges(const MixBatch& m, int max_n, int max_tiles, const uint32_t* hist_scanned,
+                           const uint64_t* total, const uint64_t* n_dev, int64_t tile_cap, uint2* ranges,
+                           hipStream_t st) {
+    if (tile_cap <= 0 || m.B <= 0) return;
+    mix_bin_ranges_kernel<<<(unsigned)((tile_cap + 255) / 256), 256, 0, st>>>(
+        hist_scanned, m, mix_geom(max_n, max_tiles), total, n_dev, tile_cap, ranges);
 }
 
 void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* hist_scanned,

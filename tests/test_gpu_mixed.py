@@ -74,3 +74,23 @@ def test_mixed_batch_rejects_what_it_does_not_take(setup):
             ctx.render_mixed([sids[0], sids[1]], tx, flags=f)
     with pytest.raises(B.SwfError):
         ctx.render_mixed([sids[0], 9999], tx, flags=B.MLP_BF16)
+
+
+def test_mixed_batch_sort_path_for_large_grids(setup):
+    # a query grid beyond the binning's tile limit (68 x 68 tiles of 16): the batch takes key emission and the
+    # radix sort instead, with the same per-query results
+    import torch
+    from paper_2506_12787_amd import binding as B
+    ctx, sids = setup
+    H, W = 1088, 1088
+    g = synth.gaussians(3000, H, W, seed=270, scale_range=(2.0, 40.0))
+    big = ctx.upload_scene(g, H, W, mlp=synth.mlp_weights(seed=3270))
+    ids = [big, sids[2], sids[0], big, sids[3]]
+    tx = torch.from_numpy(synth.tx_positions(len(ids), seed=2270)).cuda()
+    for flags in (B.MLP_BF16, B.NO_DEFORM):
+        t = None if flags == B.NO_DEFORM else tx
+        mixed = ctx.render_mixed(ids, t, flags=flags)
+        for b, sid in enumerate(ids):
+            alone = ctx.render(sid, None if t is None else tx[b:b + 1].contiguous(), flags=flags, batch=1)[0]
+            assert torch.equal(mixed[b], alone), (flags, b)
+    ctx.release_scene(big)
