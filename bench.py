@@ -351,7 +351,7 @@ def serve_sweep(a):
     budget = int(a.hbm_budget_gb * 1e9)
     # per-scene batches (one graph per scene and bucket), then batches across scenes (graphs keyed by capacities)
     for mode in ("per_scene", "mixed"):
-        ctx.serve_start(max_batch=64, n_slots=2, flags=B.MLP_BF16, hbm_budget=budget, mixed=mode == "mixed")
+        ctx.serve_start(max_batch=64, n_slots=3, flags=B.MLP_BF16, hbm_budget=budget, mixed=mode == "mixed")
         serve_run(ctx, plan, shapes)  # warm-up: one pass of the plan captures the graphs its batches need
         warm = ctx.serve_counters()
         sat, lat, st = serve_run(ctx, plan, shapes)
@@ -1013,7 +1013,8 @@ def main():
         if "fp32_batched" in rec:
             rec["fp32_batched_over_plain"] = rec["fp32_batched"]["value"] / plain
         # serving loop on the same scene: captured graphs, continuous batching
-        ctx.serve_start(max_batch=Bq, n_slots=2, flags=flags)
+        # batches across scenes (here all of one scene): a batch renders its own queries only, no padding
+        ctx.serve_start(max_batch=Bq, n_slots=3, flags=flags, mixed=True)
         R = a.serve_requests
         stx = synth.tx_positions(R, seed=2203)
         plan = [(sid, stx[i]) for i in range(R)]
@@ -1028,7 +1029,8 @@ def main():
             "saturation_spectra_per_s": sat, "saturation_p50_us": pct(lat_s, 50), "saturation_p99_us": pct(lat_s, 99),
             "poisson_rate_per_s": rate, "poisson_throughput": thr_p, "poisson_p50_us": pct(lat_p, 50),
             "poisson_p99_us": pct(lat_p, 99), "poisson_mean_batch": float(np.mean([s["batch"] for s in st_p])),
-            "requests_per_point": R, "slots": 2, "max_batch": Bq, "graphs": True, "fallbacks": cnt["fallbacks"],
+            "requests_per_point": R, "slots": 3, "max_batch": Bq, "graphs": True, "fallbacks": cnt["fallbacks"],
+            "mode": "mixed" if cnt["mixed_launches"] == cnt["launches"] else "per_scene",
             "note": "latency from scheduled arrival to the result in the caller's host buffer"}
         rec["latency_us"]["serving_p50"] = pct(lat_p, 50)
         rec["latency_us"]["serving_p99"] = pct(lat_p, 99)

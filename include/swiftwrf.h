@@ -494,12 +494,13 @@ swf_status swf_exclusive_scan_noalloc(swf_ctx *ctx, const uint32_t *counts, uint
  * hold (the paper model, other MLP shapes, SWF_TILE8) are served per scene. */
 typedef struct {
     int32_t max_batch;    /* largest batch per launch (default 64, <= 1024)    */
-    int32_t n_slots;      /* execution slots in flight (default 2, <= 16)      */
+    int32_t n_slots;      /* execution slots in flight (default 3, <= 16)      */
     int32_t flags;        /* render flags: SWF_MLP_BF16 (default), ...          */
     float key_factor;     /* key capacity headroom (default 1.5)               */
     uint64_t hbm_budget;  /* workspace bytes over all slots, 0 = unlimited     */
     int32_t use_graphs;   /* 1: replay captured graphs; 0: direct launches     */
-    int32_t mixed;        /* 1: batch requests of different scenes together    */
+    int32_t mixed;        /* 1: batch requests of different scenes together
+                             (the default when cfg is NULL)                  */
     int32_t reserved[4];
 } swf_serve_config;
 

@@ -583,8 +583,8 @@ class Context:
                                                        _stream()))
 
     # ---- serving ------------------------------------------------------------------
-    def serve_start(self, max_batch=64, n_slots=2, flags=MLP_BF16, key_factor=1.5, hbm_budget=0, use_graphs=True,
-                    mixed=False):
+    def serve_start(self, max_batch=64, n_slots=3, flags=MLP_BF16, key_factor=1.5, hbm_budget=0, use_graphs=True,
+                    mixed=True):
         cfg = _ServeCfg(max_batch=max_batch, n_slots=n_slots, flags=flags, key_factor=key_factor,
                         hbm_budget=hbm_budget, use_graphs=1 if use_graphs else 0, mixed=1 if mixed else 0)
         self._check(self._L.swf_serve_start(self._h, ctypes.byref(cfg)))

@@ -18,11 +18,17 @@
 // four steps per octave). Scenes a mixed batch cannot hold (another MLP shape,
 // the paper model) are served per scene.
 //
+// A graph is captured right after the eager render of the first batch that
+// needs it (that render is the batch's result). Finished slots go to a
+// delivery thread, which copies the results into the callers' buffers (after a
+// key-capacity overflow, seen in the status word, it first re-renders the
+// batch with exact sizing) and frees the slot; the scheduler keeps admitting
+// into the other slots meanwhile.
+//
 // Admission is bounded by a device-memory budget over all slot workspaces (a
 // batch that does not fit is shrunk, idle workspaces are released, or the
-// requests wait). A key-capacity overflow is detected from the status word and
-// the batch is re-rendered with exact sizing. Latency is measured from the
-// request's scheduled arrival time.
+// requests wait). Latency is measured from the request's scheduled arrival
+// time.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -76,7 +82,8 @@ struct Slot {
     size_t out_host_cap = 0;
     uint32_t* status_host = nullptr;
     hipEvent_t done = nullptr;
-    bool busy = false;
+    std::atomic<int> phase{0};  // 0 free, 1 rendering, 2 results being delivered
+    bool busy() const { return phase.load() != 0; }
     int scene = -1, bucket = 0;
     std::vector<Request*> reqs;
     std::map<std::pair<int, int>, GraphEntry> graphs;
@@ -103,6 +110,13 @@ struct ServeState {
     Workspace cal;                           // mixed mode: calibration renders, released after each
     std::atomic<uint64_t> launched{0}, completed{0}, fallbacks{0}, graph_builds{0}, shrinks{0};
     std::atomic<uint64_t> mixed_launches{0}, mixed_scenes{0};
+    // delivery: finished slots whose results go to the callers' buffers (and, after a key overflow, are
+    // re-rendered first) on a thread of their own, so that the scheduler keeps admitting meanwhile
+    std::thread deliverer;
+    std::mutex dmu;
+    std::condition_variable dcv;
+    std::deque<Slot*> finished;
+    bool dstop = false;
 };
 
 namespace {
@@ -202,14 +216,16 @@ static swf_status launch_batch(Ctx* c, ServeState* S, Slot* sl, int scene, std::
         auto key = std::make_pair(scene, bucket);
         GraphEntry& ge = sl->graphs[key];
         const uint64_t gen = sl->ws.generation() + sl->tx_dev.gen + sl->out_dev.gen;
+        bool rendered = false;
         if (!ge.exec || ge.gen != gen || ge.key_cap != key_cap) {
             if (ge.exec) hipGraphExecDestroy(ge.exec);
             ge.exec = nullptr;
-            // eager run sizes every buffer, then capture the same launches
+            // this batch renders eagerly, which sizes every buffer; the capture right after it records the same
+            // launches for the next batches (it executes nothing, so it needs no wait for the eager work)
             if ((s = c->render(sl->ws, scene, (const float*)sl->tx_dev.ptr, bucket, flags, (float*)sl->out_dev.ptr,
                                nullptr, st, key_cap)))
                 return s;
-            if ((s = c->hip(hipStreamSynchronize(st), "serve sync"))) return s;
+            rendered = true;
             hipGraph_t graph = nullptr;
             if ((s = c->hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture"))) return s;
             swf_status rs = c->render(sl->ws, scene, (const float*)sl->tx_dev.ptr, bucket, flags,
@@ -224,7 +240,7 @@ static swf_status launch_batch(Ctx* c, ServeState* S, Slot* sl, int scene, std::
             ge.key_cap = key_cap;
             ++S->graph_builds;
         }
-        if ((s = c->hip(hipGraphLaunch(ge.exec, st), "graph launch"))) return s;
+        if (!rendered && (s = c->hip(hipGraphLaunch(ge.exec, st), "graph launch"))) return s;
     } else {
         if ((s = c->render(sl->ws, scene, (const float*)sl->tx_dev.ptr, bucket, flags, (float*)sl->out_dev.ptr,
                            nullptr, st, key_cap)))
@@ -246,7 +262,7 @@ static swf_status launch_batch(Ctx* c, ServeState* S, Slot* sl, int scene, std::
         r->slot = sl->index;
         r->state = 1;
     }
-    sl->busy = true;
+    sl->phase = 1;
     sl->mixed = false;
     sl->scene = scene;
     sl->bucket = bucket;
@@ -321,7 +337,7 @@ static void finish_slot(Ctx* c, ServeState* S, Slot* sl) {
         ++S->completed;
     }
     sl->reqs.clear();
-    sl->busy = false;
+    sl->phase = 0;
     S->cv.notify_all();
 }
 
@@ -373,12 +389,14 @@ static swf_status launch_mixed(Ctx* c, ServeState* S, Slot* sl, std::vector<Requ
     if (S->cfg.use_graphs) {
         GraphEntry& ge = sl->mgraphs[mix_key(flags, k)];
         auto gen = [&] { return sl->ws.generation() + sl->tx_dev.gen + sl->out_dev.gen; };
+        bool rendered = false;
         if (!ge.exec || ge.gen != gen()) {
             if (ge.exec) hipGraphExecDestroy(ge.exec);
             ge.exec = nullptr;
-            // an eager run (tables copied) sizes every buffer; the capture records the launches alone
+            // this batch renders eagerly (tables copied), which sizes every buffer; the capture right after it
+            // records the launches alone, for the next batches
             if ((s = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, &k))) return s;
-            if ((s = c->hip(hipStreamSynchronize(st), "serve sync"))) return s;
+            rendered = true;
             hipGraph_t graph = nullptr;
             if ((s = c->hip(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture"))) return s;
             swf_status rs = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, &k, false);
@@ -392,10 +410,13 @@ static swf_status launch_mixed(Ctx* c, ServeState* S, Slot* sl, std::vector<Requ
             ge.key_cap = k.key_cap;
             ++S->graph_builds;
         }
-        if ((s = c->hip(hipMemcpyAsync(sl->ws.mix.ptr, sl->ws.mix_host, p.table_bytes, hipMemcpyHostToDevice, st),
-                        "mix tables H2D")))
-            return s;
-        if ((s = c->hip(hipGraphLaunch(ge.exec, st), "graph launch"))) return s;
+        if (!rendered) {
+            if ((s = c->hip(hipMemcpyAsync(sl->ws.mix.ptr, sl->ws.mix_host, p.table_bytes, hipMemcpyHostToDevice,
+                                           st),
+                            "mix tables H2D")))
+                return s;
+            if ((s = c->hip(hipGraphLaunch(ge.exec, st), "graph launch"))) return s;
+        }
     } else {
         if ((s = c->enqueue_mixed(sl->ws, p, tx, flags, out, st, &k))) return s;
     }
@@ -414,7 +435,7 @@ static swf_status launch_mixed(Ctx* c, ServeState* S, Slot* sl, std::vector<Requ
         r->slot = sl->index;
         r->state = 1;
     }
-    sl->busy = true;
+    sl->phase = 1;
     sl->mixed = true;
     sl->mix_flags = flags;
     sl->scene = reqs[0]->scene;
@@ -492,6 +513,7 @@ static int admit_mixed(Ctx* c, ServeState* S, Slot* sl) {
         k.tile_cap = round_cap(tiles, 256);
         k.bin_n = (int)round_cap(k.bin_n, 1024);
         k.key_cap = (uint64_t)round_cap((int64_t)std::ceil(keys * S->cfg.key_factor) + 4096, 1 << 16);
+        k.outs = round_cap(k.outs, 1 << 16);  // the output buffer (its address is in the graphs) grows rarely
         // capacities only grow per slot and batch size, so that after the largest batches one graph per size
         // serves them all (the binning path's cost does not grow with them: its grids follow the largest
         // query and the batch's own totals, read on the device)
@@ -503,6 +525,7 @@ static int admit_mixed(Ctx* c, ServeState* S, Slot* sl) {
             k.key_cap = std::max(k.key_cap, h.key_cap);
             k.bin_n = std::max(k.bin_n, h.bin_n);
             k.bin_tiles = std::max(k.bin_tiles, h.bin_tiles);
+            k.outs = std::max(k.outs, h.outs);
         }
         return k;
     };
@@ -516,7 +539,7 @@ static int admit_mixed(Ctx* c, ServeState* S, Slot* sl) {
         };
         if (!fits(count)) {
             for (Slot* o : S->slots)
-                if (!o->busy && o != sl && slot_bytes(o)) {
+                if (!o->busy() && o != sl && slot_bytes(o)) {
                     drop_graphs(o);
                     o->ws.release();
                     o->ws.init(c);
@@ -533,7 +556,7 @@ static int admit_mixed(Ctx* c, ServeState* S, Slot* sl) {
             }
             if (!fits(count)) {
                 bool others_busy = false;
-                for (Slot* o : S->slots) others_busy = others_busy || (o != sl && o->busy);
+                for (Slot* o : S->slots) others_busy = others_busy || (o != sl && o->busy());
                 if (others_busy) {
                     std::lock_guard<std::mutex> lk2(S->mu);
                     for (auto it = batch.rbegin(); it != batch.rend(); ++it) S->waiting.push_front(*it);
@@ -573,19 +596,24 @@ static void scheduler(Ctx* c) {
     for (;;) {
         bool any_busy = false;
         for (Slot* sl : S->slots) {
-            if (!sl->busy) continue;
-            if (hipEventQuery(sl->done) == hipSuccess)
-                finish_slot(c, S, sl);
-            else
-                any_busy = true;
+            const int ph = sl->phase.load();
+            if (ph == 1 && hipEventQuery(sl->done) == hipSuccess) {
+                sl->phase = 2;
+                {
+                    std::lock_guard<std::mutex> lk(S->dmu);
+                    S->finished.push_back(sl);
+                }
+                S->dcv.notify_one();
+            }
+            any_busy = any_busy || ph != 0;
         }
         // admission into free slots
         for (Slot* sl : S->slots) {
-            if (sl->busy) continue;
+            if (sl->busy()) continue;
             if (S->cfg.mixed) {
                 const int r = admit_mixed(c, S, sl);
                 if (r == 1) {
-                    any_busy = any_busy || sl->busy;
+                    any_busy = any_busy || sl->busy();
                     continue;
                 }
                 if (r != 3) break;
@@ -638,7 +666,7 @@ static void scheduler(Ctx* c) {
                 if (!fits(bucket)) {
                     // release idle workspaces first, then shrink the batch
                     for (Slot* o : S->slots)
-                        if (!o->busy && o != sl && slot_bytes(o)) {
+                        if (!o->busy() && o != sl && slot_bytes(o)) {
                             drop_graphs(o);
                             o->ws.release();
                             o->ws.init(c);
@@ -655,7 +683,7 @@ static void scheduler(Ctx* c) {
                     }
                     if (!fits(bucket)) {
                         bool others_busy = false;
-                        for (Slot* o : S->slots) others_busy = others_busy || (o != sl && o->busy);
+                        for (Slot* o : S->slots) others_busy = others_busy || (o != sl && o->busy());
                         if (others_busy) {
                             // does not fit now: requeue at the front, wait for a slot to finish
                             std::lock_guard<std::mutex> lk2(S->mu);
@@ -688,7 +716,7 @@ static void scheduler(Ctx* c) {
         std::unique_lock<std::mutex> lk(S->mu);
         if (S->stop) {
             bool idle = true;
-            for (Slot* sl : S->slots) idle = idle && !sl->busy;
+            for (Slot* sl : S->slots) idle = idle && !sl->busy();
             if (idle) break;
         }
         if (any_busy) {
@@ -700,6 +728,23 @@ static void scheduler(Ctx* c) {
     }
 }
 
+static void deliverer(Ctx* c) {
+    ServeState* S = c->serve;
+    t_no_timing = true;
+    hipSetDevice(c->device);
+    for (;;) {
+        Slot* sl;
+        {
+            std::unique_lock<std::mutex> lk(S->dmu);
+            S->dcv.wait(lk, [&] { return !S->finished.empty() || S->dstop; });
+            if (S->finished.empty()) return;
+            sl = S->finished.front();
+            S->finished.pop_front();
+        }
+        finish_slot(c, S, sl);
+    }
+}
+
 void serve_shutdown(Ctx* c) {
     ServeState* S = c->serve;
     if (!S) return;
@@ -708,7 +753,14 @@ void serve_shutdown(Ctx* c) {
         S->stop = true;
         S->cv.notify_all();
     }
+    // the scheduler ends once every slot is free, which the deliverer's last results make it
     if (S->thr.joinable()) S->thr.join();
+    {
+        std::lock_guard<std::mutex> lk(S->dmu);
+        S->dstop = true;
+    }
+    S->dcv.notify_all();
+    if (S->deliverer.joinable()) S->deliverer.join();
     for (Slot* sl : S->slots) {
         drop_graphs(sl);
         sl->ws.release();
@@ -743,7 +795,8 @@ swf_status swf_serve_start(swf_ctx* h, const swf_serve_config* cfg) {
     hipSetDevice(c->device);
     ServeState* S = new ServeState();
     S->cfg.max_batch = 64;
-    S->cfg.n_slots = 2;
+    S->cfg.n_slots = 3;
+    S->cfg.mixed = 1;
     S->cfg.flags = SWF_MLP_BF16;
     S->cfg.key_factor = 1.5f;
     S->cfg.hbm_budget = 0;
@@ -776,6 +829,7 @@ swf_status swf_serve_start(swf_ctx* h, const swf_serve_config* cfg) {
         }
     }
     c->serve = S;
+    S->deliverer = std::thread(deliverer, c);
     S->thr = std::thread(scheduler, c);
     return SWF_OK;
 }

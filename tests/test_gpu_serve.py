@@ -51,7 +51,7 @@ def _serve_all(c, sids, reqs, **cfg):
 @pytest.mark.parametrize("graphs", [True, False])
 def test_mixed_stream_equals_alone(setup, graphs):
     c, sids, reqs, alone = setup
-    outs, stats, cnt = _serve_all(c, sids, reqs, max_batch=8, n_slots=2, use_graphs=graphs)
+    outs, stats, cnt = _serve_all(c, sids, reqs, max_batch=8, n_slots=2, use_graphs=graphs, mixed=False)
     for o, a in zip(outs, alone):
         np.testing.assert_array_equal(o, a)
     assert cnt["completed"] == len(reqs)
@@ -127,7 +127,7 @@ def test_memory_budget_shrinks_batches(setup):
     c, sids, reqs, alone = setup
     # a 16-query batch of the largest scene needs ~30 MB: 24 MB forces shrinking
     budget = 24 << 20
-    outs, stats, cnt = _serve_all(c, sids, reqs, max_batch=16, n_slots=2, hbm_budget=budget)
+    outs, stats, cnt = _serve_all(c, sids, reqs, max_batch=16, n_slots=2, hbm_budget=budget, mixed=False)
     for o, a in zip(outs, alone):
         np.testing.assert_array_equal(o, a)
     assert cnt["budget_shrinks"] >= 1
@@ -137,7 +137,7 @@ def test_memory_budget_shrinks_batches(setup):
 
 def test_key_overflow_falls_back_to_exact_sizing(setup):
     c, sids, reqs, alone = setup
-    outs, stats, cnt = _serve_all(c, sids, reqs[:12], max_batch=4, n_slots=2, key_factor=0.05)
+    outs, stats, cnt = _serve_all(c, sids, reqs[:12], max_batch=4, n_slots=2, key_factor=0.05, mixed=False)
     for o, a in zip(outs, alone[:12]):
         np.testing.assert_array_equal(o, a)
     assert cnt["fallbacks"] >= 1 and any(s["fallback"] for s in stats)
