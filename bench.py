@@ -72,6 +72,11 @@ def parse():
                    help="summarise rocprofv3 counter CSVs (FETCH_SIZE / WRITE_SIZE runs of a --copy-probe-mib run) "
                         "into HBM bytes per launch of the MLP kernel, then exit")
     p.add_argument("--copy-mib", type=int, default=1024, help="copy size used by the counted run (for --pmc-summary)")
+    p.add_argument("--pmc-table", nargs="+", metavar="DIR",
+                   help="print mean counter values per dispatch of the kernels named by --kernels from these "
+                        "rocprofv3 counter directories")
+    p.add_argument("--kernels", default="mlp_bf16,bin_hist,bin_scatter,blend_forward",
+                   help="comma-separated name fragments for --pmc-table")
     p.add_argument("--workload", choices=("headline", "large", "train", "beamscan", "rssi", "wrap", "protocol", "paper"), default="headline",
                    help="large: N=500k Gaussians (log-scales in [log 0.5, log 20] px), 360x1440 spectra, batch 256; "
                         "BF16 and FP32 MLP; prints its own JSON line (at most 5 timed steps, 1 warm-up). "
@@ -151,6 +156,32 @@ def pmc_summary(a):
     print(f"workload: {workload_key(a)}")
     print(f"sources: {mlp_sources_hash()}")
     print(f"traffic_bytes_per_launch: {traffic:.0f}")
+
+
+def pmc_table(a):
+    """Mean counter value per dispatch for every kernel whose name contains one of --kernels, from rocprofv3
+    counter-collection CSVs; FETCH_SIZE / WRITE_SIZE also as bytes, scaled by the copy kernel of known size when
+    the same runs hold it."""
+    c = read_counters(a.pmc_table)
+    mean = lambda v: sum(v) / len(v)
+    names = sorted({k for k, _ in c})
+    cp = [n for n in names if "elementwise" in n]
+    scale = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        vals = [(n, mean(c[(n, ctr)])) for n in cp if (n, ctr) in c]
+        if vals:
+            scale[ctr] = a.copy_mib * 2 ** 20 / (max(v for _, v in vals) * 1024.0)
+    pats = [x for x in a.kernels.split(",") if x]
+    print("| Kernel | Counter | Mean per dispatch | Dispatches | Bytes per dispatch (copy-scaled) |")
+    print("|---|---|---|---|---|")
+    for n in names:
+        if not any(pt in n for pt in pats):
+            continue
+        for (kn, ctr), v in sorted(c.items()):
+            if kn != n:
+                continue
+            b = f"{mean(v) * 1024.0 * scale[ctr] / 1e6:.1f} MB" if ctr in scale else ""
+            print(f"| {n[:70]} | {ctr} | {mean(v):.6g} | {len(v)} | {b} |")
 
 
 def measured_traffic(a):
@@ -850,6 +881,9 @@ def main():
         sys.exit(2)
     if a.pmc_summary:
         pmc_summary(a)
+        return
+    if a.pmc_table:
+        pmc_table(a)
         return
     if a.serve_sweep:
         serve_sweep(a)
