@@ -129,13 +129,15 @@ void launch_mix_clear_tail(const MixBatch& m, int64_t pair_cap, const Records& r
 // tiles) for every query; ranges over its global tiles.
 bool mix_bin_fits(int B, int max_tiles);
 size_t mix_bin_hist_entries(int B, int max_n, int max_tiles);
-void launch_mix_bin_hist(const MixBatch& m, int max_n, int max_tiles, const Records& r, uint32_t* hist,
+size_t mix_bin_scan_entries(int B, int max_n, int max_tiles);
+void launch_mix_bin_hist(const MixBatch& m, int max_n, int max_tiles, const Records& r, uint32_t* bins,
                          unsigned long long* cull, hipStream_t st);
-void launch_mix_bin_scatter(const MixBatch& m, int max_n, int max_tiles, const Records& r,
-                            const uint32_t* hist_scanned, const uint64_t* n_dev, uint32_t* vals, hipStream_t st);
-void launch_mix_bin_ranges(const MixBatch& m, int max_n, int max_tiles, const uint32_t* hist_scanned,
-                           const uint64_t* total, const uint64_t* n_dev, int64_t tile_cap, uint2* ranges,
-                           hipStream_t st);
+void launch_mix_bin_offsets(const MixBatch& m, int max_n, int max_tiles, uint32_t* bins, void* scan_scratch,
+                            uint64_t* total, hipStream_t st);
+void launch_mix_bin_scatter(const MixBatch& m, int max_n, int max_tiles, const Records& r, const uint32_t* bins,
+                            const uint64_t* n_dev, uint32_t* vals, hipStream_t st);
+void launch_mix_bin_ranges(const MixBatch& m, int max_n, int max_tiles, const uint32_t* bins, const uint64_t* total,
+                           const uint64_t* n_dev, int64_t tile_cap, uint2* ranges, hipStream_t st);
 void launch_mix_emit_keys(const MixBatch& m, const Records& r, const uint32_t* offsets, int64_t pair_cap,
                           uint64_t capacity, uint32_t* keys, uint32_t* vals, uint32_t* status,
                           unsigned long long* cull, hipStream_t st);
@@ -197,18 +199,22 @@ void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gt
 void launch_clear_u32(uint32_t* p, int n, hipStream_t st);
 // n_eff = total if total <= cap else 0 (then bit 0 of *status is set)
 void launch_effective_count(const uint64_t* total, uint64_t cap, uint64_t* n_eff, uint32_t* status, hipStream_t st);
-// Binning path: per-block histograms of each tile segment of a query, then
-// (after an exclusive scan of the histogram, in place) the stable placement of
-// pair indices into per-tile lists and the tile ranges.
+// Binning path: per-block histograms of each tile segment of a query, their
+// column prefixes and the scanned tile totals (`bins` holds both), then the
+// stable placement of pair indices into per-tile lists and the tile ranges.
 bool bin_fits(int B, int N, const Grid& g);  // the segment grid fits one launch
-size_t bin_hist_entries(int B, int N, const Grid& g);
+size_t bin_hist_entries(int B, int N, const Grid& g);  // uint32 entries of `bins`
+size_t bin_scan_entries(int B, int N, const Grid& g);  // entries the tile-total scan runs over
 // cull (may be null): two device counters that receive the number of culled
 // pairs, non-finite / degenerate and off the grid (also launch_emit_keys)
-void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hist, unsigned long long* cull,
+void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* bins, unsigned long long* cull,
                      hipStream_t st);
-void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* hist_scanned,
+// column prefixes in place, tile starts, and the number of list entries in *total
+void launch_bin_offsets(int B, int N, const Grid& g, uint32_t* bins, void* scan_scratch, uint64_t* total,
+                        hipStream_t st);
+void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* bins,
                         const uint64_t* n_dev, uint32_t* vals, hipStream_t st);
-void launch_bin_ranges(const uint32_t* hist_scanned, int B, int N, const Grid& g, const uint64_t* total,
+void launch_bin_ranges(const uint32_t* bins, int B, int N, const Grid& g, const uint64_t* total,
                        const uint64_t* n_dev, uint2* ranges, hipStream_t st);
 
 // backward.hip

@@ -657,9 +657,9 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     const bool full = (flags & SWF_FULL_SORT) != 0;
     const int64_t n_gt = (int64_t)B * g.tiles;
     if ((s = w.ranges.reserve(this, (size_t)n_gt * sizeof(uint2), st))) return s;
-    // binning unless the full 64-bit sort is asked for (or the segment grid would exceed the launch limit); a
-    // wrapped rectangle (periodic azimuth) is two column runs per row, which only the key emission enumerates
-    if (!full && !g.wrap && bin_fits(B, d.n, g)) {
+    // binning unless the full 64-bit sort is asked for (or the segment grid would exceed the launch limit, or a
+    // periodic azimuth spans more than one segment: the multi-segment placement enumerates unwrapped rectangles)
+    if (!full && bin_fits(B, d.n, g)) {
         const bool spec = key_cap == 0 && spec_cap > 0 && spec_used;
         s = lists_binned(w, d, B, g, st, spec ? spec_cap : key_cap, spec);
         if (spec) *spec_used = true;
@@ -715,11 +715,11 @@ swf_status Ctx::lists_binned(Workspace& w, const DevScene& d, int B, const Grid&
     swf_status s;
     const int64_t nh = (int64_t)bin_hist_entries(B, d.n, g);
     if ((s = w.bins.reserve(this, (size_t)nh * sizeof(uint32_t) + 16, st))) return s;
-    if ((s = w.scan.reserve(this, scan_scratch_bytes(nh) + 64, st))) return s;
+    if ((s = w.scan.reserve(this, scan_scratch_bytes((int64_t)bin_scan_entries(B, d.n, g)) + 64, st))) return s;
     uint32_t* bins = (uint32_t*)w.bins.ptr;
     stage_begin(SWF_STAGE_SCAN, st);
     launch_bin_hist(w.rec, B, d.n, g, bins, w.cull_dev, st);
-    launch_exclusive_scan(bins, bins, w.total_dev, nh, w.scan.ptr, st);
+    launch_bin_offsets(B, d.n, g, bins, w.scan.ptr, w.total_dev, st);
     stage_end(st);
     uint64_t nk;
     const uint64_t* n_dev;
@@ -992,12 +992,13 @@ swf_status Ctx::enqueue_mixed(Workspace& w, const MixPlan& p, const float* tx, i
     if (binned) {
         // tile histograms per block of pairs of each query, their scan, stable placement, ranges
         const int64_t nh = (int64_t)mix_bin_hist_entries(k.B_cap, k.bin_n, k.bin_tiles);
+        const int64_t ns = (int64_t)mix_bin_scan_entries(k.B_cap, k.bin_n, k.bin_tiles);
         if ((s = w.bins.reserve(this, (size_t)nh * sizeof(uint32_t) + 16, st))) return s;
-        if ((s = w.scan.reserve(this, scan_scratch_bytes(nh) + 64, st))) return s;
+        if ((s = w.scan.reserve(this, scan_scratch_bytes(ns) + 64, st))) return s;
         uint32_t* bins = (uint32_t*)w.bins.ptr;
         stage_begin(SWF_STAGE_SCAN, st);
         launch_mix_bin_hist(mb, k.bin_n, k.bin_tiles, w.rec, bins, w.cull_dev, st);
-        launch_exclusive_scan(bins, bins, w.total_dev, nh, w.scan.ptr, st);
+        launch_mix_bin_offsets(mb, k.bin_n, k.bin_tiles, bins, w.scan.ptr, w.total_dev, st);
         stage_end(st);
         if ((s = key_count(w, st, k.key_cap, nk, n_dev))) return s;
         if ((s = w.vals.reserve(this, nk * 4 + 16, st))) return s;

@@ -309,19 +309,28 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(const K* __rest
 // ---- binning: per-query stable counting sort by tile -----------------------
 // Pairs are stored in (query, depth) order and a pair covers a tile at most
 // once, so the list of a tile is the pairs covering it in pair order. A query's
-// tiles are split into S segments of 2^db tiles (one db-bit digit each: db = 8
-// with at most 256 tiles per query, else 9); every query is
-// binned by a stable counting pass per segment, which gives exactly the order
-// of the full (tile, depth) sort without materialising keys in memory.
+// tiles are split into S segments of 2^db tiles (db = 8 with at most 256 tiles
+// per query, one segment; else 9); every query is binned by a stable counting
+// pass per segment, which gives exactly the order of the full (tile, depth)
+// sort without materialising keys in memory.
 //   bin_hist:    block (j, q) histograms the tiles covered by pairs
-//                [j * pb, (j + 1) * pb) of query q, for every segment s;
-//                hist[((q * S + s) * 2^db + tile - 2^db s) * nbq + j]
-//   scan:        one exclusive scan over that (query, tile, block) order gives
-//                every block's first output position per tile
-//   bin_scatter: the same block, segment by segment, computes its keys in pair
-//                order and writes each pair index to its position, ranked
-//                stably with wave64 ballots over the db digit bits
-//   bin_ranges:  tile (q, t) spans [hist(q, t, 0), hist(q, t + 1, 0))
+//                [j * pb, (j + 1) * pb) of query q, for every segment s, into
+//                its own row: hist[((q * S + s) * nbq + j) * 2^db + tile - 2^db s]
+//   bin_colscan: per column (q, s, tile) the exclusive prefix over the blocks,
+//                in place, and the column total; an exclusive scan of the totals
+//                in (query, tile) order gives every tile's first list position
+//                (`starts`, stored after the histogram) and the entry count. A
+//                block's first position in a tile's list is the tile's start
+//                plus the block's column prefix.
+//   bin_place:   (one segment) the block places its pairs batch by batch: each
+//                key sets its pair's bit in a per-tile mask of the batch, and
+//                its rank in the tile's list is the number of the batch's pairs
+//                below its own in that mask
+//   bin_scatter: (several segments) the block, segment by segment, ranks its
+//                keys stably with wave64 ballots over the db digit bits
+//   bin_ranges:  tile (q, t) spans [start(q, t), start(q, t + 1))
+// A periodic azimuth (wrapped rectangles, tx1 < tx0: columns tx0 .. TW - 1,
+// then 0 .. tx1) is binned when a query has one segment.
 struct BinGeom {
     int N, TW, tiles, db, S, pb, nbq;  // pairs per query, tile grid, digit bits, segments, pairs/block, blocks/query
 };
@@ -341,17 +350,17 @@ BinGeom bin_geom(int N, const Grid& g) {
     return b;
 }
 
-// Keys of one pair inside segment [t0, t0 + seg): visits them in row-major
-// tile order (the pair's key order) and calls f(local index, tile - t0).
+// Every tile of a pair's rectangle (rows top to bottom, columns from tx0, a
+// wrapped rectangle continuing at column 0): calls f(tile).
 template <typename F>
-__device__ __forceinline__ void for_seg_tiles(uint2 r, int TW, int t0, int seg, F&& f) {
+__device__ __forceinline__ void for_rect_tiles(uint2 r, int TW, F&& f) {
     const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
-    if (ty1 * TW + tx1 < t0 || ty0 * TW + tx0 >= t0 + seg) return;
-    uint32_t m = 0;
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        const int a = max(ty * TW + tx0, t0), b = min(ty * TW + tx1, t0 + seg - 1);
-        for (int t = a; t <= b; ++t) f(m++, (uint32_t)(t - t0));
-    }
+    const int w = tx1 >= tx0 ? tx1 - tx0 + 1 : TW - tx0 + tx1 + 1;
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int k = 0; k < w; ++k) {
+            const int col = tx0 + k < TW ? tx0 + k : tx0 + k - TW;
+            f((uint32_t)(ty * TW + col));
+        }
 }
 
 __device__ __forceinline__ uint32_t seg_count(uint2 r, int TW, int t0, int seg) {
@@ -395,9 +404,9 @@ __device__ __forceinline__ BinQuery bin_query(const BinGeom& G, const MixBatch& 
     return b;
 }
 
-// Tile histogram of one block of pairs of one query, for every tile segment:
-// hist[((q * S + segment) * 256 + tile % 256) * nbq + block]. With one segment
-// the counts are kept per wave (less atomic contention).
+// Tile histogram of one block of pairs of one query, for every tile segment, in
+// the block's own row: hist[((q * S + segment) * nbq + block) * 2^db + tile % 2^db].
+// With one segment the counts are kept per wave (less atomic contention).
 template <bool kMix = false>
 __global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restrict__ rect,
                                                             const uint32_t* __restrict__ count, BinGeom G,
@@ -425,7 +434,7 @@ __global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restr
             og += r.y == kCullOffGrid;
             continue;
         }
-        for_seg_tiles(r, Q.TW, 0, Q.tiles, [&](uint32_t, uint32_t t) { atomicAdd(&hw[t], 1u); });
+        for_rect_tiles(r, Q.TW, [&](uint32_t t) { atomicAdd(&hw[t], 1u); });
     }
     if (nf) atomicAdd(&nculled[0], nf);
     if (og) atomicAdd(&nculled[1], og);
@@ -437,7 +446,160 @@ __global__ __launch_bounds__(kThreads) void bin_hist_kernel(const uint2* __restr
 #pragma unroll
             for (int k = 1; k < kWaves; ++k) v += h[k * kSegTiles + i];
         const int sg = i / kSegTiles, d = i - sg * kSegTiles;
-        hist[((size_t)(q * G.S + sg) * kSegTiles + d) * G.nbq + j] = v;
+        hist[(((size_t)(q * G.S + sg) * G.nbq + j) << G.db) + d] = v;
+    }
+}
+
+// Column (query-segment, tile) i of the histogram: the exclusive prefix over
+// its nbq blocks, in place, and the column total. Consecutive threads take
+// consecutive tiles, so every access is coalesced.
+__global__ __launch_bounds__(kThreads) void bin_colscan_kernel(uint32_t* __restrict__ hist, int64_t cols, int nbq,
+                                                               int db, uint32_t* __restrict__ totals) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= cols) return;
+    const int64_t qs = i >> db, d = i & ((1 << db) - 1);
+    uint32_t* col = hist + ((qs * nbq) << db) + d;
+    const size_t stride = (size_t)1 << db;
+    uint32_t run = 0;
+    int j = 0;
+    for (; j + 8 <= nbq; j += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = col[(size_t)(j + k) * stride];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            col[(size_t)(j + k) * stride] = run;
+            run += v[k];
+        }
+    }
+    for (; j < nbq; ++j) {
+        const uint32_t v = col[(size_t)j * stride];
+        col[(size_t)j * stride] = run;
+        run += v;
+    }
+    totals[i] = run;
+}
+
+// Placement for one segment (at most 256 tiles per query): one block of pairs
+// of one query, in batches of 256 pairs (one per thread). A batch's keys, in
+// pair order, are processed in chunks of kTile positions; every lane computes
+// the key at its position directly (the owning pair by binary search over the
+// batch's key offsets, the tile by enumerating the pair's rectangle row by row)
+// and sets the pair's bit in the tile's 256-bit mask. The key's rank in the
+// tile's list is then the tile's start for this block, plus the batch's earlier
+// pairs covering the tile (their keys all lie at earlier positions, so their
+// bits are set by then), plus the entries of the block's earlier batches.
+template <bool kMix = false>
+__global__ __launch_bounds__(kThreads) void bin_place_kernel(const uint2* __restrict__ rect,
+                                                             const uint32_t* __restrict__ count, BinGeom G,
+                                                             const uint32_t* __restrict__ hs,
+                                                             const uint32_t* __restrict__ starts,
+                                                             const uint64_t* __restrict__ n_dev,
+                                                             uint32_t* __restrict__ vals, MixBatch mix = MixBatch{}) {
+    constexpr int kSeg = 256;
+    constexpr int kBatch = kThreads;
+    constexpr int kWords = kBatch / 64;
+    static_assert(kSeg == kThreads, "one tile per thread in the per-tile steps");
+    // fixed-capacity run that overflowed: nothing is placed (block-uniform)
+    if (n_dev && *n_dev == 0) return;
+    __shared__ unsigned long long mask[kSeg][kWords];  // bit p: pair p of the batch covers the tile
+    __shared__ uint32_t pre[kSeg][kWords];             // pairs covering the tile in the words before
+    __shared__ uint32_t base[kSeg];
+    __shared__ uint32_t lds[kWaves + 1];
+    __shared__ uint32_t s_o[kBatch], s_w[kBatch];
+    __shared__ int s_ty0[kBatch], s_tx0[kBatch];
+    __shared__ float s_rw[kBatch];
+    const int j = blockIdx.x, q = blockIdx.y;
+    const int t = threadIdx.x;
+    const BinQuery Q = bin_query<kMix>(G, mix, q);
+    const int p_beg = j * G.pb, p_end = min(p_beg + G.pb, Q.N);
+    const size_t row0 = Q.row0;
+    const int TW = Q.TW;
+    base[t] = hs[(((size_t)q * G.nbq + j) << 8) + t] + starts[((size_t)q << 8) + t];
+#pragma unroll
+    for (int k = 0; k < kWords; ++k) mask[t][k] = 0ull;
+    uint32_t c_next = 0u;
+    uint2 r_next = make_uint2(0u, 0u);
+    if (p_beg + t < p_end) {
+        c_next = count[row0 + p_beg + t];
+        r_next = rect[row0 + p_beg + t];
+    }
+    for (int s0 = p_beg; s0 < p_end; s0 += kBatch) {
+        const uint32_t c = c_next;
+        const uint2 r = r_next;
+        const int pn = s0 + kBatch + t;
+        c_next = pn < p_end ? count[row0 + pn] : 0u;
+        if (pn < p_end) r_next = rect[row0 + pn];
+        uint32_t K;
+        const uint32_t o = block_exclusive_scan<uint32_t>(c, lds, &K);  // synchronises
+        if (K == 0) continue;
+        s_o[t] = o;
+        if (c) {
+            const int tx0 = r.x & 0xffff, tx1 = r.x >> 16;
+            const uint32_t w = (uint32_t)(tx1 >= tx0 ? tx1 - tx0 + 1 : TW - tx0 + tx1 + 1);
+            s_ty0[t] = (int)(r.y & 0xffff);
+            s_tx0[t] = tx0;
+            s_w[t] = w;
+            s_rw[t] = 1.0f / (float)w;
+        }
+        for (uint32_t c0 = 0; c0 < K; c0 += kTile) {
+            __syncthreads();  // the batch's pair table is complete; the previous chunk's ranks are read
+            uint32_t dig[kItems], own[kItems];
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const uint32_t gp = c0 + (uint32_t)(i * kThreads + t);
+                own[i] = kBatch;  // no key at this position
+                dig[i] = 0u;
+                if (gp < K) {
+                    // last pair whose first key is at or before gp (s_o is non-decreasing; a pair without keys
+                    // shares its offset with the next pair, so the last one is the owner)
+                    int lo = 0;
+#pragma unroll
+                    for (int step = kBatch / 2; step > 0; step >>= 1)
+                        if (s_o[lo + step] <= gp) lo += step;
+                    const uint32_t m = gp - s_o[lo], w = s_w[lo];
+                    // m < 256 keys, w <= 256 columns: the product is at most one below the quotient
+                    uint32_t qr = (uint32_t)((float)m * s_rw[lo]);
+                    uint32_t cc = m - qr * w;
+                    if (cc >= w) {
+                        ++qr;
+                        cc -= w;
+                    }
+                    const int col = s_tx0[lo] + (int)cc;
+                    const uint32_t d = (uint32_t)((s_ty0[lo] + (int)qr) * TW + (col < TW ? col : col - TW));
+                    dig[i] = d;
+                    own[i] = (uint32_t)lo;
+                    atomicOr(&mask[d][lo >> 6], 1ull << (lo & 63));
+                }
+            }
+            __syncthreads();
+            {
+                uint32_t run = 0;
+#pragma unroll
+                for (int k = 0; k < kWords; ++k) {
+                    pre[t][k] = run;
+                    run += (uint32_t)__popcll(mask[t][k]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                if (own[i] < (uint32_t)kBatch) {
+                    const uint32_t d = dig[i], lo = own[i];
+                    const uint32_t rank = pre[d][lo >> 6] +
+                                          (uint32_t)__popcll(mask[d][lo >> 6] & ((1ull << (lo & 63)) - 1ull));
+                    vals[base[d] + rank] = (uint32_t)(row0 + s0 + lo);
+                }
+            }
+        }
+        __syncthreads();  // every rank of the batch is read
+        uint32_t tot = 0;
+#pragma unroll
+        for (int k = 0; k < kWords; ++k) {
+            tot += (uint32_t)__popcll(mask[t][k]);
+            mask[t][k] = 0ull;
+        }
+        base[t] += tot;  // the next batch's scan synchronises before anything reads base or the masks
     }
 }
 
@@ -462,7 +624,7 @@ __device__ __forceinline__ uint2 digit_match(uint32_t d, bool ok) {
 }
 
 // Enumeration of the keys a pair has in a tile segment [t0, t0 + seg), in the
-// row-major order of for_seg_tiles: the first intersecting row of the rectangle
+// row-major order of for_rect_tiles: the first intersecting row of the rectangle
 // (possibly clipped by the segment start) gives keys 0 .. n0 - 1 at tiles
 // a0 + m; the later rows are whole (only the last can be clipped by the segment
 // end, which the key count already excludes) and hold key n0 + q * w + c at
@@ -515,6 +677,7 @@ template <int PPT, int DB, bool kMix = false>
 __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __restrict__ rect,
                                                                const uint32_t* __restrict__ count, BinGeom G,
                                                                const uint32_t* __restrict__ hs,
+                                                               const uint32_t* __restrict__ starts,
                                                                const uint64_t* __restrict__ n_dev,
                                                                uint32_t* __restrict__ vals,
                                                                MixBatch mix = MixBatch{}) {
@@ -540,7 +703,7 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
         const int t0 = sg * kSeg;
         __syncthreads();  // the previous segment is placed
         for (int d = threadIdx.x; d < kSeg; d += kThreads)
-            base[d] = hs[((size_t)(q * G.S + sg) * kSeg + d) * G.nbq + j];
+            base[d] = hs[(((size_t)(q * G.S + sg) * G.nbq + j) << DB) + d] + starts[((size_t)(q * G.S + sg) << DB) + d];
         // the next batch's (count, rect) are loaded while this one is placed
         uint32_t c_next[PPT];
         uint2 r_next[PPT];
@@ -642,9 +805,9 @@ __global__ __launch_bounds__(kThreads) void bin_scatter_kernel(const uint2* __re
     }
 }
 
-// Ranges of a mixed batch's global tiles: tile t of query q sits at histogram
-// entry (q, segment t >> db, t mod 2^db) of the batch geometry.
-__global__ void mix_bin_ranges_kernel(const uint32_t* __restrict__ hs, MixBatch mix, BinGeom G,
+// Ranges of a mixed batch's global tiles: tile t of query q starts at entry
+// (q, segment t >> db, t mod 2^db) of the scanned tile totals.
+__global__ void mix_bin_ranges_kernel(const uint32_t* __restrict__ starts, MixBatch mix, BinGeom G,
                                       const uint64_t* __restrict__ total, const uint64_t* __restrict__ n_dev,
                                       int64_t tile_cap, uint2* __restrict__ ranges) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -656,12 +819,12 @@ __global__ void mix_bin_ranges_kernel(const uint32_t* __restrict__ hs, MixBatch 
     const int q = mix_find(mix.queries, mix.B, (int)i, [](const MixQuery& x) { return x.tile_base; });
     const int64_t t = i - mix.queries[q].tile_base;
     const size_t e = ((size_t)q * G.S << G.db) + t;
-    const uint32_t a = hs[e * G.nbq];
-    const uint32_t b = e + 1 < ((size_t)mix.B * G.S << G.db) ? hs[(e + 1) * G.nbq] : (uint32_t)*total;
+    const uint32_t a = starts[e];
+    const uint32_t b = e + 1 < ((size_t)mix.B * G.S << G.db) ? starts[e + 1] : (uint32_t)*total;
     ranges[i] = a < b ? make_uint2(a, b) : make_uint2(0u, 0u);
 }
 
-__global__ void bin_ranges_kernel(const uint32_t* __restrict__ hs, int B, BinGeom G,
+__global__ void bin_ranges_kernel(const uint32_t* __restrict__ starts, int B, BinGeom G,
                                   const uint64_t* __restrict__ total, const uint64_t* __restrict__ n_dev,
                                   uint2* __restrict__ ranges) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -671,9 +834,9 @@ __global__ void bin_ranges_kernel(const uint32_t* __restrict__ hs, int B, BinGeo
         return;
     }
     const int64_t q = i / G.tiles, t = i - q * G.tiles;
-    const size_t e = ((size_t)q * G.S << G.db) + t;  // (q, segment t >> db, t mod 2^db)
-    const uint32_t a = hs[e * G.nbq];
-    const uint32_t b = e + 1 < ((size_t)B * G.S << G.db) ? hs[(e + 1) * G.nbq] : (uint32_t)*total;
+    const size_t e = ((size_t)q * G.S << G.db) + t;  // segments of a query are consecutive
+    const uint32_t a = starts[e];
+    const uint32_t b = e + 1 < ((size_t)B * G.S << G.db) ? starts[e + 1] : (uint32_t)*total;
     ranges[i] = a < b ? make_uint2(a, b) : make_uint2(0u, 0u);
 }
 
@@ -822,22 +985,90 @@ void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gt
         tile_ranges_kernel<false><<<blocks, 256, 0, st>>>(keys, n, ranges, n_dev);
 }
 
-bool bin_fits(int B, int N, const Grid& g) { return B <= 65535 && g.tiles <= kMaxTiles; }
+bool bin_fits(int B, int N, const Grid& g) {
+    // a periodic azimuth is binned with one segment
+    return B <= 65535 && g.tiles <= kMaxTiles && (!g.wrap || g.tiles <= 256);
+}
+
+// The bins buffer: the histogram (B * S * nbq rows of 2^db), then the scanned
+// tile totals (B * S * 2^db).
+static size_t hist_entries(int B, const BinGeom& G) { return ((size_t)B * G.S * G.nbq) << G.db; }
+static size_t start_entries(int B, const BinGeom& G) { return ((size_t)B * G.S) << G.db; }
 
 size_t bin_hist_entries(int B, int N, const Grid& g) {
     const BinGeom G = bin_geom(N, g);
-    return ((size_t)B * G.S << G.db) * (size_t)G.nbq;
+    return hist_entries(B, G) + start_entries(B, G);
 }
 
-void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* hist, unsigned long long* cull,
+size_t bin_scan_entries(int B, int N, const Grid& g) { return start_entries(B, bin_geom(N, g)); }
+
+static void hist_launch(const BinGeom& G, int B, const Records& r, uint32_t* bins, unsigned long long* cull,
+                        hipStream_t st, const MixBatch* m) {
+    if (m)
+        bin_hist_kernel<true><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, bins, cull, *m);
+    else
+        bin_hist_kernel<false><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, bins, cull);
+}
+
+static void offsets_launch(const BinGeom& G, int B, uint32_t* bins, void* scratch, uint64_t* total, hipStream_t st) {
+    const int64_t cols = (int64_t)start_entries(B, G);
+    uint32_t* starts = bins + hist_entries(B, G);
+    bin_colscan_kernel<<<(unsigned)((cols + kThreads - 1) / kThreads), kThreads, 0, st>>>(bins, cols, G.nbq, G.db,
+                                                                                          starts);
+    launch_exclusive_scan(starts, starts, total, cols, scratch, st);
+}
+
+static void place_launch(const BinGeom& G, int B, const Records& r, const uint32_t* bins, const uint64_t* n_dev,
+                         uint32_t* vals, hipStream_t st, const MixBatch* m) {
+    const uint32_t* starts = bins + hist_entries(B, G);
+    const dim3 grid(G.nbq, B);
+    if (G.S == 1 && G.db == 8) {
+        if (m)
+            bin_place_kernel<true><<<grid, kThreads, 0, st>>>(r.rect, r.count, G, bins, starts, n_dev, vals, *m);
+        else
+            bin_place_kernel<false><<<grid, kThreads, 0, st>>>(r.rect, r.count, G, bins, starts, n_dev, vals);
+    } else {
+        if (m)
+            bin_scatter_kernel<4, kWideDb, true><<<grid, kThreads, 0, st>>>(r.rect, r.count, G, bins, starts, n_dev,
+                                                                            vals, *m);
+        else
+            bin_scatter_kernel<4, kWideDb><<<grid, kThreads, 0, st>>>(r.rect, r.count, G, bins, starts, n_dev, vals);
+    }
+}
+
+void launch_bin_hist(const Records& r, int B, int N, const Grid& g, uint32_t* bins, unsigned long long* cull,
                      hipStream_t st) {
     if (B <= 0) return;
     const BinGeom G = bin_geom(N, g);
     if (N <= 0) {
-        launch_clear_u32(hist, (int)bin_hist_entries(B, N, g), st);
+        launch_clear_u32(bins, (int)hist_entries(B, G), st);
         return;
     }
-    bin_hist_kernel<<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist, cull);
+    hist_launch(G, B, r, bins, cull, st, nullptr);
+}
+
+void launch_bin_offsets(int B, int N, const Grid& g, uint32_t* bins, void* scratch, uint64_t* total,
+                        hipStream_t st) {
+    if (B <= 0) {
+        launch_clear_u32(reinterpret_cast<uint32_t*>(total), 2, st);
+        return;
+    }
+    offsets_launch(bin_geom(N, g), B, bins, scratch, total, st);
+}
+
+void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* bins, const uint64_t* n_dev,
+                        uint32_t* vals, hipStream_t st) {
+    if (B <= 0 || N <= 0) return;
+    place_launch(bin_geom(N, g), B, r, bins, n_dev, vals, st, nullptr);
+}
+
+void launch_bin_ranges(const uint32_t* bins, int B, int N, const Grid& g, const uint64_t* total,
+                       const uint64_t* n_dev, uint2* ranges, hipStream_t st) {
+    const int64_t m = (int64_t)B * g.tiles;
+    if (m <= 0) return;
+    const BinGeom G = bin_geom(N, g);
+    bin_ranges_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(bins + hist_entries(B, G), B, G, total, n_dev,
+                                                                    ranges);
 }
 
 // Mixed batches: the geometry of the batch's largest query (max_n pairs, max_tiles tiles) for every query.
@@ -851,53 +1082,35 @@ bool mix_bin_fits(int B, int max_tiles) { return B <= 65535 && max_tiles <= kMax
 
 size_t mix_bin_hist_entries(int B, int max_n, int max_tiles) {
     const BinGeom G = mix_geom(max_n, max_tiles);
-    return ((size_t)B * G.S << G.db) * (size_t)G.nbq;
+    return hist_entries(B, G) + start_entries(B, G);
 }
 
-void launch_mix_bin_hist(const MixBatch& m, int max_n, int max_tiles, const Records& r, uint32_t* hist,
+size_t mix_bin_scan_entries(int B, int max_n, int max_tiles) { return start_entries(B, mix_geom(max_n, max_tiles)); }
+
+void launch_mix_bin_hist(const MixBatch& m, int max_n, int max_tiles, const Records& r, uint32_t* bins,
                          unsigned long long* cull, hipStream_t st) {
     if (m.B <= 0) return;
-    const BinGeom G = mix_geom(max_n, max_tiles);
-    bin_hist_kernel<true><<<dim3(G.nbq, m.B), kThreads, 0, st>>>(r.rect, r.count, G, hist, cull, m);
+    hist_launch(mix_geom(max_n, max_tiles), m.B, r, bins, cull, st, &m);
 }
 
-void launch_mix_bin_scatter(const MixBatch& m, int max_n, int max_tiles, const Records& r,
-                            const uint32_t* hist_scanned, const uint64_t* n_dev, uint32_t* vals, hipStream_t st) {
+void launch_mix_bin_offsets(const MixBatch& m, int max_n, int max_tiles, uint32_t* bins, void* scratch,
+                            uint64_t* total, hipStream_t st) {
     if (m.B <= 0) return;
-    const BinGeom G = mix_geom(max_n, max_tiles);
-    if (G.S == 1 && G.db == 8)
-        bin_scatter_kernel<1, 8, true><<<dim3(G.nbq, m.B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned,
-                                                                               n_dev, vals, m);
-    else
-        bin_scatter_kernel<4, kWideDb, true><<<dim3(G.nbq, m.B), kThreads, 0, st>>>(r.rect, r.count, G,
-                                                                                     hist_scanned, n_dev, vals, m);
+    offsets_launch(mix_geom(max_n, max_tiles), m.B, bins, scratch, total, st);
 }
 
-void launch_mix_bin_ranges(const MixBatch& m, int max_n, int max_tiles, const uint32_t* hist_scanned,
-                           const uint64_t* total, const uint64_t* n_dev, int64_t tile_cap, uint2* ranges,
-                           hipStream_t st) {
+void launch_mix_bin_scatter(const MixBatch& m, int max_n, int max_tiles, const Records& r, const uint32_t* bins,
+                            const uint64_t* n_dev, uint32_t* vals, hipStream_t st) {
+    if (m.B <= 0) return;
+    place_launch(mix_geom(max_n, max_tiles), m.B, r, bins, n_dev, vals, st, &m);
+}
+
+void launch_mix_bin_ranges(const MixBatch& m, int max_n, int max_tiles, const uint32_t* bins, const uint64_t* total,
+                           const uint64_t* n_dev, int64_t tile_cap, uint2* ranges, hipStream_t st) {
     if (tile_cap <= 0 || m.B <= 0) return;
-    mix_bin_ranges_kernel<<<(unsigned)((tile_cap + 255) / 256), 256, 0, st>>>(
-        hist_scanned, m, mix_geom(max_n, max_tiles), total, n_dev, tile_cap, ranges);
-}
-
-void launch_bin_scatter(const Records& r, int B, int N, const Grid& g, const uint32_t* hist_scanned,
-                        const uint64_t* n_dev, uint32_t* vals, hipStream_t st) {
-    if (B <= 0 || N <= 0) return;
-    const BinGeom G = bin_geom(N, g);
-    if (G.S == 1 && G.db == 8)
-        bin_scatter_kernel<1, 8><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev, vals);
-    else
-        bin_scatter_kernel<4, kWideDb><<<dim3(G.nbq, B), kThreads, 0, st>>>(r.rect, r.count, G, hist_scanned, n_dev,
-                                                                          vals);
-}
-
-void launch_bin_ranges(const uint32_t* hist_scanned, int B, int N, const Grid& g, const uint64_t* total,
-                       const uint64_t* n_dev, uint2* ranges, hipStream_t st) {
-    const int64_t m = (int64_t)B * g.tiles;
-    if (m <= 0) return;
-    bin_ranges_kernel<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(hist_scanned, B, bin_geom(N, g), total, n_dev,
-                                                                    ranges);
+    const BinGeom G = mix_geom(max_n, max_tiles);
+    mix_bin_ranges_kernel<<<(unsigned)((tile_cap + 255) / 256), 256, 0, st>>>(bins + hist_entries(m.B, G), m, G,
+                                                                               total, n_dev, tile_cap, ranges);
 }
 
 }  // namespace swf
