@@ -209,10 +209,13 @@ swf_status swf_render_mixed(swf_ctx *ctx, const int32_t *scene_ids, const float 
  * call that produced `aux` (flags must include SWF_KEEP_AUX there). Every
  * discrete decision is held at its forward outcome; where the 0.99 alpha clamp
  * is active the derivative through opacity and q is zero. Depth gets no
- * gradient. Recomputes the forward intermediates it needs (after a BF16
- * forward its forward pass also keeps the MLP's hidden activations). Enqueued
- * on `stream`; like swf_render it waits once for the key count of the forward
- * pass it repeats, and otherwise returns after enqueueing. aux must be the
+ * gradient. The render that filled aux keeps its records, tile lists and
+ * (after a BF16 forward) the MLP's hidden activations in the context's
+ * workspace; the backward takes them when no other pass has written records
+ * on the context since and tx is the same pointer (tx must hold the same
+ * positions in any case), and otherwise repeats the forward pass, which then
+ * waits once for its key count. SWF_DEV_BWD_REUSED in swf_last_device_status
+ * tells which. Enqueued on `stream`; returns after enqueueing. aux must be the
  * buffer such a render on this context filled (the context remembers the last
  * 1024): SWF_E_STATE if it is unknown or the scene's parameters were updated
  * (swf_scene_update) since, SWF_E_INVALID if scene, batch or flags (other
@@ -383,6 +386,8 @@ enum {
     SWF_DEV_RERENDERED = 1u << 1,       /* ... so the call rendered again, exactly sized */
     SWF_DEV_CULLED_NONFINITE = 1u << 2, /* culled_nonfinite > 0                          */
     SWF_DEV_CULLED_OFFGRID = 1u << 3,   /* culled_offgrid > 0                            */
+    SWF_DEV_BWD_REUSED = 1u << 4,       /* the last swf_render_backward took the records
+                                           and lists its forward render kept            */
 };
 typedef struct {
     uint32_t flags;             /* SWF_DEV_* bits                                     */

@@ -83,7 +83,7 @@ class _DevStatus(ctypes.Structure):
                 ("list_entries", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 3)]
 
 
-DEV_KEY_OVERFLOW, DEV_RERENDERED, DEV_CULLED_NONFINITE, DEV_CULLED_OFFGRID = 1, 2, 4, 8
+DEV_KEY_OVERFLOW, DEV_RERENDERED, DEV_CULLED_NONFINITE, DEV_CULLED_OFFGRID, DEV_BWD_REUSED = 1, 2, 4, 8, 16
 
 SERVE_COUNTERS = ("launches", "completed", "fallbacks", "graph_builds", "budget_shrinks", "workspace_bytes",
                   "mixed_launches", "mixed_scenes")

@@ -288,12 +288,13 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     Scene* sc = scene(sid);
     if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
     if (sc->d.kind == 1) return fail(SWF_E_INVALID, "paper-model scenes have no backward in this library");
+    AuxTag t;
     {
-        // the forward pass below must be the one that filled aux
+        // the forward state used below must be that of the render that filled aux
         auto it = aux_tags.find(aux);
         if (it == aux_tags.end())
             return fail(SWF_E_STATE, "aux was not filled by a swf_render with SWF_KEEP_AUX on this context");
-        const AuxTag& t = it->second;
+        t = it->second;
         if (t.scene != sid || t.B != B || t.flags != (flags & ~SWF_KEEP_AUX))
             return fail(SWF_E_INVALID, "scene, batch or flags differ from the render that filled aux");
         if (t.gen != sc->gen)
@@ -302,20 +303,25 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     const DevScene& d = sc->d;
     const bool deform = !(flags & SWF_NO_DEFORM);
     const bool want_mlp = deform && d.has_mlp;
-    // After a BF16 forward the MLP kernel of the forward pass below also stores the
-    // hidden activations the MLP backward needs (the same values the forward used).
+    // After a BF16 forward the MLP backward takes the hidden activations the forward's MLP kernel stored (the
+    // same values the forward used).
     const bool bf16 = (flags & SWF_MLP_BF16) != 0;
     const bool acts_ready = want_mlp && bf16 && B >= 1 && (uint64_t)B * (uint64_t)d.n < (1ull << 32);
     swf_status s = SWF_OK;
-    if (acts_ready) {
-        const size_t actb = (size_t)B * d.n * 256 * sizeof(uint16_t);
-        if ((s = w.act.reserve(this, actb * d.n_hidden + 16, st))) return s;
-        w.act_out = w.act.ptr;
+    // 1. the forward's records and lists: still in the workspace if no pass wrote records since that render
+    // (and it was given the same positions), else built again (deterministic: identical to the forward's)
+    const bool kept = t.seq == w.seq && t.tx == tx && (!acts_ready || t.acts);
+    if (!kept) {
+        if (acts_ready) {
+            const size_t actb = (size_t)B * d.n * 256 * sizeof(uint16_t);
+            if ((s = w.act.reserve(this, actb * d.n_hidden + 16, st))) return s;
+            w.act_out = w.act.ptr;
+        }
+        s = forward_lists(w, sid, tx, B, flags & ~SWF_KEEP_AUX, st);
+        w.act_out = nullptr;
+        if (s) return s;
     }
-    // 1. the forward lists again (deterministic: identical to the forward's)
-    s = forward_lists(w, sid, tx, B, flags & ~SWF_KEEP_AUX, st);
-    w.act_out = nullptr;
-    if (s) return s;
+    last_bwd_reused = kept;
     const int64_t P = (int64_t)B * d.n;
     const size_t npix = (size_t)B * d.H * d.W;
     const float* auxT = (const float*)aux;

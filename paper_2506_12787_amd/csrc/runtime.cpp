@@ -576,6 +576,7 @@ swf_status Ctx::release_scene(int id) {
 // Enqueue preprocess (+ MLP) for B queries into the workspace records.
 swf_status Ctx::enqueue_preprocess(Workspace& w, Scene* sc, const float* tx, int B, int flags, const Grid& g, float* delta_sorted,
                                    hipStream_t st) {
+    ++w.seq;  // the records (and the lists built from them) are about to change
     const DevScene& d = sc->d;
     const bool deform = !(flags & SWF_NO_DEFORM);
     if (d.kind == 1 && (flags & (SWF_MLP_BF16 | SWF_TILE8 | SWF_KEEP_AUX)))
@@ -795,17 +796,36 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
     hipSetDevice(device);
     const uint64_t spec_cap = speculate && key_cap == 0 && w.vals.cap >= 16 + 4 * 4096 ? (w.vals.cap - 16) / 4 : 0;
     bool spec = false;
-    swf_status s = forward_lists(w, sid, tx, B, flags, st, key_cap, spec_cap, &spec, rH, rW);
+    // a render whose state the backward will need keeps its records and lists in the workspace; after a BF16
+    // forward also the hidden activations, stored by the MLP kernel (what the backward's GEMMs take)
+    const bool keep = (flags & SWF_KEEP_AUX) && &w == &ws;
+    bool keep_acts = false;
+    swf_status s;
+    if (keep) {
+        Scene* sc0 = scene(sid);
+        if (sc0 && sc0->d.kind == 0 && sc0->d.has_mlp && !(flags & SWF_NO_DEFORM) && (flags & SWF_MLP_BF16) &&
+            (uint64_t)B * (uint64_t)sc0->d.n < (1ull << 32)) {
+            const size_t actb = (size_t)B * sc0->d.n * 256 * sizeof(uint16_t);
+            if ((s = w.act.reserve(this, actb * sc0->d.n_hidden + 16, st))) return s;
+            w.act_out = w.act.ptr;
+            keep_acts = true;
+        }
+    }
+    s = forward_lists(w, sid, tx, B, flags, st, key_cap, spec_cap, &spec, rH, rW);
+    w.act_out = nullptr;
     if (s) return s;
     const DevScene& d = scene(sid)->d;
     float* auxT = nullptr;
     uint32_t* auxL = nullptr;
-    if ((flags & SWF_KEEP_AUX) && &w == &ws) {
+    if (keep) {
         AuxTag t;
         t.scene = sid;
         t.B = B;
         t.flags = flags & ~SWF_KEEP_AUX;
         t.gen = scene(sid)->gen;
+        t.seq = w.seq;
+        t.tx = tx;
+        t.acts = keep_acts;
         tag_aux(aux, t);
     }
     if (flags & SWF_KEEP_AUX) {
@@ -955,6 +975,7 @@ swf_status Ctx::enqueue_mixed(Workspace& w, const MixPlan& p, const float* tx, i
     if (copy_tables &&
         (s = hip(hipMemcpyAsync(w.mix.ptr, w.mix_host, p.table_bytes, hipMemcpyHostToDevice, st), "mix tables")))
         return s;
+    ++w.seq;  // the records and lists are about to change
     MixBatch mb;
     mb.scenes = (const MixScene*)w.mix.ptr;
     mb.queries = (const MixQuery*)((char*)w.mix.ptr + p.query_off);
@@ -1380,6 +1401,7 @@ swf_status swf_last_device_status(swf_ctx* h, swf_device_status* out) {
     out->list_entries = w.last.n_keys;
     if (out->culled_nonfinite) out->flags |= SWF_DEV_CULLED_NONFINITE;
     if (out->culled_offgrid) out->flags |= SWF_DEV_CULLED_OFFGRID;
+    if (c->last_bwd_reused) out->flags |= SWF_DEV_BWD_REUSED;
     return SWF_OK;
 }
 

@@ -62,7 +62,8 @@ struct Workspace {
     unsigned long long* cull_dev = nullptr;  //   culled pairs: [0] non-finite/degenerate, [1] off the grid
     uint64_t* total_host = nullptr;  // pinned
     hipEvent_t total_ev = nullptr;   // the scan total has reached total_host (speculative renders)
-    void* act_out = nullptr;         // set during the backward's forward pass: BF16 hidden activations go here
+    void* act_out = nullptr;         // set during a forward pass whose BF16 hidden activations are kept: they go here
+    uint64_t seq = 0;                // record generation: incremented by every pass that writes the records
     void* mix_host = nullptr;        // pinned staging of a mixed batch's scene and query tables
     size_t mix_host_cap = 0;
     LastRender last;
@@ -85,6 +86,11 @@ struct Workspace {
 struct AuxTag {
     int scene = -1, B = 0, flags = 0;
     uint64_t gen = 0;
+    // the forward's records, lists (and, after a BF16 forward, hidden activations) stay in the workspace until
+    // the next pass that writes records: seq is the workspace's record generation right after that forward
+    uint64_t seq = 0;
+    const float* tx = nullptr;
+    bool acts = false;
 };
 
 // A mixed batch's plan (runtime.cpp): totals, output offsets and the layout of
@@ -131,6 +137,7 @@ struct Ctx {
     // aux buffers filled by direct renders (device address -> tag), newest last;
     // bounded, the oldest forgotten first
     std::map<const void*, AuxTag> aux_tags;
+    bool last_bwd_reused = false;  // the last backward took the forward's kept records and lists
     std::vector<const void*> aux_order;
     void tag_aux(const void* aux, const AuxTag& t);
 

@@ -212,3 +212,37 @@ def test_autograd_training_step_matches_direct_backward(ctx):
     print("L1 before / after one step", float(l0), l1)
     assert l1 < float(l0)
     ctx.release_scene(model.sid)
+
+
+@pytest.mark.parametrize("bf16", [True, False], ids=["bf16", "fp32"])
+def test_backward_takes_the_kept_forward_state(ctx, bf16):
+    # right after its forward the backward takes that render's records, lists and (BF16) activations; with another
+    # render on the context in between it builds them again: both give the same gradients (up to the order of the
+    # blend backward's atomic sums)
+    import torch
+    from paper_2506_12787_amd import binding as B
+    H, W, n, nb = 45, 90, 1500, 3
+    g = synth.gaussians(n, H, W, seed=610, scale_range=(1.0, 6.0))
+    Ws, bs = synth.mlp_weights(seed=3610, out_scale=0.3)
+    sid = ctx.upload_scene(g, H, W, mlp=(Ws, bs))
+    tx = torch.from_numpy(synth.tx_positions(nb, seed=710)).cuda()
+    flags = B.MLP_BF16 if bf16 else B.MLP_FP32
+    w = np.random.default_rng(5).normal(0, 1, (nb, H, W))
+    _, g1 = _gpu_grads(ctx, sid, tx, flags, w, n, Ws)
+    assert ctx.device_status()["flags"] & B.DEV_BWD_REUSED
+    _, aux = ctx.render(sid, tx, flags=flags | B.KEEP_AUX, batch=nb)
+    ctx.render(sid, tx[:1].contiguous(), flags=flags)
+    gr = {k: torch.zeros(n, device="cuda") for k in PARAMS}
+    gr["weight"] = [torch.zeros(x.shape, device="cuda") for x in Ws]
+    gr["bias"] = [torch.zeros(x.shape[0], device="cuda") for x in Ws]
+    ctx.render_backward(sid, tx, flags, torch.from_numpy(w.astype(np.float32)).cuda(), aux, gr)
+    torch.cuda.synchronize()
+    assert not ctx.device_status()["flags"] & B.DEV_BWD_REUSED
+    for k in PARAMS:
+        a, b = g1[k], gr[k].cpu().numpy()
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-5 * np.abs(a).max() + 1e-30, err_msg=k)
+    for l, x in enumerate(gr["weight"]):
+        a = g1["weight"][l]
+        np.testing.assert_allclose(x.cpu().numpy(), a, rtol=0, atol=1e-5 * np.abs(a).max() + 1e-30,
+                                   err_msg=f"weight {l}")
+    ctx.release_scene(sid)
