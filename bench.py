@@ -532,12 +532,12 @@ def bench_train(a):
     count = [0]
     reused = []
 
-    def step(i, probe=False):
+    def step(i, probe=False, det=False):
         out, aux = ctx.render(sid, tx_dev[i], flags=B.MLP_BF16 | B.KEEP_AUX)
         loss, grad = ctx.l1_loss(out, targets[i])
         for t in grads:
             t.zero_()
-        ctx.render_backward(sid, tx_dev[i], B.MLP_BF16, grad, aux, gd)
+        ctx.render_backward(sid, tx_dev[i], B.MLP_BF16 | (B.DETERMINISTIC if det else 0), grad, aux, gd)
         if probe:  # (waits) whether the backward took its forward's kept records and lists
             reused.append(bool(ctx.device_status()["flags"] & B.DEV_BWD_REUSED))
         count[0] += 1
@@ -570,6 +570,15 @@ def bench_train(a):
     stages = {k: v[0] / n_inst for k, v in ctx.stage_times().items() if v[1] > 0}
     ctx.stage_timing(False)
     step(warmup, probe=True)
+    # the same steps with the deterministic backward (fixed-order gradient sums)
+    nd = min(steps, 10)
+    step(warmup, det=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(nd):
+        step(warmup + i, det=True)
+    torch.cuda.synchronize()
+    det_ms = 1e3 * (time.perf_counter() - t1) / nd
     # MLP backward FLOPs per pair: weight gradients and input gradients of the output layer (7 x 256) and of the
     # three 256 x 256 layers, 2 FLOP per multiply-add each (layer 1's gradients are per Gaussian and per query)
     bwd_flop = Bq * N * 2 * 2 * (7 * 256 + 3 * 256 * 256)
@@ -591,6 +600,7 @@ def bench_train(a):
                      "frac": None if ach is None else ach / PEAK["bf16"], "traffic": None,
                      "flop_per_step": bwd_flop, "avg_ms": t_bwd},
         "backward_reused_forward": reused[0],
+        "deterministic_ms_per_step": det_ms,
         "note": "targets: a separately seeded ground-truth Gaussian set rendered by this library at the same TX "
                 "positions; stage times from 5 more steps with stage events on; the backward takes the records, "
                 "lists and BF16 activations its forward render kept (backward_reused_forward)",

@@ -77,12 +77,17 @@ enum {
     SWF_TILE8 = 1 << 4,      /* 8x8 tiles instead of 16x16 (same result)         */
     SWF_PAPER_DEFORM = 1 << 5,/* zero the covariance residuals (outputs 2..4), as
                                 the paper does not deform the covariance         */
-    SWF_WRAP_AZIMUTH = 1 << 6 /* periodic azimuth: columns 0 and W-1 are
+    SWF_WRAP_AZIMUTH = 1 << 6, /* periodic azimuth: columns 0 and W-1 are
                                 neighbours (0 and 360 degrees are one direction,
                                 Sec. 3.1 spectrum grid); a Gaussian acts at each
                                 pixel through the image of its mean (shifted by a
                                 whole number of grid widths) nearest to it. Lists
-                                are built by key sorting (no binning)             */
+                                are built by binning when a query's tiles form one
+                                segment (at most 256), else by key sorting         */
+    SWF_DETERMINISTIC = 1 << 7 /* swf_render_backward: gradients summed in a fixed
+                                order (bitwise the same from run to run) instead of
+                                by atomic adds; takes 128 bytes per list entry of
+                                device memory and one more pass                   */
 };
 
 typedef struct swf_ctx swf_ctx;
@@ -215,7 +220,11 @@ swf_status swf_render_mixed(swf_ctx *ctx, const int32_t *scene_ids, const float 
  * on the context since and tx is the same pointer (tx must hold the same
  * positions in any case), and otherwise repeats the forward pass, which then
  * waits once for its key count. SWF_DEV_BWD_REUSED in swf_last_device_status
- * tells which. Enqueued on `stream`; returns after enqueueing. aux must be the
+ * tells which. With SWF_DETERMINISTIC in flags (here; the render's flags
+ * need not carry it) every per-pixel contribution to a Gaussian's gradient is
+ * first summed per (list entry, wave) and the sums are added per pair in the
+ * order of its tiles, so the result does not depend on scheduling. Enqueued
+ * on `stream`; returns after enqueueing. aux must be the
  * buffer such a render on this context filled (the context remembers the last
  * 1024): SWF_E_STATE if it is unknown or the scene's parameters were updated
  * (swf_scene_update) since, SWF_E_INVALID if scene, batch or flags (other

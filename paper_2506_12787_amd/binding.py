@@ -23,6 +23,7 @@ FULL_SORT = 1 << 3
 TILE8 = 1 << 4
 PAPER_DEFORM = 1 << 5
 WRAP_AZIMUTH = 1 << 6
+DETERMINISTIC = 1 << 7
 
 STAGES = ("tx_features", "mlp_preprocess", "scan", "emit_keys", "radix_sort", "tile_ranges", "blend",
           "blend_backward", "preprocess_backward", "mlp_backward")

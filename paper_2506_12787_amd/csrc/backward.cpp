@@ -295,7 +295,7 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
         if (it == aux_tags.end())
             return fail(SWF_E_STATE, "aux was not filled by a swf_render with SWF_KEEP_AUX on this context");
         t = it->second;
-        if (t.scene != sid || t.B != B || t.flags != (flags & ~SWF_KEEP_AUX))
+        if (t.scene != sid || t.B != B || t.flags != (flags & ~(SWF_KEEP_AUX | SWF_DETERMINISTIC)))
             return fail(SWF_E_INVALID, "scene, batch or flags differ from the render that filled aux");
         if (t.gen != sc->gen)
             return fail(SWF_E_STATE, "the scene's parameters were updated after the render that filled aux");
@@ -317,7 +317,7 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
             if ((s = w.act.reserve(this, actb * d.n_hidden + 16, st))) return s;
             w.act_out = w.act.ptr;
         }
-        s = forward_lists(w, sid, tx, B, flags & ~SWF_KEEP_AUX, st);
+        s = forward_lists(w, sid, tx, B, flags & ~(SWF_KEEP_AUX | SWF_DETERMINISTIC), st);
         w.act_out = nullptr;
         if (s) return s;
     }
@@ -331,8 +331,16 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     if ((s = w.dbase.reserve(this, (size_t)P * kOut * sizeof(float) + 16, st))) return s;
     if ((s = hip(hipMemsetAsync(w.dpair.ptr, 0, (size_t)P * 8 * sizeof(float), st), "memset dpair"))) return s;
     stage_begin(SWF_STAGE_BWD_BLEND, st);
+    float* det_part = nullptr;
+    if (flags & SWF_DETERMINISTIC) {
+        // per (list entry, wave) sums, zero where a wave contributes nothing
+        const size_t db = (size_t)w.last.n_keys * 32 * sizeof(float);
+        if ((s = w.det.reserve(this, db + 16, st))) return s;
+        if (db && (s = hip(hipMemsetAsync(w.det.ptr, 0, db, st), "memset entry sums"))) return s;
+        det_part = (float*)w.det.ptr;
+    }
     launch_blend_backward((const uint2*)w.ranges.ptr, w.last.vals, w.rec, B, w.last.grid, grad_out, auxT, auxL,
-                          (float*)w.dpair.ptr, st);
+                          (float*)w.dpair.ptr, st, det_part, d.n);
     stage_end(st);
     // 3. preprocess backward -> residual-coordinate gradients
     float* dy = nullptr;

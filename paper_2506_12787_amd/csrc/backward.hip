@@ -65,7 +65,10 @@ __device__ __forceinline__ float wave_sum8(float (&a)[8]) {
 // leave every one of its pixels unchanged.
 // kWrap: periodic azimuth, as in the forward kernel (same staged image, same
 // displacement, same culling exemption), so that every decision replays exactly.
-template <int TILE, bool kWrap = false>
+// kDet: instead of adding into dpair, each wave writes its 8 sums of an entry
+// to part[(list position) * 32 + wave * 8 + k] (zeroed beforehand); the
+// per-pair sums are then taken in a fixed order by det_reduce_kernel.
+template <int TILE, bool kWrap = false, bool kDet = false>
 __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals, const float4* __restrict__ geo,
     const float4* __restrict__ wm, const float2* __restrict__ oa, int H, int W, int TW, int tiles,
@@ -158,7 +161,10 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
         const unsigned l = lane_id();
         if (l < 8u && v != 0.0f) {
             const int k = 4 * (int)(l & 1u) + 2 * (int)((l >> 1) & 1u) + (int)((l >> 2) & 1u);
-            atomicAdd(dpair + (size_t)s_v[jj] * 8 + k, v);
+            if constexpr (kDet)
+                dpair[((size_t)rg.x + (size_t)j) * 32 + (size_t)wq * 8 + k] = v;
+            else
+                atomicAdd(dpair + (size_t)s_v[jj] * 8 + k, v);
         }
     };
 
@@ -205,6 +211,54 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
             for (int jj = cnt - 1; jj >= 0; --jj) entry(beg, jj);
         }
     }
+}
+
+// Deterministic gradient sums: pair i (query b = i / N) adds, for every tile
+// of its rectangle in row-major order (a wrapped rectangle's columns from tx0
+// on), the four waves' sums of its entry in that tile's list, found by binary
+// search (a list holds its pairs in increasing order).
+__global__ void det_reduce_kernel(const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+                                  const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
+                                  const float* __restrict__ part, int64_t P, int N, int TW, int tiles,
+                                  float* __restrict__ dpair) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (count[i]) {
+        const uint2 r = rect[i];
+        const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
+        const int w = tx1 >= tx0 ? tx1 - tx0 + 1 : TW - tx0 + tx1 + 1;
+        const size_t gt0 = (size_t)(i / N) * tiles;
+        for (int ty = ty0; ty <= ty1; ++ty)
+            for (int k = 0; k < w; ++k) {
+                const int col = tx0 + k < TW ? tx0 + k : tx0 + k - TW;
+                const uint2 rg = ranges[gt0 + (size_t)(ty * TW + col)];
+                uint32_t lo = rg.x, hi = rg.y;  // first position in [lo, hi) whose value is >= i
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (vals[mid] < (uint32_t)i)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                if (lo >= rg.y || vals[lo] != (uint32_t)i) continue;  // an empty range (no entries kept)
+                const float4* e = reinterpret_cast<const float4*>(part + (size_t)lo * 32);
+#pragma unroll
+                for (int wv = 0; wv < 4; ++wv) {
+                    const float4 a = e[2 * wv], b = e[2 * wv + 1];
+                    acc[0] += a.x;
+                    acc[1] += a.y;
+                    acc[2] += a.z;
+                    acc[3] += a.w;
+                    acc[4] += b.x;
+                    acc[5] += b.y;
+                    acc[6] += b.z;
+                    acc[7] += b.w;
+                }
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) dpair[i * 8 + k] = acc[k];
 }
 
 // d(mean, M, opacity, amp) -> d(residual coordinates); the unmasked result
@@ -988,24 +1042,36 @@ __global__ void mean_features_f32_kernel(const float* __restrict__ mx, const flo
 
 void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
                            const float* grad_out, const float* aux_T, const uint32_t* aux_last, float* dpair,
-                           hipStream_t st) {
+                           hipStream_t st, float* det_part, int N) {
     const unsigned blocks = (unsigned)(B * g.tiles);
     if (!blocks) return;
-#define SWF_BLEND_BWD(TILE, WRAP)                                                                              \
-    blend_backward_kernel<TILE, WRAP><<<blocks, TILE * TILE, 0, st>>>(ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, \
-                                                                       g.TW, g.tiles, grad_out, aux_T, aux_last, \
-                                                                       dpair)
-    if (g.tile == 8) {
-        if (g.wrap)
-            SWF_BLEND_BWD(8, true);
+    float* dst = det_part ? det_part : dpair;
+#define SWF_BLEND_BWD(TILE, WRAP, DET)                                                                         \
+    blend_backward_kernel<TILE, WRAP, DET><<<blocks, TILE * TILE, 0, st>>>(                                    \
+        ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles, grad_out, aux_T, aux_last, dst)
+#define SWF_BLEND_BWD_T(TILE, DET)   \
+    do {                             \
+        if (g.wrap)                  \
+            SWF_BLEND_BWD(TILE, true, DET);  \
+        else                         \
+            SWF_BLEND_BWD(TILE, false, DET); \
+    } while (0)
+    if (det_part) {
+        if (g.tile == 8)
+            SWF_BLEND_BWD_T(8, true);
         else
-            SWF_BLEND_BWD(8, false);
+            SWF_BLEND_BWD_T(16, true);
+        const int64_t P = (int64_t)B * N;
+        if (P > 0)
+            det_reduce_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(ranges, vals, r.rect, r.count, det_part, P,
+                                                                           N, g.TW, g.tiles, dpair);
     } else {
-        if (g.wrap)
-            SWF_BLEND_BWD(16, true);
+        if (g.tile == 8)
+            SWF_BLEND_BWD_T(8, false);
         else
-            SWF_BLEND_BWD(16, false);
+            SWF_BLEND_BWD_T(16, false);
     }
+#undef SWF_BLEND_BWD_T
 #undef SWF_BLEND_BWD
 }
 

@@ -218,9 +218,11 @@ void launch_bin_ranges(const uint32_t* bins, int B, int N, const Grid& g, const 
                        const uint64_t* n_dev, uint2* ranges, hipStream_t st);
 
 // backward.hip
+// det_part (may be null): per (list entry, wave) sums, 32 floats per entry of the lists, zeroed by the caller;
+// with it the per-pair sums in dpair are taken in a fixed order (N: Gaussians per query)
 void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
                            const float* grad_out, const float* aux_T, const uint32_t* aux_last, float* dpair,
-                           hipStream_t st);
+                           hipStream_t st, float* det_part = nullptr, int N = 0);
 void launch_preprocess_backward(const float* dpair, const Records& r, int64_t P, bool paper_mask, float* dbase,
                                 float* dy, hipStream_t st);
 struct BaseGrads {  // destinations of the 7 base-parameter gradients (device; NULL skips one)

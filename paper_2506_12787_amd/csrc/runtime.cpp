@@ -821,7 +821,7 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
         AuxTag t;
         t.scene = sid;
         t.B = B;
-        t.flags = flags & ~SWF_KEEP_AUX;
+        t.flags = flags & ~(SWF_KEEP_AUX | SWF_DETERMINISTIC);
         t.gen = scene(sid)->gen;
         t.seq = w.seq;
         t.tx = tx;

@@ -55,7 +55,7 @@ struct LastRender {
 // Scratch memory of one render stream: every pipeline stage writes here.
 struct Workspace {
     Buf qs, geo, wm, oa, rect, count, off, scan, keys, keys2, vals, vals2, hist, ranges, bins, delta, sortk, sortv,
-        grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, stage, work, beam, pool, ssim, mix;
+        grad, dpair, dbase, dy, act, dz, part, fmean, ftx, dmu, stage, work, beam, pool, ssim, mix, det;
     Records rec;
     uint64_t* total_dev = nullptr;           // device status block: scan total, effective count, then:
     uint32_t* status_dev = nullptr;          //   status word (bit 0: key overflow at a fixed capacity)
@@ -70,7 +70,7 @@ struct Workspace {
     std::vector<Buf*> bufs() {
         return {&qs, &geo, &wm, &oa, &rect, &count, &off, &scan, &keys, &keys2, &vals, &vals2, &hist, &ranges, &bins,
                 &delta, &sortk, &sortv, &grad, &dpair, &dbase, &dy, &act, &dz, &part, &fmean, &ftx, &dmu,
-                &stage, &work, &beam, &pool, &ssim, &mix};
+                &stage, &work, &beam, &pool, &ssim, &mix, &det};
     }
     uint64_t generation() {
         uint64_t g = 0;
