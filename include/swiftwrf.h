@@ -96,7 +96,11 @@ typedef struct {
     int32_t device;             /* HIP device ordinal                             */
     int32_t mlp_pairs_per_wave; /* BF16 MLP tuning: pairs per wave, 48 (default
                                    or 0) or 32 (two waves per SIMD), or 64 (one)  */
-    int32_t reserved[6];
+    uint32_t max_list_entries;  /* most tile-list entries one launch sequence of
+                                   swf_render builds (0: 2^32 - 1, the most the
+                                   32-bit list positions address); a batch with
+                                   more is rendered in chunks of queries           */
+    int32_t reserved[5];
 } swf_config;
 
 typedef struct {
@@ -170,7 +174,11 @@ swf_status swf_scene_bytes(swf_ctx *ctx, int32_t scene_id, uint64_t *bytes);
  * scan). The first render of a context sizes the key buffers from that count
  * before enqueueing the rest; later ones enqueue the rest at the buffers'
  * capacity and wait for the count meanwhile, rendering again at the exact size
- * (the same call, still on `stream`) if it did not fit. */
+ * (the same call, still on `stream`) if it did not fit. A batch whose lists
+ * would hold more entries than the context's max_list_entries (or whose
+ * batch * n reaches 2^32) is rendered in chunks of queries, halving until each
+ * fits (not with SWF_KEEP_AUX: SWF_E_OVERFLOW then); the outputs are those of
+ * one launch. */
 swf_status swf_render(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_t batch, int32_t flags, float *out,
                       void *aux, void *stream);
 
@@ -397,6 +405,10 @@ enum {
     SWF_DEV_CULLED_OFFGRID = 1u << 3,   /* culled_offgrid > 0                            */
     SWF_DEV_BWD_REUSED = 1u << 4,       /* the last swf_render_backward took the records
                                            and lists its forward render kept            */
+    SWF_DEV_CHUNKED = 1u << 5,          /* the last swf_render split its batch into chunks
+                                           of queries (more list entries than
+                                           max_list_entries, or 2^32 pairs); the other
+                                           fields describe its last chunk               */
 };
 typedef struct {
     uint32_t flags;             /* SWF_DEV_* bits                                     */

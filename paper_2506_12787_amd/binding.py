@@ -35,7 +35,7 @@ _fp = ctypes.POINTER(ctypes.c_float)
 
 class _Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("mlp_pairs_per_wave", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("max_list_entries", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class _Gaussians(ctypes.Structure):
@@ -84,7 +84,8 @@ class _DevStatus(ctypes.Structure):
                 ("list_entries", ctypes.c_uint64), ("reserved", ctypes.c_uint64 * 3)]
 
 
-DEV_KEY_OVERFLOW, DEV_RERENDERED, DEV_CULLED_NONFINITE, DEV_CULLED_OFFGRID, DEV_BWD_REUSED = 1, 2, 4, 8, 16
+DEV_KEY_OVERFLOW, DEV_RERENDERED, DEV_CULLED_NONFINITE, DEV_CULLED_OFFGRID, DEV_BWD_REUSED, DEV_CHUNKED = (
+    1, 2, 4, 8, 16, 32)
 
 SERVE_COUNTERS = ("launches", "completed", "fallbacks", "graph_builds", "budget_shrinks", "workspace_bytes",
                   "mixed_launches", "mixed_scenes")
@@ -172,13 +173,13 @@ def _stream():
 class Context:
     """One libswiftwrf context on one GPU."""
 
-    def __init__(self, device: int = 0, mlp_pairs_per_wave: int = 0):
+    def __init__(self, device: int = 0, mlp_pairs_per_wave: int = 0, max_list_entries: int = 0):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
         self._L = lib()
         h = ctypes.c_void_p()
-        cfg = _Config(device=device, mlp_pairs_per_wave=mlp_pairs_per_wave)
+        cfg = _Config(device=device, mlp_pairs_per_wave=mlp_pairs_per_wave, max_list_entries=max_list_entries)
         self._check(self._L.swf_create(ctypes.byref(h), ctypes.byref(cfg)), ctx=False)
         self._h = h
         self._keep = {}

@@ -642,7 +642,8 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     if (!sc) return fail(SWF_E_NOT_FOUND, "unknown scene id");
     if (B < 1) return fail(SWF_E_INVALID, "batch must be >= 1");
     const DevScene& d = sc->d;
-    if ((uint64_t)B * (uint64_t)d.n >= (1ull << 32)) return fail(SWF_E_INVALID, "batch * n must be < 2^32");
+    if ((uint64_t)B * (uint64_t)d.n >= (1ull << 32))
+        return fail(SWF_E_OVERFLOW, "batch * n must be < 2^32 (32-bit pair indices)");
     // the scene's own grid, or another resolution of the same field of view
     const int gH = rH > 0 ? rH : d.H, gW = rW > 0 ? rW : d.W;
     if (gH > 4096 || gW > 4096) return fail(SWF_E_INVALID, "height and width must lie in [1, 4096]");
@@ -674,6 +675,7 @@ swf_status Ctx::forward_lists(Workspace& w, int sid, const float* tx, int B, int
     w.last.flags = flags;
     w.last.grid = g;
     w.last.rerenders = 0;
+    w.last.chunked = false;
     w.last.nan_depth_pairs = (uint64_t)B * (uint64_t)(d.n - d.n_live);
     return hip(hipGetLastError(), "forward launch");
 }
@@ -705,7 +707,9 @@ swf_status Ctx::key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64
             if ((s = hip(hipEventRecord(w.total_ev, st), "total event"))) return s;
         }
     }
-    if (nk >= (1ull << 32)) return fail(SWF_E_OVERFLOW, "more than 2^32 - 1 keys; render a smaller batch");
+    if (nk > max_list_entries)
+        return fail(SWF_E_OVERFLOW, "more list entries than one launch sequence takes (max_list_entries, at most "
+                                    "2^32 - 1)");
     return SWF_OK;
 }
 
@@ -813,6 +817,20 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
     }
     s = forward_lists(w, sid, tx, B, flags, st, key_cap, spec_cap, &spec, rH, rW);
     w.act_out = nullptr;
+    if (s == SWF_E_OVERFLOW && B > 1 && key_cap == 0 && !(flags & SWF_KEEP_AUX)) {
+        // more list entries (or pairs) than one launch sequence addresses: the first half of the queries, then
+        // the rest (each split again if needed); the outputs are per query, so they land where one launch puts them
+        Scene* sc1 = scene(sid);
+        const int oH = rH > 0 ? rH : sc1->d.H, oW = rW > 0 ? rW : sc1->d.W;
+        const int b1 = B / 2;
+        const size_t plane = (size_t)oH * oW;
+        s = render(w, sid, tx, b1, flags, out, nullptr, st, 0, false, chan, rH, rW);
+        if (!s)
+            s = render(w, sid, tx ? tx + (size_t)3 * b1 : nullptr, B - b1, flags, out + (size_t)b1 * plane, nullptr,
+                       st, 0, false, chan ? chan + (size_t)b1 * 2 * plane : nullptr, rH, rW);
+        if (!s) w.last.chunked = true;
+        return s;
+    }
     if (s) return s;
     const DevScene& d = scene(sid)->d;
     float* auxT = nullptr;
@@ -1121,6 +1139,7 @@ swf_status swf_create(swf_ctx** out, const swf_config* cfg) {
     if (!c) return SWF_E_OOM;
     c->device = dev;
     c->mlp_pairs_per_wave = cfg ? cfg->mlp_pairs_per_wave : 0;
+    if (cfg && cfg->max_list_entries) c->max_list_entries = cfg->max_list_entries;
     if (c->ws.init(c) != SWF_OK) {
         c->ws.release();
         delete c;
@@ -1402,6 +1421,7 @@ swf_status swf_last_device_status(swf_ctx* h, swf_device_status* out) {
     if (out->culled_nonfinite) out->flags |= SWF_DEV_CULLED_NONFINITE;
     if (out->culled_offgrid) out->flags |= SWF_DEV_CULLED_OFFGRID;
     if (c->last_bwd_reused) out->flags |= SWF_DEV_BWD_REUSED;
+    if (w.last.chunked) out->flags |= SWF_DEV_CHUNKED;
     return SWF_OK;
 }
 

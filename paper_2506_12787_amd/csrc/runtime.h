@@ -50,6 +50,7 @@ struct LastRender {
     hipStream_t stream = nullptr;  // stream of the last render (status reads wait for it)
     uint32_t rerenders = 0;        // exact-size re-renders after a speculative key overflow
     uint64_t nan_depth_pairs = 0;  // pairs of Gaussians with a NaN depth (never preprocessed)
+    bool chunked = false;          // the call rendered its batch in chunks of queries (this is the last chunk)
 };
 
 // Scratch memory of one render stream: every pipeline stage writes here.
@@ -143,6 +144,7 @@ struct Ctx {
 
     ServeState* serve = nullptr;
     int mlp_pairs_per_wave = 0;  // BF16 MLP register tile: 48 (default, 0), 32 or 64 pairs per wave
+    uint64_t max_list_entries = 0xffffffffull;  // list entries per launch sequence; more: chunks of queries
 
     swf_status fail(swf_status s, const std::string& msg);
     swf_status hip(hipError_t e, const char* what);

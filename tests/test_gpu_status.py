@@ -116,3 +116,40 @@ def test_status_before_any_render_is_a_state_error(fresh):
     from paper_2506_12787_amd import binding as B
     with pytest.raises(B.SwfError):
         fresh.device_status()
+
+
+def test_batch_rendered_in_chunks_beyond_the_list_limit():
+    # a context whose launch sequence takes at most a third of the batch's list entries renders it in chunks of
+    # queries; every spectrum equals the one-launch render bitwise (deformable BF16, static, another resolution);
+    # with SWF_KEEP_AUX it refuses instead
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+    H, W, n, nb = 45, 130, 3000, 7
+    g = synth.gaussians(n, H, W, seed=630)
+    mlp = synth.mlp_weights(seed=3630)
+    tx = torch.from_numpy(synth.tx_positions(nb, seed=730)).cuda()
+    full = B.Context(0)
+    sid = full.upload_scene(g, H, W, mlp=mlp)
+    ref = full.render(sid, tx, flags=B.MLP_BF16)
+    entries = full.device_status()["list_entries"]
+    ref_s = full.render(sid, None, flags=B.NO_DEFORM, batch=nb)
+    ref_r = full.render_at(sid, 60, 200, tx=tx, flags=B.MLP_BF16)
+    full.close()
+    small = B.Context(0, max_list_entries=entries // 3)
+    sid = small.upload_scene(g, H, W, mlp=mlp)
+    got = small.render(sid, tx, flags=B.MLP_BF16)
+    st = small.device_status()
+    assert st["flags"] & B.DEV_CHUNKED and st["list_entries"] <= entries // 3
+    assert torch.equal(got, ref)
+    assert torch.equal(small.render(sid, None, flags=B.NO_DEFORM, batch=nb), ref_s)
+    assert torch.equal(small.render_at(sid, 60, 200, tx=tx, flags=B.MLP_BF16), ref_r)
+    with pytest.raises(B.SwfError):
+        small.render(sid, tx, flags=B.MLP_BF16 | B.KEEP_AUX)
+    # one query beyond the limit on its own cannot be split
+    tiny = B.Context(0, max_list_entries=max(entries // (4 * nb), 1))
+    sid = tiny.upload_scene(g, H, W, mlp=mlp)
+    with pytest.raises(B.SwfError):
+        tiny.render(sid, tx, flags=B.MLP_BF16)
+    tiny.close()
+    small.close()
