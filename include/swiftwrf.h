@@ -459,6 +459,15 @@ swf_status swf_debug_keys(swf_ctx *ctx, uint32_t *counts, uint32_t *offsets, uin
  * partitioning): tx0, ty0, tx1, ty1 (inclusive tile indices), or four -1 for a
  * culled pair. capacity = number of pairs rects holds. Synchronous. */
 swf_status swf_debug_rects(swf_ctx *ctx, int32_t *rects, uint64_t capacity);
+/* swf_debug_relu_pattern: after a swf_render_backward on this context that ran
+ * the MLP backward, copies to the HOST buffer pattern [batch][n][layers][256]
+ * (uint8, pairs in (query, original Gaussian id) order) the ReLU decisions of
+ * every hidden unit that backward used (1: the unit passed, its activation is
+ * positive): the forward kernel's after a BF16 forward, the recomputed ones
+ * after an FP32 forward (Sec. 4.2 network; the gradient holds them).
+ * capacity = bytes pattern holds. Synchronous. SWF_E_STATE without such a
+ * backward. */
+swf_status swf_debug_relu_pattern(swf_ctx *ctx, uint8_t *pattern, uint64_t capacity);
 /* swf_debug_blend_work: the work of the last swf_render's blend stage (Sec. 3.2
  * front-to-back rule), for roofline accounting: re-walks the same tile lists
  * without writing a spectrum and returns, in host memory, the number of (pixel,

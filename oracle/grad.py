@@ -74,38 +74,115 @@ def chain_to_params(g: dict, rg: dict, graster: np.ndarray) -> np.ndarray:
     return out
 
 
-def mlp_backward(x_mean, x_tx, mlp: M.MLP, dout, bf16=False, dabs=None):
+U32, U16 = 2.0 ** -24, 2.0 ** -8  # unit roundoffs: binary32, bfloat16 (8 significant bits)
+
+
+def _bf16_gap(v):
+    """(distance from v to the nearest boundary of its bfloat16 rounding interval,
+    the bfloat16 step at the rounded value); the interval below a power of two is
+    half as wide, so there the smaller half-step is taken."""
+    r = M.bf16_round(v)
+    m, e = np.frexp(r)
+    step = np.ldexp(1.0, e - 8)
+    half = np.where(np.abs(m) == 0.5, step / 4.0, step / 2.0)
+    return half - np.abs(np.asarray(v, np.float64) - r), step
+
+
+def _decision_slack(x_mean, x_tx, mlp, pres, acts, bf16, relu_masks=None):
+    """Per hidden layer: a bound T on |z' - z| between the pre-activation z of
+    this network and the z' an implementation in binary32 arithmetic computes
+    (FP32 accumulation of K products: (K + 2) u32 times the magnitude sum, plus
+    the differences its operands may carry), and a bound on the differences of
+    each layer's input operands. Operands: mean and position features computed
+    in binary32 (4 u32 of absolute error, |feature| <= 1); with bf16, rounded
+    operands agree exactly unless a rounding boundary lies within their slack
+    (then they may be one bfloat16 step apart), and a unit whose ReLU decision
+    is within its slack may pass up to T. With relu_masks the decisions are
+    held: no unit takes the other one, and only the passing units carry slack."""
+    rnd = M.bf16_round if bf16 else (lambda a: a)
+    dm = x_mean.shape[1]
+    W1m, W1s = rnd(mlp.W[0][:, :dm]), mlp.W[0][:, dm:]
+    xs = np.atleast_2d(x_tx)
+    if bf16:
+        gap, step = _bf16_gap(x_mean)
+        dxm = np.where(gap <= 4 * U32, step, 0.0)
+    else:
+        dxm = np.full(x_mean.shape, 4 * U32)
+    dxs = np.full(xs.shape[-1], 4 * U32)
+    A = np.abs(rnd(x_mean)) @ np.abs(W1m).T + np.abs(xs) @ np.abs(W1s).T + np.abs(mlp.b[0])
+    T = [(mlp.W[0].shape[1] + 2) * U32 * A + dxm @ np.abs(W1m).T + np.abs(W1s) @ dxs]
+    dins = [np.concatenate([dxm, np.broadcast_to(dxs, (dxm.shape[0], len(dxs)))], -1)]
+    for l in range(1, mlp.n_layers):
+        z, t, a = pres[l - 1], T[l - 1], acts[l - 1]
+        if relu_masks is not None:
+            held = relu_masks[l - 1].astype(bool)
+            amb = np.zeros(z.shape, bool)
+        else:
+            held = z > -t
+            amb = np.abs(z) <= t
+        if bf16:
+            gap, step = _bf16_gap(a)
+            da = np.where(held & (gap <= t), step, 0.0) + np.where(amb, t * (1.0 + 2.0 ** -7), 0.0)
+        else:
+            da = np.where(held, t, 0.0)
+        dins.append(da)
+        if l == mlp.n_layers - 1:
+            break
+        Wl = np.abs(rnd(mlp.W[l]))
+        A = np.abs(rnd(a)) @ Wl.T + np.abs(mlp.b[l])
+        T.append((mlp.W[l].shape[1] + 2) * U32 * A + da @ Wl.T)
+    return T, dins
+
+
+def mlp_backward(x_mean, x_tx, mlp: M.MLP, dout, bf16=False, dabs=None, relu_masks=None):
     """Backward of F_theta for rows sharing one TX feature vector. Returns
     (dW list, db list, d x_mean).
 
     bf16=True differentiates the BF16-rounding network of mlp_forward(bf16=True)
     with its rounded operands (weights, mean features, hidden activations) as
     the operands of every product, arithmetic exact; a rounding has derivative
-    one (its operand is treated as the value the forward used).
+    one (its operand is treated as the value the forward used). relu_masks
+    (one boolean array per hidden layer) holds the activation pattern.
 
     dabs (magnitudes >= |dout|, same shape), if given, also runs the same chain
     on absolute values, D_L = dabs, D_l = mask_l * (D_{l+1} |W_{l+1}|), and
     returns as a fourth item (A_W, A_b, D_xm): A_W[l] = sum over rows of
     D_l^T |a_{l-1}|, A_b[l] = sum of D_l, D_xm = D_1 |W1m|: the scales of
-    componentwise bounds on rounding errors made along the chain."""
-    out, pres, acts = M.mlp_forward(x_mean, x_tx, mlp, bf16=bf16)
+    componentwise bounds on rounding errors made along the chain. A fifth item
+    (F_W, F_b, F_xm) bounds what the decisions of this network's ReLUs may
+    change in an implementation that computes the pre-activations in binary32
+    (see _decision_slack): a unit whose pre-activation lies within its slack of
+    zero may take the other decision, which adds or removes its whole term
+    (F_l = amb_l * (D_{l+1} |W_{l+1}|), carried down the chain like D and
+    through every unit that may pass it), and operands that may differ by their
+    slack add D^T times that slack."""
+    out, pres, acts = M.mlp_forward(x_mean, x_tx, mlp, bf16=bf16, relu_masks=relu_masks)
     rnd = M.bf16_round if bf16 else (lambda a: a)
     L = mlp.n_layers
     dW = [None] * L
     db = [None] * L
     AW, Ab = [None] * L, [None] * L
+    FW, Fb = [None] * L, [None] * L
     d, D = dout, dabs
+    if D is not None:
+        T, dins = _decision_slack(x_mean, x_tx, mlp, pres, acts, bf16, relu_masks)
+        F = np.zeros_like(D)
     for l in range(L - 1, 0, -1):
         h = rnd(acts[l - 1])
         dW[l] = d.T @ h
         db[l] = d.sum(0)
         Wl = rnd(mlp.W[l])
-        mask = pres[l - 1] > 0
+        mask = (pres[l - 1] > 0) if relu_masks is None else relu_masks[l - 1].astype(bool)
         d = (d @ Wl) * mask
         if D is not None:
             AW[l] = D.T @ np.abs(h)
             Ab[l] = D.sum(0)
-            D = (D @ np.abs(Wl)) * mask
+            FW[l] = F.T @ np.abs(h) + D.T @ dins[l]
+            Fb[l] = F.sum(0)
+            G = D @ np.abs(Wl)
+            amb = (np.abs(pres[l - 1]) <= T[l - 1]) if relu_masks is None else np.zeros(mask.shape, bool)
+            F = (F @ np.abs(Wl)) * (mask | amb) + G * amb
+            D = G * mask
     dm = x_mean.shape[1]
     x_full = np.concatenate([rnd(x_mean), np.broadcast_to(np.atleast_2d(x_tx), (x_mean.shape[0], x_tx.shape[-1]))],
                             -1)
@@ -117,7 +194,9 @@ def mlp_backward(x_mean, x_tx, mlp: M.MLP, dout, bf16=False, dabs=None):
         return dW, db, dxm
     AW[0] = D.T @ np.abs(x_full)
     Ab[0] = D.sum(0)
-    return dW, db, dxm, (AW, Ab, D @ np.abs(W1m))
+    FW[0] = F.T @ np.abs(x_full) + D.T @ dins[0]
+    Fb[0] = F.sum(0)
+    return dW, db, dxm, (AW, Ab, D @ np.abs(W1m)), (FW, Fb, F @ np.abs(W1m))
 
 
 def posenc_backward(v, L, dgamma):
@@ -171,7 +250,7 @@ def posenc_backward_abs(v, L, dabs):
 
 
 def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAULT_ROOM, stop_grad_pos=False,
-                  pixel_weights=None, bf16=False, deltas=None, bounds=False, wrap=False):
+                  pixel_weights=None, bf16=False, deltas=None, bounds=False, wrap=False, relu_masks=None):
     """L1 loss over a batch of queries and its FP64 gradient.
 
     Returns (loss, grads) where grads has 'base' (n, 7) for
@@ -187,9 +266,13 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
     magnitude sums for componentwise error bounds: 'base_abs' (n, 7) of the
     compositing-and-covariance part, 'pe_abs' (n, 2) of the mean features' part
     through the network, 'W_abs' / 'b_abs' of the network's gradients (each the
-    absolute-value chain of the same computation), and 'replay' = the largest
-    number of Gaussians composited at a weighted pixel. wrap: periodic azimuth
-    (period W, nearest image of each mean)."""
+    absolute-value chain of the same computation), 'replay' = the largest
+    number of Gaussians composited at a weighted pixel, and 'W_flip' / 'b_flip'
+    / 'pe_flip': what the network's ReLU decisions within binary32 slack of
+    zero, and operand differences within that slack, may change (mlp_backward). wrap: periodic azimuth
+    (period W, nearest image of each mean). relu_masks (per query, one (n, 256)
+    boolean array per hidden layer): the network's activation pattern held at
+    the given decisions (e.g. those another implementation took)."""
     B = len(txs)
     H, W = scene.H, scene.W
     count = B * H * W
@@ -204,6 +287,9 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
         pe_abs = np.zeros((scene.n, 2))
         W_abs = [np.zeros_like(w) for w in mlp.W] if mlp is not None else None
         b_abs = [np.zeros_like(b) for b in mlp.b] if mlp is not None else None
+        W_flip = [np.zeros_like(w) for w in mlp.W] if mlp is not None else None
+        b_flip = [np.zeros_like(b) for b in mlp.b] if mlp is not None else None
+        pe_flip = np.zeros((scene.n, 2))
         replay = 0
     loss = 0.0
     period = float(W) if wrap else 0.0
@@ -239,7 +325,8 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
                 replay = max(replay, int(res.ncontrib.max()))
         if mlp is not None:
             xs = M.posenc(M.normalize_tx(txs[b], room), M.TX_BANDS)
-            r = mlp_backward(xm, xs, mlp, gp, bf16=bf16, dabs=gpa if bounds else None)
+            r = mlp_backward(xm, xs, mlp, gp, bf16=bf16, dabs=gpa if bounds else None,
+                             relu_masks=None if relu_masks is None else relu_masks[b])
             dW, db, dxm = r[:3]
             for l in range(mlp.n_layers):
                 gW[l] += dW[l]
@@ -250,17 +337,24 @@ def loss_and_grad(scene: M.Scene, mlp: M.MLP | None, txs, targets, room=M.DEFAUL
             gbase[:, 1] += dmu_hat[:, 1] / H
             if bounds:
                 AW, Ab, Dxm = r[3]
+                FW, Fb, Fxm = r[4]
                 for l in range(mlp.n_layers):
                     W_abs[l] += AW[l]
                     b_abs[l] += Ab[l]
+                    W_flip[l] += FW[l]
+                    b_flip[l] += Fb[l]
                 pa = posenc_backward_abs(mu_hat, M.MEAN_BANDS, Dxm)
                 pe_abs[:, 0] += pa[:, 0] / W
                 pe_abs[:, 1] += pa[:, 1] / H
+                pf = posenc_backward_abs(mu_hat, M.MEAN_BANDS, Fxm)
+                pe_flip[:, 0] += pf[:, 0] / W
+                pe_flip[:, 1] += pf[:, 1] / H
     if stop_grad_pos:
         gbase[:, 0:2] = 0.0
     out = dict(base=gbase, W=gW, b=gb, flagged=gflag.astype(bool))
     if bounds:
-        out.update(base_abs=base_abs, pe_abs=pe_abs, W_abs=W_abs, b_abs=b_abs, replay=replay)
+        out.update(base_abs=base_abs, pe_abs=pe_abs, W_abs=W_abs, b_abs=b_abs, replay=replay, W_flip=W_flip,
+                   b_flip=b_flip, pe_flip=pe_flip)
     return loss, out
 
 

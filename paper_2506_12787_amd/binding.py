@@ -131,6 +131,7 @@ def lib():
             "swf_debug_keys": [P, P, P, P, P, P, P, ctypes.c_uint64],
             "swf_debug_blend_work": [P, P, P, P],
             "swf_debug_rects": [P, P, ctypes.c_uint64],
+            "swf_debug_relu_pattern": [P, P, ctypes.c_uint64],
             "swf_last_device_status": [P, P],
             "swf_measure_peaks": [P, P, P, P],
             "swf_radix_sort": [P, P, P, I64, I32, I32, I32, P],
@@ -520,6 +521,12 @@ class Context:
         d = torch.empty((tx.shape[0], n, 7), device=self.device, dtype=torch.float32)
         self._check(self._L.swf_debug_deform(self._h, sid, _ptr(tx), tx.shape[0], flags, _ptr(d), _stream()))
         return d
+
+    def debug_relu_pattern(self, batch: int, n: int, layers: int):
+        """ReLU decisions of the hidden units the last backward used, (batch, n, layers, 256) bool, original ids."""
+        r = np.zeros((batch, n, layers, 256), np.uint8)
+        self._check(self._L.swf_debug_relu_pattern(self._h, r.ctypes.data_as(ctypes.c_void_p), r.size))
+        return r.astype(bool)
 
     def debug_rects(self, batch: int, n: int):
         """Tile rectangles of the last render's pairs, (batch, n, 4) int32 (tx0, ty0, tx1, ty1; -1 if culled)."""

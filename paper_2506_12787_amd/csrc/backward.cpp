@@ -357,6 +357,12 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     if (want_mlp) {
         stage_begin(SWF_STAGE_BWD_MLP, st);
         s = mlp_backward(w, d, tx, B, dy, gr, bf16, acts_ready, st);
+        last_mlp_bwd.valid = s == SWF_OK;
+        last_mlp_bwd.scene = sid;
+        last_mlp_bwd.B = B;
+        last_mlp_bwd.n = d.n;
+        last_mlp_bwd.layers = d.n_hidden;
+        last_mlp_bwd.bf16 = bf16;
         stage_end(st);
         if (s) return s;
         dmu = (float*)w.dmu.ptr;

@@ -1300,6 +1300,45 @@ swf_status swf_debug_deform(swf_ctx* h, int32_t scene_id, const float* tx, int32
     return c->hip(hipGetLastError(), "debug deform");
 }
 
+swf_status swf_debug_relu_pattern(swf_ctx* h, uint8_t* pattern, uint64_t capacity) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    if (!pattern) return c->fail(SWF_E_INVALID, "pattern is NULL");
+    const auto& L = c->last_mlp_bwd;
+    if (!L.valid) return c->fail(SWF_E_STATE, "no MLP backward to inspect");
+    Scene* sc = c->scene(L.scene);
+    if (!sc) return c->fail(SWF_E_STATE, "scene of the last backward was released");
+    const size_t pairs = (size_t)L.B * L.n, per = (size_t)L.layers * 256;
+    if (capacity < pairs * per) return c->fail(SWF_E_OVERFLOW, "capacity below batch * n * layers * 256");
+    swf_status s;
+    if ((s = c->hip(hipDeviceSynchronize(), "device sync"))) return s;
+    const size_t esz = L.bf16 ? 2 : 4, layer_bytes = pairs * 256 * esz;
+    std::vector<uint8_t> a(layer_bytes);
+    for (int l = 0; l < L.layers; ++l) {
+        if ((s = c->hip(hipMemcpy(a.data(), (const char*)c->ws.act.ptr + layer_bytes * l, layer_bytes,
+                                  hipMemcpyDeviceToHost),
+                        "D2H activations")))
+            return s;
+        for (size_t i = 0; i < pairs; ++i) {
+            const size_t q = i / L.n, id = sc->host_perm[i % L.n];
+            uint8_t* o = pattern + ((q * L.n + id) * L.layers + l) * 256;
+            for (int k = 0; k < 256; ++k) {
+                // positive activation: BF16 sign bit clear and not zero; FP32 likewise
+                if (L.bf16) {
+                    uint16_t v;
+                    std::memcpy(&v, a.data() + (i * 256 + k) * 2, 2);
+                    o[k] = (v & 0x8000u) == 0 && (v & 0x7fffu) != 0;
+                } else {
+                    float v;
+                    std::memcpy(&v, a.data() + (i * 256 + k) * 4, 4);
+                    o[k] = v > 0.0f;
+                }
+            }
+        }
+    }
+    return SWF_OK;
+}
+
 swf_status swf_debug_rects(swf_ctx* h, int32_t* rects, uint64_t capacity) {
     Ctx* c = reinterpret_cast<Ctx*>(h);
     CTX_GUARD(c);

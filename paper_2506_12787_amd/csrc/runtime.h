@@ -139,6 +139,13 @@ struct Ctx {
     // bounded, the oldest forgotten first
     std::map<const void*, AuxTag> aux_tags;
     bool last_bwd_reused = false;  // the last backward took the forward's kept records and lists
+    // the last backward that ran the MLP backward: its hidden activations stay in ws.act (layer-major rows of
+    // 256 per pair, BF16 or FP32)
+    struct {
+        bool valid = false;
+        int scene = -1, B = 0, n = 0, layers = 0;
+        bool bf16 = false;
+    } last_mlp_bwd;
     std::vector<const void*> aux_order;
     void tag_aux(const void* aux, const AuxTag& t);
 

@@ -98,3 +98,78 @@ def golden_pixel(px: dict) -> tuple:
 
 def golden_scene(case: dict) -> dict:
     return {k: np.asarray(v, np.float32) for k, v in case["gaussians"].items()}
+
+
+# ---------------------------------------------------------------------------
+# Gradient checks with derived componentwise bounds (the GPU backward against
+# the oracle's FP64 analytic gradient, Sec. 3.2 blending rule differentiated
+# with decisions held). The unit roundoffs: FP32 2^-24, BF16 operands 2^-8.
+U32, U16 = 2.0 ** -24, 2.0 ** -8
+
+
+def unflagged_weights(scene: M.Scene, deltas, seed, pix_per_query=None):
+    """One weight array of H*W per query: random normal weights on (sampled, or
+    all) pixels whose every decision, for these residuals (None: static), is
+    clear of its threshold; zero elsewhere. Returns (weights, kept pixels)."""
+    H, W = scene.H, scene.W
+    rng = np.random.default_rng(seed)
+    order = M.depth_order(scene.depth)
+    out, kept = [], 0
+    for d in deltas:
+        idx = (rng.choice(H * W, pix_per_query, replace=False) if pix_per_query else np.arange(H * W))
+        px, py = (idx % W).astype(np.int32), (idx // W).astype(np.int32)
+        res = M.composite(M.gaussians_for_raster(M.deform(scene, d), scene.depth), order, px, py)
+        ok = idx[res.nflags == 0]
+        w = np.zeros(H * W)
+        w[ok] = rng.normal(0, 1, len(ok))
+        out.append(w)
+        kept += len(ok)
+    return out, kept
+
+
+def gradient_bound_factors(ref: dict, n_layers: int, pairs: int, bf16: bool):
+    """(c_r, c_mlp): bound = c_r * magnitude sum of the compositing and covariance
+    part, c_mlp * magnitude sum of the network's part.
+      c_r = (3 m + 32) u32, m the longest composited run at a weighted pixel (the
+          replay divides T by (1 - alpha) once per entry, the forward multiplied
+          once per entry; 32 covers q, exp and the chain);
+      c_mlp = 3 (L + 1) u + L K u32 + 4 sqrt(P) u32 + c_r, u the unit roundoff of
+          the network's operands, K = 256 (FP32 accumulation inside each
+          product), P pairs summed per weight (blocked FP32 sums)."""
+    m = ref["replay"]
+    c_r = (3 * m + 32) * U32
+    c_mlp = 3 * (n_layers + 1) * (U16 if bf16 else U32) + n_layers * 256 * U32 + 4 * np.sqrt(pairs) * U32 + c_r
+    return c_r, c_mlp
+
+
+def within_bound(name, got, ref, bound):
+    """Worst componentwise |got - ref| / bound (printed)."""
+    got = np.asarray(got, np.float64)
+    err = np.abs(got - ref)
+    scale = max(float(np.abs(ref).max()), 1e-300)
+    ratio = float((err / np.maximum(bound, 1e-300)).max())
+    print(f"  {name}: normwise err {err.max() / scale:.2e}, worst err / bound {ratio:.3f}", flush=True)
+    return ratio
+
+
+def check_gradients(got: dict, ref: dict, params, n_layers: int, pairs: int, bf16: bool):
+    """Every component of every block within its derived bound: the rounding
+    terms above plus the oracle's allowance for the network's decisions and
+    operands (W_flip, b_flip, pe_flip; with the implementation's ReLU pattern
+    held only the operand differences within binary32 slack remain)."""
+    assert not ref["flagged"].any()
+    c_r, c_mlp = gradient_bound_factors(ref, n_layers, pairs, bf16)
+    print(f"  longest run {ref['replay']}: bound factors {c_r:.2e} / {c_mlp:.2e}", flush=True)
+    worst = {}
+    for j, k in enumerate(params):
+        bound = c_r * ref["base_abs"][:, j]
+        if j < 2 and n_layers:
+            bound = bound + c_mlp * ref["pe_abs"][:, j] + ref["pe_flip"][:, j]
+        worst[k] = within_bound(k, got[k], ref["base"][:, j], bound + 1e-300)
+    for l in range(n_layers):
+        worst[f"W{l}"] = within_bound(f"W{l}", got["weight"][l], ref["W"][l],
+                                      c_mlp * ref["W_abs"][l] + ref["W_flip"][l])
+        worst[f"b{l}"] = within_bound(f"b{l}", got["bias"][l], ref["b"][l], c_mlp * ref["b_abs"][l] + ref["b_flip"][l])
+    bad = {k: v for k, v in worst.items() if not v <= 1.0}
+    assert not bad, bad
+    return worst

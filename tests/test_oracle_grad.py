@@ -187,3 +187,59 @@ def test_residual_override_reproduces_the_network():
     l1, r1 = G.loss_and_grad(s, mlp, txs, targets, deltas=d)
     assert l0 == l1
     np.testing.assert_allclose(r0["base"], r1["base"], rtol=1e-12, atol=1e-15 * np.abs(r0["base"]).max())
+
+
+def _own_pattern(s, mlp, txs):
+    xm = M.posenc(M.normalize_mean(s.mx, s.my, s.H, s.W), M.MEAN_BANDS)
+    out = []
+    for tx in txs:
+        xs = M.posenc(M.normalize_tx(tx, M.DEFAULT_ROOM), M.TX_BANDS)
+        _, pres, _ = M.mlp_forward(xm, xs, mlp)
+        out.append([p > 0 for p in pres])
+    return out
+
+
+def test_held_relu_pattern_of_the_network_itself_changes_nothing():
+    # Holding the network's own ReLU decisions reproduces the gradient exactly, and a held pattern can only shrink
+    # the allowance for decisions (no unit may take the other one).
+    s, mlp, txs, _ = _problem(n=120, B=2)
+    rng = np.random.default_rng(8)
+    w = [rng.normal(0, 1, s.H * s.W) * (rng.uniform(0, 1, s.H * s.W) < 0.3) for _ in txs]
+    _, r0 = G.loss_and_grad(s, mlp, txs, None, pixel_weights=w, bounds=True)
+    _, r1 = G.loss_and_grad(s, mlp, txs, None, pixel_weights=w, bounds=True, relu_masks=_own_pattern(s, mlp, txs))
+    # (up to the order in which the compositor's threads add their partial sums)
+    np.testing.assert_allclose(r1["base"], r0["base"], rtol=1e-12, atol=1e-15 * np.abs(r0["base"]).max())
+    for l in range(mlp.n_layers):
+        np.testing.assert_allclose(r1["W"][l], r0["W"][l], rtol=1e-12, atol=1e-15 * np.abs(r0["W"][l]).max())
+        assert np.all(r1["W_flip"][l] <= r0["W_flip"][l] * (1 + 1e-9) + 1e-15 * r0["W_abs"][l].max())
+
+
+def test_decision_allowance_covers_a_flipped_unit():
+    # A hidden unit whose pre-activation is set within its binary32 slack of zero (by its bias, for one query and
+    # Gaussian) may take the other decision: the gradient with that one decision flipped (the pattern held) differs
+    # from the network's own by no more than the allowance the oracle gives for its decisions; with the decision
+    # held both ways, the allowance has no such term.
+    s, mlp, txs, _ = _problem(n=60, B=1, hidden=64)
+    xm = M.posenc(M.normalize_mean(s.mx, s.my, s.H, s.W), M.MEAN_BANDS)
+    xs = M.posenc(M.normalize_tx(txs[0], M.DEFAULT_ROOM), M.TX_BANDS)
+    _, pres, _ = M.mlp_forward(xm, xs, mlp)
+    l, k = 1, 5                                   # second hidden layer, unit 5
+    p = int(np.argmax(np.abs(pres[l][:, k]) > 0))  # a Gaussian whose unit is not exactly zero
+    mlp.b[l][k] -= pres[l][p, k] - 1e-12 * (1.0 + abs(pres[l][p, k]))  # its pre-activation now just above zero
+    rng = np.random.default_rng(9)
+    w = [rng.normal(0, 1, s.H * s.W)]
+    own = _own_pattern(s, mlp, txs)
+    assert own[0][l][p, k]
+    flipped = [[m.copy() for m in own[0]]]
+    flipped[0][l][p, k] = False
+    _, r0 = G.loss_and_grad(s, mlp, txs, None, pixel_weights=w, bounds=True)
+    _, r1 = G.loss_and_grad(s, mlp, txs, None, pixel_weights=w, bounds=True, relu_masks=flipped)
+    moved = 0.0
+    for j in range(mlp.n_layers):
+        diff = np.abs(r1["W"][j] - r0["W"][j])
+        moved = max(moved, float(diff.max()))
+        assert np.all(diff <= r0["W_flip"][j] * (1 + 1e-9) + 1e-15 * r0["W_abs"][j].max()), j
+        assert np.all(np.abs(r1["b"][j] - r0["b"][j]) <= r0["b_flip"][j] * (1 + 1e-9) + 1e-15 * r0["b_abs"][j].max())
+    assert moved > 0.0  # the flip changed the gradient, so the allowance was exercised
+    _, r2 = G.loss_and_grad(s, mlp, txs, None, pixel_weights=w, bounds=True, relu_masks=own)
+    assert r2["W_flip"][l - 1][k].max() < r0["W_flip"][l - 1][k].max()
