@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "spectra/s at N=100k, 90x360 (batched vs plain); p50/p99 query latency us"
 FLOP_PER_PAIR = 2 * (26 * 256 + 3 * 256 * 256 + 256 * 7)  # MLP per (query, Gaussian) pair
-PEAK = {"bf16": 2500.0, "fp32": 157.3}  # dense TFLOP/s (MFMA bf16; fp32 vector incl. packed)
+PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp32_mfma": 157.3}  # dense TFLOP/s: MFMA bf16, fp32 (vector incl. packed),
+# fp32 MFMA
 FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # FP32 FMA TFLOP/s without packed instructions
 HBM_PEAK_GBS = 8000.0
 # FP32 lane-operations per second without FMA doubling or packing: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
@@ -860,12 +861,13 @@ def bench_paper(a):
                       "height": H, "width": W, "batch": Bq},
            "stages_ms_per_step": st,
            "latency_us": {"batch_p50": 1e3 * pct(ms, 50), "batch_p99": 1e3 * pct(ms, 99)},
-           "roofline": {"kernel": "paper_mlp_kernel (FP32 MLP + deform + preprocess)", "bound": "alu",
-                        "achieved": flops / (mlp_ms * 1e-3) / 1e12, "peak": FP32_VALU_PEAK, "unit": "TFLOP/s",
-                        "frac": flops / (mlp_ms * 1e-3) / 1e12 / FP32_VALU_PEAK, "traffic": None,
-                        "flop_per_pair": flop_pair, "avg_launch_ms": mlp_ms,
-                        "note": "algorithmic FLOPs of the unpadded 156-wide layers; the kernel pads to 160 (and the "
-                                "skip layers' inputs to 256)"}}
+           "roofline": {"kernel": "paper_mlp_kernel (FP32 MLP on v_mfma_f32_16x16x4_f32 + deform + preprocess)",
+                        "bound": "mfma", "achieved": flops / (mlp_ms * 1e-3) / 1e12, "peak": PEAK["fp32_mfma"],
+                        "unit": "TFLOP/s", "frac": flops / (mlp_ms * 1e-3) / 1e12 / PEAK["fp32_mfma"],
+                        "traffic": None, "flop_per_pair": flop_pair, "avg_launch_ms": mlp_ms,
+                        "note": "algorithmic FLOPs of the unpadded 156-wide layers (the kernel pads the widths to "
+                                "160 and the inputs to 96: 6% more); FP32 operands and accumulation, the paper's "
+                                "precision"}}
     # plain: one query per launch
     o1 = torch.empty((1, H, W), device="cuda")
     for i in range(2):

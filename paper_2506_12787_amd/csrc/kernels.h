@@ -37,7 +37,6 @@ struct DevScene {
     float* pfeat = nullptr;
     float *pw[9] = {}, *pb[9] = {};
     float *pwt[9] = {}, *pbt[9] = {};
-    int pK[8] = {};
 };
 
 // The paper's model (paper.hip): positional encoding bands, layer sizes and
@@ -73,11 +72,10 @@ struct PaperArgs {
     const float *l1, *l2, *l3, *att, *pre, *pim;
     const float* feat;  // [N][48] centre features
     const float* txf;   // [B][48] position features
-    const float* wt[kPaperLayers];
-    const float* bt[kPaperLayers];
-    int K[kPaperLayers];
-    const float* wo;
-    const float* bo;
+    const float* wt[kPaperLayers];  // fragment-major MFMA operands (paper.hip)
+    const float* bt[kPaperLayers];  // biases padded to 160
+    const float* wo;                // output layer, one 16-row tile
+    const float* bo;                // output biases padded to 16
     Records rec;
     float* delta_out;  // [B * N][5] residuals (debug), or null
 };

@@ -173,118 +173,106 @@ __global__ __launch_bounds__(256) void paper_static_kernel(PaperArgs a) {
     write_rec(a.rec, row, o);
 }
 
-// ---- paper MLP, FP32 ----------------------------------------------------------
-// 32 pairs per block, 160 threads: thread (tr, tc) owns rows 4 tr .. 4 tr + 3 and
-// columns 8 tc .. 8 tc + 7 of every 160-wide layer (156 units, 4 zero pads).
-// One LDS row per pair holds [h (160) | x (81 + 15 zero pads)]; layer 1 reads
-// columns 160..255, the plain layers 0..159, the skip layers 0..255 (the
-// input concatenated after the hidden state). Weights are packed in-major per
-// layer with zero rows and columns for every pad, so the pads stay zero
-// through the ReLUs; they stream through LDS in 32-row slabs.
-constexpr int kPR = 32;
-constexpr int kPW = 160;
-constexpr int kPKS = 32;
-constexpr int kPStride = 260;
+// ---- paper MLP, FP32 on the matrix cores --------------------------------------
+// v_mfma_f32_16x16x4_f32 (FP32 products, FP32 accumulation): per layer D = W H
+// with 16 output units x 16 pairs per instruction, K = 4 inputs. A wave holds
+// 2 x 16 pairs; every hidden state and the 81 input features stay in
+// registers as B operands: lane l holds, for chunk c of a layer's input,
+// feature k(c, l / 16) of pair l % 16. The result of output tile t (4 registers
+// per lane: units 16 t + 4 (l / 16) + i, i = 0..3) is, after the ReLU, exactly
+// the next layer's chunks 4 t + i once that layer's weights list their input
+// columns in that order (fragment-major packing on upload, zero rows and
+// columns for every pad: the 156 units are padded to 160, the 81 inputs to
+// 96). A layer reads its input as [h chunks (40) | x chunks (24)] (layer 1: x
+// only; the skip layers 3, 5, 7: both; the others: h only); a fragment of 4
+// chunks is one 16-byte load per lane from the L2-resident weights.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMNB = 2;        // column blocks of 16 pairs per wave
+constexpr int kMWaves = 4;     // waves per block
+constexpr int kHC = 40, kXC = 24;  // chunks of 4 inputs: hidden state, input features
 
-__global__ __launch_bounds__(160, 2) void paper_mlp_kernel(PaperArgs a) {
-    __shared__ __attribute__((aligned(16))) float act[kPR * kPStride];
-    __shared__ __attribute__((aligned(16))) float ws[kPKS * kPW];
-    __shared__ float outv[kPR][kPaperOut + 1];
-    const int tid = threadIdx.x;
-    const int tr = tid / 20, tc = tid % 20;
-    const size_t total = (size_t)a.N * a.B;
-    const size_t row0 = (size_t)blockIdx.x * kPR;
-    // inputs: centre features of the pair's Gaussian, position features of its query
-    for (int i = tid; i < kPR * 96; i += 160) {
-        const int r = i / 96, k = i % 96;
-        const size_t row = row0 + r;
-        float v = 0.0f;
-        if (row < total && k < kPaperCenterFeat + kPaperTxFeat) {
-            const int p = (int)(row % a.N);
-            const int b = (int)(row / a.N);
-            v = k < kPaperCenterFeat ? a.feat[(size_t)p * kPaperFeatStride + k]
-                                     : a.txf[(size_t)b * kPaperFeatStride + (k - kPaperCenterFeat)];
-        }
-        act[r * kPStride + kPW + k] = v;
-    }
-    float acc[4][8];
-    constexpr int kPf = kPKS * kPW / 4 / 160;  // float4 per thread per slab (8)
-    float4 pf[kPf];
-    for (int l = 0; l < kPaperLayers; ++l) {
-        const int k0 = l == 0 ? kPW : 0;
-        const int K = a.K[l];
-        const float4* wsrc = reinterpret_cast<const float4*>(a.wt[l]);
-        __syncthreads();  // inputs / previous layer written
+template <bool kH, bool kX, int kTiles, bool kRelu>
+__device__ __forceinline__ void paper_mfma_layer(const float4* __restrict__ wf, const float* __restrict__ bias,
+                                                 int lane, const float (&hin)[kMNB][kHC],
+                                                 const float (&x)[kMNB][kXC], float (&hout)[kMNB][kHC]) {
+    constexpr int G = (kH ? kHC / 4 : 0) + (kX ? kXC / 4 : 0);  // 16-byte fragments per output tile
 #pragma unroll
-        for (int j = 0; j < kPf; ++j) pf[j] = wsrc[tid + j * 160];
+    for (int t = 0; t < kTiles; ++t) {
+        const float4 b4 = *reinterpret_cast<const float4*>(bias + 16 * t + 4 * (lane >> 4));
+        f32x4 acc[kMNB];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float4* b4 = reinterpret_cast<const float4*>(a.bt[l] + tc * 8);
-            const float4 b0 = b4[0], b1 = b4[1];
-            acc[i][0] = b0.x; acc[i][1] = b0.y; acc[i][2] = b0.z; acc[i][3] = b0.w;
-            acc[i][4] = b1.x; acc[i][5] = b1.y; acc[i][6] = b1.z; acc[i][7] = b1.w;
-        }
-        const int slabs = K / kPKS;
-        for (int sl = 0; sl < slabs; ++sl) {
-            __syncthreads();
+        for (int cb = 0; cb < kMNB; ++cb) acc[cb] = f32x4{b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
-            for (int j = 0; j < kPf; ++j) reinterpret_cast<float4*>(ws)[tid + j * 160] = pf[j];
-            __syncthreads();
-            if (sl + 1 < slabs) {
-                const float4* nsrc = wsrc + (size_t)(sl + 1) * (kPKS * kPW / 4);
+        for (int gq = 0; gq < G; ++gq) {
+            const float4 w = wf[((size_t)t * G + gq) * 64 + lane];
+            const float wv[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-                for (int j = 0; j < kPf; ++j) pf[j] = nsrc[tid + j * 160];
-            }
-            const int kb = k0 + sl * kPKS;
-#pragma unroll 2
-            for (int kk = 0; kk < kPKS; kk += 4) {
-                float4 av[4];
+            for (int j = 0; j < 4; ++j) {
+                const int c = gq * 4 + j;
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    av[i] = *reinterpret_cast<const float4*>(&act[(tr * 4 + i) * kPStride + kb + kk]);
-#pragma unroll
-                for (int k4 = 0; k4 < 4; ++k4) {
-                    const float4 w0 = *reinterpret_cast<const float4*>(&ws[(kk + k4) * kPW + tc * 8]);
-                    const float4 w1 = *reinterpret_cast<const float4*>(&ws[(kk + k4) * kPW + tc * 8 + 4]);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float x = k4 == 0 ? av[i].x : (k4 == 1 ? av[i].y : (k4 == 2 ? av[i].z : av[i].w));
-                        acc[i][0] = fmaf(x, w0.x, acc[i][0]); acc[i][1] = fmaf(x, w0.y, acc[i][1]);
-                        acc[i][2] = fmaf(x, w0.z, acc[i][2]); acc[i][3] = fmaf(x, w0.w, acc[i][3]);
-                        acc[i][4] = fmaf(x, w1.x, acc[i][4]); acc[i][5] = fmaf(x, w1.y, acc[i][5]);
-                        acc[i][6] = fmaf(x, w1.z, acc[i][6]); acc[i][7] = fmaf(x, w1.w, acc[i][7]);
-                    }
+                for (int cb = 0; cb < kMNB; ++cb) {
+                    const float bv = (kH && c < kHC) ? hin[cb][c] : x[cb][c - (kH ? kHC : 0)];
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[j], bv, acc[cb], 0, 0, 0);
                 }
             }
         }
-        __syncthreads();  // every thread is done reading h before it is overwritten
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float4* dst = reinterpret_cast<float4*>(&act[(tr * 4 + i) * kPStride + tc * 8]);
-            dst[0] = make_float4(fmaxf(acc[i][0], 0.f), fmaxf(acc[i][1], 0.f), fmaxf(acc[i][2], 0.f),
-                                 fmaxf(acc[i][3], 0.f));
-            dst[1] = make_float4(fmaxf(acc[i][4], 0.f), fmaxf(acc[i][5], 0.f), fmaxf(acc[i][6], 0.f),
-                                 fmaxf(acc[i][7], 0.f));
+        for (int cb = 0; cb < kMNB; ++cb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) hout[cb][4 * t + i] = kRelu ? fmaxf(acc[cb][i], 0.0f) : acc[cb][i];
+    }
+}
+
+__global__ __launch_bounds__(64 * kMWaves, 2) void paper_mlp_kernel(PaperArgs a) {
+    __shared__ float outv[kMWaves][16 * kMNB][kPaperOutPad];
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const size_t total = (size_t)a.N * a.B;
+    const size_t p0 = ((size_t)blockIdx.x * kMWaves + wave) * (16 * kMNB);
+    if (p0 < total) {  // wave-uniform
+        // input features as B operands: x index 4 c + l / 16 (centre features 0..41, position features 42..80)
+        float x[kMNB][kXC];
+        const int g = lane >> 4;
+#pragma unroll
+        for (int cb = 0; cb < kMNB; ++cb) {
+            const size_t row = p0 + 16 * cb + (lane & 15);
+            const bool in = row < total;
+            const int p = in ? (int)(row % a.N) : 0, b = in ? (int)(row / a.N) : 0;
+#pragma unroll
+            for (int c = 0; c < kXC; ++c) {
+                const int j = 4 * c + g;
+                float v = 0.0f;
+                if (in && j < kPaperCenterFeat + kPaperTxFeat)
+                    v = j < kPaperCenterFeat ? a.feat[(size_t)p * kPaperFeatStride + j]
+                                             : a.txf[(size_t)b * kPaperFeatStride + (j - kPaperCenterFeat)];
+                x[cb][c] = v;
+            }
+        }
+        float hA[kMNB][kHC], hB[kMNB][kHC];
+        const auto W = [&](int l) { return reinterpret_cast<const float4*>(a.wt[l]); };
+        paper_mfma_layer<false, true, 10, true>(W(0), a.bt[0], lane, hB, x, hA);  // layer 1 (hB unused)
+        for (int r = 0; r < 3; ++r) {
+            paper_mfma_layer<true, false, 10, true>(W(1 + 2 * r), a.bt[1 + 2 * r], lane, hA, x, hB);
+            paper_mfma_layer<true, true, 10, true>(W(2 + 2 * r), a.bt[2 + 2 * r], lane, hB, x, hA);  // skip
+        }
+        paper_mfma_layer<true, false, 10, true>(W(7), a.bt[7], lane, hA, x, hB);
+        // output layer: one tile of 16 rows (5 used); lane l holds outputs 4 (l / 16) + i of pair l % 16
+        paper_mfma_layer<true, false, 1, false>(reinterpret_cast<const float4*>(a.wo), a.bo, lane, hB, x, hA);
+        if (g < 2) {
+#pragma unroll
+            for (int cb = 0; cb < kMNB; ++cb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (4 * g + i < kPaperOutPad) outv[wave][16 * cb + (lane & 15)][4 * g + i] = hA[cb][i];
         }
     }
-    // output layer: 5 dot products of length 160 per pair (one per thread)
     __syncthreads();
-    for (int i = tid; i < kPW * kPaperOutPad; i += 160) ws[i] = a.wo[i];
-    __syncthreads();
-    {
-        const int r = tid / kPaperOut, o = tid % kPaperOut;
-        float s = a.bo[o];
-        for (int k = 0; k < kPW; ++k) s = fmaf(act[r * kPStride + k], ws[k * kPaperOutPad + o], s);
-        outv[r][o] = s;
-    }
-    __syncthreads();
-    if (tid < kPR) {
-        const size_t row = row0 + tid;
+    if (p0 < total && lane < 16 * kMNB) {
+        const size_t row = p0 + lane;
         if (row < total) {
             const int p = (int)(row % a.N);
             float d[kPaperOut];
 #pragma unroll
-            for (int k = 0; k < kPaperOut; ++k) d[k] = outv[tid][k];
+            for (int k = 0; k < kPaperOut; ++k) d[k] = outv[wave][lane][k];
             if (a.delta_out)
 #pragma unroll
                 for (int k = 0; k < kPaperOut; ++k) a.delta_out[row * kPaperOut + k] = d[k];
@@ -416,7 +404,6 @@ static PaperArgs paper_args(const DevScene& d, int B, const Grid& g, const Recor
     for (int l = 0; l < kPaperLayers; ++l) {
         a.wt[l] = d.pwt[l];
         a.bt[l] = d.pbt[l];
-        a.K[l] = d.pK[l];
     }
     a.wo = d.pwt[kPaperLayers];
     a.bo = d.pbt[kPaperLayers];
@@ -438,7 +425,8 @@ void launch_paper_mlp(const DevScene& d, const float* txf, int B, const Grid& g,
     PaperArgs a = paper_args(d, B, g, r);
     a.txf = txf;
     a.delta_out = delta_out;
-    paper_mlp_kernel<<<(unsigned)((total + kPR - 1) / kPR), 160, 0, st>>>(a);
+    const size_t per_block = (size_t)kMWaves * 16 * kMNB;
+    paper_mlp_kernel<<<(unsigned)((total + per_block - 1) / per_block), 64 * kMWaves, 0, st>>>(a);
 }
 
 void launch_gmm_blend(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g, float* out,

@@ -354,34 +354,35 @@ swf_status Ctx::upload_paper_scene(const swf_paper_gaussians* g, const swf_paper
             st = upload(this, s, &d.pw[l], Wm[l].data(), Wm[l].size());
             if (!st) st = upload(this, s, &d.pb[l], Bm[l].data(), Bm[l].size());
         }
-        for (int l = 0; l < kPaperLayers && !st; ++l) {
-            const bool skip = l == 2 || l == 4 || l == 6;  // layers 3, 5, 7 (1-based)
-            const int K = l == 0 ? 96 : (skip ? 256 : 160);
-            d.pK[l] = K;
-            std::vector<float> t((size_t)K * 160, 0.0f), b(160, 0.0f);
-            for (int j = 0; j < kPaperWidth; ++j) {
-                b[j] = Bm[l][j];
-                for (int i = 0; i < kIn[l]; ++i) {
-                    // input column i of the layer -> packed row
-                    int r;
-                    if (l == 0)
-                        r = i;                                     // x[i] at kernel column 160 + i
-                    else
-                        r = i < kPaperWidth ? i : 160 + (i - kPaperWidth);  // h[i], then x[i - 156]
-                    t[(size_t)r * 160 + j] = Wm[l][(size_t)j * kIn[l] + i];
-                }
-            }
+        // MFMA operands, fragment-major (paper.hip): per layer, output tile t (16 units), fragment q of 4 input
+        // chunks, lane l, chunk j: W[unit 16 t + l % 16][input of chunk 4 q + j for lane group l / 16]. A layer's
+        // chunks are [h (40) | x (24)] as it takes them; h chunk c holds the previous layer's unit
+        // 16 (c / 4) + 4 g + c % 4 (g = l / 16), x chunk c the input feature 4 c + g. Pads are zero.
+        for (int l = 0; l <= kPaperLayers && !st; ++l) {
+            const bool out_layer = l == kPaperLayers;
+            const bool hasH = l != 0, hasX = l == 0 || l == 2 || l == 4 || l == 6;
+            const int G = (hasH ? 10 : 0) + (hasX ? 6 : 0), tiles = out_layer ? 1 : 10;
+            const int units = out_layer ? kPaperOut : kPaperWidth;
+            std::vector<float> t((size_t)tiles * G * 64 * 4, 0.0f), b((size_t)tiles * 16, 0.0f);
+            for (int tt = 0; tt < tiles; ++tt)
+                for (int q = 0; q < G; ++q)
+                    for (int ln = 0; ln < 64; ++ln)
+                        for (int j = 0; j < 4; ++j) {
+                            const int unit = 16 * tt + ln % 16, g = ln / 16, c = 4 * q + j;
+                            if (unit >= units) continue;
+                            int col = -1;  // the paper layer's input column
+                            if (hasH && c < 40) {
+                                const int f = 16 * (c / 4) + 4 * g + c % 4;
+                                if (f < kPaperWidth) col = f;
+                            } else {
+                                const int xf = 4 * (c - (hasH ? 40 : 0)) + g;
+                                if (xf < kIn[0]) col = l == 0 ? xf : kPaperWidth + xf;
+                            }
+                            if (col >= 0) t[(((size_t)tt * G + q) * 64 + ln) * 4 + j] = Wm[l][(size_t)unit * kIn[l] + col];
+                        }
+            for (int u = 0; u < units; ++u) b[u] = Bm[l][u];
             st = upload(this, s, &d.pwt[l], t.data(), t.size());
             if (!st) st = upload(this, s, &d.pbt[l], b.data(), b.size());
-        }
-        if (!st) {
-            std::vector<float> t((size_t)160 * kPaperOutPad, 0.0f), b(kPaperOutPad, 0.0f);
-            for (int o = 0; o < kPaperOut; ++o) {
-                b[o] = Bm[8][o];
-                for (int k = 0; k < kPaperWidth; ++k) t[(size_t)k * kPaperOutPad + o] = Wm[8][(size_t)o * 156 + k];
-            }
-            st = upload(this, s, &d.pwt[8], t.data(), t.size());
-            if (!st) st = upload(this, s, &d.pbt[8], b.data(), b.size());
         }
     }
     if (!st) {
