@@ -1000,6 +1000,8 @@ def main():
                   "frac": work["evaluations"] * BLEND_OPS_PER_EVAL / (blend_ms * 1e-3) / VALU_PEAK_LANE_OPS,
                   "evaluations": work["evaluations"], "ops_per_evaluation": BLEND_OPS_PER_EVAL, "ms": blend_ms,
                   "staged_records": work["staged"],
+                  "executed_lane_evaluations": work["executed"],
+                  "executed_over_needed": work["executed"] / max(work["evaluations"], 1),
                   "gather_GBs": work["staged"] * 44 / (blend_ms * 1e-3) / 1e9},
     }
 

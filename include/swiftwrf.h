@@ -476,6 +476,14 @@ swf_status swf_debug_relu_pattern(swf_ctx *ctx, uint8_t *pattern, uint64_t capac
  * records staged into LDS, and the number of list entries. Synchronous; any
  * output may be NULL. */
 swf_status swf_debug_blend_work(swf_ctx *ctx, uint64_t *evaluations, uint64_t *staged, uint64_t *n_entries);
+/* swf_debug_blend_executed: the lane-evaluations the blend kernel of the last
+ * swf_render executes on 16 x 16 tiles (every lane of a wave evaluates each
+ * entry its wave visits: the entries that reach its 8 x 8 quadrant, in groups
+ * of 8, until all its pixels have ended), counted by the same walk without
+ * writing a spectrum; set against the evaluations swf_debug_blend_work reports
+ * as needed, the share of the blend's vector work that is the branch-free
+ * walk's no-ops. 0 for 8 x 8 tiles. Synchronous. */
+swf_status swf_debug_blend_executed(swf_ctx *ctx, uint64_t *lane_evaluations);
 /* swf_measure_peaks: on-device peaks for roofline accounting (not part of the
  * method): the rates this GPU sustains in plain loops of BF16 MFMA
  * (v_mfma_f32_16x16x32_bf16 chains held in registers, TFLOP/s), FP32 FMA

@@ -130,6 +130,7 @@ def lib():
             "swf_debug_deform": [P, I32, P, I32, I32, P, P],
             "swf_debug_keys": [P, P, P, P, P, P, P, ctypes.c_uint64],
             "swf_debug_blend_work": [P, P, P, P],
+            "swf_debug_blend_executed": [P, P],
             "swf_debug_rects": [P, P, ctypes.c_uint64],
             "swf_debug_relu_pattern": [P, P, ctypes.c_uint64],
             "swf_last_device_status": [P, P],
@@ -552,9 +553,10 @@ class Context:
     def blend_work(self):
         """Work of the last render's blend: (pixel, entry) evaluations inside the 3-sigma cutoff before the pixel
         ends, staged records, list entries."""
-        ev, st, ne = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        ev, st, ne, ex = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
         self._check(self._L.swf_debug_blend_work(self._h, ctypes.byref(ev), ctypes.byref(st), ctypes.byref(ne)))
-        return dict(evaluations=ev.value, staged=st.value, entries=ne.value)
+        self._check(self._L.swf_debug_blend_executed(self._h, ctypes.byref(ex)))
+        return dict(evaluations=ev.value, staged=st.value, entries=ne.value, executed=ex.value)
 
     def device_status(self):
         """What the device saw during the last render: flags (DEV_* bits), exact-size re-renders, pairs, culled

@@ -28,7 +28,12 @@ __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & 63u; }
 // kMix: the workgroup's global tile belongs to a query of a mixed batch (its
 // query, grid and output offset come from the batch's tables; workgroups past
 // the batch's tiles exit).
-template <int TILE, bool kCount = false, bool kAux = true, bool kWrap = false, bool kMix = false>
+//
+// kVisit: the rendering walk itself (culling, termination, groups of 8), but
+// instead of writing the spectrum it adds to work[2] the lane-evaluations it
+// executes (every lane of a wave evaluates each entry the wave visits), for the
+// ratio of executed to needed evaluations.
+template <int TILE, bool kCount = false, bool kAux = true, bool kWrap = false, bool kMix = false, bool kVisit = false>
 __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* __restrict__ ranges,
                                                                     const uint32_t* __restrict__ vals,
                                                                     const float4* __restrict__ geo,
@@ -97,7 +102,7 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     float T = 1.0f, C = 0.0f;
     uint32_t last = 0;
     bool done = !inside;
-    uint32_t evals = 0, staged = 0;
+    uint32_t evals = 0, staged = 0, visits = 0;
 
     for (uint32_t start = rg.x; start < rg.y; start += kN) {
         if (__syncthreads_count(done) == kN) break;
@@ -148,6 +153,7 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
             __builtin_amdgcn_wave_barrier();
             for (int j0 = 0; j0 < nlist; j0 += kUnroll) {
                 if (__all(done)) break;
+                if (kVisit) visits += kUnroll;
                 const uint4 ja = *reinterpret_cast<const uint4*>(idx + j0);  // 8 record offsets
                 const uint4 jb = *reinterpret_cast<const uint4*>(idx + j0 + 4);
                 const uint32_t jw[8] = {ja.x, ja.y, ja.z, ja.w, jb.x, jb.y, jb.z, jb.w};
@@ -200,6 +206,15 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
             }
         }
     }
+    if (kVisit) {
+        __shared__ unsigned long long s_vi;
+        if (threadIdx.x == 0) s_vi = 0;
+        __syncthreads();
+        atomicAdd(&s_vi, (unsigned long long)visits);
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&work[2], s_vi);
+        return;
+    }
     if (kCount) {
         __shared__ unsigned long long s_ev;
         if (threadIdx.x == 0) s_ev = 0;
@@ -222,14 +237,14 @@ __global__ __launch_bounds__(TILE* TILE) void blend_forward_kernel(const uint2* 
     }
 }
 
-template <int TILE, bool kCount, bool kAux>
+template <int TILE, bool kCount, bool kAux, bool kVisit = false>
 void blend_launch(const uint2* ranges, const uint32_t* vals, const Records& r, unsigned blocks, const Grid& g,
                   float* out, float* aux_T, uint32_t* aux_last, unsigned long long* work, hipStream_t st) {
     if (g.wrap)
-        blend_forward_kernel<TILE, kCount, kAux, true><<<blocks, TILE * TILE, 0, st>>>(
+        blend_forward_kernel<TILE, kCount, kAux, true, false, kVisit><<<blocks, TILE * TILE, 0, st>>>(
             ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles, out, aux_T, aux_last, work);
     else
-        blend_forward_kernel<TILE, kCount, kAux, false><<<blocks, TILE * TILE, 0, st>>>(
+        blend_forward_kernel<TILE, kCount, kAux, false, false, kVisit><<<blocks, TILE * TILE, 0, st>>>(
             ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles, out, aux_T, aux_last, work);
 }
 
@@ -246,10 +261,13 @@ void launch_blend_work(const uint2* ranges, const uint32_t* vals, const Records&
                        unsigned long long* work, hipStream_t st) {
     const unsigned blocks = (unsigned)(B * g.tiles);
     if (!blocks) return;
-    if (g.tile == 8)
+    if (g.tile == 8) {
         blend_launch<8, true, true>(ranges, vals, r, blocks, g, nullptr, nullptr, nullptr, work, st);
-    else
+    } else {
         blend_launch<16, true, true>(ranges, vals, r, blocks, g, nullptr, nullptr, nullptr, work, st);
+        // the walk the spectrum render executes (without the blend state, as a plain render)
+        blend_launch<16, false, false, true>(ranges, vals, r, blocks, g, nullptr, nullptr, nullptr, work, st);
+    }
 }
 
 void launch_blend_forward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,

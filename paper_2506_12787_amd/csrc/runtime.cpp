@@ -1474,14 +1474,26 @@ swf_status swf_debug_blend_work(swf_ctx* h, uint64_t* evaluations, uint64_t* sta
     if (n_entries) *n_entries = L.n_keys;
     swf_status s = c->hip(hipDeviceSynchronize(), "sync");
     if (s) return s;
-    if ((s = c->ws.work.reserve(c, 2 * sizeof(unsigned long long), nullptr))) return s;
+    if ((s = c->ws.work.reserve(c, 3 * sizeof(unsigned long long), nullptr))) return s;
     unsigned long long* d = (unsigned long long*)c->ws.work.ptr;
-    launch_clear_u32((uint32_t*)d, 4, nullptr);
+    launch_clear_u32((uint32_t*)d, 6, nullptr);
     launch_blend_work((const uint2*)c->ws.ranges.ptr, L.vals, c->ws.rec, L.B, L.grid, d, nullptr);
-    unsigned long long hw[2] = {0, 0};
+    unsigned long long hw[3] = {0, 0, 0};
     if ((s = c->hip(hipMemcpy(hw, d, sizeof(hw), hipMemcpyDeviceToHost), "D2H work"))) return s;
     if (evaluations) *evaluations = hw[0];
     if (staged) *staged = hw[1];
+    c->last_blend_executed = hw[2];
+    return SWF_OK;
+}
+
+swf_status swf_debug_blend_executed(swf_ctx* h, uint64_t* lane_evaluations) {
+    Ctx* c = reinterpret_cast<Ctx*>(h);
+    CTX_GUARD(c);
+    if (!lane_evaluations) return c->fail(SWF_E_INVALID, "lane_evaluations is NULL");
+    uint64_t ev = 0, st = 0, ne = 0;
+    swf_status s = swf_debug_blend_work(h, &ev, &st, &ne);
+    if (s) return s;
+    *lane_evaluations = c->last_blend_executed;
     return SWF_OK;
 }
 

@@ -139,6 +139,7 @@ struct Ctx {
     // bounded, the oldest forgotten first
     std::map<const void*, AuxTag> aux_tags;
     bool last_bwd_reused = false;  // the last backward took the forward's kept records and lists
+    uint64_t last_blend_executed = 0;  // lane-evaluations of the last blend walk counted (swf_debug_blend_executed)
     // the last backward that ran the MLP backward: its hidden activations stay in ws.act (layer-major rows of
     // 256 per pair, BF16 or FP32)
     struct {

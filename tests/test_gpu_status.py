@@ -153,3 +153,23 @@ def test_batch_rendered_in_chunks_beyond_the_list_limit():
         tiny.render(sid, tx, flags=B.MLP_BF16)
     tiny.close()
     small.close()
+
+
+def test_blend_work_counts_are_consistent():
+    # the blend's work counts for roofline accounting: every evaluation the rule needs is executed by its lane, so
+    # the executed lane-evaluations of the culled branch-free walk are at least the needed ones; every list entry is
+    # staged at most once per tile walk
+    import torch
+    from paper_2506_12787_amd import binding as B
+    from paper_2506_12787_amd import synth
+    ctx = B.Context(0)
+    H, W, n, nb = 90, 360, 20_000, 4
+    sid = ctx.upload_scene(synth.gaussians(n, H, W, seed=640), H, W, mlp=synth.mlp_weights(seed=3640))
+    tx = torch.from_numpy(synth.tx_positions(nb, seed=740)).cuda()
+    ctx.render(sid, tx, flags=B.MLP_BF16)
+    w = ctx.blend_work()
+    print(w, f"executed / needed {w['executed'] / max(w['evaluations'], 1):.2f}")
+    assert 0 < w["evaluations"] <= w["executed"]
+    assert w["staged"] <= w["entries"]
+    assert w["executed"] % 8 == 0
+    ctx.close()
