@@ -26,9 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "spectra/s at N=100k, 90x360 (batched vs plain); p50/p99 query latency us"
 FLOP_PER_PAIR = 2 * (26 * 256 + 3 * 256 * 256 + 256 * 7)  # MLP per (query, Gaussian) pair
-PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp32_mfma": 157.3}  # dense TFLOP/s: MFMA bf16, fp32 (vector incl. packed),
-# fp32 MFMA
-FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # FP32 FMA TFLOP/s without packed instructions
+PEAK = {"bf16": 2500.0, "fp32": 157.3}  # dense MFMA TFLOP/s: BF16, FP32 (v_mfma_f32_16x16x4_f32)
+FP32_VALU_PEAK = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # FP32 FMA TFLOP/s on the vector ALUs without packed instructions
 HBM_PEAK_GBS = 8000.0
 # FP32 lane-operations per second without FMA doubling or packing: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
@@ -862,8 +861,8 @@ def bench_paper(a):
            "stages_ms_per_step": st,
            "latency_us": {"batch_p50": 1e3 * pct(ms, 50), "batch_p99": 1e3 * pct(ms, 99)},
            "roofline": {"kernel": "paper_mlp_kernel (FP32 MLP on v_mfma_f32_16x16x4_f32 + deform + preprocess)",
-                        "bound": "mfma", "achieved": flops / (mlp_ms * 1e-3) / 1e12, "peak": PEAK["fp32_mfma"],
-                        "unit": "TFLOP/s", "frac": flops / (mlp_ms * 1e-3) / 1e12 / PEAK["fp32_mfma"],
+                        "bound": "mfma", "achieved": flops / (mlp_ms * 1e-3) / 1e12, "peak": PEAK["fp32"],
+                        "unit": "TFLOP/s", "frac": flops / (mlp_ms * 1e-3) / 1e12 / PEAK["fp32"],
                         "traffic": None, "flop_per_pair": flop_pair, "avg_launch_ms": mlp_ms,
                         "note": "algorithmic FLOPs of the unpadded 156-wide layers (the kernel pads the widths to "
                                 "160 and the inputs to 96: 6% more); FP32 operands and accumulation, the paper's "
@@ -966,7 +965,7 @@ def main():
     flops = float(FLOP_PER_PAIR) * N * Bq
     achieved = flops / (avg_mlp_ms * 1e-3) / 1e12
     peak = PEAK[a.mlp]
-    roofline = {"kernel": f"mlp_{a.mlp}_deform_preprocess", "bound": "mfma" if a.mlp == "bf16" else "alu",
+    roofline = {"kernel": f"mlp_{a.mlp}_deform_preprocess", "bound": "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(a) if a.mlp == "bf16" else None,
                 "algorithmic_bytes_per_launch": MLP_ALGO_BYTES_PER_PAIR * N * Bq,
@@ -1044,12 +1043,9 @@ def main():
         rec["fp32_batched"] = {
             "value": v32, "unit": "spectra/s", "dtype": "fp32", "batch": Bq, "steps": nb32 - 1,
             "ms_per_step": 1e3 * el32 / (nb32 - 1), "stages_ms_per_step": st32,
-            "roofline": {"kernel": "mlp_fp32_deform_preprocess", "bound": "alu", "achieved": ach32,
-                         "peak": FP32_VALU_PEAK, "unit": "TFLOP/s", "frac": ach32 / FP32_VALU_PEAK,
-                         "peak_packed": PEAK["fp32"], "frac_of_packed": ach32 / PEAK["fp32"],
-                         "avg_launch_ms": mlp32, "flop_per_launch": flops,
-                         "note": "FP32 FMA without packed FP32 instructions (disabled in this build): 256 CUs x 4 "
-                                 "SIMDs x 16 lanes x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s; 157.3 is the packed figure"}}
+            "roofline": {"kernel": "mlp_fp32_deform_preprocess", "bound": "mfma", "achieved": ach32,
+                         "peak": PEAK["fp32"], "unit": "TFLOP/s", "frac": ach32 / PEAK["fp32"],
+                         "avg_launch_ms": mlp32, "flop_per_launch": flops}}
         rec["bf16_over_fp32_batched"] = value / v32
     if not a.quick:
         # plain one-query-per-launch FP32 path

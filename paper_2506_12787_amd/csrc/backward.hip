@@ -311,43 +311,6 @@ __global__ void base_reduce_kernel(const float* __restrict__ dbase, const float*
         if (out.p[k]) out.p[k][id] = s[k];
 }
 
-// ---- MLP backward helpers (the GEMMs run in rocBLAS) --------------------------
-// act0[p][k] = ReLU(Pm[p mod N][k] + qs[p / N][k]): layer-1 activations from
-// the per-Gaussian mean part and the per-query TX part (with the bias)
-__global__ void layer1_act_kernel(const float* __restrict__ Pm, const float* __restrict__ qs, int N, int64_t P,
-                                  float* __restrict__ act) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * 64) return;
-    const int64_t p = i >> 6;
-    const int k = (int)(i & 63) * 4;
-    const int64_t q = p / N, n = p - q * N;
-    const float4 a = *reinterpret_cast<const float4*>(Pm + n * 256 + k);
-    const float4 b = *reinterpret_cast<const float4*>(qs + q * 256 + k);
-    *reinterpret_cast<float4*>(act + p * 256 + k) =
-        make_float4(fmaxf(a.x + b.x, 0.f), fmaxf(a.y + b.y, 0.f), fmaxf(a.z + b.z, 0.f), fmaxf(a.w + b.w, 0.f));
-}
-
-// z[p][k] = ReLU(z[p][k] + bias[k]) in place (256 columns)
-__global__ void bias_relu_kernel(float* __restrict__ z, const float* __restrict__ bias, int64_t P) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * 64) return;
-    const int k = (int)(i & 63) * 4;
-    float4 v = *reinterpret_cast<float4*>(z + i * 4);
-    const float4 b = *reinterpret_cast<const float4*>(bias + k);
-    v = make_float4(fmaxf(v.x + b.x, 0.f), fmaxf(v.y + b.y, 0.f), fmaxf(v.z + b.z, 0.f), fmaxf(v.w + b.w, 0.f));
-    *reinterpret_cast<float4*>(z + i * 4) = v;
-}
-
-// d[p][k] *= (act[p][k] > 0): back through the ReLU (256 columns)
-__global__ void relu_mask_kernel(float* __restrict__ d, const float* __restrict__ act, int64_t P) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * 64) return;
-    float4 v = *reinterpret_cast<float4*>(d + i * 4);
-    const float4 a = *reinterpret_cast<const float4*>(act + i * 4);
-    v = make_float4(a.x > 0.f ? v.x : 0.f, a.y > 0.f ? v.y : 0.f, a.z > 0.f ? v.z : 0.f, a.w > 0.f ? v.w : 0.f);
-    *reinterpret_cast<float4*>(d + i * 4) = v;
-}
-
 // Column sums of row-major [rows x cols] matrices (one per z, batch stride
 // bs), in two stages: part[z][y][c] over row block y, then out[z][c].
 __global__ __launch_bounds__(256) void colsum_stage1_kernel(const float* __restrict__ A, int64_t rows, int64_t cols,
@@ -473,39 +436,6 @@ __global__ void pe_chain_kernel(const float* __restrict__ dgm, const float* __re
 // ---- BF16 variants (the MLP backward of a BF16 forward) ----------------------
 __device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }  // round to nearest even
 
-// act[p][k] = bf16(ReLU(Pm[p mod N][k] + qs[p / N][k]))
-__global__ void layer1_act_bf16_kernel(const float* __restrict__ Pm, const float* __restrict__ qs, int N, int64_t P,
-                                       __bf16* __restrict__ act) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * 64) return;
-    const int64_t p = i >> 6;
-    const int k = (int)(i & 63) * 4;
-    const int64_t q = p / N, n = p - q * N;
-    const float4 a = *reinterpret_cast<const float4*>(Pm + n * 256 + k);
-    const float4 b = *reinterpret_cast<const float4*>(qs + q * 256 + k);
-    __bf16* o = act + p * 256 + k;
-    o[0] = to_bf16(fmaxf(a.x + b.x, 0.f));
-    o[1] = to_bf16(fmaxf(a.y + b.y, 0.f));
-    o[2] = to_bf16(fmaxf(a.z + b.z, 0.f));
-    o[3] = to_bf16(fmaxf(a.w + b.w, 0.f));
-}
-
-// out[p][k] = bf16(ReLU(z[p][k] + bias[k])): a recomputed hidden layer
-__global__ void bias_relu_bf16_kernel(const float* __restrict__ z, const float* __restrict__ bias, int64_t P,
-                                      __bf16* __restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P * 64) return;
-    const int k = (int)(i & 63) * 4;
-    const float4 v = *reinterpret_cast<const float4*>(z + i * 4);
-    const float4 b = *reinterpret_cast<const float4*>(bias + k);
-    __bf16* o = out + i * 4;
-    o[0] = to_bf16(fmaxf(v.x + b.x, 0.f));
-    o[1] = to_bf16(fmaxf(v.y + b.y, 0.f));
-    o[2] = to_bf16(fmaxf(v.z + b.z, 0.f));
-    o[3] = to_bf16(fmaxf(v.w + b.w, 0.f));
-}
-
-// d[p][k] = [act[p][k] > 0] ? d[p][k] : 0 in place, BF16 d and act (8 per thread)
 // Input gradient of a 256 x 256 layer on BF16 MFMA (v_mfma_f32_16x16x32_bf16,
 // FP32 accumulation): out[p][i] = sum_o dz[p][o] W[o][i] for every pair p, W
 // row-major [o][i] (the layer's [out][in] weights). kF32: FP32 result (the
@@ -925,23 +855,6 @@ __global__ __launch_bounds__(256) void out_bwd_bf16_kernel(const float* __restri
     }
 }
 
-__global__ void relu_mask_inplace_bf16_kernel(__bf16* __restrict__ d, const __bf16* __restrict__ act, int64_t n8) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n8) return;
-    uint4 v = reinterpret_cast<uint4*>(d)[i];
-    const uint4 a = reinterpret_cast<const uint4*>(act)[i];
-    auto m = [](uint32_t x, uint32_t y) {  // per 16-bit half: keep x where the bf16 in y is > 0
-        const uint32_t lo = ((y & 0x8000u) == 0 && (y & 0x7fffu) != 0) ? 0x0000ffffu : 0u;
-        const uint32_t hi = ((y & 0x80000000u) == 0 && (y & 0x7fff0000u) != 0) ? 0xffff0000u : 0u;
-        return x & (lo | hi);
-    };
-    v.x = m(v.x, a.x);
-    v.y = m(v.y, a.y);
-    v.z = m(v.z, a.z);
-    v.w = m(v.w, a.w);
-    reinterpret_cast<uint4*>(d)[i] = v;
-}
-
 // Layer-1 gradient sums of a BF16 backward in one pass over the unmasked FP32
 // gradient z [B][N][256] and the BF16 activations act [B][N][256]: with
 // dz = z * [act > 0], S[n][k] = sum_b dz[b][n][k] (complete: the block owns
@@ -1087,18 +1000,6 @@ void launch_base_reduce(const float* dbase, const float* dmu_pe, const uint32_t*
     if (N > 0) base_reduce_kernel<<<(N + 255) / 256, 256, 0, st>>>(dbase, dmu_pe, perm, B, N, out);
 }
 
-void launch_layer1_act(const float* Pm, const float* qs, int N, int64_t P, float* act, hipStream_t st) {
-    if (P > 0) layer1_act_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(Pm, qs, N, P, act);
-}
-
-void launch_bias_relu(float* z, const float* bias, int64_t P, hipStream_t st) {
-    if (P > 0) bias_relu_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(z, bias, P);
-}
-
-void launch_relu_mask(float* d, const float* act, int64_t P, hipStream_t st) {
-    if (P > 0) relu_mask_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(d, act, P);
-}
-
 int colsum_blocks(int64_t rows) { return (int)std::max<int64_t>(1, std::min<int64_t>(2048, (rows + 255) / 256)); }
 
 namespace {
@@ -1134,22 +1035,6 @@ void launch_fill(float* p, float v, int64_t n, hipStream_t st) {
 
 void launch_pe_chain(const float* dg, const DevScene& s, float* dmu, hipStream_t st) {
     if (s.n > 0) pe_chain_kernel<<<(s.n + 255) / 256, 256, 0, st>>>(dg, s.mx, s.my, s.n, s.W, s.H, dmu);
-}
-
-void launch_layer1_act_bf16(const float* Pm, const float* qs, int N, int64_t P, void* act, hipStream_t st) {
-    if (P > 0)
-        layer1_act_bf16_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(Pm, qs, N, P, (__bf16*)act);
-}
-
-void launch_bias_relu_bf16(const float* z, const float* bias, int64_t P, void* out, hipStream_t st) {
-    if (P > 0) bias_relu_bf16_kernel<<<(unsigned)((P * 64 + 255) / 256), 256, 0, st>>>(z, bias, P, (__bf16*)out);
-}
-
-void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStream_t st) {
-    const int64_t n8 = P * 32;  // 256 columns = 32 groups of 8
-    if (n8 > 0)
-        relu_mask_inplace_bf16_kernel<<<(unsigned)((n8 + 255) / 256), 256, 0, st>>>((__bf16*)d, (const __bf16*)act,
-                                                                                   n8);
 }
 
 void launch_dz_gemm(const void* dz, const void* W, const void* act, int64_t P, void* out, bool f32_out,

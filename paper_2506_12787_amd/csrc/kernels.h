@@ -20,9 +20,7 @@ struct DevScene {
     bool has_mlp = false;
     int hidden = 0, n_hidden = 0, in_dim = 0;
     float *w[8] = {}, *b[8] = {};   // FP32 master, row-major [out][in]
-    float *w1m_t = nullptr;         // [26][hidden]   layer-1 mean part, in-major
-    float *wh_t[8] = {};            // [hidden][hidden] hidden->hidden, in-major
-    float *wo_t = nullptr;          // [hidden][7]
+    float *f32_frag = nullptr;      // FP32 weights in MFMA fragment order (layout below)
     uint16_t *bf_stream = nullptr;  // BF16 weights in MFMA fragment order (16 KiB units)
     uint16_t *bf_mfeat = nullptr;   // [n][32] BF16 gamma(mu_hat), zero padded
     float room_lo[3] = {0, 0, 0}, room_hi[3] = {6, 6, 3};
@@ -38,6 +36,19 @@ struct DevScene {
     float *pw[9] = {}, *pb[9] = {};
     float *pwt[9] = {}, *pbt[9] = {};
 };
+
+// FP32 weights of the deformation MLP in the fragment order of the FP32 MFMA
+// kernel (pe_mlp.hip), one float4 per lane and fragment (16 output units x 4
+// input chunks of 4): layer 1's mean part (16 tiles x 2 fragments, K = 26
+// padded to 32), each hidden -> hidden layer (16 tiles x 16 fragments), the
+// output layer (1 tile x 16 fragments, rows 7..15 zero), then the output bias
+// padded to 16. Built on the device from the FP32 masters (pack.hip).
+constexpr size_t kFragL1 = 16 * 2 * 64 * 4;
+constexpr size_t kFragHidden = 16 * 16 * 64 * 4;
+constexpr size_t kFragOut = 16 * 64 * 4;
+__host__ __device__ inline size_t frag_hidden_at(int L) { return kFragL1 + (size_t)(L - 1) * kFragHidden; }  // L = 1 .. n_hidden - 1
+__host__ __device__ inline size_t frag_out_at(int n_hidden) { return kFragL1 + (size_t)(n_hidden - 1) * kFragHidden; }
+__host__ __device__ inline size_t frag_floats(int n_hidden) { return frag_out_at(n_hidden) + kFragOut + 16; }
 
 // The paper's model (paper.hip): positional encoding bands, layer sizes and
 // padded layouts of its MLP.
@@ -172,6 +183,8 @@ void compute_mean_features_bf16(DevScene& s, hipStream_t st);
 // pack.hip: rebuild the in-major FP32 copies and the BF16 weight stream from the
 // FP32 master weights d.w[] on the device (after a device-side MLP update)
 void launch_pack_mlp(const DevScene& d, hipStream_t st);
+// the fragment-major FP32 copy alone (frag_floats(n_hidden) floats at d.f32_frag)
+void launch_pack_f32_frag(const DevScene& d, hipStream_t st);
 
 // act_out (optional): also store the hidden activations, BF16 [n_hidden][B * N][256] (the backward's operands)
 void launch_mlp_bf16(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
@@ -228,10 +241,15 @@ struct BaseGrads {  // destinations of the 7 base-parameter gradients (device; N
 };
 void launch_base_reduce(const float* dbase, const float* dmu_pe, const uint32_t* perm, int B, int N,
                         const BaseGrads& out, hipStream_t st);
-// MLP backward helpers (the GEMMs themselves run in rocBLAS)
-void launch_layer1_act(const float* Pm, const float* qs, int N, int64_t P, float* act, hipStream_t st);
-void launch_bias_relu(float* z, const float* bias, int64_t P, hipStream_t st);
-void launch_relu_mask(float* d, const float* act, int64_t P, hipStream_t st);
+// gemm.hip: C = op(A) op(B) in FP32 on the matrix cores, row-major (op(A) M x K, op(B) K x N; A / B FP32, or
+// BF16 bits when bf16). mask (optional, leading dimension ldm): C *= [mask > 0]. A small C over a long K is
+// split into gemm_split(M, N, K) K-slices summed in slice order; part then holds gemm_part_floats(M, N, K)
+// floats (unused otherwise).
+int gemm_split(int64_t M, int64_t N, int64_t K);
+size_t gemm_part_floats(int64_t M, int64_t N, int64_t K);
+void launch_gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
+                     int64_t ldb, float* C, int64_t ldc, float* part, hipStream_t st, const float* mask = nullptr,
+                     int64_t ldm = 0, bool bf16 = false);
 void launch_fill(float* p, float v, int64_t n, hipStream_t st);
 // out[z * out_bs + c] = sum_r A[z * bs + r * cols + c] for z < nz; part holds
 // colsum_blocks(rows) * cols * nz floats
@@ -240,10 +258,6 @@ void launch_colsum(const float* A, int64_t rows, int64_t cols, int nz, int64_t b
                    int64_t out_bs, hipStream_t st);
 // dg: [N][26] gradient of gamma(mu_hat) summed over the batch -> dmu [N][2]
 void launch_pe_chain(const float* dg, const DevScene& s, float* dmu, hipStream_t st);
-// BF16 operands of the MLP backward of a BF16 forward (void* = __bf16 arrays)
-void launch_layer1_act_bf16(const float* Pm, const float* qs, int N, int64_t P, void* act, hipStream_t st);
-void launch_bias_relu_bf16(const float* z, const float* bias, int64_t P, void* out, hipStream_t st);
-void launch_relu_mask_inplace_bf16(void* d, const void* act, int64_t P, hipStream_t st);
 // Input gradient of a 256 x 256 layer on MFMA: out = dz W (dz [P][256] BF16, W [256][256] BF16 row-major
 // [out][in]); FP32 output (f32_out) or BF16 output masked by act > 0 (act [P][256] BF16)
 void launch_dz_gemm(const void* dz, const void* W, const void* act, int64_t P, void* out, bool f32_out,

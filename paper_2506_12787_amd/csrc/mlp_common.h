@@ -23,11 +23,12 @@ struct MlpArgs {
     float sx, sy;        // render pixels per scene pixel
     const float *mx, *my, *lsx, *lsy, *rot, *logit, *amp;
     const float* qs;
-    const float* w1m_t;
-    const float* wh_t[7];
+    const float4* wf1;   // fragment-major FP32 weights: layer 1's mean part, hidden layers, output layer
+    const float4* wfh[7];
     const float* bh[7];
-    const float* wo_t;
-    const float* bo;
+    const float4* wfo;
+    const float* bo;     // output bias (7)
+    const float* bo16;   // the same padded to 16
     Records rec;         // rec.geo == nullptr: no records (activation recompute only)
     float* delta_out;
     float* act_out[8];   // FP32 kernel only: store hidden activations H_l [P][256] when set
@@ -78,13 +79,15 @@ inline MlpArgs make_args(const DevScene& s, const float* qs, int B, const Grid& 
     a.sy = g.sy;
     a.mx = s.mx; a.my = s.my; a.lsx = s.lsx; a.lsy = s.lsy; a.rot = s.rot; a.logit = s.logit; a.amp = s.amp;
     a.qs = qs;
-    a.w1m_t = s.w1m_t;
     a.n_mid = s.has_mlp ? s.n_hidden - 1 : 0;
-    for (int l = 0; l < a.n_mid && l < 7; ++l) {
-        a.wh_t[l] = s.wh_t[l];
-        a.bh[l] = s.b[l + 1];
+    if (s.has_mlp && s.f32_frag) {
+        a.wf1 = reinterpret_cast<const float4*>(s.f32_frag);
+        for (int l = 0; l < a.n_mid && l < 7; ++l)
+            a.wfh[l] = reinterpret_cast<const float4*>(s.f32_frag + frag_hidden_at(l + 1));
+        a.wfo = reinterpret_cast<const float4*>(s.f32_frag + frag_out_at(s.n_hidden));
+        a.bo16 = s.f32_frag + frag_out_at(s.n_hidden) + kFragOut;
     }
-    a.wo_t = s.wo_t;
+    for (int l = 0; l < a.n_mid && l < 7; ++l) a.bh[l] = s.b[l + 1];
     a.bo = s.has_mlp ? s.b[s.n_hidden] : nullptr;
     a.rec = r;
     a.delta_out = delta_out;

@@ -1,8 +1,8 @@
-// Device-side repacking of an updated deformation MLP whose new weights are
-// already on the device (training): the in-major FP32 copies read by the FP32
-// kernel and the BF16 weight stream of the MFMA kernel are rebuilt from the
-// FP32 master copies where they live, on the caller's stream, with no host
-// round trip. The layouts are those the upload builds on the host.
+// Device-side packing of the deformation MLP from its FP32 master weights on
+// the device: the fragment-major FP32 copy read by the FP32 MFMA kernel (built
+// here at upload and after every update) and, after a training update, the
+// BF16 weight stream of the BF16 MFMA kernel (whose upload builds it on the
+// host in the same layout). Runs on the caller's stream with no host round trip.
 #include "kernels.h"
 #include "swf_device.h"
 
@@ -26,9 +26,8 @@ struct PackArgs {
     const float* w[8];  // FP32 master weights, row-major [out][in]
     int n_hidden, in_dim, n_units;
     uint16_t* stream;   // n_units x 8192 BF16
-    float* w1m_t;       // [26][256]
-    float* wh_t[8];     // [256][256] per hidden->hidden layer
-    float* wo_t;        // [256][7]
+    const float* bout;  // output bias (7)
+    float* frag;        // frag_floats(n_hidden) FP32, fragment-major
 };
 
 // One thread per element of the BF16 stream: unit 0 = layer 1 (mean part,
@@ -58,41 +57,63 @@ __global__ void pack_stream_kernel(PackArgs a) {
     a.stream[e] = bf16_bits_rne(v);
 }
 
-// In-major FP32 copies: w1m_t[k][j] = W0[j][k] (k < 26), wh_t[L-1][k][j] =
-// W_L[j][k], wo_t[k][o] = W_out[o][k]. blockIdx.y selects the matrix.
-__global__ void pack_transpose_kernel(PackArgs a) {
-    const int m = blockIdx.y;  // 0: layer-1 mean part, 1..n_hidden-1: hidden, n_hidden: output
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m == 0) {
-        if (e >= kMeanFeat * 256) return;
-        const int k = e / 256, jj = e % 256;
-        a.w1m_t[e] = a.w[0][(size_t)jj * a.in_dim + k];
-    } else if (m < a.n_hidden) {
-        if (e >= 256 * 256) return;
-        const int k = e / 256, jj = e % 256;
-        a.wh_t[m - 1][e] = a.w[m][(size_t)jj * 256 + k];
+// One thread per float of the FP32 fragment copy. Fragment q of output tile t
+// holds, in lane l = 16 g + r, element j: the weight of output unit 16 t + r
+// for input chunk c = 4 q + j at input k(c, g). Layer 1 (mean features,
+// chunk c of lane group g = feature 4 c + g): k = 4 c + g, zero past 26.
+// Hidden and output layers: k = 16 q + 4 g + j, the unit the previous layer's
+// output tile q leaves in element j of lane group g.
+__global__ void pack_frag_kernel(PackArgs a) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t out_at = (int64_t)frag_out_at(a.n_hidden);
+    if (e >= out_at + (int64_t)kFragOut + 16) return;
+    float v = 0.0f;
+    if (e < (int64_t)kFragL1) {
+        const int t = (int)(e / 512), q = (int)(e / 256) % 2, l = (int)(e / 4) % 64, j = (int)(e % 4);
+        const int k = 4 * (4 * q + j) + (l >> 4), row = 16 * t + (l & 15);
+        if (k < kMeanFeat) v = a.w[0][(size_t)row * a.in_dim + k];
+    } else if (e < out_at) {
+        const int64_t r = e - (int64_t)kFragL1;
+        const int L = 1 + (int)(r / (int64_t)kFragHidden);
+        const int rr = (int)(r % (int64_t)kFragHidden);
+        const int t = rr / 4096, q = (rr / 256) % 16, l = (rr / 4) % 64, j = rr % 4;
+        v = a.w[L][(size_t)(16 * t + (l & 15)) * 256 + 16 * q + 4 * (l >> 4) + j];
+    } else if (e < out_at + (int64_t)kFragOut) {
+        const int rr = (int)(e - out_at);
+        const int q = rr / 256, l = (rr / 4) % 64, j = rr % 4, o = l & 15;
+        if (o < kOut) v = a.w[a.n_hidden][(size_t)o * 256 + 16 * q + 4 * (l >> 4) + j];
     } else {
-        if (e >= 256 * kOut) return;
-        const int k = e / kOut, o = e % kOut;
-        a.wo_t[e] = a.w[a.n_hidden][(size_t)o * 256 + k];
+        const int o = (int)(e - out_at - (int64_t)kFragOut);
+        if (o < kOut) v = a.bout[o];
     }
+    a.frag[e] = v;
 }
 
 }  // namespace
 
-void launch_pack_mlp(const DevScene& d, hipStream_t st) {
+static PackArgs pack_args(const DevScene& d) {
     PackArgs a{};
     for (int l = 0; l <= d.n_hidden && l < 8; ++l) a.w[l] = d.w[l];
     a.n_hidden = d.n_hidden;
     a.in_dim = d.in_dim;
     a.n_units = 2 + 8 * (d.n_hidden - 1);
     a.stream = d.bf_stream;
-    a.w1m_t = d.w1m_t;
-    for (int l = 0; l + 1 < d.n_hidden && l < 8; ++l) a.wh_t[l] = d.wh_t[l];
-    a.wo_t = d.wo_t;
+    a.bout = d.b[d.n_hidden];
+    a.frag = d.f32_frag;
+    return a;
+}
+
+void launch_pack_f32_frag(const DevScene& d, hipStream_t st) {
+    const PackArgs a = pack_args(d);
+    const int64_t nf = (int64_t)frag_floats(d.n_hidden);
+    pack_frag_kernel<<<(unsigned)((nf + 255) / 256), 256, 0, st>>>(a);
+}
+
+void launch_pack_mlp(const DevScene& d, hipStream_t st) {
+    const PackArgs a = pack_args(d);
     const int64_t ns = (int64_t)a.n_units * 8192;
     pack_stream_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(a);
-    pack_transpose_kernel<<<dim3(256, d.n_hidden + 1), 256, 0, st>>>(a);
+    launch_pack_f32_frag(d, st);
 }
 
 }  // namespace swf

@@ -53,152 +53,110 @@ __global__ __launch_bounds__(256) void tx_features_kernel(const float* __restric
     }
 }
 
-constexpr int kR = 32;          // rows per block
-constexpr int kHid = 256;       // hidden width
-constexpr int kKS = 32;         // k rows per weight slab
-constexpr int kActStride = 260; // padded row stride of the activation tile
+// ---- FP32 MLP on the matrix cores ---------------------------------------------
+// v_mfma_f32_16x16x4_f32 (FP32 products and sums): per layer D = W H with 16
+// output units x 16 pairs per instruction and K = 4 inputs. A wave holds 16
+// pairs; the hidden state stays in registers as B operands: for input chunk c
+// lane l holds input k(c, l / 16) of pair l % 16. The result of output tile t
+// (4 registers per lane: units 16 t + 4 (l / 16) + i, i = 0..3) is, after the
+// ReLU, exactly the next layer's chunks 4 t + i, since the fragment-major
+// weights list their input columns in that order. Layer 1 takes the 26 mean
+// features (chunk c of lane group g = feature 4 c + g, zero past 26) with the
+// per-query TX part qs[b] + b1 as its bias; the output layer is one tile of 16
+// rows, 7 used. Weight fragments (16 bytes per lane) are read from the
+// L2-resident packed copy; two output tiles are accumulated side by side so
+// that consecutive instructions are independent.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kFWaves = 4;  // waves per block, 16 pairs each
 
-// FP32 MLP over kR rows per block; 256 threads; thread (tr, tc) owns rows
-// tr*4..tr*4+3 and columns tc*8..tc*8+7 of each hidden layer.
-__global__ __launch_bounds__(256, 2) void mlp_fp32_kernel(MlpArgs a) {
-    __shared__ __attribute__((aligned(16))) float act[kR * kActStride];
-    __shared__ __attribute__((aligned(16))) float ws[kKS * kHid];
-    __shared__ float xin[kR][kMeanFeat + 2];
-    __shared__ float outv[kR][8];
-
-    const int tid = threadIdx.x;
-    const int tr = tid >> 5, tc = tid & 31;
-    const size_t total = (size_t)a.N * a.B;
-    const size_t row0 = (size_t)blockIdx.x * kR;
-
-    // mean features of the block's rows, and the layer-1 mean weights into ws
-    if (tid < kR) {
-        const size_t row = row0 + tid;
-        float f[kMeanFeat];
-        if (row < total) {
-            const int p = (int)(row % a.N);
-            mean_features(a.mx[p], a.my[p], a.sW, a.sH, f);
-        } else {
+template <int kTiles, int kIn, bool kRelu>
+__device__ __forceinline__ void f32_mfma_layer(const float4* __restrict__ wf, const float* brow, int lane,
+                                               const float (&hin)[kIn], float (&hout)[64], float* store) {
+    constexpr int G = kIn / 4;  // fragments per output tile
+    constexpr int kStep = kTiles > 1 ? 2 : 1;
+    const int g = lane >> 4;
 #pragma unroll
-            for (int k = 0; k < kMeanFeat; ++k) f[k] = 0.f;
+    for (int t0 = 0; t0 < kTiles; t0 += kStep) {
+        f32x4 acc[kStep];
+#pragma unroll
+        for (int u = 0; u < kStep; ++u) {
+            const float4 b4 = *reinterpret_cast<const float4*>(brow + 16 * (t0 + u) + 4 * g);
+            acc[u] = f32x4{b4.x, b4.y, b4.z, b4.w};
         }
 #pragma unroll
-        for (int k = 0; k < kMeanFeat; ++k) xin[tid][k] = f[k];
-    }
-    for (int i = tid; i < kMeanFeat * kHid; i += 256) ws[i] = a.w1m_t[i];
-    __syncthreads();
-
-    float acc[4][8];
-    // layer 1: relu(qs[b] + W1m x_mean)
+        for (int q = 0; q < G; ++q) {
+            float4 w[kStep];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const size_t row = row0 + tr * 4 + i;
-        const int b = row < total ? (int)(row / a.N) : 0;
-        const float4* q4 = reinterpret_cast<const float4*>(a.qs + (size_t)b * kHid + tc * 8);
-        const float4 q0 = q4[0], q1 = q4[1];
-        acc[i][0] = q0.x; acc[i][1] = q0.y; acc[i][2] = q0.z; acc[i][3] = q0.w;
-        acc[i][4] = q1.x; acc[i][5] = q1.y; acc[i][6] = q1.z; acc[i][7] = q1.w;
-    }
-    for (int k = 0; k < kMeanFeat; ++k) {
-        const float4 w0 = *reinterpret_cast<const float4*>(&ws[k * kHid + tc * 8]);
-        const float4 w1 = *reinterpret_cast<const float4*>(&ws[k * kHid + tc * 8 + 4]);
+            for (int u = 0; u < kStep; ++u) w[u] = wf[((t0 + u) * G + q) * 64 + lane];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float x = xin[tr * 4 + i][k];
-            acc[i][0] = fmaf(x, w0.x, acc[i][0]); acc[i][1] = fmaf(x, w0.y, acc[i][1]);
-            acc[i][2] = fmaf(x, w0.z, acc[i][2]); acc[i][3] = fmaf(x, w0.w, acc[i][3]);
-            acc[i][4] = fmaf(x, w1.x, acc[i][4]); acc[i][5] = fmaf(x, w1.y, acc[i][5]);
-            acc[i][6] = fmaf(x, w1.z, acc[i][6]); acc[i][7] = fmaf(x, w1.w, acc[i][7]);
-        }
-    }
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        float4* dst = reinterpret_cast<float4*>(&act[(tr * 4 + i) * kActStride + tc * 8]);
-        dst[0] = make_float4(fmaxf(acc[i][0], 0.f), fmaxf(acc[i][1], 0.f), fmaxf(acc[i][2], 0.f), fmaxf(acc[i][3], 0.f));
-        dst[1] = make_float4(fmaxf(acc[i][4], 0.f), fmaxf(acc[i][5], 0.f), fmaxf(acc[i][6], 0.f), fmaxf(acc[i][7], 0.f));
-        const size_t row = row0 + tr * 4 + i;
-        if (a.act_out[0] && row < total) {
-            float4* g = reinterpret_cast<float4*>(a.act_out[0] + row * kHid + tc * 8);
-            g[0] = dst[0];
-            g[1] = dst[1];
-        }
-    }
-
-    // hidden -> hidden layers; weights streamed through ws in kKS-row slabs
-    constexpr int kSlabs = kHid / kKS;
-    constexpr int kPf = kKS * kHid / 4 / 256;  // float4 per thread per slab (8)
-    float4 pf[kPf];
-    for (int l = 0; l < a.n_mid; ++l) {
-        const float4* wsrc = reinterpret_cast<const float4*>(a.wh_t[l]);
-#pragma unroll
-        for (int j = 0; j < kPf; ++j) pf[j] = wsrc[tid + j * 256];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float4* b4 = reinterpret_cast<const float4*>(a.bh[l] + tc * 8);
-            const float4 b0 = b4[0], b1 = b4[1];
-            acc[i][0] = b0.x; acc[i][1] = b0.y; acc[i][2] = b0.z; acc[i][3] = b0.w;
-            acc[i][4] = b1.x; acc[i][5] = b1.y; acc[i][6] = b1.z; acc[i][7] = b1.w;
-        }
-        for (int sl = 0; sl < kSlabs; ++sl) {
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kPf; ++j) reinterpret_cast<float4*>(ws)[tid + j * 256] = pf[j];
-            __syncthreads();
-            if (sl + 1 < kSlabs) {
-                const float4* nsrc = wsrc + (size_t)(sl + 1) * (kKS * kHid / 4);
-#pragma unroll
-                for (int j = 0; j < kPf; ++j) pf[j] = nsrc[tid + j * 256];
-            }
-            const int kb = sl * kKS;
-#pragma unroll 2
-            for (int kk = 0; kk < kKS; kk += 4) {
-                float4 av[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    av[i] = *reinterpret_cast<const float4*>(&act[(tr * 4 + i) * kActStride + kb + kk]);
-#pragma unroll
-                for (int k4 = 0; k4 < 4; ++k4) {
-                    const float4 w0 = *reinterpret_cast<const float4*>(&ws[(kk + k4) * kHid + tc * 8]);
-                    const float4 w1 = *reinterpret_cast<const float4*>(&ws[(kk + k4) * kHid + tc * 8 + 4]);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float x = k4 == 0 ? av[i].x : (k4 == 1 ? av[i].y : (k4 == 2 ? av[i].z : av[i].w));
-                        acc[i][0] = fmaf(x, w0.x, acc[i][0]); acc[i][1] = fmaf(x, w0.y, acc[i][1]);
-                        acc[i][2] = fmaf(x, w0.z, acc[i][2]); acc[i][3] = fmaf(x, w0.w, acc[i][3]);
-                        acc[i][4] = fmaf(x, w1.x, acc[i][4]); acc[i][5] = fmaf(x, w1.y, acc[i][5]);
-                        acc[i][6] = fmaf(x, w1.z, acc[i][6]); acc[i][7] = fmaf(x, w1.w, acc[i][7]);
-                    }
+                for (int u = 0; u < kStep; ++u) {
+                    const float wv = j == 0 ? w[u].x : (j == 1 ? w[u].y : (j == 2 ? w[u].z : w[u].w));
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, hin[4 * q + j], acc[u], 0, 0, 0);
                 }
-            }
         }
-        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float4* dst = reinterpret_cast<float4*>(&act[(tr * 4 + i) * kActStride + tc * 8]);
-            dst[0] = make_float4(fmaxf(acc[i][0], 0.f), fmaxf(acc[i][1], 0.f), fmaxf(acc[i][2], 0.f), fmaxf(acc[i][3], 0.f));
-            dst[1] = make_float4(fmaxf(acc[i][4], 0.f), fmaxf(acc[i][5], 0.f), fmaxf(acc[i][6], 0.f), fmaxf(acc[i][7], 0.f));
-            const size_t row = row0 + tr * 4 + i;
-            if (a.act_out[l + 1] && row < total) {
-                float4* g = reinterpret_cast<float4*>(a.act_out[l + 1] + row * kHid + tc * 8);
-                g[0] = dst[0];
-                g[1] = dst[1];
-            }
+        for (int u = 0; u < kStep; ++u) {
+            const int t = t0 + u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) hout[4 * t + i] = kRelu ? fmaxf(acc[u][i], 0.0f) : acc[u][i];
+            if (store)
+                *reinterpret_cast<float4*>(store + 16 * t + 4 * g) =
+                    make_float4(hout[4 * t], hout[4 * t + 1], hout[4 * t + 2], hout[4 * t + 3]);
         }
     }
-    // output layer: 7 dot products of length 256 per row
-    __syncthreads();
-    for (int i = tid; i < kHid * kOut; i += 256) ws[i] = a.wo_t[i];
-    __syncthreads();
-    if (tid < kR * kOut) {
-        const int r = tid / kOut, o = tid % kOut;
-        float s = a.bo[o];
-        for (int k = 0; k < kHid; ++k) s = fmaf(act[r * kActStride + k], ws[k * kOut + o], s);
-        outv[r][o] = s;
+}
+
+__global__ __launch_bounds__(64 * kFWaves, 3) void mlp_fp32_kernel(MlpArgs a) {
+    __shared__ float outv[kFWaves][16][8];
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int g = lane >> 4;
+    const size_t total = (size_t)a.N * a.B;
+    const size_t p0 = ((size_t)blockIdx.x * kFWaves + wave) * 16;
+    if (p0 < total) {  // wave-uniform
+        const size_t row = p0 + (lane & 15);
+        const bool in = row < total;
+        const int p = in ? (int)(row % a.N) : 0, b = in ? (int)(row / a.N) : 0;
+        float x[8];
+        {
+            float f[kMeanFeat];
+            mean_features(a.mx[p], a.my[p], a.sW, a.sH, f);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float v0 = 4 * c < kMeanFeat ? f[4 * c] : 0.0f;
+                const float v1 = 4 * c + 1 < kMeanFeat ? f[4 * c + 1] : 0.0f;
+                const float v2 = 4 * c + 2 < kMeanFeat ? f[4 * c + 2] : 0.0f;
+                const float v3 = 4 * c + 3 < kMeanFeat ? f[4 * c + 3] : 0.0f;
+                x[c] = g == 0 ? v0 : (g == 1 ? v1 : (g == 2 ? v2 : v3));
+            }
+        }
+        const auto st_of = [&](int l) -> float* {
+            return (in && a.act_out[l]) ? a.act_out[l] + row * 256 : nullptr;
+        };
+        float hA[64], hB[64];
+        f32_mfma_layer<16, 8, true>(a.wf1, a.qs + (size_t)b * 256, lane, x, hA, st_of(0));
+        int l = 0;
+        for (; l + 2 <= a.n_mid; l += 2) {
+            f32_mfma_layer<16, 64, true>(a.wfh[l], a.bh[l], lane, hA, hB, st_of(l + 1));
+            f32_mfma_layer<16, 64, true>(a.wfh[l + 1], a.bh[l + 1], lane, hB, hA, st_of(l + 2));
+        }
+        if (l < a.n_mid) {
+            f32_mfma_layer<16, 64, true>(a.wfh[l], a.bh[l], lane, hA, hB, st_of(l + 1));
+#pragma unroll
+            for (int k = 0; k < 64; ++k) hA[k] = hB[k];
+        }
+        // output layer: lane l holds outputs 4 (l / 16) + i of pair l % 16
+        f32_mfma_layer<1, 64, false>(a.wfo, a.bo16, lane, hA, hB, nullptr);
+        if (g < 2) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) outv[wave][lane & 15][4 * g + i] = hB[i];
+        }
     }
     __syncthreads();
-    if (tid < kR) {
-        const size_t row = row0 + tid;
-        if (row < total) deform_epilogue(a, row, (int)(row % a.N), outv[tid]);
+    if (p0 < total && lane < 16) {
+        const size_t row = p0 + lane;
+        if (row < total) deform_epilogue(a, row, (int)(row % a.N), outv[wave][lane]);
     }
 }
 
@@ -267,8 +225,9 @@ void launch_mlp_fp32(const DevScene& s, const float* qs, int B, const Grid& g, b
     if (act_out)
         for (int l = 0; l < s.n_hidden && l < 8; ++l) a.act_out[l] = act_out[l];
     const size_t total = (size_t)s.n * B;
-    const unsigned blocks = (unsigned)((total + kR - 1) / kR);
-    if (blocks) mlp_fp32_kernel<<<blocks, 256, 0, st>>>(a);
+    const size_t per_block = (size_t)kFWaves * 16;
+    const unsigned blocks = (unsigned)((total + per_block - 1) / per_block);
+    if (blocks) mlp_fp32_kernel<<<blocks, 64 * kFWaves, 0, st>>>(a);
 }
 
 void launch_preprocess_static(const DevScene& s, int B, const Grid& g, const Records& r, hipStream_t st) {

@@ -431,23 +431,13 @@ swf_status Ctx::pack_mlp(Scene* s, const swf_mlp* mlp, bool dev, bool alloc) {
             if (!st) st = put(&d.w[l], Wh[l].data(), Wh[l].size());
             if (!st) st = put(&d.b[l], Bh[l].data(), Bh[l].size());
         }
-        if (!st) {
-            std::vector<float> t((size_t)kMeanFeat * Hd);
-            for (int k = 0; k < kMeanFeat; ++k)
-                for (int j = 0; j < Hd; ++j) t[(size_t)k * Hd + j] = Wh[0][(size_t)j * d.in_dim + k];
-            st = put(&d.w1m_t, t.data(), t.size());
+        if (!st && alloc) {
+            std::vector<float> z(frag_floats(d.n_hidden), 0.0f);
+            st = put(&d.f32_frag, z.data(), z.size());
         }
-        for (int l = 1; l < d.n_hidden && !st; ++l) {
-            std::vector<float> t((size_t)Hd * Hd);
-            for (int k = 0; k < Hd; ++k)
-                for (int j = 0; j < Hd; ++j) t[(size_t)k * Hd + j] = Wh[l][(size_t)j * Hd + k];
-            st = put(&d.wh_t[l - 1], t.data(), t.size());
-        }
-        if (!st) {
-            std::vector<float> t((size_t)Hd * kOut);
-            for (int k = 0; k < Hd; ++k)
-                for (int o = 0; o < kOut; ++o) t[(size_t)k * kOut + o] = Wh[d.n_hidden][(size_t)o * Hd + k];
-            st = put(&d.wo_t, t.data(), t.size());
+        if (!st) {  // the FP32 MFMA kernel's fragment-major copy, packed on the device from the masters
+            launch_pack_f32_frag(d, nullptr);
+            st = hip(hipDeviceSynchronize(), "pack FP32 fragments");
         }
         // BF16 weight stream for the MFMA kernel: per tile of pairs the kernel
         // consumes the stream in order; fragment (t, c) of a layer holds, for
@@ -623,8 +613,13 @@ swf_status Ctx::enqueue_preprocess(Workspace& w, Scene* sc, const float* tx, int
         if (flags & SWF_MLP_BF16)
             launch_mlp_bf16(d, (const float*)w.qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, w.rec, delta_sorted, st,
                             mlp_pairs_per_wave, w.act_out);
-        else
-            launch_mlp_fp32(d, (const float*)w.qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, w.rec, delta_sorted, st);
+        else {
+            float* ap[8] = {};  // per-layer activation stores, [n_hidden][B * N][256]
+            for (int l = 0; w.act_out && l < d.n_hidden && l < 8; ++l)
+                ap[l] = (float*)w.act_out + (size_t)l * B * d.n * 256;
+            launch_mlp_fp32(d, (const float*)w.qs.ptr, B, g, (flags & SWF_PAPER_DEFORM) != 0, w.rec, delta_sorted, st,
+                            w.act_out ? ap : nullptr);
+        }
         stage_end(st);
     } else {
         stage_begin(SWF_STAGE_MLP, st);
@@ -801,16 +796,17 @@ swf_status Ctx::render(Workspace& w, int sid, const float* tx, int B, int flags,
     hipSetDevice(device);
     const uint64_t spec_cap = speculate && key_cap == 0 && w.vals.cap >= 16 + 4 * 4096 ? (w.vals.cap - 16) / 4 : 0;
     bool spec = false;
-    // a render whose state the backward will need keeps its records and lists in the workspace; after a BF16
-    // forward also the hidden activations, stored by the MLP kernel (what the backward's GEMMs take)
+    // a render whose state the backward will need keeps its records and lists in the workspace, and the hidden
+    // activations, stored by the MLP kernel (what the backward's GEMMs take)
     const bool keep = (flags & SWF_KEEP_AUX) && &w == &ws;
     bool keep_acts = false;
     swf_status s;
     if (keep) {
         Scene* sc0 = scene(sid);
-        if (sc0 && sc0->d.kind == 0 && sc0->d.has_mlp && !(flags & SWF_NO_DEFORM) && (flags & SWF_MLP_BF16) &&
+        if (sc0 && sc0->d.kind == 0 && sc0->d.has_mlp && !(flags & SWF_NO_DEFORM) &&
             (uint64_t)B * (uint64_t)sc0->d.n < (1ull << 32)) {
-            const size_t actb = (size_t)B * sc0->d.n * 256 * sizeof(uint16_t);
+            const size_t esz = (flags & SWF_MLP_BF16) ? sizeof(uint16_t) : sizeof(float);
+            const size_t actb = (size_t)B * sc0->d.n * 256 * esz;
             if ((s = w.act.reserve(this, actb * sc0->d.n_hidden + 16, st))) return s;
             w.act_out = w.act.ptr;
             keep_acts = true;
@@ -1167,7 +1163,6 @@ swf_status swf_destroy(swf_ctx* h) {
     }
     c->scenes.clear();
     c->ws.release();
-    blas_release(c);
     c->resolve_timing();
     for (auto e : c->event_pool) hipEventDestroy(e);
     delete c;

@@ -63,7 +63,7 @@ struct Workspace {
     unsigned long long* cull_dev = nullptr;  //   culled pairs: [0] non-finite/degenerate, [1] off the grid
     uint64_t* total_host = nullptr;  // pinned
     hipEvent_t total_ev = nullptr;   // the scan total has reached total_host (speculative renders)
-    void* act_out = nullptr;         // set during a forward pass whose BF16 hidden activations are kept: they go here
+    void* act_out = nullptr;         // set during a forward pass whose hidden activations are kept: they go here
     uint64_t seq = 0;                // record generation: incremented by every pass that writes the records
     void* mix_host = nullptr;        // pinned staging of a mixed batch's scene and query tables
     size_t mix_host_cap = 0;
@@ -117,7 +117,6 @@ struct MixCaps {
 
 struct ServeState;
 struct Ctx;
-void blas_release(Ctx* c);  // destroys the rocBLAS handle (backward.cpp)
 
 struct Ctx {
     int device = 0;
@@ -198,8 +197,7 @@ struct Ctx {
     swf_status backward(Workspace& w, int sid, const float* tx, int B, int flags, const float* grad_out,
                         const void* aux, const swf_grads* grads, hipStream_t st);
     swf_status mlp_backward(Workspace& w, const DevScene& d, const float* tx, int B, const float* dy,
-                            const swf_grads* gr, bool bf16, bool acts_ready, hipStream_t st);
-    void* blas = nullptr;  // rocBLAS handle of the MLP backward (created on first use)
+                            const swf_grads* gr, bool bf16, hipStream_t st);
     void* noalloc_scratch = nullptr;  // device address of the static scan scratch (noalloc.hip) on `device`
     void stage_begin(int stage, hipStream_t st);
     void stage_end(hipStream_t st);

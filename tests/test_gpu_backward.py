@@ -266,6 +266,9 @@ def test_deterministic_backward_is_bitwise_repeatable(ctx, bf16):
         e_det, e_atomic = np.abs(xs - ys).max(), np.abs(zs - ys).max()
         print(f"  {name}: deterministic vs atomic {e_det / scale:.1e}, atomic run to run {e_atomic / scale:.1e}")
         # both are the same terms summed in another order: the fixed order is as far from one atomic run as
-        # another atomic run is (a few times), plus a floor of FP32 rounding over the blocks' cancelling sums
-        assert e_det <= 4.0 * e_atomic + 1e-5 * scale, name
+        # another atomic run is (a few times), plus a floor: FP32 rounding over the blocks' cancelling sums, or,
+        # after a BF16 forward, one BF16 unit (2^-8) of the gradients the backward rounds to BF16 (dz of every
+        # hidden layer), which a change of summation order can move across a rounding boundary
+        floor = 2.0 ** -8 if bf16 else 1e-5
+        assert e_det <= 4.0 * e_atomic + floor * scale, name
     ctx.release_scene(sid)

@@ -130,9 +130,10 @@ def test_bf16_render_parity_with_bf16_oracle(ctx):
 
 def test_device_side_mlp_update_matches_upload(ctx):
     """An MLP update from device tensors rebuilds the BF16 weight stream and the
-    FP32 in-major copies on the device. Renders after it (BF16 and FP32 MLP) are
-    bitwise those of the same weights packed on the host at upload; a scene
-    updated to other weights and back gives the original renders again."""
+    FP32 fragment-major copy on the device. Renders after it (BF16 and FP32 MLP)
+    are bitwise those of the same weights uploaded from the host (the BF16
+    stream packed on the host there); a scene updated to other weights and back
+    gives the original renders again."""
     import torch
     from paper_2506_12787_amd import binding as B
     g, s = Hh.problem(3000, H0, W0, seed=77)
