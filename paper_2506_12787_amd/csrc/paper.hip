@@ -185,7 +185,8 @@ __global__ __launch_bounds__(256) void paper_static_kernel(PaperArgs a) {
 // columns for every pad: the 156 units are padded to 160, the 81 inputs to
 // 96). A layer reads its input as [h chunks (40) | x chunks (24)] (layer 1: x
 // only; the skip layers 3, 5, 7: both; the others: h only); a fragment of 4
-// chunks is one 16-byte load per lane from the L2-resident weights.
+// chunks is one 16-byte load per lane from the L2-resident weights, issued one
+// fragment ahead.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMNB = 2;        // column blocks of 16 pairs per wave
 constexpr int kMWaves = 4;     // waves per block
@@ -196,6 +197,10 @@ __device__ __forceinline__ void paper_mfma_layer(const float4* __restrict__ wf, 
                                                  int lane, const float (&hin)[kMNB][kHC],
                                                  const float (&x)[kMNB][kXC], float (&hout)[kMNB][kHC]) {
     constexpr int G = (kH ? kHC / 4 : 0) + (kX ? kXC / 4 : 0);  // 16-byte fragments per output tile
+    constexpr int F = kTiles * G;
+    // the next fragment is loaded while the current one's instructions run; the scheduling barrier after them
+    // keeps that load where it is written (the compiler would sink it next to its use)
+    float4 wn = wf[lane];
 #pragma unroll
     for (int t = 0; t < kTiles; ++t) {
         const float4 b4 = *reinterpret_cast<const float4*>(bias + 16 * t + 4 * (lane >> 4));
@@ -204,7 +209,9 @@ __device__ __forceinline__ void paper_mfma_layer(const float4* __restrict__ wf, 
         for (int cb = 0; cb < kMNB; ++cb) acc[cb] = f32x4{b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
         for (int gq = 0; gq < G; ++gq) {
-            const float4 w = wf[((size_t)t * G + gq) * 64 + lane];
+            const int f = t * G + gq;
+            const float4 w = wn;
+            if (f + 1 < F) wn = wf[((size_t)f + 1) * 64 + lane];
             const float wv[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -215,6 +222,7 @@ __device__ __forceinline__ void paper_mfma_layer(const float4* __restrict__ wf, 
                     acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv[j], bv, acc[cb], 0, 0, 0);
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int cb = 0; cb < kMNB; ++cb)

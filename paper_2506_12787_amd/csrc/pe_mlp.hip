@@ -63,48 +63,46 @@ __global__ __launch_bounds__(256) void tx_features_kernel(const float* __restric
 // weights list their input columns in that order. Layer 1 takes the 26 mean
 // features (chunk c of lane group g = feature 4 c + g, zero past 26) with the
 // per-query TX part qs[b] + b1 as its bias; the output layer is one tile of 16
-// rows, 7 used. Weight fragments (16 bytes per lane) are read from the
-// L2-resident packed copy; two output tiles are accumulated side by side so
-// that consecutive instructions are independent.
+// rows, 7 used. Weight fragments (16 bytes per lane, 4 instructions each) are
+// read from the L2-resident packed copy kPrefetch fragments ahead of their use;
+// a scheduling barrier after each fragment's instructions keeps every load
+// where it is written (left free, the compiler sinks the loads next to their
+// use, which leaves one or two in flight and exposes the L2 latency).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kFWaves = 4;  // waves per block, 16 pairs each
+constexpr int kFWaves = 4;     // waves per block, 16 pairs each
+constexpr int kPrefetch = 2;   // weight fragments in flight ahead of the one in use
 
 template <int kTiles, int kIn, bool kRelu>
 __device__ __forceinline__ void f32_mfma_layer(const float4* __restrict__ wf, const float* brow, int lane,
                                                const float (&hin)[kIn], float (&hout)[64], float* store) {
     constexpr int G = kIn / 4;  // fragments per output tile
-    constexpr int kStep = kTiles > 1 ? 2 : 1;
+    constexpr int F = kTiles * G;
     const int g = lane >> 4;
+    float4 wq[kPrefetch];
 #pragma unroll
-    for (int t0 = 0; t0 < kTiles; t0 += kStep) {
-        f32x4 acc[kStep];
+    for (int i = 0; i < kPrefetch; ++i) wq[i] = i < F ? wf[i * 64 + lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
-        for (int u = 0; u < kStep; ++u) {
-            const float4 b4 = *reinterpret_cast<const float4*>(brow + 16 * (t0 + u) + 4 * g);
-            acc[u] = f32x4{b4.x, b4.y, b4.z, b4.w};
-        }
+    for (int t = 0; t < kTiles; ++t) {
+        const float4 b4 = *reinterpret_cast<const float4*>(brow + 16 * t + 4 * g);
+        f32x4 acc = f32x4{b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-            float4 w[kStep];
+            const int f = t * G + q;
+            const float4 w = wq[0];
 #pragma unroll
-            for (int u = 0; u < kStep; ++u) w[u] = wf[((t0 + u) * G + q) * 64 + lane];
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int u = 0; u < kStep; ++u) {
-                    const float wv = j == 0 ? w[u].x : (j == 1 ? w[u].y : (j == 2 ? w[u].z : w[u].w));
-                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, hin[4 * q + j], acc[u], 0, 0, 0);
-                }
+            for (int i = 0; i + 1 < kPrefetch; ++i) wq[i] = wq[i + 1];
+            if (f + kPrefetch < F) wq[kPrefetch - 1] = wf[(f + kPrefetch) * 64 + lane];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, hin[4 * q + 0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, hin[4 * q + 1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.z, hin[4 * q + 2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w, hin[4 * q + 3], acc, 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int u = 0; u < kStep; ++u) {
-            const int t = t0 + u;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) hout[4 * t + i] = kRelu ? fmaxf(acc[u][i], 0.0f) : acc[u][i];
-            if (store)
-                *reinterpret_cast<float4*>(store + 16 * t + 4 * g) =
-                    make_float4(hout[4 * t], hout[4 * t + 1], hout[4 * t + 2], hout[4 * t + 3]);
-        }
+        for (int i = 0; i < 4; ++i) hout[4 * t + i] = kRelu ? fmaxf(acc[i], 0.0f) : acc[i];
+        if (store)
+            *reinterpret_cast<float4*>(store + 16 * t + 4 * g) =
+                make_float4(hout[4 * t], hout[4 * t + 1], hout[4 * t + 2], hout[4 * t + 3]);
     }
 }
 
