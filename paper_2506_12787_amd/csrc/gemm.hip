@@ -6,12 +6,15 @@
 // product with FP32 accumulation). Optional epilogue: C *= [mask > 0] (the
 // ReLU derivative of the layer below).
 //
-// Block tile 64 x 64, K in steps of 16 staged through LDS (double-buffered,
+// Block tile 64 x 64 (128 x 32 when C has at most 32 columns, so no wave
+// computes padding only), K in steps of 32 staged through LDS (double-buffered,
 // one barrier per step); four waves of 32 x 32 = 2 x 2 instructions of
-// 16 x 16. Every operand layout is loaded along its contiguous dimension.
-// Products with a small C and a long K (weight gradients: K = pairs) are cut
-// into K-slices whose partial products are summed afterwards in slice order,
-// so every result is the same from run to run.
+// 16 x 16. Every operand layout is loaded along its contiguous dimension, four
+// elements per thread and run (one 16-byte load where the run is aligned and
+// inside the matrix). Products with a small C and a long K (weight gradients:
+// K = pairs or Gaussians) are cut into K-slices whose partial products are
+// summed afterwards in a fixed order, so every result is the same from run to
+// run.
 #include <algorithm>
 
 #include "kernels.h"
@@ -21,9 +24,7 @@ namespace swf {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kGT = 64;        // block tile (M and N)
-constexpr int kGK = 16;        // K per LDS stage
-constexpr int kGLd = kGT + 16; // LDS row stride: the 4 k-rows of one read land on disjoint banks
+constexpr int kGK = 32;  // K per LDS stage
 
 struct GemmArgs {
     const void* A;
@@ -33,6 +34,7 @@ struct GemmArgs {
     int64_t M, N, K, lda, ldb, ldc, ldm;
     int64_t kc;         // K per slice (blockIdx.z)
     int a_kc, b_kc;     // operand contiguous along K (else along M / N)
+    int a_vec, b_vec;   // FP32 operand whose runs of 4 are 16-byte aligned (ld % 4 == 0, aligned base)
 };
 
 template <bool kBf>
@@ -45,43 +47,72 @@ __device__ __forceinline__ float elem(const void* p, int64_t i) {
     }
 }
 
-// The 4 elements this thread stages of a 64 (outer: M or N) x 16 (K) operand
-// tile starting at (o0, k0); zero outside olim / klim. kcontig: element
-// (o, k) at p[o * ld + k], else at p[k * ld + o].
-template <bool kBf>
-__device__ __forceinline__ void tile_load(const void* p, int64_t ld, bool kcontig, int64_t o0, int64_t olim,
-                                          int64_t k0, int64_t klim, float (&v)[4]) {
+// The elements this thread stages of an O (outer: M or N) x 32 (K) operand
+// tile starting at (o0, k0): O / 32 runs of 4 along the contiguous dimension,
+// run u = 256 r + t of the tile's 8 O runs; zero outside olim / klim.
+// kcontig: element (o, k) at p[o * ld + k], run u covers o = u / 8,
+// k = 4 (u % 8) + 0..3; else element (o, k) at p[k * ld + o], run u covers
+// k = u / (O / 4), o = 4 (u % (O / 4)) + 0..3. A run inside the matrix is one
+// 16-byte load when the operand allows it.
+template <bool kBf, int O>
+__device__ __forceinline__ void tile_load(const void* p, int64_t ld, bool kcontig, bool vec, int64_t o0,
+                                          int64_t olim, int64_t k0, int64_t klim, float (&v)[O / 8]) {
     const int t = (int)threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int o = kcontig ? t >> 2 : (t & 15) * 4 + j;
-        const int k = kcontig ? (t & 3) * 4 + j : t >> 4;
+    for (int r = 0; r < O / 32; ++r) {
+        const int u = 256 * r + t;
+        const int o = kcontig ? u >> 3 : 4 * (u % (O / 4));
+        const int k = kcontig ? 4 * (u & 7) : u / (O / 4);
         const int64_t go = o0 + o, gk = k0 + k;
-        v[j] = (go < olim && gk < klim) ? elem<kBf>(p, kcontig ? go * ld + gk : gk * ld + go) : 0.0f;
+        const bool whole = kcontig ? (go < olim && gk + 3 < klim) : (gk < klim && go + 3 < olim);
+        const int64_t at = kcontig ? go * ld + gk : gk * ld + go;
+        if (!kBf && vec && whole) {
+            const float4 f = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(p) + at);
+            v[4 * r] = f.x;
+            v[4 * r + 1] = f.y;
+            v[4 * r + 2] = f.z;
+            v[4 * r + 3] = f.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool in = kcontig ? (go < olim && gk + j < klim) : (gk < klim && go + j < olim);
+                v[4 * r + j] = in ? elem<kBf>(p, at + j) : 0.0f;
+            }
+        }
     }
 }
 
-__device__ __forceinline__ void tile_store(float (*s)[kGLd], bool kcontig, const float (&v)[4]) {
+template <int O>
+__device__ __forceinline__ void tile_store(float (*s)[O + 16], bool kcontig, const float (&v)[O / 8]) {
     const int t = (int)threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int o = kcontig ? t >> 2 : (t & 15) * 4 + j;
-        const int k = kcontig ? (t & 3) * 4 + j : t >> 4;
-        s[k][o] = v[j];
+    for (int r = 0; r < O / 32; ++r) {
+        const int u = 256 * r + t;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = kcontig ? u >> 3 : 4 * (u % (O / 4)) + j;
+            const int k = kcontig ? 4 * (u & 7) + j : u / (O / 4);
+            s[k][o] = v[4 * r + j];
+        }
     }
 }
 
-template <bool kBf>
+// Block tile TM x TN (64 x 64, or 128 x 32 for a narrow C), four waves of
+// 32 x 32 each = 2 x 2 instructions of 16 x 16. LDS rows are padded by 16
+// floats, so the 4 k-rows one read touches land on disjoint banks.
+template <bool kBf, int TM, int TN>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
-    __shared__ float As[2][kGK][kGLd];
-    __shared__ float Bs[2][kGK][kGLd];
+    static_assert((TM / 32) * (TN / 32) == 4, "four waves of 32 x 32");
+    __shared__ float As[2][kGK][TM + 16];
+    __shared__ float Bs[2][kGK][TN + 16];
     const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-    const int wm = wave >> 1, wn = wave & 1;
-    const int64_t m0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
+    const int wm = wave % (TM / 32), wn = wave / (TM / 32);
+    const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
     const int64_t kb = (int64_t)blockIdx.z * g.kc;
     const int64_t ke = g.K < kb + g.kc ? g.K : kb + g.kc;
     const int steps = ke > kb ? (int)((ke - kb + kGK - 1) / kGK) : 0;
     const bool akc = g.a_kc != 0, bkc = g.b_kc != 0;
+    const bool avec = g.a_vec != 0, bvec = g.b_vec != 0;
 
     f32x4 acc[2][2];
 #pragma unroll
@@ -89,12 +120,12 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    float va[4], vb[4];
+    float va[TM / 8], vb[TN / 8];
     if (steps > 0) {
-        tile_load<kBf>(g.A, g.lda, akc, m0, g.M, kb, ke, va);
-        tile_load<kBf>(g.B, g.ldb, bkc, n0, g.N, kb, ke, vb);
-        tile_store(As[0], akc, va);
-        tile_store(Bs[0], bkc, vb);
+        tile_load<kBf, TM>(g.A, g.lda, akc, avec, m0, g.M, kb, ke, va);
+        tile_load<kBf, TN>(g.B, g.ldb, bkc, bvec, n0, g.N, kb, ke, vb);
+        tile_store<TM>(As[0], akc, va);
+        tile_store<TN>(Bs[0], bkc, vb);
     }
     __syncthreads();
     for (int s = 0; s < steps; ++s) {
@@ -102,8 +133,8 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
         const bool more = s + 1 < steps;
         if (more) {
             const int64_t k1 = kb + (int64_t)(s + 1) * kGK;
-            tile_load<kBf>(g.A, g.lda, akc, m0, g.M, k1, ke, va);
-            tile_load<kBf>(g.B, g.ldb, bkc, n0, g.N, k1, ke, vb);
+            tile_load<kBf, TM>(g.A, g.lda, akc, avec, m0, g.M, k1, ke, va);
+            tile_load<kBf, TN>(g.B, g.ldb, bkc, bvec, n0, g.N, k1, ke, vb);
         }
 #pragma unroll
         for (int q = 0; q < kGK / 4; ++q) {
@@ -119,8 +150,8 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
                 for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (more) {
-            tile_store(As[cur ^ 1], akc, va);
-            tile_store(Bs[cur ^ 1], bkc, vb);
+            tile_store<TM>(As[cur ^ 1], akc, va);
+            tile_store<TN>(Bs[cur ^ 1], bkc, vb);
         }
         __syncthreads();
     }
@@ -145,28 +176,42 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmArgs g) {
         }
 }
 
-// C[m][n] (ld ldc) = sum over the slices, in slice order, of part[z][m][n]; then the mask
+// C[m][n] (ld ldc) = sum over the slices of part[z][m][n], then the mask. A
+// block takes 64 consecutive outputs; thread group w (of 4) sums the slices
+// z = w, w + 4, ... in order, and the four partial sums are added in the
+// order w = 0..3, so the result does not depend on the launch.
 __global__ __launch_bounds__(256) void gemm_reduce_kernel(const float* __restrict__ part, int sp, int64_t M,
                                                           int64_t N, float* __restrict__ C, int64_t ldc,
                                                           const float* __restrict__ mask, int64_t ldm) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= M * N) return;
+    __shared__ float red[4][64];
+    const int64_t i = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int w = (int)(threadIdx.x >> 6);
+    const size_t plane = (size_t)(M * N);
     float s = 0.0f;
-    for (int z = 0; z < sp; ++z) s += part[(size_t)z * (size_t)(M * N) + i];
-    const int64_t m = i / N, n = i - m * N;
-    if (mask && !(mask[m * ldm + n] > 0.0f)) s = 0.0f;
-    C[m * ldc + n] = s;
+    if (i < M * N)
+        for (int z = w; z < sp; z += 4) s += part[(size_t)z * plane + i];
+    red[w][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (w == 0 && i < M * N) {
+        const int c = (int)threadIdx.x;
+        float v = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+        const int64_t m = i / N, n = i - m * N;
+        if (mask && !(mask[m * ldm + n] > 0.0f)) v = 0.0f;
+        C[m * ldc + n] = v;
+    }
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+bool narrow(int64_t N) { return N <= 32; }  // the 128 x 32 tile
+
 }  // namespace
 
 int gemm_split(int64_t M, int64_t N, int64_t K) {
-    const int64_t tiles = cdiv(M, kGT) * cdiv(N, kGT);
-    // enough blocks to cover the chip a few times, each slice at least 2048 deep
-    const int64_t want = cdiv(2048, tiles), deep = K / 2048;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(64, std::min(want, deep)));
+    const int64_t tiles = narrow(N) ? cdiv(M, 128) * cdiv(N, 32) : cdiv(M, 64) * cdiv(N, 64);
+    // enough blocks to cover the chip a few times, each slice at least 256 deep
+    const int64_t want = cdiv(2048, tiles), deep = K / 256;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(256, std::min(want, deep)));
 }
 
 size_t gemm_part_floats(int64_t M, int64_t N, int64_t K) {
@@ -198,13 +243,23 @@ void launch_gemm_f32(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const vo
     // contiguous along N, B^T (B stored N x K) along K.
     g.a_kc = ta ? 0 : 1;
     g.b_kc = tb ? 1 : 0;
-    const dim3 grid((unsigned)cdiv(M, kGT), (unsigned)cdiv(N, kGT), (unsigned)slices);
-    if (bf16)
-        gemm_f32_kernel<true><<<grid, 256, 0, st>>>(g);
-    else
-        gemm_f32_kernel<false><<<grid, 256, 0, st>>>(g);
+    g.a_vec = !bf16 && lda % 4 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+    g.b_vec = !bf16 && ldb % 4 == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+    if (narrow(N)) {
+        const dim3 grid((unsigned)cdiv(M, 128), (unsigned)cdiv(N, 32), (unsigned)slices);
+        if (bf16)
+            gemm_f32_kernel<true, 128, 32><<<grid, 256, 0, st>>>(g);
+        else
+            gemm_f32_kernel<false, 128, 32><<<grid, 256, 0, st>>>(g);
+    } else {
+        const dim3 grid((unsigned)cdiv(M, 64), (unsigned)cdiv(N, 64), (unsigned)slices);
+        if (bf16)
+            gemm_f32_kernel<true, 64, 64><<<grid, 256, 0, st>>>(g);
+        else
+            gemm_f32_kernel<false, 64, 64><<<grid, 256, 0, st>>>(g);
+    }
     if (slices > 1)
-        gemm_reduce_kernel<<<(unsigned)cdiv(M * N, 256), 256, 0, st>>>(part, slices, M, N, C, ldc, mask, ldm);
+        gemm_reduce_kernel<<<(unsigned)cdiv(M * N, 64), 256, 0, st>>>(part, slices, M, N, C, ldc, mask, ldm);
 }
 
 }  // namespace swf
