@@ -532,12 +532,13 @@ def bench_train(a):
     count = [0]
     reused = []
 
-    def step(i, probe=False, det=False):
-        out, aux = ctx.render(sid, tx_dev[i], flags=B.MLP_BF16 | B.KEEP_AUX)
+    def step(i, probe=False, det=False, fp32=False):
+        mf = B.MLP_FP32 if fp32 else B.MLP_BF16
+        out, aux = ctx.render(sid, tx_dev[i], flags=mf | B.KEEP_AUX)
         loss, grad = ctx.l1_loss(out, targets[i])
         for t in grads:
             t.zero_()
-        ctx.render_backward(sid, tx_dev[i], B.MLP_BF16 | (B.DETERMINISTIC if det else 0), grad, aux, gd)
+        ctx.render_backward(sid, tx_dev[i], mf | (B.DETERMINISTIC if det else 0), grad, aux, gd)
         if probe:  # (waits) whether the backward took its forward's kept records and lists
             reused.append(bool(ctx.device_status()["flags"] & B.DEV_BWD_REUSED))
         count[0] += 1
@@ -579,6 +580,21 @@ def bench_train(a):
         step(warmup + i, det=True)
     torch.cuda.synchronize()
     det_ms = 1e3 * (time.perf_counter() - t1) / nd
+    # the same steps at the paper's precision: FP32 MLP forward and backward (FP32 matrix cores), with their stages
+    step(warmup, fp32=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for i in range(nd):
+        step(warmup + i, fp32=True)
+    torch.cuda.synchronize()
+    fp32_ms = 1e3 * (time.perf_counter() - t2) / nd
+    ctx.stage_timing(True)
+    ctx.stage_times()  # reset
+    for i in range(n_inst):
+        step(warmup + i, fp32=True)
+    torch.cuda.synchronize()
+    stages32 = {k: v[0] / n_inst for k, v in ctx.stage_times().items() if v[1] > 0}
+    ctx.stage_timing(False)
     # MLP backward FLOPs per pair: weight gradients and input gradients of the output layer (7 x 256) and of the
     # three 256 x 256 layers, 2 FLOP per multiply-add each (layer 1's gradients are per Gaussian and per query)
     bwd_flop = Bq * N * 2 * 2 * (7 * 256 + 3 * 256 * 256)
@@ -601,6 +617,8 @@ def bench_train(a):
                      "flop_per_step": bwd_flop, "avg_ms": t_bwd},
         "backward_reused_forward": reused[0],
         "deterministic_ms_per_step": det_ms,
+        "fp32": {"ms_per_step": fp32_ms, "stages_ms_per_step": stages32,
+                 "note": "FP32 MLP forward and backward (the paper's precision), the same loop otherwise"},
         "note": "targets: a separately seeded ground-truth Gaussian set rendered by this library at the same TX "
                 "positions; stage times from 5 more steps with stage events on; the backward takes the records, "
                 "lists and BF16 activations its forward render kept (backward_reused_forward)",
