@@ -201,15 +201,23 @@ swf_status Ctx::backward(Workspace& w, int sid, const float* tx, int B, int flag
     if ((s = hip(hipMemsetAsync(w.dpair.ptr, 0, (size_t)P * 8 * sizeof(float), st), "memset dpair"))) return s;
     stage_begin(SWF_STAGE_BWD_BLEND, st);
     float* det_part = nullptr;
+    const uint32_t* det_off = nullptr;
     if (flags & SWF_DETERMINISTIC) {
-        // per (list entry, wave) sums, zero where a wave contributes nothing
+        // per (list entry, wave) sums, zero where a wave contributes nothing, stored per pair: a pair's entries
+        // from its first slot on (the exclusive scan of the key counts), in the row-major order of its tiles
         const size_t db = (size_t)w.last.n_keys * 32 * sizeof(float);
         if ((s = w.det.reserve(this, db + 16, st))) return s;
         if (db && (s = hip(hipMemsetAsync(w.det.ptr, 0, db, st), "memset entry sums"))) return s;
         det_part = (float*)w.det.ptr;
+        const size_t ob = ((size_t)P * sizeof(uint32_t) + 7) / 8 * 8;
+        if ((s = w.off.reserve(this, ob + 16, st))) return s;
+        if ((s = w.scan.reserve(this, scan_scratch_bytes(P) + 64, st))) return s;
+        launch_exclusive_scan(w.rec.count, (uint32_t*)w.off.ptr, (uint64_t*)((char*)w.off.ptr + ob), P, w.scan.ptr,
+                              st);
+        det_off = (const uint32_t*)w.off.ptr;
     }
     launch_blend_backward((const uint2*)w.ranges.ptr, w.last.vals, w.rec, B, w.last.grid, grad_out, auxT, auxL,
-                          (float*)w.dpair.ptr, st, det_part, d.n);
+                          (float*)w.dpair.ptr, st, det_part, d.n, det_off);
     stage_end(st);
     // 3. preprocess backward -> residual-coordinate gradients
     float* dy = nullptr;

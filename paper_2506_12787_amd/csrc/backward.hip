@@ -66,14 +66,16 @@ __device__ __forceinline__ float wave_sum8(float (&a)[8]) {
 // kWrap: periodic azimuth, as in the forward kernel (same staged image, same
 // displacement, same culling exemption), so that every decision replays exactly.
 // kDet: instead of adding into dpair, each wave writes its 8 sums of an entry
-// to part[(list position) * 32 + wave * 8 + k] (zeroed beforehand); the
-// per-pair sums are then taken in a fixed order by det_reduce_kernel.
+// to part[slot * 32 + wave * 8 + k] (zeroed beforehand), slot = the pair's
+// first slot (det_off: the exclusive scan of the key counts) + the tile's
+// row-major index in the pair's rectangle; det_reduce_kernel then sums each
+// pair's slots in that order.
 template <int TILE, bool kWrap = false, bool kDet = false>
 __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals, const float4* __restrict__ geo,
     const float4* __restrict__ wm, const float2* __restrict__ oa, int H, int W, int TW, int tiles,
     const float* __restrict__ grad_out, const float* __restrict__ aux_T, const uint32_t* __restrict__ aux_last,
-    float* __restrict__ dpair) {
+    float* __restrict__ dpair, const uint2* __restrict__ rect = nullptr, const uint32_t* __restrict__ det_off = nullptr) {
     constexpr int kN = TILE * TILE;
     constexpr bool kCull = TILE == 16;
     constexpr int kWaves = kN / 64;
@@ -81,6 +83,7 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
     __shared__ float4 s_wm[kN];
     __shared__ float2 s_oa[kN];
     __shared__ uint32_t s_v[kN];
+    __shared__ uint32_t s_slot[kDet ? kN : 1];
     __shared__ uint8_t s_strip[kCull ? kN : 1];
     __shared__ uint16_t s_idx[kCull ? kWaves : 1][kN];
     __shared__ uint32_t s_max;
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
         if (l < 8u && v != 0.0f) {
             const int k = 4 * (int)(l & 1u) + 2 * (int)((l >> 1) & 1u) + (int)((l >> 2) & 1u);
             if constexpr (kDet)
-                dpair[((size_t)rg.x + (size_t)j) * 32 + (size_t)wq * 8 + k] = v;
+                dpair[(size_t)s_slot[jj] * 32 + (size_t)wq * 8 + k] = v;
             else
                 atomicAdd(dpair + (size_t)s_v[jj] * 8 + k, v);
         }
@@ -183,6 +186,13 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
                 s_wm[threadIdx.x] = m;
                 s_oa[threadIdx.x] = oa[v];
                 s_v[threadIdx.x] = v;
+                if constexpr (kDet) {  // this tile's slot of the pair: row-major in its (possibly wrapped) rectangle
+                    const uint2 rr = rect[v];
+                    const int rx0 = (int)(rr.x & 0xffff), rx1 = (int)(rr.x >> 16), ry0 = (int)(rr.y & 0xffff);
+                    const int rw = rx1 >= rx0 ? rx1 - rx0 + 1 : TW - rx0 + rx1 + 1;
+                    const int cx = tx >= rx0 ? tx - rx0 : tx - rx0 + TW;
+                    s_slot[threadIdx.x] = det_off[v] + (uint32_t)((ty - ry0) * rw + cx);
+                }
                 if (kCull)
                     s_strip[threadIdx.x] =
                         (kWrap && fabsf(pos.x - cx) > 0.5f * Wf - (float)TILE)
@@ -217,46 +227,26 @@ __global__ __launch_bounds__(TILE* TILE) void blend_backward_kernel(
 // of its rectangle in row-major order (a wrapped rectangle's columns from tx0
 // on), the four waves' sums of its entry in that tile's list, found by binary
 // search (a list holds its pairs in increasing order).
-__global__ void det_reduce_kernel(const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
-                                  const uint2* __restrict__ rect, const uint32_t* __restrict__ count,
-                                  const float* __restrict__ part, int64_t P, int N, int TW, int tiles,
-                                  float* __restrict__ dpair) {
+__global__ void det_reduce_kernel(const uint32_t* __restrict__ count, const uint32_t* __restrict__ det_off,
+                                  const float* __restrict__ part, int64_t P, float* __restrict__ dpair) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (count[i]) {
-        const uint2 r = rect[i];
-        const int tx0 = r.x & 0xffff, tx1 = r.x >> 16, ty0 = r.y & 0xffff, ty1 = r.y >> 16;
-        const int w = tx1 >= tx0 ? tx1 - tx0 + 1 : TW - tx0 + tx1 + 1;
-        const size_t gt0 = (size_t)(i / N) * tiles;
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int k = 0; k < w; ++k) {
-                const int col = tx0 + k < TW ? tx0 + k : tx0 + k - TW;
-                const uint2 rg = ranges[gt0 + (size_t)(ty * TW + col)];
-                uint32_t lo = rg.x, hi = rg.y;  // first position in [lo, hi) whose value is >= i
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (vals[mid] < (uint32_t)i)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-                if (lo >= rg.y || vals[lo] != (uint32_t)i) continue;  // an empty range (no entries kept)
-                const float4* e = reinterpret_cast<const float4*>(part + (size_t)lo * 32);
+    const uint32_t c = count[i];
+    const float4* e = reinterpret_cast<const float4*>(part + (size_t)(c ? det_off[i] : 0u) * 32);
+    for (uint32_t k = 0; k < c; ++k)  // the pair's tiles in row-major order, then the 4 waves of each
 #pragma unroll
-                for (int wv = 0; wv < 4; ++wv) {
-                    const float4 a = e[2 * wv], b = e[2 * wv + 1];
-                    acc[0] += a.x;
-                    acc[1] += a.y;
-                    acc[2] += a.z;
-                    acc[3] += a.w;
-                    acc[4] += b.x;
-                    acc[5] += b.y;
-                    acc[6] += b.z;
-                    acc[7] += b.w;
-                }
-            }
-    }
+        for (int wv = 0; wv < 4; ++wv) {
+            const float4 a = e[(size_t)k * 8 + 2 * wv], b = e[(size_t)k * 8 + 2 * wv + 1];
+            acc[0] += a.x;
+            acc[1] += a.y;
+            acc[2] += a.z;
+            acc[3] += a.w;
+            acc[4] += b.x;
+            acc[5] += b.y;
+            acc[6] += b.z;
+            acc[7] += b.w;
+        }
 #pragma unroll
     for (int k = 0; k < 8; ++k) dpair[i * 8 + k] = acc[k];
 }
@@ -955,13 +945,13 @@ __global__ void mean_features_f32_kernel(const float* __restrict__ mx, const flo
 
 void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
                            const float* grad_out, const float* aux_T, const uint32_t* aux_last, float* dpair,
-                           hipStream_t st, float* det_part, int N) {
+                           hipStream_t st, float* det_part, int N, const uint32_t* det_off) {
     const unsigned blocks = (unsigned)(B * g.tiles);
     if (!blocks) return;
     float* dst = det_part ? det_part : dpair;
 #define SWF_BLEND_BWD(TILE, WRAP, DET)                                                                         \
     blend_backward_kernel<TILE, WRAP, DET><<<blocks, TILE * TILE, 0, st>>>(                                    \
-        ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles, grad_out, aux_T, aux_last, dst)
+        ranges, vals, r.geo, r.wm, r.oa, g.H, g.W, g.TW, g.tiles, grad_out, aux_T, aux_last, dst, r.rect, det_off)
 #define SWF_BLEND_BWD_T(TILE, DET)   \
     do {                             \
         if (g.wrap)                  \
@@ -976,8 +966,7 @@ void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Reco
             SWF_BLEND_BWD_T(16, true);
         const int64_t P = (int64_t)B * N;
         if (P > 0)
-            det_reduce_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(ranges, vals, r.rect, r.count, det_part, P,
-                                                                           N, g.TW, g.tiles, dpair);
+            det_reduce_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(r.count, det_off, det_part, P, dpair);
     } else {
         if (g.tile == 8)
             SWF_BLEND_BWD_T(8, false);

@@ -233,7 +233,7 @@ void launch_bin_ranges(const uint32_t* bins, int B, int N, const Grid& g, const 
 // with it the per-pair sums in dpair are taken in a fixed order (N: Gaussians per query)
 void launch_blend_backward(const uint2* ranges, const uint32_t* vals, const Records& r, int B, const Grid& g,
                            const float* grad_out, const float* aux_T, const uint32_t* aux_last, float* dpair,
-                           hipStream_t st, float* det_part = nullptr, int N = 0);
+                           hipStream_t st, float* det_part = nullptr, int N = 0, const uint32_t* det_off = nullptr);
 void launch_preprocess_backward(const float* dpair, const Records& r, int64_t P, bool paper_mask, float* dbase,
                                 float* dy, hipStream_t st);
 struct BaseGrads {  // destinations of the 7 base-parameter gradients (device; NULL skips one)
