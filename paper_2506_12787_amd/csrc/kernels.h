@@ -27,7 +27,7 @@ struct DevScene {
     uint64_t bytes = 0;
     // kind 1: the paper's own model (GMM sum over Cholesky Gaussians with tanh centres and complex responses,
     // in id order; paper.hip). Raw parameters, the FP64-mapped centres (hi, lo) and their 10-band encoding, and
-    // the paper MLP: FP32 masters (out, in) and the packed in-major layers of the kernel.
+    // the paper MLP: FP32 masters (out, in) and the kernel's fragment-major layers with padded biases.
     int kind = 0;
     float *pcx = nullptr, *pcy = nullptr, *pl1 = nullptr, *pl2 = nullptr, *pl3 = nullptr;
     float *patt = nullptr, *ppre = nullptr, *ppim = nullptr;
@@ -180,8 +180,8 @@ void launch_permute_delta(const float* delta_sorted, const uint32_t* perm, int B
 // mlp_bf16.hip
 bool bf16_available();
 void compute_mean_features_bf16(DevScene& s, hipStream_t st);
-// pack.hip: rebuild the in-major FP32 copies and the BF16 weight stream from the
-// FP32 master weights d.w[] on the device (after a device-side MLP update)
+// pack.hip: rebuild the fragment-major FP32 copy and the BF16 weight stream from
+// the FP32 master weights d.w[] on the device (after a device-side MLP update)
 void launch_pack_mlp(const DevScene& d, hipStream_t st);
 // the fragment-major FP32 copy alone (frag_floats(n_hidden) floats at d.f32_frag)
 void launch_pack_f32_frag(const DevScene& d, hipStream_t st);

@@ -31,7 +31,7 @@ struct MlpArgs {
     const float* bo16;   // the same padded to 16
     Records rec;         // rec.geo == nullptr: no records (activation recompute only)
     float* delta_out;
-    float* act_out[8];   // FP32 kernel only: store hidden activations H_l [P][256] when set
+    float* act_out[8];   // FP32 kernel: store hidden activations H_l [P][256] when set (the BF16 kernel takes its own)
 };
 
 

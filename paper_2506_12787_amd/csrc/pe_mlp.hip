@@ -4,8 +4,8 @@
 // Deformation MLP (Sec. 4.2): residuals = F_theta(gamma(mu_hat), gamma(s_hat)).
 // Layer 1 is split: its transceiver part W1s gamma(s_hat) + b1 is the same for
 // every Gaussian of a query and is computed once per query (tx_features); its
-// mean part W1m gamma(mu_hat) (K = 26) runs per row. Every later layer is a
-// dense 256 x 256 contraction over the rows of the block.
+// mean part W1m gamma(mu_hat) (K = 26) runs per pair. Every later layer is a
+// dense 256 x 256 contraction per pair, on the FP32 matrix cores.
 #include "kernels.h"
 #include "swf_device.h"
 #include "mlp_common.h"

@@ -289,10 +289,8 @@ swf_status Ctx::upload_scene(const swf_gaussians* g, const swf_mlp* mlp, int H, 
 
 // The paper's model: raw parameters in id order (the sum has no order), the
 // FP64 centre map and its encoding on the device, and the paper MLP packed for
-// paper_mlp_kernel: per layer an in-major [K][160] array whose row k multiplies
-// column k0 + k of the kernel's [h (160) | x (96)] row (layer 1: the x part,
-// K = 96; plain layers: h, K = 160; skip layers 3, 5, 7: both, K = 256), every
-// pad row and column zero; the output layer [160][8].
+// paper_mlp_kernel in MFMA fragment order (layout below), every pad row and
+// column zero.
 swf_status Ctx::upload_paper_scene(const swf_paper_gaussians* g, const swf_paper_mlp* mlp, int H, int W, bool dev,
                                    int* id) {
     if (!g || !id || g->n < 0) return fail(SWF_E_INVALID, "null gaussians/id or n < 0");
