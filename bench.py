@@ -600,6 +600,13 @@ def bench_train(a):
     bwd_flop = Bq * N * 2 * 2 * (7 * 256 + 3 * 256 * 256)
     t_bwd = stages.get("mlp_backward", 0.0)
     ach = bwd_flop / (t_bwd * 1e-3) / 1e12 if t_bwd > 0 else None
+    # HBM bytes the MLP backward must move per pair (BF16 activations and gradients, 512 B per 256-row): dy read
+    # (7 FP32); the output layer reads the last activations and writes their gradient; the two upper 256 x 256
+    # layers read their output gradient and input activations and write their input gradient; the lowest one
+    # reads its output gradient and input activations (the first layer's gradient is reduced into per-Gaussian
+    # and per-query sums, never stored)
+    bwd_bytes = Bq * N * (28 + 2 * 512 + 2 * 3 * 512 + 2 * 512)
+    gbs = bwd_bytes / (t_bwd * 1e-3) / 1e9 if t_bwd > 0 else None
     rec = {
         "metric": "training steps/s at N=50k, batch 16, 90x360", "value": steps / el, "unit": "steps/s",
         "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps, "higher_is_better": True,
@@ -612,9 +619,14 @@ def bench_train(a):
         "latency_us": {"step_p50": 1e3 * pct(step_ms, 50), "step_p99": 1e3 * pct(step_ms, 99)},
         "stages_ms_per_step": stages,
         "roofline": {"kernel": "mlp_backward (BF16 layer GEMMs with FP32 accumulation, ReLU masks, column sums)",
-                     "bound": "mfma", "achieved": ach, "peak": PEAK["bf16"], "unit": "TFLOP/s",
-                     "frac": None if ach is None else ach / PEAK["bf16"], "traffic": None,
-                     "flop_per_step": bwd_flop, "avg_ms": t_bwd},
+                     "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": None if gbs is None else gbs / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_step": bwd_bytes, "avg_ms": t_bwd,
+                     "mfma": {"achieved": ach, "peak": PEAK["bf16"], "unit": "TFLOP/s",
+                              "frac": None if ach is None else ach / PEAK["bf16"], "flop_per_step": bwd_flop},
+                     "note": "5,148 B per pair: the rows the backward must read and write once each (BF16); the "
+                             "kernels read each layer's gradient and activations twice (weight and input gradient "
+                             "in separate passes), 7,220 B per pair"},
         "backward_reused_forward": reused[0],
         "deterministic_ms_per_step": det_ms,
         "fp32": {"ms_per_step": fp32_ms, "stages_ms_per_step": stages32,
