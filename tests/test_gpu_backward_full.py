@@ -1,7 +1,8 @@
 """Gradient parity at the training workload's size: N = 50,000 Gaussians, a
 batch of 16 spectra at 90x360, the 4 x 256 network (800k pairs: every
 multi-block path of the backward runs as in the training step), BF16 and FP32
-forwards, through the C ABI, against the oracle's FP64 analytic gradient (the
+forwards and the deterministic BF16 backward, through the C ABI, against the
+oracle's FP64 analytic gradient (the
 Sec. 3.2 blending rule differentiated with decisions held, through the Sec. 4.1
 kernel and the Sec. 4.2 deformation network).
 
@@ -89,13 +90,16 @@ def _compare(name, got, ref, bound):
     return ratio
 
 
-@pytest.mark.parametrize("mode", ["fp32", "bf16"])
+@pytest.mark.parametrize("mode", ["fp32", "bf16", "bf16-deterministic"])
 def test_training_size_gradient_within_derived_bounds(setup, mode):
+    # the deterministic backward (fixed-order sums of per-entry partials) is held to the same bounds: it sums the
+    # same terms as the atomic one, in another order
     import torch
     from paper_2506_12787_amd import binding as Bd
     ctx, sid, s, Ws, bs, tx = setup
-    bf16 = mode == "bf16"
+    bf16 = mode.startswith("bf16")
     flags = Bd.MLP_BF16 if bf16 else Bd.MLP_FP32
+    bwd_flags = flags | (Bd.DETERMINISTIC if mode.endswith("deterministic") else 0)
     print(f"training-size gradient, {mode}: N={N} B={B}", flush=True)
     deltas = ctx.debug_deform(sid, tx, flags).cpu().numpy().astype(np.float64)
     w, kept = _weights(s, deltas, seed=99 if bf16 else 98)
@@ -105,7 +109,7 @@ def test_training_size_gradient_within_derived_bounds(setup, mode):
     gr["weight"] = [torch.zeros(Wl.shape, device="cuda") for Wl in Ws]
     gr["bias"] = [torch.zeros(Wl.shape[0], device="cuda") for Wl in Ws]
     gw = torch.from_numpy(np.stack(w).astype(np.float32)).cuda()
-    ctx.render_backward(sid, tx, flags, gw, aux, gr)
+    ctx.render_backward(sid, tx, bwd_flags, gw, aux, gr)
     torch.cuda.synchronize()
     got = {k: (v.cpu().numpy() if not isinstance(v, list) else [x.cpu().numpy() for x in v]) for k, v in gr.items()}
     mlp = Hh.mlp_f64(Ws, bs)
