@@ -235,16 +235,19 @@ def test_radix_sort_matches_stable_sort(ctx, n, kind, bits):
     np.testing.assert_array_equal(tv.cpu().numpy().view(np.uint32), v[o])
 
 
-def _deform_problem(n, B, seed, out_scale):
+def _deform_problem(n, B, seed, out_scale, n_hidden=4):
     g, s = Hh.problem(n, H0, W0, seed=seed)
-    Ws, bs = synth.mlp_weights(seed=seed + 2000, out_scale=out_scale)
+    Ws, bs = synth.mlp_weights(seed=seed + 2000, out_scale=out_scale, n_hidden=n_hidden)
     rng = np.random.default_rng(seed)
     bs = [b + rng.normal(0, 0.05, b.shape).astype(np.float32) for b in bs]
     return g, s, Ws, bs
 
 
-def test_deform_residuals_fp32_match_oracle(ctx):
-    g, s, Ws, bs = _deform_problem(3000, 4, seed=41, out_scale=1.0)
+@pytest.mark.parametrize("n_hidden", [4, 3, 2, 1])
+def test_deform_residuals_fp32_match_oracle(ctx, n_hidden):
+    # depths 1..4: no hidden-to-hidden layer, one (the odd tail of the kernel's two-layer loop), two (the loop
+    # only) and three (loop and tail); 4 x 3001 pairs leave a ragged last wave (4 of its 16 pairs)
+    g, s, Ws, bs = _deform_problem(3001, 4, seed=41 + n_hidden, out_scale=1.0, n_hidden=n_hidden)
     sid = ctx.upload_scene(g, H0, W0, mlp=(Ws, bs))
     tx = _tx(4, 2041)
     d = ctx.debug_deform(sid, tx).cpu().numpy().astype(np.float64)
@@ -256,7 +259,7 @@ def test_deform_residuals_fp32_match_oracle(ctx):
         scale = np.abs(ref).max(axis=0)
         err = np.abs(d[b] - ref).max(axis=0) / scale
         worst = max(worst, err.max())
-    print("FP32 MLP residual normwise rel err", worst)
+    print(f"FP32 MLP residual normwise rel err (depth {n_hidden})", worst)
     assert worst < 2e-5
     ctx.release_scene(sid)
 
