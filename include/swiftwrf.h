@@ -67,7 +67,7 @@ enum {
 
 /* Render flags (bitwise or). */
 enum {
-    SWF_MLP_FP32 = 0,        /* deformation MLP in FP32 (FMA, FP32 accumulate)   */
+    SWF_MLP_FP32 = 0,        /* deformation MLP in FP32 (FP32 MFMA and sums)     */
     SWF_MLP_BF16 = 1 << 0,   /* deformation MLP on BF16 MFMA, FP32 accumulate    */
     SWF_NO_DEFORM = 1 << 1,  /* static render of the canonical Gaussians         */
     SWF_KEEP_AUX = 1 << 2,   /* write the per-pixel blend state `aux` (training) */
@@ -204,10 +204,11 @@ swf_status swf_render_at(swf_ctx *ctx, int32_t scene_id, const float *tx, int32_
  * float32, the batch's spectra concatenated in query order (query b's H_b x W_b
  * values start at out_offsets[b]); out_offsets (host, may be NULL) receives the
  * batch + 1 offsets (the last is the total). Every query renders exactly the
- * values swf_render gives it alone. flags: SWF_MLP_BF16 (every scene with a
- * 4 x 256 MLP) or SWF_NO_DEFORM, optionally SWF_PAPER_DEFORM; compositing-model
- * scenes only; lists are built by key sorting over every global tile of the
- * batch. SWF_E_INVALID for other flags or scenes, SWF_E_NOT_FOUND for an
+ * values swf_render gives it alone. flags: SWF_MLP_BF16 or SWF_MLP_FP32 (every
+ * scene with a 4 x 256 MLP) or SWF_NO_DEFORM, optionally SWF_PAPER_DEFORM;
+ * compositing-model scenes only; lists are built by binning per query (by key
+ * sorting over every global tile of the batch when the largest query grid is
+ * beyond the binning's tile limit). SWF_E_INVALID for other flags or scenes, SWF_E_NOT_FOUND for an
  * unknown scene. Waits once for the batch's key count, like swf_render; the
  * device status then describes the batch as one query holding every pair. */
 swf_status swf_render_mixed(swf_ctx *ctx, const int32_t *scene_ids, const float *tx, int32_t batch, int32_t flags,
@@ -530,7 +531,7 @@ swf_status swf_exclusive_scan_noalloc(swf_ctx *ctx, const uint32_t *counts, uint
  * never fit fails with SWF_E_OOM. Scenes must stay uploaded while served.
  * mixed = 1 batches across scenes: the waiting requests in arrival order, of
  * up to 64 distinct scenes sharing the oldest request's deformation mode (all
- * with a 4 x 256 MLP and SWF_MLP_BF16, or all static), go into one mixed batch
+ * with a 4 x 256 MLP, in the precision of flags, or all static), go into one mixed batch
  * (swf_render_mixed's launches); its graph is keyed by capacities (queries,
  * pairs, tiles, keys, rounded up to four steps per octave), not by scene, so
  * any mix of scenes whose totals fit replays it. Scenes a mixed batch cannot

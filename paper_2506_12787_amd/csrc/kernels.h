@@ -98,6 +98,7 @@ struct MixScene {
     const float *mx, *my, *lsx, *lsy, *rot, *logit, *amp;  // canonical parameters, (depth, id) order
     const float *w1, *b1;                                   // layer 1, row-major [256][89], for the TX term
     const uint16_t* stream;                                 // BF16 weight stream
+    const float* f32_frag;                                  // FP32 weights, fragment-major (frag_floats(4))
     const uint16_t* mfeat;                                  // BF16 gamma(mu_hat) [N][32]
     const float* bias_h[7];
     const float* bias_o;
@@ -156,6 +157,11 @@ void launch_mix_blend(const MixBatch& m, int tile_cap, const uint2* ranges, cons
 // mlp_bf16.hip: the BF16 MLP over the batch's tiles of pairs (the default 384-pair variant)
 void launch_mix_mlp_bf16(const MixBatch& m, const float* qs, const Records& r, hipStream_t st, bool paper_mask,
                          bool wrap);
+// The FP32 MLP over a mixed batch (every scene with four hidden layers of 256): every 16-pair group of the batch's
+// 384-pair MLP tiles, at most pair_cap pairs over B_cap queries (graph-capturable: the batch's totals are read from
+// its tables).
+void launch_mix_mlp_fp32(const MixBatch& m, const float* qs, const Records& r, int64_t pair_cap, int B_cap,
+                         hipStream_t st, bool paper_mask, bool wrap);
 
 // paper.hip
 void launch_paper_centers(const DevScene& d, hipStream_t st);

@@ -68,26 +68,6 @@ struct Bf16Args {
     MixBatch mix;             // kMix: the batch's scene and query tables (per tile: query, scene, stream, biases)
 };
 
-// Records of a mixed batch's pair: residuals -> deformed Gaussian -> record, with the pair's own scene.
-__device__ __forceinline__ void mix_epilogue(const MixScene& s, const MlpArgs& a, size_t row, int p, const float* d) {
-    float dv[kOut];
-#pragma unroll
-    for (int k = 0; k < kOut; ++k) dv[k] = d[k];
-    if (a.paper_mask) dv[2] = dv[3] = dv[4] = 0.0f;
-    PairOut o;
-    if (p < s.n_live) {
-        o = preprocess_pair(s.mx[p], s.my[p], dv[0], dv[1], s.lsx[p] + dv[2], s.lsy[p] + dv[3], s.rot[p] + dv[4],
-                            s.logit[p] + dv[5], s.amp[p] + dv[6], s.W, s.H, s.TW, s.TH, a.inv_tile, a.wrap);
-    } else {
-        o.geo = make_float4(0, 0, 0, 0);
-        o.wm = make_float4(0, 0, 0, 0);
-        o.oa = make_float2(0, 0);
-        o.rect_x = o.rect_y = 0;
-        o.count = 0;
-    }
-    write_record(a.rec, row, o);
-}
-
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }

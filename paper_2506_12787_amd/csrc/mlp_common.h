@@ -60,6 +60,26 @@ __device__ __forceinline__ void deform_epilogue(const MlpArgs& a, size_t row, in
     if (a.rec.geo) write_record(a.rec, row, o);
 }
 
+// Records of a mixed batch's pair: residuals -> deformed Gaussian -> record, with the pair's own scene.
+__device__ __forceinline__ void mix_epilogue(const MixScene& s, const MlpArgs& a, size_t row, int p, const float* d) {
+    float dv[kOut];
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) dv[k] = d[k];
+    if (a.paper_mask) dv[2] = dv[3] = dv[4] = 0.0f;
+    PairOut o;
+    if (p < s.n_live) {
+        o = preprocess_pair(s.mx[p], s.my[p], dv[0], dv[1], s.lsx[p] + dv[2], s.lsy[p] + dv[3], s.rot[p] + dv[4],
+                            s.logit[p] + dv[5], s.amp[p] + dv[6], s.W, s.H, s.TW, s.TH, a.inv_tile, a.wrap);
+    } else {
+        o.geo = make_float4(0, 0, 0, 0);
+        o.wm = make_float4(0, 0, 0, 0);
+        o.oa = make_float2(0, 0);
+        o.rect_x = o.rect_y = 0;
+        o.count = 0;
+    }
+    write_record(a.rec, row, o);
+}
+
 inline MlpArgs make_args(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
                   float* delta_out) {
     MlpArgs a{};

@@ -106,20 +106,58 @@ __device__ __forceinline__ void f32_mfma_layer(const float4* __restrict__ wf, co
     }
 }
 
-__global__ __launch_bounds__(64 * kFWaves, 3) void mlp_fp32_kernel(MlpArgs a) {
+// kMix: the queries of a mixed batch, each with its own scene (parameters, grid
+// and weights). A wave's 16 pairs lie in one 384-pair MLP tile of one query
+// (the tiling of the batch's tables: a query's pairs padded to whole tiles), so
+// every pair of a wave takes the same weights; waves past the batch's tiles or
+// past their query's pairs do nothing.
+constexpr int kMixGroups = 24;  // 16-pair groups per 384-pair MLP tile of a mixed batch
+
+template <bool kMix>
+__global__ __launch_bounds__(64 * kFWaves, 3) void mlp_fp32_kernel(MlpArgs a, MixBatch mix) {
     __shared__ float outv[kFWaves][16][8];
     const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const int g = lane >> 4;
-    const size_t total = (size_t)a.N * a.B;
-    const size_t p0 = ((size_t)blockIdx.x * kFWaves + wave) * 16;
-    if (p0 < total) {  // wave-uniform
-        const size_t row = p0 + (lane & 15);
-        const bool in = row < total;
-        const int p = in ? (int)(row % a.N) : 0, b = in ? (int)(row / a.N) : 0;
+    // the wave's 16 pairs: this lane's record row and its index p in the scene; rows past the query are computed
+    // on index 0 and not written
+    bool active;  // wave-uniform
+    size_t row = 0;
+    int p = 0, npairs = 0;
+    const MixScene* sc = nullptr;
+    const float* qrow = nullptr;  // the layer-1 bias of the lane's query (its TX term)
+    if constexpr (kMix) {
+        const int gw = (int)blockIdx.x * kFWaves + wave;
+        const int tile = gw / kMixGroups;
+        active = tile < mix.queries[mix.B].mlp_tile_base;
+        if (active) {
+            const int q = mix_find(mix.queries, mix.B, tile, [](const MixQuery& x) { return x.mlp_tile_base; });
+            sc = &mix.scenes[mix.queries[q].scene];
+            const int pb = (tile - mix.queries[q].mlp_tile_base) * (16 * kMixGroups) + (gw % kMixGroups) * 16;
+            npairs = sc->N;
+            active = pb < npairs;
+            p = pb + (lane & 15);
+            row = (size_t)mix.queries[q].pair_base + p;
+            qrow = a.qs + (size_t)q * 256;
+        }
+    } else {
+        const size_t total = (size_t)a.N * a.B;
+        const size_t p0 = ((size_t)blockIdx.x * kFWaves + wave) * 16;
+        active = p0 < total;
+        row = p0 + (lane & 15);
+        npairs = row < total ? a.N : 0;  // a row past the batch: no pair
+        p = row < total ? (int)(row % a.N) : 0;
+        qrow = a.qs + (size_t)(row < total ? row / a.N : 0) * 256;
+    }
+    const bool in = kMix ? p < npairs : npairs > 0;
+    if (!in) p = 0;
+    if (active) {
         float x[8];
         {
             float f[kMeanFeat];
-            mean_features(a.mx[p], a.my[p], a.sW, a.sH, f);
+            if constexpr (kMix)
+                mean_features(sc->mx[p], sc->my[p], sc->W, sc->H, f);
+            else
+                mean_features(a.mx[p], a.my[p], a.sW, a.sH, f);
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 const float v0 = 4 * c < kMeanFeat ? f[4 * c] : 0.0f;
@@ -129,32 +167,44 @@ __global__ __launch_bounds__(64 * kFWaves, 3) void mlp_fp32_kernel(MlpArgs a) {
                 x[c] = g == 0 ? v0 : (g == 1 ? v1 : (g == 2 ? v2 : v3));
             }
         }
+        // the network's weights: the batch's scene (kMix, four hidden layers) or the launch's
+        const float* frag = kMix ? sc->f32_frag : nullptr;
+        const int n_mid = kMix ? 3 : a.n_mid;
+        const auto WH = [&](int l) -> const float4* {
+            return kMix ? reinterpret_cast<const float4*>(frag + frag_hidden_at(l + 1)) : a.wfh[l];
+        };
+        const auto BH = [&](int l) -> const float* { return kMix ? sc->bias_h[l] : a.bh[l]; };
+        const float4* wf1 = kMix ? reinterpret_cast<const float4*>(frag) : a.wf1;
+        const float4* wfo = kMix ? reinterpret_cast<const float4*>(frag + frag_out_at(4)) : a.wfo;
+        const float* bo16 = kMix ? frag + frag_out_at(4) + kFragOut : a.bo16;
         const auto st_of = [&](int l) -> float* {
-            return (in && a.act_out[l]) ? a.act_out[l] + row * 256 : nullptr;
+            return (!kMix && in && a.act_out[l]) ? a.act_out[l] + row * 256 : nullptr;
         };
         float hA[64], hB[64];
-        f32_mfma_layer<16, 8, true>(a.wf1, a.qs + (size_t)b * 256, lane, x, hA, st_of(0));
+        f32_mfma_layer<16, 8, true>(wf1, qrow, lane, x, hA, st_of(0));
         int l = 0;
-        for (; l + 2 <= a.n_mid; l += 2) {
-            f32_mfma_layer<16, 64, true>(a.wfh[l], a.bh[l], lane, hA, hB, st_of(l + 1));
-            f32_mfma_layer<16, 64, true>(a.wfh[l + 1], a.bh[l + 1], lane, hB, hA, st_of(l + 2));
+        for (; l + 2 <= n_mid; l += 2) {
+            f32_mfma_layer<16, 64, true>(WH(l), BH(l), lane, hA, hB, st_of(l + 1));
+            f32_mfma_layer<16, 64, true>(WH(l + 1), BH(l + 1), lane, hB, hA, st_of(l + 2));
         }
-        if (l < a.n_mid) {
-            f32_mfma_layer<16, 64, true>(a.wfh[l], a.bh[l], lane, hA, hB, st_of(l + 1));
+        if (l < n_mid) {
+            f32_mfma_layer<16, 64, true>(WH(l), BH(l), lane, hA, hB, st_of(l + 1));
 #pragma unroll
             for (int k = 0; k < 64; ++k) hA[k] = hB[k];
         }
         // output layer: lane l holds outputs 4 (l / 16) + i of pair l % 16
-        f32_mfma_layer<1, 64, false>(a.wfo, a.bo16, lane, hA, hB, nullptr);
+        f32_mfma_layer<1, 64, false>(wfo, bo16, lane, hA, hB, nullptr);
         if (g < 2) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) outv[wave][lane & 15][4 * g + i] = hB[i];
         }
     }
     __syncthreads();
-    if (p0 < total && lane < 16) {
-        const size_t row = p0 + lane;
-        if (row < total) deform_epilogue(a, row, (int)(row % a.N), outv[wave][lane]);
+    if (active && lane < 16 && in) {  // lanes 0..15 hold the wave's 16 pairs (lane l: pair l)
+        if constexpr (kMix)
+            mix_epilogue(*sc, a, row, p, outv[wave][lane]);
+        else
+            deform_epilogue(a, row, p, outv[wave][lane]);
     }
 }
 
@@ -225,7 +275,21 @@ void launch_mlp_fp32(const DevScene& s, const float* qs, int B, const Grid& g, b
     const size_t total = (size_t)s.n * B;
     const size_t per_block = (size_t)kFWaves * 16;
     const unsigned blocks = (unsigned)((total + per_block - 1) / per_block);
-    if (blocks) mlp_fp32_kernel<<<blocks, 64 * kFWaves, 0, st>>>(a);
+    if (blocks) mlp_fp32_kernel<false><<<blocks, 64 * kFWaves, 0, st>>>(a, MixBatch{});
+}
+
+void launch_mix_mlp_fp32(const MixBatch& m, const float* qs, const Records& r, int64_t pair_cap, int B_cap,
+                         hipStream_t st, bool paper_mask, bool wrap) {
+    // every 384-pair tile the batch can hold (its pairs, each query padded to whole tiles)
+    const int64_t tiles = (pair_cap + 383) / 384 + B_cap;
+    const int64_t blocks = (tiles * kMixGroups + kFWaves - 1) / kFWaves;
+    MlpArgs a{};
+    a.qs = qs;
+    a.rec = r;
+    a.inv_tile = 1.0f / 16.0f;
+    a.paper_mask = paper_mask ? 1 : 0;
+    a.wrap = wrap ? 1 : 0;
+    if (blocks > 0) mlp_fp32_kernel<true><<<(unsigned)blocks, 64 * kFWaves, 0, st>>>(a, m);
 }
 
 void launch_preprocess_static(const DevScene& s, int B, const Grid& g, const Records& r, hipStream_t st) {

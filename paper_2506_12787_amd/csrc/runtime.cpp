@@ -882,8 +882,8 @@ swf_status Ctx::plan_mixed(Workspace& w, const int32_t* scene_ids, int B, int fl
     if (B < 1 || B > 65535 || B_cap < B || !scene_ids) return fail(SWF_E_INVALID, "bad batch or scene ids");
     const bool deform = !(flags & SWF_NO_DEFORM);
     if (flags & ~(SWF_MLP_BF16 | SWF_NO_DEFORM | SWF_PAPER_DEFORM))
-        return fail(SWF_E_INVALID, "mixed batches take SWF_MLP_BF16 or SWF_NO_DEFORM (and SWF_PAPER_DEFORM)");
-    if (deform && !(flags & SWF_MLP_BF16)) return fail(SWF_E_INVALID, "mixed batches deform with the BF16 MLP");
+        return fail(SWF_E_INVALID, "mixed batches take SWF_MLP_BF16 (else the FP32 MLP) or SWF_NO_DEFORM, and "
+                                   "SWF_PAPER_DEFORM");
     std::vector<MixScene> sc;
     std::map<int, int> index;
     std::vector<MixQuery> q(B_cap + 1);
@@ -904,6 +904,7 @@ swf_status Ctx::plan_mixed(Workspace& w, const int32_t* scene_ids, int B, int fl
             m.w1 = d.w[0];
             m.b1 = d.b[0];
             m.stream = d.bf_stream;
+            m.f32_frag = d.f32_frag;
             m.mfeat = d.bf_mfeat;
             for (int l = 0; l + 1 < d.n_hidden && l < 7; ++l) m.bias_h[l] = d.b[l + 1];
             m.bias_o = d.has_mlp ? d.b[d.n_hidden] : nullptr;
@@ -1011,7 +1012,11 @@ swf_status Ctx::enqueue_mixed(Workspace& w, const MixPlan& p, const float* tx, i
     if (deform) {
         if ((s = w.qs.reserve(this, (size_t)p.B_cap * 256 * sizeof(float), st))) return s;
         launch_mix_tx_features(mb, tx, (float*)w.qs.ptr, st);
-        launch_mix_mlp_bf16(mb, (const float*)w.qs.ptr, w.rec, st, (flags & SWF_PAPER_DEFORM) != 0, false);
+        if (flags & SWF_MLP_BF16)
+            launch_mix_mlp_bf16(mb, (const float*)w.qs.ptr, w.rec, st, (flags & SWF_PAPER_DEFORM) != 0, false);
+        else
+            launch_mix_mlp_fp32(mb, (const float*)w.qs.ptr, w.rec, pair_cap, k.B_cap, st,
+                                (flags & SWF_PAPER_DEFORM) != 0, false);
         // rows past the batch's pairs: no tiles (the scan of the sort path reads them)
         if (!binned) launch_mix_clear_tail(mb, pair_cap, w.rec, st);
     } else {

@@ -341,16 +341,16 @@ static void finish_slot(Ctx* c, ServeState* S, Slot* sl) {
     S->cv.notify_all();
 }
 
-// Mixed mode of a scene: 1 deformable (a 4 x 256 MLP, BF16), 0 static (no MLP),
-// -1 served per scene (another MLP shape or model, or flags a mixed batch does
-// not take), -2 unknown.
+// Mixed mode of a scene: 1 deformable (a 4 x 256 MLP, in the server's precision),
+// 0 static (no MLP), -1 served per scene (another MLP shape or model, or flags a
+// mixed batch does not take), -2 unknown.
 static int mix_mode(Ctx* c, const ServeState* S, int id) {
     Scene* sc = c->scene(id);
     if (!sc) return -2;
     const DevScene& d = sc->d;
     if (d.kind != 0 || (S->cfg.flags & SWF_TILE8)) return -1;
     if (!d.has_mlp) return 0;
-    return (d.n_hidden == 4 && d.hidden == 256 && (S->cfg.flags & SWF_MLP_BF16)) ? 1 : -1;
+    return (d.n_hidden == 4 && d.hidden == 256) ? 1 : -1;
 }
 
 // Grow a slot's pinned output staging to n floats.
@@ -485,8 +485,7 @@ static int admit_mixed(Ctx* c, ServeState* S, Slot* sl) {
             st = c->hip(hipMemcpyAsync(sl->tx_dev.ptr, r->tx, 3 * sizeof(float), hipMemcpyHostToDevice, sl->stream),
                         "calibration tx");
         if (!st)
-            st = c->forward_lists(S->cal, r->scene, (const float*)sl->tx_dev.ptr, 1, mode ? SWF_MLP_BF16 : SWF_NO_DEFORM,
-                                  sl->stream, 0);
+            st = c->forward_lists(S->cal, r->scene, (const float*)sl->tx_dev.ptr, 1, flags, sl->stream, 0);
         if (!st) S->keys_per_query[r->scene] = std::max<uint64_t>(S->cal.last.n_keys, 1);
         calibrated = true;
     }

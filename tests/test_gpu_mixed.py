@@ -1,8 +1,8 @@
 """Mixed batches (swf_render_mixed): queries over several resident scenes with
 different Gaussian counts, grids and MLPs in one launch sequence. Every query
 must render bitwise what it renders alone (whose parity with the oracle the
-other tests hold), BF16-deformed and static; the device status counts every
-pair of the batch."""
+other tests hold), BF16- and FP32-deformed and static; the device status counts
+every pair of the batch."""
 import numpy as np
 import pytest
 
@@ -27,15 +27,16 @@ def setup():
     ctx.close()
 
 
-@pytest.mark.parametrize("static", [False, True], ids=["bf16", "static"])
-def test_mixed_batch_equals_alone(setup, static):
+@pytest.mark.parametrize("mode", ["bf16", "fp32", "static"])
+def test_mixed_batch_equals_alone(setup, mode):
     import torch
     from paper_2506_12787_amd import binding as B
     ctx, sids = setup
     order = [0, 1, 2, 1, 3, 0, 2, 1, 3, 3, 0]
     ids = [sids[k] for k in order]
     tx = torch.from_numpy(synth.tx_positions(len(ids), seed=2260)).cuda()
-    flags = B.NO_DEFORM if static else B.MLP_BF16
+    static = mode == "static"
+    flags = {"bf16": B.MLP_BF16, "fp32": B.MLP_FP32, "static": B.NO_DEFORM}[mode]
     mixed = ctx.render_mixed(ids, None if static else tx, flags=flags)
     total_pairs = 0
     for b, sid in enumerate(ids):
@@ -69,7 +70,7 @@ def test_mixed_batch_rejects_what_it_does_not_take(setup):
     from paper_2506_12787_amd import binding as B
     ctx, sids = setup
     tx = torch.from_numpy(synth.tx_positions(2, seed=2262)).cuda()
-    for f in (B.MLP_FP32, B.MLP_BF16 | B.KEEP_AUX, B.MLP_BF16 | B.WRAP_AZIMUTH):
+    for f in (B.MLP_BF16 | B.KEEP_AUX, B.MLP_BF16 | B.WRAP_AZIMUTH, B.MLP_FP32 | B.TILE8):
         with pytest.raises(B.SwfError):
             ctx.render_mixed([sids[0], sids[1]], tx, flags=f)
     with pytest.raises(B.SwfError):
@@ -87,7 +88,7 @@ def test_mixed_batch_sort_path_for_large_grids(setup):
     big = ctx.upload_scene(g, H, W, mlp=synth.mlp_weights(seed=3270))
     ids = [big, sids[2], sids[0], big, sids[3]]
     tx = torch.from_numpy(synth.tx_positions(len(ids), seed=2270)).cuda()
-    for flags in (B.MLP_BF16, B.NO_DEFORM):
+    for flags in (B.MLP_BF16, B.MLP_FP32, B.NO_DEFORM):
         t = None if flags == B.NO_DEFORM else tx
         mixed = ctx.render_mixed(ids, t, flags=flags)
         for b, sid in enumerate(ids):

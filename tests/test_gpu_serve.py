@@ -78,6 +78,25 @@ def test_mixed_mode_batches_across_scenes(setup, graphs):
     print("counters", cnt)
 
 
+def test_mixed_mode_fp32_batches_across_scenes(setup):
+    # a server at the paper's precision (FP32 MLP) batches across scenes too; every result is what the query renders
+    # alone with the FP32 MLP
+    import torch
+    from paper_2506_12787_amd import binding as B
+    c, sids, reqs, _ = setup
+    alone32 = []
+    for si, tx in reqs:
+        t = torch.from_numpy(tx[None].copy()).cuda()
+        alone32.append(c.render(sids[si], t, flags=B.MLP_FP32)[0].cpu().numpy())
+    outs, stats, cnt = _serve_all(c, sids, reqs, max_batch=16, n_slots=2, flags=B.MLP_FP32, mixed=True)
+    for i, (o, a) in enumerate(zip(outs, alone32)):
+        np.testing.assert_array_equal(o, a, err_msg=f"request {i}")
+    assert cnt["completed"] == len(reqs)
+    assert cnt["mixed_launches"] == cnt["launches"] >= 1
+    assert cnt["mixed_scenes"] > cnt["mixed_launches"]
+    print("counters", cnt)
+
+
 def test_mixed_mode_keeps_static_scenes_apart(setup):
     # a scene without an MLP renders statically: it never shares a launch with the deformable scenes, and its
     # requests still come back right
