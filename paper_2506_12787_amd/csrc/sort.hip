@@ -502,8 +502,9 @@ __global__ __launch_bounds__(kThreads) void bin_place_kernel(const uint2* __rest
     static_assert(kSeg == kThreads, "one tile per thread in the per-tile steps");
     // fixed-capacity run that overflowed: nothing is placed (block-uniform)
     if (n_dev && *n_dev == 0) return;
-    __shared__ unsigned long long mask[kSeg][kWords];  // bit p: pair p of the batch covers the tile
-    __shared__ uint32_t pre[kSeg][kWords];             // pairs covering the tile in the words before
+    // word-major, so the tiles of consecutive keys (consecutive tiles) fall on consecutive banks
+    __shared__ unsigned long long mask[kWords][kSeg];  // bit p of word w: pair 64 w + p of the batch covers the tile
+    __shared__ uint32_t pre[kWords][kSeg];             // pairs covering the tile in the words before
     __shared__ uint32_t base[kSeg];
     __shared__ uint32_t lds[kWaves + 1];
     __shared__ uint32_t s_o[kBatch], s_w[kBatch];
@@ -517,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void bin_place_kernel(const uint2* __rest
     const int TW = Q.TW;
     base[t] = hs[(((size_t)q * G.nbq + j) << 8) + t] + starts[((size_t)q << 8) + t];
 #pragma unroll
-    for (int k = 0; k < kWords; ++k) mask[t][k] = 0ull;
+    for (int k = 0; k < kWords; ++k) mask[k][t] = 0ull;
     uint32_t c_next = 0u;
     uint2 r_next = make_uint2(0u, 0u);
     if (p_beg + t < p_end) {
@@ -569,7 +570,7 @@ __global__ __launch_bounds__(kThreads) void bin_place_kernel(const uint2* __rest
                     const uint32_t d = (uint32_t)((s_ty0[lo] + (int)qr) * TW + (col < TW ? col : col - TW));
                     dig[i] = d;
                     own[i] = (uint32_t)lo;
-                    atomicOr(&mask[d][lo >> 6], 1ull << (lo & 63));
+                    atomicOr(&mask[lo >> 6][d], 1ull << (lo & 63));
                 }
             }
             __syncthreads();
@@ -577,8 +578,8 @@ __global__ __launch_bounds__(kThreads) void bin_place_kernel(const uint2* __rest
                 uint32_t run = 0;
 #pragma unroll
                 for (int k = 0; k < kWords; ++k) {
-                    pre[t][k] = run;
-                    run += (uint32_t)__popcll(mask[t][k]);
+                    pre[k][t] = run;
+                    run += (uint32_t)__popcll(mask[k][t]);
                 }
             }
             __syncthreads();
@@ -586,8 +587,8 @@ __global__ __launch_bounds__(kThreads) void bin_place_kernel(const uint2* __rest
             for (int i = 0; i < kItems; ++i) {
                 if (own[i] < (uint32_t)kBatch) {
                     const uint32_t d = dig[i], lo = own[i];
-                    const uint32_t rank = pre[d][lo >> 6] +
-                                          (uint32_t)__popcll(mask[d][lo >> 6] & ((1ull << (lo & 63)) - 1ull));
+                    const uint32_t rank = pre[lo >> 6][d] +
+                                          (uint32_t)__popcll(mask[lo >> 6][d] & ((1ull << (lo & 63)) - 1ull));
                     vals[base[d] + rank] = (uint32_t)(row0 + s0 + lo);
                 }
             }
@@ -596,8 +597,8 @@ __global__ __launch_bounds__(kThreads) void bin_place_kernel(const uint2* __rest
         uint32_t tot = 0;
 #pragma unroll
         for (int k = 0; k < kWords; ++k) {
-            tot += (uint32_t)__popcll(mask[t][k]);
-            mask[t][k] = 0ull;
+            tot += (uint32_t)__popcll(mask[k][t]);
+            mask[k][t] = 0ull;
         }
         base[t] += tot;  // the next batch's scan synchronises before anything reads base or the masks
     }
