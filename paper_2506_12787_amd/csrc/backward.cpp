@@ -42,8 +42,10 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
                                           (size_t)colsum_blocks(wgrad_mfma_blocks(P)) * (Hd * Hd + Hd),
                                           (size_t)colsum_blocks(wgrad_out_blocks(P)) * kOut * Hd});
     const size_t n_wb = bf16 ? ((size_t)(nh - 1) * Hd * Hd + (size_t)kOut * Hd + (size_t)P * kOut + 64) / 2 + 64 : 0;
+    const size_t n_wt = bf16 ? 0 : (size_t)(nh - 1) * Hd * Hd;  // FP32: W^T of the 256 x 256 layers, fragment-major
     const size_t small =
-        ((size_t)N * Hd + (size_t)B * Hd + (size_t)N * kMeanFeat + 4 + n_split + n_cs + n_wb + 64) * sizeof(float);
+        ((size_t)N * Hd + (size_t)B * Hd + (size_t)N * kMeanFeat + 4 + n_split + n_cs + n_wb + n_wt + 64) *
+        sizeof(float);
     if ((s = w.part.reserve(this, small, st))) return s;
     if ((s = w.fmean.reserve(this, (size_t)N * kMeanFeat * sizeof(float) + 16, st))) return s;
     if ((s = w.ftx.reserve(this, (size_t)B * kTxFeat * sizeof(float) + 16, st))) return s;
@@ -59,6 +61,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
     float* part = dg + ((size_t)N * kMeanFeat + 3) / 4 * 4;  // split-K partials (16-byte aligned)
     float* tmp = part + n_split;                 // column-sum partials
     uint16_t* wb = (uint16_t*)(tmp + n_cs);      // BF16 weights: hidden layers 1.., output, then dy
+    float* wt = (float*)(((uintptr_t)(tmp + n_cs + n_wb) + 15) & ~(uintptr_t)15);  // FP32 W^T, 16-byte aligned
     float* fmean = (float*)w.fmean.ptr, *ftx = (float*)w.ftx.ptr, *qs = (float*)w.qs.ptr;
     launch_tx_features(d, tx, B, qs, st, ftx);
     launch_mean_features_f32(d, fmean, st);
@@ -75,6 +78,8 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
             dyb = wl[nh] + (size_t)kOut * Hd;
             launch_to_bf16(dy, P * kOut, dyb, st);
         }
+    } else {
+        for (int l = 1; l < nh; ++l) launch_pack_wt(d.w[l], wt + (size_t)(l - 1) * Hd * Hd, st);
     }
     // ---- output layer (7 outputs)
     if (bf16) {
@@ -115,8 +120,9 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
             else
                 dz1 = dz[cur];
         } else {
-            launch_gemm_f32(false, false, P, Hd, Hd, dz[cur], Hd, d.w[l], Hd, (float*)dz[cur ^ 1], Hd, part, st,
-                            (const float*)act[l - 1], Hd);
+            // the input gradient on the FP32 matrix cores with the layer's W^T as register-fed weights, masked
+            launch_dz_f32((const float*)dz[cur], wt + (size_t)(l - 1) * Hd * Hd, (const float*)act[l - 1], P,
+                          (float*)dz[cur ^ 1], st);
         }
         cur ^= 1;
     }

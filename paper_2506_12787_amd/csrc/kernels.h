@@ -176,6 +176,10 @@ void launch_gmm_blend(const uint2* ranges, const uint32_t* vals, const Records& 
 // pe_mlp.hip
 void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hipStream_t st,
                         float* feat_out = nullptr);
+// FP32 backward of a 256 x 256 layer on the FP32 matrix cores: wt = W^T packed fragment-major (65536 floats, from
+// W [256][256] row-major); out [P][256] = (dz [P][256] W) masked by act [P][256] > 0.
+void launch_pack_wt(const float* w, float* wt, hipStream_t st);
+void launch_dz_f32(const float* dz, const float* wt, const float* act, int64_t P, float* out, hipStream_t st);
 void launch_mlp_fp32(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
                      float* delta_out, hipStream_t st, float* const* act_out = nullptr);
 void launch_preprocess_static(const DevScene& s, int B, const Grid& g, const Records& r, hipStream_t st);

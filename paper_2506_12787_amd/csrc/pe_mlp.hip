@@ -72,9 +72,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kFWaves = 4;     // waves per block, 16 pairs each
 constexpr int kPrefetch = 2;   // weight fragments in flight ahead of the one in use
 
+// store (optional): the lane's 16-byte slice of each output tile; mask (optional, with store): stored values
+// are zeroed where mask <= 0 (read at the tile's start, its latency under the tile's instructions).
 template <int kTiles, int kIn, bool kRelu>
 __device__ __forceinline__ void f32_mfma_layer(const float4* __restrict__ wf, const float* brow, int lane,
-                                               const float (&hin)[kIn], float (&hout)[64], float* store) {
+                                               const float (&hin)[kIn], float (&hout)[64], float* store,
+                                               const float* mask = nullptr) {
     constexpr int G = kIn / 4;  // fragments per output tile
     constexpr int F = kTiles * G;
     const int g = lane >> 4;
@@ -85,6 +88,8 @@ __device__ __forceinline__ void f32_mfma_layer(const float4* __restrict__ wf, co
     for (int t = 0; t < kTiles; ++t) {
         const float4 b4 = *reinterpret_cast<const float4*>(brow + 16 * t + 4 * g);
         f32x4 acc = f32x4{b4.x, b4.y, b4.z, b4.w};
+        const float4 mk = mask ? *reinterpret_cast<const float4*>(mask + 16 * t + 4 * g)
+                               : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
 #pragma unroll
         for (int q = 0; q < G; ++q) {
             const int f = t * G + q;
@@ -102,7 +107,8 @@ __device__ __forceinline__ void f32_mfma_layer(const float4* __restrict__ wf, co
         for (int i = 0; i < 4; ++i) hout[4 * t + i] = kRelu ? fmaxf(acc[i], 0.0f) : acc[i];
         if (store)
             *reinterpret_cast<float4*>(store + 16 * t + 4 * g) =
-                make_float4(hout[4 * t], hout[4 * t + 1], hout[4 * t + 2], hout[4 * t + 3]);
+                make_float4(mk.x > 0.0f ? hout[4 * t] : 0.0f, mk.y > 0.0f ? hout[4 * t + 1] : 0.0f,
+                            mk.z > 0.0f ? hout[4 * t + 2] : 0.0f, mk.w > 0.0f ? hout[4 * t + 3] : 0.0f);
     }
 }
 
@@ -208,6 +214,48 @@ __global__ __launch_bounds__(64 * kFWaves, 3) void mlp_fp32_kernel(MlpArgs a, Mi
     }
 }
 
+// Input gradient of a 256 x 256 layer of the FP32 backward on the same matrix
+// cores: out[p][i] = [act[p][i] > 0] sum_o W[o][i] dz[p][o], the layer function
+// above with W^T as its weights (fragment-major, packed by pack_wt_kernel) and
+// no bias. A wave takes 16 pairs; lane l = 16 g + r loads input chunk 4 q + j
+// (input 16 q + 4 g + j) of pair r as one 16-byte load per q, and stores the
+// masked output tile t (units 16 t + 4 g + i) with one 16-byte store.
+__device__ float kZeroBias[256];  // zero-initialised: the layer's bias
+
+__global__ __launch_bounds__(64 * kFWaves, 3) void dz_f32_kernel(const float* __restrict__ dz,
+                                                                 const float4* __restrict__ wt,
+                                                                 const float* __restrict__ act, int64_t P,
+                                                                 float* __restrict__ out) {
+    const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+    const int g = lane >> 4;
+    const int64_t p0 = ((int64_t)blockIdx.x * kFWaves + wave) * 16;
+    if (p0 >= P) return;  // wave-uniform; the kernel has no barrier
+    const int64_t row = p0 + (lane & 15);
+    const bool in = row < P;
+    float hin[64], hout[64];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const float4 v = in ? *reinterpret_cast<const float4*>(dz + row * 256 + 16 * q + 4 * g)
+                            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        hin[4 * q] = v.x;
+        hin[4 * q + 1] = v.y;
+        hin[4 * q + 2] = v.z;
+        hin[4 * q + 3] = v.w;
+    }
+    f32_mfma_layer<16, 64, false>(wt, kZeroBias, lane, hin, hout, in ? out + row * 256 : nullptr,
+                                  in ? act + row * 256 : nullptr);
+}
+
+// W^T of a 256 x 256 layer (W row-major [out][in]) in the fragment order of
+// f32_mfma_layer: fragment q of output tile t, lane l = 16 g + r, element j
+// holds W^T[16 t + r][16 q + 4 g + j] = W[16 q + 4 g + j][16 t + r].
+__global__ void pack_wt_kernel(const float* __restrict__ w, float* __restrict__ wt) {
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= 65536) return;
+    const int t = e / 4096, q = (e / 256) % 16, l = (e / 4) % 64, j = e % 4;
+    wt[e] = w[(size_t)(16 * q + 4 * (l >> 4) + j) * 256 + 16 * t + (l & 15)];
+}
+
 __global__ void preprocess_static_kernel(MlpArgs a) {
     const size_t row = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t total = (size_t)a.N * a.B;
@@ -303,6 +351,15 @@ void launch_permute_delta(const float* delta_sorted, const uint32_t* perm, int B
                           hipStream_t st) {
     const size_t total = (size_t)B * n;
     if (total) permute_delta_kernel<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(delta_sorted, perm, B, n, delta_out);
+}
+
+void launch_pack_wt(const float* w, float* wt, hipStream_t st) { pack_wt_kernel<<<256, 256, 0, st>>>(w, wt); }
+
+void launch_dz_f32(const float* dz, const float* wt, const float* act, int64_t P, float* out, hipStream_t st) {
+    const int64_t per_block = (int64_t)kFWaves * 16;
+    if (P > 0)
+        dz_f32_kernel<<<(unsigned)((P + per_block - 1) / per_block), 64 * kFWaves, 0, st>>>(
+            dz, reinterpret_cast<const float4*>(wt), act, P, out);
 }
 
 }  // namespace swf
