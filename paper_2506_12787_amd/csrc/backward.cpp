@@ -36,7 +36,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
                                      (size_t)layer1_sums_blocks((int)N) * B * Hd,
                                      (size_t)layer1_grad_blocks((int)N) * B * Hd,
                                      (size_t)wgrad_mfma_blocks(P) * (Hd * Hd + Hd),
-                                     (size_t)wgrad_out_blocks(P) * kOut * Hd});
+                                     (size_t)wgrad_out_blocks(P) * kOut * Hd, (size_t)dz_f32_blocks(P) * Hd});
     const size_t n_cs = std::max<size_t>({(size_t)colsum_blocks(P) * Hd, (size_t)colsum_blocks(B) * N * Hd,
                                           (size_t)colsum_blocks(N) * Hd * B,
                                           (size_t)colsum_blocks(wgrad_mfma_blocks(P)) * (Hd * Hd + Hd),
@@ -106,12 +106,7 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
             else
                 launch_gemm_f32(true, false, Hd, Hd, P, dz[cur], Hd, act[l - 1], Hd, gr->weight[l], Hd, part, st);
         }
-        if (gr->bias[l] && !(bf16 && gr->weight[l])) {
-            if (bf16)
-                launch_colsum_bf16(dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
-            else
-                launch_colsum((const float*)dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
-        }
+        if (bf16 && gr->bias[l] && !gr->weight[l]) launch_colsum_bf16(dz[cur], P, Hd, 1, 0, tmp, gr->bias[l], 0, st);
         if (bf16) {
             // dz W on MFMA in one pass, BF16 and masked by the previous ReLU; the layer-1 gradient is formed
             // inside its sums below
@@ -120,9 +115,12 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
             else
                 dz1 = dz[cur];
         } else {
-            // the input gradient on the FP32 matrix cores with the layer's W^T as register-fed weights, masked
+            // the input gradient on the FP32 matrix cores with the layer's W^T as register-fed weights, masked;
+            // the bias gradient's per-block column sums of dz ride along (into the split-K space, free again)
+            float* bp = gr->bias[l] ? part : nullptr;
             launch_dz_f32((const float*)dz[cur], wt + (size_t)(l - 1) * Hd * Hd, (const float*)act[l - 1], P,
-                          (float*)dz[cur ^ 1], st);
+                          (float*)dz[cur ^ 1], bp, st);
+            if (bp) launch_colsum(bp, dz_f32_blocks(P), Hd, 1, 0, tmp, gr->bias[l], 0, st);
         }
         cur ^= 1;
     }
@@ -138,13 +136,13 @@ swf_status Ctx::mlp_backward(Workspace& w, const DevScene& d, const float* tx, i
             launch_layer1_sums(zf, act[0], (int)B, (int)N, S, part, st);
             if (gr->weight[0]) launch_colsum(part, layer1_sums_blocks((int)N), B * Hd, 1, 0, tmp, R, 0, st);
         }
-        if (gr->bias[0]) launch_colsum(S, N, Hd, 1, 0, tmp, gr->bias[0], 0, st);
     } else {
-        const float* dz0 = (const float*)dz[cur];
-        if (gr->bias[0]) launch_colsum(dz0, P, Hd, 1, 0, tmp, gr->bias[0], 0, st);
-        launch_colsum(dz0, B, N * Hd, 1, 0, tmp, S, 0, st);
-        if (gr->weight[0]) launch_colsum(dz0, N, Hd, B, N * Hd, tmp, R, Hd, st);
+        // dz0 carries layer 1's ReLU mask already (applied where it was formed): one pass gives S and per-block
+        // partial sums of R
+        launch_layer1_sums((const float*)dz[cur], nullptr, (int)B, (int)N, S, part, st);
+        if (gr->weight[0]) launch_colsum(part, layer1_sums_blocks((int)N), B * Hd, 1, 0, tmp, R, 0, st);
     }
+    if (gr->bias[0]) launch_colsum(S, N, Hd, 1, 0, tmp, gr->bias[0], 0, st);  // b0: the sum of S over Gaussians
     if (gr->weight[0]) {
         // dW1 [256 x 89] = [S^T gamma(mu_hat) | R^T gamma(s_hat)]
         launch_gemm_f32(true, false, Hd, kMeanFeat, N, S, Hd, fmean, kMeanFeat, gr->weight[0], I, part, st);

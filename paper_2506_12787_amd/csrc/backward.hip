@@ -845,13 +845,15 @@ __global__ __launch_bounds__(256) void out_bwd_bf16_kernel(const float* __restri
     }
 }
 
-// Layer-1 gradient sums of a BF16 backward in one pass over the unmasked FP32
-// gradient z [B][N][256] and the BF16 activations act [B][N][256]: with
-// dz = z * [act > 0], S[n][k] = sum_b dz[b][n][k] (complete: the block owns
-// Gaussians n0 .. n0 + 63, summed over b in order) and Rpart[block][b][k] =
-// sum over the block's Gaussians of dz[b][n][k] (4 row groups through LDS).
+// Layer-1 gradient sums in one pass over the FP32 gradient z [B][N][256]:
+// with dz = z * [act > 0] (kMask: the BF16 activations act [B][N][256] mask
+// an unmasked z; else z is dz already), S[n][k] = sum_b dz[b][n][k]
+// (complete: the block owns Gaussians n0 .. n0 + 63, summed over b in order)
+// and Rpart[block][b][k] = sum over the block's Gaussians of dz[b][n][k]
+// (4 row groups through LDS).
 constexpr int kSumRows = 64;
 
+template <bool kMask>
 __global__ __launch_bounds__(256) void layer1_sums_kernel(const float* __restrict__ z, const __bf16* __restrict__ act,
                                                           int B, int N, float* __restrict__ S,
                                                           float* __restrict__ Rpart) {
@@ -870,9 +872,12 @@ __global__ __launch_bounds__(256) void layer1_sums_kernel(const float* __restric
             if (n < N) {
                 const size_t off = ((size_t)b * N + n) * 256 + c;
                 const float4 v = load4(z + off);
-                const float4 a = load4(act + off);
-                const float4 m = make_float4(a.x > 0.f ? v.x : 0.f, a.y > 0.f ? v.y : 0.f, a.z > 0.f ? v.z : 0.f,
-                                             a.w > 0.f ? v.w : 0.f);
+                float4 m = v;
+                if constexpr (kMask) {
+                    const float4 a = load4(act + off);
+                    m = make_float4(a.x > 0.f ? v.x : 0.f, a.y > 0.f ? v.y : 0.f, a.z > 0.f ? v.z : 0.f,
+                                    a.w > 0.f ? v.w : 0.f);
+                }
                 sacc[i].x += m.x;
                 sacc[i].y += m.y;
                 sacc[i].z += m.z;
@@ -1076,8 +1081,11 @@ void launch_layer1_grad(const void* dz1, const void* W, const void* act, int B, 
 int layer1_sums_blocks(int N) { return (N + kSumRows - 1) / kSumRows; }
 
 void launch_layer1_sums(const float* z, const void* act, int B, int N, float* S, float* Rpart, hipStream_t st) {
-    if (N > 0 && B > 0)
-        layer1_sums_kernel<<<layer1_sums_blocks(N), 256, 0, st>>>(z, (const __bf16*)act, B, N, S, Rpart);
+    if (N <= 0 || B <= 0) return;
+    if (act)
+        layer1_sums_kernel<true><<<layer1_sums_blocks(N), 256, 0, st>>>(z, (const __bf16*)act, B, N, S, Rpart);
+    else
+        layer1_sums_kernel<false><<<layer1_sums_blocks(N), 256, 0, st>>>(z, nullptr, B, N, S, Rpart);
 }
 
 void launch_to_bf16(const float* x, int64_t n, void* y, hipStream_t st) {

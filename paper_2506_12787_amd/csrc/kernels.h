@@ -177,9 +177,12 @@ void launch_gmm_blend(const uint2* ranges, const uint32_t* vals, const Records& 
 void launch_tx_features(const DevScene& s, const float* tx, int B, float* qs, hipStream_t st,
                         float* feat_out = nullptr);
 // FP32 backward of a 256 x 256 layer on the FP32 matrix cores: wt = W^T packed fragment-major (65536 floats, from
-// W [256][256] row-major); out [P][256] = (dz [P][256] W) masked by act [P][256] > 0.
+// W [256][256] row-major); out [P][256] = (dz [P][256] W) masked by act [P][256] > 0; with bpart (non-null,
+// [dz_f32_blocks(P)][256]) also the per-block column sums of dz (the layer's bias gradient before their sum).
 void launch_pack_wt(const float* w, float* wt, hipStream_t st);
-void launch_dz_f32(const float* dz, const float* wt, const float* act, int64_t P, float* out, hipStream_t st);
+int64_t dz_f32_blocks(int64_t P);
+void launch_dz_f32(const float* dz, const float* wt, const float* act, int64_t P, float* out, float* bpart,
+                   hipStream_t st);
 void launch_mlp_fp32(const DevScene& s, const float* qs, int B, const Grid& g, bool paper_mask, const Records& r,
                      float* delta_out, hipStream_t st, float* const* act_out = nullptr);
 void launch_preprocess_static(const DevScene& s, int B, const Grid& g, const Records& r, hipStream_t st);
@@ -289,7 +292,8 @@ void launch_layer1_grad(const void* dz1, const void* W, const void* act, int B, 
 void launch_out_bwd_bf16(const float* dy, const void* wo, const void* act, int64_t P, void* dz, float* part,
                          float* tmp, float* dWo, hipStream_t st);
 int wgrad_out_blocks(int64_t P);  // blocks (pair slices) of launch_out_bwd_bf16
-// S [N][256] = sum_b of z * [act > 0] and Rpart [layer1_sums_blocks(N)][B][256] partial sums over Gaussians
+// S [N][256] = sum_b of z * [act > 0] (act BF16; null: z is masked already) and Rpart [layer1_sums_blocks(N)][B][256]
+// partial sums over Gaussians
 int layer1_sums_blocks(int N);
 void launch_layer1_sums(const float* z, const void* act, int B, int N, float* S, float* Rpart, hipStream_t st);
 void launch_to_bf16(const float* x, int64_t n, void* y, hipStream_t st);

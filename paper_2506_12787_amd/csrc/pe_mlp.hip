@@ -219,17 +219,19 @@ __global__ __launch_bounds__(64 * kFWaves, 3) void mlp_fp32_kernel(MlpArgs a, Mi
 // above with W^T as its weights (fragment-major, packed by pack_wt_kernel) and
 // no bias. A wave takes 16 pairs; lane l = 16 g + r loads input chunk 4 q + j
 // (input 16 q + 4 g + j) of pair r as one 16-byte load per q, and stores the
-// masked output tile t (units 16 t + 4 g + i) with one 16-byte store.
+// masked output tile t (units 16 t + 4 g + i) with one 16-byte store. With
+// bpart, the layer's bias gradient rides along: bpart[block][o] = the sum of
+// dz[p][o] over the block's 64 pairs (fixed order; rows past P count zero).
 __device__ float kZeroBias[256];  // zero-initialised: the layer's bias
 
 __global__ __launch_bounds__(64 * kFWaves, 3) void dz_f32_kernel(const float* __restrict__ dz,
                                                                  const float4* __restrict__ wt,
                                                                  const float* __restrict__ act, int64_t P,
-                                                                 float* __restrict__ out) {
+                                                                 float* __restrict__ out, float* __restrict__ bpart) {
+    __shared__ float4 s_b[kFWaves][64];
     const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const int g = lane >> 4;
     const int64_t p0 = ((int64_t)blockIdx.x * kFWaves + wave) * 16;
-    if (p0 >= P) return;  // wave-uniform; the kernel has no barrier
     const int64_t row = p0 + (lane & 15);
     const bool in = row < P;
     float hin[64], hout[64];
@@ -242,8 +244,36 @@ __global__ __launch_bounds__(64 * kFWaves, 3) void dz_f32_kernel(const float* __
         hin[4 * q + 2] = v.z;
         hin[4 * q + 3] = v.w;
     }
-    f32_mfma_layer<16, 64, false>(wt, kZeroBias, lane, hin, hout, in ? out + row * 256 : nullptr,
-                                  in ? act + row * 256 : nullptr);
+    if (p0 < P)  // wave-uniform
+        f32_mfma_layer<16, 64, false>(wt, kZeroBias, lane, hin, hout, in ? out + row * 256 : nullptr,
+                                      in ? act + row * 256 : nullptr);
+    if (!bpart) return;  // kernel-uniform: no wave reaches the barrier below
+    // Column sums of dz over the wave's 16 rows, halving: at step s a lane keeps
+    // the upper half of its values if bit s of r is set (else the lower half)
+    // and adds its partner's (lane ^ 2^s) matching half. After four steps lane
+    // (r, g) holds columns 16 q + 4 g + j, j = 0..3, with q the 4-bit reversal of r.
+#pragma unroll
+    for (int step = 0; step < 4; ++step) {
+        const int half = 32 >> step;
+        const bool up = (lane >> step) & 1;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const float send = up ? hin[i] : hin[half + i];
+            const float keep = up ? hin[half + i] : hin[i];
+            hin[i] = keep + __shfl_xor(send, 1 << step);
+        }
+    }
+    const int r = lane & 15;
+    const int q = ((r & 1) << 3) | ((r & 2) << 1) | ((r & 4) >> 1) | ((r & 8) >> 3);
+    s_b[wave][4 * q + g] = make_float4(hin[0], hin[1], hin[2], hin[3]);
+    __syncthreads();
+    static_assert(64 * kFWaves == 256, "one thread per column");
+    const int c = (int)threadIdx.x;
+    const float* sb = reinterpret_cast<const float*>(s_b);
+    float sum = sb[c];
+#pragma unroll
+    for (int w = 1; w < kFWaves; ++w) sum += sb[w * 256 + c];
+    bpart[(size_t)blockIdx.x * 256 + c] = sum;
 }
 
 // W^T of a 256 x 256 layer (W row-major [out][in]) in the fragment order of
@@ -355,11 +385,13 @@ void launch_permute_delta(const float* delta_sorted, const uint32_t* perm, int B
 
 void launch_pack_wt(const float* w, float* wt, hipStream_t st) { pack_wt_kernel<<<256, 256, 0, st>>>(w, wt); }
 
-void launch_dz_f32(const float* dz, const float* wt, const float* act, int64_t P, float* out, hipStream_t st) {
-    const int64_t per_block = (int64_t)kFWaves * 16;
+int64_t dz_f32_blocks(int64_t P) { return (P + kFWaves * 16 - 1) / (kFWaves * 16); }
+
+void launch_dz_f32(const float* dz, const float* wt, const float* act, int64_t P, float* out, float* bpart,
+                   hipStream_t st) {
     if (P > 0)
-        dz_f32_kernel<<<(unsigned)((P + per_block - 1) / per_block), 64 * kFWaves, 0, st>>>(
-            dz, reinterpret_cast<const float4*>(wt), act, P, out);
+        dz_f32_kernel<<<(unsigned)dz_f32_blocks(P), 64 * kFWaves, 0, st>>>(dz, reinterpret_cast<const float4*>(wt),
+                                                                            act, P, out, bpart);
 }
 
 }  // namespace swf
