@@ -848,10 +848,10 @@ __global__ __launch_bounds__(256) void out_bwd_bf16_kernel(const float* __restri
 // Layer-1 gradient sums in one pass over the FP32 gradient z [B][N][256]:
 // with dz = z * [act > 0] (kMask: the BF16 activations act [B][N][256] mask
 // an unmasked z; else z is dz already), S[n][k] = sum_b dz[b][n][k]
-// (complete: the block owns Gaussians n0 .. n0 + 63, summed over b in order)
+// (complete: the block owns Gaussians n0 .. n0 + 31, summed over b in order)
 // and Rpart[block][b][k] = sum over the block's Gaussians of dz[b][n][k]
 // (4 row groups through LDS).
-constexpr int kSumRows = 64;
+constexpr int kSumRows = 32;
 
 template <bool kMask>
 __global__ __launch_bounds__(256) void layer1_sums_kernel(const float* __restrict__ z, const __bf16* __restrict__ act,
