@@ -35,30 +35,30 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
     return v;
 }
 
-// Exclusive scan across the 256-thread block; returns the block total in *tot.
-template <typename T>
-__device__ __forceinline__ T block_exclusive_scan(T v, T* lds /* kWaves + 1 */, T* tot) {
+// Exclusive scan across a block of W waves (256 threads by default); returns the block total in *tot.
+template <typename T, int W = kWaves>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* lds /* W + 1 */, T* tot) {
     const T inc = wave_inclusive_scan(v);
     const int w = threadIdx.x >> 6;
     if (lane_id() == 63) lds[w] = inc;
     __syncthreads();
     if (threadIdx.x == 0) {
         T run = 0;
-        for (int i = 0; i < kWaves; ++i) {
+        for (int i = 0; i < W; ++i) {
             const T t = lds[i];
             lds[i] = run;
             run += t;
         }
-        lds[kWaves] = run;
+        lds[W] = run;
     }
     __syncthreads();
     const T r = lds[w] + inc - v;
-    *tot = lds[kWaves];
+    *tot = lds[W];
     __syncthreads();
     return r;
 }
 
-// ---- exclusive scan of uint32 counts (3 kernels) ---------------------------
+// ---- exclusive scan of uint32 counts (3 kernels; 1 up to kScanSingleMax) ---
 __global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                int64_t chunk, uint64_t* __restrict__ sums) {
     __shared__ uint64_t lds[kWaves + 1];
@@ -113,6 +113,63 @@ __global__ __launch_bounds__(kThreads) void scan_down_kernel(const uint32_t* __r
         }
         base += tot;
     }
+}
+
+// Small inputs (n <= kScanSingleMax) in one launch: one 1024-thread workgroup
+// stages the counts in LDS with coalesced loads, scans 16 consecutive counts
+// per thread around one block scan, and writes the offsets back through LDS
+// with coalesced stores (in and out may be the same array); writes the total.
+constexpr int kScanSingleThreads = 1024;
+constexpr int kScanSingleItems = 16;
+constexpr int64_t kScanSingleMax = (int64_t)kScanSingleThreads * kScanSingleItems;  // 16384
+
+__global__ __launch_bounds__(kScanSingleThreads) void scan_single_kernel(const uint32_t* in, int64_t n, uint32_t* out,
+                                                                         uint64_t* __restrict__ total) {
+    constexpr int W = kScanSingleThreads / 64;
+    __shared__ uint4 s_v[kScanSingleMax / 4];
+    __shared__ uint64_t lds[W + 1];
+    uint32_t* sv = reinterpret_cast<uint32_t*>(s_v);
+    const int t = (int)threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kScanSingleItems; ++k) {
+        const int i = k * kScanSingleThreads + t;
+        sv[i] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kScanSingleItems];
+#pragma unroll
+    for (int q = 0; q < kScanSingleItems / 4; ++q) {
+        const uint4 u = s_v[t * (kScanSingleItems / 4) + q];
+        v[4 * q] = u.x;
+        v[4 * q + 1] = u.y;
+        v[4 * q + 2] = u.z;
+        v[4 * q + 3] = u.w;
+    }
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanSingleItems; ++j) s += v[j];
+    uint64_t tot;
+    uint64_t ex = block_exclusive_scan<uint64_t, W>(s, lds, &tot);  // ends with a barrier: every read above is done
+#pragma unroll
+    for (int q = 0; q < kScanSingleItems / 4; ++q) {
+        uint4 u;
+        u.x = (uint32_t)ex;
+        ex += v[4 * q];
+        u.y = (uint32_t)ex;
+        ex += v[4 * q + 1];
+        u.z = (uint32_t)ex;
+        ex += v[4 * q + 2];
+        u.w = (uint32_t)ex;
+        ex += v[4 * q + 3];
+        s_v[t * (kScanSingleItems / 4) + q] = u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanSingleItems; ++k) {
+        const int i = k * kScanSingleThreads + t;
+        if (i < n) out[i] = sv[i];
+    }
+    if (t == 0) *total = tot;
 }
 
 // Culled pairs of a wave by reason (the reason a record with no tiles keeps in
@@ -909,6 +966,10 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t* total, i
     uint64_t* sums = reinterpret_cast<uint64_t*>(scratch);
     if (n <= 0) {
         launch_clear_u32(reinterpret_cast<uint32_t*>(total), 2, st);  // kernel, not a memset node
+        return;
+    }
+    if (n <= kScanSingleMax) {  // e.g. the per-tile list totals of a batch: one launch instead of three
+        scan_single_kernel<<<1, kScanSingleThreads, 0, st>>>(in, n, out, total);
         return;
     }
     const int G = scan_grid(n);

@@ -198,7 +198,7 @@ def test_keys_offsets_ranges_bit_exact(ctx, full):
     ctx.release_scene(sid)
 
 
-@pytest.mark.parametrize("n", [0, 1, 255, 256, 257, 4097, (1 << 20) + 1])
+@pytest.mark.parametrize("n", [0, 1, 255, 256, 257, 4097, 16384, 16385, (1 << 20) + 1])
 def test_exclusive_scan_matches_sequential_sum(ctx, n):
     import torch
     rng = np.random.default_rng(n)
