@@ -221,7 +221,7 @@ int launch_radix_sort(void* keys, uint32_t* vals, void* kalt, uint32_t* valt, in
 void launch_tile_ranges(const void* keys, int key_bytes, int64_t n, int64_t n_gtiles, uint2* ranges,
                         hipStream_t st, const uint64_t* n_dev = nullptr);
 void launch_clear_u32(uint32_t* p, int n, hipStream_t st);
-// n_eff = total if total <= cap else 0 (then bit 0 of *status is set)
+// n_eff = total if total <= cap else 0; *status (if not null) is set to 1 if total > cap, else to 0
 void launch_effective_count(const uint64_t* total, uint64_t cap, uint64_t* n_eff, uint32_t* status, hipStream_t st);
 // Binning path: per-block histograms of each tile segment of a query, their
 // column prefixes and the scanned tile totals (`bins` holds both), then the

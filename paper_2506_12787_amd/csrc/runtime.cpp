@@ -689,9 +689,8 @@ swf_status Ctx::key_count(Workspace& w, hipStream_t st, uint64_t key_cap, uint64
         if ((s = hip(hipStreamSynchronize(st), "stream sync"))) return s;
         nk = *w.total_host;
     } else {
-        launch_clear_u32(w.status_dev, 1, st);
         uint64_t* n_eff = w.total_dev + 1;  // the word after the scan total
-        launch_effective_count(w.total_dev, key_cap, n_eff, w.status_dev, st);
+        launch_effective_count(w.total_dev, key_cap, n_eff, w.status_dev, st);  // also sets the status word
         n_dev = n_eff;
         if (readback) {
             swf_status s;

@@ -1023,7 +1023,7 @@ __global__ void effective_count_kernel(const uint64_t* __restrict__ total, uint6
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         const uint64_t t = *total;
         *n_eff = t <= cap ? t : 0ull;
-        if (t > cap && status) atomicOr(status, 1u);
+        if (status) *status = t > cap ? 1u : 0u;  // stored, not or-ed: this sets the word for the launch's lists
     }
 }
 }  // namespace
